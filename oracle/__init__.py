@@ -1,0 +1,242 @@
+"""ctypes binding of the FP64 CPU oracle (oracle.c).
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the benchmark's
+CPU-baseline leg use it; the product path never does.  Every function follows
+the paper step by step (see oracle.c for the passage each one follows).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_lib = None
+
+ORC_OK, ORC_ECAP, ORC_ESINGULAR, ORC_EBREAKDOWN, ORC_ENONFINITE, ORC_EINVAL = 0, -1, -2, -3, -4, -5
+
+_i32p = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+_f64p = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+_u8p = np.ctypeslib.ndpointer(dtype=np.uint8, flags="C_CONTIGUOUS")
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code, what):
+        super().__init__(f"{what}: oracle status {code}")
+        self.code = code
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_build.LIB):
+            _build.build()
+        L = C.CDLL(_build.LIB)
+        i, d, vp = C.c_int, C.c_double, C.c_void_p
+        L.orc_strength.argtypes = [i, _i32p, _i32p, _f64p, i, d, _i32p, _i32p, i]
+        L.orc_aggregate.argtypes = [i, _i32p, _i32p, _i32p, _i32p]
+        L.orc_pattern_nodes.argtypes = [i, _i32p, _i32p, _i32p, i, i, _i32p, _i32p, i]
+        L.orc_pattern_dofs.argtypes = [i, i, _i32p, _i32p, _i32p, _i32p, i, _i32p, _i32p, i, _u8p]
+        L.orc_tentative.argtypes = [i, i, _i32p, _i32p, _u8p, _i32p, _i32p, i, _f64p, i, _f64p, _f64p, C.POINTER(C.c_int)]
+        L.orc_gram_pinv.argtypes = [i, _f64p, _f64p]
+        L.orc_gram_rows.argtypes = [i, _i32p, _i32p, _u8p, _f64p, i, _f64p]
+        L.orc_project.argtypes = [i, _i32p, _i32p, _u8p, _f64p, i, _f64p, _f64p]
+        L.orc_masked_product.argtypes = [i, i, _i32p, _i32p, _f64p, _i32p, _i32p, _f64p, _f64p]
+        L.orc_emin_cg.argtypes = [i, i, _i32p, _i32p, _f64p, _i32p, _i32p, _u8p, _f64p, i, _f64p, i, _f64p,
+                                  _f64p, _f64p, _f64p, C.POINTER(C.c_int)]
+        L.orc_emin_gmres.argtypes = [i, i, _i32p, _i32p, _f64p, _i32p, _i32p, _u8p, _f64p, i, _f64p, i, _f64p,
+                                     _f64p, C.POINTER(C.c_int)]
+        L.orc_emin_cg_jvp.argtypes = [i, i, _i32p, _i32p, _f64p, _f64p, _i32p, _i32p, _u8p, _f64p, i, _f64p, i,
+                                      _f64p, _f64p]
+        L.orc_transpose.argtypes = [i, i, _i32p, _i32p, _f64p, _i32p, _i32p, _f64p]
+        L.orc_energy.argtypes = [i, i, _i32p, _i32p, _f64p, _i32p, _i32p, _f64p]
+        L.orc_energy.restype = d
+        L.orc_constraint_residual.argtypes = [i, _i32p, _i32p, _f64p, _f64p, _f64p, i]
+        L.orc_constraint_residual.restype = d
+        _lib = L
+    return _lib
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def strength(Ap, Aj, Ax, m, theta):
+    """Nodal strength graph (Sp, Sj), diagonal included, symmetrised."""
+    Ap, Aj, Ax = _i32(Ap), _i32(Aj), _f64(Ax)
+    n = Ap.size - 1
+    nn = n // m
+    cap = 2 * int(Ap[-1]) + nn
+    Sp = np.zeros(nn + 1, np.int32)
+    Sj = np.zeros(max(cap, 1), np.int32)
+    rc = lib().orc_strength(n, Ap, Aj, Ax, m, float(theta), Sp, Sj, cap)
+    if rc < 0:
+        raise OracleError(rc, "strength")
+    return Sp, Sj[:rc].copy()
+
+
+def aggregate(Sp, Sj):
+    """Greedy root-node aggregation: (agg[nn], roots[n_agg])."""
+    Sp, Sj = _i32(Sp), _i32(Sj)
+    nn = Sp.size - 1
+    agg = np.zeros(nn, np.int32)
+    roots = np.zeros(max(nn, 1), np.int32)
+    na = lib().orc_aggregate(nn, Sp, Sj, agg, roots)
+    return agg, roots[:na].copy()
+
+
+def pattern_nodes(Sp, Sj, agg, n_agg, d):
+    Sp, Sj, agg = _i32(Sp), _i32(Sj), _i32(agg)
+    nn = Sp.size - 1
+    cap = max(nn, 1)
+    while True:
+        Np = np.zeros(nn + 1, np.int32)
+        Nj = np.zeros(cap, np.int32)
+        rc = lib().orc_pattern_nodes(nn, Sp, Sj, agg, int(n_agg), int(d), Np, Nj, cap)
+        if rc == ORC_ECAP:
+            cap *= 4
+            continue
+        if rc < 0:
+            raise OracleError(rc, "pattern_nodes")
+        return Np, Nj[:rc].copy()
+
+
+def pattern_dofs(Npn, Njn, agg, roots, m):
+    Npn, Njn, agg, roots = _i32(Npn), _i32(Njn), _i32(agg), _i32(roots)
+    nn = Npn.size - 1
+    cap = max(int(Npn[-1]) * m * m + nn * m, 1)
+    Np = np.zeros(nn * m + 1, np.int32)
+    Nj = np.zeros(cap, np.int32)
+    is_root = np.zeros(nn * m, np.uint8)
+    rc = lib().orc_pattern_dofs(nn, m, Npn, Njn, agg, roots, int(roots.size), Np, Nj, cap, is_root)
+    if rc < 0:
+        raise OracleError(rc, "pattern_dofs")
+    return Np, Nj[:rc].copy(), is_root
+
+
+def tentative(Np, Nj, is_root, agg, roots, m, B):
+    """(T on N, Bc [m*n_agg, nB], rank-deficient row count)."""
+    Np, Nj, agg, roots = _i32(Np), _i32(Nj), _i32(agg), _i32(roots)
+    B = _f64(B)
+    n, nB = B.shape
+    T = np.zeros(int(Np[-1]))
+    Bc = np.zeros((m * roots.size, nB))
+    rd = C.c_int(0)
+    rc = lib().orc_tentative(n, m, Np, Nj, np.ascontiguousarray(is_root, np.uint8), agg, roots,
+                             int(roots.size), B, nB, T, Bc, C.byref(rd))
+    if rc < 0:
+        raise OracleError(rc, "tentative")
+    return T, Bc, rd.value
+
+
+def gram_pinv(G):
+    G = _f64(G)
+    nB = G.shape[0]
+    Gp = np.zeros_like(G)
+    fb = lib().orc_gram_pinv(nB, G.ravel().copy(), Gp.ravel())
+    return Gp, bool(fb)
+
+
+def gram_rows(Np, Nj, is_root, Bc, nB):
+    n = Np.size - 1
+    Gp = np.zeros(max(n * nB * nB, 1))
+    bad = lib().orc_gram_rows(n, _i32(Np), _i32(Nj), np.ascontiguousarray(is_root, np.uint8),
+                              _f64(Bc).ravel() if nB else np.zeros(1), nB, Gp)
+    return Gp, bad
+
+
+def project(Np, Nj, is_root, Bc, nB, X):
+    """Pi = Pi_B o M applied to a copy of X."""
+    Gp, _ = gram_rows(Np, Nj, is_root, Bc, nB)
+    X = _f64(X).copy()
+    lib().orc_project(Np.size - 1, _i32(Np), _i32(Nj), np.ascontiguousarray(is_root, np.uint8),
+                      _f64(Bc).ravel() if nB else np.zeros(1), nB, Gp, X)
+    return X
+
+
+def masked_product(Ap, Aj, Ax, Np, Nj, nc, X):
+    n = Np.size - 1
+    Z = np.zeros(int(Np[-1]))
+    lib().orc_masked_product(n, int(nc), _i32(Ap), _i32(Aj), _f64(Ax), _i32(Np), _i32(Nj), _f64(X), Z)
+    return Z
+
+
+def emin_cg(Ap, Aj, Ax, Np, Nj, is_root, nc, Bc, nB, T, K):
+    """K CG steps; returns (P, info) with gamma/delta/alpha histories."""
+    n = Np.size - 1
+    P = np.zeros(int(Np[-1]))
+    gam = np.zeros(K + 1)
+    dl = np.zeros(max(K, 1))
+    al = np.zeros(max(K, 1))
+    it = C.c_int(0)
+    rc = lib().orc_emin_cg(n, int(nc), _i32(Ap), _i32(Aj), _f64(Ax), _i32(Np), _i32(Nj),
+                           np.ascontiguousarray(is_root, np.uint8),
+                           _f64(Bc).ravel() if nB else np.zeros(1), nB, _f64(T), int(K), P,
+                           gam, dl, al, C.byref(it))
+    return P, dict(status=rc, iters=it.value, gamma=gam, delta=dl[:K], alpha=al[:K])
+
+
+def emin_cg_jvp(Ap, Aj, Ax, dAx, Np, Nj, is_root, nc, Bc, nB, T, K):
+    n = Np.size - 1
+    P = np.zeros(int(Np[-1]))
+    dP = np.zeros(int(Np[-1]))
+    rc = lib().orc_emin_cg_jvp(n, int(nc), _i32(Ap), _i32(Aj), _f64(Ax), _f64(dAx), _i32(Np), _i32(Nj),
+                               np.ascontiguousarray(is_root, np.uint8),
+                               _f64(Bc).ravel() if nB else np.zeros(1), nB, _f64(T), int(K), P, dP)
+    if rc < 0:
+        raise OracleError(rc, "emin_cg_jvp")
+    return P, dP
+
+
+def emin_gmres(Ap, Aj, Ax, Np, Nj, is_root, nc, Bc, nB, T, K):
+    n = Np.size - 1
+    P = np.zeros(int(Np[-1]))
+    res = np.zeros(K + 1)
+    it = C.c_int(0)
+    rc = lib().orc_emin_gmres(n, int(nc), _i32(Ap), _i32(Aj), _f64(Ax), _i32(Np), _i32(Nj),
+                              np.ascontiguousarray(is_root, np.uint8),
+                              _f64(Bc).ravel() if nB else np.zeros(1), nB, _f64(T), int(K), P,
+                              res, C.byref(it))
+    return P, dict(status=rc, iters=it.value, resid=res)
+
+
+def transpose(Ap, Aj, Ax, n_cols=None):
+    Ap, Aj, Ax = _i32(Ap), _i32(Aj), _f64(Ax)
+    nr = Ap.size - 1
+    nc = nr if n_cols is None else n_cols
+    Tp = np.zeros(nc + 1, np.int32)
+    Tj = np.zeros(max(int(Ap[-1]), 1), np.int32)
+    Tx = np.zeros(max(int(Ap[-1]), 1))
+    lib().orc_transpose(nr, nc, Ap, Aj, Ax, Tp, Tj, Tx)
+    return Tp, Tj[:Ap[-1]].copy(), Tx[:Ap[-1]].copy()
+
+
+def energy(Ap, Aj, Ax, Np, Nj, nc, P):
+    return lib().orc_energy(Np.size - 1, int(nc), _i32(Ap), _i32(Aj), _f64(Ax), _i32(Np), _i32(Nj), _f64(P))
+
+
+def constraint_residual(Np, Nj, P, Bc, B):
+    B = _f64(B)
+    return lib().orc_constraint_residual(Np.size - 1, _i32(Np), _i32(Nj), _f64(P), _f64(Bc).ravel(),
+                                         B.ravel(), B.shape[1])
+
+
+def setup(A, B, m=1, theta=0.0, degree=2, agg=None, roots=None):
+    """Strength -> aggregation -> pattern -> tentative for a CSR-like A.
+
+    Returns a dict with S, agg, roots, nodal and DOF pattern, is_root, T, Bc.
+    """
+    Sp, Sj = strength(A.rowptr, A.colind, A.vals, m, theta)
+    if agg is None:
+        agg, roots = aggregate(Sp, Sj)
+    Npn, Njn = pattern_nodes(Sp, Sj, agg, roots.size, degree)
+    Np, Nj, is_root = pattern_dofs(Npn, Njn, agg, roots, m)
+    T, Bc, rd = tentative(Np, Nj, is_root, agg, roots, m, B)
+    return dict(Sp=Sp, Sj=Sj, agg=agg, roots=roots, Npn=Npn, Njn=Njn, Np=Np, Nj=Nj,
+                is_root=is_root, T=T, Bc=Bc, nc=m * roots.size, rank_def=rd)

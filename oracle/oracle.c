@@ -1,0 +1,721 @@
+/*
+ * oracle.c -- plain FP64 CPU reference of root-node AMG interpolation setup.
+ *
+ * TEST INFRASTRUCTURE ONLY (see oracle.h).  Written from the paper's
+ * description, step by step, with no blocking, fusion or reordering: each
+ * function states the passage it follows.  Built with -O2 -ffp-contract=off
+ * so that every product and sum is rounded as written.
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define NBMAX 8
+
+/* ------------------------------------------------------------------------ */
+/* small helpers                                                             */
+/* ------------------------------------------------------------------------ */
+static int cmp_ll(const void *a, const void *b) {
+  long long x = *(const long long *)a, y = *(const long long *)b;
+  return (x > y) - (x < y);
+}
+static int cmp_int(const void *a, const void *b) {
+  int x = *(const int *)a, y = *(const int *)b;
+  return (x > y) - (x < y);
+}
+static double dot(long len, const double *x, const double *y) {
+  double s = 0.0;
+  for (long p = 0; p < len; ++p) s += x[p] * y[p];
+  return s;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Strength of connection, Sec. 3.2.  Symmetric measure: entry (i,j) is     */
+/* strong when |a_ij| >= theta sqrt(|a_ii a_jj|), evaluated squared.  For   */
+/* vector problems the amalgamate step collapses each m x m block to one    */
+/* node entry; a block is strong when any of its DOF entries is.            */
+/* ------------------------------------------------------------------------ */
+int orc_strength(int n, const int *Ap, const int *Aj, const double *Ax, int m,
+                 double theta, int *Sp, int *Sj, int cap) {
+  if (m < 1 || n % m) return ORC_EINVAL;
+  int nn = n / m;
+  double *diag = (double *)calloc((size_t)n, sizeof(double));
+  for (int i = 0; i < n; ++i)
+    for (int p = Ap[i]; p < Ap[i + 1]; ++p)
+      if (Aj[p] == i) diag[i] = Ax[p];
+  long maxk = 2L * Ap[n] + nn;
+  long long *key = (long long *)malloc((size_t)maxk * sizeof(long long));
+  long cnt = 0;
+  for (int I = 0; I < nn; ++I) key[cnt++] = (long long)I * nn + I;
+  double th2 = theta * theta;
+  for (int i = 0; i < n; ++i) {
+    for (int p = Ap[i]; p < Ap[i + 1]; ++p) {
+      int j = Aj[p];
+      double lhs = Ax[p] * Ax[p];
+      double rhs = th2 * fabs(diag[i] * diag[j]);
+      if (i == j || lhs >= rhs) {
+        int I = i / m, J = j / m;
+        key[cnt++] = (long long)I * nn + J;  /* S            */
+        key[cnt++] = (long long)J * nn + I;  /* S^T: S u S^T */
+      }
+    }
+  }
+  qsort(key, (size_t)cnt, sizeof(long long), cmp_ll);
+  long u = 0;
+  for (long q = 0; q < cnt; ++q)
+    if (q == 0 || key[q] != key[q - 1]) key[u++] = key[q];
+  int rc = (int)u;
+  if (u > cap) {
+    rc = ORC_ECAP;
+  } else {
+    for (int I = 0; I <= nn; ++I) Sp[I] = 0;
+    for (long q = 0; q < u; ++q) {
+      Sp[key[q] / nn + 1]++;
+      Sj[q] = (int)(key[q] % nn);
+    }
+    for (int I = 0; I < nn; ++I) Sp[I + 1] += Sp[I];
+  }
+  free(key);
+  free(diag);
+  return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Aggregation, Sec. 3.3: the classical greedy scheme.  An unaggregated     */
+/* node whose strong neighbours are all unaggregated becomes a root and     */
+/* collects those neighbours.  Left-over nodes then join a neighbouring     */
+/* aggregate formed in that first sweep; nodes still left form new          */
+/* aggregates with their unaggregated neighbours, rooted at themselves.     */
+/* ------------------------------------------------------------------------ */
+int orc_aggregate(int nn, const int *Sp, const int *Sj, int *agg, int *roots) {
+  int na = 0;
+  for (int i = 0; i < nn; ++i) agg[i] = -1;
+  /* sweep 1 */
+  for (int i = 0; i < nn; ++i) {
+    if (agg[i] >= 0) continue;
+    int free_nb = 1;
+    for (int p = Sp[i]; p < Sp[i + 1]; ++p)
+      if (Sj[p] != i && agg[Sj[p]] >= 0) { free_nb = 0; break; }
+    if (!free_nb) continue;
+    roots[na] = i;
+    agg[i] = na;
+    for (int p = Sp[i]; p < Sp[i + 1]; ++p) agg[Sj[p]] = na;
+    ++na;
+  }
+  /* sweep 2: join the lowest-index neighbour aggregated in sweep 1 */
+  int *snap = (int *)malloc((size_t)(nn > 0 ? nn : 1) * sizeof(int));
+  memcpy(snap, agg, (size_t)nn * sizeof(int));
+  for (int i = 0; i < nn; ++i) {
+    if (agg[i] >= 0) continue;
+    for (int p = Sp[i]; p < Sp[i + 1]; ++p) {
+      int j = Sj[p];
+      if (j != i && snap[j] >= 0) { agg[i] = snap[j]; break; }
+    }
+  }
+  free(snap);
+  /* sweep 3 */
+  for (int i = 0; i < nn; ++i) {
+    if (agg[i] >= 0) continue;
+    roots[na] = i;
+    agg[i] = na;
+    for (int p = Sp[i]; p < Sp[i + 1]; ++p)
+      if (agg[Sj[p]] < 0) agg[Sj[p]] = na;
+    ++na;
+  }
+  return na;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Pattern N = S^d C, Sec. 3.4, as d boolean sparse products: X_0 = C and   */
+/* X_{t+1} = S X_t.  A marker array gives the union of each row.            */
+/* ------------------------------------------------------------------------ */
+int orc_pattern_nodes(int nn, const int *Sp, const int *Sj, const int *agg,
+                      int n_agg, int d, int *Np, int *Nj, int cap) {
+  if (d < 0) return ORC_EINVAL;
+  int *Xp = (int *)malloc((size_t)(nn + 1) * sizeof(int));
+  int *Xj = (int *)malloc((size_t)(nn > 0 ? nn : 1) * sizeof(int));
+  for (int I = 0; I <= nn; ++I) Xp[I] = I;
+  for (int I = 0; I < nn; ++I) Xj[I] = agg[I];
+  int *mark = (int *)malloc((size_t)(n_agg > 0 ? n_agg : 1) * sizeof(int));
+  for (int t = 0; t < d; ++t) {
+    for (int a = 0; a < n_agg; ++a) mark[a] = -1;
+    int *Yp = (int *)malloc((size_t)(nn + 1) * sizeof(int));
+    Yp[0] = 0;
+    for (int I = 0; I < nn; ++I) {
+      int c = 0;
+      for (int p = Sp[I]; p < Sp[I + 1]; ++p) {
+        int J = Sj[p];
+        for (int q = Xp[J]; q < Xp[J + 1]; ++q)
+          if (mark[Xj[q]] != I) { mark[Xj[q]] = I; ++c; }
+      }
+      Yp[I + 1] = Yp[I] + c;
+    }
+    int *Yj = (int *)malloc((size_t)(Yp[nn] > 0 ? Yp[nn] : 1) * sizeof(int));
+    for (int a = 0; a < n_agg; ++a) mark[a] = -1;
+    for (int I = 0; I < nn; ++I) {
+      int w = Yp[I];
+      for (int p = Sp[I]; p < Sp[I + 1]; ++p) {
+        int J = Sj[p];
+        for (int q = Xp[J]; q < Xp[J + 1]; ++q)
+          if (mark[Xj[q]] != I) { mark[Xj[q]] = I; Yj[w++] = Xj[q]; }
+      }
+      qsort(Yj + Yp[I], (size_t)(Yp[I + 1] - Yp[I]), sizeof(int), cmp_int);
+    }
+    free(Xp);
+    free(Xj);
+    Xp = Yp;
+    Xj = Yj;
+  }
+  int rc = Xp[nn];
+  if (rc > cap) {
+    rc = ORC_ECAP;
+  } else {
+    memcpy(Np, Xp, (size_t)(nn + 1) * sizeof(int));
+    memcpy(Nj, Xj, (size_t)Xp[nn] * sizeof(int));
+  }
+  free(mark);
+  free(Xp);
+  free(Xj);
+  return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* unamalgamate and root_node_pattern, Sec. 3.4: DOF entry (i,j) exists when */
+/* nodal entry (floor(i/m), floor(j/m)) does; each root DOF row becomes the  */
+/* identity row of its coarse DOF.                                           */
+/* ------------------------------------------------------------------------ */
+int orc_pattern_dofs(int nn, int m, const int *Npn, const int *Njn,
+                     const int *agg, const int *roots, int n_agg,
+                     int *Np, int *Nj, int cap, unsigned char *is_root) {
+  (void)n_agg;
+  int n = nn * m;
+  long w = 0;
+  Np[0] = 0;
+  for (int i = 0; i < n; ++i) {
+    int I = i / m, c = i % m, a = agg[I];
+    int root = (roots[a] == I);
+    is_root[i] = (unsigned char)root;
+    if (root) {
+      if (w + 1 > cap) return ORC_ECAP;
+      Nj[w++] = m * a + c;
+    } else {
+      long len = (long)(Npn[I + 1] - Npn[I]) * m;
+      if (w + len > cap) return ORC_ECAP;
+      for (int p = Npn[I]; p < Npn[I + 1]; ++p)
+        for (int cc = 0; cc < m; ++cc) Nj[w++] = m * Njn[p] + cc;
+    }
+    Np[i + 1] = (int)w;
+  }
+  return (int)w;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Pseudo-inverse of a small SPD(-ish) Gram matrix.                          */
+/* ------------------------------------------------------------------------ */
+static void jacobi_eig(int k, double *a, double *v) {
+  /* cyclic Jacobi on the symmetric k x k matrix a; eigenvalues end up on the
+   * diagonal of a, eigenvectors in the columns of v */
+  for (int i = 0; i < k; ++i)
+    for (int j = 0; j < k; ++j) v[i * k + j] = (i == j);
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0;
+    for (int i = 0; i < k; ++i)
+      for (int j = i + 1; j < k; ++j) off += a[i * k + j] * a[i * k + j];
+    if (off == 0.0) break;
+    for (int p = 0; p < k; ++p) {
+      for (int q = p + 1; q < k; ++q) {
+        double apq = a[p * k + q];
+        if (apq == 0.0) continue;
+        double theta = (a[q * k + q] - a[p * k + p]) / (2.0 * apq);
+        double t = (theta >= 0 ? 1.0 : -1.0) /
+                   (fabs(theta) + sqrt(theta * theta + 1.0));
+        double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+        for (int r = 0; r < k; ++r) {
+          double arp = a[r * k + p], arq = a[r * k + q];
+          a[r * k + p] = c * arp - s * arq;
+          a[r * k + q] = s * arp + c * arq;
+        }
+        for (int r = 0; r < k; ++r) {
+          double apr = a[p * k + r], aqr = a[q * k + r];
+          a[p * k + r] = c * apr - s * aqr;
+          a[q * k + r] = s * apr + c * aqr;
+        }
+        for (int r = 0; r < k; ++r) {
+          double vrp = v[r * k + p], vrq = v[r * k + q];
+          v[r * k + p] = c * vrp - s * vrq;
+          v[r * k + q] = s * vrp + c * vrq;
+        }
+      }
+    }
+  }
+}
+
+int orc_gram_pinv(int nB, const double *G, double *Gp) {
+  if (nB <= 0) return 0;
+  double L[NBMAX * NBMAX], D[NBMAX], maxd = 0.0;
+  for (int i = 0; i < nB; ++i) maxd = fmax(maxd, G[i * nB + i]);
+  int ok = maxd > 0.0;
+  for (int k = 0; k < nB && ok; ++k) {
+    double dk = G[k * nB + k];
+    for (int l = 0; l < k; ++l) dk -= L[k * nB + l] * L[k * nB + l] * D[l];
+    if (!(dk > 1e-12 * maxd)) { ok = 0; break; }
+    D[k] = dk;
+    L[k * nB + k] = 1.0;
+    for (int i = k + 1; i < nB; ++i) {
+      double s = G[i * nB + k];
+      for (int l = 0; l < k; ++l) s -= L[i * nB + l] * L[k * nB + l] * D[l];
+      L[i * nB + k] = s / dk;
+    }
+  }
+  if (ok) {
+    /* Linv: inverse of unit lower-triangular L */
+    double Li[NBMAX * NBMAX];
+    for (int j = 0; j < nB; ++j) {
+      for (int i = 0; i < nB; ++i) Li[i * nB + j] = (i == j);
+      for (int i = j + 1; i < nB; ++i) {
+        double s = 0.0;
+        for (int l = j; l < i; ++l) s += L[i * nB + l] * Li[l * nB + j];
+        Li[i * nB + j] = -s;
+      }
+    }
+    /* G^-1 = Li^T D^-1 Li */
+    for (int i = 0; i < nB; ++i)
+      for (int j = 0; j < nB; ++j) {
+        double s = 0.0;
+        for (int l = 0; l < nB; ++l) s += Li[l * nB + i] * Li[l * nB + j] / D[l];
+        Gp[i * nB + j] = s;
+      }
+    return 0;
+  }
+  double a[NBMAX * NBMAX], v[NBMAX * NBMAX];
+  memcpy(a, G, sizeof(double) * (size_t)(nB * nB));
+  jacobi_eig(nB, a, v);
+  double lmax = 0.0;
+  for (int i = 0; i < nB; ++i) lmax = fmax(lmax, a[i * nB + i]);
+  for (int i = 0; i < nB * nB; ++i) Gp[i] = 0.0;
+  for (int l = 0; l < nB; ++l) {
+    double lam = a[l * nB + l];
+    if (!(lam > 1e-12 * lmax) || lam <= 0.0) continue;
+    for (int i = 0; i < nB; ++i)
+      for (int j = 0; j < nB; ++j) Gp[i * nB + j] += v[i * nB + l] * v[j * nB + l] / lam;
+  }
+  return 1;
+}
+
+int orc_gram_rows(int n, const int *Np, const int *Nj,
+                  const unsigned char *is_root, const double *Bc, int nB,
+                  double *Gp) {
+  int bad = 0;
+  double G[NBMAX * NBMAX];
+  for (int i = 0; i < n; ++i) {
+    double *gi = Gp + (long)i * nB * nB;
+    for (int q = 0; q < nB * nB; ++q) gi[q] = 0.0;
+    if (is_root[i] || nB == 0) continue;
+    for (int q = 0; q < nB * nB; ++q) G[q] = 0.0;
+    for (int p = Np[i]; p < Np[i + 1]; ++p) {
+      const double *b = Bc + (long)Nj[p] * nB;
+      for (int r = 0; r < nB; ++r)
+        for (int c = 0; c < nB; ++c) G[r * nB + c] += b[r] * b[c];
+    }
+    bad += orc_gram_pinv(nB, G, gi);
+  }
+  return bad;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Projection onto the constraint space (Sec. 3.6: updates U must satisfy   */
+/* U Bc = 0 on the pattern, with root rows fixed): zero the root rows; on   */
+/* each F row remove the least-squares component x B_J G^+ B_J^T.           */
+/* ------------------------------------------------------------------------ */
+void orc_project(int n, const int *Np, const int *Nj,
+                 const unsigned char *is_root, const double *Bc, int nB,
+                 const double *Gp, double *X) {
+  double s[NBMAX], y[NBMAX];
+  for (int i = 0; i < n; ++i) {
+    if (is_root[i]) {
+      for (int p = Np[i]; p < Np[i + 1]; ++p) X[p] = 0.0;
+      continue;
+    }
+    if (nB == 0) continue;
+    const double *gi = Gp + (long)i * nB * nB;
+    for (int q = 0; q < nB; ++q) s[q] = 0.0;
+    for (int p = Np[i]; p < Np[i + 1]; ++p)
+      for (int q = 0; q < nB; ++q) s[q] += X[p] * Bc[(long)Nj[p] * nB + q];
+    for (int q = 0; q < nB; ++q) {
+      y[q] = 0.0;
+      for (int r = 0; r < nB; ++r) y[q] += gi[q * nB + r] * s[r];
+    }
+    for (int p = Np[i]; p < Np[i + 1]; ++p) {
+      double u = 0.0;
+      for (int q = 0; q < nB; ++q) u += Bc[(long)Nj[p] * nB + q] * y[q];
+      X[p] -= u;
+    }
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Product A X kept to the pattern (Sec. 3.6: the smoothing product whose   */
+/* fill is dropped outside N).  Row-by-row Gustavson product with a dense   */
+/* accumulator, contributions summed in the order of A's row.               */
+/* ------------------------------------------------------------------------ */
+void orc_masked_product(int n, int nc, const int *Ap, const int *Aj,
+                        const double *Ax, const int *Np, const int *Nj,
+                        const double *X, double *Z) {
+  double *acc = (double *)calloc((size_t)(nc > 0 ? nc : 1), sizeof(double));
+  for (int i = 0; i < n; ++i) {
+    for (int t = Ap[i]; t < Ap[i + 1]; ++t) {
+      int k = Aj[t];
+      for (int q = Np[k]; q < Np[k + 1]; ++q) acc[Nj[q]] += Ax[t] * X[q];
+    }
+    for (int p = Np[i]; p < Np[i + 1]; ++p) Z[p] = acc[Nj[p]];
+    for (int t = Ap[i]; t < Ap[i + 1]; ++t) {
+      int k = Aj[t];
+      for (int q = Np[k]; q < Np[k + 1]; ++q) acc[Nj[q]] = 0.0;
+    }
+  }
+  free(acc);
+}
+
+/* ------------------------------------------------------------------------ */
+/* inject, Sec. 3.6: coarse candidates by injection at the root DOFs; T     */
+/* from the first m candidates normalised so that coarse DOFs inject to the */
+/* roots (Eq. root-nodeform); further candidates by the minimum-norm row    */
+/* update of Eq. Tproj.                                                     */
+/* ------------------------------------------------------------------------ */
+static int invert_small(int m, const double *a, double *ai) {
+  double w[NBMAX * 2 * NBMAX];
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < 2 * m; ++j)
+      w[i * 2 * m + j] = j < m ? a[i * m + j] : (double)(j - m == i);
+  for (int c = 0; c < m; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < m; ++r)
+      if (fabs(w[r * 2 * m + c]) > fabs(w[piv * 2 * m + c])) piv = r;
+    if (w[piv * 2 * m + c] == 0.0) return ORC_ESINGULAR;
+    if (piv != c)
+      for (int j = 0; j < 2 * m; ++j) {
+        double t = w[c * 2 * m + j];
+        w[c * 2 * m + j] = w[piv * 2 * m + j];
+        w[piv * 2 * m + j] = t;
+      }
+    double d = w[c * 2 * m + c];
+    for (int j = 0; j < 2 * m; ++j) w[c * 2 * m + j] /= d;
+    for (int r = 0; r < m; ++r) {
+      if (r == c) continue;
+      double f = w[r * 2 * m + c];
+      for (int j = 0; j < 2 * m; ++j) w[r * 2 * m + j] -= f * w[c * 2 * m + j];
+    }
+  }
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < m; ++j) ai[i * m + j] = w[i * 2 * m + m + j];
+  return ORC_OK;
+}
+
+int orc_tentative(int n, int m, const int *Np, const int *Nj,
+                  const unsigned char *is_root, const int *agg,
+                  const int *roots, int n_agg, const double *B, int nB,
+                  double *T, double *Bc, int *rank_def) {
+  if (m < 1 || nB < m || m > NBMAX || nB > NBMAX) return ORC_EINVAL;
+  int nc = m * n_agg;
+  for (int a = 0; a < n_agg; ++a)
+    for (int c = 0; c < m; ++c)
+      for (int q = 0; q < nB; ++q)
+        Bc[(long)(m * a + c) * nB + q] = B[(long)(m * roots[a] + c) * nB + q];
+  double *binv = (double *)malloc((size_t)(n_agg > 0 ? n_agg : 1) * m * m * sizeof(double));
+  for (int a = 0; a < n_agg; ++a) {
+    double blk[NBMAX * NBMAX];
+    for (int r = 0; r < m; ++r)
+      for (int c = 0; c < m; ++c) blk[r * m + c] = B[(long)(m * roots[a] + r) * nB + c];
+    if (invert_small(m, blk, binv + (long)a * m * m) != ORC_OK) {
+      free(binv);
+      return ORC_ESINGULAR;
+    }
+  }
+  for (int i = 0; i < n; ++i) {
+    int a = agg[i / m];
+    for (int p = Np[i]; p < Np[i + 1]; ++p) {
+      int j = Nj[p];
+      if (is_root[i]) {
+        T[p] = (j == m * a + i % m) ? 1.0 : 0.0;
+      } else if (j / m == a) {
+        int cc = j % m;
+        double s = 0.0;
+        for (int r = 0; r < m; ++r) s += B[(long)i * nB + r] * binv[(long)a * m * m + r * m + cc];
+        T[p] = s;
+      } else {
+        T[p] = 0.0;
+      }
+    }
+  }
+  free(binv);
+  int bad = 0;
+  if (nB > m) {
+    double G[NBMAX * NBMAX], Gp[NBMAX * NBMAX], r[NBMAX], y[NBMAX];
+    for (int i = 0; i < n; ++i) {
+      if (is_root[i]) continue;
+      for (int q = 0; q < nB * nB; ++q) G[q] = 0.0;
+      for (int p = Np[i]; p < Np[i + 1]; ++p) {
+        const double *b = Bc + (long)Nj[p] * nB;
+        for (int u = 0; u < nB; ++u)
+          for (int v = 0; v < nB; ++v) G[u * nB + v] += b[u] * b[v];
+      }
+      bad += orc_gram_pinv(nB, G, Gp);
+      for (int q = 0; q < nB; ++q) {
+        double s = 0.0;
+        for (int p = Np[i]; p < Np[i + 1]; ++p) s += T[p] * Bc[(long)Nj[p] * nB + q];
+        r[q] = B[(long)i * nB + q] - s;
+      }
+      for (int q = 0; q < nB; ++q) {
+        y[q] = 0.0;
+        for (int u = 0; u < nB; ++u) y[q] += Gp[q * nB + u] * r[u];
+      }
+      for (int p = Np[i]; p < Np[i + 1]; ++p) {
+        double u = 0.0;
+        for (int q = 0; q < nB; ++q) u += Bc[(long)Nj[p] * nB + q] * y[q];
+        T[p] += u;
+      }
+    }
+  }
+  (void)nc;
+  if (rank_def) *rank_def = bad;
+  return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* improve by conjugate gradients, Sec. 3.6 and Sec. 4.1 (Lemma th:cg):     */
+/* minimise E(P) = trace(P^T A P) over P in T + V, V = {U on N, zero root   */
+/* rows, U Bc = 0}.  The gradient direction is -Pi(A P); the operator is    */
+/* Pi A Pi restricted to V.                                                 */
+/* ------------------------------------------------------------------------ */
+int orc_emin_cg(int n, int nc, const int *Ap, const int *Aj, const double *Ax,
+                const int *Np, const int *Nj, const unsigned char *is_root,
+                const double *Bc, int nB, const double *T, int K, double *P,
+                double *gam, double *del, double *alp, int *iters) {
+  long nz = Np[n];
+  size_t sz = (size_t)(nz > 0 ? nz : 1) * sizeof(double);
+  double *R = (double *)malloc(sz), *D = (double *)malloc(sz), *Z = (double *)malloc(sz);
+  double *Gp = (double *)malloc((size_t)n * (nB > 0 ? nB * nB : 1) * sizeof(double));
+  orc_gram_rows(n, Np, Nj, is_root, Bc, nB, Gp);
+  memcpy(P, T, (size_t)nz * sizeof(double));
+  orc_masked_product(n, nc, Ap, Aj, Ax, Np, Nj, P, Z);
+  orc_project(n, Np, Nj, is_root, Bc, nB, Gp, Z);
+  for (long p = 0; p < nz; ++p) { R[p] = -Z[p]; D[p] = R[p]; }
+  double g = dot(nz, R, R);
+  if (gam) gam[0] = g;
+  int rc = ORC_OK, it = 0;
+  if (!isfinite(g)) rc = ORC_ENONFINITE;
+  for (int k = 0; k < K && rc == ORC_OK; ++k) {
+    if (g == 0.0) break;
+    orc_masked_product(n, nc, Ap, Aj, Ax, Np, Nj, D, Z);
+    orc_project(n, Np, Nj, is_root, Bc, nB, Gp, Z);
+    double dl = dot(nz, D, Z);
+    if (del) del[k] = dl;
+    if (!isfinite(dl)) { rc = ORC_ENONFINITE; break; }
+    if (dl <= 0.0) { rc = ORC_EBREAKDOWN; break; }
+    double al = g / dl;
+    if (alp) alp[k] = al;
+    for (long p = 0; p < nz; ++p) P[p] += al * D[p];
+    for (long p = 0; p < nz; ++p) R[p] -= al * Z[p];
+    double gn = dot(nz, R, R);
+    if (gam) gam[k + 1] = gn;
+    if (!isfinite(gn)) { rc = ORC_ENONFINITE; break; }
+    double be = gn / g;
+    g = gn;
+    for (long p = 0; p < nz; ++p) D[p] = R[p] + be * D[p];
+    ++it;
+  }
+  if (iters) *iters = it;
+  free(R); free(D); free(Z); free(Gp);
+  return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Tangent-linear model of orc_emin_cg: every statement above differentiated */
+/* in direction dA (A's stored values), pattern and T held fixed.            */
+/* ------------------------------------------------------------------------ */
+int orc_emin_cg_jvp(int n, int nc, const int *Ap, const int *Aj,
+                    const double *Ax, const double *dAx, const int *Np,
+                    const int *Nj, const unsigned char *is_root,
+                    const double *Bc, int nB, const double *T, int K,
+                    double *P, double *dP) {
+  long nz = Np[n];
+  size_t sz = (size_t)(nz > 0 ? nz : 1) * sizeof(double);
+  double *R = (double *)malloc(sz), *D = (double *)malloc(sz), *Z = (double *)malloc(sz);
+  double *dR = (double *)malloc(sz), *dD = (double *)malloc(sz), *dZ = (double *)malloc(sz);
+  double *tmp = (double *)malloc(sz);
+  double *Gp = (double *)malloc((size_t)n * (nB > 0 ? nB * nB : 1) * sizeof(double));
+  orc_gram_rows(n, Np, Nj, is_root, Bc, nB, Gp);
+  memcpy(P, T, (size_t)nz * sizeof(double));
+  for (long p = 0; p < nz; ++p) dP[p] = 0.0;
+  /* R = -Pi(A P), dR = -Pi(dA P) */
+  orc_masked_product(n, nc, Ap, Aj, Ax, Np, Nj, P, Z);
+  orc_project(n, Np, Nj, is_root, Bc, nB, Gp, Z);
+  orc_masked_product(n, nc, Ap, Aj, dAx, Np, Nj, P, dZ);
+  orc_project(n, Np, Nj, is_root, Bc, nB, Gp, dZ);
+  for (long p = 0; p < nz; ++p) {
+    R[p] = -Z[p]; D[p] = R[p];
+    dR[p] = -dZ[p]; dD[p] = dR[p];
+  }
+  double g = dot(nz, R, R), dg = 2.0 * dot(nz, R, dR);
+  int rc = isfinite(g) ? ORC_OK : ORC_ENONFINITE;
+  for (int k = 0; k < K && rc == ORC_OK; ++k) {
+    if (g == 0.0) break;
+    /* Z = Pi(A D), dZ = Pi(dA D + A dD) */
+    orc_masked_product(n, nc, Ap, Aj, Ax, Np, Nj, D, Z);
+    orc_project(n, Np, Nj, is_root, Bc, nB, Gp, Z);
+    orc_masked_product(n, nc, Ap, Aj, dAx, Np, Nj, D, dZ);
+    orc_masked_product(n, nc, Ap, Aj, Ax, Np, Nj, dD, tmp);
+    for (long p = 0; p < nz; ++p) dZ[p] += tmp[p];
+    orc_project(n, Np, Nj, is_root, Bc, nB, Gp, dZ);
+    double dl = dot(nz, D, Z);
+    double ddl = dot(nz, dD, Z) + dot(nz, D, dZ);
+    if (!isfinite(dl)) { rc = ORC_ENONFINITE; break; }
+    if (dl <= 0.0) { rc = ORC_EBREAKDOWN; break; }
+    double al = g / dl;
+    double dal = (dg * dl - g * ddl) / (dl * dl);
+    for (long p = 0; p < nz; ++p) {
+      dP[p] += dal * D[p] + al * dD[p];
+      P[p] += al * D[p];
+      dR[p] -= dal * Z[p] + al * dZ[p];
+      R[p] -= al * Z[p];
+    }
+    double gn = dot(nz, R, R), dgn = 2.0 * dot(nz, R, dR);
+    double be = gn / g;
+    double dbe = (dgn * g - gn * dg) / (g * g);
+    g = gn;
+    dg = dgn;
+    for (long p = 0; p < nz; ++p) {
+      dD[p] = dR[p] + dbe * D[p] + be * dD[p];
+      D[p] = R[p] + be * D[p];
+    }
+  }
+  free(R); free(D); free(Z); free(dR); free(dD); free(dZ); free(tmp); free(Gp);
+  return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* improve by GMRES, Sec. 3.6 and Sec. 4.2 (non-symmetric A): minimise      */
+/* ||Pi(A P)||_F over T plus the Krylov space of Pi A Pi from               */
+/* R_0 = -Pi(A T).  Unrestarted, modified Gram-Schmidt in the Frobenius     */
+/* inner product on N, Givens rotations for the small least-squares problem.*/
+/* ------------------------------------------------------------------------ */
+int orc_emin_gmres(int n, int nc, const int *Ap, const int *Aj,
+                   const double *Ax, const int *Np, const int *Nj,
+                   const unsigned char *is_root, const double *Bc, int nB,
+                   const double *T, int K, double *P, double *resid,
+                   int *iters) {
+  long nz = Np[n];
+  size_t sz = (size_t)(nz > 0 ? nz : 1) * sizeof(double);
+  double **V = (double **)malloc((size_t)(K + 1) * sizeof(double *));
+  for (int k = 0; k <= K; ++k) V[k] = (double *)malloc(sz);
+  double *W = (double *)malloc(sz);
+  double *H = (double *)calloc((size_t)(K + 1) * (K > 0 ? K : 1), sizeof(double));
+#define HH(i, j) H[(long)(i) * (K > 0 ? K : 1) + (j)]
+  double *cs = (double *)calloc((size_t)(K + 1), sizeof(double));
+  double *sn = (double *)calloc((size_t)(K + 1), sizeof(double));
+  double *gv = (double *)calloc((size_t)(K + 2), sizeof(double));
+  double *Gp = (double *)malloc((size_t)n * (nB > 0 ? nB * nB : 1) * sizeof(double));
+  orc_gram_rows(n, Np, Nj, is_root, Bc, nB, Gp);
+  memcpy(P, T, (size_t)nz * sizeof(double));
+  orc_masked_product(n, nc, Ap, Aj, Ax, Np, Nj, P, W);
+  orc_project(n, Np, Nj, is_root, Bc, nB, Gp, W);
+  for (long p = 0; p < nz; ++p) V[0][p] = -W[p];
+  double beta = sqrt(dot(nz, V[0], V[0]));
+  if (resid) resid[0] = beta;
+  int rc = isfinite(beta) ? ORC_OK : ORC_ENONFINITE;
+  int kd = 0;
+  if (rc == ORC_OK && beta > 0.0) {
+    for (long p = 0; p < nz; ++p) V[0][p] /= beta;
+    gv[0] = beta;
+    for (int k = 0; k < K; ++k) {
+      orc_masked_product(n, nc, Ap, Aj, Ax, Np, Nj, V[k], W);
+      orc_project(n, Np, Nj, is_root, Bc, nB, Gp, W);
+      for (int j = 0; j <= k; ++j) {
+        double h = dot(nz, W, V[j]);
+        HH(j, k) = h;
+        for (long p = 0; p < nz; ++p) W[p] -= h * V[j][p];
+      }
+      double hn = sqrt(dot(nz, W, W));
+      if (!isfinite(hn)) { rc = ORC_ENONFINITE; break; }
+      HH(k + 1, k) = hn;
+      /* apply earlier rotations to column k, then a new one */
+      for (int j = 0; j < k; ++j) {
+        double a = HH(j, k), b = HH(j + 1, k);
+        HH(j, k) = cs[j] * a + sn[j] * b;
+        HH(j + 1, k) = -sn[j] * a + cs[j] * b;
+      }
+      double a = HH(k, k), b = HH(k + 1, k);
+      double r = hypot(a, b);
+      cs[k] = a / r;
+      sn[k] = b / r;
+      HH(k, k) = r;
+      HH(k + 1, k) = 0.0;
+      gv[k + 1] = -sn[k] * gv[k];
+      gv[k] = cs[k] * gv[k];
+      if (resid) resid[k + 1] = fabs(gv[k + 1]);
+      kd = k + 1;
+      if (hn == 0.0) break; /* the Krylov space is invariant */
+      for (long p = 0; p < nz; ++p) V[k + 1][p] = W[p] / hn;
+    }
+    if (rc == ORC_OK) {
+      double *y = (double *)calloc((size_t)(kd > 0 ? kd : 1), sizeof(double));
+      for (int j = kd - 1; j >= 0; --j) {
+        double s = gv[j];
+        for (int l = j + 1; l < kd; ++l) s -= HH(j, l) * y[l];
+        y[j] = s / HH(j, j);
+      }
+      for (int j = 0; j < kd; ++j)
+        for (long p = 0; p < nz; ++p) P[p] += y[j] * V[j][p];
+      free(y);
+    }
+  }
+#undef HH
+  if (iters) *iters = kd;
+  for (int k = 0; k <= K; ++k) free(V[k]);
+  free(V); free(W); free(H); free(cs); free(sn); free(gv); free(Gp);
+  return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Metrics and utilities                                                    */
+/* ------------------------------------------------------------------------ */
+void orc_transpose(int n_rows, int n_cols, const int *Ap, const int *Aj,
+                   const double *Ax, int *Tp, int *Tj, double *Tx) {
+  for (int j = 0; j <= n_cols; ++j) Tp[j] = 0;
+  for (int p = 0; p < Ap[n_rows]; ++p) Tp[Aj[p] + 1]++;
+  for (int j = 0; j < n_cols; ++j) Tp[j + 1] += Tp[j];
+  int *w = (int *)malloc((size_t)(n_cols > 0 ? n_cols : 1) * sizeof(int));
+  for (int j = 0; j < n_cols; ++j) w[j] = Tp[j];
+  for (int i = 0; i < n_rows; ++i)
+    for (int p = Ap[i]; p < Ap[i + 1]; ++p) {
+      int q = w[Aj[p]]++;
+      Tj[q] = i;
+      Tx[q] = Ax[p];
+    }
+  free(w);
+}
+
+double orc_energy(int n, int nc, const int *Ap, const int *Aj, const double *Ax,
+                  const int *Np, const int *Nj, const double *P) {
+  long nz = Np[n];
+  double *Y = (double *)malloc((size_t)(nz > 0 ? nz : 1) * sizeof(double));
+  orc_masked_product(n, nc, Ap, Aj, Ax, Np, Nj, P, Y);
+  double e = dot(nz, P, Y);
+  free(Y);
+  return e;
+}
+
+double orc_constraint_residual(int n, const int *Np, const int *Nj,
+                               const double *P, const double *Bc,
+                               const double *B, int nB) {
+  double mx = 0.0;
+  for (int i = 0; i < n; ++i)
+    for (int q = 0; q < nB; ++q) {
+      double s = 0.0;
+      for (int p = Np[i]; p < Np[i + 1]; ++p) s += P[p] * Bc[(long)Nj[p] * nB + q];
+      mx = fmax(mx, fabs(s - B[(long)i * nB + q]));
+    }
+  return mx;
+}
