@@ -25,11 +25,28 @@ static int cmp_int(const void *a, const void *b) {
   int x = *(const int *)a, y = *(const int *)b;
   return (x > y) - (x < y);
 }
+/* Frobenius inner product <X, Y> = sum over the pattern of X_ij Y_ij.
+ * Evaluated with compensated (Neumaier) summation: a plain running sum of
+ * 10^6 terms carries a relative error of ~1e-12 into P, which is larger than
+ * the FP64 parity tolerance, while the compensated sum is accurate to a few
+ * units in the last place whatever the length. */
 static double dot(long len, const double *x, const double *y) {
-  double s = 0.0;
-  for (long p = 0; p < len; ++p) s += x[p] * y[p];
-  return s;
+  double s = 0.0, c = 0.0;
+  for (long p = 0; p < len; ++p) {
+    const double v = x[p] * y[p];
+    const double t = s + v;
+    c += (fabs(s) >= fabs(v)) ? (s - t) + v : (v - t) + s;
+    s = t;
+  }
+  return s + c;
 }
+
+/* Stopping rules for iterations that have converged to round-off: CG stops
+ * once <R,R> <= CG_STOP <R0,R0> (the residual has dropped by 1e12), GMRES
+ * once its residual estimate is <= GM_STOP ||R0||.  Past that point both
+ * methods would only iterate on rounding noise. */
+#define CG_STOP 1e-24
+#define GM_STOP 1e-12
 
 /* ------------------------------------------------------------------------ */
 /* Strength of connection, Sec. 3.2.  Symmetric measure: entry (i,j) is     */
@@ -503,11 +520,12 @@ int orc_emin_cg(int n, int nc, const int *Ap, const int *Aj, const double *Ax,
   orc_project(n, Np, Nj, is_root, Bc, nB, Gp, Z);
   for (long p = 0; p < nz; ++p) { R[p] = -Z[p]; D[p] = R[p]; }
   double g = dot(nz, R, R);
+  const double g0 = g;
   if (gam) gam[0] = g;
   int rc = ORC_OK, it = 0;
   if (!isfinite(g)) rc = ORC_ENONFINITE;
   for (int k = 0; k < K && rc == ORC_OK; ++k) {
-    if (g == 0.0) break;
+    if (g <= CG_STOP * g0) break;
     orc_masked_product(n, nc, Ap, Aj, Ax, Np, Nj, D, Z);
     orc_project(n, Np, Nj, is_root, Bc, nB, Gp, Z);
     double dl = dot(nz, D, Z);
@@ -559,9 +577,10 @@ int orc_emin_cg_jvp(int n, int nc, const int *Ap, const int *Aj,
     dR[p] = -dZ[p]; dD[p] = dR[p];
   }
   double g = dot(nz, R, R), dg = 2.0 * dot(nz, R, dR);
+  const double g0 = g;
   int rc = isfinite(g) ? ORC_OK : ORC_ENONFINITE;
   for (int k = 0; k < K && rc == ORC_OK; ++k) {
-    if (g == 0.0) break;
+    if (g <= CG_STOP * g0) break;
     /* Z = Pi(A D), dZ = Pi(dA D + A dD) */
     orc_masked_product(n, nc, Ap, Aj, Ax, Np, Nj, D, Z);
     orc_project(n, Np, Nj, is_root, Bc, nB, Gp, Z);
@@ -656,7 +675,8 @@ int orc_emin_gmres(int n, int nc, const int *Ap, const int *Aj,
       gv[k] = cs[k] * gv[k];
       if (resid) resid[k + 1] = fabs(gv[k + 1]);
       kd = k + 1;
-      if (hn == 0.0) break; /* the Krylov space is invariant */
+      /* invariant Krylov space, or converged to round-off */
+      if (hn == 0.0 || fabs(gv[k + 1]) <= GM_STOP * beta) break;
       for (long p = 0; p < nz; ++p) V[k + 1][p] = W[p] / hn;
     }
     if (rc == ORC_OK) {

@@ -348,12 +348,11 @@ def test_cg_converges_to_kkt(case):
     st = _setup(A, B, m, 0.25 if m == 1 else 0.0, 1 if m == 1 else 2)
     assert st["rank_def"] == 0
     ref = brute.kkt_solution(A.to_dense(), st["Np"], st["Nj"], st["is_root"], st["Bc"], st["T"])
-    # stop at exact convergence: past it gamma is round-off and beta = gamma'/gamma
-    # amplifies noise outside the constraint space, as for any CG
-    _, hist = _cg(A, st, 200)
-    kstar = int(np.argmax(hist["gamma"] < 1e-26 * hist["gamma"][0]))
-    assert kstar > 0
-    P, info = _cg(A, st, kstar)
+    # the oracle stops by itself once <R,R> has dropped by 1e24 (past that
+    # point CG would iterate on round-off)
+    P, info = _cg(A, st, 400)
+    assert 0 < info["iters"] < 400
+    assert info["gamma"][info["iters"]] <= 1e-24 * info["gamma"][0]
     assert np.max(np.abs(P - ref)) < 1e-9
 
 
@@ -376,10 +375,8 @@ def test_cg_reaches_ideal_interpolation():
     r, c = brute.entries(Np, Nj)
     T = (c == agg[r]).astype(float)
     st2 = dict(Np=Np, Nj=Nj, is_root=is_root, nc=nc, Bc=np.zeros((nc, 1)), T=T)
-    _, hist = _cg(A, st2, 500, nB=0)
-    kstar = int(np.argmax(hist["gamma"] < 1e-26 * hist["gamma"][0]))
-    assert kstar > 0
-    P, info = _cg(A, st2, kstar, nB=0)
+    P, info = _cg(A, st2, 500, nB=0)
+    assert 0 < info["iters"] < 500
     Ad = A.to_dense()
     F = np.flatnonzero(is_root == 0)
     Cpts = roots                      # coarse column a injects at node roots[a]
@@ -438,11 +435,11 @@ def test_gmres_on_spd_reaches_cg_limit():
     ref = brute.kkt_solution(A.to_dense(), st["Np"], st["Nj"], st["is_root"], st["Bc"], st["T"])
     dim = brute.null_basis(brute.constraint_matrix(st["Np"], st["Nj"], st["is_root"], st["Bc"]),
                            st["T"].size).shape[1]
-    # stop once converged: later basis vectors would be normalised round-off
-    _, hist = _gmres(A, st, dim)
-    kstar = int(np.argmax(hist["resid"] < 1e-11 * hist["resid"][0]))
-    assert 0 < kstar <= dim
-    P, info = _gmres(A, st, kstar)
+    # the oracle stops once its residual estimate has dropped by 1e12: later
+    # basis vectors would be normalised round-off
+    P, info = _gmres(A, st, dim)
+    assert 0 < info["iters"] <= dim
+    assert info["resid"][info["iters"]] <= 1e-12 * info["resid"][0]
     assert np.max(np.abs(P - ref)) < 1e-9
 
 
