@@ -1,0 +1,193 @@
+"""Benchmark: energy-minimisation setup of the root-node interpolation on one GPU.
+
+Workload (one "step" = the whole hot path over one operator, inputs resident
+in HBM before timing): rotated anisotropic diffusion, Q1 FEM, eps = 1e-3,
+angle pi/8, 512 x 512 interior nodes (n = 262144, nnz(A) = 2353156), B = ones,
+symmetric strength theta = 0.1, pattern S^2 C, 6 CG iterations, FP64:
+
+    strength (two-phase) -> pattern (two-phase) -> tentative T, Bc
+    -> plan (positions + Gram data) -> 6 CG energy-minimisation steps
+
+The aggregation is an input (computed once on the host before timing).
+Printed: ONE JSON line.  value = seconds per step (lower is better).
+Extra fields: the same step with the FP32-mixed energy minimisation, the
+masked-product kernel's HBM roofline, and the CPU oracle on the same step.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "energy-min setup s & masked-SpGEMM HBM GB/s; FP32-mix vs FP64; fwd+bwd time"
+HBM_PEAK_GBS = 8000.0
+NX, EPS, PSI, THETA, DEGREE, ITERS = 512, 1e-3, np.pi / 8, 0.1, 2, 6
+
+
+def build_inputs():
+    import oracle as O  # noqa: F401  (aggregation input is computed by the library helper below)
+    import workloads as W
+    import paper_1610_03154_amd as R
+    import torch
+    A = W.q1_aniso(NX, EPS, PSI)
+    dA = R.DeviceCSR.from_host(A.rowptr, A.colind, A.vals)
+    ctx = R.Context()
+    Sp, Sj = ctx.strength(dA, THETA)
+    agg, roots = R.aggregate_host(Sp.cpu().numpy(), Sj.cpu().numpy())
+    B = torch.ones((A.n_rows, 1), dtype=torch.float64, device="cuda")
+    return dict(A=A, dA=dA, ctx=ctx, agg=torch.as_tensor(agg, device="cuda"),
+                roots=torch.as_tensor(roots, device="cuda"), B=B, agg_host=agg, roots_host=roots)
+
+
+def gpu_step(inp, precision):
+    """One pass of the hot path; returns (P, stats, plan)."""
+    import paper_1610_03154_amd as R
+    ctx, dA = inp["ctx"], inp["dA"]
+    Sp, Sj = ctx.strength(dA, THETA)
+    Np, Nj, is_root = ctx.pattern(Sp, Sj, inp["agg"], inp["roots"], DEGREE, 1)
+    T, Bc, _ = ctx.tentative(Np, Nj, is_root, inp["agg"], inp["roots"], 1, inp["B"])
+    plan = ctx.plan(dA, int(inp["roots"].numel()), Np, Nj, is_root, Bc)
+    P, stats, _ = ctx.energy_min(plan, dA.vals, T, R.RN_CG, ITERS, precision)
+    return P, stats, plan, (Np, Nj, is_root, T, Bc)
+
+
+def time_steps(inp, precision, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        P, st, plan, _ = gpu_step(inp, precision)
+        plan.close()
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record()
+    for _ in range(steps):
+        P, st, plan, aux = gpu_step(inp, precision)
+        plan.close()
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    return wall, ev0.elapsed_time(ev1) / 1e3 / steps, P, st, aux
+
+
+def roofline(inp, aux, precision, reps):
+    """Average duration of the masked-product kernel (Z = Pi(M(A X))) timed
+    with HIP events on the library's stream, back to back (warm caches)."""
+    import torch
+    import paper_1610_03154_amd as R
+    ctx, dA = inp["ctx"], inp["dA"]
+    Np, Nj, is_root, T, Bc = aux
+    plan = ctx.plan(dA, int(inp["roots"].numel()), Np, Nj, is_root, Bc)
+    X = torch.randn(Nj.numel(), dtype=torch.float64, device="cuda")
+    Z = ctx.masked_product(plan, dA.vals, X, True, precision)  # warm-up / allocation
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(reps):
+        ctx.masked_product(plan, dA.vals, X, True, precision)
+    ev1.record()
+    torch.cuda.synchronize()
+    dur = ev0.elapsed_time(ev1) / 1e3 / reps
+    _, st, _ = ctx.energy_min(plan, dA.vals, T, R.RN_CG, 1, precision)
+    plan.close()
+    return dur, st.spgemm_bytes, st.spgemm_flops
+
+
+def cpu_baseline(budget_s=12.0):
+    """The oracle (single-threaded C) on the same step, repeated for ~budget."""
+    import oracle as O
+    import workloads as W
+    A = W.q1_aniso(NX, EPS, PSI)
+    B = W.ones(A.n_rows)
+    Sp, Sj = O.strength(A.rowptr, A.colind, A.vals, 1, THETA)
+    agg, roots = O.aggregate(Sp, Sj)
+    times = []
+    t_end = time.perf_counter() + budget_s
+    while True:
+        t0 = time.perf_counter()
+        st = O.setup(A, B, 1, THETA, DEGREE, agg=agg, roots=roots)
+        O.emin_cg(A.rowptr, A.colind, A.vals, st["Np"], st["Nj"], st["is_root"], st["nc"], st["Bc"], 1, st["T"],
+                  ITERS)
+        times.append(time.perf_counter() - t0)
+        if time.perf_counter() > t_end or len(times) >= 50:
+            break
+    return float(np.median(times)), len(times)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--reps", type=int, default=200, help="launches for the kernel roofline timing")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--roofline-only", action="store_true", help="only the masked-product timing loop")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: the energy-minimisation path here is single-GPU "
+              "(see DESIGN.md for how it would shard); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_1610_03154_amd as R
+    torch.cuda.set_device(0)
+    inp = build_inputs()
+    if args.roofline_only:
+        P, st, plan, aux = gpu_step(inp, R.RN_FP64)
+        plan.close()
+        dur, nbytes, _ = roofline(inp, aux, R.RN_FP64, args.reps)
+        print(json.dumps({"kernel_avg_us": dur * 1e6, "bytes": nbytes, "GBps": nbytes / dur / 1e9}))
+        return
+    wall64, ev64, P64, st64, aux = time_steps(inp, R.RN_FP64, args.steps, args.warmup)
+    wall32, ev32, P32, st32, _ = time_steps(inp, R.RN_FP32_MIXED, args.steps, args.warmup)
+    dur, nbytes, flops = roofline(inp, aux, R.RN_FP64, args.reps)
+    dur32, nbytes32, _ = roofline(inp, aux, R.RN_FP32_MIXED, args.reps)
+    achieved = nbytes / dur / 1e9
+    p64 = P64.cpu().numpy()
+    mix_err = float(np.max(np.abs(P32.cpu().numpy() - p64)) / np.max(np.abs(p64)))
+    out = {
+        "metric": METRIC,
+        "value": ev64,
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ev64 * 1e3,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "q1_aniso_eps1e-3_pi8_512x512_cg6_fp64", "n": int(inp["A"].n_rows),
+                   "nnz_A": int(inp["A"].nnz), "nnz_N": int(aux[1].numel()), "iters": ITERS,
+                   "degree": DEGREE, "theta": THETA},
+        "wall_s_per_step": wall64,
+        "fp32_mixed_s_per_step": ev32,
+        "fp32_mixed_vs_fp64_time": ev32 / ev64,
+        "fp32_mixed_max_rel_dP_vs_fp64": mix_err,
+        "spgemm_GBps_fp64": achieved,
+        "spgemm_GBps_fp32_mixed": nbytes32 / dur32 / 1e9,
+        "spgemm_us_fp64": dur * 1e6,
+        "spgemm_us_fp32_mixed": dur32 * 1e6,
+        "fwd_bwd_s": None,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_spgemm<1,1,MODE_PRODUCT,false>", "bytes_per_launch": nbytes,
+                     "flops_per_launch": flops},
+    }
+    if not args.no_cpu:
+        med, cnt = cpu_baseline()
+        out["cpu_baseline"] = {"value": med, "unit": "s", "cores": 1, "kind": "oracle",
+                               "sample": f"the full step (strength, pattern, tentative, 6 CG steps) on the "
+                                         f"512x512 workload, median of {cnt} runs"}
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,241 @@
+/*
+ * rnamg.h -- C ABI of librnamg: the data-parallel hot path of root-node AMG
+ * interpolation setup on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Manteuffel, Olson, Schroder, Southworth, "A Root-Node Based
+ * Algebraic Multigrid Method", Sec. 3 (Alg. root_node_setup) and Sec. 4.
+ * Given a sparse operator A, its aggregates with root nodes, candidate
+ * vectors B and a pattern degree d, the library forms the pattern
+ * N = S^d C with root rows set to identity, the tentative T and coarse
+ * candidates Bc, and runs K energy-minimisation iterations (CG for SPD A,
+ * GMRES otherwise, and on A^T for R^T) that keep P on N with P Bc = B.
+ *
+ * General conventions (apply to every call):
+ *   - Pointers are DEVICE pointers unless the parameter says "host".
+ *   - Indices are int32, 0-based.  CSR column indices are sorted ascending
+ *     and unique within each row.  Every count of stored entries must be
+ *     below 2^31 (checked, RN_ELIMIT).
+ *   - Inputs are owned by the caller, read-only, and must stay valid until
+ *     the work queued on the context's stream has completed (and, for
+ *     arrays captured by a plan, until rn_plan_destroy).
+ *   - Outputs are allocated by the caller.  Calls whose output size is only
+ *     known after the computation are TWO-PHASE: the first call (output
+ *     index array NULL) computes the result into the context, writes the
+ *     row pointer array and the host-side count; the second call (same
+ *     context, same arguments, output array non-NULL) copies it out.
+ *   - All device work is queued on the context's HIP stream.  Calls that
+ *     return a size, a status found on the device or host statistics read
+ *     back from the device and therefore synchronise that stream.
+ *   - Every call returns rn_status.  Arguments are validated on the host
+ *     before any launch (RN_EINVAL).  Nothing aborts; no C++ exception
+ *     crosses the ABI.  rn_last_error() gives a message for the last
+ *     failure on the context.
+ *   - One context per stream; contexts share no state.  Calls on one
+ *     context must not overlap in time (the context owns scratch memory).
+ */
+#ifndef RNAMG_H
+#define RNAMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RN_OK = 0,
+  RN_EINVAL = 1,      /* malformed argument, detected on the host          */
+  RN_ENOMEM = 2,      /* device allocation of scratch memory failed        */
+  RN_ESINGULAR = 3,   /* singular root block of B (cannot normalise T)     */
+  RN_EBREAKDOWN = 4,  /* CG curvature <D, Pi(A D)> <= 0: A not SPD on V    */
+  RN_ENONFINITE = 5,  /* NaN or Inf in a Krylov scalar                     */
+  RN_EHIP = 6,        /* HIP runtime error                                 */
+  RN_ELIMIT = 7       /* a documented size limit was exceeded              */
+} rn_status;
+
+typedef enum { RN_CG = 0, RN_GMRES = 1 } rn_method;
+typedef enum { RN_FP64 = 0, RN_FP32_MIXED = 1 } rn_precision;
+
+typedef struct rn_ctx rn_ctx;
+typedef struct rn_plan rn_plan;
+typedef struct rn_tape rn_tape;
+
+/* Sparse operator A (Sec. 3 input A_l).  block_m = 1: scalar CSR with n
+ * rows; block_m = 2: node-blocked BSR (Sec. 5.5 elasticity) with n/2 node
+ * rows, nnz stored 2x2 blocks, values row-major inside a block.  Scalar DOF
+ * of node I and component c is 2*I + c. */
+typedef struct {
+  int32_t n;               /* scalar rows (= scalar columns)                */
+  int32_t block_m;         /* 1 or 2                                        */
+  int64_t nnz;             /* stored entries (m=1) or stored blocks (m=2)   */
+  const int32_t *rowptr;   /* device, n/block_m + 1                         */
+  const int32_t *colind;   /* device, nnz                                   */
+  const double *vals;      /* device, nnz*block_m*block_m (may be NULL where
+                              only the structure is used)                   */
+} rn_matrix;
+
+/* Statistics of one rn_energy_min call, for batch entry 0. */
+typedef struct {
+  int32_t iters_done;          /* Krylov steps completed                    */
+  int32_t rank_deficient_rows; /* F rows whose Gram matrix took the
+                                  pseudo-inverse fallback                   */
+  int32_t status_code;         /* device-side status (an rn_status value)   */
+  int32_t reserved;
+  double first;                /* CG: <R0,R0>; GMRES: ||Pi(A T)||_F         */
+  double last;                 /* CG: last <R,R>; GMRES: last residual      */
+  double spgemm_bytes;         /* algorithmic bytes of one masked product   */
+  double spgemm_flops;         /* 2 x multiply-adds of one masked product   */
+} rn_emin_stats;
+
+/* ---- context ----------------------------------------------------------- */
+/* Create a context bound to hip_stream (a hipStream_t; NULL = the null
+ * stream) on the current device.  The context owns grow-only scratch. */
+rn_status rn_create(rn_ctx **ctx, void *hip_stream);
+/* Free all scratch owned by the context.  Plans made on it must be
+ * destroyed first. */
+void rn_destroy(rn_ctx *ctx);
+rn_status rn_set_stream(rn_ctx *ctx, void *hip_stream);
+/* Message of the last failure on ctx ("" if none).  Valid until the next
+ * call on ctx. */
+const char *rn_last_error(const rn_ctx *ctx);
+/* Library version string. */
+const char *rn_version(void);
+
+/* ---- a1/a2: strength of connection (Sec. 3.2, strength and amalgamate
+ * steps of Alg. root_node_setup) --------------------------------------- */
+/* Symmetric measure: stored (i,j) is strong when a_ij^2 >= theta^2 |a_ii
+ * a_jj| (no fused multiply-add); (i,i) is always strong.  For block_m = 2
+ * a node pair is strong when any DOF entry of its block is (boolean
+ * amalgamation).  The result is symmetrised, S <- S u S^T, and returned as
+ * a boolean node graph (n/block_m node rows, diagonal included).
+ * TWO-PHASE.  S_rowptr (n/block_m + 1) is written in phase 1 together with
+ * *nnz_S (host); S_colind (nnz_S) in phase 2.  theta >= 0. */
+rn_status rn_strength(rn_ctx *ctx, const rn_matrix *A, double theta,
+                      int32_t *S_rowptr, int32_t *S_colind, int64_t *nnz_S);
+
+/* ---- aggregation (Sec. 3.3), host helper --------------------------------
+ * Standard greedy aggregation on the HOST (host pointers): sweep 1 makes a
+ * node whose strong neighbours are all free the root of a new aggregate
+ * holding them; sweep 2 attaches each left-over node to the aggregate of
+ * its lowest-index neighbour aggregated in sweep 1; sweep 3 makes each node
+ * still free the root of a new aggregate with its free neighbours.
+ * agg: n_nodes, roots: room for n_nodes.  The GPU path takes agg/roots as
+ * inputs; this helper is inherently sequential. */
+rn_status rn_aggregate_host(int32_t n_nodes, const int32_t *S_rowptr_host,
+                            const int32_t *S_colind_host, int32_t *agg_host,
+                            int32_t *roots_host, int32_t *n_agg_host);
+
+/* ---- a3/a4: interpolation pattern (Sec. 3.4) ----------------------------
+ * Nodal pattern N_node = S^d C (boolean product, d >= 0, S with diagonal),
+ * then unamalgamate (DOF (i,j) present when node entry (i/m, j/m) is) and
+ * root_node_pattern (each root DOF row becomes the identity row of its
+ * coarse DOF m*agg + c).  Output: DOF pattern, n = m*n_nodes rows, m*n_agg
+ * columns, sorted rows; is_root[i] = 1 for root DOF rows.
+ * TWO-PHASE.  Phase 1 writes N_rowptr (n+1), is_root (n) and *nnz_N;
+ * phase 2 writes N_colind.  Limit: a nodal row may gather at most 512
+ * candidate entries in one expansion step (RN_ELIMIT). */
+rn_status rn_pattern(rn_ctx *ctx, int32_t n_nodes, const int32_t *S_rowptr,
+                     const int32_t *S_colind, const int32_t *agg,
+                     const int32_t *roots, int32_t n_agg, int32_t degree,
+                     int32_t block_m, int32_t *N_rowptr, int32_t *N_colind,
+                     uint8_t *is_root, int64_t *nnz_N);
+
+/* ---- a5/a6: inject (Sec. 3.6, Eq. root-nodeform, Eq. Tproj) -------------
+ * Bc[m*a + c, :] = B[m*roots[a] + c, :] (n_agg*m x nB, row-major).
+ * T (aligned with N): root rows exactly 1; F row i in aggregate a gets
+ * (B[i,0:m] inv(B[root block,0:m]))_c' at columns m*a + c', zero elsewhere.
+ * When nB > m each F row then takes the minimum-norm update of Eq. Tproj so
+ * that T Bc = B (least squares through the Gram pseudo-inverse where the
+ * row's pattern cannot carry all candidates).  B is n x nB row-major,
+ * m <= nB <= 4.  *rank_deficient (host, nullable) counts F rows whose Gram
+ * matrix took the eigen pseudo-inverse (synchronises the stream).
+ * RN_ESINGULAR if a root block of B is singular. */
+rn_status rn_tentative(rn_ctx *ctx, int32_t n, int32_t block_m,
+                       const int32_t *N_rowptr, const int32_t *N_colind,
+                       int64_t nnz_N, const uint8_t *is_root,
+                       const int32_t *agg, const int32_t *roots, int32_t n_agg,
+                       const double *B, int32_t nB, double *T, double *Bc,
+                       int32_t *rank_deficient);
+
+/* ---- transpose (needed for R^T on A^T, Alg. root_node_setup non-symmetric
+ * branch, and for the adjoint) ------------------------------------------
+ * Scalar CSR only (block_m = 1).  AT_rowptr: n+1, AT_colind/AT_vals: nnz
+ * (AT_vals may be NULL), perm (nullable): perm[q] = index in A of the q-th
+ * entry of A^T, so that AT_vals[q] = A.vals[perm[q]]. */
+rn_status rn_transpose(rn_ctx *ctx, const rn_matrix *A, int32_t *AT_rowptr,
+                       int32_t *AT_colind, double *AT_vals, int32_t *perm);
+
+/* ---- plan: the symbolic part of energy minimisation ---------------------
+ * Binds the structure of A (values unused) to the pattern N and the coarse
+ * candidates: per F row the Gram pseudo-inverse of B_J^T B_J (projection
+ * Pi_B of Sec. 3.6), and for every pattern entry (i,j) and every stored
+ * A(i,k) the position of j in N(k) (the intersection the masked product
+ * needs).  The plan keeps the device pointers it was given (A->rowptr,
+ * A->colind, N_rowptr, N_colind, is_root, Bc): they must stay valid until
+ * rn_plan_destroy.  Limits (RN_ELIMIT): rows of N hold at most 253
+ * entries (block_m = 1) or 253 nodal entries (block_m = 2); 1 <= nB <= 4;
+ * block_m = 2 requires nB >= 2. */
+rn_status rn_plan_create(rn_ctx *ctx, const rn_matrix *A, int32_t n_cols,
+                         const int32_t *N_rowptr, const int32_t *N_colind,
+                         int64_t nnz_N, const uint8_t *is_root,
+                         const double *Bc, int32_t nB, rn_plan **plan);
+void rn_plan_destroy(rn_plan *plan);
+/* Bytes of device memory held by the plan (codes, Gram data, workspace). */
+size_t rn_plan_bytes(const rn_plan *plan);
+
+/* ---- a7/a8: one masked product (Sec. 3.6: the smoothing product whose
+ * fill outside N is dropped, followed by the constraint projection) -------
+ * Z = M(A X): (A X)_ij for (i,j) in N on F rows, zero on root rows; when
+ * project != 0, each F row then loses its least-squares component along
+ * B_J (Pi_B).  A_vals: [batch][nnz(A) m m], X and Z: [batch][nnz_N].
+ * RN_FP32_MIXED rounds A and X to FP32 and accumulates in FP32; the
+ * projection runs in FP64 on the FP32 product.  Asynchronous (no stream
+ * synchronisation). */
+rn_status rn_masked_product(rn_ctx *ctx, rn_plan *plan, const double *A_vals,
+                            int32_t batch, const double *X, int32_t project,
+                            rn_precision precision, double *Z);
+
+/* ---- a7-a11: energy minimisation (Sec. 3.6 improve, Sec. 4) -------------
+ * P = T + U minimising trace(P^T A P) (RN_CG) or ||Pi(A P)||_F (RN_GMRES)
+ * over U in the Krylov space of Pi A Pi started from -Pi(A T), after
+ * `iters` steps; Pi zeroes root rows and removes, row by row, the
+ * least-squares component along B_J (so U Bc = 0 and root rows stay 1).
+ * A_vals: [batch][nnz(A) * m * m] values for the plan's structure (batch
+ * entries share structure, T and Bc).  T: [nnz_N].  P: [batch][nnz_N].
+ * RN_FP32_MIXED: the masked products read FP32 copies of A and of the
+ * search direction and accumulate in FP32; projection, inner products,
+ * step lengths and the P, R, D iterates stay FP64 (RN_CG only).
+ * hist (device, nullable): [batch][3*iters + 1] doubles: CG: gamma_0..K,
+ * delta_0..K-1, alpha_0..K-1; GMRES: residual estimates 0..K then zeros.
+ * stats (host, nullable).  The call synchronises the stream to read the
+ * device status: RN_EBREAKDOWN / RN_ENONFINITE report the first failing
+ * batch entry (its P holds the last good iterate).
+ * tape (nullable, RN_CG + RN_FP64 only): records what rn_energy_min_bwd
+ * needs (scalars and the iterates R_k, D_k). */
+rn_status rn_energy_min(rn_ctx *ctx, rn_plan *plan, const double *A_vals,
+                        int32_t batch, const double *T, rn_method method,
+                        int32_t iters, rn_precision precision, double *P,
+                        double *hist, rn_emin_stats *stats, rn_tape *tape);
+
+/* ---- a12: adjoint of the CG energy minimisation (map A values -> P) -----
+ * Tape for `batch` problems of `iters` CG steps on `plan`; holds the Krylov
+ * scalars and the iterates R_k, D_k of every step (checkpoint interval 1;
+ * Z_k = Pi(A D_k) is recomputed in the reverse sweep). */
+rn_status rn_tape_create(rn_ctx *ctx, rn_plan *plan, int32_t batch,
+                         int32_t iters, rn_tape **tape);
+void rn_tape_destroy(rn_tape *tape);
+/* Given P_bar [batch][nnz_N] (dL/dP), write A_bar [batch][nnz(A)]
+ * = dL/dA_vals for the stored entries of A (each stored value an
+ * independent variable).  plan_T is a plan on A^T (same N, is_root, Bc)
+ * whose A^T structure came from rn_transpose with permutation perm
+ * (nnz(A)).  Scalar CSR only. */
+rn_status rn_energy_min_bwd(rn_ctx *ctx, rn_plan *plan, rn_plan *plan_T,
+                            const int32_t *perm, rn_tape *tape,
+                            const double *A_vals, const double *P_bar,
+                            double *A_bar);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RNAMG_H */

@@ -269,6 +269,23 @@ static void jacobi_eig(int k, double *a, double *v) {
   }
 }
 
+/* Eigen pseudo-inverse of a symmetric Gram matrix: eigenvalues above
+ * 1e-12 lambda_max are inverted, the rest dropped. */
+static void orc_gram_pinv_eig(int nB, const double *G, double *Gp) {
+  double a[NBMAX * NBMAX], v[NBMAX * NBMAX];
+  memcpy(a, G, sizeof(double) * (size_t)(nB * nB));
+  jacobi_eig(nB, a, v);
+  double lmax = 0.0;
+  for (int i = 0; i < nB; ++i) lmax = fmax(lmax, a[i * nB + i]);
+  for (int i = 0; i < nB * nB; ++i) Gp[i] = 0.0;
+  for (int l = 0; l < nB; ++l) {
+    double lam = a[l * nB + l];
+    if (!(lam > 1e-12 * lmax) || lam <= 0.0) continue;
+    for (int i = 0; i < nB; ++i)
+      for (int j = 0; j < nB; ++j) Gp[i * nB + j] += v[i * nB + l] * v[j * nB + l] / lam;
+  }
+}
+
 int orc_gram_pinv(int nB, const double *G, double *Gp) {
   if (nB <= 0) return 0;
   double L[NBMAX * NBMAX], D[NBMAX], maxd = 0.0;
@@ -306,38 +323,97 @@ int orc_gram_pinv(int nB, const double *G, double *Gp) {
       }
     return 0;
   }
-  double a[NBMAX * NBMAX], v[NBMAX * NBMAX];
-  memcpy(a, G, sizeof(double) * (size_t)(nB * nB));
-  jacobi_eig(nB, a, v);
-  double lmax = 0.0;
-  for (int i = 0; i < nB; ++i) lmax = fmax(lmax, a[i * nB + i]);
-  for (int i = 0; i < nB * nB; ++i) Gp[i] = 0.0;
-  for (int l = 0; l < nB; ++l) {
-    double lam = a[l * nB + l];
-    if (!(lam > 1e-12 * lmax) || lam <= 0.0) continue;
-    for (int i = 0; i < nB; ++i)
-      for (int j = 0; j < nB; ++j) Gp[i * nB + j] += v[i * nB + l] * v[j * nB + l] / lam;
+  orc_gram_pinv_eig(nB, G, Gp);
+  return 1;
+}
+
+/* Least-squares data of one F row i: G^+ for G = B_J^T B_J, where B_J is the
+ * len x nB matrix of the coarse candidates at the row's pattern columns.
+ * Formed through a Householder QR, B_J = Q R, as G^+ = R^-1 R^-T: its
+ * rounding error grows like cond(B_J) rather than cond(B_J)^2 for the normal
+ * equations (cond(G) ~ 1e5 for rigid-body modes, where forming G^-1 from G
+ * alone was measured to move P by 2e-11).  Rank test: every R_kk^2 must
+ * exceed 1e-12 max_q ||B_J e_q||^2 (in exact arithmetic R_kk^2 are the
+ * pivots of G's LDL^T and the column norms its diagonal); otherwise the
+ * eigen pseudo-inverse of G = R^T R is used.  W: scratch of len * nB.
+ * Returns 1 when the fallback was taken. */
+static int row_pinv(int len, const int *J, const double *Bc, int nB, double *W, double *Gp) {
+  double R[NBMAX * NBMAX], cmax = 0.0;
+  for (int r = 0; r < len; ++r)
+    for (int q = 0; q < nB; ++q) W[(long)r * nB + q] = Bc[(long)J[r] * nB + q];
+  for (int q = 0; q < nB; ++q) {
+    double s = 0.0;
+    for (int r = 0; r < len; ++r) s += W[(long)r * nB + q] * W[(long)r * nB + q];
+    cmax = fmax(cmax, s);
   }
+  for (int q = 0; q < nB * nB; ++q) R[q] = 0.0;
+  for (int k = 0; k < nB && k < len; ++k) {
+    /* Householder reflector zeroing column k below row k */
+    double nx = 0.0;
+    for (int r = k; r < len; ++r) nx += W[(long)r * nB + k] * W[(long)r * nB + k];
+    nx = sqrt(nx);
+    const double x0 = W[(long)k * nB + k];
+    const double alpha = x0 >= 0.0 ? -nx : nx;
+    double vv = 0.0;
+    W[(long)k * nB + k] = x0 - alpha; /* v stored in place, column k rows k.. */
+    for (int r = k; r < len; ++r) vv += W[(long)r * nB + k] * W[(long)r * nB + k];
+    for (int j = k + 1; j < nB; ++j) {
+      if (vv == 0.0) break;
+      double w = 0.0;
+      for (int r = k; r < len; ++r) w += W[(long)r * nB + k] * W[(long)r * nB + j];
+      const double f = 2.0 * w / vv;
+      for (int r = k; r < len; ++r) W[(long)r * nB + j] -= f * W[(long)r * nB + k];
+    }
+    R[k * nB + k] = alpha;
+    for (int j = k + 1; j < nB; ++j) R[k * nB + j] = W[(long)k * nB + j];
+  }
+  int ok = cmax > 0.0 && len >= nB;
+  for (int k = 0; k < nB && ok; ++k)
+    if (!(R[k * nB + k] * R[k * nB + k] > 1e-12 * cmax)) ok = 0;
+  if (ok) {
+    /* Ri = R^-1 (upper triangular), G^+ = Ri Ri^T */
+    double Ri[NBMAX * NBMAX];
+    for (int q = 0; q < nB * nB; ++q) Ri[q] = 0.0;
+    for (int c = 0; c < nB; ++c) {
+      Ri[c * nB + c] = 1.0 / R[c * nB + c];
+      for (int r = c - 1; r >= 0; --r) {
+        double s = 0.0;
+        for (int l = r + 1; l <= c; ++l) s += R[r * nB + l] * Ri[l * nB + c];
+        Ri[r * nB + c] = -s / R[r * nB + r];
+      }
+    }
+    for (int q = 0; q < nB; ++q)
+      for (int r = 0; r < nB; ++r) {
+        double s = 0.0;
+        for (int l = 0; l < nB; ++l) s += Ri[q * nB + l] * Ri[r * nB + l];
+        Gp[q * nB + r] = s;
+      }
+    return 0;
+  }
+  double G[NBMAX * NBMAX];
+  for (int q = 0; q < nB; ++q)
+    for (int r = 0; r < nB; ++r) {
+      double s = 0.0;
+      for (int l = 0; l < nB; ++l) s += R[l * nB + q] * R[l * nB + r];
+      G[q * nB + r] = s;
+    }
+  orc_gram_pinv_eig(nB, G, Gp);
   return 1;
 }
 
 int orc_gram_rows(int n, const int *Np, const int *Nj,
                   const unsigned char *is_root, const double *Bc, int nB,
                   double *Gp) {
-  int bad = 0;
-  double G[NBMAX * NBMAX];
+  int bad = 0, maxlen = 1;
+  for (int i = 0; i < n; ++i) maxlen = Np[i + 1] - Np[i] > maxlen ? Np[i + 1] - Np[i] : maxlen;
+  double *W = (double *)malloc((size_t)maxlen * (nB > 0 ? nB : 1) * sizeof(double));
   for (int i = 0; i < n; ++i) {
     double *gi = Gp + (long)i * nB * nB;
     for (int q = 0; q < nB * nB; ++q) gi[q] = 0.0;
     if (is_root[i] || nB == 0) continue;
-    for (int q = 0; q < nB * nB; ++q) G[q] = 0.0;
-    for (int p = Np[i]; p < Np[i + 1]; ++p) {
-      const double *b = Bc + (long)Nj[p] * nB;
-      for (int r = 0; r < nB; ++r)
-        for (int c = 0; c < nB; ++c) G[r * nB + c] += b[r] * b[c];
-    }
-    bad += orc_gram_pinv(nB, G, gi);
+    bad += row_pinv(Np[i + 1] - Np[i], Nj + Np[i], Bc, nB, W, gi);
   }
+  free(W);
   return bad;
 }
 
@@ -469,16 +545,13 @@ int orc_tentative(int n, int m, const int *Np, const int *Nj,
   free(binv);
   int bad = 0;
   if (nB > m) {
-    double G[NBMAX * NBMAX], Gp[NBMAX * NBMAX], r[NBMAX], y[NBMAX];
+    double Gp[NBMAX * NBMAX], r[NBMAX], y[NBMAX];
+    int maxlen = 1;
+    for (int i = 0; i < n; ++i) maxlen = Np[i + 1] - Np[i] > maxlen ? Np[i + 1] - Np[i] : maxlen;
+    double *W = (double *)malloc((size_t)maxlen * nB * sizeof(double));
     for (int i = 0; i < n; ++i) {
       if (is_root[i]) continue;
-      for (int q = 0; q < nB * nB; ++q) G[q] = 0.0;
-      for (int p = Np[i]; p < Np[i + 1]; ++p) {
-        const double *b = Bc + (long)Nj[p] * nB;
-        for (int u = 0; u < nB; ++u)
-          for (int v = 0; v < nB; ++v) G[u * nB + v] += b[u] * b[v];
-      }
-      bad += orc_gram_pinv(nB, G, Gp);
+      bad += row_pinv(Np[i + 1] - Np[i], Nj + Np[i], Bc, nB, W, Gp);
       for (int q = 0; q < nB; ++q) {
         double s = 0.0;
         for (int p = Np[i]; p < Np[i + 1]; ++p) s += T[p] * Bc[(long)Nj[p] * nB + q];
@@ -494,6 +567,7 @@ int orc_tentative(int n, int m, const int *Np, const int *Nj,
         T[p] += u;
       }
     }
+    free(W);
   }
   (void)nc;
   if (rank_def) *rank_def = bad;

@@ -1,0 +1,305 @@
+"""Root-node AMG interpolation setup on MI355X: Python binding of librnamg.
+
+The functions here only marshal arguments to the C ABI (include/rnamg.h);
+every step of the path runs in the library's HIP kernels.  torch provides
+device memory and the stream.  There is no CPU fallback: without the built
+library, importing the binding's entry points raises.
+"""
+from __future__ import annotations
+
+import atexit
+import ctypes as C
+import sys
+import weakref
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import _lib as L
+from ._lib import RN_CG, RN_GMRES, RN_FP64, RN_FP32_MIXED  # noqa: F401
+
+__all__ = ["RnError", "DeviceCSR", "Context", "Plan", "aggregate_host", "setup", "RN_CG", "RN_GMRES",
+           "RN_FP64", "RN_FP32_MIXED"]
+
+
+_LIVE_PLANS: "weakref.WeakSet" = weakref.WeakSet()
+_LIVE_CTX: "weakref.WeakSet" = weakref.WeakSet()
+
+
+_EXIT_HOOK = []
+
+
+def _close_all():
+    # free library objects while the HIP runtime is still alive: plans first,
+    # then the contexts they were made on
+    for p in list(_LIVE_PLANS):
+        p.close()
+    for c in list(_LIVE_CTX):
+        c.close()
+
+
+def _register_exit_hook():
+    # registered after torch is imported, so it runs before torch's own exit
+    # handlers (atexit runs handlers last-registered first)
+    if not _EXIT_HOOK:
+        atexit.register(_close_all)
+        _EXIT_HOOK.append(True)
+
+
+class RnError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{L.STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t):
+    return C.c_void_p(0 if t is None else t.data_ptr())
+
+
+@dataclass
+class DeviceCSR:
+    """Device matrix: block_m = 1 scalar CSR, block_m = 2 node-blocked BSR."""
+    n: int
+    block_m: int
+    rowptr: "object"
+    colind: "object"
+    vals: "object"
+
+    @property
+    def nnz(self) -> int:
+        return int(self.colind.numel())
+
+    def desc(self) -> L.rn_matrix:
+        return L.rn_matrix(self.n, self.block_m, self.nnz, self.rowptr.data_ptr(), self.colind.data_ptr(),
+                           0 if self.vals is None else self.vals.data_ptr())
+
+    @staticmethod
+    def from_host(rowptr, colind, vals, n=None, block_m=1, device="cuda"):
+        torch = _torch()
+        rp = torch.as_tensor(np.ascontiguousarray(rowptr, np.int32), device=device)
+        cj = torch.as_tensor(np.ascontiguousarray(colind, np.int32), device=device)
+        vv = None if vals is None else torch.as_tensor(np.ascontiguousarray(vals, np.float64), device=device)
+        nrow = (rp.numel() - 1) * block_m if n is None else n
+        return DeviceCSR(nrow, block_m, rp, cj, vv)
+
+
+class Plan:
+    """Symbolic part of the energy minimisation bound to (A structure, N, Bc)."""
+
+    def __init__(self, ctx: "Context", handle, keep):
+        self.ctx = ctx
+        self.handle = handle
+        self._keep = keep  # tensors whose device pointers the plan holds
+        _LIVE_PLANS.add(self)
+
+    def bytes(self) -> int:
+        return int(L.lib().rn_plan_bytes(self.handle))
+
+    def close(self):
+        if self.handle:
+            L.lib().rn_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        if sys.is_finalizing():
+            return
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Context:
+    """An rn_ctx bound to a HIP stream (default: torch's current stream)."""
+
+    def __init__(self, stream=None):
+        torch = _torch()
+        if not torch.cuda.is_available():
+            raise RuntimeError("librnamg needs a GPU (torch.cuda.is_available() is False)")
+        _register_exit_hook()
+        self.torch = torch
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = C.c_void_p()
+        st = L.lib().rn_create(C.byref(h), C.c_void_p(self.stream.cuda_stream))
+        if st != L.RN_OK:
+            raise RnError(st, "rn_create failed")
+        self.h = h
+        _LIVE_CTX.add(self)
+
+    def close(self):
+        if getattr(self, "h", None):
+            for p in list(_LIVE_PLANS):  # plans made on this context go first
+                if p.ctx is self:
+                    p.close()
+            L.lib().rn_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        if sys.is_finalizing():
+            return
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st, what):
+        if st != L.RN_OK:
+            raise RnError(st, f"{what}: {L.lib().rn_last_error(self.h).decode()}")
+
+    # -- a1/a2 ---------------------------------------------------------------
+    def strength(self, A: DeviceCSR, theta: float):
+        torch = self.torch
+        nn = A.n // A.block_m
+        Sp = torch.empty(nn + 1, dtype=torch.int32, device="cuda")
+        nnz = C.c_int64()
+        d = A.desc()
+        self._check(L.lib().rn_strength(self.h, C.byref(d), C.c_double(theta), _ptr(Sp), None, C.byref(nnz)),
+                    "rn_strength")
+        Sj = torch.empty(max(nnz.value, 1), dtype=torch.int32, device="cuda")
+        self._check(L.lib().rn_strength(self.h, C.byref(d), C.c_double(theta), _ptr(Sp), _ptr(Sj), C.byref(nnz)),
+                    "rn_strength")
+        return Sp, Sj[:nnz.value]
+
+    # -- a3/a4 ---------------------------------------------------------------
+    def pattern(self, Sp, Sj, agg, roots, degree: int, block_m: int):
+        torch = self.torch
+        nn = Sp.numel() - 1
+        n = nn * block_m
+        n_agg = int(roots.numel())
+        Np = torch.empty(n + 1, dtype=torch.int32, device="cuda")
+        is_root = torch.empty(max(n, 1), dtype=torch.uint8, device="cuda")
+        nnz = C.c_int64()
+        args = (self.h, nn, _ptr(Sp), _ptr(Sj), _ptr(agg), _ptr(roots), n_agg, degree, block_m)
+        self._check(L.lib().rn_pattern(*args, _ptr(Np), None, _ptr(is_root), C.byref(nnz)), "rn_pattern")
+        Nj = torch.empty(max(nnz.value, 1), dtype=torch.int32, device="cuda")
+        self._check(L.lib().rn_pattern(*args, _ptr(Np), _ptr(Nj), _ptr(is_root), C.byref(nnz)), "rn_pattern")
+        return Np, Nj[:nnz.value], is_root[:n]
+
+    # -- a5/a6 ---------------------------------------------------------------
+    def tentative(self, Np, Nj, is_root, agg, roots, block_m: int, B):
+        torch = self.torch
+        n = Np.numel() - 1
+        nB = int(B.shape[1])
+        n_agg = int(roots.numel())
+        T = torch.empty(max(Nj.numel(), 1), dtype=torch.float64, device="cuda")
+        Bc = torch.empty((max(block_m * n_agg, 1), nB), dtype=torch.float64, device="cuda")
+        rd = C.c_int32()
+        self._check(L.lib().rn_tentative(self.h, n, block_m, _ptr(Np), _ptr(Nj), Nj.numel(), _ptr(is_root),
+                                         _ptr(agg), _ptr(roots), n_agg, _ptr(B), nB, _ptr(T), _ptr(Bc),
+                                         C.byref(rd)), "rn_tentative")
+        return T[:Nj.numel()], Bc[:block_m * n_agg], rd.value
+
+    # -- transpose -----------------------------------------------------------
+    def transpose(self, A: DeviceCSR):
+        torch = self.torch
+        ATp = torch.empty(A.n + 1, dtype=torch.int32, device="cuda")
+        ATj = torch.empty(max(A.nnz, 1), dtype=torch.int32, device="cuda")
+        ATx = torch.empty(max(A.nnz, 1), dtype=torch.float64, device="cuda")
+        perm = torch.empty(max(A.nnz, 1), dtype=torch.int32, device="cuda")
+        d = A.desc()
+        self._check(L.lib().rn_transpose(self.h, C.byref(d), _ptr(ATp), _ptr(ATj), _ptr(ATx), _ptr(perm)),
+                    "rn_transpose")
+        return DeviceCSR(A.n, 1, ATp, ATj[:A.nnz], ATx[:A.nnz]), perm[:A.nnz]
+
+    # -- plan ----------------------------------------------------------------
+    def plan(self, A: DeviceCSR, n_cols: int, Np, Nj, is_root, Bc) -> Plan:
+        h = C.c_void_p()
+        d = A.desc()
+        nB = int(Bc.shape[1])
+        self._check(L.lib().rn_plan_create(self.h, C.byref(d), n_cols, _ptr(Np), _ptr(Nj), Nj.numel(),
+                                           _ptr(is_root), _ptr(Bc), nB, C.byref(h)), "rn_plan_create")
+        return Plan(self, h, (A.rowptr, A.colind, Np, Nj, is_root, Bc))
+
+    # -- a7/a8 ---------------------------------------------------------------
+    def masked_product(self, plan: Plan, A_vals, X, project=True, precision=RN_FP64):
+        torch = self.torch
+        batch = 1 if X.dim() == 1 else X.shape[0]
+        Z = torch.empty_like(X)
+        self._check(L.lib().rn_masked_product(self.h, plan.handle, _ptr(A_vals), batch, _ptr(X), int(project),
+                                              precision, _ptr(Z)), "rn_masked_product")
+        return Z
+
+    # -- a7-a11 --------------------------------------------------------------
+    def energy_min(self, plan: Plan, A_vals, T, method=RN_CG, iters=4, precision=RN_FP64, batch=None,
+                   want_hist=False, out=None):
+        torch = self.torch
+        if batch is None:
+            batch = 1 if A_vals.dim() == 1 else A_vals.shape[0]
+        nz = T.numel()
+        P = out if out is not None else torch.empty((batch, nz) if batch > 1 else (nz,), dtype=torch.float64,
+                                                    device="cuda")
+        hist = torch.empty((batch, 3 * iters + 1), dtype=torch.float64, device="cuda") if want_hist else None
+        stats = L.rn_emin_stats()
+        self._check(L.lib().rn_energy_min(self.h, plan.handle, _ptr(A_vals), batch, _ptr(T), method, iters,
+                                          precision, _ptr(P), _ptr(hist), C.byref(stats), None),
+                    "rn_energy_min")
+        return P, stats, hist
+
+
+def aggregate_host(Sp, Sj):
+    """Greedy root-node aggregation on the host (library routine)."""
+    Sp = np.ascontiguousarray(Sp, np.int32)
+    Sj = np.ascontiguousarray(Sj, np.int32)
+    nn = Sp.size - 1
+    agg = np.empty(max(nn, 1), np.int32)
+    roots = np.empty(max(nn, 1), np.int32)
+    na = C.c_int32()
+    st = L.lib().rn_aggregate_host(nn, Sp.ctypes.data_as(C.c_void_p), Sj.ctypes.data_as(C.c_void_p),
+                                   agg.ctypes.data_as(C.c_void_p), roots.ctypes.data_as(C.c_void_p),
+                                   C.byref(na))
+    if st != L.RN_OK:
+        raise RnError(st, "rn_aggregate_host: malformed strength graph")
+    return agg[:nn].copy(), roots[:na.value].copy()
+
+
+@dataclass
+class Setup:
+    """Everything the path produced for one operator."""
+    A: DeviceCSR
+    S: tuple
+    agg: "object"
+    roots: "object"
+    N: tuple        # (rowptr, colind, is_root)
+    T: "object"
+    Bc: "object"
+    plan: Plan
+    P: "object"
+    stats: "object"
+    RT: "object" = None
+    stats_RT: "object" = None
+    rank_deficient: int = 0
+
+
+def setup(ctx: Context, A: DeviceCSR, B, theta=0.0, degree=2, iters=4, method=RN_CG, precision=RN_FP64,
+          Bhat=None, agg=None, roots=None) -> Setup:
+    """strength -> aggregation (host, when not given) -> pattern -> T -> plan
+    -> energy minimisation (and R^T on A^T when Bhat is given)."""
+    torch = ctx.torch
+    m = A.block_m
+    Sp, Sj = ctx.strength(A, theta)
+    if agg is None:
+        a, r = aggregate_host(Sp.cpu().numpy(), Sj.cpu().numpy())
+        agg = torch.as_tensor(a, device="cuda")
+        roots = torch.as_tensor(r, device="cuda")
+    Np, Nj, is_root = ctx.pattern(Sp, Sj, agg, roots, degree, m)
+    T, Bc, rd = ctx.tentative(Np, Nj, is_root, agg, roots, m, B)
+    nc = m * int(roots.numel())
+    plan = ctx.plan(A, nc, Np, Nj, is_root, Bc)
+    P, stats, _ = ctx.energy_min(plan, A.vals, T, method, iters, precision)
+    res = Setup(A, (Sp, Sj), agg, roots, (Np, Nj, is_root), T, Bc, plan, P, stats, rank_deficient=rd)
+    if Bhat is not None:
+        AT, _ = ctx.transpose(A)
+        That, Bch, _ = ctx.tentative(Np, Nj, is_root, agg, roots, m, Bhat)
+        planT = ctx.plan(AT, nc, Np, Nj, is_root, Bch)
+        RT, sRT, _ = ctx.energy_min(planT, AT.vals, That, method, iters, precision)
+        res.RT, res.stats_RT = RT, sRT
+        res.planT = planT
+        res.AT = AT
+        res.That = That
+        res.Bch = Bch
+    return res

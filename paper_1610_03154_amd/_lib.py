@@ -1,0 +1,75 @@
+"""ctypes declarations of librnamg (include/rnamg.h).
+
+Argument marshalling only.  Importing this module loads the in-tree
+librnamg.so and fails loudly when it is missing: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librnamg.so")
+
+RN_OK, RN_EINVAL, RN_ENOMEM, RN_ESINGULAR, RN_EBREAKDOWN, RN_ENONFINITE, RN_EHIP, RN_ELIMIT = range(8)
+RN_CG, RN_GMRES = 0, 1
+RN_FP64, RN_FP32_MIXED = 0, 1
+STATUS_NAMES = {0: "RN_OK", 1: "RN_EINVAL", 2: "RN_ENOMEM", 3: "RN_ESINGULAR", 4: "RN_EBREAKDOWN",
+                5: "RN_ENONFINITE", 6: "RN_EHIP", 7: "RN_ELIMIT"}
+
+
+class rn_matrix(C.Structure):
+    _fields_ = [("n", C.c_int32), ("block_m", C.c_int32), ("nnz", C.c_int64),
+                ("rowptr", C.c_void_p), ("colind", C.c_void_p), ("vals", C.c_void_p)]
+
+
+class rn_emin_stats(C.Structure):
+    _fields_ = [("iters_done", C.c_int32), ("rank_deficient_rows", C.c_int32),
+                ("status_code", C.c_int32), ("reserved", C.c_int32),
+                ("first", C.c_double), ("last", C.c_double),
+                ("spgemm_bytes", C.c_double), ("spgemm_flops", C.c_double)]
+
+
+# name -> (restype, argtypes); every declaration of include/rnamg.h
+_vp, _i32, _i64, _d = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+_pi32, _pi64 = C.POINTER(C.c_int32), C.POINTER(C.c_int64)
+SIGNATURES = {
+    "rn_create": (_i32, [C.POINTER(C.c_void_p), _vp]),
+    "rn_destroy": (None, [_vp]),
+    "rn_set_stream": (_i32, [_vp, _vp]),
+    "rn_last_error": (C.c_char_p, [_vp]),
+    "rn_version": (C.c_char_p, []),
+    "rn_strength": (_i32, [_vp, C.POINTER(rn_matrix), _d, _vp, _vp, _pi64]),
+    "rn_aggregate_host": (_i32, [_i32, _vp, _vp, _vp, _vp, _pi32]),
+    "rn_pattern": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp, _i32, _i32, _i32, _vp, _vp, _vp, _pi64]),
+    "rn_tentative": (_i32, [_vp, _i32, _i32, _vp, _vp, _i64, _vp, _vp, _vp, _i32, _vp, _i32, _vp, _vp, _pi32]),
+    "rn_transpose": (_i32, [_vp, C.POINTER(rn_matrix), _vp, _vp, _vp, _vp]),
+    "rn_plan_create": (_i32, [_vp, C.POINTER(rn_matrix), _i32, _vp, _vp, _i64, _vp, _vp, _i32,
+                              C.POINTER(C.c_void_p)]),
+    "rn_plan_destroy": (None, [_vp]),
+    "rn_plan_bytes": (C.c_size_t, [_vp]),
+    "rn_masked_product": (_i32, [_vp, _vp, _vp, _i32, _vp, _i32, _i32, _vp]),
+    "rn_energy_min": (_i32, [_vp, _vp, _vp, _i32, _vp, _i32, _i32, _i32, _vp, _vp,
+                             C.POINTER(rn_emin_stats), _vp]),
+    "rn_tape_create": (_i32, [_vp, _vp, _i32, _i32, C.POINTER(C.c_void_p)]),
+    "rn_tape_destroy": (None, [_vp]),
+    "rn_energy_min_bwd": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+}
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises ImportError when it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              f"`python -c 'import __graft_entry__ as g; g.build()'`")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib

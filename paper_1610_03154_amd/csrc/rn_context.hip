@@ -1,0 +1,383 @@
+// rn_context.hip -- context, scratch, scan and CSR transpose.
+#include "rn_internal.h"
+
+#include <cstdlib>
+#include <cstring>
+#include <new>
+
+rn_status rn_fail(rn_ctx *ctx, rn_status st, const char *fmt, ...) {
+  if (ctx) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    ctx->err = buf;
+  }
+  return st;
+}
+
+void *rn_scratch(rn_ctx *ctx, int slot, size_t bytes, rn_status *st) {
+  RnScratch &s = ctx->slot[slot];
+  if (bytes == 0) bytes = 16;
+  if (s.cap >= bytes) return s.ptr;
+  if (s.ptr) {
+    (void)hipStreamSynchronize(ctx->stream);
+    (void)hipFree(s.ptr);
+    s.ptr = nullptr;
+    s.cap = 0;
+  }
+  size_t cap = bytes + bytes / 4 + 256;
+  if (hipMalloc(&s.ptr, cap) != hipSuccess) {
+    s.ptr = nullptr;
+    *st = rn_fail(ctx, RN_ENOMEM, "scratch allocation of %zu bytes failed", cap);
+    return nullptr;
+  }
+  s.cap = cap;
+  return s.ptr;
+}
+
+rn_status rn_read_i64(rn_ctx *ctx, const void *dev, int64_t *out) {
+  HIP_TRY(ctx, hipMemcpyAsync(ctx->pinned, dev, sizeof(int64_t), hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  *out = ctx->pinned[0];
+  return RN_OK;
+}
+
+// ---------------------------------------------------------------------------
+// exclusive scan of int32 counts: per-block totals, one-block scan of the
+// totals (int64, sequential over chunks of 1024), then the add-back pass.
+// ---------------------------------------------------------------------------
+#define SCAN_ITEMS 4
+#define SCAN_TILE (RN_BLOCK * SCAN_ITEMS)
+
+__global__ __launch_bounds__(RN_BLOCK) void k_scan_tiles(const int32_t *__restrict__ cnt, int64_t n,
+                                                        int64_t *__restrict__ bsum) {
+  __shared__ int64_t lds[RN_BLOCK];
+  const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
+  int64_t s = 0;
+#pragma unroll
+  for (int q = 0; q < SCAN_ITEMS; ++q)
+    if (base + q < n) s += cnt[base + q];
+  lds[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = RN_BLOCK / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) lds[threadIdx.x] += lds[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) bsum[blockIdx.x] = lds[0];
+}
+
+__global__ __launch_bounds__(1024) void k_scan_bsum(int64_t *__restrict__ bsum, int64_t nb,
+                                                   int64_t *__restrict__ total) {
+  __shared__ int64_t lds[1024];
+  int64_t carry = 0;
+  for (int64_t c0 = 0; c0 < nb; c0 += 1024) {
+    const int64_t i = c0 + threadIdx.x;
+    const int64_t v = i < nb ? bsum[i] : 0;
+    lds[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {  // Hillis-Steele inclusive
+      int64_t t = threadIdx.x >= (unsigned)off ? lds[threadIdx.x - off] : 0;
+      __syncthreads();
+      lds[threadIdx.x] += t;
+      __syncthreads();
+    }
+    if (i < nb) bsum[i] = carry + lds[threadIdx.x] - v;  // exclusive prefix
+    carry += lds[1023];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *total = carry;
+}
+
+__global__ __launch_bounds__(RN_BLOCK) void k_scan_apply(const int32_t *__restrict__ cnt, int64_t n,
+                                                        const int64_t *__restrict__ bpre,
+                                                        const int64_t *__restrict__ total,
+                                                        int32_t *__restrict__ out) {
+  __shared__ int64_t lds[RN_BLOCK];
+  const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
+  int32_t v[SCAN_ITEMS];
+  int64_t s = 0;
+#pragma unroll
+  for (int q = 0; q < SCAN_ITEMS; ++q) {
+    v[q] = base + q < n ? cnt[base + q] : 0;
+    s += v[q];
+  }
+  lds[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 1; off < RN_BLOCK; off <<= 1) {
+    int64_t t = threadIdx.x >= (unsigned)off ? lds[threadIdx.x - off] : 0;
+    __syncthreads();
+    lds[threadIdx.x] += t;
+    __syncthreads();
+  }
+  int64_t run = bpre[blockIdx.x] + lds[threadIdx.x] - s;
+#pragma unroll
+  for (int q = 0; q < SCAN_ITEMS; ++q) {
+    if (base + q < n) out[base + q] = (int32_t)run;
+    run += v[q];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = (int32_t)*total;
+}
+
+rn_status rn_scan_counts(rn_ctx *ctx, const int32_t *counts, int32_t *out, int64_t n,
+                         int64_t *total_host) {
+  rn_status st = RN_OK;
+  const int64_t nb = n > 0 ? (n + SCAN_TILE - 1) / SCAN_TILE : 1;
+  int64_t *bsum = (int64_t *)rn_scratch(ctx, SLOT_SCAN_BSUM, (size_t)nb * sizeof(int64_t), &st);
+  if (!bsum) return st;
+  int64_t *total = (int64_t *)rn_scratch(ctx, SLOT_SCAN_TOTAL, sizeof(int64_t), &st);
+  if (!total) return st;
+  hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)nb), dim3(RN_BLOCK), 0, ctx->stream, counts, n, bsum);
+  LAUNCH_CHECK(ctx);
+  hipLaunchKernelGGL(k_scan_bsum, dim3(1), dim3(1024), 0, ctx->stream, bsum, nb, total);
+  LAUNCH_CHECK(ctx);
+  hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(RN_BLOCK), 0, ctx->stream, counts, n, bsum,
+                     total, out);
+  LAUNCH_CHECK(ctx);
+  if (total_host) {
+    RN_TRY(rn_read_i64(ctx, total, total_host));
+    if (*total_host >= ((int64_t)1 << 31))
+      return rn_fail(ctx, RN_ELIMIT, "count %lld reaches 2^31", (long long)*total_host);
+  }
+  return RN_OK;
+}
+
+// ---------------------------------------------------------------------------
+// CSR transpose: count columns, scan, scatter with atomics, then sort each
+// row of the transpose by its (unique) column so the result is canonical.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(RN_BLOCK) void k_tr_count(const int32_t *__restrict__ Aj, int64_t nnz,
+                                                      int32_t *__restrict__ cnt, const int32_t *__restrict__ guard) {
+  if (*guard) return;
+  for (int64_t p = (int64_t)blockIdx.x * RN_BLOCK + threadIdx.x; p < nnz; p += (int64_t)gridDim.x * RN_BLOCK)
+    atomicAdd(&cnt[Aj[p]], 1);
+}
+
+__global__ __launch_bounds__(RN_BLOCK) void k_tr_scatter(int32_t rows, const int32_t *__restrict__ Ap,
+                                                        const int32_t *__restrict__ Aj,
+                                                        int32_t *__restrict__ cursor,
+                                                        int32_t *__restrict__ trow,
+                                                        int32_t *__restrict__ tperm,
+                                                        const int32_t *__restrict__ guard) {
+  const int i = blockIdx.x * RN_BLOCK + threadIdx.x;
+  if (i >= rows || *guard) return;
+  for (int p = Ap[i]; p < Ap[i + 1]; ++p) {
+    const int q = atomicAdd(&cursor[Aj[p]], 1);
+    trow[q] = i;
+    tperm[q] = p;
+  }
+}
+
+__global__ __launch_bounds__(RN_BLOCK) void k_tr_sort(int32_t cols, const int32_t *__restrict__ Tp,
+                                                     const int32_t *__restrict__ trow,
+                                                     const int32_t *__restrict__ tperm,
+                                                     int32_t *__restrict__ Tj, int32_t *__restrict__ perm,
+                                                     const int32_t *__restrict__ guard) {
+  const int j = blockIdx.x * RN_BLOCK + threadIdx.x;
+  if (j >= cols || *guard) return;
+  const int s = Tp[j], e = Tp[j + 1];
+  for (int q = s; q < e; ++q) {
+    const int key = trow[q];
+    int rank = 0;
+    for (int u = s; u < e; ++u) rank += trow[u] < key;
+    Tj[s + rank] = key;
+    if (perm) perm[s + rank] = tperm[q];
+  }
+}
+
+rn_status rn_transpose_structure(rn_ctx *ctx, int32_t rows, int32_t cols, int64_t nnz,
+                                 const int32_t *Ap, const int32_t *Aj, int32_t *Tp, int32_t *Tj,
+                                 int32_t *perm, const int32_t *guard) {
+  rn_status st = RN_OK;
+  int32_t *cnt = (int32_t *)rn_scratch(ctx, SLOT_TR_CNT, (size_t)(cols + 1) * sizeof(int32_t), &st);
+  if (!cnt) return st;
+  int32_t *trow = (int32_t *)rn_scratch(ctx, SLOT_TR_ROW, (size_t)(nnz + 1) * sizeof(int32_t), &st);
+  if (!trow) return st;
+  int32_t *tperm = (int32_t *)rn_scratch(ctx, SLOT_TR_PERM, (size_t)(nnz + 1) * sizeof(int32_t), &st);
+  if (!tperm) return st;
+  HIP_TRY(ctx, hipMemsetAsync(cnt, 0, (size_t)(cols + 1) * sizeof(int32_t), ctx->stream));
+  unsigned g = rn_div_up(nnz, RN_BLOCK);
+  if (g > 4096) g = 4096;
+  if (g == 0) g = 1;
+  hipLaunchKernelGGL(k_tr_count, dim3(g), dim3(RN_BLOCK), 0, ctx->stream, Aj, nnz, cnt, guard);
+  LAUNCH_CHECK(ctx);
+  RN_TRY(rn_scan_counts(ctx, cnt, Tp, cols, nullptr));
+  HIP_TRY(ctx, hipMemcpyAsync(cnt, Tp, (size_t)cols * sizeof(int32_t), hipMemcpyDeviceToDevice, ctx->stream));
+  if (rows > 0) {
+    hipLaunchKernelGGL(k_tr_scatter, dim3(rn_div_up(rows, RN_BLOCK)), dim3(RN_BLOCK), 0, ctx->stream, rows,
+                       Ap, Aj, cnt, trow, tperm, guard);
+    LAUNCH_CHECK(ctx);
+  }
+  if (cols > 0) {
+    hipLaunchKernelGGL(k_tr_sort, dim3(rn_div_up(cols, RN_BLOCK)), dim3(RN_BLOCK), 0, ctx->stream, cols, Tp,
+                       trow, tperm, Tj, perm, guard);
+    LAUNCH_CHECK(ctx);
+  }
+  return RN_OK;
+}
+
+// ---------------------------------------------------------------------------
+// public: context
+// ---------------------------------------------------------------------------
+extern "C" rn_status rn_create(rn_ctx **out, void *stream) {
+  if (!out) return RN_EINVAL;
+  *out = nullptr;
+  rn_ctx *ctx = new (std::nothrow) rn_ctx();
+  if (!ctx) return RN_ENOMEM;
+  ctx->stream = (hipStream_t)stream;
+  if (hipGetDevice(&ctx->device) != hipSuccess) {
+    delete ctx;
+    return RN_EHIP;
+  }
+  if (hipHostMalloc((void **)&ctx->pinned, 64 * sizeof(int64_t), hipHostMallocDefault) != hipSuccess) {
+    delete ctx;
+    return RN_ENOMEM;
+  }
+  *out = ctx;
+  return RN_OK;
+}
+
+extern "C" void rn_destroy(rn_ctx *ctx) {
+  if (!ctx) return;
+  (void)hipStreamSynchronize(ctx->stream);
+  for (int s = 0; s < SLOT_COUNT; ++s)
+    if (ctx->slot[s].ptr) (void)hipFree(ctx->slot[s].ptr);
+  if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+  delete ctx;
+}
+
+extern "C" rn_status rn_set_stream(rn_ctx *ctx, void *stream) {
+  if (!ctx) return RN_EINVAL;
+  ctx->stream = (hipStream_t)stream;
+  return RN_OK;
+}
+
+extern "C" const char *rn_last_error(const rn_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+extern "C" const char *rn_version(void) { return "rnamg 0.1 gfx950"; }
+
+extern "C" rn_status rn_transpose(rn_ctx *ctx, const rn_matrix *A, int32_t *ATp, int32_t *ATj, double *ATx,
+                                  int32_t *perm) {
+  if (!ctx || !A) return RN_EINVAL;
+  ctx->err.clear();
+  if (A->block_m != 1) return rn_fail(ctx, RN_EINVAL, "rn_transpose: scalar CSR only (block_m = 1)");
+  if (A->n < 0 || A->nnz < 0 || !A->rowptr || (A->nnz && !A->colind) || !ATp || (A->nnz && !ATj))
+    return rn_fail(ctx, RN_EINVAL, "rn_transpose: null or negative argument");
+  if (A->nnz >= ((int64_t)1 << 31)) return rn_fail(ctx, RN_ELIMIT, "rn_transpose: nnz >= 2^31");
+  if (ATx && !A->vals) return rn_fail(ctx, RN_EINVAL, "rn_transpose: AT_vals requested but A->vals is NULL");
+  rn_status st = RN_OK;
+  int32_t *pm = perm;
+  if (!pm && ATx) {
+    pm = (int32_t *)rn_scratch(ctx, SLOT_MISC, (size_t)(A->nnz + 1) * sizeof(int32_t), &st);
+    if (!pm) return st;
+  }
+  int32_t *guard = rn_guard_begin(ctx, &st);
+  if (!guard) return st;
+  RN_TRY(rn_validate_csr(ctx, A->n, A->n, A->nnz, A->rowptr, A->colind, guard, GUARD_A));
+  RN_TRY(rn_transpose_structure(ctx, A->n, A->n, A->nnz, A->rowptr, A->colind, ATp, ATj, pm, guard));
+  if (ATx) RN_TRY(rn_gather_values(ctx, A->vals, pm, A->nnz, ATx));
+  return rn_check_guard(ctx, guard, "rn_transpose");
+}
+
+__global__ __launch_bounds__(RN_BLOCK) void k_gather(const double *__restrict__ src,
+                                                    const int32_t *__restrict__ idx, int64_t n,
+                                                    double *__restrict__ dst) {
+  for (int64_t q = (int64_t)blockIdx.x * RN_BLOCK + threadIdx.x; q < n; q += (int64_t)gridDim.x * RN_BLOCK)
+    dst[q] = src[idx[q]];
+}
+
+rn_status rn_gather_values(rn_ctx *ctx, const double *src, const int32_t *idx, int64_t n, double *dst) {
+  if (n == 0) return RN_OK;
+  unsigned g = rn_div_up(n, RN_BLOCK);
+  if (g > 8192) g = 8192;
+  hipLaunchKernelGGL(k_gather, dim3(g), dim3(RN_BLOCK), 0, ctx->stream, src, idx, n, dst);
+  LAUNCH_CHECK(ctx);
+  return RN_OK;
+}
+
+// ---------------------------------------------------------------------------
+// input validation
+// ---------------------------------------------------------------------------
+int32_t *rn_guard_begin(rn_ctx *ctx, rn_status *st) {
+  int32_t *g = (int32_t *)rn_scratch(ctx, SLOT_GUARD, 64, st);
+  if (!g) return nullptr;
+  if (hipMemsetAsync(g, 0, sizeof(int32_t), ctx->stream) != hipSuccess) {
+    *st = rn_fail(ctx, RN_EHIP, "guard reset failed");
+    return nullptr;
+  }
+  return g;
+}
+
+__global__ __launch_bounds__(RN_BLOCK) void k_validate_csr(int32_t rows, int32_t cols, int64_t nnz,
+                                                          const int32_t *__restrict__ Ap,
+                                                          const int32_t *__restrict__ Aj,
+                                                          int32_t *__restrict__ guard, int32_t bit) {
+  const int i = blockIdx.x * RN_BLOCK + threadIdx.x;
+  if (i > rows) return;
+  if (nnz < 0) nnz = Ap[rows];  // structure sized by its own last row pointer
+  const int64_t s = Ap[i];
+  bool bad = (i == 0 && s != 0) || (i == rows && s != nnz) || s < 0 || s > nnz;
+  if (!bad && i < rows) {
+    const int64_t e = Ap[i + 1];
+    if (e < s || e > nnz) {
+      bad = true;
+    } else {
+      int prev = -1;
+      for (int64_t p = s; p < e; ++p) {
+        const int j = Aj[p];
+        if (j <= prev || j >= cols) { bad = true; break; }
+        prev = j;
+      }
+    }
+  }
+  if (bad) atomicOr(guard, bit);
+}
+
+__global__ __launch_bounds__(RN_BLOCK) void k_validate_range(int64_t n, const int32_t *__restrict__ a, int32_t lo,
+                                                            int32_t hi, int32_t *__restrict__ guard, int32_t bit) {
+  bool bad = false;
+  for (int64_t q = (int64_t)blockIdx.x * RN_BLOCK + threadIdx.x; q < n; q += (int64_t)gridDim.x * RN_BLOCK)
+    bad |= (a[q] < lo || a[q] >= hi);
+  if (bad) atomicOr(guard, bit);
+}
+
+rn_status rn_validate_csr(rn_ctx *ctx, int32_t rows, int32_t cols, int64_t nnz, const int32_t *Ap,
+                          const int32_t *Aj, int32_t *guard, int32_t bit) {
+  hipLaunchKernelGGL(k_validate_csr, dim3(rn_div_up((int64_t)rows + 1, RN_BLOCK)), dim3(RN_BLOCK), 0, ctx->stream,
+                     rows, cols, nnz, Ap, Aj, guard, bit);
+  LAUNCH_CHECK(ctx);
+  return RN_OK;
+}
+
+rn_status rn_validate_range(rn_ctx *ctx, int64_t n, const int32_t *a, int32_t lo, int32_t hi, int32_t *guard,
+                            int32_t bit) {
+  if (n <= 0) return RN_OK;
+  unsigned g = rn_div_up(n, RN_BLOCK);
+  if (g > 4096) g = 4096;
+  hipLaunchKernelGGL(k_validate_range, dim3(g), dim3(RN_BLOCK), 0, ctx->stream, n, a, lo, hi, guard, bit);
+  LAUNCH_CHECK(ctx);
+  return RN_OK;
+}
+
+static rn_status guard_message(rn_ctx *ctx, int32_t g, const char *what) {
+  if (!g) return RN_OK;
+  if (g & GUARD_LIMIT) return rn_fail(ctx, RN_ELIMIT, "%s: a documented size limit was exceeded", what);
+  return rn_fail(ctx, RN_EINVAL, "%s: malformed input (%s%s%s%s%s)", what, (g & GUARD_A) ? "A " : "",
+                 (g & GUARD_S) ? "S " : "", (g & GUARD_N) ? "N " : "", (g & GUARD_AGG) ? "agg " : "",
+                 (g & GUARD_ROOTS) ? "roots" : "");
+}
+
+rn_status rn_check_guard(rn_ctx *ctx, const int32_t *guard, const char *what) {
+  HIP_TRY(ctx, hipMemcpyAsync(ctx->pinned, guard, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  return guard_message(ctx, ((int32_t *)ctx->pinned)[0], what);
+}
+
+rn_status rn_read_guard_i64(rn_ctx *ctx, const int32_t *guard, const void *dev, int64_t *out, const char *what) {
+  HIP_TRY(ctx, hipMemcpyAsync(ctx->pinned, dev, sizeof(int64_t), hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(ctx, hipMemcpyAsync(ctx->pinned + 1, guard, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  *out = ctx->pinned[0];
+  return guard_message(ctx, ((int32_t *)(ctx->pinned + 1))[0], what);
+}

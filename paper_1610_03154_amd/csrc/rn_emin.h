@@ -1,0 +1,123 @@
+// rn_emin.h -- plan object and kernel parameter blocks of the energy
+// minimisation (Sec. 3.6 improve).  Internal.
+#pragma once
+#include "rn_gram.h"
+#include "rn_internal.h"
+
+// Position codes: for pattern entry r of row i and the t-th stored entry
+// A(i,k), the position of column j_r in row k of the pattern (0..252), or
+// CODE_ROOT (k is a root node, block_m = 2: its two DOF rows hold one entry
+// each), or CODE_NONE.  Layout per row: entry-major, each entry's codes padded
+// to a multiple of 4 bytes so a lane reads them as 32-bit words.
+#define CODE_NONE 255
+#define CODE_ROOT 254
+#define CODE_MAXLEN 253
+
+// Block-row A entries staged in LDS by the product kernel (larger blocks read
+// A from global memory directly).
+#define SPG_ACAP 1024
+
+// per-batch integer state
+enum { ST_STATUS = 0, ST_DONE = 1, ST_ITERS = 2, ST_KD = 3, ST_STRIDE = 8 };
+
+// per-batch double scalars
+enum { SC_GAMMA0 = 0, SC_BETA0, SC_BASE = 4 };
+// CG: gamma[K+1], delta[K], alpha[K], beta[K] after SC_BASE
+struct CgLayout {
+  int gam, del, alp, bet, total;
+  __host__ __device__ CgLayout(int K) {
+    gam = SC_BASE;
+    del = gam + K + 1;
+    alp = del + K;
+    bet = alp + K;
+    total = bet + K;
+  }
+};
+// GMRES: scales, Hessenberg, Givens, residual vector, y, two GS passes
+struct GmLayout {
+  int s, H, cs, sn, g, y, h1, h2, total;
+  __host__ __device__ GmLayout(int K) {
+    s = SC_BASE;
+    H = s + (K + 1);
+    cs = H + (K + 1) * K;
+    sn = cs + K;
+    g = sn + K;
+    y = g + (K + 1);
+    h1 = y + K;
+    h2 = h1 + (K + 1);
+    total = h2 + (K + 1);
+  }
+};
+
+enum { MODE_PRODUCT = 0, MODE_CG_INIT, MODE_CG_STEP, MODE_GM_INIT, MODE_GM_STEP };
+
+#define RN_MAXDOT 65  // GMRES iterations <= 64
+
+enum RnWs {
+  WS_R = 0, WS_D, WS_Z, WS_D32, WS_A32, WS_T32, WS_U, WS_U32, WS_PART, WS_SCAL, WS_ST, WS_CNT,
+  WS_TAPE_TMP0, WS_TAPE_TMP1, WS_TAPE_TMP2, WS_TAPE_TMP3, WS_COUNT
+};
+
+struct rn_plan {
+  rn_ctx *ctx = nullptr;
+  int32_t n = 0, nc = 0, m = 1, nB = 1, nr = 0;
+  int64_t nnzN = 0, nnzA = 0, nnzN_node = 0;
+  const int32_t *Ap = nullptr, *Aj = nullptr, *Np = nullptr, *Nj = nullptr;
+  const uint8_t *is_root = nullptr;
+  const double *Bc = nullptr;
+  int32_t *code_ptr = nullptr;  // byte offset of each row's codes (multiple of 4)
+  uint8_t *codes = nullptr;
+  int64_t ncodes = 0;
+  int32_t *nodeptr = nullptr;   // block_m = 2: node-entry row pointer
+  int32_t *blk_row = nullptr;   // product blocks: first row of block b, b = 0..nblk
+  double *gp = nullptr;         // packed Gram pseudo-inverse per DOF row
+  int32_t rank_def = 0, maxlen = 0, chunk = 1, nblk = 0;
+  unsigned long long *d_terms = nullptr;  // multiply-add terms of one product
+  size_t fixed_bytes = 0;
+  RnScratch ws[WS_COUNT];
+};
+
+void *rn_plan_ws(rn_plan *pl, int slot, size_t bytes, rn_status *st);
+
+// Parameters of one masked-product launch (passed by value).
+struct SpgParams {
+  int32_t n, nr, nblk, k, K, hist_stride, project, scal_stride;
+  int64_t nnzN, strideA, strideX, strideZ, Ubatch;
+  const int32_t *Ap, *Aj, *Np, *Nj, *code_ptr, *nodeptr, *blk_row;
+  const uint8_t *codes, *is_root;
+  const double *Bc, *gp;
+  const void *Ax;      // double or float, [batch][strideA]
+  const void *X;       // double or float, [batch][strideX]
+  const double *Xown;  // FP64 own-entry values for the CG dot (D)
+  double *Z, *Z2;
+  const double *U;     // GMRES basis: vector j of batch b at U + b*Ubatch + j*nnzN
+  double *part;        // [batch][RN_MAXDOT][nblk]
+  double *scal;        // [batch][scal_stride]
+  int32_t *st;         // [batch][ST_STRIDE]
+};
+
+// Launch the masked product in one of the modes (rn_spgemm.hip).
+rn_status rn_launch_spgemm(rn_ctx *ctx, const rn_plan *pl, int mode, const SpgParams &p, int batch, bool mixed);
+SpgParams rn_spg_params(const rn_plan *pl);
+
+// tape hooks called by rn_energy_min (CG, FP64) -- implemented with the adjoint
+rn_status rn_tape_record_begin(rn_ctx *ctx, rn_plan *pl, rn_tape *tape, int32_t batch, int32_t iters,
+                               rn_method method, rn_precision prec);
+// before CG step k: R_k, D_k of every batch entry ([batch][nnzN])
+rn_status rn_tape_record_step(rn_ctx *ctx, rn_tape *tape, int k, const double *R, const double *D, int64_t nnzN,
+                              int32_t batch);
+// after the last step: the per-batch scalars and status
+rn_status rn_tape_record_end(rn_ctx *ctx, rn_tape *tape, const double *scal, const int32_t *st, int32_t batch);
+
+// Deterministic sum of nb partials by the whole block (fixed assignment of
+// partials to threads, compensated, fixed tree).
+__device__ inline double rn_reduce_part(const double *__restrict__ part, int nb, double *lds8) {
+  RnAcc a;
+  for (int q = threadIdx.x; q < nb; q += RN_BLOCK) a.add(part[q]);
+  return rn_block_sum2(a.hi, a.lo, lds8);
+}
+
+// Krylov stopping rules (converged to round-off): CG once <R,R> <= 1e-24
+// <R0,R0>, GMRES once the residual estimate is <= 1e-12 ||R0||.
+#define RN_CG_STOP 1e-24
+#define RN_GM_STOP 1e-12

@@ -1,0 +1,552 @@
+// rn_emin.hip -- energy minimisation of the interpolation operator
+// (Sec. 3.6 improve; Sec. 4.1 CG form, Sec. 4.2 GMRES form).
+//
+// CG step k:   product (Z = Pi(A D), partials of <D,Z>)
+//              -> update: every block sums the <D,Z> partials itself (same
+//                 fixed order in every block, so every block gets the same
+//                 alpha), P += alpha D, R -= alpha Z, partials of <R,R>
+//              -> direction: every block sums the <R,R> partials, beta,
+//                 D = R + beta D.
+// No inter-block synchronisation and no host round trip inside the loop; the
+// scalars of step k are kept per step so no kernel overwrites a value another
+// block of the same kernel still reads.
+// GMRES step k: product with the first Gram-Schmidt pass fused (partials of
+// <W, V_j>), then two element-wise passes (classical Gram-Schmidt twice), each
+// followed by a one-block kernel that sums the partials; the Hessenberg
+// column, Givens rotations and the stopping test run on the device.
+#include <cstring>
+#include <new>
+
+#include "rn_emin.h"
+
+// ---------------------------------------------------------------------------
+// CG
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(RN_BLOCK) void k_cg_fin_init(int nblk, const double *__restrict__ part,
+                                                         double *__restrict__ scal, int scal_stride, int K,
+                                                         int32_t *__restrict__ stv, double *__restrict__ histv,
+                                                         int hist_stride) {
+  __shared__ double s_w[8];
+  const int b = blockIdx.x;
+  const double g = rn_reduce_part(part + (int64_t)b * RN_MAXDOT * nblk, nblk, s_w);
+  if (threadIdx.x != 0) return;
+  double *sc = scal + (int64_t)b * scal_stride;
+  int32_t *st = stv + (int64_t)b * ST_STRIDE;
+  const CgLayout L(K);
+  sc[SC_GAMMA0] = g;
+  sc[L.gam] = g;
+  if (histv) histv[(int64_t)b * hist_stride] = g;
+  if (!isfinite(g)) st[ST_STATUS] = RN_ENONFINITE;
+  else if (g == 0.0) st[ST_DONE] = 1;
+}
+
+__global__ __launch_bounds__(RN_BLOCK) void k_cg_update(int64_t nnz, int64_t stride, int K, int k, int nblk,
+                                                       double *__restrict__ P, double *__restrict__ R,
+                                                       const double *__restrict__ D, const double *__restrict__ Z,
+                                                       const double *__restrict__ part_spg,
+                                                       double *__restrict__ part_ew, double *__restrict__ scal,
+                                                       int scal_stride, int32_t *__restrict__ stv,
+                                                       double *__restrict__ histv, int hist_stride) {
+  __shared__ double s_w[8];
+  const int b = blockIdx.y;
+  int32_t *st = stv + (int64_t)b * ST_STRIDE;
+  if (st[ST_STATUS] || st[ST_DONE]) return;
+  double *sc = scal + (int64_t)b * scal_stride;
+  const CgLayout L(K);
+  const double dl = rn_reduce_part(part_spg + (int64_t)b * RN_MAXDOT * nblk, nblk, s_w);
+  const bool first = blockIdx.x == 0 && threadIdx.x == 0;
+  double *hist = histv ? histv + (int64_t)b * hist_stride : nullptr;
+  if (first) {
+    sc[L.del + k] = dl;
+    if (hist) hist[1 + K + k] = dl;
+  }
+  if (!isfinite(dl)) {
+    if (first) st[ST_STATUS] = RN_ENONFINITE;
+    return;
+  }
+  if (dl <= 0.0) {
+    if (first) st[ST_STATUS] = RN_EBREAKDOWN;
+    return;
+  }
+  const double al = sc[L.gam + k] / dl;
+  if (first) {
+    sc[L.alp + k] = al;
+    if (hist) hist[1 + 2 * K + k] = al;
+  }
+  const int64_t off = (int64_t)b * stride;
+  RnAcc s;
+  for (int64_t e = (int64_t)blockIdx.x * RN_BLOCK + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * RN_BLOCK) {
+    P[off + e] += al * D[off + e];
+    const double r = R[off + e] - al * Z[off + e];
+    R[off + e] = r;
+    s.add(r * r);
+  }
+  const double S = rn_block_sum2(s.hi, s.lo, s_w);
+  if (threadIdx.x == 0) part_ew[(int64_t)b * RN_MAXDOT * gridDim.x + blockIdx.x] = S;
+}
+
+template <bool MIXED>
+__global__ __launch_bounds__(RN_BLOCK) void k_cg_dir(int64_t nnz, int64_t stride, int K, int k, int nb_ew,
+                                                    const double *__restrict__ R, double *__restrict__ D,
+                                                    float *__restrict__ D32, const double *__restrict__ part_ew,
+                                                    double *__restrict__ scal, int scal_stride,
+                                                    int32_t *__restrict__ stv, double *__restrict__ histv,
+                                                    int hist_stride) {
+  __shared__ double s_w[8];
+  const int b = blockIdx.y;
+  int32_t *st = stv + (int64_t)b * ST_STRIDE;
+  if (st[ST_STATUS] || st[ST_DONE]) return;
+  double *sc = scal + (int64_t)b * scal_stride;
+  const CgLayout L(K);
+  const double g = rn_reduce_part(part_ew + (int64_t)b * RN_MAXDOT * nb_ew, nb_ew, s_w);
+  const double be = g / sc[L.gam + k];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    sc[L.gam + k + 1] = g;
+    sc[L.bet + k] = be;
+    if (histv) histv[(int64_t)b * hist_stride + k + 1] = g;
+    st[ST_ITERS] = k + 1;
+    if (!isfinite(g)) st[ST_STATUS] = RN_ENONFINITE;
+    else if (g <= RN_CG_STOP * sc[SC_GAMMA0]) st[ST_DONE] = 1;
+  }
+  if (!isfinite(g)) return;
+  const int64_t off = (int64_t)b * stride;
+  for (int64_t e = (int64_t)blockIdx.x * RN_BLOCK + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * RN_BLOCK) {
+    const double d = R[off + e] + be * D[off + e];
+    D[off + e] = d;
+    if (MIXED) D32[off + e] = (float)d;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// GMRES
+// ---------------------------------------------------------------------------
+// Sums partial rows and finishes the scalars of one stage (one block per
+// batch entry).  STAGE 0: beta0 after the initial product; 1: first-pass
+// coefficients h1_j = s_j <W, U_j>; 2: second-pass h2_j; 3: ||W||, column k
+// of H, Givens rotation, residual estimate, next scale, stopping test.
+template <int STAGE>
+__global__ __launch_bounds__(RN_BLOCK) void k_gm_fin(int nb, const double *__restrict__ part, int K, int k,
+                                                    double *__restrict__ scal, int scal_stride,
+                                                    int32_t *__restrict__ stv, double *__restrict__ histv,
+                                                    int hist_stride) {
+  __shared__ double s_w[8];
+  const int b = blockIdx.x;
+  int32_t *st = stv + (int64_t)b * ST_STRIDE;
+  if (STAGE > 0 && (st[ST_STATUS] || st[ST_DONE])) return;
+  double *sc = scal + (int64_t)b * scal_stride;
+  const GmLayout L(K);
+  const double *pb = part + (int64_t)b * RN_MAXDOT * nb;
+  double *hist = histv ? histv + (int64_t)b * hist_stride : nullptr;
+  if (STAGE == 1 || STAGE == 2) {
+    for (int j = 0; j <= k; ++j) {
+      const double tot = rn_reduce_part(pb + (int64_t)j * nb, nb, s_w);
+      if (threadIdx.x == 0) sc[(STAGE == 1 ? L.h1 : L.h2) + j] = sc[L.s + j] * tot;
+    }
+    return;
+  }
+  const double tot = rn_reduce_part(pb, nb, s_w);
+  if (threadIdx.x != 0) return;
+  if (STAGE == 0) {
+    const double beta = sqrt(tot);
+    sc[SC_BETA0] = beta;
+    sc[L.g] = beta;
+    if (hist) hist[0] = beta;
+    if (!isfinite(beta)) st[ST_STATUS] = RN_ENONFINITE;
+    else if (beta == 0.0) st[ST_DONE] = 1;
+    else sc[L.s] = 1.0 / beta;
+    return;
+  }
+  double *H = sc + L.H;
+  const double hn = sqrt(tot);
+  for (int j = 0; j <= k; ++j) H[j * K + k] = sc[L.h1 + j] + sc[L.h2 + j];
+  H[(k + 1) * K + k] = hn;
+  if (!isfinite(hn)) {
+    st[ST_STATUS] = RN_ENONFINITE;
+    return;
+  }
+  for (int j = 0; j < k; ++j) {
+    const double a = H[j * K + k], bb = H[(j + 1) * K + k];
+    H[j * K + k] = sc[L.cs + j] * a + sc[L.sn + j] * bb;
+    H[(j + 1) * K + k] = -sc[L.sn + j] * a + sc[L.cs + j] * bb;
+  }
+  const double a = H[k * K + k], bb = H[(k + 1) * K + k];
+  const double r = hypot(a, bb);
+  sc[L.cs + k] = a / r;
+  sc[L.sn + k] = bb / r;
+  H[k * K + k] = r;
+  H[(k + 1) * K + k] = 0.0;
+  sc[L.g + k + 1] = -sc[L.sn + k] * sc[L.g + k];
+  sc[L.g + k] = sc[L.cs + k] * sc[L.g + k];
+  if (hist) hist[k + 1] = fabs(sc[L.g + k + 1]);
+  st[ST_KD] = k + 1;
+  st[ST_ITERS] = k + 1;
+  if (hn == 0.0 || fabs(sc[L.g + k + 1]) <= RN_GM_STOP * sc[SC_BETA0]) st[ST_DONE] = 1;
+  else sc[L.s + k + 1] = 1.0 / hn;
+}
+
+// Re-orthogonalisation passes on the new vector W = U_{k+1}:
+// pass 1: W -= sum_j h1_j V_j, partials of <W, U_j>
+// pass 2: W -= sum_j h2_j V_j, partials of ||W||^2 (and the FP32 shadow)
+template <int NJ, int PASS, bool MIXED>
+__global__ __launch_bounds__(RN_BLOCK) void k_gm_orth(int64_t nnz, int64_t ubatch, int K, int k,
+                                                     double *__restrict__ Uall, float *__restrict__ U32all,
+                                                     double *__restrict__ part, const double *__restrict__ scal,
+                                                     int scal_stride, const int32_t *__restrict__ stv) {
+  __shared__ double s_w[8];
+  const int b = blockIdx.y;
+  const int32_t *st = stv + (int64_t)b * ST_STRIDE;
+  if (st[ST_STATUS] || st[ST_DONE]) return;
+  const double *sc = scal + (int64_t)b * scal_stride;
+  const GmLayout L(K);
+  double *U = Uall + (int64_t)b * ubatch;
+  double *W = U + (int64_t)(k + 1) * nnz;
+  double coef[NJ];
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) coef[j] = j <= k ? sc[(PASS == 1 ? L.h1 : L.h2) + j] * sc[L.s + j] : 0.0;
+  RnAcc acc[NJ];
+  for (int64_t e = (int64_t)blockIdx.x * RN_BLOCK + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * RN_BLOCK) {
+    double w = W[e];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j)
+      if (j <= k) w -= coef[j] * U[(int64_t)j * nnz + e];
+    W[e] = w;
+    if (PASS == 1) {
+#pragma unroll
+      for (int j = 0; j < NJ; ++j)
+        if (j <= k) acc[j].add(w * U[(int64_t)j * nnz + e]);
+    } else {
+      acc[0].add(w * w);
+      if (MIXED) U32all[(int64_t)b * ubatch + (int64_t)(k + 1) * nnz + e] = (float)w;
+    }
+  }
+  double *pb = part + (int64_t)b * RN_MAXDOT * gridDim.x;
+  const int nd = PASS == 1 ? k + 1 : 1;
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) {
+    if (j >= nd) break;
+    const double S = rn_block_sum2(acc[j].hi, acc[j].lo, s_w);
+    if (threadIdx.x == 0) pb[(int64_t)j * gridDim.x + blockIdx.x] = S;
+  }
+}
+
+__global__ void k_gm_solve(int K, double *__restrict__ scal, int scal_stride, const int32_t *__restrict__ stv) {
+  const int b = blockIdx.x;
+  if (threadIdx.x != 0) return;
+  const int32_t *st = stv + (int64_t)b * ST_STRIDE;
+  double *sc = scal + (int64_t)b * scal_stride;
+  const GmLayout L(K);
+  const int kd = st[ST_KD];
+  const double *H = sc + L.H;
+  for (int j = kd - 1; j >= 0; --j) {
+    double v = sc[L.g + j];
+    for (int l = j + 1; l < kd; ++l) v -= H[j * K + l] * sc[L.y + l];
+    sc[L.y + j] = v / H[j * K + j];
+  }
+}
+
+template <int NJ>
+__global__ __launch_bounds__(RN_BLOCK) void k_gm_combine(int64_t nnz, int64_t ubatch, int K,
+                                                        const double *__restrict__ T, const double *__restrict__ Uall,
+                                                        double *__restrict__ P, const double *__restrict__ scal,
+                                                        int scal_stride, const int32_t *__restrict__ stv) {
+  const int b = blockIdx.y;
+  const int32_t *st = stv + (int64_t)b * ST_STRIDE;
+  const double *sc = scal + (int64_t)b * scal_stride;
+  const GmLayout L(K);
+  const int kd = st[ST_STATUS] ? 0 : st[ST_KD];
+  double c[NJ];
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) c[j] = j < kd ? sc[L.y + j] * sc[L.s + j] : 0.0;
+  const double *U = Uall + (int64_t)b * ubatch;
+  double *Pb = P + (int64_t)b * nnz;
+  for (int64_t e = (int64_t)blockIdx.x * RN_BLOCK + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * RN_BLOCK) {
+    double v = T[e];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j)
+      if (j < kd) v += c[j] * U[(int64_t)j * nnz + e];
+    Pb[e] = v;
+  }
+}
+
+__global__ __launch_bounds__(RN_BLOCK) void k_to_f32(const double *__restrict__ src, int64_t n,
+                                                    float *__restrict__ dst) {
+  for (int64_t q = (int64_t)blockIdx.x * RN_BLOCK + threadIdx.x; q < n; q += (int64_t)gridDim.x * RN_BLOCK)
+    dst[q] = (float)src[q];
+}
+
+__global__ __launch_bounds__(RN_BLOCK) void k_bcast(const double *__restrict__ src, int64_t n, int64_t stride,
+                                                   double *__restrict__ dst) {
+  const int b = blockIdx.y;
+  for (int64_t q = (int64_t)blockIdx.x * RN_BLOCK + threadIdx.x; q < n; q += (int64_t)gridDim.x * RN_BLOCK)
+    dst[(int64_t)b * stride + q] = src[q];
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+static unsigned ew_grid(int64_t n) {
+  unsigned g = rn_div_up(n, RN_BLOCK * 8);
+  if (g < 1) g = 1;
+  if (g > 512) g = 512;
+  return g;
+}
+
+// Algorithmic bytes / flops of one masked product: A values + indices + row
+// pointers, pattern indices + row pointers, X read once, Z written once, the
+// root flags, the coarse candidates and the stored Gram data of the F rows.
+static void product_cost(const rn_plan *pl, bool mixed, unsigned long long terms, double *bytes, double *flops) {
+  const double val = mixed ? 4.0 : 8.0;
+  const double mm = (double)pl->m * pl->m;
+  double b = (4.0 + val * mm) * (double)pl->nnzA + 4.0 * (pl->nr + 1);  // A
+  b += 4.0 * (double)pl->nnzN + 4.0 * (pl->n + 1);                      // N
+  b += val * (double)pl->nnzN + 8.0 * (double)pl->nnzN;                 // X in, Z out
+  b += (double)pl->n;                                                   // root flags
+  const double nF = (double)pl->n - (double)pl->nc;
+  b += 8.0 * (double)pl->nc * pl->nB + 8.0 * nF * (pl->nB * (pl->nB + 1) / 2);
+  *bytes = b;
+  // one term is a scalar multiply-add (block_m = 1) or a 2x2 block product
+  // (8 multiply-adds, block_m = 2)
+  *flops = 2.0 * (double)terms * (pl->m == 1 ? 1.0 : 8.0);
+}
+
+static rn_status common_ws(rn_plan *pl, int batch, int scal_stride, unsigned gew, SpgParams &p) {
+  rn_status st = RN_OK;
+  p.st = (int32_t *)rn_plan_ws(pl, WS_ST, (size_t)batch * ST_STRIDE * 4, &st);
+  p.scal = (double *)rn_plan_ws(pl, WS_SCAL, (size_t)batch * scal_stride * 8, &st);
+  // product partials [batch][RN_MAXDOT][nblk] then element-wise partials
+  p.part = (double *)rn_plan_ws(pl, WS_PART, (size_t)batch * RN_MAXDOT * ((size_t)pl->nblk + gew + 2) * 8, &st);
+  if (!p.st || !p.scal || !p.part) return st;
+  p.scal_stride = scal_stride;
+  return RN_OK;
+}
+
+extern "C" rn_status rn_masked_product(rn_ctx *ctx, rn_plan *pl, const double *A_vals, int32_t batch,
+                                       const double *X, int32_t project, rn_precision prec, double *Z) {
+  if (!ctx) return RN_EINVAL;
+  ctx->err.clear();
+  if (!pl || !A_vals || !X || !Z || batch < 1) return rn_fail(ctx, RN_EINVAL, "rn_masked_product: bad argument");
+  if (prec != RN_FP64 && prec != RN_FP32_MIXED) return rn_fail(ctx, RN_EINVAL, "rn_masked_product: bad precision");
+  const bool mixed = prec == RN_FP32_MIXED;
+  SpgParams p = rn_spg_params(pl);
+  RN_TRY(common_ws(pl, batch, SC_BASE, 1, p));
+  p.project = project != 0;
+  p.Z = Z;
+  p.Ax = A_vals;
+  p.X = X;
+  if (mixed) {
+    rn_status st = RN_OK;
+    const int64_t na = (int64_t)batch * p.strideA, nx = (int64_t)batch * pl->nnzN;
+    float *A32 = (float *)rn_plan_ws(pl, WS_A32, (size_t)na * 4, &st);
+    float *X32 = (float *)rn_plan_ws(pl, WS_D32, (size_t)nx * 4, &st);
+    if (!A32 || !X32) return st;
+    hipLaunchKernelGGL(k_to_f32, dim3(ew_grid(na)), dim3(RN_BLOCK), 0, ctx->stream, A_vals, na, A32);
+    hipLaunchKernelGGL(k_to_f32, dim3(ew_grid(nx)), dim3(RN_BLOCK), 0, ctx->stream, X, nx, X32);
+    LAUNCH_CHECK(ctx);
+    p.Ax = A32;
+    p.X = X32;
+  }
+  return rn_launch_spgemm(ctx, pl, MODE_PRODUCT, p, batch, mixed);
+}
+
+extern "C" rn_status rn_energy_min(rn_ctx *ctx, rn_plan *pl, const double *A_vals, int32_t batch, const double *T,
+                                   rn_method method, int32_t iters, rn_precision prec, double *P, double *hist,
+                                   rn_emin_stats *stats, rn_tape *tape) {
+  if (!ctx) return RN_EINVAL;
+  ctx->err.clear();
+  if (!pl || !A_vals || !T || !P || batch < 1 || iters < 0)
+    return rn_fail(ctx, RN_EINVAL, "rn_energy_min: bad argument");
+  if (method != RN_CG && method != RN_GMRES) return rn_fail(ctx, RN_EINVAL, "rn_energy_min: bad method");
+  if (prec != RN_FP64 && prec != RN_FP32_MIXED) return rn_fail(ctx, RN_EINVAL, "rn_energy_min: bad precision");
+  if (method == RN_GMRES && iters > RN_MAXDOT - 1)
+    return rn_fail(ctx, RN_ELIMIT, "rn_energy_min: GMRES supports at most %d iterations", RN_MAXDOT - 1);
+  if (tape) RN_TRY(rn_tape_record_begin(ctx, pl, tape, batch, iters, method, prec));
+  const bool mixed = prec == RN_FP32_MIXED;
+  const bool gm = method == RN_GMRES;
+  const int K = iters;
+  const int64_t nz = pl->nnzN, nzb = (int64_t)batch * nz;
+  rn_status st = RN_OK;
+  const unsigned gew = ew_grid(nz);
+  const int scal_stride = gm ? GmLayout(K).total : CgLayout(K).total;
+  const int hist_stride = 3 * K + 1;
+  SpgParams p = rn_spg_params(pl);
+  RN_TRY(common_ws(pl, batch, scal_stride, gew, p));
+  p.K = K;
+  double *part_spg = p.part;
+  double *part_ew = p.part + (int64_t)batch * RN_MAXDOT * pl->nblk;
+  HIP_TRY(ctx, hipMemsetAsync(p.st, 0, (size_t)batch * ST_STRIDE * 4, ctx->stream));
+  HIP_TRY(ctx, hipMemsetAsync(p.scal, 0, (size_t)batch * scal_stride * 8, ctx->stream));
+  if (hist) HIP_TRY(ctx, hipMemsetAsync(hist, 0, (size_t)batch * hist_stride * 8, ctx->stream));
+  const float *A32 = nullptr, *T32 = nullptr;
+  if (mixed) {
+    const int64_t na = (int64_t)batch * p.strideA;
+    float *a32 = (float *)rn_plan_ws(pl, WS_A32, (size_t)na * 4, &st);
+    float *t32 = (float *)rn_plan_ws(pl, WS_T32, (size_t)nz * 4, &st);
+    if (!a32 || !t32) return st;
+    hipLaunchKernelGGL(k_to_f32, dim3(ew_grid(na)), dim3(RN_BLOCK), 0, ctx->stream, A_vals, na, a32);
+    hipLaunchKernelGGL(k_to_f32, dim3(ew_grid(nz)), dim3(RN_BLOCK), 0, ctx->stream, T, nz, t32);
+    LAUNCH_CHECK(ctx);
+    A32 = a32;
+    T32 = t32;
+  }
+  const void *Aop = mixed ? (const void *)A32 : (const void *)A_vals;
+  const void *Top = mixed ? (const void *)T32 : (const void *)T;
+  const dim3 g2(gew, (unsigned)batch), blk(RN_BLOCK);
+  if (!gm) {
+    double *R = (double *)rn_plan_ws(pl, WS_R, (size_t)nzb * 8, &st);
+    double *D = (double *)rn_plan_ws(pl, WS_D, (size_t)nzb * 8, &st);
+    double *Z = (double *)rn_plan_ws(pl, WS_Z, (size_t)nzb * 8, &st);
+    float *D32 = mixed ? (float *)rn_plan_ws(pl, WS_D32, (size_t)nzb * 4, &st) : nullptr;
+    if (!R || !D || !Z || (mixed && !D32)) return st;
+    hipLaunchKernelGGL(k_bcast, g2, blk, 0, ctx->stream, T, nz, nz, P);
+    LAUNCH_CHECK(ctx);
+    // R_0 = D_0 = -Pi(A T), gamma_0
+    SpgParams q = p;
+    q.Ax = Aop;
+    q.X = Top;
+    q.strideX = 0;
+    q.Z = R;
+    q.Z2 = D;
+    RN_TRY(rn_launch_spgemm(ctx, pl, MODE_CG_INIT, q, batch, mixed));
+    hipLaunchKernelGGL(k_cg_fin_init, dim3(batch), blk, 0, ctx->stream, pl->nblk, part_spg, p.scal, scal_stride, K,
+                       p.st, hist, hist_stride);
+    LAUNCH_CHECK(ctx);
+    if (mixed) {
+      hipLaunchKernelGGL(k_to_f32, dim3(ew_grid(nzb)), blk, 0, ctx->stream, D, nzb, D32);
+      LAUNCH_CHECK(ctx);
+    }
+    for (int k = 0; k < K; ++k) {
+      if (tape) RN_TRY(rn_tape_record_step(ctx, tape, k, R, D, nz, batch));
+      SpgParams s = p;
+      s.k = k;
+      s.Ax = Aop;
+      s.X = mixed ? (const void *)D32 : (const void *)D;
+      s.Xown = D;
+      s.Z = Z;
+      RN_TRY(rn_launch_spgemm(ctx, pl, MODE_CG_STEP, s, batch, mixed));
+      hipLaunchKernelGGL(k_cg_update, g2, blk, 0, ctx->stream, nz, nz, K, k, pl->nblk, P, R, D, Z, part_spg, part_ew,
+                         p.scal, scal_stride, p.st, hist, hist_stride);
+      LAUNCH_CHECK(ctx);
+      if (mixed)
+        hipLaunchKernelGGL(k_cg_dir<true>, g2, blk, 0, ctx->stream, nz, nz, K, k, (int)gew, R, D, D32, part_ew, p.scal,
+                           scal_stride, p.st, hist, hist_stride);
+      else
+        hipLaunchKernelGGL(k_cg_dir<false>, g2, blk, 0, ctx->stream, nz, nz, K, k, (int)gew, R, D, (float *)nullptr,
+                           part_ew, p.scal, scal_stride, p.st, hist, hist_stride);
+      LAUNCH_CHECK(ctx);
+    }
+    if (tape) RN_TRY(rn_tape_record_end(ctx, tape, p.scal, p.st, batch));
+  } else {
+    const int64_t ub = (int64_t)(K + 1) * nz;
+    double *U = (double *)rn_plan_ws(pl, WS_U, (size_t)batch * ub * 8, &st);
+    float *U32 = mixed ? (float *)rn_plan_ws(pl, WS_U32, (size_t)batch * ub * 4, &st) : nullptr;
+    if (!U || (mixed && !U32)) return st;
+    SpgParams q = p;
+    q.Ax = Aop;
+    q.X = Top;
+    q.strideX = 0;
+    q.Z = U;
+    q.strideZ = ub;
+    RN_TRY(rn_launch_spgemm(ctx, pl, MODE_GM_INIT, q, batch, mixed));
+    hipLaunchKernelGGL(k_gm_fin<0>, dim3(batch), blk, 0, ctx->stream, pl->nblk, part_spg, K, 0, p.scal, scal_stride,
+                       p.st, hist, hist_stride);
+    LAUNCH_CHECK(ctx);
+    if (mixed) {
+      for (int b = 0; b < batch; ++b)
+        hipLaunchKernelGGL(k_to_f32, dim3(ew_grid(nz)), blk, 0, ctx->stream, U + (int64_t)b * ub, nz,
+                           U32 + (int64_t)b * ub);
+      LAUNCH_CHECK(ctx);
+    }
+    for (int k = 0; k < K; ++k) {
+      SpgParams s = p;
+      s.k = k;
+      s.Ax = Aop;
+      s.X = mixed ? (const void *)(U32 + (int64_t)k * nz) : (const void *)(U + (int64_t)k * nz);
+      s.strideX = ub;
+      s.Z = U + (int64_t)(k + 1) * nz;
+      s.strideZ = ub;
+      s.U = U;
+      s.Ubatch = ub;
+      RN_TRY(rn_launch_spgemm(ctx, pl, MODE_GM_STEP, s, batch, mixed));
+      hipLaunchKernelGGL(k_gm_fin<1>, dim3(batch), blk, 0, ctx->stream, pl->nblk, part_spg, K, k, p.scal,
+                         scal_stride, p.st, hist, hist_stride);
+      LAUNCH_CHECK(ctx);
+#define GM_ORTH(NJ, PASS)                                                                                       \
+  if (mixed)                                                                                                    \
+    hipLaunchKernelGGL((k_gm_orth<NJ, PASS, true>), g2, blk, 0, ctx->stream, nz, ub, K, k, U, U32, part_ew,      \
+                       p.scal, scal_stride, p.st);                                                              \
+  else                                                                                                          \
+    hipLaunchKernelGGL((k_gm_orth<NJ, PASS, false>), g2, blk, 0, ctx->stream, nz, ub, K, k, U, U32, part_ew,     \
+                       p.scal, scal_stride, p.st);                                                              \
+  LAUNCH_CHECK(ctx);
+      if (K + 1 <= 16) {
+        GM_ORTH(16, 1);
+      } else {
+        GM_ORTH(65, 1);
+      }
+      hipLaunchKernelGGL(k_gm_fin<2>, dim3(batch), blk, 0, ctx->stream, (int)gew, part_ew, K, k, p.scal, scal_stride,
+                         p.st, hist, hist_stride);
+      LAUNCH_CHECK(ctx);
+      if (K + 1 <= 16) {
+        GM_ORTH(16, 2);
+      } else {
+        GM_ORTH(65, 2);
+      }
+#undef GM_ORTH
+      hipLaunchKernelGGL(k_gm_fin<3>, dim3(batch), blk, 0, ctx->stream, (int)gew, part_ew, K, k, p.scal, scal_stride,
+                         p.st, hist, hist_stride);
+      LAUNCH_CHECK(ctx);
+    }
+    hipLaunchKernelGGL(k_gm_solve, dim3(batch), dim3(64), 0, ctx->stream, K, p.scal, scal_stride, p.st);
+    LAUNCH_CHECK(ctx);
+    if (K + 1 <= 16)
+      hipLaunchKernelGGL(k_gm_combine<16>, g2, blk, 0, ctx->stream, nz, ub, K, T, U, P, p.scal, scal_stride, p.st);
+    else
+      hipLaunchKernelGGL(k_gm_combine<65>, g2, blk, 0, ctx->stream, nz, ub, K, T, U, P, p.scal, scal_stride, p.st);
+    LAUNCH_CHECK(ctx);
+  }
+  // read back the device status of every batch entry and batch 0's scalars
+  const size_t stb = (size_t)batch * ST_STRIDE * 4;
+  const size_t need = stb + (size_t)scal_stride * 8 + 16;
+  int64_t *hp = ctx->pinned;
+  void *big = nullptr;
+  if (need > 64 * sizeof(int64_t)) {
+    if (hipHostMalloc(&big, need, hipHostMallocDefault) != hipSuccess)
+      return rn_fail(ctx, RN_ENOMEM, "rn_energy_min: pinned staging");
+    hp = (int64_t *)big;
+  }
+  unsigned long long *hterms = (unsigned long long *)((char *)hp + stb + (size_t)scal_stride * 8);
+  HIP_TRY(ctx, hipMemcpyAsync(hp, p.st, stb, hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(ctx, hipMemcpyAsync((char *)hp + stb, p.scal, (size_t)scal_stride * 8, hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(ctx, hipMemcpyAsync(hterms, pl->d_terms, 8, hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  const int32_t *hst = (const int32_t *)hp;
+  const double *hsc = (const double *)((const char *)hp + stb);
+  rn_status res = RN_OK;
+  int bad = -1;
+  for (int b = 0; b < batch; ++b)
+    if (hst[b * ST_STRIDE + ST_STATUS]) {
+      res = (rn_status)hst[b * ST_STRIDE + ST_STATUS];
+      bad = b;
+      break;
+    }
+  if (stats) {
+    stats->iters_done = hst[gm ? ST_KD : ST_ITERS];
+    stats->rank_deficient_rows = pl->rank_def;
+    stats->status_code = hst[ST_STATUS];
+    if (gm) {
+      const GmLayout L(K);
+      stats->first = hsc[SC_BETA0];
+      stats->last = fabs(hsc[L.g + hst[ST_KD]]);
+    } else {
+      const CgLayout L(K);
+      stats->first = hsc[SC_GAMMA0];
+      stats->last = hsc[L.gam + hst[ST_ITERS]];
+    }
+    product_cost(pl, mixed, *hterms, &stats->spgemm_bytes, &stats->spgemm_flops);
+  }
+  if (big) (void)hipHostFree(big);
+  if (res == RN_EBREAKDOWN)
+    return rn_fail(ctx, res, "rn_energy_min: CG curvature <D, Pi(A D)> <= 0 (batch entry %d)", bad);
+  if (res != RN_OK) return rn_fail(ctx, res, "rn_energy_min: non-finite Krylov scalar (batch entry %d)", bad);
+  return RN_OK;
+}

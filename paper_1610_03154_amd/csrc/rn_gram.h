@@ -1,0 +1,186 @@
+// rn_gram.h -- per-row Gram pseudo-inverse used by Eq. Tproj and by the
+// constraint projection Pi_B (Sec. 3.6).  nB <= RN_NBMAX.
+//
+// Decision rule of the least-squares solve: when every Cholesky pivot of
+// G = B_J^T B_J exceeds 1e-12 * max(diag G), G^+ = G^-1 is formed from a
+// backward-stable QR of B_J (CholeskyQR2); otherwise the pseudo-inverse comes
+// from a cyclic Jacobi eigen-decomposition of G keeping eigenvalues above
+// 1e-12 * lambda_max.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#define RN_NBMAX 4
+
+// index of (q, r), q <= r, in the packed upper triangle of an nB x nB matrix
+__host__ __device__ inline int rn_pk(int nB, int q, int r) {
+  if (q > r) { const int t = q; q = r; r = t; }
+  return q * nB - (q * (q - 1)) / 2 + (r - q);
+}
+
+__device__ inline void rn_gram_pinv_eig(int nB, const double *G, double *Gp);
+
+// Least-squares data of one pattern row: Gp = pinv(B_J^T B_J) where the rows
+// of B_J are Bc[J[p]], p in [s, e).  Formed by CholeskyQR2 over the row's
+// entries (two streaming passes, no storage of B_J): G = B_J^T B_J = R1^T R1,
+// then Q1 = B_J R1^-1 and Q1^T Q1 = R2^T R2, R = R2 R1, Gp = R^-1 R^-T.  The
+// result is backward stable (error ~ cond(B_J) eps instead of cond(B_J)^2 eps
+// for inverting G directly).  Rank rule: every pivot of the first Cholesky
+// must exceed 1e-12 max(diag G); otherwise the eigen pseudo-inverse of G.
+// Returns 1 when the fallback was taken.
+template <int NB>
+__device__ inline int rn_row_pinv(const int32_t *__restrict__ J, int s, int e, const double *__restrict__ Bc,
+                                  double *Gp) {
+  double G[NB * NB];
+#pragma unroll
+  for (int q = 0; q < NB * NB; ++q) G[q] = 0.0;
+  for (int p = s; p < e; ++p) {
+    const double *b = Bc + (int64_t)J[p] * NB;
+#pragma unroll
+    for (int q = 0; q < NB; ++q)
+#pragma unroll
+      for (int r = 0; r < NB; ++r) G[q * NB + r] += b[q] * b[r];
+  }
+  double dmax = 0.0;
+#pragma unroll
+  for (int q = 0; q < NB; ++q) dmax = fmax(dmax, G[q * NB + q]);
+  // Cholesky G = R1^T R1, R1 upper triangular
+  double R1[NB * NB];
+#pragma unroll
+  for (int q = 0; q < NB * NB; ++q) R1[q] = 0.0;
+  bool ok = dmax > 0.0 && (e - s) >= NB;
+  for (int k = 0; k < NB && ok; ++k) {
+    double d = G[k * NB + k];
+    for (int l = 0; l < k; ++l) d -= R1[l * NB + k] * R1[l * NB + k];
+    if (!(d > 1e-12 * dmax)) {
+      ok = false;
+      break;
+    }
+    const double rk = sqrt(d);
+    R1[k * NB + k] = rk;
+    for (int j = k + 1; j < NB; ++j) {
+      double v = G[k * NB + j];
+      for (int l = 0; l < k; ++l) v -= R1[l * NB + k] * R1[l * NB + j];
+      R1[k * NB + j] = v / rk;
+    }
+  }
+  if (!ok) {
+    rn_gram_pinv_eig(NB, G, Gp);
+    return 1;
+  }
+  // second pass: G2 = sum q q^T with q = b R1^-1 (forward substitution)
+  double G2[NB * NB];
+#pragma unroll
+  for (int q = 0; q < NB * NB; ++q) G2[q] = 0.0;
+  for (int p = s; p < e; ++p) {
+    const double *b = Bc + (int64_t)J[p] * NB;
+    double qv[NB];
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+      double v = b[k];
+#pragma unroll
+      for (int l = 0; l < k; ++l) v -= R1[l * NB + k] * qv[l];
+      qv[k] = v / R1[k * NB + k];
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q)
+#pragma unroll
+      for (int r = 0; r < NB; ++r) G2[q * NB + r] += qv[q] * qv[r];
+  }
+  double R2[NB * NB];
+#pragma unroll
+  for (int q = 0; q < NB * NB; ++q) R2[q] = 0.0;
+  for (int k = 0; k < NB; ++k) {
+    double d = G2[k * NB + k];
+    for (int l = 0; l < k; ++l) d -= R2[l * NB + k] * R2[l * NB + k];
+    if (!(d > 0.0)) {
+      rn_gram_pinv_eig(NB, G, Gp);
+      return 1;
+    }
+    const double rk = sqrt(d);
+    R2[k * NB + k] = rk;
+    for (int j = k + 1; j < NB; ++j) {
+      double v = G2[k * NB + j];
+      for (int l = 0; l < k; ++l) v -= R2[l * NB + k] * R2[l * NB + j];
+      R2[k * NB + j] = v / rk;
+    }
+  }
+  // R = R2 R1 (upper), Ri = R^-1, Gp = Ri Ri^T
+  double R[NB * NB], Ri[NB * NB];
+#pragma unroll
+  for (int q = 0; q < NB; ++q)
+#pragma unroll
+    for (int r = 0; r < NB; ++r) {
+      double v = 0.0;
+      for (int l = q; l <= r; ++l) v += R2[q * NB + l] * R1[l * NB + r];
+      R[q * NB + r] = r >= q ? v : 0.0;
+      Ri[q * NB + r] = 0.0;
+    }
+  for (int c = 0; c < NB; ++c) {
+    Ri[c * NB + c] = 1.0 / R[c * NB + c];
+    for (int r = c - 1; r >= 0; --r) {
+      double v = 0.0;
+      for (int l = r + 1; l <= c; ++l) v += R[r * NB + l] * Ri[l * NB + c];
+      Ri[r * NB + c] = -v / R[r * NB + r];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < NB; ++q)
+#pragma unroll
+    for (int r = 0; r < NB; ++r) {
+      double v = 0.0;
+#pragma unroll
+      for (int l = 0; l < NB; ++l) v += Ri[q * NB + l] * Ri[r * NB + l];
+      Gp[q * NB + r] = v;
+    }
+  return 0;
+}
+
+// Eigen pseudo-inverse of a symmetric nB x nB Gram matrix (cyclic Jacobi):
+// eigenvalues above 1e-12 lambda_max are inverted, the rest dropped.
+__device__ inline void rn_gram_pinv_eig(int nB, const double *G, double *Gp) {
+  // cyclic Jacobi eigen-decomposition of G
+  double w[RN_NBMAX][RN_NBMAX], v[RN_NBMAX][RN_NBMAX];
+  for (int q = 0; q < nB; ++q)
+    for (int r = 0; r < nB; ++r) {
+      w[q][r] = G[q * nB + r];
+      v[q][r] = (q == r) ? 1.0 : 0.0;
+    }
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0;
+    for (int q = 0; q < nB; ++q)
+      for (int r = q + 1; r < nB; ++r) off += w[q][r] * w[q][r];
+    if (off == 0.0) break;
+    for (int q = 0; q < nB; ++q)
+      for (int r = q + 1; r < nB; ++r) {
+        const double wqr = w[q][r];
+        if (wqr == 0.0) continue;
+        const double th = (w[r][r] - w[q][q]) / (2.0 * wqr);
+        const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+        const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+        for (int k = 0; k < nB; ++k) {  // columns q, r
+          const double x = w[k][q], y = w[k][r];
+          w[k][q] = c * x - s * y;
+          w[k][r] = s * x + c * y;
+        }
+        for (int k = 0; k < nB; ++k) {  // rows q, r
+          const double x = w[q][k], y = w[r][k];
+          w[q][k] = c * x - s * y;
+          w[r][k] = s * x + c * y;
+        }
+        for (int k = 0; k < nB; ++k) {
+          const double x = v[k][q], y = v[k][r];
+          v[k][q] = c * x - s * y;
+          v[k][r] = s * x + c * y;
+        }
+      }
+  }
+  double lmax = 0.0;
+  for (int q = 0; q < nB; ++q) lmax = fmax(lmax, w[q][q]);
+  for (int q = 0; q < nB * nB; ++q) Gp[q] = 0.0;
+  for (int e = 0; e < nB; ++e) {
+    const double lam = w[e][e];
+    if (!(lam > 1e-12 * lmax) || lam <= 0.0) continue;
+    for (int q = 0; q < nB; ++q)
+      for (int r = 0; r < nB; ++r) Gp[q * nB + r] += v[q][e] * v[r][e] / lam;
+  }
+}

@@ -1,0 +1,229 @@
+// rn_internal.h -- shared internals of librnamg (context, scratch, launch
+// checks, deterministic block reductions).  gfx950 only: wave64.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "rnamg.h"
+
+#define RN_WAVE 64
+#define RN_BLOCK 256
+
+// ---------------------------------------------------------------------------
+// scratch slots owned by a context (grow-only)
+// ---------------------------------------------------------------------------
+enum RnSlot {
+  SLOT_SCAN_BSUM = 0,
+  SLOT_SCAN_TOTAL,
+  SLOT_STR_DIAG,
+  SLOT_STR_MASK,
+  SLOT_STR_TP,
+  SLOT_STR_TJ,
+  SLOT_STR_TPERM,
+  SLOT_STR_TMASK,
+  SLOT_STR_CNT,
+  SLOT_STR_SJ,
+  SLOT_TR_CNT,
+  SLOT_TR_ROW,
+  SLOT_TR_PERM,
+  SLOT_PAT_XP0,
+  SLOT_PAT_XJ0,
+  SLOT_PAT_XP1,
+  SLOT_PAT_XJ1,
+  SLOT_PAT_CNT,
+  SLOT_PAT_FLAG,
+  SLOT_TEN_BINV,
+  SLOT_TEN_FLAG,
+  SLOT_MISC,
+  SLOT_GUARD,
+  SLOT_COUNT
+};
+
+struct RnScratch {
+  void *ptr = nullptr;
+  size_t cap = 0;
+};
+
+struct rn_ctx {
+  hipStream_t stream = nullptr;
+  int device = 0;
+  std::string err;
+  RnScratch slot[SLOT_COUNT];
+  int64_t *pinned = nullptr;  // small pinned host staging area (64 x int64)
+  // two-phase caches
+  int64_t str_nnz = -1;
+  int32_t str_nodes = -1;
+  int64_t pat_nnz = -1;        // nnz of the DOF pattern
+  int32_t pat_n = -1;          // rows of the DOF pattern
+  int pat_buf = 0;             // which of XP0/XP1 holds the final nodal pattern
+  int32_t pat_m = 1;
+};
+
+// Error helpers -------------------------------------------------------------
+rn_status rn_fail(rn_ctx *ctx, rn_status st, const char *fmt, ...);
+
+#define RN_TRY(expr)                   \
+  do {                                 \
+    rn_status _s = (expr);             \
+    if (_s != RN_OK) return _s;        \
+  } while (0)
+
+#define HIP_TRY(ctx, expr)                                                       \
+  do {                                                                           \
+    hipError_t _e = (expr);                                                      \
+    if (_e != hipSuccess)                                                        \
+      return rn_fail((ctx), RN_EHIP, "%s:%d %s: %s", __FILE__, __LINE__, #expr,  \
+                     hipGetErrorString(_e));                                     \
+  } while (0)
+
+#define LAUNCH_CHECK(ctx) HIP_TRY(ctx, hipGetLastError())
+
+// Grow-only scratch; contents are not preserved on growth.
+void *rn_scratch(rn_ctx *ctx, int slot, size_t bytes, rn_status *st);
+
+// Device exclusive scan of n int32 counts into out[0..n] (out[n] = total).
+// The total is also left in device memory at *total_dev (int64) and, when
+// total_host != NULL, copied to the host (synchronising the stream).
+// RN_ELIMIT when the total reaches 2^31.
+rn_status rn_scan_counts(rn_ctx *ctx, const int32_t *counts, int32_t *out,
+                         int64_t n, int64_t *total_host);
+
+// Read one int64 from device memory (synchronises the stream).
+rn_status rn_read_i64(rn_ctx *ctx, const void *dev, int64_t *out);
+
+// Input guard of one public call.  Validation kernels set bits in a device
+// int32; every kernel that indexes memory with caller data reads the guard
+// first and does nothing when it is set, so malformed input cannot fault.
+// The host reads the guard at the call's next synchronisation.
+enum RnGuardBits { GUARD_A = 1, GUARD_S = 2, GUARD_N = 4, GUARD_AGG = 8, GUARD_ROOTS = 16, GUARD_LIMIT = 32 };
+int32_t *rn_guard_begin(rn_ctx *ctx, rn_status *st);
+// rows x cols CSR: rowptr[0] = 0, non-decreasing, rowptr[rows] = nnz,
+// columns in [0, cols) and strictly increasing within a row.
+rn_status rn_validate_csr(rn_ctx *ctx, int32_t rows, int32_t cols, int64_t nnz, const int32_t *Ap,
+                          const int32_t *Aj, int32_t *guard, int32_t bit);
+// every a[q] in [lo, hi)
+rn_status rn_validate_range(rn_ctx *ctx, int64_t n, const int32_t *a, int32_t lo, int32_t hi, int32_t *guard,
+                            int32_t bit);
+// Reads the guard (synchronises); RN_EINVAL naming the failed input.
+rn_status rn_check_guard(rn_ctx *ctx, const int32_t *guard, const char *what);
+// Reads the guard and one int64 with a single synchronisation.
+rn_status rn_read_guard_i64(rn_ctx *ctx, const int32_t *guard, const void *dev, int64_t *out, const char *what);
+rn_status rn_gather_values(rn_ctx *ctx, const double *src, const int32_t *idx, int64_t n, double *dst);
+
+// Internal transpose of a CSR structure with a permutation (used by the
+// strength symmetrisation and by rn_transpose).  rows x cols -> cols x rows.
+rn_status rn_transpose_structure(rn_ctx *ctx, int32_t rows, int32_t cols,
+                                 int64_t nnz, const int32_t *Ap,
+                                 const int32_t *Aj, int32_t *Tp, int32_t *Tj,
+                                 int32_t *perm, const int32_t *guard);
+
+static inline unsigned rn_div_up(int64_t a, int64_t b) {
+  return (unsigned)((a + b - 1) / b);
+}
+
+// ---------------------------------------------------------------------------
+// device helpers
+// ---------------------------------------------------------------------------
+// Error-free transformation a + b = s + e (Knuth's TwoSum).
+__device__ inline void rn_two_sum(double a, double b, double &s, double &e) {
+  s = a + b;
+  const double bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+
+// Compensated running sum: hi carries the sum, lo the accumulated rounding.
+struct RnAcc {
+  double hi = 0.0, lo = 0.0;
+  __device__ inline void add(double v) {
+    double s, e;
+    rn_two_sum(hi, v, s, e);
+    hi = s;
+    lo += e;
+  }
+};
+
+// Deterministic compensated block sum (blockDim.x == 256): a fixed shuffle
+// tree within each wave and a fixed-order combination of the four waves, each
+// addition done with TwoSum so the result is accurate to a few ulp whatever
+// the number of terms.  lds8 holds 8 doubles.  Every thread gets the result.
+__device__ inline double rn_block_sum2(double hi, double lo, double *lds8) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const double oh = __shfl_down(hi, off, RN_WAVE), ol = __shfl_down(lo, off, RN_WAVE);
+    double s, e;
+    rn_two_sum(hi, oh, s, e);
+    hi = s;
+    lo = lo + ol + e;
+  }
+  const int lane = threadIdx.x & (RN_WAVE - 1), wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) {
+    lds8[wid] = hi;
+    lds8[4 + wid] = lo;
+  }
+  __syncthreads();
+  double h = lds8[0], l = lds8[4];
+#pragma unroll
+  for (int w = 1; w < 4; ++w) {
+    double s, e;
+    rn_two_sum(h, lds8[w], s, e);
+    h = s;
+    l = l + lds8[4 + w] + e;
+  }
+  __syncthreads();
+  return h + l;
+}
+__device__ inline double rn_block_sum(double v, double *lds8) { return rn_block_sum2(v, 0.0, lds8); }
+
+// Ticket of the last block to finish: every block's thread 0 calls this
+// after its partial results are stored.  Release/acquire at agent scope
+// make all blocks' partials visible to the last one (works across XCDs).
+__device__ inline bool rn_last_block(unsigned *counter, unsigned nblocks) {
+  __shared__ int s_last;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned t = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL,
+                                        __HIP_MEMORY_SCOPE_AGENT);
+    s_last = (t == nblocks - 1);
+    if (s_last)
+      __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __syncthreads();
+  const bool last = s_last != 0;
+  if (last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  return last;
+}
+
+// Release the partial results written by this block before taking a ticket.
+__device__ inline void rn_release() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+}
+
+// First index i in [0, n] with a[i] >= x (a non-decreasing, a[n] exists).
+__device__ inline int rn_lower_bound(const int32_t *a, int n, int64_t x) {
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    int mid = (lo + hi) >> 1;
+    if ((int64_t)a[mid] < x) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+// XCD-aware block order: hardware dispatches consecutive workgroups to the
+// 8 XCDs round-robin; remap so each XCD walks one contiguous range of the
+// logical blocks (keeps neighbouring rows in one L2).  Grid must be padded
+// to a multiple of 8; returns -1 for padding blocks.
+__device__ inline int rn_xcd_block(int hw, int nlogical) {
+  const int per = (nlogical + 7) >> 3;
+  const int lb = (hw & 7) * per + (hw >> 3);
+  return lb < nlogical ? lb : -1;
+}
+static inline unsigned rn_xcd_grid(unsigned nlogical) {
+  unsigned per = (nlogical + 7u) / 8u;
+  return per * 8u;
+}

@@ -1,0 +1,451 @@
+// rn_pattern.hip -- strength of connection (Sec. 3.2) and the interpolation
+// pattern N = S^d C with unamalgamation and root rows (Sec. 3.4).
+// Integer work: results are bit-exact by construction (sorted, unique rows).
+#include "rn_internal.h"
+
+// ---------------------------------------------------------------------------
+// strength
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(RN_BLOCK) void k_diag_csr(int n, const int32_t *__restrict__ Ap,
+                                                      const int32_t *__restrict__ Aj,
+                                                      const double *__restrict__ Ax, double *__restrict__ diag,
+                                                      const int32_t *__restrict__ guard) {
+  const int i = blockIdx.x * RN_BLOCK + threadIdx.x;
+  if (i >= n || *guard) return;
+  double d = 0.0;
+  for (int p = Ap[i]; p < Ap[i + 1]; ++p)
+    if (Aj[p] == i) d = Ax[p];
+  diag[i] = d;
+}
+
+__global__ __launch_bounds__(RN_BLOCK) void k_diag_bsr(int nn, const int32_t *__restrict__ Ap,
+                                                      const int32_t *__restrict__ Aj,
+                                                      const double *__restrict__ Ax, double *__restrict__ diag,
+                                                      const int32_t *__restrict__ guard) {
+  const int I = blockIdx.x * RN_BLOCK + threadIdx.x;
+  if (I >= nn || *guard) return;
+  double d0 = 0.0, d1 = 0.0;
+  for (int p = Ap[I]; p < Ap[I + 1]; ++p)
+    if (Aj[p] == I) { d0 = Ax[4 * (int64_t)p + 0]; d1 = Ax[4 * (int64_t)p + 3]; }
+  diag[2 * I] = d0;
+  diag[2 * I + 1] = d1;
+}
+
+// strong when a^2 >= theta^2 |a_ii a_jj| (rounded products, no FMA); the
+// diagonal is always strong.
+__device__ inline bool rn_is_strong(double a, double di, double dj, double th2, bool on_diag) {
+  return on_diag || (__dmul_rn(a, a) >= __dmul_rn(th2, fabs(__dmul_rn(di, dj))));
+}
+
+__global__ __launch_bounds__(RN_BLOCK) void k_strong_csr(int n, const int32_t *__restrict__ Ap,
+                                                        const int32_t *__restrict__ Aj,
+                                                        const double *__restrict__ Ax,
+                                                        const double *__restrict__ diag, double th2,
+                                                        uint8_t *__restrict__ mask,
+                                                        const int32_t *__restrict__ guard) {
+  const int i = blockIdx.x * RN_BLOCK + threadIdx.x;
+  if (i >= n || *guard) return;
+  const double di = diag[i];
+  for (int p = Ap[i]; p < Ap[i + 1]; ++p) {
+    const int j = Aj[p];
+    mask[p] = rn_is_strong(Ax[p], di, diag[j], th2, i == j);
+  }
+}
+
+__global__ __launch_bounds__(RN_BLOCK) void k_strong_bsr(int nn, const int32_t *__restrict__ Ap,
+                                                        const int32_t *__restrict__ Aj,
+                                                        const double *__restrict__ Ax,
+                                                        const double *__restrict__ diag, double th2,
+                                                        uint8_t *__restrict__ mask,
+                                                        const int32_t *__restrict__ guard) {
+  const int I = blockIdx.x * RN_BLOCK + threadIdx.x;
+  if (I >= nn || *guard) return;
+  for (int p = Ap[I]; p < Ap[I + 1]; ++p) {
+    const int J = Aj[p];
+    bool s = false;
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int cc = 0; cc < 2; ++cc)
+        s |= rn_is_strong(Ax[4 * (int64_t)p + 2 * c + cc], diag[2 * I + c], diag[2 * J + cc], th2,
+                          (2 * I + c) == (2 * J + cc));
+    mask[p] = s;
+  }
+}
+
+__global__ __launch_bounds__(RN_BLOCK) void k_gather_u8(const uint8_t *__restrict__ src,
+                                                       const int32_t *__restrict__ idx, int64_t n,
+                                                       uint8_t *__restrict__ dst,
+                                                       const int32_t *__restrict__ guard) {
+  if (*guard) return;
+  for (int64_t q = (int64_t)blockIdx.x * RN_BLOCK + threadIdx.x; q < n; q += (int64_t)gridDim.x * RN_BLOCK)
+    dst[q] = src[idx[q]];
+}
+
+// Node row I of S u S^T u {I}: a three-way merge of the strong entries of row
+// I of A, of row I of A^T and of the diagonal.  FILL = false counts.
+template <bool FILL>
+__global__ __launch_bounds__(RN_BLOCK) void k_sym_merge(int nn, const int32_t *__restrict__ Ap,
+                                                       const int32_t *__restrict__ Aj,
+                                                       const uint8_t *__restrict__ mask,
+                                                       const int32_t *__restrict__ Tp,
+                                                       const int32_t *__restrict__ Tj,
+                                                       const uint8_t *__restrict__ tmask,
+                                                       int32_t *__restrict__ cnt_or_ptr,
+                                                       int32_t *__restrict__ Sj,
+                                                       const int32_t *__restrict__ guard) {
+  const int I = blockIdx.x * RN_BLOCK + threadIdx.x;
+  if (I >= nn) return;
+  if (*guard) {
+    if (!FILL) cnt_or_ptr[I] = 0;
+    return;
+  }
+  int p = Ap[I], pe = Ap[I + 1], q = Tp[I], qe = Tp[I + 1];
+  const int INF = 0x7fffffff;
+  bool dtodo = true;
+  int last = -1, c = 0, w = FILL ? cnt_or_ptr[I] : 0;
+  while (true) {
+    while (p < pe && !mask[p]) ++p;
+    while (q < qe && !tmask[q]) ++q;
+    const int a = p < pe ? Aj[p] : INF;
+    const int b = q < qe ? Tj[q] : INF;
+    const int d = dtodo ? I : INF;
+    const int v = min(a, min(b, d));
+    if (v == INF) break;
+    if (v != last) {
+      if (FILL) Sj[w + c] = v;
+      ++c;
+      last = v;
+    }
+    if (a == v) ++p;
+    if (b == v) ++q;
+    if (d == v) dtodo = false;
+  }
+  if (!FILL) cnt_or_ptr[I] = c;
+}
+
+__global__ __launch_bounds__(RN_BLOCK) void k_copy_i32(const int32_t *__restrict__ src, int64_t n,
+                                                      int32_t *__restrict__ dst) {
+  for (int64_t q = (int64_t)blockIdx.x * RN_BLOCK + threadIdx.x; q < n; q += (int64_t)gridDim.x * RN_BLOCK)
+    dst[q] = src[q];
+}
+
+static unsigned grid_for(int64_t n, unsigned cap = 8192) {
+  unsigned g = rn_div_up(n, RN_BLOCK);
+  if (g == 0) g = 1;
+  return g > cap ? cap : g;
+}
+
+extern "C" rn_status rn_strength(rn_ctx *ctx, const rn_matrix *A, double theta, int32_t *S_rowptr,
+                                 int32_t *S_colind, int64_t *nnz_S) {
+  if (!ctx) return RN_EINVAL;
+  ctx->err.clear();
+  if (!A || !S_rowptr || !nnz_S) return rn_fail(ctx, RN_EINVAL, "rn_strength: null argument");
+  const int m = A->block_m;
+  if ((m != 1 && m != 2) || A->n < 0 || A->n % m || A->nnz < 0 || !A->rowptr || (A->nnz && (!A->colind || !A->vals)))
+    return rn_fail(ctx, RN_EINVAL, "rn_strength: bad matrix descriptor");
+  if (!(theta >= 0.0)) return rn_fail(ctx, RN_EINVAL, "rn_strength: theta must be >= 0");
+  if (A->nnz >= ((int64_t)1 << 31)) return rn_fail(ctx, RN_ELIMIT, "rn_strength: nnz >= 2^31");
+  const int nn = A->n / m;
+  if (S_colind) {  // phase 2
+    if (ctx->str_nnz < 0 || ctx->str_nodes != nn)
+      return rn_fail(ctx, RN_EINVAL, "rn_strength: phase 2 without a matching phase 1");
+    if (ctx->str_nnz > 0)
+      HIP_TRY(ctx, hipMemcpyAsync(S_colind, ctx->slot[SLOT_STR_SJ].ptr, (size_t)ctx->str_nnz * sizeof(int32_t),
+                                  hipMemcpyDeviceToDevice, ctx->stream));
+    *nnz_S = ctx->str_nnz;
+    ctx->str_nnz = -1;
+    return RN_OK;
+  }
+  rn_status st = RN_OK;
+  const int64_t nz = A->nnz;
+  double *diag = (double *)rn_scratch(ctx, SLOT_STR_DIAG, (size_t)(A->n + 1) * sizeof(double), &st);
+  if (!diag) return st;
+  uint8_t *mask = (uint8_t *)rn_scratch(ctx, SLOT_STR_MASK, (size_t)(nz + 1), &st);
+  if (!mask) return st;
+  int32_t *Tp = (int32_t *)rn_scratch(ctx, SLOT_STR_TP, (size_t)(nn + 1) * sizeof(int32_t), &st);
+  if (!Tp) return st;
+  int32_t *Tj = (int32_t *)rn_scratch(ctx, SLOT_STR_TJ, (size_t)(nz + 1) * sizeof(int32_t), &st);
+  if (!Tj) return st;
+  int32_t *Tperm = (int32_t *)rn_scratch(ctx, SLOT_STR_TPERM, (size_t)(nz + 1) * sizeof(int32_t), &st);
+  if (!Tperm) return st;
+  uint8_t *tmask = (uint8_t *)rn_scratch(ctx, SLOT_STR_TMASK, (size_t)(nz + 1), &st);
+  if (!tmask) return st;
+  int32_t *cnt = (int32_t *)rn_scratch(ctx, SLOT_STR_CNT, (size_t)(nn + 1) * sizeof(int32_t), &st);
+  if (!cnt) return st;
+  int32_t *guard = rn_guard_begin(ctx, &st);
+  if (!guard) return st;
+  RN_TRY(rn_validate_csr(ctx, nn, nn, nz, A->rowptr, A->colind, guard, GUARD_A));
+  const double th2 = theta * theta;
+  if (nn > 0) {
+    if (m == 1) {
+      hipLaunchKernelGGL(k_diag_csr, dim3(rn_div_up(nn, RN_BLOCK)), dim3(RN_BLOCK), 0, ctx->stream, nn, A->rowptr,
+                         A->colind, A->vals, diag, guard);
+      LAUNCH_CHECK(ctx);
+      hipLaunchKernelGGL(k_strong_csr, dim3(rn_div_up(nn, RN_BLOCK)), dim3(RN_BLOCK), 0, ctx->stream, nn,
+                         A->rowptr, A->colind, A->vals, diag, th2, mask, guard);
+    } else {
+      hipLaunchKernelGGL(k_diag_bsr, dim3(rn_div_up(nn, RN_BLOCK)), dim3(RN_BLOCK), 0, ctx->stream, nn, A->rowptr,
+                         A->colind, A->vals, diag, guard);
+      LAUNCH_CHECK(ctx);
+      hipLaunchKernelGGL(k_strong_bsr, dim3(rn_div_up(nn, RN_BLOCK)), dim3(RN_BLOCK), 0, ctx->stream, nn,
+                         A->rowptr, A->colind, A->vals, diag, th2, mask, guard);
+    }
+    LAUNCH_CHECK(ctx);
+  }
+  RN_TRY(rn_transpose_structure(ctx, nn, nn, nz, A->rowptr, A->colind, Tp, Tj, Tperm, guard));
+  if (nz > 0) {
+    hipLaunchKernelGGL(k_gather_u8, dim3(grid_for(nz)), dim3(RN_BLOCK), 0, ctx->stream, mask, Tperm, nz, tmask, guard);
+    LAUNCH_CHECK(ctx);
+  }
+  if (nn > 0) {
+    hipLaunchKernelGGL(k_sym_merge<false>, dim3(rn_div_up(nn, RN_BLOCK)), dim3(RN_BLOCK), 0, ctx->stream, nn,
+                       A->rowptr, A->colind, mask, Tp, Tj, tmask, cnt, (int32_t *)nullptr, guard);
+    LAUNCH_CHECK(ctx);
+  }
+  RN_TRY(rn_scan_counts(ctx, cnt, S_rowptr, nn, nullptr));
+  int64_t total = 0;
+  RN_TRY(rn_read_guard_i64(ctx, guard, ctx->slot[SLOT_SCAN_TOTAL].ptr, &total, "rn_strength"));
+  int32_t *Sj = (int32_t *)rn_scratch(ctx, SLOT_STR_SJ, (size_t)(total + 1) * sizeof(int32_t), &st);
+  if (!Sj) return st;
+  if (nn > 0) {
+    hipLaunchKernelGGL(k_sym_merge<true>, dim3(rn_div_up(nn, RN_BLOCK)), dim3(RN_BLOCK), 0, ctx->stream, nn,
+                       A->rowptr, A->colind, mask, Tp, Tj, tmask, S_rowptr, Sj, guard);
+    LAUNCH_CHECK(ctx);
+  }
+  ctx->str_nnz = total;
+  ctx->str_nodes = nn;
+  *nnz_S = total;
+  return RN_OK;
+}
+
+// ---------------------------------------------------------------------------
+// pattern expansion: X_{t+1}(I) = sorted unique union of X_t(J), J in S(I).
+// A group of EG lanes owns one node row; candidates are staged in LDS and
+// deduplicated by first occurrence, ranks give the sorted position.
+// ---------------------------------------------------------------------------
+#define EG 16
+#define ECAP 512
+#define ERPB (RN_BLOCK / EG)
+
+template <bool FILL>
+__global__ __launch_bounds__(RN_BLOCK) void k_expand(int nn, const int32_t *__restrict__ Sp,
+                                                    const int32_t *__restrict__ Sj,
+                                                    const int32_t *__restrict__ Xp,
+                                                    const int32_t *__restrict__ Xj,
+                                                    int32_t *__restrict__ cnt_or_ptr,
+                                                    int32_t *__restrict__ Yj, int32_t *__restrict__ flag,
+                                                    const int32_t *__restrict__ guard) {
+  __shared__ int32_t cand[ERPB][ECAP];
+  __shared__ uint8_t first[ERPB][ECAP];
+  const int g = threadIdx.x / EG, l = threadIdx.x % EG;
+  const int I = blockIdx.x * ERPB + g;
+  if (*guard) {
+    if (!FILL && I < nn && l == 0) cnt_or_ptr[I] = 0;
+    return;
+  }
+  const bool ok = I < nn;
+  int L = 0;
+  if (ok) {
+    const int s = Sp[I], e = Sp[I + 1];
+    for (int c0 = s; c0 < e; c0 += EG) {
+      const int p = c0 + l;
+      int len = 0, xs = 0;
+      if (p < e) {
+        const int J = Sj[p];
+        xs = Xp[J];
+        len = Xp[J + 1] - xs;
+      }
+      int inc = len;
+#pragma unroll
+      for (int off = 1; off < EG; off <<= 1) {
+        const int t = __shfl_up(inc, off, EG);
+        if (l >= off) inc += t;
+      }
+      const int excl = L + inc - len;
+      const int tot = __shfl(inc, EG - 1, EG);
+      for (int q = 0; q < len; ++q) {
+        const int pos = excl + q;
+        if (pos < ECAP) cand[g][pos] = Xj[xs + q];
+      }
+      L += tot;
+    }
+  }
+  __syncthreads();
+  const int Lc = L < ECAP ? L : ECAP;
+  for (int c = l; c < Lc; c += EG) {
+    const int v = cand[g][c];
+    uint8_t f = 1;
+    for (int u = 0; u < c; ++u)
+      if (cand[g][u] == v) { f = 0; break; }
+    first[g][c] = f;
+  }
+  __syncthreads();
+  if (!ok) return;
+  if (L > ECAP) {
+    if (l == 0) {
+      atomicOr(flag, GUARD_LIMIT);
+      if (!FILL) cnt_or_ptr[I] = 0;
+    }
+    return;
+  }
+  if (!FILL) {
+    int mc = 0;
+    for (int c = l; c < Lc; c += EG) mc += first[g][c];
+#pragma unroll
+    for (int off = EG / 2; off > 0; off >>= 1) mc += __shfl_xor(mc, off, EG);
+    if (l == 0) cnt_or_ptr[I] = mc;
+  } else {
+    const int base = cnt_or_ptr[I];
+    for (int c = l; c < Lc; c += EG) {
+      if (!first[g][c]) continue;
+      const int v = cand[g][c];
+      int rank = 0;
+      for (int u = 0; u < Lc; ++u) rank += (first[g][u] && cand[g][u] < v);
+      Yj[base + rank] = v;
+    }
+  }
+}
+
+__global__ __launch_bounds__(RN_BLOCK) void k_iota(int n, int32_t *__restrict__ out) {
+  const int i = blockIdx.x * RN_BLOCK + threadIdx.x;
+  if (i <= n) out[i] = i;
+}
+
+__global__ __launch_bounds__(RN_BLOCK) void k_dof_count(int n, int m, const int32_t *__restrict__ Xp,
+                                                       const int32_t *__restrict__ agg,
+                                                       const int32_t *__restrict__ roots, int n_agg,
+                                                       int32_t *__restrict__ cnt, uint8_t *__restrict__ is_root,
+                                                       int32_t *__restrict__ flag,
+                                                       const int32_t *__restrict__ guard) {
+  const int i = blockIdx.x * RN_BLOCK + threadIdx.x;
+  if (i >= n) return;
+  if (*guard) {
+    cnt[i] = 0;
+    is_root[i] = 0;
+    return;
+  }
+  const int I = i / m, a = agg[I];
+  if (a < 0 || a >= n_agg) {  // malformed aggregation: reported, row left empty
+    atomicOr(flag, GUARD_AGG);
+    cnt[i] = 0;
+    is_root[i] = 0;
+    return;
+  }
+  const bool root = roots[a] == I;
+  is_root[i] = root;
+  cnt[i] = root ? 1 : m * (Xp[I + 1] - Xp[I]);
+}
+
+__global__ __launch_bounds__(RN_BLOCK) void k_dof_fill(int n, int m, const int32_t *__restrict__ Xp,
+                                                      const int32_t *__restrict__ Xj,
+                                                      const int32_t *__restrict__ agg,
+                                                      const int32_t *__restrict__ Np,
+                                                      const uint8_t *__restrict__ is_root,
+                                                      int32_t *__restrict__ Nj) {
+  // runs only after phase 1 reported success, so its inputs were validated
+  const int i = blockIdx.x * RN_BLOCK + threadIdx.x;
+  if (i >= n) return;
+  const int I = i / m, c = i % m;
+  int w = Np[i];
+  if (is_root[i]) {
+    Nj[w] = m * agg[I] + c;
+    return;
+  }
+  for (int p = Xp[I]; p < Xp[I + 1]; ++p)
+    for (int cc = 0; cc < m; ++cc) Nj[w++] = m * Xj[p] + cc;
+}
+
+extern "C" rn_status rn_pattern(rn_ctx *ctx, int32_t nn, const int32_t *Sp, const int32_t *Sj, const int32_t *agg,
+                                const int32_t *roots, int32_t n_agg, int32_t degree, int32_t m, int32_t *Np,
+                                int32_t *Nj, uint8_t *is_root, int64_t *nnz_N) {
+  if (!ctx) return RN_EINVAL;
+  ctx->err.clear();
+  if (!nnz_N || !Np || (nn > 0 && (!Sp || !Sj || !agg || !is_root)) || (n_agg > 0 && !roots))
+    return rn_fail(ctx, RN_EINVAL, "rn_pattern: null argument");
+  if (nn < 0 || n_agg < 0 || degree < 0 || (m != 1 && m != 2))
+    return rn_fail(ctx, RN_EINVAL, "rn_pattern: bad size (n_nodes %d, n_agg %d, degree %d, m %d)", nn, n_agg,
+                   degree, m);
+  if ((int64_t)nn * m >= ((int64_t)1 << 31)) return rn_fail(ctx, RN_ELIMIT, "rn_pattern: rows >= 2^31");
+  const int n = nn * m;
+  if (Nj) {  // phase 2
+    if (ctx->pat_nnz < 0 || ctx->pat_n != n || ctx->pat_m != m)
+      return rn_fail(ctx, RN_EINVAL, "rn_pattern: phase 2 without a matching phase 1");
+    const int b = ctx->pat_buf;
+    const int32_t *Xp = (const int32_t *)ctx->slot[b ? SLOT_PAT_XP1 : SLOT_PAT_XP0].ptr;
+    const int32_t *Xj = (const int32_t *)ctx->slot[b ? SLOT_PAT_XJ1 : SLOT_PAT_XJ0].ptr;
+    if (n > 0) {
+      hipLaunchKernelGGL(k_dof_fill, dim3(rn_div_up(n, RN_BLOCK)), dim3(RN_BLOCK), 0, ctx->stream, n, m, Xp, Xj,
+                         agg, Np, is_root, Nj);
+      LAUNCH_CHECK(ctx);
+    }
+    *nnz_N = ctx->pat_nnz;
+    ctx->pat_nnz = -1;
+    return RN_OK;
+  }
+  rn_status st = RN_OK;
+  int32_t *cnt = (int32_t *)rn_scratch(ctx, SLOT_PAT_CNT, (size_t)(n + 1) * sizeof(int32_t), &st);
+  if (!cnt) return st;
+  int32_t *guard = rn_guard_begin(ctx, &st);
+  if (!guard) return st;
+  // S is validated against its own last row pointer (nnz = -1)
+  RN_TRY(rn_validate_csr(ctx, nn, nn, -1, Sp, Sj, guard, GUARD_S));
+  RN_TRY(rn_validate_range(ctx, nn, agg, 0, n_agg, guard, GUARD_AGG));
+  RN_TRY(rn_validate_range(ctx, n_agg, roots, 0, nn, guard, GUARD_ROOTS));
+  // X_0 = C: row I holds agg[I]
+  int cur = 0;
+  {
+    int32_t *Xp = (int32_t *)rn_scratch(ctx, SLOT_PAT_XP0, (size_t)(nn + 1) * sizeof(int32_t), &st);
+    if (!Xp) return st;
+    int32_t *Xj = (int32_t *)rn_scratch(ctx, SLOT_PAT_XJ0, (size_t)(nn + 1) * sizeof(int32_t), &st);
+    if (!Xj) return st;
+    hipLaunchKernelGGL(k_iota, dim3(rn_div_up(nn + 1, RN_BLOCK)), dim3(RN_BLOCK), 0, ctx->stream, nn, Xp);
+    LAUNCH_CHECK(ctx);
+    if (nn > 0) {
+      hipLaunchKernelGGL(k_copy_i32, dim3(grid_for(nn)), dim3(RN_BLOCK), 0, ctx->stream, agg, (int64_t)nn, Xj);
+      LAUNCH_CHECK(ctx);
+    }
+  }
+  for (int t = 0; t < degree; ++t) {
+    const int32_t *Xp = (const int32_t *)ctx->slot[cur ? SLOT_PAT_XP1 : SLOT_PAT_XP0].ptr;
+    const int32_t *Xj = (const int32_t *)ctx->slot[cur ? SLOT_PAT_XJ1 : SLOT_PAT_XJ0].ptr;
+    int32_t *Yp = (int32_t *)rn_scratch(ctx, cur ? SLOT_PAT_XP0 : SLOT_PAT_XP1, (size_t)(nn + 1) * sizeof(int32_t),
+                                        &st);
+    if (!Yp) return st;
+    const unsigned g = rn_div_up(nn, ERPB) ? rn_div_up(nn, ERPB) : 1;
+    hipLaunchKernelGGL(k_expand<false>, dim3(g), dim3(RN_BLOCK), 0, ctx->stream, nn, Sp, Sj, Xp, Xj, cnt,
+                       (int32_t *)nullptr, guard, guard);
+    LAUNCH_CHECK(ctx);
+    RN_TRY(rn_scan_counts(ctx, cnt, Yp, nn, nullptr));
+    int64_t total = 0;
+    st = rn_read_guard_i64(ctx, guard, ctx->slot[SLOT_SCAN_TOTAL].ptr, &total, "rn_pattern");
+    if (st == RN_ELIMIT)
+      return rn_fail(ctx, RN_ELIMIT, "rn_pattern: a node row gathers more than %d candidates in step %d", ECAP,
+                     t + 1);
+    RN_TRY(st);
+    if (total >= ((int64_t)1 << 31)) return rn_fail(ctx, RN_ELIMIT, "rn_pattern: nodal pattern reaches 2^31");
+    int32_t *Yj = (int32_t *)rn_scratch(ctx, cur ? SLOT_PAT_XJ0 : SLOT_PAT_XJ1, (size_t)(total + 1) * sizeof(int32_t),
+                                        &st);
+    if (!Yj) return st;
+    hipLaunchKernelGGL(k_expand<true>, dim3(g), dim3(RN_BLOCK), 0, ctx->stream, nn, Sp, Sj, Xp, Xj, Yp, Yj, guard,
+                       guard);
+    LAUNCH_CHECK(ctx);
+    cur ^= 1;
+  }
+  const int32_t *Xp = (const int32_t *)ctx->slot[cur ? SLOT_PAT_XP1 : SLOT_PAT_XP0].ptr;
+  if (n > 0) {
+    hipLaunchKernelGGL(k_dof_count, dim3(rn_div_up(n, RN_BLOCK)), dim3(RN_BLOCK), 0, ctx->stream, n, m, Xp, agg,
+                       roots, n_agg, cnt, is_root, guard, guard);
+    LAUNCH_CHECK(ctx);
+  }
+  RN_TRY(rn_scan_counts(ctx, cnt, Np, n, nullptr));
+  int64_t total = 0;
+  RN_TRY(rn_read_guard_i64(ctx, guard, ctx->slot[SLOT_SCAN_TOTAL].ptr, &total, "rn_pattern"));
+  if (total >= ((int64_t)1 << 31)) return rn_fail(ctx, RN_ELIMIT, "rn_pattern: pattern nnz reaches 2^31");
+  ctx->pat_nnz = total;
+  ctx->pat_n = n;
+  ctx->pat_m = m;
+  ctx->pat_buf = cur;
+  *nnz_N = total;
+  return RN_OK;
+}

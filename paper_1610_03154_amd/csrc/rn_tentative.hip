@@ -1,0 +1,161 @@
+// rn_tentative.hip -- inject (Sec. 3.6): coarse candidates by injection at
+// the root DOFs, the root-node tentative operator of Eq. root-nodeform, and
+// the minimum-norm row update of Eq. Tproj for candidates beyond the first m.
+#include "rn_gram.h"
+#include "rn_internal.h"
+
+__global__ __launch_bounds__(RN_BLOCK) void k_inject_bc(int n_agg, int m, int nB, const int32_t *__restrict__ roots,
+                                                       const double *__restrict__ B, double *__restrict__ Bc,
+                                                       const int32_t *__restrict__ guard) {
+  const int q = blockIdx.x * RN_BLOCK + threadIdx.x;  // coarse DOF m*a + c
+  if (q >= n_agg * m || *guard) return;
+  const int a = q / m, c = q % m;
+  const int64_t src = (int64_t)(m * roots[a] + c) * nB;
+  for (int k = 0; k < nB; ++k) Bc[(int64_t)q * nB + k] = B[src + k];
+}
+
+// inverse of the m x m root block of the first m candidates (m <= 2 here)
+__global__ __launch_bounds__(RN_BLOCK) void k_root_inverse(int n_agg, int m, int nB,
+                                                          const int32_t *__restrict__ roots,
+                                                          const double *__restrict__ B, double *__restrict__ binv,
+                                                          int32_t *__restrict__ flags,
+                                                          const int32_t *__restrict__ guard) {
+  const int a = blockIdx.x * RN_BLOCK + threadIdx.x;
+  if (a >= n_agg || *guard) return;
+  const int64_t r0 = (int64_t)m * roots[a];
+  if (m == 1) {
+    const double b = B[r0 * nB];
+    if (b == 0.0) atomicOr(flags, 1);
+    binv[a] = b != 0.0 ? 1.0 / b : 0.0;
+  } else {
+    const double b00 = B[r0 * nB], b01 = B[r0 * nB + 1];
+    const double b10 = B[(r0 + 1) * nB], b11 = B[(r0 + 1) * nB + 1];
+    const double det = b00 * b11 - b01 * b10;
+    if (det == 0.0) atomicOr(flags, 1);
+    const double id = det != 0.0 ? 1.0 / det : 0.0;
+    binv[4 * a + 0] = b11 * id;
+    binv[4 * a + 1] = -b01 * id;
+    binv[4 * a + 2] = -b10 * id;
+    binv[4 * a + 3] = b00 * id;
+  }
+}
+
+// T on the pattern: root rows = identity row; F row i of aggregate a holds
+// B[i, 0:m] inv(root block) at columns m*a .. m*a+m-1, zero elsewhere.
+__global__ __launch_bounds__(RN_BLOCK) void k_tent_T(int n, int m, int nB, const int32_t *__restrict__ Np,
+                                                    const int32_t *__restrict__ Nj,
+                                                    const uint8_t *__restrict__ is_root,
+                                                    const int32_t *__restrict__ agg, const double *__restrict__ B,
+                                                    const double *__restrict__ binv, double *__restrict__ T,
+                                                    const int32_t *__restrict__ guard) {
+  const int i = blockIdx.x * RN_BLOCK + threadIdx.x;
+  if (i >= n || *guard) return;
+  const int a = agg[i / m], c = i % m;
+  const bool root = is_root[i];
+  for (int p = Np[i]; p < Np[i + 1]; ++p) {
+    const int j = Nj[p];
+    double t = 0.0;
+    if (root) {
+      t = (j == m * a + c) ? 1.0 : 0.0;
+    } else if (j / m == a) {
+      const int cc = j % m;
+      for (int r = 0; r < m; ++r) t += B[(int64_t)i * nB + r] * binv[(int64_t)a * m * m + r * m + cc];
+    }
+    T[p] = t;
+  }
+}
+
+// Eq. Tproj on F rows: t <- t + (B_i - t B_J) G^+ B_J^T, G = B_J^T B_J
+template <int NB>
+__global__ __launch_bounds__(RN_BLOCK) void k_tproj(int n, const int32_t *__restrict__ Np,
+                                                   const int32_t *__restrict__ Nj,
+                                                   const uint8_t *__restrict__ is_root,
+                                                   const double *__restrict__ B, const double *__restrict__ Bc,
+                                                   double *__restrict__ T, int32_t *__restrict__ rank_def,
+                                                   const int32_t *__restrict__ guard) {
+  const int i = blockIdx.x * RN_BLOCK + threadIdx.x;
+  if (i >= n || *guard || is_root[i]) return;
+  double Gp[NB * NB], rr[NB], y[NB], ts[NB];
+  const int s = Np[i], e = Np[i + 1];
+  // r = B_i - t B_J
+#pragma unroll
+  for (int q = 0; q < NB; ++q) ts[q] = 0.0;
+  for (int p = s; p < e; ++p) {
+    const double *b = Bc + (int64_t)Nj[p] * NB;
+    const double t = T[p];
+#pragma unroll
+    for (int q = 0; q < NB; ++q) ts[q] += t * b[q];
+  }
+#pragma unroll
+  for (int q = 0; q < NB; ++q) rr[q] = B[(int64_t)i * NB + q] - ts[q];
+  if (rn_row_pinv<NB>(Nj, s, e, Bc, Gp)) atomicAdd(rank_def, 1);
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    double v = 0.0;
+#pragma unroll
+    for (int r = 0; r < NB; ++r) v += Gp[q * NB + r] * rr[r];
+    y[q] = v;
+  }
+  for (int p = s; p < e; ++p) {
+    const double *b = Bc + (int64_t)Nj[p] * NB;
+    double u = 0.0;
+#pragma unroll
+    for (int q = 0; q < NB; ++q) u += b[q] * y[q];
+    T[p] += u;
+  }
+}
+
+extern "C" rn_status rn_tentative(rn_ctx *ctx, int32_t n, int32_t m, const int32_t *Np, const int32_t *Nj,
+                                  int64_t nnz_N, const uint8_t *is_root, const int32_t *agg, const int32_t *roots,
+                                  int32_t n_agg, const double *B, int32_t nB, double *T, double *Bc,
+                                  int32_t *rank_deficient) {
+  if (!ctx) return RN_EINVAL;
+  ctx->err.clear();
+  if ((m != 1 && m != 2) || n < 0 || n % m || n_agg < 0 || nnz_N < 0 || nB < m || nB > RN_NBMAX)
+    return rn_fail(ctx, RN_EINVAL, "rn_tentative: bad sizes (n %d, m %d, n_agg %d, nB %d; need m <= nB <= %d)", n,
+                   m, n_agg, nB, RN_NBMAX);
+  if (n > 0 && (!Np || !Nj || !is_root || !agg || !B || !T)) return rn_fail(ctx, RN_EINVAL, "rn_tentative: null argument");
+  if (n_agg > 0 && (!roots || !Bc)) return rn_fail(ctx, RN_EINVAL, "rn_tentative: null argument");
+  if (nnz_N >= ((int64_t)1 << 31)) return rn_fail(ctx, RN_ELIMIT, "rn_tentative: nnz_N >= 2^31");
+  rn_status st = RN_OK;
+  const int nn = n / m, nc = m * n_agg;
+  double *binv = (double *)rn_scratch(ctx, SLOT_TEN_BINV, (size_t)(n_agg + 1) * m * m * sizeof(double), &st);
+  if (!binv) return st;
+  int32_t *flags = (int32_t *)rn_scratch(ctx, SLOT_TEN_FLAG, 4 * sizeof(int32_t), &st);
+  if (!flags) return st;
+  HIP_TRY(ctx, hipMemsetAsync(flags, 0, 4 * sizeof(int32_t), ctx->stream));
+  int32_t *guard = rn_guard_begin(ctx, &st);
+  if (!guard) return st;
+  RN_TRY(rn_validate_csr(ctx, n, nc, nnz_N, Np, Nj, guard, GUARD_N));
+  RN_TRY(rn_validate_range(ctx, nn, agg, 0, n_agg, guard, GUARD_AGG));
+  RN_TRY(rn_validate_range(ctx, n_agg, roots, 0, nn, guard, GUARD_ROOTS));
+  if (nc > 0) {
+    hipLaunchKernelGGL(k_inject_bc, dim3(rn_div_up(nc, RN_BLOCK)), dim3(RN_BLOCK), 0, ctx->stream, n_agg, m, nB,
+                       roots, B, Bc, guard);
+    LAUNCH_CHECK(ctx);
+    hipLaunchKernelGGL(k_root_inverse, dim3(rn_div_up(n_agg, RN_BLOCK)), dim3(RN_BLOCK), 0, ctx->stream, n_agg, m,
+                       nB, roots, B, binv, flags, guard);
+    LAUNCH_CHECK(ctx);
+  }
+  if (n > 0) {
+    hipLaunchKernelGGL(k_tent_T, dim3(rn_div_up(n, RN_BLOCK)), dim3(RN_BLOCK), 0, ctx->stream, n, m, nB, Np, Nj,
+                       is_root, agg, B, binv, T, guard);
+    LAUNCH_CHECK(ctx);
+    if (nB > m) {
+      const dim3 g(rn_div_up(n, RN_BLOCK)), b(RN_BLOCK);
+      switch (nB) {
+        case 2: hipLaunchKernelGGL(k_tproj<2>, g, b, 0, ctx->stream, n, Np, Nj, is_root, B, Bc, T, flags + 1, guard); break;
+        case 3: hipLaunchKernelGGL(k_tproj<3>, g, b, 0, ctx->stream, n, Np, Nj, is_root, B, Bc, T, flags + 1, guard); break;
+        case 4: hipLaunchKernelGGL(k_tproj<4>, g, b, 0, ctx->stream, n, Np, Nj, is_root, B, Bc, T, flags + 1, guard); break;
+      }
+      LAUNCH_CHECK(ctx);
+    }
+  }
+  // flags land in pinned[4..]; rn_check_guard uses pinned[0] and synchronises
+  const int32_t *hf = (const int32_t *)(ctx->pinned + 4);
+  HIP_TRY(ctx, hipMemcpyAsync((void *)hf, flags, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
+  RN_TRY(rn_check_guard(ctx, guard, "rn_tentative"));
+  if (hf[0]) return rn_fail(ctx, RN_ESINGULAR, "rn_tentative: singular root block of B");
+  if (rank_deficient) *rank_deficient = hf[1];
+  return RN_OK;
+}
