@@ -70,6 +70,9 @@ struct rn_plan {
   int64_t ncodes = 0;
   int32_t *nodeptr = nullptr;   // block_m = 2: node-entry row pointer
   int32_t *blk_row = nullptr;   // product blocks: first row of block b, b = 0..nblk
+  int32_t *blk_hdr = nullptr;   // per block: r0, r1, e0, e1, a0, a1 (8 ints)
+  int32_t *xoff = nullptr;      // per stored A entry: first pattern entry of the
+                                // neighbour row (block_m = 2: of rows 2K, 2K+1)
   double *gp = nullptr;         // packed Gram pseudo-inverse per DOF row
   int32_t rank_def = 0, maxlen = 0, chunk = 1, nblk = 0;
   unsigned long long *d_terms = nullptr;  // multiply-add terms of one product
@@ -83,7 +86,7 @@ void *rn_plan_ws(rn_plan *pl, int slot, size_t bytes, rn_status *st);
 struct SpgParams {
   int32_t n, nr, nblk, k, K, hist_stride, project, scal_stride;
   int64_t nnzN, strideA, strideX, strideZ, Ubatch;
-  const int32_t *Ap, *Aj, *Np, *Nj, *code_ptr, *nodeptr, *blk_row;
+  const int32_t *Ap, *Aj, *Np, *Nj, *code_ptr, *nodeptr, *blk_row, *blk_hdr, *xoff;
   const uint8_t *codes, *is_root;
   const double *Bc, *gp;
   const void *Ax;      // double or float, [batch][strideA]

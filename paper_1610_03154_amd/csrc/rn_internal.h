@@ -41,6 +41,9 @@ enum RnSlot {
   SLOT_TEN_FLAG,
   SLOT_MISC,
   SLOT_GUARD,
+  SLOT_BLK0,
+  SLOT_BLK1,
+  SLOT_BLK2,
   SLOT_COUNT
 };
 

@@ -136,8 +136,132 @@ static unsigned grid_for(int64_t n, unsigned cap = 8192) {
   return g > cap ? cap : g;
 }
 
+// Strong set of node row I made symmetric through A's own structure: entry
+// (I,J) is kept when it or its partner (J,I) is strong.  Valid when A is
+// structurally symmetric; a missing partner sets *asym (the caller then takes
+// the transpose path).  cnt[I] counts the kept entries plus the diagonal when
+// it is not stored.
+__global__ __launch_bounds__(RN_BLOCK) void k_partner_mask(int nn, const int32_t *__restrict__ Ap,
+                                                          const int32_t *__restrict__ Aj,
+                                                          const uint8_t *__restrict__ mask,
+                                                          uint8_t *__restrict__ symmask, int32_t *__restrict__ cnt,
+                                                          int32_t *__restrict__ asym,
+                                                          const int32_t *__restrict__ guard) {
+  const int I = blockIdx.x * RN_BLOCK + threadIdx.x;
+  if (*guard) {
+    if (I < nn) cnt[I] = 0;
+    return;
+  }
+  bool missing = false;
+  if (I < nn) {
+    int c = 0;
+    bool diag = false;
+    for (int p = Ap[I]; p < Ap[I + 1]; ++p) {
+      const int J = Aj[p];
+      bool s = mask[p];
+      if (J == I) {
+        diag = true;
+      } else {
+        int lo = Ap[J], hi = Ap[J + 1];
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if (Aj[mid] < I) lo = mid + 1; else hi = mid;
+        }
+        if (lo < Ap[J + 1] && Aj[lo] == I) s = s || mask[lo];
+        else missing = true;
+      }
+      symmask[p] = s;
+      c += s;
+    }
+    cnt[I] = c + (diag ? 0 : 1);
+  }
+  if (__any(missing) && (threadIdx.x & (RN_WAVE - 1)) == 0) atomicOr(asym, 1);
+}
+
+__global__ __launch_bounds__(RN_BLOCK) void k_partner_fill(int nn, const int32_t *__restrict__ Ap,
+                                                          const int32_t *__restrict__ Aj,
+                                                          const uint8_t *__restrict__ symmask,
+                                                          const int32_t *__restrict__ Sp, int32_t *__restrict__ Sj) {
+  const int I = blockIdx.x * RN_BLOCK + threadIdx.x;
+  if (I >= nn) return;
+  int w = Sp[I];
+  bool placed = false;
+  for (int p = Ap[I]; p < Ap[I + 1]; ++p) {
+    const int J = Aj[p];
+    if (!placed && J >= I) {
+      if (J != I) Sj[w++] = I;  // diagonal not stored: insert it in order
+      placed = true;
+    }
+    if (symmask[p] || J == I) Sj[w++] = J;
+  }
+  if (!placed) Sj[w++] = I;
+}
+
+static rn_status strength_transpose_path(rn_ctx *ctx, const rn_matrix *A, double theta, int32_t *S_rowptr,
+                                         int32_t *S_colind, int64_t *nnz_S);
+
 extern "C" rn_status rn_strength(rn_ctx *ctx, const rn_matrix *A, double theta, int32_t *S_rowptr,
                                  int32_t *S_colind, int64_t *nnz_S) {
+  if (!ctx) return RN_EINVAL;
+  ctx->err.clear();
+  if (!A || !S_rowptr || !nnz_S) return rn_fail(ctx, RN_EINVAL, "rn_strength: null argument");
+  const int m = A->block_m;
+  if ((m != 1 && m != 2) || A->n < 0 || A->n % m || A->nnz < 0 || !A->rowptr || (A->nnz && (!A->colind || !A->vals)))
+    return rn_fail(ctx, RN_EINVAL, "rn_strength: bad matrix descriptor");
+  if (!(theta >= 0.0)) return rn_fail(ctx, RN_EINVAL, "rn_strength: theta must be >= 0");
+  if (A->nnz >= ((int64_t)1 << 31)) return rn_fail(ctx, RN_ELIMIT, "rn_strength: nnz >= 2^31");
+  if (S_colind) return strength_transpose_path(ctx, A, theta, S_rowptr, S_colind, nnz_S);  // phase 2 copy
+  const int nn = A->n / m;
+  const int64_t nz = A->nnz;
+  rn_status st = RN_OK;
+  double *diag = (double *)rn_scratch(ctx, SLOT_STR_DIAG, (size_t)(A->n + 1) * sizeof(double), &st);
+  uint8_t *mask = (uint8_t *)rn_scratch(ctx, SLOT_STR_MASK, (size_t)(nz + 1), &st);
+  uint8_t *symmask = (uint8_t *)rn_scratch(ctx, SLOT_STR_TMASK, (size_t)(nz + 1), &st);
+  int32_t *cnt = (int32_t *)rn_scratch(ctx, SLOT_STR_CNT, (size_t)(nn + 1) * sizeof(int32_t), &st);
+  int32_t *asym = (int32_t *)rn_scratch(ctx, SLOT_BLK0, 64, &st);
+  if (!diag || !mask || !symmask || !cnt || !asym) return st;
+  HIP_TRY(ctx, hipMemsetAsync(asym, 0, sizeof(int32_t), ctx->stream));
+  int32_t *guard = rn_guard_begin(ctx, &st);
+  if (!guard) return st;
+  RN_TRY(rn_validate_csr(ctx, nn, nn, nz, A->rowptr, A->colind, guard, GUARD_A));
+  const double th2 = theta * theta;
+  const dim3 g(rn_div_up(nn > 0 ? nn : 1, RN_BLOCK)), b(RN_BLOCK);
+  if (nn > 0) {
+    if (m == 1) {
+      hipLaunchKernelGGL(k_diag_csr, g, b, 0, ctx->stream, nn, A->rowptr, A->colind, A->vals, diag, guard);
+      hipLaunchKernelGGL(k_strong_csr, g, b, 0, ctx->stream, nn, A->rowptr, A->colind, A->vals, diag, th2, mask,
+                         guard);
+    } else {
+      hipLaunchKernelGGL(k_diag_bsr, g, b, 0, ctx->stream, nn, A->rowptr, A->colind, A->vals, diag, guard);
+      hipLaunchKernelGGL(k_strong_bsr, g, b, 0, ctx->stream, nn, A->rowptr, A->colind, A->vals, diag, th2, mask,
+                         guard);
+    }
+    hipLaunchKernelGGL(k_partner_mask, g, b, 0, ctx->stream, nn, A->rowptr, A->colind, mask, symmask, cnt, asym,
+                       guard);
+    LAUNCH_CHECK(ctx);
+  }
+  RN_TRY(rn_scan_counts(ctx, cnt, S_rowptr, nn, nullptr));
+  // one synchronisation: total, guard and the structural-asymmetry flag
+  int32_t *hasym = (int32_t *)(ctx->pinned + 6);
+  HIP_TRY(ctx, hipMemcpyAsync(hasym, asym, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
+  int64_t total = 0;
+  RN_TRY(rn_read_guard_i64(ctx, guard, ctx->slot[SLOT_SCAN_TOTAL].ptr, &total, "rn_strength"));
+  if (*hasym) return strength_transpose_path(ctx, A, theta, S_rowptr, nullptr, nnz_S);
+  int32_t *Sj = (int32_t *)rn_scratch(ctx, SLOT_STR_SJ, (size_t)(total + 1) * sizeof(int32_t), &st);
+  if (!Sj) return st;
+  if (nn > 0) {
+    hipLaunchKernelGGL(k_partner_fill, g, b, 0, ctx->stream, nn, A->rowptr, A->colind, symmask, S_rowptr, Sj);
+    LAUNCH_CHECK(ctx);
+  }
+  ctx->str_nnz = total;
+  ctx->str_nodes = nn;
+  *nnz_S = total;
+  return RN_OK;
+}
+
+// General path: S u S^T through an explicit transpose of the strong set.
+static rn_status strength_transpose_path(rn_ctx *ctx, const rn_matrix *A, double theta, int32_t *S_rowptr,
+                                         int32_t *S_colind, int64_t *nnz_S) {
   if (!ctx) return RN_EINVAL;
   ctx->err.clear();
   if (!A || !S_rowptr || !nnz_S) return rn_fail(ctx, RN_EINVAL, "rn_strength: null argument");

@@ -28,57 +28,65 @@ void *rn_plan_ws(rn_plan *pl, int slot, size_t bytes, rn_status *st) {
 
 static __device__ inline int pad4(int x) { return (x + 3) & ~3; }
 
-// ---- block_m = 1 ----------------------------------------------------------
+// Block-wide maximum / sum of one int per thread, written by thread 0 to
+// out[blockIdx.x] (no atomics on a shared address: thousands of waves
+// updating one word serialise in the memory system).  Every thread calls it.
+template <bool MAX>
+static __device__ inline void block_to_slot(int v, int32_t *out) {
+  __shared__ int s[RN_BLOCK / RN_WAVE];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const int o = __shfl_xor(v, off, RN_WAVE);
+    v = MAX ? max(v, o) : v + o;
+  }
+  __syncthreads();
+  if ((threadIdx.x & (RN_WAVE - 1)) == 0) s[threadIdx.x / RN_WAVE] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int r = s[0];
+    for (int w = 1; w < RN_BLOCK / RN_WAVE; ++w) r = MAX ? max(r, s[w]) : r + s[w];
+    out[blockIdx.x] = r;
+  }
+}
+
+// one block: out = max or sum of in[0..n)
+template <bool MAX, typename TO>
+__global__ __launch_bounds__(RN_BLOCK) void k_finish_slots(const int32_t *__restrict__ in, int n,
+                                                          TO *__restrict__ out) {
+  __shared__ long long s[RN_BLOCK];
+  long long v = 0;
+  for (int q = threadIdx.x; q < n; q += RN_BLOCK) v = MAX ? (v > in[q] ? v : in[q]) : v + in[q];
+  s[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = RN_BLOCK / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) s[threadIdx.x] = MAX ? (s[threadIdx.x] > s[threadIdx.x + w] ? s[threadIdx.x] : s[threadIdx.x + w])
+                                               : s[threadIdx.x] + s[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = (TO)s[0];
+}
+
+// ---- sizes: code bytes per row (block_m = 1: DOF rows, 2: node rows) -----
 __global__ __launch_bounds__(RN_BLOCK) void k_plan_count_m1(int n, const int32_t *__restrict__ Ap,
                                                            const int32_t *__restrict__ Np,
                                                            const uint8_t *__restrict__ is_root,
                                                            int32_t *__restrict__ ccnt, int32_t *__restrict__ maxlen,
                                                            int32_t *__restrict__ guard) {
   const int i = blockIdx.x * RN_BLOCK + threadIdx.x;
-  if (i >= n) return;
   if (*guard) {
-    ccnt[i] = 0;
+    if (i < n) ccnt[i] = 0;
     return;
   }
-  const int len = Np[i + 1] - Np[i];
-  if (len > CODE_MAXLEN) atomicOr(guard, GUARD_LIMIT);
-  if (len == 0 || (is_root[i] && len != 1)) atomicOr(guard, GUARD_N);
-  atomicMax(maxlen, len);
-  ccnt[i] = is_root[i] ? 0 : len * pad4(Ap[i + 1] - Ap[i]);
-}
-
-__global__ __launch_bounds__(RN_BLOCK) void k_plan_codes_m1(int n, const int32_t *__restrict__ Ap,
-                                                           const int32_t *__restrict__ Aj,
-                                                           const int32_t *__restrict__ Np,
-                                                           const int32_t *__restrict__ Nj,
-                                                           const uint8_t *__restrict__ is_root,
-                                                           const int32_t *__restrict__ code_ptr,
-                                                           uint8_t *__restrict__ codes,
-                                                           unsigned long long *__restrict__ terms,
-                                                           const int32_t *__restrict__ guard) {
-  const int i = blockIdx.x * RN_BLOCK + threadIdx.x;
-  if (i >= n || *guard || is_root[i]) return;
-  const int s = Np[i], len = Np[i + 1] - s;
-  const int a0 = Ap[i], na = Ap[i + 1] - a0, na4 = pad4(na);
-  uint8_t *cw = codes + code_ptr[i];
-  unsigned long long hit = 0;
-  for (int t = 0; t < na; ++t) {
-    const int k = Aj[a0 + t], ks = Np[k], ke = Np[k + 1];
-    int u = ks;
-    for (int r = 0; r < len; ++r) {
-      const int j = Nj[s + r];
-      while (u < ke && Nj[u] < j) ++u;
-      const bool f = u < ke && Nj[u] == j;
-      cw[r * na4 + t] = f ? (uint8_t)(u - ks) : (uint8_t)CODE_NONE;
-      hit += f;
-    }
+  int len = 0;
+  if (i < n) {
+    len = Np[i + 1] - Np[i];
+    if (len > CODE_MAXLEN) atomicOr(guard, GUARD_LIMIT);
+    if (len == 0 || (is_root[i] && len != 1)) atomicOr(guard, GUARD_N);
+    ccnt[i] = is_root[i] ? 0 : len * pad4(Ap[i + 1] - Ap[i]);
   }
-  for (int r = 0; r < len; ++r)
-    for (int t = na; t < na4; ++t) cw[r * na4 + t] = CODE_NONE;
-  atomicAdd(terms, hit);
+  block_to_slot<true>(len, maxlen);  // per-block maxima, finished by k_finish_slots
 }
 
-// ---- block_m = 2 (node rows) --------------------------------------------------
 __global__ __launch_bounds__(RN_BLOCK) void k_plan_count_m2(int nr, const int32_t *__restrict__ Ap,
                                                            const int32_t *__restrict__ Np,
                                                            const uint8_t *__restrict__ is_root,
@@ -86,68 +94,32 @@ __global__ __launch_bounds__(RN_BLOCK) void k_plan_count_m2(int nr, const int32_
                                                            int32_t *__restrict__ maxlen,
                                                            int32_t *__restrict__ guard) {
   const int I = blockIdx.x * RN_BLOCK + threadIdx.x;
-  if (I >= nr) return;
   if (*guard) {
-    ncnt[I] = 0;
-    ccnt[I] = 0;
+    if (I < nr) {
+      ncnt[I] = 0;
+      ccnt[I] = 0;
+    }
     return;
   }
-  const bool root = is_root[2 * I];
-  const int l0 = Np[2 * I + 1] - Np[2 * I], l1 = Np[2 * I + 2] - Np[2 * I + 1];
-  if (root != (bool)is_root[2 * I + 1]) atomicOr(guard, GUARD_N);
-  if (root) {
-    if (l0 != 1 || l1 != 1) atomicOr(guard, GUARD_N);
-    ncnt[I] = 1;
-    ccnt[I] = 0;
-    return;
-  }
-  if (l0 != l1 || (l0 & 1) || l0 == 0) atomicOr(guard, GUARD_N);
-  const int len = l0 / 2;
-  if (len > CODE_MAXLEN) atomicOr(guard, GUARD_LIMIT);
-  atomicMax(maxlen, len);
-  ncnt[I] = len;
-  ccnt[I] = len * pad4(Ap[I + 1] - Ap[I]);
-}
-
-__global__ __launch_bounds__(RN_BLOCK) void k_plan_codes_m2(int nr, const int32_t *__restrict__ Ap,
-                                                           const int32_t *__restrict__ Aj,
-                                                           const int32_t *__restrict__ Np,
-                                                           const int32_t *__restrict__ Nj,
-                                                           const uint8_t *__restrict__ is_root,
-                                                           const int32_t *__restrict__ code_ptr,
-                                                           uint8_t *__restrict__ codes,
-                                                           unsigned long long *__restrict__ terms,
-                                                           const int32_t *__restrict__ guard) {
-  const int I = blockIdx.x * RN_BLOCK + threadIdx.x;
-  if (I >= nr || *guard || is_root[2 * I]) return;
-  const int s = Np[2 * I], len = (Np[2 * I + 1] - s) / 2;
-  const int a0 = Ap[I], na = Ap[I + 1] - a0, na4 = pad4(na);
-  uint8_t *cw = codes + code_ptr[I];
-  unsigned long long hit = 0;
-  for (int t = 0; t < na; ++t) {
-    const int K = Aj[a0 + t], ks = Np[2 * K];
-    if (is_root[2 * K]) {
-      const int aK = Nj[ks] / 2;
-      for (int r = 0; r < len; ++r) {
-        const bool f = Nj[s + 2 * r] / 2 == aK;
-        cw[r * na4 + t] = f ? (uint8_t)CODE_ROOT : (uint8_t)CODE_NONE;
-        hit += f;
-      }
+  int len = 0;
+  if (I < nr) {
+    const bool root = is_root[2 * I];
+    const int l0 = Np[2 * I + 1] - Np[2 * I], l1 = Np[2 * I + 2] - Np[2 * I + 1];
+    if (root != (bool)is_root[2 * I + 1]) atomicOr(guard, GUARD_N);
+    if (root) {
+      if (l0 != 1 || l1 != 1) atomicOr(guard, GUARD_N);
+      ncnt[I] = 1;
+      ccnt[I] = 0;
+      len = 1;
     } else {
-      const int lk = (Np[2 * K + 1] - ks) / 2;
-      int u = 0;
-      for (int r = 0; r < len; ++r) {
-        const int a = Nj[s + 2 * r] / 2;
-        while (u < lk && Nj[ks + 2 * u] / 2 < a) ++u;
-        const bool f = u < lk && Nj[ks + 2 * u] / 2 == a;
-        cw[r * na4 + t] = f ? (uint8_t)u : (uint8_t)CODE_NONE;
-        hit += f;
-      }
+      if (l0 != l1 || (l0 & 1) || l0 == 0) atomicOr(guard, GUARD_N);
+      len = l0 / 2;
+      if (len > CODE_MAXLEN) atomicOr(guard, GUARD_LIMIT);
+      ncnt[I] = len;
+      ccnt[I] = len * pad4(Ap[I + 1] - Ap[I]);
     }
   }
-  for (int r = 0; r < len; ++r)
-    for (int t = na; t < na4; ++t) cw[r * na4 + t] = CODE_NONE;
-  atomicAdd(terms, hit);
+  block_to_slot<true>(len, maxlen);  // per-block maxima, finished by k_finish_slots
 }
 
 template <int NB>
@@ -159,27 +131,121 @@ __global__ __launch_bounds__(RN_BLOCK) void k_plan_gram(int n, const int32_t *__
                                                        const int32_t *__restrict__ guard) {
   constexpr int NP = NB * (NB + 1) / 2;
   const int i = blockIdx.x * RN_BLOCK + threadIdx.x;
-  if (i >= n || *guard) return;
-  double *out = gp + (int64_t)i * NP;
-  if (is_root[i]) {
-    for (int q = 0; q < NP; ++q) out[q] = 0.0;
-    return;
+  if (*guard) return;
+  int bad = 0;
+  if (i < n) {
+    double *out = gp + (int64_t)i * NP;
+    if (is_root[i]) {
+      for (int q = 0; q < NP; ++q) out[q] = 0.0;
+    } else {
+      double Gp[NB * NB];
+      bad = rn_row_pinv<NB>(Nj, Np[i], Np[i + 1], Bc, Gp);
+#pragma unroll
+      for (int q = 0; q < NB; ++q)
+#pragma unroll
+        for (int r = q; r < NB; ++r) out[rn_pk(NB, q, r)] = Gp[q * NB + r];
+    }
   }
-  double Gp[NB * NB];
-  if (rn_row_pinv<NB>(Nj, Np[i], Np[i + 1], Bc, Gp)) atomicAdd(rank_def, 1);
-#pragma unroll
-  for (int q = 0; q < NB; ++q)
-#pragma unroll
-    for (int r = q; r < NB; ++r) out[rn_pk(NB, q, r)] = Gp[q * NB + r];
+  block_to_slot<false>(bad, rank_def);  // per-block counts
 }
 
-// first row of each product block: rows whose first entry falls in
-// [b*chunk, (b+1)*chunk) belong to block b
-__global__ __launch_bounds__(RN_BLOCK) void k_plan_blocks(int nr, const int32_t *__restrict__ rp, int nblk,
-                                                         int chunk, int32_t *__restrict__ blk_row) {
+// ---- block partition: rows whose first entry lies in [b*chunk, (b+1)*chunk)
+// belong to block b; header = r0, r1, e0, e1, a0, a1 (A entries/blocks) ----
+__global__ __launch_bounds__(RN_BLOCK) void k_plan_blocks(int nr, const int32_t *__restrict__ rp,
+                                                         const int32_t *__restrict__ Ap, int nblk, int chunk,
+                                                         int32_t *__restrict__ blk_row,
+                                                         int32_t *__restrict__ hdr) {
   const int b = blockIdx.x * RN_BLOCK + threadIdx.x;
   if (b > nblk) return;
-  blk_row[b] = b == nblk ? nr : rn_lower_bound(rp, nr, (int64_t)b * chunk);
+  const int r0 = rn_lower_bound(rp, nr, (int64_t)b * chunk);
+  blk_row[b] = b == nblk ? nr : r0;
+  if (b == nblk) return;
+  const int r1 = b + 1 == nblk ? nr : rn_lower_bound(rp, nr, (int64_t)(b + 1) * chunk);
+  int32_t *h = hdr + 8 * (int64_t)b;
+  h[0] = r0;
+  h[1] = r1;
+  h[2] = rp[r0];
+  h[3] = rp[r1];
+  h[4] = Ap[r0];
+  h[5] = Ap[r1];
+  h[6] = 0;
+  h[7] = 0;
+}
+
+// ---- first pattern entry of each stored entry's neighbour row -------------
+__global__ __launch_bounds__(RN_BLOCK) void k_plan_xoff(int64_t nnzA, int m, const int32_t *__restrict__ Aj,
+                                                       const int32_t *__restrict__ Np, int32_t *__restrict__ xoff) {
+  for (int64_t q = (int64_t)blockIdx.x * RN_BLOCK + threadIdx.x; q < nnzA; q += (int64_t)gridDim.x * RN_BLOCK) {
+    const int k = Aj[q];
+    if (m == 1) {
+      xoff[q] = Np[k];
+    } else {
+      xoff[2 * q] = Np[2 * k];
+      xoff[2 * q + 1] = Np[2 * k + 1];
+    }
+  }
+}
+
+// ---- position codes: one lane per pattern entry (node entry for block_m = 2),
+// binary search of the entry's column in each neighbour row ----------------
+template <int M>
+__global__ __launch_bounds__(RN_BLOCK) void k_plan_codes(int nr, const int32_t *__restrict__ hdr,
+                                                        const int32_t *__restrict__ rp,
+                                                        const int32_t *__restrict__ Ap,
+                                                        const int32_t *__restrict__ Aj,
+                                                        const int32_t *__restrict__ Np,
+                                                        const int32_t *__restrict__ Nj,
+                                                        const uint8_t *__restrict__ is_root,
+                                                        const int32_t *__restrict__ code_ptr,
+                                                        uint8_t *__restrict__ codes,
+                                                        int32_t *__restrict__ terms) {
+  __shared__ uint8_t s_row[RN_BLOCK];
+  const int32_t *h = hdr + 8 * (int64_t)blockIdx.x;
+  const int r0 = h[0], nrows = h[1] - h[0], e0 = h[2], ne = h[3] - h[2];
+  for (int rr = threadIdx.x; rr < nrows; rr += RN_BLOCK)
+    for (int q = rp[r0 + rr] - e0; q < rp[r0 + rr + 1] - e0; ++q) s_row[q] = (uint8_t)rr;
+  __syncthreads();
+  unsigned long long hit = 0;
+  const int t = threadIdx.x;
+  if (t < ne) {
+    const int i = r0 + s_row[t];
+    const int rdof = M == 1 ? i : 2 * i;
+    if (!is_root[rdof]) {
+      const int r = e0 + t - rp[i];
+      const int a0 = Ap[i], na = Ap[i + 1] - a0, na4 = pad4(na);
+      const int j = M == 1 ? Nj[Np[i] + r] : Nj[Np[2 * i] + 2 * r] / 2;
+      uint32_t *cw = (uint32_t *)(codes + code_ptr[i] + r * na4);
+      for (int t4 = 0; t4 < na4; t4 += 4) {
+        uint32_t word = 0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int tt = t4 + u;
+          uint32_t code = CODE_NONE;
+          if (tt < na) {
+            const int k = Aj[a0 + tt];
+            if (M == 2 && is_root[2 * k]) {
+              code = (Nj[Np[2 * k]] / 2 == j) ? CODE_ROOT : CODE_NONE;
+            } else {
+              // search j among the (node) columns of row k
+              const int ks = Np[M * k], len = (Np[M * k + 1] - ks) / M;
+              int lo = 0, hi = len;
+              while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                const int c = M == 1 ? Nj[ks + mid] : Nj[ks + 2 * mid] / 2;
+                if (c < j) lo = mid + 1; else hi = mid;
+              }
+              const int c = lo < len ? (M == 1 ? Nj[ks + lo] : Nj[ks + 2 * lo] / 2) : -1;
+              if (c == j) code = (uint32_t)lo;
+            }
+            hit += code != CODE_NONE;
+          }
+          word |= code << (8 * u);
+        }
+        cw[t4 >> 2] = word;
+      }
+    }
+  }
+  block_to_slot<false>((int)hit, terms);  // per-block term counts
 }
 
 extern "C" rn_status rn_plan_create(rn_ctx *ctx, const rn_matrix *A, int32_t n_cols, const int32_t *Np,
@@ -196,7 +262,7 @@ extern "C" rn_status rn_plan_create(rn_ctx *ctx, const rn_matrix *A, int32_t n_c
     return rn_fail(ctx, RN_ELIMIT, "rn_plan_create: nB = %d outside the supported range", nB);
   if (A->n > 0 && (!A->rowptr || !Np || !is_root || !Bc || (A->nnz && !A->colind) || (nnz_N && !Nj)))
     return rn_fail(ctx, RN_EINVAL, "rn_plan_create: null argument");
-  if (A->nnz >= ((int64_t)1 << 31) || nnz_N >= ((int64_t)1 << 31))
+  if (A->nnz >= ((int64_t)1 << 30) || nnz_N >= ((int64_t)1 << 31))
     return rn_fail(ctx, RN_ELIMIT, "rn_plan_create: counts reach 2^31");
   rn_plan *pl = new (std::nothrow) rn_plan();
   if (!pl) return rn_fail(ctx, RN_ENOMEM, "rn_plan_create: host allocation");
@@ -234,21 +300,31 @@ extern "C" rn_status rn_plan_create(rn_ctx *ctx, const rn_matrix *A, int32_t n_c
   if (!ccnt) return fail(st);
   if (hipMalloc(&pl->code_ptr, (size_t)(nr + 1) * sizeof(int32_t)) != hipSuccess ||
       hipMalloc(&pl->gp, (size_t)(n + 1) * NP * sizeof(double)) != hipSuccess ||
-      hipMalloc(&pl->d_terms, 16) != hipSuccess)
+      hipMalloc(&pl->d_terms, 16) != hipSuccess ||
+      hipMalloc(&pl->xoff, (size_t)(A->nnz + 1) * m * sizeof(int32_t)) != hipSuccess)
     return fail(rn_fail(ctx, RN_ENOMEM, "rn_plan_create: device allocation"));
   if (m == 2 && hipMalloc(&pl->nodeptr, (size_t)(nr + 1) * sizeof(int32_t)) != hipSuccess)
     return fail(rn_fail(ctx, RN_ENOMEM, "rn_plan_create: device allocation"));
-  pl->fixed_bytes = (size_t)(nr + 1) * 4 * (m == 2 ? 2 : 1) + (size_t)(n + 1) * NP * 8;
+  pl->fixed_bytes = (size_t)(nr + 1) * 4 * (m == 2 ? 2 : 1) + (size_t)(n + 1) * NP * 8 +
+                    (size_t)(A->nnz + 1) * m * 4;
   if (hipMemsetAsync(pl->d_terms, 0, 16, ctx->stream) != hipSuccess) return fail(rn_fail(ctx, RN_EHIP, "memset"));
+  // per-block partial results of the counting kernels
+  const int nbn = (int)rn_div_up(n > 0 ? n : 1, RN_BLOCK);
+  int32_t *blk_max = (int32_t *)rn_scratch(ctx, SLOT_BLK0, (size_t)(nbn + 1) * sizeof(int32_t), &st);
+  int32_t *blk_bad = (int32_t *)rn_scratch(ctx, SLOT_BLK1, (size_t)(nbn + 1) * sizeof(int32_t), &st);
+  if (!blk_max || !blk_bad) return fail(st);
   if (nr > 0) {
+    int nbc;
     if (m == 1) {
-      hipLaunchKernelGGL(k_plan_count_m1, dim3(rn_div_up(n, RN_BLOCK)), dim3(RN_BLOCK), 0, ctx->stream, n, A->rowptr,
-                         Np, is_root, ccnt, misc, guard);
+      nbc = (int)rn_div_up(n, RN_BLOCK);
+      hipLaunchKernelGGL(k_plan_count_m1, dim3(nbc), dim3(RN_BLOCK), 0, ctx->stream, n, A->rowptr, Np, is_root, ccnt,
+                         blk_max, guard);
     } else {
       int32_t *ncnt = (int32_t *)rn_scratch(ctx, SLOT_STR_CNT, (size_t)(nr + 1) * sizeof(int32_t), &st);
       if (!ncnt) return fail(st);
-      hipLaunchKernelGGL(k_plan_count_m2, dim3(rn_div_up(nr, RN_BLOCK)), dim3(RN_BLOCK), 0, ctx->stream, nr,
-                         A->rowptr, Np, is_root, ncnt, ccnt, misc, guard);
+      nbc = (int)rn_div_up(nr, RN_BLOCK);
+      hipLaunchKernelGGL(k_plan_count_m2, dim3(nbc), dim3(RN_BLOCK), 0, ctx->stream, nr, A->rowptr, Np, is_root, ncnt,
+                         ccnt, blk_max, guard);
       if (hipGetLastError() != hipSuccess) return fail(rn_fail(ctx, RN_EHIP, "launch"));
       if (rn_scan_counts(ctx, ncnt, pl->nodeptr, nr, nullptr) != RN_OK) return fail(RN_EHIP);
       if (hipMemcpyAsync(misc + 8, ctx->slot[SLOT_SCAN_TOTAL].ptr, 8, hipMemcpyDeviceToDevice, ctx->stream) !=
@@ -256,13 +332,16 @@ extern "C" rn_status rn_plan_create(rn_ctx *ctx, const rn_matrix *A, int32_t n_c
         return fail(rn_fail(ctx, RN_EHIP, "copy"));
     }
     if (hipGetLastError() != hipSuccess) return fail(rn_fail(ctx, RN_EHIP, "launch"));
-    const dim3 g(rn_div_up(n, RN_BLOCK)), bl(RN_BLOCK);
+    hipLaunchKernelGGL((k_finish_slots<true, int32_t>), dim3(1), dim3(RN_BLOCK), 0, ctx->stream, blk_max, nbc, misc);
+    const dim3 g(nbn), bl(RN_BLOCK);
     switch (nB) {
-      case 1: hipLaunchKernelGGL(k_plan_gram<1>, g, bl, 0, ctx->stream, n, Np, Nj, is_root, Bc, pl->gp, misc + 1, guard); break;
-      case 2: hipLaunchKernelGGL(k_plan_gram<2>, g, bl, 0, ctx->stream, n, Np, Nj, is_root, Bc, pl->gp, misc + 1, guard); break;
-      case 3: hipLaunchKernelGGL(k_plan_gram<3>, g, bl, 0, ctx->stream, n, Np, Nj, is_root, Bc, pl->gp, misc + 1, guard); break;
-      case 4: hipLaunchKernelGGL(k_plan_gram<4>, g, bl, 0, ctx->stream, n, Np, Nj, is_root, Bc, pl->gp, misc + 1, guard); break;
+      case 1: hipLaunchKernelGGL(k_plan_gram<1>, g, bl, 0, ctx->stream, n, Np, Nj, is_root, Bc, pl->gp, blk_bad, guard); break;
+      case 2: hipLaunchKernelGGL(k_plan_gram<2>, g, bl, 0, ctx->stream, n, Np, Nj, is_root, Bc, pl->gp, blk_bad, guard); break;
+      case 3: hipLaunchKernelGGL(k_plan_gram<3>, g, bl, 0, ctx->stream, n, Np, Nj, is_root, Bc, pl->gp, blk_bad, guard); break;
+      case 4: hipLaunchKernelGGL(k_plan_gram<4>, g, bl, 0, ctx->stream, n, Np, Nj, is_root, Bc, pl->gp, blk_bad, guard); break;
     }
+    hipLaunchKernelGGL((k_finish_slots<false, int32_t>), dim3(1), dim3(RN_BLOCK), 0, ctx->stream, blk_bad, nbn,
+                       misc + 1);
     if (hipGetLastError() != hipSuccess) return fail(rn_fail(ctx, RN_EHIP, "launch"));
   }
   if (rn_scan_counts(ctx, ccnt, pl->code_ptr, nr, nullptr) != RN_OK) return fail(RN_EHIP);
@@ -284,29 +363,39 @@ extern "C" rn_status rn_plan_create(rn_ctx *ctx, const rn_matrix *A, int32_t n_c
   pl->nnzN_node = m == 1 ? nnz_N : hp[4];
   if (ncodes >= ((int64_t)1 << 31)) return fail(rn_fail(ctx, RN_ELIMIT, "rn_plan_create: plan codes reach 2^31"));
   pl->ncodes = ncodes;
-  if (hipMalloc(&pl->codes, (size_t)ncodes + 16) != hipSuccess)
-    return fail(rn_fail(ctx, RN_ENOMEM, "rn_plan_create: code allocation (%lld bytes)", (long long)ncodes));
-  pl->fixed_bytes += (size_t)ncodes;
-  if (nr > 0) {
-    if (m == 1)
-      hipLaunchKernelGGL(k_plan_codes_m1, dim3(rn_div_up(n, RN_BLOCK)), dim3(RN_BLOCK), 0, ctx->stream, n, A->rowptr,
-                         A->colind, Np, Nj, is_root, pl->code_ptr, pl->codes, pl->d_terms, guard);
-    else
-      hipLaunchKernelGGL(k_plan_codes_m2, dim3(rn_div_up(nr, RN_BLOCK)), dim3(RN_BLOCK), 0, ctx->stream, nr,
-                         A->rowptr, A->colind, Np, Nj, is_root, pl->code_ptr, pl->codes, pl->d_terms, guard);
-    if (hipGetLastError() != hipSuccess) return fail(rn_fail(ctx, RN_EHIP, "launch"));
-  }
   // product blocks: every block holds at most 256 entries (node entries for
   // block_m = 2): rows starting in a chunk of 257 - maxlen entries
   const int ml = pl->maxlen < 1 ? 1 : pl->maxlen;
   pl->chunk = RN_BLOCK + 1 - ml;
   pl->nblk = (int)((pl->nnzN_node + pl->chunk - 1) / pl->chunk);
-  if (hipMalloc(&pl->blk_row, (size_t)(pl->nblk + 1) * sizeof(int32_t)) != hipSuccess)
-    return fail(rn_fail(ctx, RN_ENOMEM, "rn_plan_create: device allocation"));
-  pl->fixed_bytes += (size_t)(pl->nblk + 1) * 4;
-  hipLaunchKernelGGL(k_plan_blocks, dim3(rn_div_up(pl->nblk + 1, RN_BLOCK)), dim3(RN_BLOCK), 0, ctx->stream, nr,
-                     m == 1 ? Np : pl->nodeptr, pl->nblk, pl->chunk, pl->blk_row);
+  if (hipMalloc(&pl->codes, (size_t)ncodes + 16) != hipSuccess ||
+      hipMalloc(&pl->blk_row, (size_t)(pl->nblk + 1) * sizeof(int32_t)) != hipSuccess ||
+      hipMalloc(&pl->blk_hdr, (size_t)(pl->nblk + 1) * 8 * sizeof(int32_t)) != hipSuccess)
+    return fail(rn_fail(ctx, RN_ENOMEM, "rn_plan_create: code allocation (%lld bytes)", (long long)ncodes));
+  pl->fixed_bytes += (size_t)ncodes + (size_t)(pl->nblk + 1) * 36;
+  const int32_t *rp = m == 1 ? Np : pl->nodeptr;
+  hipLaunchKernelGGL(k_plan_blocks, dim3(rn_div_up(pl->nblk + 1, RN_BLOCK)), dim3(RN_BLOCK), 0, ctx->stream, nr, rp,
+                     A->rowptr, pl->nblk, pl->chunk, pl->blk_row, pl->blk_hdr);
   if (hipGetLastError() != hipSuccess) return fail(rn_fail(ctx, RN_EHIP, "launch"));
+  if (A->nnz > 0) {
+    unsigned g = rn_div_up(A->nnz, RN_BLOCK);
+    hipLaunchKernelGGL(k_plan_xoff, dim3(g > 8192 ? 8192 : g), dim3(RN_BLOCK), 0, ctx->stream, A->nnz, m, A->colind,
+                       Np, pl->xoff);
+    if (hipGetLastError() != hipSuccess) return fail(rn_fail(ctx, RN_EHIP, "launch"));
+  }
+  if (pl->nblk > 0) {
+    int32_t *blk_hit = (int32_t *)rn_scratch(ctx, SLOT_BLK2, (size_t)(pl->nblk + 1) * sizeof(int32_t), &st);
+    if (!blk_hit) return fail(st);
+    if (m == 1)
+      hipLaunchKernelGGL(k_plan_codes<1>, dim3(pl->nblk), dim3(RN_BLOCK), 0, ctx->stream, nr, pl->blk_hdr, rp,
+                         A->rowptr, A->colind, Np, Nj, is_root, pl->code_ptr, pl->codes, blk_hit);
+    else
+      hipLaunchKernelGGL(k_plan_codes<2>, dim3(pl->nblk), dim3(RN_BLOCK), 0, ctx->stream, nr, pl->blk_hdr, rp,
+                         A->rowptr, A->colind, Np, Nj, is_root, pl->code_ptr, pl->codes, blk_hit);
+    hipLaunchKernelGGL((k_finish_slots<false, unsigned long long>), dim3(1), dim3(RN_BLOCK), 0, ctx->stream, blk_hit,
+                       pl->nblk, pl->d_terms);
+    if (hipGetLastError() != hipSuccess) return fail(rn_fail(ctx, RN_EHIP, "launch"));
+  }
   *out = pl;
   return RN_OK;
 }
@@ -314,7 +403,7 @@ extern "C" rn_status rn_plan_create(rn_ctx *ctx, const rn_matrix *A, int32_t n_c
 extern "C" void rn_plan_destroy(rn_plan *pl) {
   if (!pl) return;
   if (pl->ctx) (void)hipStreamSynchronize(pl->ctx->stream);
-  void *bufs[] = {pl->code_ptr, pl->codes, pl->nodeptr, pl->gp, pl->d_terms, pl->blk_row};
+  void *bufs[] = {pl->code_ptr, pl->codes, pl->nodeptr, pl->gp, pl->d_terms, pl->blk_row, pl->blk_hdr, pl->xoff};
   for (void *b : bufs)
     if (b) (void)hipFree(b);
   for (int s = 0; s < WS_COUNT; ++s)

@@ -4,13 +4,15 @@
 //
 // One lane per pattern entry (per 2x2 block of node entries when A is
 // node-blocked); a block owns the rows whose first entry lies in its chunk,
-// so it holds <= 256 entries and whole rows.  The block's stored entries of A
-// (values and the pattern row start of each neighbour) are staged in LDS with
-// coalesced loads; each lane then walks its row of A with one-byte position
-// codes read four at a time and gathers X.  Terms are added one at a time in
-// the order of A's row.  Per-row sums of the projection go through LDS in
-// pattern order.  Krylov dot products are fused into the epilogue as
-// per-block partials (no inter-block synchronisation).
+// so it holds <= 256 entries and whole rows.  The plan supplies, per block,
+// a header (row, entry and A ranges) and, per stored A entry, the first
+// pattern entry of the neighbour row, so a block stages its rows' metadata
+// and its slice of A in LDS with one level of coalesced loads.  Each lane
+// then reads its one-byte position codes four at a time and gathers X;
+// terms are added one at a time in the order of A's row.  Per-row sums of
+// the projection go through LDS in pattern order.  Krylov dot products are
+// fused into the epilogue as per-block partials (no inter-block
+// synchronisation).
 #include <cstring>
 #include <type_traits>
 
@@ -31,7 +33,11 @@ __global__ __launch_bounds__(RN_BLOCK) void k_spgemm(const SpgParams p) {
   using TV = typename SM::TV;
   constexpr int NP = NB * (NB + 1) / 2;
   constexpr int NO = M * M;
-  __shared__ int s_hdr[6];
+  __shared__ int s_rp[RN_BLOCK + 1];   // row starts, relative to the block's first entry
+  __shared__ int s_ap[RN_BLOCK + 1];   // row starts in A, relative to the block's first A entry
+  __shared__ int s_cp[RN_BLOCK];       // code offsets
+  __shared__ int s_np0[M == 2 ? RN_BLOCK : 1], s_np1[M == 2 ? RN_BLOCK : 1];
+  __shared__ uint8_t s_root[RN_BLOCK];
   __shared__ uint8_t s_row[RN_BLOCK];
   __shared__ double s_w[8];
   __shared__ __align__(16) unsigned char s_buf[SM::BYTES];
@@ -51,86 +57,133 @@ __global__ __launch_bounds__(RN_BLOCK) void k_spgemm(const SpgParams p) {
   if (MODE == MODE_CG_STEP || MODE == MODE_GM_STEP)
     if (st[ST_STATUS] || st[ST_DONE]) return;
 
-  const int32_t *rp = (M == 1) ? p.Np : p.nodeptr;
-  if (threadIdx.x == 0) {
-    const int r0 = p.blk_row[blk], r1 = p.blk_row[blk + 1];
-    s_hdr[0] = r0;
-    s_hdr[1] = r1;
-    s_hdr[2] = rp[r0];
-    s_hdr[3] = rp[r1];
-    s_hdr[4] = p.Ap[r0];
-    s_hdr[5] = p.Ap[r1];
-  }
-  __syncthreads();
-  const int r0 = s_hdr[0], nrows = s_hdr[1] - s_hdr[0], e0 = s_hdr[2], ne = s_hdr[3] - s_hdr[2];
-  const int aB = s_hdr[4], naB = s_hdr[5] - s_hdr[4];
+  const int4 h0 = ((const int4 *)p.blk_hdr)[2 * blk];
+  const int4 h1 = ((const int4 *)p.blk_hdr)[2 * blk + 1];
+  const int r0 = h0.x, nrows = h0.y - h0.x, e0 = h0.z, ne = h0.w - h0.z;
+  const int aB = h1.x, naB = h1.y - h1.x;
   const bool staged = naB <= SPG_ACAP;
   const TV *Ax = (const TV *)p.Ax + (int64_t)b * p.strideA;
   const TV *X = (const TV *)p.X + (int64_t)b * p.strideX;
-  for (int rr = threadIdx.x; rr < nrows; rr += RN_BLOCK) {
-    const int s = rp[r0 + rr] - e0, e = rp[r0 + rr + 1] - e0;
-    for (int q = s; q < e; ++q) s_row[q] = (uint8_t)rr;
+  const int32_t *rp = (M == 1) ? p.Np : p.nodeptr;
+  const int t = threadIdx.x;
+  const bool valid = t < ne;
+
+  // ---- stage row metadata and the block's slice of A (one load level) ----
+  for (int rr = t; rr <= nrows; rr += RN_BLOCK) {
+    s_rp[rr] = rp[r0 + rr] - e0;
+    s_ap[rr] = p.Ap[r0 + rr] - aB;
+    if (rr < nrows) {
+      s_cp[rr] = p.code_ptr[r0 + rr];
+      if constexpr (M == 1) {
+        s_root[rr] = p.is_root[r0 + rr];
+      } else {
+        s_root[rr] = p.is_root[2 * (r0 + rr)];
+        s_np0[rr] = p.Np[2 * (r0 + rr)];
+        s_np1[rr] = p.Np[2 * (r0 + rr) + 1];
+      }
+    }
   }
   if (staged) {
-    for (int q = threadIdx.x; q < naB; q += RN_BLOCK) {
-      const int k = p.Aj[aB + q];
-      if (M == 1) {
-        s_x0[q] = p.Np[k];
+    for (int q = t; q < naB; q += RN_BLOCK) {
+      if constexpr (M == 1) {
+        s_x0[q] = p.xoff[aB + q];
       } else {
-        s_x0[q] = p.Np[2 * k];
-        s_x1[q] = p.Np[2 * k + 1];
+        s_x0[q] = p.xoff[2 * (aB + q)];
+        s_x1[q] = p.xoff[2 * (aB + q) + 1];
       }
 #pragma unroll
       for (int o = 0; o < NO; ++o) s_ax[q * NO + o] = Ax[(int64_t)(aB + q) * NO + o];
     }
   }
+  // the lane's own column and candidates (block_m = 1) load meanwhile
+  const bool proj = (MODE != MODE_PRODUCT) || p.project;
+  double bc[M][NB];
+  int jc[M];
+#pragma unroll
+  for (int c = 0; c < M; ++c) {
+    jc[c] = 0;
+#pragma unroll
+    for (int q = 0; q < NB; ++q) bc[c][q] = 0.0;
+  }
+  if constexpr (M == 1) {
+    if (valid) {
+      jc[0] = p.Nj[e0 + t];
+      if (proj)
+#pragma unroll
+        for (int q = 0; q < NB; ++q) bc[0][q] = p.Bc[(int64_t)jc[0] * NB + q];
+    }
+  }
+  __syncthreads();
+  for (int rr = t; rr < nrows; rr += RN_BLOCK)
+    for (int q = s_rp[rr]; q < s_rp[rr + 1]; ++q) s_row[q] = (uint8_t)rr;
   __syncthreads();
 
-  const int t = threadIdx.x;
-  const bool valid = t < ne;
   double z[NO];
   int64_t zi[NO];
-  int jc[M];
 #pragma unroll
   for (int o = 0; o < NO; ++o) {
     z[o] = 0.0;
     zi[o] = -1;
   }
-#pragma unroll
-  for (int c = 0; c < M; ++c) jc[c] = 0;
   int lrow = 0;
   bool froot = true;
   if (valid) {
     lrow = s_row[t];
-    const int i = r0 + lrow;
-    const int ai = p.Ap[i], na = p.Ap[i + 1] - ai, na4 = (na + 3) & ~3, la = ai - aB;
+    froot = s_root[lrow];
+    const int la = s_ap[lrow], na = s_ap[lrow + 1] - la, na4 = (na + 3) & ~3;
+    const int r = t - s_rp[lrow];
     if constexpr (M == 1) {
-      const int e = e0 + t;
-      zi[0] = e;
-      froot = p.is_root[i];
-      if (!froot) {
-        jc[0] = p.Nj[e];
-        const uint32_t *cw = (const uint32_t *)(p.codes + p.code_ptr[i] + (e - p.Np[i]) * na4);
+      zi[0] = e0 + t;
+      if (!froot && na <= 12) {
+        // fast path: every code, A value and X load of the row issued before
+        // the first multiply-add (one memory latency per lane)
+        const uint32_t *cw = (const uint32_t *)(p.codes + s_cp[lrow] + r * na4);
+        const uint32_t w0 = cw[0];
+        const uint32_t w1 = na > 4 ? cw[1] : 0xffffffffu;
+        const uint32_t w2 = na > 8 ? cw[2] : 0xffffffffu;
+        TV av[12], xv[12];
+        bool hit[12];
+#pragma unroll
+        for (int u = 0; u < 12; ++u) {
+          const uint32_t w = u < 4 ? w0 : (u < 8 ? w1 : w2);
+          const uint32_t c = (w >> (8 * (u & 3))) & 0xffu;
+          hit[u] = u < na && c != CODE_NONE;
+          av[u] = 0;
+          xv[u] = 0;
+          if (u < na) {
+            const int xo = staged ? s_x0[la + u] : p.xoff[aB + la + u];
+            av[u] = staged ? s_ax[la + u] : Ax[aB + la + u];
+            // safe index for a miss: the neighbour row's first entry
+            xv[u] = X[xo + (hit[u] ? (int)c : 0)];
+          }
+        }
+        TV acc = 0;
+#pragma unroll
+        for (int u = 0; u < 12; ++u) acc += hit[u] ? av[u] * xv[u] : TV(0);
+        z[0] = (double)acc;
+      } else if (!froot) {
+        const uint32_t *cw = (const uint32_t *)(p.codes + s_cp[lrow] + r * na4);
         TV acc = 0;
         for (int t0 = 0; t0 < na; t0 += 4) {
           const uint32_t w = cw[t0 >> 2];
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
-            const uint32_t c = (w >> (8 * u)) & 0xffu;
-            if (c != CODE_NONE) {  // padding codes are CODE_NONE
-              const int tt = t0 + u;
-              const int xo = staged ? s_x0[la + tt] : p.Np[p.Aj[ai + tt]];
-              const TV a = staged ? s_ax[la + tt] : Ax[ai + tt];
-              acc += a * X[xo + (int)c];
+            const int tt = t0 + u;
+            if (tt < na) {
+              const uint32_t c = (w >> (8 * u)) & 0xffu;
+              const bool hit = c != CODE_NONE;
+              const int xo = staged ? s_x0[la + tt] : p.xoff[aB + la + tt];
+              const TV a = staged ? s_ax[la + tt] : Ax[aB + la + tt];
+              // safe index for a miss: the neighbour row's first entry
+              const TV x = X[xo + (hit ? (int)c : 0)];
+              acc += hit ? a * x : TV(0);
             }
           }
         }
         z[0] = (double)acc;
       }
     } else {
-      const int r = e0 + t - p.nodeptr[i];
-      const int s0 = p.Np[2 * i], s1 = p.Np[2 * i + 1];
-      froot = p.is_root[2 * i];
+      const int s0 = s_np0[lrow], s1 = s_np1[lrow];
       if (froot) {
         zi[0] = s0;
         zi[M] = s1;
@@ -141,14 +194,14 @@ __global__ __launch_bounds__(RN_BLOCK) void k_spgemm(const SpgParams p) {
         zi[M + 1] = s1 + 2 * r + 1;
         jc[0] = p.Nj[s0 + 2 * r];
         jc[1] = jc[0] + 1;
-        const uint32_t *cw = (const uint32_t *)(p.codes + p.code_ptr[i] + r * na4);
+        const uint32_t *cw = (const uint32_t *)(p.codes + s_cp[lrow] + r * na4);
         TV z00 = 0, z01 = 0, z10 = 0, z11 = 0;
         for (int t0 = 0; t0 < na; t0 += 4) {
           const uint32_t w = cw[t0 >> 2];
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
             const uint32_t c = (w >> (8 * u)) & 0xffu;
-            if (c == CODE_NONE) continue;
+            if (c == CODE_NONE) continue;  // also every padding code
             const int tt = t0 + u;
             int x0, x1;
             const TV *a;
@@ -157,10 +210,9 @@ __global__ __launch_bounds__(RN_BLOCK) void k_spgemm(const SpgParams p) {
               x1 = s_x1[la + tt];
               a = s_ax + (la + tt) * NO;
             } else {
-              const int K = p.Aj[ai + tt];
-              x0 = p.Np[2 * K];
-              x1 = p.Np[2 * K + 1];
-              a = Ax + (int64_t)(ai + tt) * NO;
+              x0 = p.xoff[2 * (aB + la + tt)];
+              x1 = p.xoff[2 * (aB + la + tt) + 1];
+              a = Ax + (int64_t)(aB + la + tt) * NO;
             }
             TV x00, x01, x10, x11;
             if (c == CODE_ROOT) {
@@ -189,6 +241,11 @@ __global__ __launch_bounds__(RN_BLOCK) void k_spgemm(const SpgParams p) {
         z[1] = (double)z01;
         z[M] = (double)z10;
         z[M + 1] = (double)z11;
+        if (proj)
+#pragma unroll
+          for (int cc = 0; cc < M; ++cc)
+#pragma unroll
+            for (int q = 0; q < NB; ++q) bc[cc][q] = p.Bc[(int64_t)jc[cc] * NB + q];
       }
     }
   }
@@ -200,20 +257,14 @@ __global__ __launch_bounds__(RN_BLOCK) void k_spgemm(const SpgParams p) {
   __syncthreads();  // phase 1 LDS (A staging) is reused below
 
   // ---- projection Pi_B on F rows (root rows stay zero) ----
-  const bool proj = (MODE != MODE_PRODUCT) || p.project;
   if (proj) {
-    double bc[M][NB];
-#pragma unroll
-    for (int cc = 0; cc < M; ++cc)
-#pragma unroll
-      for (int q = 0; q < NB; ++q) bc[cc][q] = (valid && !froot) ? p.Bc[(int64_t)jc[cc] * NB + q] : 0.0;
     if (valid) {
 #pragma unroll
       for (int c = 0; c < M; ++c)
 #pragma unroll
         for (int q = 0; q < NB; ++q)
 #pragma unroll
-          for (int cc = 0; cc < M; ++cc) s_red[c][q][M * t + cc] = z[c * M + cc] * bc[cc][q];
+          for (int cc = 0; cc < M; ++cc) s_red[c][q][M * t + cc] = froot ? 0.0 : z[c * M + cc] * bc[cc][q];
     }
     __syncthreads();
     for (int w = threadIdx.x; w < nrows * M; w += RN_BLOCK) {
@@ -223,7 +274,7 @@ __global__ __launch_bounds__(RN_BLOCK) void k_spgemm(const SpgParams p) {
 #pragma unroll
       for (int q = 0; q < NB; ++q) sv[q] = 0.0;
       // the row's entries in pattern order, summed one at a time
-      const int s = M * (rp[r0 + lr] - e0), e = M * (rp[r0 + lr + 1] - e0);
+      const int s = M * s_rp[lr], e = M * s_rp[lr + 1];
       for (int u = s; u < e; ++u)
 #pragma unroll
         for (int q = 0; q < NB; ++q) sv[q] += s_red[c][q][u];
@@ -359,6 +410,8 @@ SpgParams rn_spg_params(const rn_plan *pl) {
   p.code_ptr = pl->code_ptr;
   p.nodeptr = pl->nodeptr;
   p.blk_row = pl->blk_row;
+  p.blk_hdr = pl->blk_hdr;
+  p.xoff = pl->xoff;
   p.codes = pl->codes;
   p.is_root = pl->is_root;
   p.Bc = pl->Bc;
