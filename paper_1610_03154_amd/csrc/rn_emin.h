@@ -7,8 +7,9 @@
 // Position codes: for pattern entry r of row i and the t-th stored entry
 // A(i,k), the position of column j_r in row k of the pattern (0..252), or
 // CODE_ROOT (k is a root node, block_m = 2: its two DOF rows hold one entry
-// each), or CODE_NONE.  Layout per row: entry-major, each entry's codes padded
-// to a multiple of 4 bytes so a lane reads them as 32-bit words.
+// each), or CODE_NONE.  Layout: entry-major with one stride for every entry
+// (the longest A row of a non-root row, rounded up to 4 bytes), so a lane
+// finds its codes from its entry index alone and reads them as 32-bit words.
 #define CODE_NONE 255
 #define CODE_ROOT 254
 #define CODE_MAXLEN 253
@@ -65,10 +66,11 @@ struct rn_plan {
   const int32_t *Ap = nullptr, *Aj = nullptr, *Np = nullptr, *Nj = nullptr;
   const uint8_t *is_root = nullptr;
   const double *Bc = nullptr;
-  int32_t *code_ptr = nullptr;  // byte offset of each row's codes (multiple of 4)
-  uint8_t *codes = nullptr;
+  uint8_t *codes = nullptr;     // [entries][cstride]
   int64_t ncodes = 0;
+  int32_t cstride = 4;          // code bytes per (node) entry, multiple of 4
   int32_t *nodeptr = nullptr;   // block_m = 2: node-entry row pointer
+  int32_t *ncol = nullptr;      // block_m = 2: node column of each node entry
   int32_t *blk_row = nullptr;   // product blocks: first row of block b, b = 0..nblk
   int32_t *blk_hdr = nullptr;   // per block: r0, r1, e0, e1, a0, a1 (8 ints)
   int32_t *xoff = nullptr;      // per stored A entry: first pattern entry of the
@@ -84,9 +86,9 @@ void *rn_plan_ws(rn_plan *pl, int slot, size_t bytes, rn_status *st);
 
 // Parameters of one masked-product launch (passed by value).
 struct SpgParams {
-  int32_t n, nr, nblk, k, K, hist_stride, project, scal_stride;
+  int32_t n, nr, nblk, k, K, hist_stride, project, scal_stride, cstride;
   int64_t nnzN, strideA, strideX, strideZ, Ubatch;
-  const int32_t *Ap, *Aj, *Np, *Nj, *code_ptr, *nodeptr, *blk_row, *blk_hdr, *xoff;
+  const int32_t *Ap, *Aj, *Np, *Nj, *nodeptr, *ncol, *blk_row, *blk_hdr, *xoff;
   const uint8_t *codes, *is_root;
   const double *Bc, *gp;
   const void *Ax;      // double or float, [batch][strideA]

@@ -66,42 +66,38 @@ __global__ __launch_bounds__(RN_BLOCK) void k_finish_slots(const int32_t *__rest
   if (threadIdx.x == 0) *out = (TO)s[0];
 }
 
-// ---- sizes: code bytes per row (block_m = 1: DOF rows, 2: node rows) -----
+// ---- sizes: longest pattern row and longest A row of a non-root row
+// (block_m = 1: DOF rows, 2: node rows), as per-block maxima ---------------
 __global__ __launch_bounds__(RN_BLOCK) void k_plan_count_m1(int n, const int32_t *__restrict__ Ap,
                                                            const int32_t *__restrict__ Np,
                                                            const uint8_t *__restrict__ is_root,
-                                                           int32_t *__restrict__ ccnt, int32_t *__restrict__ maxlen,
+                                                           int32_t *__restrict__ maxlen, int32_t *__restrict__ maxna,
                                                            int32_t *__restrict__ guard) {
   const int i = blockIdx.x * RN_BLOCK + threadIdx.x;
-  if (*guard) {
-    if (i < n) ccnt[i] = 0;
-    return;
-  }
-  int len = 0;
+  if (*guard) return;
+  int len = 0, na = 0;
   if (i < n) {
     len = Np[i + 1] - Np[i];
     if (len > CODE_MAXLEN) atomicOr(guard, GUARD_LIMIT);
     if (len == 0 || (is_root[i] && len != 1)) atomicOr(guard, GUARD_N);
-    ccnt[i] = is_root[i] ? 0 : len * pad4(Ap[i + 1] - Ap[i]);
+    na = is_root[i] ? 0 : Ap[i + 1] - Ap[i];
   }
-  block_to_slot<true>(len, maxlen);  // per-block maxima, finished by k_finish_slots
+  block_to_slot<true>(len, maxlen);  // finished by k_finish_slots
+  block_to_slot<true>(na, maxna);
 }
 
 __global__ __launch_bounds__(RN_BLOCK) void k_plan_count_m2(int nr, const int32_t *__restrict__ Ap,
                                                            const int32_t *__restrict__ Np,
                                                            const uint8_t *__restrict__ is_root,
-                                                           int32_t *__restrict__ ncnt, int32_t *__restrict__ ccnt,
-                                                           int32_t *__restrict__ maxlen,
+                                                           int32_t *__restrict__ ncnt, int32_t *__restrict__ maxlen,
+                                                           int32_t *__restrict__ maxna,
                                                            int32_t *__restrict__ guard) {
   const int I = blockIdx.x * RN_BLOCK + threadIdx.x;
   if (*guard) {
-    if (I < nr) {
-      ncnt[I] = 0;
-      ccnt[I] = 0;
-    }
+    if (I < nr) ncnt[I] = 0;
     return;
   }
-  int len = 0;
+  int len = 0, na = 0;
   if (I < nr) {
     const bool root = is_root[2 * I];
     const int l0 = Np[2 * I + 1] - Np[2 * I], l1 = Np[2 * I + 2] - Np[2 * I + 1];
@@ -109,17 +105,17 @@ __global__ __launch_bounds__(RN_BLOCK) void k_plan_count_m2(int nr, const int32_
     if (root) {
       if (l0 != 1 || l1 != 1) atomicOr(guard, GUARD_N);
       ncnt[I] = 1;
-      ccnt[I] = 0;
       len = 1;
     } else {
       if (l0 != l1 || (l0 & 1) || l0 == 0) atomicOr(guard, GUARD_N);
       len = l0 / 2;
       if (len > CODE_MAXLEN) atomicOr(guard, GUARD_LIMIT);
       ncnt[I] = len;
-      ccnt[I] = len * pad4(Ap[I + 1] - Ap[I]);
+      na = Ap[I + 1] - Ap[I];
     }
   }
-  block_to_slot<true>(len, maxlen);  // per-block maxima, finished by k_finish_slots
+  block_to_slot<true>(len, maxlen);  // finished by k_finish_slots
+  block_to_slot<true>(na, maxna);
 }
 
 template <int NB>
@@ -187,7 +183,8 @@ __global__ __launch_bounds__(RN_BLOCK) void k_plan_xoff(int64_t nnzA, int m, con
 }
 
 // ---- position codes: one lane per pattern entry (node entry for block_m = 2),
-// binary search of the entry's column in each neighbour row ----------------
+// binary search of the entry's column in each neighbour row; root entries
+// get CODE_NONE throughout ----------------------------------------------------
 template <int M>
 __global__ __launch_bounds__(RN_BLOCK) void k_plan_codes(int nr, const int32_t *__restrict__ hdr,
                                                         const int32_t *__restrict__ rp,
@@ -195,9 +192,8 @@ __global__ __launch_bounds__(RN_BLOCK) void k_plan_codes(int nr, const int32_t *
                                                         const int32_t *__restrict__ Aj,
                                                         const int32_t *__restrict__ Np,
                                                         const int32_t *__restrict__ Nj,
-                                                        const uint8_t *__restrict__ is_root,
-                                                        const int32_t *__restrict__ code_ptr,
-                                                        uint8_t *__restrict__ codes,
+                                                        const uint8_t *__restrict__ is_root, int cstride,
+                                                        uint8_t *__restrict__ codes, int32_t *__restrict__ ncol,
                                                         int32_t *__restrict__ terms) {
   __shared__ uint8_t s_row[RN_BLOCK];
   const int32_t *h = hdr + 8 * (int64_t)blockIdx.x;
@@ -210,16 +206,21 @@ __global__ __launch_bounds__(RN_BLOCK) void k_plan_codes(int nr, const int32_t *
   if (t < ne) {
     const int i = r0 + s_row[t];
     const int rdof = M == 1 ? i : 2 * i;
-    if (!is_root[rdof]) {
+    uint32_t *cw = (uint32_t *)(codes + (int64_t)(e0 + t) * cstride);
+    const int nw = cstride >> 2;
+    if (is_root[rdof]) {
+      for (int w = 0; w < nw; ++w) cw[w] = 0xffffffffu;
+      if (M == 2) ncol[e0 + t] = Nj[Np[2 * i]] / 2;
+    } else {
       const int r = e0 + t - rp[i];
-      const int a0 = Ap[i], na = Ap[i + 1] - a0, na4 = pad4(na);
+      const int a0 = Ap[i], na = Ap[i + 1] - a0;
       const int j = M == 1 ? Nj[Np[i] + r] : Nj[Np[2 * i] + 2 * r] / 2;
-      uint32_t *cw = (uint32_t *)(codes + code_ptr[i] + r * na4);
-      for (int t4 = 0; t4 < na4; t4 += 4) {
+      if (M == 2) ncol[e0 + t] = j;
+      for (int w = 0; w < nw; ++w) {
         uint32_t word = 0;
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-          const int tt = t4 + u;
+          const int tt = 4 * w + u;
           uint32_t code = CODE_NONE;
           if (tt < na) {
             const int k = Aj[a0 + tt];
@@ -241,7 +242,7 @@ __global__ __launch_bounds__(RN_BLOCK) void k_plan_codes(int nr, const int32_t *
           }
           word |= code << (8 * u);
         }
-        cw[t4 >> 2] = word;
+        cw[w] = word;
       }
     }
   }
@@ -292,39 +293,38 @@ extern "C" rn_status rn_plan_create(rn_ctx *ctx, const rn_matrix *A, int32_t n_c
   if (rn_validate_csr(ctx, nr, nr, A->nnz, A->rowptr, A->colind, guard, GUARD_A) != RN_OK ||
       rn_validate_csr(ctx, n, n_cols, nnz_N, Np, Nj, guard, GUARD_N) != RN_OK)
     return fail(RN_EHIP);
-  // scratch: [0] maxlen, [1] rank_def, [8..9] node-entry total (int64)
+  // scratch: [0] maxlen, [1] rank_def, [2] longest A row of a non-root row,
+  // [8..9] node-entry total (int64)
   int32_t *misc = (int32_t *)rn_scratch(ctx, SLOT_MISC, 64, &st);
   if (!misc) return fail(st);
   if (hipMemsetAsync(misc, 0, 64, ctx->stream) != hipSuccess) return fail(rn_fail(ctx, RN_EHIP, "memset"));
-  int32_t *ccnt = (int32_t *)rn_scratch(ctx, SLOT_PAT_CNT, (size_t)(nr + 1) * sizeof(int32_t), &st);
-  if (!ccnt) return fail(st);
-  if (hipMalloc(&pl->code_ptr, (size_t)(nr + 1) * sizeof(int32_t)) != hipSuccess ||
-      hipMalloc(&pl->gp, (size_t)(n + 1) * NP * sizeof(double)) != hipSuccess ||
+  if (hipMalloc(&pl->gp, (size_t)(n + 1) * NP * sizeof(double)) != hipSuccess ||
       hipMalloc(&pl->d_terms, 16) != hipSuccess ||
       hipMalloc(&pl->xoff, (size_t)(A->nnz + 1) * m * sizeof(int32_t)) != hipSuccess)
     return fail(rn_fail(ctx, RN_ENOMEM, "rn_plan_create: device allocation"));
   if (m == 2 && hipMalloc(&pl->nodeptr, (size_t)(nr + 1) * sizeof(int32_t)) != hipSuccess)
     return fail(rn_fail(ctx, RN_ENOMEM, "rn_plan_create: device allocation"));
-  pl->fixed_bytes = (size_t)(nr + 1) * 4 * (m == 2 ? 2 : 1) + (size_t)(n + 1) * NP * 8 +
+  pl->fixed_bytes = (size_t)(nr + 1) * 4 * (m == 2 ? 1 : 0) + (size_t)(n + 1) * NP * 8 +
                     (size_t)(A->nnz + 1) * m * 4;
   if (hipMemsetAsync(pl->d_terms, 0, 16, ctx->stream) != hipSuccess) return fail(rn_fail(ctx, RN_EHIP, "memset"));
   // per-block partial results of the counting kernels
   const int nbn = (int)rn_div_up(n > 0 ? n : 1, RN_BLOCK);
   int32_t *blk_max = (int32_t *)rn_scratch(ctx, SLOT_BLK0, (size_t)(nbn + 1) * sizeof(int32_t), &st);
   int32_t *blk_bad = (int32_t *)rn_scratch(ctx, SLOT_BLK1, (size_t)(nbn + 1) * sizeof(int32_t), &st);
-  if (!blk_max || !blk_bad) return fail(st);
+  int32_t *blk_na = (int32_t *)rn_scratch(ctx, SLOT_PAT_CNT, (size_t)(nbn + 1) * sizeof(int32_t), &st);
+  if (!blk_max || !blk_bad || !blk_na) return fail(st);
   if (nr > 0) {
     int nbc;
     if (m == 1) {
       nbc = (int)rn_div_up(n, RN_BLOCK);
-      hipLaunchKernelGGL(k_plan_count_m1, dim3(nbc), dim3(RN_BLOCK), 0, ctx->stream, n, A->rowptr, Np, is_root, ccnt,
-                         blk_max, guard);
+      hipLaunchKernelGGL(k_plan_count_m1, dim3(nbc), dim3(RN_BLOCK), 0, ctx->stream, n, A->rowptr, Np, is_root,
+                         blk_max, blk_na, guard);
     } else {
       int32_t *ncnt = (int32_t *)rn_scratch(ctx, SLOT_STR_CNT, (size_t)(nr + 1) * sizeof(int32_t), &st);
       if (!ncnt) return fail(st);
       nbc = (int)rn_div_up(nr, RN_BLOCK);
       hipLaunchKernelGGL(k_plan_count_m2, dim3(nbc), dim3(RN_BLOCK), 0, ctx->stream, nr, A->rowptr, Np, is_root, ncnt,
-                         ccnt, blk_max, guard);
+                         blk_max, blk_na, guard);
       if (hipGetLastError() != hipSuccess) return fail(rn_fail(ctx, RN_EHIP, "launch"));
       if (rn_scan_counts(ctx, ncnt, pl->nodeptr, nr, nullptr) != RN_OK) return fail(RN_EHIP);
       if (hipMemcpyAsync(misc + 8, ctx->slot[SLOT_SCAN_TOTAL].ptr, 8, hipMemcpyDeviceToDevice, ctx->stream) !=
@@ -333,6 +333,8 @@ extern "C" rn_status rn_plan_create(rn_ctx *ctx, const rn_matrix *A, int32_t n_c
     }
     if (hipGetLastError() != hipSuccess) return fail(rn_fail(ctx, RN_EHIP, "launch"));
     hipLaunchKernelGGL((k_finish_slots<true, int32_t>), dim3(1), dim3(RN_BLOCK), 0, ctx->stream, blk_max, nbc, misc);
+    hipLaunchKernelGGL((k_finish_slots<true, int32_t>), dim3(1), dim3(RN_BLOCK), 0, ctx->stream, blk_na, nbc,
+                       misc + 2);
     const dim3 g(nbn), bl(RN_BLOCK);
     switch (nB) {
       case 1: hipLaunchKernelGGL(k_plan_gram<1>, g, bl, 0, ctx->stream, n, Np, Nj, is_root, Bc, pl->gp, blk_bad, guard); break;
@@ -344,11 +346,9 @@ extern "C" rn_status rn_plan_create(rn_ctx *ctx, const rn_matrix *A, int32_t n_c
                        misc + 1);
     if (hipGetLastError() != hipSuccess) return fail(rn_fail(ctx, RN_EHIP, "launch"));
   }
-  if (rn_scan_counts(ctx, ccnt, pl->code_ptr, nr, nullptr) != RN_OK) return fail(RN_EHIP);
-  // one synchronisation: guard, code total, maxlen, rank_def, node-entry total
+  // one synchronisation: guard, maxlen, rank_def, longest A row, node-entry total
   int64_t *hp = ctx->pinned;
-  if (hipMemcpyAsync(hp + 1, ctx->slot[SLOT_SCAN_TOTAL].ptr, 8, hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
-      hipMemcpyAsync(hp + 2, misc, 8, hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
+  if (hipMemcpyAsync(hp + 2, misc, 16, hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
       hipMemcpyAsync(hp + 4, misc + 8, 8, hipMemcpyDeviceToHost, ctx->stream) != hipSuccess)
     return fail(rn_fail(ctx, RN_EHIP, "copy"));
   st = rn_check_guard(ctx, guard, "rn_plan_create");
@@ -357,22 +357,27 @@ extern "C" rn_status rn_plan_create(rn_ctx *ctx, const rn_matrix *A, int32_t n_c
       rn_fail(ctx, RN_ELIMIT, "rn_plan_create: a pattern row holds more than %d entries", CODE_MAXLEN);
     return fail(st);
   }
-  const int64_t ncodes = hp[1];
   pl->maxlen = ((const int32_t *)(hp + 2))[0];
   pl->rank_def = ((const int32_t *)(hp + 2))[1];
+  const int maxna = ((const int32_t *)(hp + 2))[2];
   pl->nnzN_node = m == 1 ? nnz_N : hp[4];
-  if (ncodes >= ((int64_t)1 << 31)) return fail(rn_fail(ctx, RN_ELIMIT, "rn_plan_create: plan codes reach 2^31"));
+  if (maxna > CODE_MAXLEN)
+    return fail(rn_fail(ctx, RN_ELIMIT, "rn_plan_create: an A row holds more than %d entries", CODE_MAXLEN));
+  pl->cstride = 4 * ((maxna + 3) / 4);
+  if (pl->cstride == 0) pl->cstride = 4;
+  const int64_t ncodes = pl->nnzN_node * pl->cstride;
   pl->ncodes = ncodes;
   // product blocks: every block holds at most 256 entries (node entries for
   // block_m = 2): rows starting in a chunk of 257 - maxlen entries
   const int ml = pl->maxlen < 1 ? 1 : pl->maxlen;
   pl->chunk = RN_BLOCK + 1 - ml;
   pl->nblk = (int)((pl->nnzN_node + pl->chunk - 1) / pl->chunk);
-  if (hipMalloc(&pl->codes, (size_t)ncodes + 16) != hipSuccess ||
+  if ((m == 2 && hipMalloc(&pl->ncol, (size_t)(pl->nnzN_node + 1) * sizeof(int32_t)) != hipSuccess) ||
+      hipMalloc(&pl->codes, (size_t)ncodes + 16) != hipSuccess ||
       hipMalloc(&pl->blk_row, (size_t)(pl->nblk + 1) * sizeof(int32_t)) != hipSuccess ||
       hipMalloc(&pl->blk_hdr, (size_t)(pl->nblk + 1) * 8 * sizeof(int32_t)) != hipSuccess)
     return fail(rn_fail(ctx, RN_ENOMEM, "rn_plan_create: code allocation (%lld bytes)", (long long)ncodes));
-  pl->fixed_bytes += (size_t)ncodes + (size_t)(pl->nblk + 1) * 36;
+  pl->fixed_bytes += (size_t)ncodes + (size_t)(pl->nblk + 1) * 36 + (m == 2 ? (size_t)(pl->nnzN_node + 1) * 4 : 0);
   const int32_t *rp = m == 1 ? Np : pl->nodeptr;
   hipLaunchKernelGGL(k_plan_blocks, dim3(rn_div_up(pl->nblk + 1, RN_BLOCK)), dim3(RN_BLOCK), 0, ctx->stream, nr, rp,
                      A->rowptr, pl->nblk, pl->chunk, pl->blk_row, pl->blk_hdr);
@@ -388,10 +393,10 @@ extern "C" rn_status rn_plan_create(rn_ctx *ctx, const rn_matrix *A, int32_t n_c
     if (!blk_hit) return fail(st);
     if (m == 1)
       hipLaunchKernelGGL(k_plan_codes<1>, dim3(pl->nblk), dim3(RN_BLOCK), 0, ctx->stream, nr, pl->blk_hdr, rp,
-                         A->rowptr, A->colind, Np, Nj, is_root, pl->code_ptr, pl->codes, blk_hit);
+                         A->rowptr, A->colind, Np, Nj, is_root, pl->cstride, pl->codes, pl->ncol, blk_hit);
     else
       hipLaunchKernelGGL(k_plan_codes<2>, dim3(pl->nblk), dim3(RN_BLOCK), 0, ctx->stream, nr, pl->blk_hdr, rp,
-                         A->rowptr, A->colind, Np, Nj, is_root, pl->code_ptr, pl->codes, blk_hit);
+                         A->rowptr, A->colind, Np, Nj, is_root, pl->cstride, pl->codes, pl->ncol, blk_hit);
     hipLaunchKernelGGL((k_finish_slots<false, unsigned long long>), dim3(1), dim3(RN_BLOCK), 0, ctx->stream, blk_hit,
                        pl->nblk, pl->d_terms);
     if (hipGetLastError() != hipSuccess) return fail(rn_fail(ctx, RN_EHIP, "launch"));
@@ -403,7 +408,7 @@ extern "C" rn_status rn_plan_create(rn_ctx *ctx, const rn_matrix *A, int32_t n_c
 extern "C" void rn_plan_destroy(rn_plan *pl) {
   if (!pl) return;
   if (pl->ctx) (void)hipStreamSynchronize(pl->ctx->stream);
-  void *bufs[] = {pl->code_ptr, pl->codes, pl->nodeptr, pl->gp, pl->d_terms, pl->blk_row, pl->blk_hdr, pl->xoff};
+  void *bufs[] = {pl->codes, pl->ncol, pl->nodeptr, pl->gp, pl->d_terms, pl->blk_row, pl->blk_hdr, pl->xoff};
   for (void *b : bufs)
     if (b) (void)hipFree(b);
   for (int s = 0; s < WS_COUNT; ++s)

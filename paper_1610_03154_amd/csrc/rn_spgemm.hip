@@ -4,15 +4,15 @@
 //
 // One lane per pattern entry (per 2x2 block of node entries when A is
 // node-blocked); a block owns the rows whose first entry lies in its chunk,
-// so it holds <= 256 entries and whole rows.  The plan supplies, per block,
-// a header (row, entry and A ranges) and, per stored A entry, the first
-// pattern entry of the neighbour row, so a block stages its rows' metadata
-// and its slice of A in LDS with one level of coalesced loads.  Each lane
-// then reads its one-byte position codes four at a time and gathers X;
-// terms are added one at a time in the order of A's row.  Per-row sums of
-// the projection go through LDS in pattern order.  Krylov dot products are
-// fused into the epilogue as per-block partials (no inter-block
-// synchronisation).
+// so it holds <= 256 entries and whole rows.  The per-block header (row,
+// entry and A ranges) is the only load the rest depends on: row metadata,
+// the block's slice of A with the first pattern entry of each neighbour row,
+// each lane's position codes (fixed stride per entry), its column, its own
+// Krylov value and the projection data of the row it reduces all load in one
+// round; X is gathered in the next.  Terms are added one at a time in the
+// order of A's row.  Per-row sums of the projection go through LDS in
+// pattern order.  Krylov dot products are fused into the epilogue as
+// per-block partials (no inter-block synchronisation).
 #include <cstring>
 #include <type_traits>
 
@@ -27,6 +27,17 @@ struct SpgSmem {
   static constexpr size_t BYTES = P1 > P2 ? P1 : P2;
 };
 
+// Local row of entry t: the largest rr < nrows with s_rp[rr] <= t (rows are
+// never empty, so s_rp is strictly increasing).
+__device__ inline int spg_row_of(const int *s_rp, int nrows, int t) {
+  int lo = 0, hi = nrows;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (s_rp[mid] <= t) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
 template <int M, int NB, int MODE, bool MIXED>
 __global__ __launch_bounds__(RN_BLOCK) void k_spgemm(const SpgParams p) {
   using SM = SpgSmem<M, NB, MIXED>;
@@ -35,10 +46,8 @@ __global__ __launch_bounds__(RN_BLOCK) void k_spgemm(const SpgParams p) {
   constexpr int NO = M * M;
   __shared__ int s_rp[RN_BLOCK + 1];   // row starts, relative to the block's first entry
   __shared__ int s_ap[RN_BLOCK + 1];   // row starts in A, relative to the block's first A entry
-  __shared__ int s_cp[RN_BLOCK];       // code offsets
   __shared__ int s_np0[M == 2 ? RN_BLOCK : 1], s_np1[M == 2 ? RN_BLOCK : 1];
   __shared__ uint8_t s_root[RN_BLOCK];
-  __shared__ uint8_t s_row[RN_BLOCK];
   __shared__ double s_w[8];
   __shared__ __align__(16) unsigned char s_buf[SM::BYTES];
   // phase 1 view: neighbour row starts and A values
@@ -64,60 +73,113 @@ __global__ __launch_bounds__(RN_BLOCK) void k_spgemm(const SpgParams p) {
   const bool staged = naB <= SPG_ACAP;
   const TV *Ax = (const TV *)p.Ax + (int64_t)b * p.strideA;
   const TV *X = (const TV *)p.X + (int64_t)b * p.strideX;
+  const int64_t zb = (int64_t)b * p.strideZ;
   const int32_t *rp = (M == 1) ? p.Np : p.nodeptr;
   const int t = threadIdx.x;
   const bool valid = t < ne;
-
-  // ---- stage row metadata and the block's slice of A (one load level) ----
-  for (int rr = t; rr <= nrows; rr += RN_BLOCK) {
-    s_rp[rr] = rp[r0 + rr] - e0;
-    s_ap[rr] = p.Ap[r0 + rr] - aB;
-    if (rr < nrows) {
-      s_cp[rr] = p.code_ptr[r0 + rr];
-      if constexpr (M == 1) {
-        s_root[rr] = p.is_root[r0 + rr];
-      } else {
-        s_root[rr] = p.is_root[2 * (r0 + rr)];
-        s_np0[rr] = p.Np[2 * (r0 + rr)];
-        s_np1[rr] = p.Np[2 * (r0 + rr) + 1];
-      }
-    }
-  }
-  if (staged) {
-    for (int q = t; q < naB; q += RN_BLOCK) {
-      if constexpr (M == 1) {
-        s_x0[q] = p.xoff[aB + q];
-      } else {
-        s_x0[q] = p.xoff[2 * (aB + q)];
-        s_x1[q] = p.xoff[2 * (aB + q) + 1];
-      }
-#pragma unroll
-      for (int o = 0; o < NO; ++o) s_ax[q * NO + o] = Ax[(int64_t)(aB + q) * NO + o];
-    }
-  }
-  // the lane's own column and candidates (block_m = 1) load meanwhile
   const bool proj = (MODE != MODE_PRODUCT) || p.project;
+
+  // ---- one round of loads that depend on the header only ----
+  // Straight-line code with clamped, always in-bounds indices, so every load
+  // is issued before the first wait (a block has >= 1 entry and >= 1 row).
+  // the lane's column (node column for block_m = 2), codes and own value;
+  // the code array carries 16 bytes of slack, so three words are always
+  // readable
+  const int nw = p.cstride >> 2;
+  const int te = valid ? t : 0;
+  const uint32_t *cwp = (const uint32_t *)(p.codes + (int64_t)(e0 + t) * p.cstride);
+  const uint32_t *cwq = (const uint32_t *)(p.codes + (int64_t)(e0 + te) * p.cstride);
+  const int jc0 = (M == 1) ? p.Nj[e0 + te] : p.ncol[e0 + te];
+  const uint32_t cw0 = cwq[0], cw1 = nw > 1 ? cwq[1] : 0xffffffffu, cw2 = nw > 2 ? cwq[2] : 0xffffffffu;
+  double ownv[NO];
+#pragma unroll
+  for (int o = 0; o < NO; ++o) ownv[o] = 0.0;
+  if constexpr (M == 1)
+    if (MODE == MODE_CG_STEP) ownv[0] = p.Xown[zb + e0 + te];
+  // row metadata: thread rr holds row rr (rows <= 256; row 256's start is
+  // read separately below)
+  const int rq = t < nrows ? t : nrows - 1;
+  const int v_rp = rp[r0 + t < r0 + nrows ? r0 + t : r0 + nrows];
+  const int v_ap = p.Ap[r0 + t < r0 + nrows ? r0 + t : r0 + nrows];
+  const uint8_t v_root = p.is_root[(M == 1) ? r0 + rq : 2 * (r0 + rq)];
+  int v_np0 = 0, v_np1 = 0;
+  if constexpr (M == 2) {
+    v_np0 = p.Np[2 * (r0 + rq)];
+    v_np1 = p.Np[2 * (r0 + rq) + 1];
+  }
+  // projection data of the row this thread reduces in the first pass
+  double gpre[NP];
+#pragma unroll
+  for (int q = 0; q < NP; ++q) gpre[q] = 0.0;
+  if (proj) {
+    const int tg = t < nrows * M ? t : 0;
+    const int grow = (M == 1) ? r0 + tg : 2 * (r0 + tg / M) + tg % M;
+#pragma unroll
+    for (int q = 0; q < NP; ++q) gpre[q] = p.gp[(int64_t)grow * NP + q];
+  }
+  // the block's slice of A: at most SPG_ACAP / RN_BLOCK entries per thread
+  constexpr int NIT = SPG_ACAP / RN_BLOCK;
+  int v_x0[NIT], v_x1[NIT];
+  TV v_ax[NIT][NO];
+  if (staged && naB > 0) {
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+      v_x0[it] = 0;
+      v_x1[it] = 0;
+#pragma unroll
+      for (int o = 0; o < NO; ++o) v_ax[it][o] = 0;
+      if (it * RN_BLOCK < naB) {  // uniform
+        const int q = aB + (t + it * RN_BLOCK < naB ? t + it * RN_BLOCK : naB - 1);
+        if constexpr (M == 1) {
+          v_x0[it] = p.xoff[q];
+        } else {
+          v_x0[it] = p.xoff[2 * q];
+          v_x1[it] = p.xoff[2 * q + 1];
+        }
+#pragma unroll
+        for (int o = 0; o < NO; ++o) v_ax[it][o] = Ax[(int64_t)q * NO + o];
+      }
+    }
+  }
+  // LDS stores once everything is in flight
+  if (t <= nrows) {
+    s_rp[t] = v_rp - e0;
+    s_ap[t] = v_ap - aB;
+  }
+  if (t < nrows) {
+    s_root[t] = v_root;
+    if constexpr (M == 2) {
+      s_np0[t] = v_np0;
+      s_np1[t] = v_np1;
+    }
+  }
+  if (nrows == RN_BLOCK && t == 0) {
+    s_rp[RN_BLOCK] = rp[r0 + RN_BLOCK] - e0;
+    s_ap[RN_BLOCK] = p.Ap[r0 + RN_BLOCK] - aB;
+  }
+  if (staged && naB > 0) {
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+      const int q = t + it * RN_BLOCK;
+      if (q < naB) {
+        s_x0[q] = v_x0[it];
+        if constexpr (M == 2) s_x1[q] = v_x1[it];
+#pragma unroll
+        for (int o = 0; o < NO; ++o) s_ax[q * NO + o] = v_ax[it][o];
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- the product: X gathered in the second round ----
   double bc[M][NB];
   int jc[M];
 #pragma unroll
   for (int c = 0; c < M; ++c) {
-    jc[c] = 0;
+    jc[c] = M * jc0 + c;
 #pragma unroll
     for (int q = 0; q < NB; ++q) bc[c][q] = 0.0;
   }
-  if constexpr (M == 1) {
-    if (valid) {
-      jc[0] = p.Nj[e0 + t];
-      if (proj)
-#pragma unroll
-        for (int q = 0; q < NB; ++q) bc[0][q] = p.Bc[(int64_t)jc[0] * NB + q];
-    }
-  }
-  __syncthreads();
-  for (int rr = t; rr < nrows; rr += RN_BLOCK)
-    for (int q = s_rp[rr]; q < s_rp[rr + 1]; ++q) s_row[q] = (uint8_t)rr;
-  __syncthreads();
-
   double z[NO];
   int64_t zi[NO];
 #pragma unroll
@@ -128,54 +190,49 @@ __global__ __launch_bounds__(RN_BLOCK) void k_spgemm(const SpgParams p) {
   int lrow = 0;
   bool froot = true;
   if (valid) {
-    lrow = s_row[t];
+    lrow = spg_row_of(s_rp, nrows, t);
     froot = s_root[lrow];
-    const int la = s_ap[lrow], na = s_ap[lrow + 1] - la, na4 = (na + 3) & ~3;
+    const int la = s_ap[lrow], na = s_ap[lrow + 1] - la;
     const int r = t - s_rp[lrow];
+    if (proj)  // root lanes load too (their column is in range): no branch
+#pragma unroll
+      for (int c = 0; c < M; ++c)
+#pragma unroll
+        for (int q = 0; q < NB; ++q) bc[c][q] = p.Bc[(int64_t)jc[c] * NB + q];
     if constexpr (M == 1) {
       zi[0] = e0 + t;
-      if (!froot && na <= 12) {
-        // fast path: every code, A value and X load of the row issued before
-        // the first multiply-add (one memory latency per lane)
-        const uint32_t *cw = (const uint32_t *)(p.codes + s_cp[lrow] + r * na4);
-        const uint32_t w0 = cw[0];
-        const uint32_t w1 = na > 4 ? cw[1] : 0xffffffffu;
-        const uint32_t w2 = na > 8 ? cw[2] : 0xffffffffu;
-        TV av[12], xv[12];
+      if (!froot && staged && nw <= 3) {
+        // every X load of the row issued before the first multiply-add:
+        // straight-line code, a miss (codes past the row's length are
+        // CODE_NONE) loads X[0]
+        TV xv[12], av[12];
         bool hit[12];
 #pragma unroll
         for (int u = 0; u < 12; ++u) {
-          const uint32_t w = u < 4 ? w0 : (u < 8 ? w1 : w2);
+          const uint32_t w = u < 4 ? cw0 : (u < 8 ? cw1 : cw2);
           const uint32_t c = (w >> (8 * (u & 3))) & 0xffu;
-          hit[u] = u < na && c != CODE_NONE;
-          av[u] = 0;
-          xv[u] = 0;
-          if (u < na) {
-            const int xo = staged ? s_x0[la + u] : p.xoff[aB + la + u];
-            av[u] = staged ? s_ax[la + u] : Ax[aB + la + u];
-            // safe index for a miss: the neighbour row's first entry
-            xv[u] = X[xo + (hit[u] ? (int)c : 0)];
-          }
+          hit[u] = c != CODE_NONE;
+          const int q = la + (hit[u] ? u : 0);
+          av[u] = s_ax[q];
+          xv[u] = X[hit[u] ? s_x0[q] + (int)c : 0];
         }
         TV acc = 0;
 #pragma unroll
         for (int u = 0; u < 12; ++u) acc += hit[u] ? av[u] * xv[u] : TV(0);
         z[0] = (double)acc;
       } else if (!froot) {
-        const uint32_t *cw = (const uint32_t *)(p.codes + s_cp[lrow] + r * na4);
         TV acc = 0;
         for (int t0 = 0; t0 < na; t0 += 4) {
-          const uint32_t w = cw[t0 >> 2];
+          const uint32_t w = cwp[t0 >> 2];
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
             const int tt = t0 + u;
             if (tt < na) {
               const uint32_t c = (w >> (8 * u)) & 0xffu;
               const bool hit = c != CODE_NONE;
-              const int xo = staged ? s_x0[la + tt] : p.xoff[aB + la + tt];
               const TV a = staged ? s_ax[la + tt] : Ax[aB + la + tt];
-              // safe index for a miss: the neighbour row's first entry
-              const TV x = X[xo + (hit ? (int)c : 0)];
+              TV x = 0;
+              if (hit) x = X[(staged ? s_x0[la + tt] : p.xoff[aB + la + tt]) + (int)c];
               acc += hit ? a * x : TV(0);
             }
           }
@@ -192,12 +249,15 @@ __global__ __launch_bounds__(RN_BLOCK) void k_spgemm(const SpgParams p) {
         zi[1] = s0 + 2 * r + 1;
         zi[M] = s1 + 2 * r;
         zi[M + 1] = s1 + 2 * r + 1;
-        jc[0] = p.Nj[s0 + 2 * r];
-        jc[1] = jc[0] + 1;
-        const uint32_t *cw = (const uint32_t *)(p.codes + s_cp[lrow] + r * na4);
+      }
+      if (MODE == MODE_CG_STEP)
+#pragma unroll
+        for (int o = 0; o < NO; ++o)
+          if (zi[o] >= 0) ownv[o] = p.Xown[zb + zi[o]];
+      if (!froot) {
         TV z00 = 0, z01 = 0, z10 = 0, z11 = 0;
         for (int t0 = 0; t0 < na; t0 += 4) {
-          const uint32_t w = cw[t0 >> 2];
+          const uint32_t w = nw <= 3 ? (t0 == 0 ? cw0 : (t0 == 4 ? cw1 : cw2)) : cwp[t0 >> 2];
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
             const uint32_t c = (w >> (8 * u)) & 0xffu;
@@ -241,11 +301,6 @@ __global__ __launch_bounds__(RN_BLOCK) void k_spgemm(const SpgParams p) {
         z[1] = (double)z01;
         z[M] = (double)z10;
         z[M + 1] = (double)z11;
-        if (proj)
-#pragma unroll
-          for (int cc = 0; cc < M; ++cc)
-#pragma unroll
-            for (int q = 0; q < NB; ++q) bc[cc][q] = p.Bc[(int64_t)jc[cc] * NB + q];
       }
     }
   }
@@ -278,7 +333,12 @@ __global__ __launch_bounds__(RN_BLOCK) void k_spgemm(const SpgParams p) {
       for (int u = s; u < e; ++u)
 #pragma unroll
         for (int q = 0; q < NB; ++q) sv[q] += s_red[c][q][u];
-      const double *g = p.gp + (int64_t)row * NP;
+      double g[NP];
+#pragma unroll
+      for (int q = 0; q < NP; ++q) g[q] = gpre[q];
+      if (w != t)
+#pragma unroll
+        for (int q = 0; q < NP; ++q) g[q] = p.gp[(int64_t)row * NP + q];
 #pragma unroll
       for (int q = 0; q < NB; ++q) {
         double y = 0.0;
@@ -302,7 +362,6 @@ __global__ __launch_bounds__(RN_BLOCK) void k_spgemm(const SpgParams p) {
   }
 
   // ---- epilogues: outputs and per-block partials of the fused dots ----
-  const int64_t zb = (int64_t)b * p.strideZ;
   double *part = p.part + (int64_t)b * RN_MAXDOT * p.nblk;
   if (MODE == MODE_PRODUCT) {
 #pragma unroll
@@ -325,13 +384,12 @@ __global__ __launch_bounds__(RN_BLOCK) void k_spgemm(const SpgParams p) {
     return;
   }
   if (MODE == MODE_CG_STEP) {
-    const double *own = p.Xown + zb;
     RnAcc d;
 #pragma unroll
     for (int o = 0; o < NO; ++o)
       if (zi[o] >= 0) {
         p.Z[zb + zi[o]] = z[o];
-        d.add(own[zi[o]] * z[o]);
+        d.add(ownv[o] * z[o]);
       }
     const double S = rn_block_sum2(d.hi, d.lo, s_w);
     if (threadIdx.x == 0) part[blk] = S;
@@ -407,7 +465,8 @@ SpgParams rn_spg_params(const rn_plan *pl) {
   p.Aj = pl->Aj;
   p.Np = pl->Np;
   p.Nj = pl->Nj;
-  p.code_ptr = pl->code_ptr;
+  p.cstride = pl->cstride;
+  p.ncol = pl->ncol;
   p.nodeptr = pl->nodeptr;
   p.blk_row = pl->blk_row;
   p.blk_hdr = pl->blk_hdr;
