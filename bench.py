@@ -33,7 +33,6 @@ NX, EPS, PSI, THETA, DEGREE, ITERS = 512, 1e-3, np.pi / 8, 0.1, 2, 6
 
 
 def build_inputs():
-    import oracle as O  # noqa: F401  (aggregation input is computed by the library helper below)
     import workloads as W
     import paper_1610_03154_amd as R
     import torch

@@ -106,7 +106,7 @@ class Plan:
             self.handle = None
 
     def __del__(self):
-        if sys.is_finalizing():
+        if sys is None or sys.is_finalizing():
             return
         try:
             self.close()
@@ -140,7 +140,7 @@ class Context:
             self.h = None
 
     def __del__(self):
-        if sys.is_finalizing():
+        if sys is None or sys.is_finalizing():
             return
         try:
             self.close()

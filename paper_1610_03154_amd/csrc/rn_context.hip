@@ -238,9 +238,13 @@ extern "C" rn_status rn_create(rn_ctx **out, void *stream) {
   return RN_OK;
 }
 
+void rn_plan_detach(rn_plan *pl);
+
 extern "C" void rn_destroy(rn_ctx *ctx) {
   if (!ctx) return;
   (void)hipStreamSynchronize(ctx->stream);
+  for (rn_plan *pl : ctx->plans) rn_plan_detach(pl);
+  ctx->plans.clear();
   for (int s = 0; s < SLOT_COUNT; ++s)
     if (ctx->slot[s].ptr) (void)hipFree(ctx->slot[s].ptr);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);

@@ -7,9 +7,11 @@
 // Position codes: for pattern entry r of row i and the t-th stored entry
 // A(i,k), the position of column j_r in row k of the pattern (0..252), or
 // CODE_ROOT (k is a root node, block_m = 2: its two DOF rows hold one entry
-// each), or CODE_NONE.  Layout: entry-major with one stride for every entry
-// (the longest A row of a non-root row, rounded up to 4 bytes), so a lane
-// finds its codes from its entry index alone and reads them as 32-bit words.
+// each), or CODE_NONE.  Layout: one record per (node) entry with one stride
+// for every entry (the longest A row of a non-root row plus one byte, rounded
+// up to 4 bytes): the codes, CODE_NONE padding, and in the last byte the
+// entry's row within its product block.  A lane finds its record from its
+// entry index alone and reads it as 32-bit words.
 #define CODE_NONE 255
 #define CODE_ROOT 254
 #define CODE_MAXLEN 253

@@ -8,6 +8,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <string>
+#include <vector>
 
 #include "rnamg.h"
 
@@ -65,6 +66,9 @@ struct rn_ctx {
   int32_t pat_n = -1;          // rows of the DOF pattern
   int pat_buf = 0;             // which of XP0/XP1 holds the final nodal pattern
   int32_t pat_m = 1;
+  // live plans made on this context: rn_destroy detaches them, so a plan
+  // destroyed after its context frees its memory without touching the context
+  std::vector<rn_plan *> plans;
 };
 
 // Error helpers -------------------------------------------------------------

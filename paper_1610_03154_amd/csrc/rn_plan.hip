@@ -146,9 +146,11 @@ __global__ __launch_bounds__(RN_BLOCK) void k_plan_gram(int n, const int32_t *__
 }
 
 // ---- block partition: rows whose first entry lies in [b*chunk, (b+1)*chunk)
-// belong to block b; header = r0, r1, e0, e1, a0, a1 (A entries/blocks) ----
-__global__ __launch_bounds__(RN_BLOCK) void k_plan_blocks(int nr, const int32_t *__restrict__ rp,
-                                                         const int32_t *__restrict__ Ap, int nblk, int chunk,
+// belong to block b; header = r0, r1, e0, e1, a0, a1 (A entries/blocks) and
+// the longest A row of the block's non-root rows ----
+__global__ __launch_bounds__(RN_BLOCK) void k_plan_blocks(int nr, int m, const int32_t *__restrict__ rp,
+                                                         const int32_t *__restrict__ Ap,
+                                                         const uint8_t *__restrict__ is_root, int nblk, int chunk,
                                                          int32_t *__restrict__ blk_row,
                                                          int32_t *__restrict__ hdr) {
   const int b = blockIdx.x * RN_BLOCK + threadIdx.x;
@@ -164,7 +166,10 @@ __global__ __launch_bounds__(RN_BLOCK) void k_plan_blocks(int nr, const int32_t 
   h[3] = rp[r1];
   h[4] = Ap[r0];
   h[5] = Ap[r1];
-  h[6] = 0;
+  int na = 0;
+  for (int r = r0; r < r1; ++r)
+    if (!is_root[m * r]) na = max(na, Ap[r + 1] - Ap[r]);
+  h[6] = na;
   h[7] = 0;
 }
 
@@ -183,10 +188,12 @@ __global__ __launch_bounds__(RN_BLOCK) void k_plan_xoff(int64_t nnzA, int m, con
 }
 
 // ---- position codes: one lane per pattern entry (node entry for block_m = 2),
-// binary search of the entry's column in each neighbour row; root entries
-// get CODE_NONE throughout ----------------------------------------------------
+// one block per product block.  The column of the entry is searched in every
+// neighbour row; up to 12 searches run in lockstep so their loads overlap.
+// Root entries get CODE_NONE throughout; the record's last byte is the
+// entry's row within the block. ----------------------------------------------
 template <int M>
-__global__ __launch_bounds__(RN_BLOCK) void k_plan_codes(int nr, const int32_t *__restrict__ hdr,
+__global__ __launch_bounds__(RN_BLOCK) void k_plan_codes(int nblk, const int32_t *__restrict__ hdr,
                                                         const int32_t *__restrict__ rp,
                                                         const int32_t *__restrict__ Ap,
                                                         const int32_t *__restrict__ Aj,
@@ -196,57 +203,78 @@ __global__ __launch_bounds__(RN_BLOCK) void k_plan_codes(int nr, const int32_t *
                                                         uint8_t *__restrict__ codes, int32_t *__restrict__ ncol,
                                                         int32_t *__restrict__ terms) {
   __shared__ uint8_t s_row[RN_BLOCK];
+  const int t = threadIdx.x;
   const int32_t *h = hdr + 8 * (int64_t)blockIdx.x;
-  const int r0 = h[0], nrows = h[1] - h[0], e0 = h[2], ne = h[3] - h[2];
-  for (int rr = threadIdx.x; rr < nrows; rr += RN_BLOCK)
+  const int r0 = h[0], e0 = h[2], ne = h[3] - h[2], nrows = h[1] - h[0];
+  for (int rr = t; rr < nrows; rr += RN_BLOCK)
     for (int q = rp[r0 + rr] - e0; q < rp[r0 + rr + 1] - e0; ++q) s_row[q] = (uint8_t)rr;
   __syncthreads();
-  unsigned long long hit = 0;
-  const int t = threadIdx.x;
+  int hit = 0;
   if (t < ne) {
-    const int i = r0 + s_row[t];
+    const int lr = s_row[t];
+    const int i = r0 + lr;
     const int rdof = M == 1 ? i : 2 * i;
     uint32_t *cw = (uint32_t *)(codes + (int64_t)(e0 + t) * cstride);
     const int nw = cstride >> 2;
     if (is_root[rdof]) {
-      for (int w = 0; w < nw; ++w) cw[w] = 0xffffffffu;
+      for (int w = 0; w < nw - 1; ++w) cw[w] = 0xffffffffu;
+      cw[nw - 1] = 0x00ffffffu | ((uint32_t)lr << 24);
       if (M == 2) ncol[e0 + t] = Nj[Np[2 * i]] / 2;
     } else {
       const int r = e0 + t - rp[i];
       const int a0 = Ap[i], na = Ap[i + 1] - a0;
       const int j = M == 1 ? Nj[Np[i] + r] : Nj[Np[2 * i] + 2 * r] / 2;
       if (M == 2) ncol[e0 + t] = j;
-      for (int w = 0; w < nw; ++w) {
-        uint32_t word = 0;
+      for (int w0 = 0; w0 < nw; w0 += 3) {
+        constexpr int U = 12;
+        int ks[U], lo[U], hi[U], len[U];
+        bool live[U], kroot[U];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int tt = 4 * w + u;
+        for (int u = 0; u < U; ++u) {
+          const int tt = 4 * w0 + u;
+          live[u] = tt < na;
+          const int k = live[u] ? Aj[a0 + tt] : 0;
+          ks[u] = Np[M * k];
+          lo[u] = 0;
+          len[u] = (Np[M * k + 1] - ks[u]) / M;
+          hi[u] = len[u];
+          kroot[u] = M == 2 && is_root[2 * k];
+        }
+        // lockstep binary search for j among the (node) columns of each row
+        bool more = true;
+        while (more) {
+          more = false;
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            if (live[u] && !kroot[u] && lo[u] < hi[u]) {
+              const int mid = (lo[u] + hi[u]) >> 1;
+              const int c = M == 1 ? Nj[ks[u] + mid] : Nj[ks[u] + 2 * mid] / 2;
+              if (c < j) lo[u] = mid + 1; else hi[u] = mid;
+              more = more || lo[u] < hi[u];
+            }
+          }
+        }
+        uint32_t word[3] = {0u, 0u, 0u};
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
           uint32_t code = CODE_NONE;
-          if (tt < na) {
-            const int k = Aj[a0 + tt];
-            if (M == 2 && is_root[2 * k]) {
-              code = (Nj[Np[2 * k]] / 2 == j) ? CODE_ROOT : CODE_NONE;
-            } else {
-              // search j among the (node) columns of row k
-              const int ks = Np[M * k], len = (Np[M * k + 1] - ks) / M;
-              int lo = 0, hi = len;
-              while (lo < hi) {
-                const int mid = (lo + hi) >> 1;
-                const int c = M == 1 ? Nj[ks + mid] : Nj[ks + 2 * mid] / 2;
-                if (c < j) lo = mid + 1; else hi = mid;
-              }
-              const int c = lo < len ? (M == 1 ? Nj[ks + lo] : Nj[ks + 2 * lo] / 2) : -1;
-              if (c == j) code = (uint32_t)lo;
+          if (live[u]) {
+            if (kroot[u]) {
+              code = (Nj[ks[u]] / 2 == j) ? CODE_ROOT : CODE_NONE;
+            } else if (lo[u] < len[u]) {
+              const int c = M == 1 ? Nj[ks[u] + lo[u]] : Nj[ks[u] + 2 * lo[u]] / 2;
+              if (c == j) code = (uint32_t)lo[u];
             }
             hit += code != CODE_NONE;
           }
-          word |= code << (8 * u);
+          word[u >> 2] |= code << (8 * (u & 3));
         }
-        cw[w] = word;
+        for (int w = w0; w < nw && w < w0 + 3; ++w)
+          cw[w] = w == nw - 1 ? (word[w - w0] & 0x00ffffffu) | ((uint32_t)lr << 24) : word[w - w0];
       }
     }
   }
-  block_to_slot<false>((int)hit, terms);  // per-block term counts
+  block_to_slot<false>(hit, terms);  // per-workgroup term counts
 }
 
 extern "C" rn_status rn_plan_create(rn_ctx *ctx, const rn_matrix *A, int32_t n_cols, const int32_t *Np,
@@ -363,10 +391,15 @@ extern "C" rn_status rn_plan_create(rn_ctx *ctx, const rn_matrix *A, int32_t n_c
   pl->nnzN_node = m == 1 ? nnz_N : hp[4];
   if (maxna > CODE_MAXLEN)
     return fail(rn_fail(ctx, RN_ELIMIT, "rn_plan_create: an A row holds more than %d entries", CODE_MAXLEN));
-  pl->cstride = 4 * ((maxna + 3) / 4);
-  if (pl->cstride == 0) pl->cstride = 4;
+  // record: the codes, then the row byte
+  pl->cstride = 4 * ((maxna + 1 + 3) / 4);
   const int64_t ncodes = pl->nnzN_node * pl->cstride;
   pl->ncodes = ncodes;
+  // the product forms element offsets in 32 bits
+  const int64_t lim = (int64_t)1 << 29;
+  if (ncodes >= ((int64_t)1 << 31) || nnz_N >= lim || A->nnz * m * m >= lim || (int64_t)(n + 1) * NP >= lim ||
+      (int64_t)n_cols * nB >= lim)
+    return fail(rn_fail(ctx, RN_ELIMIT, "rn_plan_create: pattern or operator too large for 32-bit offsets"));
   // product blocks: every block holds at most 256 entries (node entries for
   // block_m = 2): rows starting in a chunk of 257 - maxlen entries
   const int ml = pl->maxlen < 1 ? 1 : pl->maxlen;
@@ -379,8 +412,8 @@ extern "C" rn_status rn_plan_create(rn_ctx *ctx, const rn_matrix *A, int32_t n_c
     return fail(rn_fail(ctx, RN_ENOMEM, "rn_plan_create: code allocation (%lld bytes)", (long long)ncodes));
   pl->fixed_bytes += (size_t)ncodes + (size_t)(pl->nblk + 1) * 36 + (m == 2 ? (size_t)(pl->nnzN_node + 1) * 4 : 0);
   const int32_t *rp = m == 1 ? Np : pl->nodeptr;
-  hipLaunchKernelGGL(k_plan_blocks, dim3(rn_div_up(pl->nblk + 1, RN_BLOCK)), dim3(RN_BLOCK), 0, ctx->stream, nr, rp,
-                     A->rowptr, pl->nblk, pl->chunk, pl->blk_row, pl->blk_hdr);
+  hipLaunchKernelGGL(k_plan_blocks, dim3(rn_div_up(pl->nblk + 1, RN_BLOCK)), dim3(RN_BLOCK), 0, ctx->stream, nr, m,
+                     rp, A->rowptr, is_root, pl->nblk, pl->chunk, pl->blk_row, pl->blk_hdr);
   if (hipGetLastError() != hipSuccess) return fail(rn_fail(ctx, RN_EHIP, "launch"));
   if (A->nnz > 0) {
     unsigned g = rn_div_up(A->nnz, RN_BLOCK);
@@ -391,23 +424,43 @@ extern "C" rn_status rn_plan_create(rn_ctx *ctx, const rn_matrix *A, int32_t n_c
   if (pl->nblk > 0) {
     int32_t *blk_hit = (int32_t *)rn_scratch(ctx, SLOT_BLK2, (size_t)(pl->nblk + 1) * sizeof(int32_t), &st);
     if (!blk_hit) return fail(st);
+    const dim3 gc(pl->nblk), bc(RN_BLOCK);
+    const int nb = pl->nblk;
     if (m == 1)
-      hipLaunchKernelGGL(k_plan_codes<1>, dim3(pl->nblk), dim3(RN_BLOCK), 0, ctx->stream, nr, pl->blk_hdr, rp,
-                         A->rowptr, A->colind, Np, Nj, is_root, pl->cstride, pl->codes, pl->ncol, blk_hit);
+      hipLaunchKernelGGL((k_plan_codes<1>), gc, bc, 0, ctx->stream, nb, pl->blk_hdr, rp, A->rowptr, A->colind, Np,
+                         Nj, is_root, pl->cstride, pl->codes, pl->ncol, blk_hit);
     else
-      hipLaunchKernelGGL(k_plan_codes<2>, dim3(pl->nblk), dim3(RN_BLOCK), 0, ctx->stream, nr, pl->blk_hdr, rp,
-                         A->rowptr, A->colind, Np, Nj, is_root, pl->cstride, pl->codes, pl->ncol, blk_hit);
+      hipLaunchKernelGGL((k_plan_codes<2>), gc, bc, 0, ctx->stream, nb, pl->blk_hdr, rp, A->rowptr, A->colind, Np,
+                         Nj, is_root, pl->cstride, pl->codes, pl->ncol, blk_hit);
     hipLaunchKernelGGL((k_finish_slots<false, unsigned long long>), dim3(1), dim3(RN_BLOCK), 0, ctx->stream, blk_hit,
                        pl->nblk, pl->d_terms);
     if (hipGetLastError() != hipSuccess) return fail(rn_fail(ctx, RN_EHIP, "launch"));
+  }
+  try {
+    ctx->plans.push_back(pl);
+  } catch (...) {
+    return fail(rn_fail(ctx, RN_ENOMEM, "rn_plan_create: host allocation"));
   }
   *out = pl;
   return RN_OK;
 }
 
+void rn_plan_detach(rn_plan *pl) { pl->ctx = nullptr; }
+
 extern "C" void rn_plan_destroy(rn_plan *pl) {
   if (!pl) return;
-  if (pl->ctx) (void)hipStreamSynchronize(pl->ctx->stream);
+  if (pl->ctx) {
+    (void)hipStreamSynchronize(pl->ctx->stream);
+    auto &v = pl->ctx->plans;
+    for (size_t q = 0; q < v.size(); ++q)
+      if (v[q] == pl) {
+        v[q] = v.back();
+        v.pop_back();
+        break;
+      }
+  } else {
+    (void)hipDeviceSynchronize();  // its context is gone: wait for any work still reading the plan
+  }
   void *bufs[] = {pl->codes, pl->ncol, pl->nodeptr, pl->gp, pl->d_terms, pl->blk_row, pl->blk_hdr, pl->xoff};
   for (void *b : bufs)
     if (b) (void)hipFree(b);

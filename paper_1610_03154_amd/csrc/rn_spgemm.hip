@@ -7,9 +7,9 @@
 // so it holds <= 256 entries and whole rows.  The per-block header (row,
 // entry and A ranges) is the only load the rest depends on: row metadata,
 // the block's slice of A with the first pattern entry of each neighbour row,
-// each lane's position codes (fixed stride per entry), its column, its own
-// Krylov value and the projection data of the row it reduces all load in one
-// round; X is gathered in the next.  Terms are added one at a time in the
+// each lane's record (position codes and its row within the block, fixed
+// stride per entry), its column and its own Krylov value all load in one
+// round; X and the row's projection data are gathered in the next.  Terms are added one at a time in the
 // order of A's row.  Per-row sums of the projection go through LDS in
 // pattern order.  Krylov dot products are fused into the epilogue as
 // per-block partials (no inter-block synchronisation).
@@ -18,45 +18,50 @@
 
 #include "rn_emin.h"
 
+// Byte offsets from a uniform base are formed in 32 bits (the plan keeps
+// every array of the product below 2^29 elements), so each load is one
+// scalar-base + vector-offset instruction with no 64-bit address arithmetic.
+template <class T>
+__device__ inline T spg_ld(const T *base, uint32_t i) {
+  return *(const T *)((const char *)base + i * (uint32_t)sizeof(T));
+}
+template <class T>
+__device__ inline void spg_st(T *base, uint32_t i, T v) {
+  *(T *)((char *)base + i * (uint32_t)sizeof(T)) = v;
+}
+
 template <int M, int NB, bool MIXED>
-struct SpgSmem {
+struct SpgShape {
   using TV = typename std::conditional<MIXED, float, double>::type;
   static constexpr int NO = M * M;
-  static constexpr size_t P1 = SPG_ACAP * sizeof(int) * M + SPG_ACAP * NO * sizeof(TV);
-  static constexpr size_t P2 = (size_t)M * NB * (M * RN_BLOCK + RN_BLOCK) * sizeof(double);
-  static constexpr size_t BYTES = P1 > P2 ? P1 : P2;
+  static constexpr int ACAP = M == 1 ? SPG_ACAP : SPG_ACAP / 2;  // staged A entries
+  static constexpr int NIT = ACAP / RN_BLOCK;                    // staging loads per thread
+  static constexpr size_t P1 = (size_t)ACAP * (sizeof(int) * M + NO * sizeof(TV));
+  static constexpr size_t P2 = (size_t)M * NB * M * RN_BLOCK * sizeof(double);
+  // + 128 bytes: the register path reads up to 15 entries past a row's start
+  static constexpr size_t BYTES = (P1 > P2 ? P1 : P2) + 128;
 };
-
-// Local row of entry t: the largest rr < nrows with s_rp[rr] <= t (rows are
-// never empty, so s_rp is strictly increasing).
-__device__ inline int spg_row_of(const int *s_rp, int nrows, int t) {
-  int lo = 0, hi = nrows;
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (s_rp[mid] <= t) lo = mid; else hi = mid;
-  }
-  return lo;
-}
 
 template <int M, int NB, int MODE, bool MIXED>
 __global__ __launch_bounds__(RN_BLOCK) void k_spgemm(const SpgParams p) {
-  using SM = SpgSmem<M, NB, MIXED>;
-  using TV = typename SM::TV;
+  using SH = SpgShape<M, NB, MIXED>;
+  using TV = typename SH::TV;
   constexpr int NP = NB * (NB + 1) / 2;
   constexpr int NO = M * M;
+  constexpr int ACAP = SH::ACAP, NIT = SH::NIT;
+  constexpr int UMAX = 15;  // terms of the register path (records of <= 16 bytes)
   __shared__ int s_rp[RN_BLOCK + 1];   // row starts, relative to the block's first entry
   __shared__ int s_ap[RN_BLOCK + 1];   // row starts in A, relative to the block's first A entry
   __shared__ int s_np0[M == 2 ? RN_BLOCK : 1], s_np1[M == 2 ? RN_BLOCK : 1];
   __shared__ uint8_t s_root[RN_BLOCK];
   __shared__ double s_w[8];
-  __shared__ __align__(16) unsigned char s_buf[SM::BYTES];
+  __shared__ __align__(16) unsigned char s_buf[SH::BYTES];
   // phase 1 view: neighbour row starts and A values
   int *s_x0 = (int *)s_buf;
-  int *s_x1 = s_x0 + SPG_ACAP;  // block_m = 2 only
-  TV *s_ax = (TV *)(s_buf + SPG_ACAP * sizeof(int) * M);
-  // phase 2 view: projection sums
+  int *s_x1 = s_x0 + ACAP;  // block_m = 2 only
+  TV *s_ax = (TV *)(s_buf + (size_t)ACAP * sizeof(int) * M);
+  // phase 2 view: per-entry projection terms
   double(*s_red)[NB][M * RN_BLOCK] = (double(*)[NB][M * RN_BLOCK])s_buf;
-  double(*s_y)[NB][RN_BLOCK] = (double(*)[NB][RN_BLOCK])(s_buf + (size_t)M * NB * M * RN_BLOCK * sizeof(double));
 
   const int blk = rn_xcd_block(blockIdx.x, p.nblk);
   if (blk < 0) return;
@@ -69,56 +74,48 @@ __global__ __launch_bounds__(RN_BLOCK) void k_spgemm(const SpgParams p) {
   const int4 h0 = ((const int4 *)p.blk_hdr)[2 * blk];
   const int4 h1 = ((const int4 *)p.blk_hdr)[2 * blk + 1];
   const int r0 = h0.x, nrows = h0.y - h0.x, e0 = h0.z, ne = h0.w - h0.z;
-  const int aB = h1.x, naB = h1.y - h1.x;
-  const bool staged = naB <= SPG_ACAP;
+  const int aB = h1.x, naB = h1.y - h1.x, namax = h1.z;
+  const bool staged = naB <= ACAP;
   const TV *Ax = (const TV *)p.Ax + (int64_t)b * p.strideA;
   const TV *X = (const TV *)p.X + (int64_t)b * p.strideX;
   const int64_t zb = (int64_t)b * p.strideZ;
+  double *Z = p.Z + zb;
   const int32_t *rp = (M == 1) ? p.Np : p.nodeptr;
   const int t = threadIdx.x;
   const bool valid = t < ne;
   const bool proj = (MODE != MODE_PRODUCT) || p.project;
+  const uint32_t *codes = (const uint32_t *)p.codes;
 
   // ---- one round of loads that depend on the header only ----
   // Straight-line code with clamped, always in-bounds indices, so every load
   // is issued before the first wait (a block has >= 1 entry and >= 1 row).
-  // the lane's column (node column for block_m = 2), codes and own value;
-  // the code array carries 16 bytes of slack, so three words are always
-  // readable
+  // The lane's record: its codes, then CODE_NONE padding, and in the last
+  // byte its row within the block; the code array carries 16 bytes of slack.
   const int nw = p.cstride >> 2;
   const int te = valid ? t : 0;
-  const uint32_t *cwp = (const uint32_t *)(p.codes + (int64_t)(e0 + t) * p.cstride);
-  const uint32_t *cwq = (const uint32_t *)(p.codes + (int64_t)(e0 + te) * p.cstride);
-  const int jc0 = (M == 1) ? p.Nj[e0 + te] : p.ncol[e0 + te];
-  const uint32_t cw0 = cwq[0], cw1 = nw > 1 ? cwq[1] : 0xffffffffu, cw2 = nw > 2 ? cwq[2] : 0xffffffffu;
+  const uint32_t rec = (uint32_t)(e0 + te) * (uint32_t)nw;
+  const uint32_t w0 = spg_ld(codes, rec), w1 = spg_ld(codes, rec + 1), w2 = spg_ld(codes, rec + 2),
+                 w3 = spg_ld(codes, rec + 3);
+  const uint32_t wl = nw == 1 ? w0 : nw == 2 ? w1 : nw == 3 ? w2 : nw == 4 ? w3 : spg_ld(codes, rec + nw - 1);
+  int jc0 = 0;
+  if (proj) jc0 = (M == 1) ? spg_ld(p.Nj, (uint32_t)(e0 + te)) : spg_ld(p.ncol, (uint32_t)(e0 + te));
   double ownv[NO];
 #pragma unroll
   for (int o = 0; o < NO; ++o) ownv[o] = 0.0;
   if constexpr (M == 1)
-    if (MODE == MODE_CG_STEP) ownv[0] = p.Xown[zb + e0 + te];
-  // row metadata: thread rr holds row rr (rows <= 256; row 256's start is
-  // read separately below)
+    if (MODE == MODE_CG_STEP) ownv[0] = spg_ld(p.Xown + zb, (uint32_t)(e0 + te));
+  // row metadata: thread rr holds row rr (row 256's start is read below)
   const int rq = t < nrows ? t : nrows - 1;
-  const int v_rp = rp[r0 + t < r0 + nrows ? r0 + t : r0 + nrows];
-  const int v_ap = p.Ap[r0 + t < r0 + nrows ? r0 + t : r0 + nrows];
-  const uint8_t v_root = p.is_root[(M == 1) ? r0 + rq : 2 * (r0 + rq)];
+  const int rt = t < nrows ? t : nrows;
+  const int v_rp = spg_ld(rp, (uint32_t)(r0 + rt));
+  const int v_ap = spg_ld(p.Ap, (uint32_t)(r0 + rt));
+  const uint8_t v_root = spg_ld(p.is_root, (uint32_t)((M == 1) ? r0 + rq : 2 * (r0 + rq)));
   int v_np0 = 0, v_np1 = 0;
   if constexpr (M == 2) {
-    v_np0 = p.Np[2 * (r0 + rq)];
-    v_np1 = p.Np[2 * (r0 + rq) + 1];
+    v_np0 = spg_ld(p.Np, (uint32_t)(2 * (r0 + rq)));
+    v_np1 = spg_ld(p.Np, (uint32_t)(2 * (r0 + rq) + 1));
   }
-  // projection data of the row this thread reduces in the first pass
-  double gpre[NP];
-#pragma unroll
-  for (int q = 0; q < NP; ++q) gpre[q] = 0.0;
-  if (proj) {
-    const int tg = t < nrows * M ? t : 0;
-    const int grow = (M == 1) ? r0 + tg : 2 * (r0 + tg / M) + tg % M;
-#pragma unroll
-    for (int q = 0; q < NP; ++q) gpre[q] = p.gp[(int64_t)grow * NP + q];
-  }
-  // the block's slice of A: at most SPG_ACAP / RN_BLOCK entries per thread
-  constexpr int NIT = SPG_ACAP / RN_BLOCK;
+  // the block's slice of A
   int v_x0[NIT], v_x1[NIT];
   TV v_ax[NIT][NO];
   if (staged && naB > 0) {
@@ -129,15 +126,15 @@ __global__ __launch_bounds__(RN_BLOCK) void k_spgemm(const SpgParams p) {
 #pragma unroll
       for (int o = 0; o < NO; ++o) v_ax[it][o] = 0;
       if (it * RN_BLOCK < naB) {  // uniform
-        const int q = aB + (t + it * RN_BLOCK < naB ? t + it * RN_BLOCK : naB - 1);
+        const uint32_t q = (uint32_t)(aB + (t + it * RN_BLOCK < naB ? t + it * RN_BLOCK : naB - 1));
         if constexpr (M == 1) {
-          v_x0[it] = p.xoff[q];
+          v_x0[it] = spg_ld(p.xoff, q);
         } else {
-          v_x0[it] = p.xoff[2 * q];
-          v_x1[it] = p.xoff[2 * q + 1];
+          v_x0[it] = spg_ld(p.xoff, 2 * q);
+          v_x1[it] = spg_ld(p.xoff, 2 * q + 1);
         }
 #pragma unroll
-        for (int o = 0; o < NO; ++o) v_ax[it][o] = Ax[(int64_t)q * NO + o];
+        for (int o = 0; o < NO; ++o) v_ax[it][o] = spg_ld(Ax, q * NO + o);
       }
     }
   }
@@ -172,58 +169,65 @@ __global__ __launch_bounds__(RN_BLOCK) void k_spgemm(const SpgParams p) {
   __syncthreads();
 
   // ---- the product: X gathered in the second round ----
-  double bc[M][NB];
-  int jc[M];
+  double bc[M][NB], gq[M][NP];
 #pragma unroll
   for (int c = 0; c < M; ++c) {
-    jc[c] = M * jc0 + c;
 #pragma unroll
     for (int q = 0; q < NB; ++q) bc[c][q] = 0.0;
+#pragma unroll
+    for (int q = 0; q < NP; ++q) gq[c][q] = 0.0;
   }
   double z[NO];
-  int64_t zi[NO];
+  int zi[NO];
 #pragma unroll
   for (int o = 0; o < NO; ++o) {
     z[o] = 0.0;
     zi[o] = -1;
   }
-  int lrow = 0;
-  bool froot = true;
+  const int lrow = valid ? (int)(wl >> 24) : 0;
+  const bool froot = !valid || s_root[lrow];
   if (valid) {
-    lrow = spg_row_of(s_rp, nrows, t);
-    froot = s_root[lrow];
-    const int la = s_ap[lrow], na = s_ap[lrow + 1] - la;
+    const int la = s_ap[lrow];
     const int r = t - s_rp[lrow];
-    if (proj)  // root lanes load too (their column is in range): no branch
+    if (proj) {  // root lanes load too (their row and column are in range): no branch
 #pragma unroll
-      for (int c = 0; c < M; ++c)
+      for (int c = 0; c < M; ++c) {
+        const uint32_t grow = (M == 1) ? (uint32_t)(r0 + lrow) : (uint32_t)(2 * (r0 + lrow) + c);
 #pragma unroll
-        for (int q = 0; q < NB; ++q) bc[c][q] = p.Bc[(int64_t)jc[c] * NB + q];
+        for (int q = 0; q < NP; ++q) gq[c][q] = spg_ld(p.gp, grow * NP + q);
+#pragma unroll
+        for (int q = 0; q < NB; ++q) bc[c][q] = spg_ld(p.Bc, (uint32_t)(M * jc0 + c) * NB + q);
+      }
+    }
     if constexpr (M == 1) {
       zi[0] = e0 + t;
-      if (!froot && staged && nw <= 3) {
-        // every X load of the row issued before the first multiply-add:
-        // straight-line code, a miss (codes past the row's length are
-        // CODE_NONE) loads X[0]
-        TV xv[12], av[12];
-        bool hit[12];
+      if (!froot && staged && nw <= 4) {
+        // every X load of the row issued before the first multiply-add; the
+        // term count is the block's longest row (uniform), a miss (codes past
+        // a row's length are CODE_NONE) loads X[0]
+        TV xv[UMAX];
+        uint32_t hitm = 0;
 #pragma unroll
-        for (int u = 0; u < 12; ++u) {
-          const uint32_t w = u < 4 ? cw0 : (u < 8 ? cw1 : cw2);
-          const uint32_t c = (w >> (8 * (u & 3))) & 0xffu;
-          hit[u] = c != CODE_NONE;
-          const int q = la + (hit[u] ? u : 0);
-          av[u] = s_ax[q];
-          xv[u] = X[hit[u] ? s_x0[q] + (int)c : 0];
+        for (int u = 0; u < UMAX; ++u) {
+          xv[u] = 0;
+          if (u < namax) {  // uniform
+            const uint32_t w = u < 4 ? w0 : (u < 8 ? w1 : (u < 12 ? w2 : w3));
+            const uint32_t c = __builtin_amdgcn_ubfe(w, 8 * (u & 3), 8);
+            const bool hit = c != CODE_NONE;
+            hitm |= (uint32_t)hit << u;
+            xv[u] = spg_ld(X, hit ? (uint32_t)s_x0[la + u] + c : 0u);
+          }
         }
         TV acc = 0;
 #pragma unroll
-        for (int u = 0; u < 12; ++u) acc += hit[u] ? av[u] * xv[u] : TV(0);
+        for (int u = 0; u < UMAX; ++u)
+          if (u < namax) acc += ((hitm >> u) & 1u) ? s_ax[la + u] * xv[u] : TV(0);
         z[0] = (double)acc;
       } else if (!froot) {
+        const int na = s_ap[lrow + 1] - la;
         TV acc = 0;
         for (int t0 = 0; t0 < na; t0 += 4) {
-          const uint32_t w = cwp[t0 >> 2];
+          const uint32_t w = spg_ld(codes, rec + (t0 >> 2));
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
             const int tt = t0 + u;
@@ -253,16 +257,18 @@ __global__ __launch_bounds__(RN_BLOCK) void k_spgemm(const SpgParams p) {
       if (MODE == MODE_CG_STEP)
 #pragma unroll
         for (int o = 0; o < NO; ++o)
-          if (zi[o] >= 0) ownv[o] = p.Xown[zb + zi[o]];
+          if (zi[o] >= 0) ownv[o] = spg_ld(p.Xown + zb, (uint32_t)zi[o]);
       if (!froot) {
+        const int na = s_ap[lrow + 1] - la;
         TV z00 = 0, z01 = 0, z10 = 0, z11 = 0;
         for (int t0 = 0; t0 < na; t0 += 4) {
-          const uint32_t w = nw <= 3 ? (t0 == 0 ? cw0 : (t0 == 4 ? cw1 : cw2)) : cwp[t0 >> 2];
+          const uint32_t w = nw <= 4 ? (t0 == 0 ? w0 : (t0 == 4 ? w1 : (t0 == 8 ? w2 : w3)))
+                                     : spg_ld(codes, rec + (t0 >> 2));
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
-            const uint32_t c = (w >> (8 * u)) & 0xffu;
-            if (c == CODE_NONE) continue;  // also every padding code
             const int tt = t0 + u;
+            const uint32_t c = (w >> (8 * u)) & 0xffu;
+            if (tt >= na || c == CODE_NONE) continue;  // the record's last byte is no code
             int x0, x1;
             const TV *a;
             if (staged) {
@@ -276,15 +282,15 @@ __global__ __launch_bounds__(RN_BLOCK) void k_spgemm(const SpgParams p) {
             }
             TV x00, x01, x10, x11;
             if (c == CODE_ROOT) {
-              x00 = X[x0];
-              x11 = X[x1];
+              x00 = spg_ld(X, (uint32_t)x0);
+              x11 = spg_ld(X, (uint32_t)x1);
               x01 = 0;
               x10 = 0;
             } else {
-              x00 = X[x0 + 2 * (int)c];
-              x01 = X[x0 + 2 * (int)c + 1];
-              x10 = X[x1 + 2 * (int)c];
-              x11 = X[x1 + 2 * (int)c + 1];
+              x00 = spg_ld(X, (uint32_t)(x0 + 2 * (int)c));
+              x01 = spg_ld(X, (uint32_t)(x0 + 2 * (int)c + 1));
+              x10 = spg_ld(X, (uint32_t)(x1 + 2 * (int)c));
+              x11 = spg_ld(X, (uint32_t)(x1 + 2 * (int)c + 1));
             }
             // one term at a time, in the order of the scalar row (2K, 2K+1)
             z00 += a[0] * x00;
@@ -309,10 +315,11 @@ __global__ __launch_bounds__(RN_BLOCK) void k_spgemm(const SpgParams p) {
 #pragma unroll
     for (int o = 0; o < NO; ++o) z[o] *= xs;
   }
-  __syncthreads();  // phase 1 LDS (A staging) is reused below
 
-  // ---- projection Pi_B on F rows (root rows stay zero) ----
+  // ---- projection Pi_B on F rows (root rows stay zero): every lane sums
+  // its row's terms in pattern order and applies the row's G^+ itself ----
   if (proj) {
+    __syncthreads();  // phase 1 LDS (A staging) is reused
     if (valid) {
 #pragma unroll
       for (int c = 0; c < M; ++c)
@@ -322,42 +329,31 @@ __global__ __launch_bounds__(RN_BLOCK) void k_spgemm(const SpgParams p) {
           for (int cc = 0; cc < M; ++cc) s_red[c][q][M * t + cc] = froot ? 0.0 : z[c * M + cc] * bc[cc][q];
     }
     __syncthreads();
-    for (int w = threadIdx.x; w < nrows * M; w += RN_BLOCK) {
-      const int lr = w / M, c = w % M;
-      const int row = (M == 1) ? r0 + lr : 2 * (r0 + lr) + c;
-      double sv[NB];
+    if (!froot) {
+      const int s = M * s_rp[lrow], e = M * s_rp[lrow + 1];
 #pragma unroll
-      for (int q = 0; q < NB; ++q) sv[q] = 0.0;
-      // the row's entries in pattern order, summed one at a time
-      const int s = M * s_rp[lr], e = M * s_rp[lr + 1];
-      for (int u = s; u < e; ++u)
+      for (int c = 0; c < M; ++c) {
+        double sv[NB];
 #pragma unroll
-        for (int q = 0; q < NB; ++q) sv[q] += s_red[c][q][u];
-      double g[NP];
+        for (int q = 0; q < NB; ++q) sv[q] = 0.0;
+        for (int u = s; u < e; ++u)
 #pragma unroll
-      for (int q = 0; q < NP; ++q) g[q] = gpre[q];
-      if (w != t)
+          for (int q = 0; q < NB; ++q) sv[q] += s_red[c][q][u];
+        double y[NB];
 #pragma unroll
-        for (int q = 0; q < NP; ++q) g[q] = p.gp[(int64_t)row * NP + q];
+        for (int q = 0; q < NB; ++q) {
+          y[q] = 0.0;
 #pragma unroll
-      for (int q = 0; q < NB; ++q) {
-        double y = 0.0;
-#pragma unroll
-        for (int r = 0; r < NB; ++r) y += g[rn_pk(NB, q, r)] * sv[r];
-        s_y[c][q][lr] = y;
-      }
-    }
-    __syncthreads();
-    if (valid && !froot) {
-#pragma unroll
-      for (int c = 0; c < M; ++c)
+          for (int r2 = 0; r2 < NB; ++r2) y[q] += gq[c][rn_pk(NB, q, r2)] * sv[r2];
+        }
 #pragma unroll
         for (int cc = 0; cc < M; ++cc) {
           double u = 0.0;
 #pragma unroll
-          for (int q = 0; q < NB; ++q) u += bc[cc][q] * s_y[c][q][lrow];
+          for (int q = 0; q < NB; ++q) u += bc[cc][q] * y[q];
           z[c * M + cc] -= u;
         }
+      }
     }
   }
 
@@ -366,7 +362,7 @@ __global__ __launch_bounds__(RN_BLOCK) void k_spgemm(const SpgParams p) {
   if (MODE == MODE_PRODUCT) {
 #pragma unroll
     for (int o = 0; o < NO; ++o)
-      if (zi[o] >= 0) p.Z[zb + zi[o]] = z[o];
+      if (zi[o] >= 0) spg_st(Z, (uint32_t)zi[o], z[o]);
     return;
   }
   if (MODE == MODE_CG_INIT || MODE == MODE_GM_INIT) {
@@ -375,8 +371,8 @@ __global__ __launch_bounds__(RN_BLOCK) void k_spgemm(const SpgParams p) {
     for (int o = 0; o < NO; ++o)
       if (zi[o] >= 0) {
         const double v = -z[o];
-        p.Z[zb + zi[o]] = v;
-        if (p.Z2) p.Z2[zb + zi[o]] = v;
+        spg_st(Z, (uint32_t)zi[o], v);
+        if (p.Z2) spg_st(p.Z2 + zb, (uint32_t)zi[o], v);
         d.add(v * v);
       }
     const double S = rn_block_sum2(d.hi, d.lo, s_w);
@@ -388,7 +384,7 @@ __global__ __launch_bounds__(RN_BLOCK) void k_spgemm(const SpgParams p) {
 #pragma unroll
     for (int o = 0; o < NO; ++o)
       if (zi[o] >= 0) {
-        p.Z[zb + zi[o]] = z[o];
+        spg_st(Z, (uint32_t)zi[o], z[o]);
         d.add(ownv[o] * z[o]);
       }
     const double S = rn_block_sum2(d.hi, d.lo, s_w);
@@ -398,14 +394,14 @@ __global__ __launch_bounds__(RN_BLOCK) void k_spgemm(const SpgParams p) {
   if (MODE == MODE_GM_STEP) {
 #pragma unroll
     for (int o = 0; o < NO; ++o)
-      if (zi[o] >= 0) p.Z[zb + zi[o]] = z[o];
+      if (zi[o] >= 0) spg_st(Z, (uint32_t)zi[o], z[o]);
     const double *U = p.U + (int64_t)b * p.Ubatch;
     for (int j = 0; j <= p.k; ++j) {
       const double *Uj = U + (int64_t)j * p.nnzN;
       RnAcc d;
 #pragma unroll
       for (int o = 0; o < NO; ++o)
-        if (zi[o] >= 0) d.add(Uj[zi[o]] * z[o]);
+        if (zi[o] >= 0) d.add(spg_ld(Uj, (uint32_t)zi[o]) * z[o]);
       const double S = rn_block_sum2(d.hi, d.lo, s_w);
       if (threadIdx.x == 0) part[(int64_t)j * p.nblk + blk] = S;
     }
