@@ -99,6 +99,54 @@ def roofline(inp, aux, precision, reps):
     return dur, st.spgemm_bytes, st.spgemm_flops
 
 
+def fwd_bwd(reps):
+    """Batched differentiable form: 16 rotated anisotropic problems on 256 x 256
+    grids (eps = 10^U(-3,0), angle U(0,pi), seed 0; shared structure, theta = 0,
+    pattern S^2 C), loss <W, P> with W ~ N(0,1); one forward (6 CG steps with
+    the tape) plus one backward per repetition, structure set up beforehand."""
+    import torch
+    import workloads as W
+    import paper_1610_03154_amd as R
+    A0, vals, params, rng = W.aniso_batch(256, 16, 0)
+    ctx = R.Context()
+    A = R.DeviceCSR.from_host(A0.rowptr, A0.colind, A0.vals)
+    Sp, Sj = ctx.strength(A, 0.0)
+    agg, roots = R.aggregate_host(Sp.cpu().numpy(), Sj.cpu().numpy())
+    agg, roots = torch.as_tensor(agg, device="cuda"), torch.as_tensor(roots, device="cuda")
+    Np, Nj, is_root = ctx.pattern(Sp, Sj, agg, roots, 2, 1)
+    B = torch.ones((A0.n_rows, 1), dtype=torch.float64, device="cuda")
+    T, Bc, _ = ctx.tentative(Np, Nj, is_root, agg, roots, 1, B)
+    op = R.EnergyMinOperator(ctx, A, int(roots.numel()), Np, Nj, is_root, T, Bc, ITERS)
+    Wt = torch.as_tensor(W.loss_weights(rng, 16, Nj.numel()), device="cuda")
+    a = torch.as_tensor(vals, device="cuda")
+
+    def one(backward):
+        x = a.detach().requires_grad_(backward)
+        P = op(x)
+        if backward:
+            (g,) = torch.autograd.grad((P * Wt).sum(), x)
+            return g
+        return P
+
+    one(True)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    ev[0].record()
+    for _ in range(reps):
+        one(True)
+    ev[1].record()
+    with torch.no_grad():
+        ev[2].record()
+        for _ in range(reps):
+            one(False)
+        ev[3].record()
+    torch.cuda.synchronize()
+    t_fb = ev[0].elapsed_time(ev[1]) / 1e3 / reps
+    t_f = ev[2].elapsed_time(ev[3]) / 1e3 / reps
+    op.close()
+    return t_fb, t_f, int(Nj.numel())
+
+
 def cpu_baseline(budget_s=12.0):
     """The oracle (single-threaded C) on the same step, repeated for ~budget."""
     import oracle as O
@@ -127,6 +175,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--reps", type=int, default=200, help="launches for the kernel roofline timing")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--fb-reps", type=int, default=5, help="repetitions of the batched forward+backward")
     ap.add_argument("--roofline-only", action="store_true", help="only the masked-product timing loop")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -147,6 +196,7 @@ def main():
     wall32, ev32, P32, st32, _ = time_steps(inp, R.RN_FP32_MIXED, args.steps, args.warmup)
     dur, nbytes, flops = roofline(inp, aux, R.RN_FP64, args.reps)
     dur32, nbytes32, _ = roofline(inp, aux, R.RN_FP32_MIXED, args.reps)
+    t_fb, t_f, nnz_n5 = fwd_bwd(args.fb_reps)
     achieved = nbytes / dur / 1e9
     p64 = P64.cpu().numpy()
     mix_err = float(np.max(np.abs(P32.cpu().numpy() - p64)) / np.max(np.abs(p64)))
@@ -174,7 +224,10 @@ def main():
         "spgemm_GBps_fp32_mixed": nbytes32 / dur32 / 1e9,
         "spgemm_us_fp64": dur * 1e6,
         "spgemm_us_fp32_mixed": dur32 * 1e6,
-        "fwd_bwd_s": None,
+        "fwd_bwd_s": t_fb,
+        "fwd_bwd_workload": f"16 x q1_aniso 256x256 (eps 10^U(-3,0), angle U(0,pi), seed 0), theta 0, "
+                            f"S^2 C (nnz_N {nnz_n5} each), 6 CG steps FP64, loss <W,P>",
+        "fwd_only_s": t_f,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "k_spgemm<1,1,MODE_PRODUCT,false>", "bytes_per_launch": nbytes,

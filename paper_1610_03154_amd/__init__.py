@@ -18,12 +18,13 @@ import numpy as np
 from . import _lib as L
 from ._lib import RN_CG, RN_GMRES, RN_FP64, RN_FP32_MIXED  # noqa: F401
 
-__all__ = ["RnError", "DeviceCSR", "Context", "Plan", "aggregate_host", "setup", "RN_CG", "RN_GMRES",
-           "RN_FP64", "RN_FP32_MIXED"]
+__all__ = ["RnError", "DeviceCSR", "Context", "Plan", "Tape", "EnergyMinOperator", "aggregate_host", "setup",
+           "RN_CG", "RN_GMRES", "RN_FP64", "RN_FP32_MIXED"]
 
 
 _LIVE_PLANS: "weakref.WeakSet" = weakref.WeakSet()
 _LIVE_CTX: "weakref.WeakSet" = weakref.WeakSet()
+_LIVE_TAPES: "weakref.WeakSet" = weakref.WeakSet()
 
 
 _EXIT_HOOK = []
@@ -32,6 +33,8 @@ _EXIT_HOOK = []
 def _close_all():
     # free library objects while the HIP runtime is still alive: plans first,
     # then the contexts they were made on
+    for t in list(_LIVE_TAPES):
+        t.close()
     for p in list(_LIVE_PLANS):
         p.close()
     for c in list(_LIVE_CTX):
@@ -103,6 +106,30 @@ class Plan:
     def close(self):
         if self.handle:
             L.lib().rn_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        if sys is None or sys.is_finalizing():
+            return
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Tape:
+    """An rn_tape: the recorded CG iterates of one forward run, for the adjoint."""
+
+    def __init__(self, handle, plan: "Plan", batch: int, iters: int):
+        self.handle = handle
+        self.plan = plan
+        self.batch = batch
+        self.iters = iters
+        _LIVE_TAPES.add(self)
+
+    def close(self):
+        if self.handle:
+            L.lib().rn_tape_destroy(self.handle)
             self.handle = None
 
     def __del__(self):
@@ -226,7 +253,7 @@ class Context:
 
     # -- a7-a11 --------------------------------------------------------------
     def energy_min(self, plan: Plan, A_vals, T, method=RN_CG, iters=4, precision=RN_FP64, batch=None,
-                   want_hist=False, out=None):
+                   want_hist=False, out=None, tape: "Tape | None" = None):
         torch = self.torch
         if batch is None:
             batch = 1 if A_vals.dim() == 1 else A_vals.shape[0]
@@ -236,9 +263,24 @@ class Context:
         hist = torch.empty((batch, 3 * iters + 1), dtype=torch.float64, device="cuda") if want_hist else None
         stats = L.rn_emin_stats()
         self._check(L.lib().rn_energy_min(self.h, plan.handle, _ptr(A_vals), batch, _ptr(T), method, iters,
-                                          precision, _ptr(P), _ptr(hist), C.byref(stats), None),
+                                          precision, _ptr(P), _ptr(hist), C.byref(stats),
+                                          tape.handle if tape is not None else None),
                     "rn_energy_min")
         return P, stats, hist
+
+    # -- a12 -----------------------------------------------------------------
+    def tape(self, plan: Plan, batch: int, iters: int) -> Tape:
+        h = C.c_void_p()
+        self._check(L.lib().rn_tape_create(self.h, plan.handle, batch, iters, C.byref(h)), "rn_tape_create")
+        return Tape(h, plan, batch, iters)
+
+    def energy_min_bwd(self, plan: Plan, plan_T: Plan, perm, tape: Tape, A_vals, P_bar):
+        """dL/dA_vals for the stored entries of A, given dL/dP (P_bar)."""
+        torch = self.torch
+        A_bar = torch.empty_like(A_vals)
+        self._check(L.lib().rn_energy_min_bwd(self.h, plan.handle, plan_T.handle, _ptr(perm), tape.handle,
+                                              _ptr(A_vals), _ptr(P_bar), _ptr(A_bar)), "rn_energy_min_bwd")
+        return A_bar
 
 
 def aggregate_host(Sp, Sj):
@@ -303,3 +345,87 @@ def setup(ctx: Context, A: DeviceCSR, B, theta=0.0, degree=2, iters=4, method=RN
         res.That = That
         res.Bch = Bch
     return res
+
+
+class EnergyMinOperator:
+    """The map (stored values of A) -> P of a fixed number of FP64 CG steps,
+    differentiable through torch.autograd (reverse mode in the library).
+
+    The structure of A (scalar CSR), the pattern N, T and Bc are fixed; a
+    call takes A values of shape [nnz] or [batch, nnz] and returns P of shape
+    [nnz_N] or [batch, nnz_N]."""
+
+    def __init__(self, ctx: Context, A: DeviceCSR, n_cols: int, Np, Nj, is_root, T, Bc, iters: int):
+        if A.block_m != 1:
+            raise ValueError("EnergyMinOperator takes a scalar CSR operator")
+        self.ctx = ctx
+        self.A = A
+        self.T = T
+        self.iters = iters
+        self.plan = ctx.plan(A, n_cols, Np, Nj, is_root, Bc)
+        AT, perm = ctx.transpose(A)
+        self.AT = AT
+        self.perm = perm
+        self.plan_T = ctx.plan(AT, n_cols, Np, Nj, is_root, Bc)
+        self._free_tapes = {}  # batch -> tapes whose backward has run (reused, no allocation)
+
+    def _take_tape(self, batch):
+        free = self._free_tapes.get(batch)
+        if free:
+            return free.pop()
+        return self.ctx.tape(self.plan, batch, self.iters)
+
+    def _give_tape(self, tape):
+        self._free_tapes.setdefault(tape.batch, []).append(tape)
+
+    def __call__(self, A_vals):
+        return _EnergyMinFn.apply(A_vals, self)
+
+    def close(self):
+        for tapes in self._free_tapes.values():
+            for t in tapes:
+                t.close()
+        self._free_tapes = {}
+        self.plan.close()
+        self.plan_T.close()
+
+
+def _make_fn():
+    torch = _torch()
+
+    class EnergyMinFn(torch.autograd.Function):
+        @staticmethod
+        def forward(fctx, A_vals, op: EnergyMinOperator):
+            A_vals = A_vals.detach().contiguous()
+            batch = 1 if A_vals.dim() == 1 else A_vals.shape[0]
+            tape = op._take_tape(batch) if fctx.needs_input_grad[0] else None
+            P, stats, _ = op.ctx.energy_min(op.plan, A_vals, op.T, RN_CG, op.iters, RN_FP64, batch=batch,
+                                            tape=tape)
+            fctx.save_for_backward(A_vals)
+            fctx.op = op
+            fctx.tape = tape
+            return P
+
+        @staticmethod
+        def backward(fctx, P_bar):
+            (A_vals,) = fctx.saved_tensors
+            op = fctx.op
+            A_bar = op.ctx.energy_min_bwd(op.plan, op.plan_T, op.perm, fctx.tape, A_vals,
+                                          P_bar.contiguous().to(A_vals.dtype))
+            op._give_tape(fctx.tape)
+            fctx.tape = None
+            return A_bar, None
+
+    return EnergyMinFn
+
+
+class _LazyFn:
+    _fn = None
+
+    def apply(self, *args):
+        if _LazyFn._fn is None:
+            _LazyFn._fn = _make_fn()
+        return _LazyFn._fn.apply(*args)
+
+
+_EnergyMinFn = _LazyFn()

@@ -1,28 +1,393 @@
-// rn_adjoint.hip -- reverse mode of the CG energy minimisation.
+// rn_adjoint.hip -- reverse mode of the CG energy minimisation: the map from
+// the stored values of A to P after K CG steps (Sec. 3.6 improve, in the CG
+// form of Sec. 4.1), differentiated through the recurrences with every
+// stored a_ik an independent variable and pattern, T and Bc held fixed.
+//
+// Forward, with Q(X) = Pi(M(A X)):
+//   R_0 = D_0 = -Q(T), gamma_0 = <R_0,R_0>; step k:
+//   Z_k = Q(D_k), delta_k = <D_k,Z_k>, alpha_k = gamma_k/delta_k,
+//   P_{k+1} = P_k + alpha_k D_k, R_{k+1} = R_k - alpha_k Z_k,
+//   gamma_{k+1} = <R_{k+1},R_{k+1}>, beta_k = gamma_{k+1}/gamma_k,
+//   D_{k+1} = R_{k+1} + beta_k D_k.
+// Reverse step k (bars are adjoints, Pbar is the same at every step):
+//   betabar_k  = <Dbar, D_k>,  gammabar_{k+1} += betabar_k / gamma_k,
+//   Rbar      += Dbar + 2 gammabar_{k+1} R_{k+1},
+//   alphabar_k = <Pbar, D_k> - <Rbar, Z_k>,
+//   deltabar_k = -alphabar_k alpha_k / delta_k,
+//   gammabar_k = alphabar_k / delta_k - betabar_k gamma_{k+1} / gamma_k^2,
+//   Zbar       = deltabar_k D_k - alpha_k Rbar,
+//   Dbar       = beta_k Dbar + alpha_k Pbar + deltabar_k Z_k + Q^T(Zbar),
+//   Abar      += d<Zbar, Q(D_k)>/dA;
+// and at the start: Abar += d<Ybar, Q(T)>/dA with
+//   Ybar = -(Rbar + Dbar + 2 gammabar_0 R_0).
+// Pi is an orthogonal projector row by row, so Q^T(Y) = M(A^T Pi(Y)) (the
+// masked product on a plan of A^T, same pattern, no output projection), and
+// d<Y, Q(X)>/dA_ik = sum over the pattern of row i of Pi(Y)_ij X_kj, which
+// the product's position codes give directly.  Z_k is recomputed from the
+// recorded D_k (the tape keeps R_k and D_k of every step).
+#include <cstring>
+#include <new>
+
 #include "rn_emin.h"
 
 struct rn_tape {
-  int placeholder;
+  const rn_plan *pl = nullptr;
+  int32_t batch = 0, K = 0, scal_stride = 0;
+  int64_t nz = 0, nzb = 0;
+  double *R = nullptr, *D = nullptr;  // [K+1][batch][nz]
+  double *T = nullptr;                // [nz]
+  double *scal = nullptr;             // [batch][scal_stride], the forward CG scalars
+  int32_t *st = nullptr;              // [batch][ST_STRIDE]
+  // reverse-sweep workspace
+  double *Rb = nullptr, *Db = nullptr, *Zk = nullptr, *Yb = nullptr, *Yh = nullptr;  // [batch][nz]
+  double *gbar = nullptr;             // [batch][K+1]
+  double *part = nullptr;             // [batch][RN_MAXDOT][ew blocks]
+  double *ATv = nullptr;              // [batch][nnz(A)]
+  int64_t nnzA = 0;
+  bool recorded = false;
 };
 
-extern "C" rn_status rn_tape_create(rn_ctx *ctx, rn_plan *, int32_t, int32_t, rn_tape **tape) {
-  if (tape) *tape = nullptr;
-  return rn_fail(ctx, RN_EINVAL, "rn_tape_create: not available in this build");
+static unsigned adj_grid(int64_t n) {
+  int64_t g = (n + 8 * RN_BLOCK - 1) / (8 * RN_BLOCK);
+  if (g < 1) g = 1;
+  if (g > 512) g = 512;
+  return (unsigned)g;
 }
 
-extern "C" void rn_tape_destroy(rn_tape *tape) { delete tape; }
-
-rn_status rn_tape_record_begin(rn_ctx *ctx, rn_plan *, rn_tape *, int32_t, int32_t, rn_method, rn_precision) {
-  return rn_fail(ctx, RN_EINVAL, "tape recording not available in this build");
-}
-rn_status rn_tape_record_step(rn_ctx *ctx, rn_tape *, int, const double *, const double *, int64_t, int32_t) {
-  return rn_fail(ctx, RN_EINVAL, "tape recording not available in this build");
-}
-rn_status rn_tape_record_end(rn_ctx *ctx, rn_tape *, const double *, const int32_t *, int32_t) {
-  return rn_fail(ctx, RN_EINVAL, "tape recording not available in this build");
+extern "C" void rn_tape_destroy(rn_tape *tape) {
+  if (!tape) return;
+  (void)hipDeviceSynchronize();  // the tape may still be read by queued work
+  void *bufs[] = {tape->R, tape->D, tape->T, tape->scal, tape->st, tape->Rb, tape->Db,
+                  tape->Zk, tape->Yb, tape->Yh, tape->gbar, tape->part, tape->ATv};
+  for (void *b : bufs)
+    if (b) (void)hipFree(b);
+  delete tape;
 }
 
-extern "C" rn_status rn_energy_min_bwd(rn_ctx *ctx, rn_plan *, rn_plan *, const int32_t *, rn_tape *,
-                                       const double *, const double *, double *) {
-  return rn_fail(ctx, RN_EINVAL, "rn_energy_min_bwd: not available in this build");
+extern "C" rn_status rn_tape_create(rn_ctx *ctx, rn_plan *pl, int32_t batch, int32_t iters, rn_tape **out) {
+  if (!ctx) return RN_EINVAL;
+  ctx->err.clear();
+  if (!out) return rn_fail(ctx, RN_EINVAL, "rn_tape_create: null argument");
+  *out = nullptr;
+  if (!pl || batch < 1 || iters < 0) return rn_fail(ctx, RN_EINVAL, "rn_tape_create: bad argument");
+  if (pl->m != 1) return rn_fail(ctx, RN_EINVAL, "rn_tape_create: the adjoint takes scalar CSR operators (block_m = 1)");
+  rn_tape *t = new (std::nothrow) rn_tape();
+  if (!t) return rn_fail(ctx, RN_ENOMEM, "rn_tape_create: host allocation");
+  t->pl = pl;
+  t->batch = batch;
+  t->K = iters;
+  t->nz = pl->nnzN;
+  t->nzb = (int64_t)batch * pl->nnzN;
+  t->nnzA = pl->nnzA;
+  t->scal_stride = CgLayout(iters).total;
+  const size_t v = (size_t)(t->nzb + 1) * 8;
+  const size_t slots = (size_t)(iters + 1) * v;
+  bool ok = hipMalloc(&t->R, slots) == hipSuccess && hipMalloc(&t->D, slots) == hipSuccess &&
+            hipMalloc(&t->T, (size_t)(t->nz + 1) * 8) == hipSuccess &&
+            hipMalloc(&t->scal, (size_t)batch * t->scal_stride * 8) == hipSuccess &&
+            hipMalloc(&t->st, (size_t)batch * ST_STRIDE * 4) == hipSuccess &&
+            hipMalloc(&t->Rb, v) == hipSuccess && hipMalloc(&t->Db, v) == hipSuccess &&
+            hipMalloc(&t->Zk, v) == hipSuccess && hipMalloc(&t->Yb, v) == hipSuccess &&
+            hipMalloc(&t->Yh, v) == hipSuccess &&
+            hipMalloc(&t->gbar, (size_t)batch * (iters + 1) * 8) == hipSuccess &&
+            hipMalloc(&t->part, (size_t)batch * RN_MAXDOT * (adj_grid(t->nz) + 2) * 8) == hipSuccess &&
+            hipMalloc(&t->ATv, (size_t)batch * (pl->nnzA + 1) * 8) == hipSuccess;
+  if (!ok) {
+    rn_tape_destroy(t);
+    return rn_fail(ctx, RN_ENOMEM, "rn_tape_create: device allocation (%zu bytes of iterates)", 2 * slots);
+  }
+  *out = t;
+  return RN_OK;
+}
+
+rn_status rn_tape_record_begin(rn_ctx *ctx, rn_plan *pl, rn_tape *tape, int32_t batch, int32_t iters,
+                               rn_method method, rn_precision prec, const double *T) {
+  if (method != RN_CG || prec != RN_FP64)
+    return rn_fail(ctx, RN_EINVAL, "rn_energy_min: a tape records the FP64 CG form only");
+  if (tape->pl != pl || tape->batch != batch || tape->K != iters)
+    return rn_fail(ctx, RN_EINVAL, "rn_energy_min: tape made for another plan, batch or iteration count");
+  tape->recorded = false;
+  HIP_TRY(ctx, hipMemcpyAsync(tape->T, T, (size_t)tape->nz * 8, hipMemcpyDeviceToDevice, ctx->stream));
+  return RN_OK;
+}
+
+double *rn_tape_R(rn_tape *tape, int k) { return tape->R + (int64_t)k * tape->nzb; }
+double *rn_tape_D(rn_tape *tape, int k) { return tape->D + (int64_t)k * tape->nzb; }
+
+rn_status rn_tape_record_end(rn_ctx *ctx, rn_tape *tape, const double *scal, const int32_t *st, int32_t batch) {
+  HIP_TRY(ctx, hipMemcpyAsync(tape->scal, scal, (size_t)batch * tape->scal_stride * 8, hipMemcpyDeviceToDevice,
+                              ctx->stream));
+  HIP_TRY(ctx, hipMemcpyAsync(tape->st, st, (size_t)batch * ST_STRIDE * 4, hipMemcpyDeviceToDevice, ctx->stream));
+  tape->recorded = true;
+  return RN_OK;
+}
+
+// ---------------------------------------------------------------------------
+// reverse-sweep kernels; grid.y = batch entry, a batch entry whose forward
+// stopped before step k skips step k
+// ---------------------------------------------------------------------------
+__device__ inline bool adj_active(const int32_t *tst, int b, int k) {
+  const int32_t *st = tst + (int64_t)b * ST_STRIDE;
+  return st[ST_STATUS] == 0 && k < st[ST_ITERS];
+}
+
+// partials of <Dbar,D_k>, <Pbar,D_k>, <Rbar,Z_k>, <Dbar,Z_k>, <R_{k+1},Z_k>
+__global__ __launch_bounds__(RN_BLOCK) void k_adj_dots(int64_t nz, int k, const double *__restrict__ Db,
+                                                      const double *__restrict__ Pb, const double *__restrict__ Rb,
+                                                      const double *__restrict__ Zk, const double *__restrict__ R1,
+                                                      const double *__restrict__ Dk, double *__restrict__ part,
+                                                      const int32_t *__restrict__ tst) {
+  __shared__ double s_w[8];
+  const int b = blockIdx.y;
+  if (!adj_active(tst, b, k)) return;
+  const int64_t off = (int64_t)b * nz;
+  RnAcc a[5];
+  for (int64_t e = (int64_t)blockIdx.x * RN_BLOCK + threadIdx.x; e < nz; e += (int64_t)gridDim.x * RN_BLOCK) {
+    const double db = Db[off + e], dk = Dk[off + e], z = Zk[off + e];
+    a[0].add(db * dk);
+    a[1].add(Pb[off + e] * dk);
+    a[2].add(Rb[off + e] * z);
+    a[3].add(db * z);
+    a[4].add(R1[off + e] * z);
+  }
+  double *pb = part + (int64_t)b * RN_MAXDOT * gridDim.x;
+#pragma unroll
+  for (int j = 0; j < 5; ++j) {
+    const double S = rn_block_sum2(a[j].hi, a[j].lo, s_w);
+    if (threadIdx.x == 0) pb[(int64_t)j * gridDim.x + blockIdx.x] = S;
+  }
+}
+
+// Every block sums the partials itself (same fixed order, same scalars),
+// block 0 stores gammabar_k; then the element-wise updates of Rbar, Zbar
+// (into Yb) and the first part of Dbar.
+__global__ __launch_bounds__(RN_BLOCK) void k_adj_update(int64_t nz, int K, int k, int nb,
+                                                        const double *__restrict__ part,
+                                                        const double *__restrict__ tscal, int scal_stride,
+                                                        const int32_t *__restrict__ tst, double *__restrict__ gbar,
+                                                        double *__restrict__ Rb, double *__restrict__ Db,
+                                                        const double *__restrict__ Pb,
+                                                        const double *__restrict__ R1, const double *__restrict__ Dk,
+                                                        const double *__restrict__ Zk, double *__restrict__ Yb) {
+  __shared__ double s_w[8];
+  const int b = blockIdx.y;
+  if (!adj_active(tst, b, k)) return;
+  const double *pb = part + (int64_t)b * RN_MAXDOT * nb;
+  double d[5];
+#pragma unroll
+  for (int j = 0; j < 5; ++j) d[j] = rn_reduce_part(pb + (int64_t)j * nb, nb, s_w);
+  const double *sc = tscal + (int64_t)b * scal_stride;
+  const CgLayout L(K);
+  const double gk = sc[L.gam + k], gk1 = sc[L.gam + k + 1], dl = sc[L.del + k], al = sc[L.alp + k],
+               be = sc[L.bet + k];
+  double *gb = gbar + (int64_t)b * (K + 1);
+  const double betabar = d[0];
+  const double gb1 = gb[k + 1] + betabar / gk;  // final gammabar_{k+1}
+  const double c = 2.0 * gb1;
+  const double rz = d[2] + d[3] + c * d[4];     // <Rbar + Dbar + c R_{k+1}, Z_k>
+  const double alphabar = d[1] - rz;
+  const double deltabar = -alphabar * al / dl;
+  if (blockIdx.x == 0 && threadIdx.x == 0) gb[k] = alphabar / dl - betabar * gk1 / (gk * gk);
+  const int64_t off = (int64_t)b * nz;
+  for (int64_t e = (int64_t)blockIdx.x * RN_BLOCK + threadIdx.x; e < nz; e += (int64_t)gridDim.x * RN_BLOCK) {
+    const double db = Db[off + e], dk = Dk[off + e];
+    const double rb = Rb[off + e] + db + c * R1[off + e];
+    Rb[off + e] = rb;
+    Yb[off + e] = deltabar * dk - al * rb;
+    Db[off + e] = be * db + al * Pb[off + e] + deltabar * Zk[off + e];
+  }
+}
+
+// Ybar = -(Rbar + Dbar + 2 gammabar_0 R_0): the adjoint of R_0 = -Q(T) (every
+// batch entry, also those whose forward did no step)
+__global__ __launch_bounds__(RN_BLOCK) void k_adj_init(int64_t nz, int K, const double *__restrict__ gbar,
+                                                      const double *__restrict__ Rb, const double *__restrict__ Db,
+                                                      const double *__restrict__ R0, double *__restrict__ Yb,
+                                                      const int32_t *__restrict__ tst) {
+  const int b = blockIdx.y;
+  const int64_t off = (int64_t)b * nz;
+  if (tst[(int64_t)b * ST_STRIDE + ST_STATUS]) return;
+  const double c = 2.0 * gbar[(int64_t)b * (K + 1)];
+  for (int64_t e = (int64_t)blockIdx.x * RN_BLOCK + threadIdx.x; e < nz; e += (int64_t)gridDim.x * RN_BLOCK)
+    Yb[off + e] = -(Rb[off + e] + Db[off + e] + c * R0[off + e]);
+}
+
+// Yh = Pi(Yb): one thread per DOF row, the same arithmetic as the product's
+// projection (row sums in pattern order, then the packed G^+); root rows 0.
+template <int NB>
+__global__ __launch_bounds__(RN_BLOCK) void k_adj_project(int n, int64_t nz, int k, const int32_t *__restrict__ Np,
+                                                         const int32_t *__restrict__ Nj,
+                                                         const uint8_t *__restrict__ is_root,
+                                                         const double *__restrict__ Bc, const double *__restrict__ gp,
+                                                         const double *__restrict__ Yb, double *__restrict__ Yh,
+                                                         const int32_t *__restrict__ tst) {
+  constexpr int NP = NB * (NB + 1) / 2;
+  const int b = blockIdx.y;
+  if (k >= 0 && !adj_active(tst, b, k)) return;
+  if (k < 0 && tst[(int64_t)b * ST_STRIDE + ST_STATUS]) return;
+  const int i = blockIdx.x * RN_BLOCK + threadIdx.x;
+  if (i >= n) return;
+  const int64_t off = (int64_t)b * nz;
+  const int s = Np[i], e = Np[i + 1];
+  if (is_root[i]) {
+    for (int r = s; r < e; ++r) Yh[off + r] = 0.0;
+    return;
+  }
+  double sv[NB];
+#pragma unroll
+  for (int q = 0; q < NB; ++q) sv[q] = 0.0;
+  for (int r = s; r < e; ++r) {
+    const double y = Yb[off + r];
+#pragma unroll
+    for (int q = 0; q < NB; ++q) sv[q] += y * Bc[(int64_t)Nj[r] * NB + q];
+  }
+  double w[NB];
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    w[q] = 0.0;
+#pragma unroll
+    for (int r2 = 0; r2 < NB; ++r2) w[q] += gp[(int64_t)i * NP + rn_pk(NB, q, r2)] * sv[r2];
+  }
+  for (int r = s; r < e; ++r) {
+    double u = 0.0;
+#pragma unroll
+    for (int q = 0; q < NB; ++q) u += Bc[(int64_t)Nj[r] * NB + q] * w[q];
+    Yh[off + r] = Yb[off + r] - u;
+  }
+}
+
+// Abar_ik += sum over the pattern entries r of row i of Yh_r X[k, j_r]
+// (X = D_k, or T for the start term): one thread per F row; the position
+// codes of the plan locate j_r in row k.
+__global__ __launch_bounds__(RN_BLOCK) void k_adj_sddmm(int n, int64_t nz, int64_t nnzA, int64_t strideX, int k,
+                                                       const int32_t *__restrict__ Ap,
+                                                       const int32_t *__restrict__ Np,
+                                                       const uint8_t *__restrict__ is_root,
+                                                       const uint8_t *__restrict__ codes, int cstride,
+                                                       const int32_t *__restrict__ xoff,
+                                                       const double *__restrict__ Yh, const double *__restrict__ X,
+                                                       double *__restrict__ Abar, const int32_t *__restrict__ tst) {
+  const int b = blockIdx.y;
+  if (k >= 0 && !adj_active(tst, b, k)) return;
+  if (k < 0 && tst[(int64_t)b * ST_STRIDE + ST_STATUS]) return;
+  const int i = blockIdx.x * RN_BLOCK + threadIdx.x;
+  if (i >= n || is_root[i]) return;
+  const double *y = Yh + (int64_t)b * nz;
+  const double *x = X + (int64_t)b * strideX;
+  double *ab = Abar + (int64_t)b * nnzA;
+  const int la = Ap[i], na = Ap[i + 1] - la, s = Np[i], e = Np[i + 1];
+  for (int u = 0; u < na; ++u) {
+    const int xo = xoff[la + u];
+    double acc = 0.0;
+    for (int r = s; r < e; ++r) {
+      const uint32_t c = codes[(int64_t)r * cstride + u];
+      if (c != CODE_NONE) acc += y[r] * x[xo + (int)c];
+    }
+    ab[la + u] += acc;
+  }
+}
+
+__global__ __launch_bounds__(RN_BLOCK) void k_adj_gather(const double *__restrict__ src, const int32_t *__restrict__ perm,
+                                                        int64_t n, double *__restrict__ dst) {
+  const int b = blockIdx.y;
+  for (int64_t q = (int64_t)blockIdx.x * RN_BLOCK + threadIdx.x; q < n; q += (int64_t)gridDim.x * RN_BLOCK)
+    dst[(int64_t)b * n + q] = src[(int64_t)b * n + perm[q]];
+}
+
+static rn_status adj_project(rn_ctx *ctx, const rn_plan *pl, int k, rn_tape *t) {
+  const dim3 g(rn_div_up(pl->n > 0 ? pl->n : 1, RN_BLOCK), (unsigned)t->batch), bl(RN_BLOCK);
+  switch (pl->nB) {
+    case 1: hipLaunchKernelGGL(k_adj_project<1>, g, bl, 0, ctx->stream, pl->n, t->nz, k, pl->Np, pl->Nj, pl->is_root, pl->Bc, pl->gp, t->Yb, t->Yh, t->st); break;
+    case 2: hipLaunchKernelGGL(k_adj_project<2>, g, bl, 0, ctx->stream, pl->n, t->nz, k, pl->Np, pl->Nj, pl->is_root, pl->Bc, pl->gp, t->Yb, t->Yh, t->st); break;
+    case 3: hipLaunchKernelGGL(k_adj_project<3>, g, bl, 0, ctx->stream, pl->n, t->nz, k, pl->Np, pl->Nj, pl->is_root, pl->Bc, pl->gp, t->Yb, t->Yh, t->st); break;
+    case 4: hipLaunchKernelGGL(k_adj_project<4>, g, bl, 0, ctx->stream, pl->n, t->nz, k, pl->Np, pl->Nj, pl->is_root, pl->Bc, pl->gp, t->Yb, t->Yh, t->st); break;
+    default: return rn_fail(ctx, RN_EINVAL, "nB out of range");
+  }
+  LAUNCH_CHECK(ctx);
+  return RN_OK;
+}
+
+static rn_status adj_sddmm(rn_ctx *ctx, const rn_plan *pl, int k, rn_tape *t, const double *X, int64_t strideX,
+                           double *A_bar) {
+  const dim3 g(rn_div_up(pl->n > 0 ? pl->n : 1, RN_BLOCK), (unsigned)t->batch), bl(RN_BLOCK);
+  hipLaunchKernelGGL(k_adj_sddmm, g, bl, 0, ctx->stream, pl->n, t->nz, pl->nnzA, strideX, k, pl->Ap, pl->Np,
+                     pl->is_root, pl->codes, pl->cstride, pl->xoff, t->Yh, X, A_bar, t->st);
+  LAUNCH_CHECK(ctx);
+  return RN_OK;
+}
+
+extern "C" rn_status rn_energy_min_bwd(rn_ctx *ctx, rn_plan *pl, rn_plan *plT, const int32_t *perm, rn_tape *t,
+                                       const double *A_vals, const double *P_bar, double *A_bar) {
+  if (!ctx) return RN_EINVAL;
+  ctx->err.clear();
+  if (!pl || !plT || !t || !A_vals || !P_bar || !A_bar || (pl->nnzA > 0 && !perm))
+    return rn_fail(ctx, RN_EINVAL, "rn_energy_min_bwd: null argument");
+  if (!t->recorded || t->pl != pl)
+    return rn_fail(ctx, RN_EINVAL, "rn_energy_min_bwd: the tape holds no forward run of this plan");
+  if (pl->m != 1 || plT->m != 1 || plT->n != pl->n || plT->nnzN != pl->nnzN || plT->nnzA != pl->nnzA ||
+      plT->nB != pl->nB)
+    return rn_fail(ctx, RN_EINVAL, "rn_energy_min_bwd: plan_T does not match plan (A^T with the same pattern)");
+  const int B = t->batch, K = t->K;
+  const int64_t nz = t->nz;
+  // the forward's status and step count of every batch entry
+  const size_t stb = (size_t)B * ST_STRIDE * 4;
+  void *hbuf = nullptr;
+  if (hipHostMalloc(&hbuf, stb, hipHostMallocDefault) != hipSuccess)
+    return rn_fail(ctx, RN_ENOMEM, "rn_energy_min_bwd: pinned staging");
+  HIP_TRY(ctx, hipMemcpyAsync(hbuf, t->st, stb, hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  int kmax = 0, bad = -1;
+  for (int b = 0; b < B; ++b) {
+    const int32_t *s = (const int32_t *)hbuf + b * ST_STRIDE;
+    if (s[ST_STATUS]) bad = b;
+    kmax = s[ST_ITERS] > kmax ? s[ST_ITERS] : kmax;
+  }
+  (void)hipHostFree(hbuf);
+  if (bad >= 0) return rn_fail(ctx, RN_EINVAL, "rn_energy_min_bwd: the forward run failed (batch entry %d)", bad);
+  const size_t vb = (size_t)t->nzb * 8;
+  HIP_TRY(ctx, hipMemsetAsync(t->Rb, 0, vb, ctx->stream));
+  HIP_TRY(ctx, hipMemsetAsync(t->Db, 0, vb, ctx->stream));
+  HIP_TRY(ctx, hipMemsetAsync(t->gbar, 0, (size_t)B * (K + 1) * 8, ctx->stream));
+  HIP_TRY(ctx, hipMemsetAsync(A_bar, 0, (size_t)B * pl->nnzA * 8, ctx->stream));
+  const unsigned ge = adj_grid(nz);
+  const dim3 g2(ge, (unsigned)B), bl(RN_BLOCK);
+  if (pl->nnzA > 0) {
+    hipLaunchKernelGGL(k_adj_gather, dim3(adj_grid(pl->nnzA), (unsigned)B), bl, 0, ctx->stream, A_vals, perm,
+                       pl->nnzA, t->ATv);
+    LAUNCH_CHECK(ctx);
+  }
+  for (int k = kmax - 1; k >= 0; --k) {
+    const double *Dk = rn_tape_D(t, k), *R1 = rn_tape_R(t, k + 1);
+    // Z_k = Q(D_k), recomputed
+    SpgParams q = rn_spg_params(pl);
+    q.Ax = A_vals;
+    q.X = Dk;
+    q.Z = t->Zk;
+    q.project = 1;
+    q.st = t->st;
+    q.kact = k;
+    RN_TRY(rn_launch_spgemm(ctx, pl, MODE_PRODUCT, q, B, false));
+    hipLaunchKernelGGL(k_adj_dots, g2, bl, 0, ctx->stream, nz, k, t->Db, P_bar, t->Rb, t->Zk, R1, Dk, t->part, t->st);
+    LAUNCH_CHECK(ctx);
+    hipLaunchKernelGGL(k_adj_update, g2, bl, 0, ctx->stream, nz, K, k, (int)ge, t->part, t->scal, t->scal_stride,
+                       t->st, t->gbar, t->Rb, t->Db, P_bar, R1, Dk, t->Zk, t->Yb);
+    LAUNCH_CHECK(ctx);
+    RN_TRY(adj_project(ctx, pl, k, t));
+    // Dbar += M(A^T Pi(Zbar))
+    SpgParams r = rn_spg_params(plT);
+    r.Ax = t->ATv;
+    r.X = t->Yh;
+    r.Z = t->Db;
+    r.project = 0;
+    r.accum = 1;
+    r.st = t->st;
+    r.kact = k;
+    RN_TRY(rn_launch_spgemm(ctx, plT, MODE_PRODUCT, r, B, false));
+    RN_TRY(adj_sddmm(ctx, pl, k, t, Dk, nz, A_bar));
+  }
+  hipLaunchKernelGGL(k_adj_init, g2, bl, 0, ctx->stream, nz, K, t->gbar, t->Rb, t->Db, rn_tape_R(t, 0), t->Yb, t->st);
+  LAUNCH_CHECK(ctx);
+  RN_TRY(adj_project(ctx, pl, -1, t));
+  RN_TRY(adj_sddmm(ctx, pl, -1, t, t->T, 0, A_bar));
+  return RN_OK;
 }

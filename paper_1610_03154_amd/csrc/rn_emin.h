@@ -89,6 +89,8 @@ void *rn_plan_ws(rn_plan *pl, int slot, size_t bytes, rn_status *st);
 // Parameters of one masked-product launch (passed by value).
 struct SpgParams {
   int32_t n, nr, nblk, k, K, hist_stride, project, scal_stride, cstride;
+  int32_t accum;  // MODE_PRODUCT: Z += result instead of Z = result
+  int32_t kact;   // >= 0: batch entries whose st[ST_ITERS] <= kact do nothing
   int64_t nnzN, strideA, strideX, strideZ, Ubatch;
   const int32_t *Ap, *Aj, *Np, *Nj, *nodeptr, *ncol, *blk_row, *blk_hdr, *xoff;
   const uint8_t *codes, *is_root;
@@ -109,10 +111,11 @@ SpgParams rn_spg_params(const rn_plan *pl);
 
 // tape hooks called by rn_energy_min (CG, FP64) -- implemented with the adjoint
 rn_status rn_tape_record_begin(rn_ctx *ctx, rn_plan *pl, rn_tape *tape, int32_t batch, int32_t iters,
-                               rn_method method, rn_precision prec);
-// before CG step k: R_k, D_k of every batch entry ([batch][nnzN])
-rn_status rn_tape_record_step(rn_ctx *ctx, rn_tape *tape, int k, const double *R, const double *D, int64_t nnzN,
-                              int32_t batch);
+                               rn_method method, rn_precision prec, const double *T);
+// the tape's slot k of R (k = 0..K) and of D (k = 0..K), each [batch][nnzN]:
+// the CG kernels write R_k and D_k there as they produce them
+double *rn_tape_R(rn_tape *tape, int k);
+double *rn_tape_D(rn_tape *tape, int k);
 // after the last step: the per-batch scalars and status
 rn_status rn_tape_record_end(rn_ctx *ctx, rn_tape *tape, const double *scal, const int32_t *st, int32_t batch);
 

@@ -46,7 +46,8 @@ __global__ __launch_bounds__(RN_BLOCK) void k_cg_update(int64_t nnz, int64_t str
                                                        const double *__restrict__ part_spg,
                                                        double *__restrict__ part_ew, double *__restrict__ scal,
                                                        int scal_stride, int32_t *__restrict__ stv,
-                                                       double *__restrict__ histv, int hist_stride) {
+                                                       double *__restrict__ histv, int hist_stride,
+                                                       double *__restrict__ Rrec) {
   __shared__ double s_w[8];
   const int b = blockIdx.y;
   int32_t *st = stv + (int64_t)b * ST_STRIDE;
@@ -79,6 +80,7 @@ __global__ __launch_bounds__(RN_BLOCK) void k_cg_update(int64_t nnz, int64_t str
     P[off + e] += al * D[off + e];
     const double r = R[off + e] - al * Z[off + e];
     R[off + e] = r;
+    if (Rrec) Rrec[off + e] = r;
     s.add(r * r);
   }
   const double S = rn_block_sum2(s.hi, s.lo, s_w);
@@ -91,7 +93,7 @@ __global__ __launch_bounds__(RN_BLOCK) void k_cg_dir(int64_t nnz, int64_t stride
                                                     float *__restrict__ D32, const double *__restrict__ part_ew,
                                                     double *__restrict__ scal, int scal_stride,
                                                     int32_t *__restrict__ stv, double *__restrict__ histv,
-                                                    int hist_stride) {
+                                                    int hist_stride, double *__restrict__ Drec) {
   __shared__ double s_w[8];
   const int b = blockIdx.y;
   int32_t *st = stv + (int64_t)b * ST_STRIDE;
@@ -113,6 +115,7 @@ __global__ __launch_bounds__(RN_BLOCK) void k_cg_dir(int64_t nnz, int64_t stride
   for (int64_t e = (int64_t)blockIdx.x * RN_BLOCK + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * RN_BLOCK) {
     const double d = R[off + e] + be * D[off + e];
     D[off + e] = d;
+    if (Drec) Drec[off + e] = d;
     if (MIXED) D32[off + e] = (float)d;
   }
 }
@@ -359,7 +362,7 @@ extern "C" rn_status rn_energy_min(rn_ctx *ctx, rn_plan *pl, const double *A_val
   if (prec != RN_FP64 && prec != RN_FP32_MIXED) return rn_fail(ctx, RN_EINVAL, "rn_energy_min: bad precision");
   if (method == RN_GMRES && iters > RN_MAXDOT - 1)
     return rn_fail(ctx, RN_ELIMIT, "rn_energy_min: GMRES supports at most %d iterations", RN_MAXDOT - 1);
-  if (tape) RN_TRY(rn_tape_record_begin(ctx, pl, tape, batch, iters, method, prec));
+  if (tape) RN_TRY(rn_tape_record_begin(ctx, pl, tape, batch, iters, method, prec, T));
   const bool mixed = prec == RN_FP32_MIXED;
   const bool gm = method == RN_GMRES;
   const int K = iters;
@@ -414,8 +417,11 @@ extern "C" rn_status rn_energy_min(rn_ctx *ctx, rn_plan *pl, const double *A_val
       hipLaunchKernelGGL(k_to_f32, dim3(ew_grid(nzb)), blk, 0, ctx->stream, D, nzb, D32);
       LAUNCH_CHECK(ctx);
     }
+    if (tape) {  // R_0 = D_0 into slot 0; later iterates are written by the kernels
+      HIP_TRY(ctx, hipMemcpyAsync(rn_tape_R(tape, 0), R, (size_t)nzb * 8, hipMemcpyDeviceToDevice, ctx->stream));
+      HIP_TRY(ctx, hipMemcpyAsync(rn_tape_D(tape, 0), D, (size_t)nzb * 8, hipMemcpyDeviceToDevice, ctx->stream));
+    }
     for (int k = 0; k < K; ++k) {
-      if (tape) RN_TRY(rn_tape_record_step(ctx, tape, k, R, D, nz, batch));
       SpgParams s = p;
       s.k = k;
       s.Ax = Aop;
@@ -424,14 +430,15 @@ extern "C" rn_status rn_energy_min(rn_ctx *ctx, rn_plan *pl, const double *A_val
       s.Z = Z;
       RN_TRY(rn_launch_spgemm(ctx, pl, MODE_CG_STEP, s, batch, mixed));
       hipLaunchKernelGGL(k_cg_update, g2, blk, 0, ctx->stream, nz, nz, K, k, pl->nblk, P, R, D, Z, part_spg, part_ew,
-                         p.scal, scal_stride, p.st, hist, hist_stride);
+                         p.scal, scal_stride, p.st, hist, hist_stride, tape ? rn_tape_R(tape, k + 1) : nullptr);
       LAUNCH_CHECK(ctx);
       if (mixed)
         hipLaunchKernelGGL(k_cg_dir<true>, g2, blk, 0, ctx->stream, nz, nz, K, k, (int)gew, R, D, D32, part_ew, p.scal,
-                           scal_stride, p.st, hist, hist_stride);
+                           scal_stride, p.st, hist, hist_stride, (double *)nullptr);
       else
         hipLaunchKernelGGL(k_cg_dir<false>, g2, blk, 0, ctx->stream, nz, nz, K, k, (int)gew, R, D, (float *)nullptr,
-                           part_ew, p.scal, scal_stride, p.st, hist, hist_stride);
+                           part_ew, p.scal, scal_stride, p.st, hist, hist_stride,
+                           tape ? rn_tape_D(tape, k + 1) : nullptr);
       LAUNCH_CHECK(ctx);
     }
     if (tape) RN_TRY(rn_tape_record_end(ctx, tape, p.scal, p.st, batch));

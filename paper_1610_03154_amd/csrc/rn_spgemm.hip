@@ -70,6 +70,7 @@ __global__ __launch_bounds__(RN_BLOCK) void k_spgemm(const SpgParams p) {
   const double *sc = p.scal + (int64_t)b * p.scal_stride;
   if (MODE == MODE_CG_STEP || MODE == MODE_GM_STEP)
     if (st[ST_STATUS] || st[ST_DONE]) return;
+  if (p.kact >= 0 && st[ST_ITERS] <= p.kact) return;
 
   const int4 h0 = ((const int4 *)p.blk_hdr)[2 * blk];
   const int4 h1 = ((const int4 *)p.blk_hdr)[2 * blk + 1];
@@ -362,7 +363,7 @@ __global__ __launch_bounds__(RN_BLOCK) void k_spgemm(const SpgParams p) {
   if (MODE == MODE_PRODUCT) {
 #pragma unroll
     for (int o = 0; o < NO; ++o)
-      if (zi[o] >= 0) spg_st(Z, (uint32_t)zi[o], z[o]);
+      if (zi[o] >= 0) spg_st(Z, (uint32_t)zi[o], p.accum ? spg_ld((const double *)Z, (uint32_t)zi[o]) + z[o] : z[o]);
     return;
   }
   if (MODE == MODE_CG_INIT || MODE == MODE_GM_INIT) {
@@ -462,6 +463,7 @@ SpgParams rn_spg_params(const rn_plan *pl) {
   p.Np = pl->Np;
   p.Nj = pl->Nj;
   p.cstride = pl->cstride;
+  p.kact = -1;
   p.ncol = pl->ncol;
   p.nodeptr = pl->nodeptr;
   p.blk_row = pl->blk_row;
