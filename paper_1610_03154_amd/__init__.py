@@ -243,10 +243,10 @@ class Context:
         return Plan(self, h, (A.rowptr, A.colind, Np, Nj, is_root, Bc))
 
     # -- a7/a8 ---------------------------------------------------------------
-    def masked_product(self, plan: Plan, A_vals, X, project=True, precision=RN_FP64):
+    def masked_product(self, plan: Plan, A_vals, X, project=True, precision=RN_FP64, out=None):
         torch = self.torch
         batch = 1 if X.dim() == 1 else X.shape[0]
-        Z = torch.empty_like(X)
+        Z = out if out is not None else torch.empty_like(X)
         self._check(L.lib().rn_masked_product(self.h, plan.handle, _ptr(A_vals), batch, _ptr(X), int(project),
                                               precision, _ptr(Z)), "rn_masked_product")
         return Z

@@ -257,9 +257,13 @@ __global__ __launch_bounds__(RN_BLOCK) void k_adj_project(int n, int64_t nz, int
 }
 
 // Abar_ik += sum over the pattern entries r of row i of Yh_r X[k, j_r]
-// (X = D_k, or T for the start term): one thread per F row; the position
-// codes of the plan locate j_r in row k.
-__global__ __launch_bounds__(RN_BLOCK) void k_adj_sddmm(int n, int64_t nz, int64_t nnzA, int64_t strideX, int k,
+// (X = D_k, or T for the start term).  Organised by the product's blocks:
+// block b owns the stored A entries of its rows, one thread per entry; the
+// entry's row comes from the block's A row starts in LDS, and the position
+// codes of the row's pattern entries locate j_r in row k.  Root rows get no
+// contribution (Q is zero there).
+__global__ __launch_bounds__(RN_BLOCK) void k_adj_sddmm(int nblk, int64_t nz, int64_t nnzA, int64_t strideX, int k,
+                                                       const int32_t *__restrict__ hdr,
                                                        const int32_t *__restrict__ Ap,
                                                        const int32_t *__restrict__ Np,
                                                        const uint8_t *__restrict__ is_root,
@@ -267,23 +271,36 @@ __global__ __launch_bounds__(RN_BLOCK) void k_adj_sddmm(int n, int64_t nz, int64
                                                        const int32_t *__restrict__ xoff,
                                                        const double *__restrict__ Yh, const double *__restrict__ X,
                                                        double *__restrict__ Abar, const int32_t *__restrict__ tst) {
+  __shared__ int s_ap[RN_BLOCK + 1];
   const int b = blockIdx.y;
   if (k >= 0 && !adj_active(tst, b, k)) return;
   if (k < 0 && tst[(int64_t)b * ST_STRIDE + ST_STATUS]) return;
-  const int i = blockIdx.x * RN_BLOCK + threadIdx.x;
-  if (i >= n || is_root[i]) return;
+  const int blk = rn_xcd_block(blockIdx.x, nblk);
+  if (blk < 0) return;
+  const int4 h0 = ((const int4 *)hdr)[2 * blk];
+  const int4 h1 = ((const int4 *)hdr)[2 * blk + 1];
+  const int r0 = h0.x, nrows = h0.y - h0.x, a0 = h1.x, na = h1.y - h1.x;
+  for (int rr = threadIdx.x; rr <= nrows; rr += RN_BLOCK) s_ap[rr] = Ap[r0 + rr] - a0;
+  __syncthreads();
   const double *y = Yh + (int64_t)b * nz;
   const double *x = X + (int64_t)b * strideX;
   double *ab = Abar + (int64_t)b * nnzA;
-  const int la = Ap[i], na = Ap[i + 1] - la, s = Np[i], e = Np[i + 1];
-  for (int u = 0; u < na; ++u) {
-    const int xo = xoff[la + u];
+  for (int q = threadIdx.x; q < na; q += RN_BLOCK) {
+    int lo = 0, hi = nrows;  // row: the largest rr with s_ap[rr] <= q
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (s_ap[mid] <= q) lo = mid; else hi = mid;
+    }
+    const int i = r0 + lo;
+    if (is_root[i]) continue;
+    const int u = q - s_ap[lo];
+    const int xo = xoff[a0 + q];
     double acc = 0.0;
-    for (int r = s; r < e; ++r) {
+    for (int r = Np[i]; r < Np[i + 1]; ++r) {
       const uint32_t c = codes[(int64_t)r * cstride + u];
       if (c != CODE_NONE) acc += y[r] * x[xo + (int)c];
     }
-    ab[la + u] += acc;
+    ab[a0 + q] += acc;
   }
 }
 
@@ -309,9 +326,10 @@ static rn_status adj_project(rn_ctx *ctx, const rn_plan *pl, int k, rn_tape *t) 
 
 static rn_status adj_sddmm(rn_ctx *ctx, const rn_plan *pl, int k, rn_tape *t, const double *X, int64_t strideX,
                            double *A_bar) {
-  const dim3 g(rn_div_up(pl->n > 0 ? pl->n : 1, RN_BLOCK), (unsigned)t->batch), bl(RN_BLOCK);
-  hipLaunchKernelGGL(k_adj_sddmm, g, bl, 0, ctx->stream, pl->n, t->nz, pl->nnzA, strideX, k, pl->Ap, pl->Np,
-                     pl->is_root, pl->codes, pl->cstride, pl->xoff, t->Yh, X, A_bar, t->st);
+  if (pl->nblk == 0) return RN_OK;
+  const dim3 g(rn_xcd_grid((unsigned)pl->nblk), (unsigned)t->batch), bl(RN_BLOCK);
+  hipLaunchKernelGGL(k_adj_sddmm, g, bl, 0, ctx->stream, pl->nblk, t->nz, pl->nnzA, strideX, k, pl->blk_hdr, pl->Ap,
+                     pl->Np, pl->is_root, pl->codes, pl->cstride, pl->xoff, t->Yh, X, A_bar, t->st);
   LAUNCH_CHECK(ctx);
   return RN_OK;
 }
