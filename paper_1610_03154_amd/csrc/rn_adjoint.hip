@@ -350,7 +350,7 @@ extern "C" rn_status rn_energy_min_bwd(rn_ctx *ctx, rn_plan *pl, rn_plan *plT, c
   // the forward's status and step count of every batch entry
   const size_t stb = (size_t)B * ST_STRIDE * 4;
   void *hbuf = nullptr;
-  if (hipHostMalloc(&hbuf, stb, hipHostMallocDefault) != hipSuccess)
+  if (!(hbuf = rn_pinned(ctx, stb)))
     return rn_fail(ctx, RN_ENOMEM, "rn_energy_min_bwd: pinned staging");
   HIP_TRY(ctx, hipMemcpyAsync(hbuf, t->st, stb, hipMemcpyDeviceToHost, ctx->stream));
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
@@ -360,7 +360,6 @@ extern "C" rn_status rn_energy_min_bwd(rn_ctx *ctx, rn_plan *pl, rn_plan *plT, c
     if (s[ST_STATUS]) bad = b;
     kmax = s[ST_ITERS] > kmax ? s[ST_ITERS] : kmax;
   }
-  (void)hipHostFree(hbuf);
   if (bad >= 0) return rn_fail(ctx, RN_EINVAL, "rn_energy_min_bwd: the forward run failed (batch entry %d)", bad);
   const size_t vb = (size_t)t->nzb * 8;
   HIP_TRY(ctx, hipMemsetAsync(t->Rb, 0, vb, ctx->stream));

@@ -17,6 +17,92 @@ rn_status rn_fail(rn_ctx *ctx, rn_status st, const char *fmt, ...) {
   return st;
 }
 
+#define RN_CACHE_MAX ((size_t)8 << 30)  // bytes a context keeps for reuse
+
+static void cache_release(rn_ctx *ctx, size_t keep) {
+  while (ctx->cached_bytes > keep && !ctx->cache.empty()) {
+    const rn_ctx::Block b = ctx->cache.front();  // oldest first
+    ctx->cache.erase(ctx->cache.begin());
+    ctx->cached_bytes -= b.cap;
+    (void)hipFree(b.p);
+  }
+}
+
+void *rn_dev_alloc(rn_ctx *ctx, size_t bytes) {
+  bytes = bytes == 0 ? 256 : (bytes + 255) & ~(size_t)255;
+  try {
+    // the smallest cached block that fits and wastes at most half of itself
+    int best = -1;
+    for (int i = 0; i < (int)ctx->cache.size(); ++i) {
+      const size_t c = ctx->cache[i].cap;
+      if (c >= bytes && c <= 2 * bytes + 4096 && (best < 0 || c < ctx->cache[best].cap)) best = i;
+    }
+    if (best >= 0) {
+      const rn_ctx::Block b = ctx->cache[best];
+      ctx->cache.erase(ctx->cache.begin() + best);
+      ctx->cached_bytes -= b.cap;
+      ctx->live[b.p] = b.cap;
+      return b.p;
+    }
+    void *p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      (void)hipStreamSynchronize(ctx->stream);
+      cache_release(ctx, 0);
+      if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+      }
+    }
+    ctx->live[p] = bytes;
+    return p;
+  } catch (...) {
+    return nullptr;
+  }
+}
+
+void rn_dev_free(rn_ctx *ctx, void *p) {
+  if (!p) return;
+  if (!ctx) {
+    (void)hipFree(p);
+    return;
+  }
+  auto it = ctx->live.find(p);
+  if (it == ctx->live.end()) {
+    (void)hipFree(p);
+    return;
+  }
+  try {
+    ctx->cache.push_back({p, it->second});
+    ctx->cached_bytes += it->second;
+    ctx->live.erase(it);
+    if (ctx->cached_bytes > RN_CACHE_MAX) {
+      (void)hipStreamSynchronize(ctx->stream);
+      cache_release(ctx, RN_CACHE_MAX / 2);
+    }
+  } catch (...) {
+    ctx->live.erase(p);
+    (void)hipFree(p);
+  }
+}
+
+void *rn_pinned(rn_ctx *ctx, size_t bytes) {
+  if (ctx->pinned_big_cap >= bytes) return ctx->pinned_big;
+  if (ctx->pinned_big) {
+    (void)hipStreamSynchronize(ctx->stream);
+    (void)hipHostFree(ctx->pinned_big);
+    ctx->pinned_big = nullptr;
+    ctx->pinned_big_cap = 0;
+  }
+  const size_t cap = bytes + bytes / 2 + 256;
+  if (hipHostMalloc(&ctx->pinned_big, cap, hipHostMallocDefault) != hipSuccess) {
+    ctx->pinned_big = nullptr;
+    return nullptr;
+  }
+  ctx->pinned_big_cap = cap;
+  return ctx->pinned_big;
+}
+
 void *rn_scratch(rn_ctx *ctx, int slot, size_t bytes, rn_status *st) {
   RnScratch &s = ctx->slot[slot];
   if (bytes == 0) bytes = 16;
@@ -245,14 +331,18 @@ extern "C" void rn_destroy(rn_ctx *ctx) {
   (void)hipStreamSynchronize(ctx->stream);
   for (rn_plan *pl : ctx->plans) rn_plan_detach(pl);
   ctx->plans.clear();
+  cache_release(ctx, 0);
   for (int s = 0; s < SLOT_COUNT; ++s)
     if (ctx->slot[s].ptr) (void)hipFree(ctx->slot[s].ptr);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+  if (ctx->pinned_big) (void)hipHostFree(ctx->pinned_big);
   delete ctx;
 }
 
 extern "C" rn_status rn_set_stream(rn_ctx *ctx, void *stream) {
   if (!ctx) return RN_EINVAL;
+  // cached blocks and scratch may still be read by work on the old stream
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
   ctx->stream = (hipStream_t)stream;
   return RN_OK;
 }

@@ -517,7 +517,7 @@ extern "C" rn_status rn_energy_min(rn_ctx *ctx, rn_plan *pl, const double *A_val
   int64_t *hp = ctx->pinned;
   void *big = nullptr;
   if (need > 64 * sizeof(int64_t)) {
-    if (hipHostMalloc(&big, need, hipHostMallocDefault) != hipSuccess)
+    if (!(big = rn_pinned(ctx, need)))
       return rn_fail(ctx, RN_ENOMEM, "rn_energy_min: pinned staging");
     hp = (int64_t *)big;
   }
@@ -551,7 +551,6 @@ extern "C" rn_status rn_energy_min(rn_ctx *ctx, rn_plan *pl, const double *A_val
     }
     product_cost(pl, mixed, *hterms, &stats->spgemm_bytes, &stats->spgemm_flops);
   }
-  if (big) (void)hipHostFree(big);
   if (res == RN_EBREAKDOWN)
     return rn_fail(ctx, res, "rn_energy_min: CG curvature <D, Pi(A D)> <= 0 (batch entry %d)", bad);
   if (res != RN_OK) return rn_fail(ctx, res, "rn_energy_min: non-finite Krylov scalar (batch entry %d)", bad);

@@ -8,6 +8,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "rnamg.h"
@@ -38,6 +39,7 @@ enum RnSlot {
   SLOT_PAT_XJ1,
   SLOT_PAT_CNT,
   SLOT_PAT_FLAG,
+  SLOT_PAT_OVF,
   SLOT_TEN_BINV,
   SLOT_TEN_FLAG,
   SLOT_MISC,
@@ -59,6 +61,8 @@ struct rn_ctx {
   std::string err;
   RnScratch slot[SLOT_COUNT];
   int64_t *pinned = nullptr;  // small pinned host staging area (64 x int64)
+  void *pinned_big = nullptr;  // grow-only pinned staging for larger read-backs
+  size_t pinned_big_cap = 0;
   // two-phase caches
   int64_t str_nnz = -1;
   int32_t str_nodes = -1;
@@ -69,6 +73,14 @@ struct rn_ctx {
   // live plans made on this context: rn_destroy detaches them, so a plan
   // destroyed after its context frees its memory without touching the context
   std::vector<rn_plan *> plans;
+  // caching device allocator (rn_dev_alloc / rn_dev_free)
+  struct Block {
+    void *p;
+    size_t cap;
+  };
+  std::vector<Block> cache;                  // freed blocks, reusable
+  std::unordered_map<void *, size_t> live;   // blocks handed out
+  size_t cached_bytes = 0;
 };
 
 // Error helpers -------------------------------------------------------------
@@ -89,6 +101,18 @@ rn_status rn_fail(rn_ctx *ctx, rn_status st, const char *fmt, ...);
   } while (0)
 
 #define LAUNCH_CHECK(ctx) HIP_TRY(ctx, hipGetLastError())
+
+// Device memory for objects made on a context (plans and their workspaces):
+// freed blocks stay with the context and serve later requests of a similar
+// size, so repeated set-ups do not call hipMalloc / hipFree.  Reuse is
+// ordered by the context's stream (a block is handed out again only to work
+// queued after the work that used it).  rn_dev_free with ctx = NULL frees
+// the block outright.  rn_dev_alloc returns NULL when the device is full.
+void *rn_dev_alloc(rn_ctx *ctx, size_t bytes);
+void rn_dev_free(rn_ctx *ctx, void *p);
+
+// Grow-only pinned host staging of at least `bytes` (NULL on failure).
+void *rn_pinned(rn_ctx *ctx, size_t bytes);
 
 // Grow-only scratch; contents are not preserved on growth.
 void *rn_scratch(rn_ctx *ctx, int slot, size_t bytes, rn_status *st);

@@ -345,12 +345,17 @@ static rn_status strength_transpose_path(rn_ctx *ctx, const rn_matrix *A, double
 
 // ---------------------------------------------------------------------------
 // pattern expansion: X_{t+1}(I) = sorted unique union of X_t(J), J in S(I).
-// A group of EG lanes owns one node row; candidates are staged in LDS and
-// deduplicated by first occurrence, ranks give the sorted position.
+// A group of EG lanes owns one node row; its candidates (the concatenated
+// rows X_t(J)) are staged in an LDS window of ECAP entries, deduplicated by
+// first occurrence and placed by rank.  Rows with more candidates go to a
+// device-side list that a second kernel works through with one block per
+// row and a window of BCAP entries.  COUNT passes write row sizes, FILL
+// passes the sorted columns.
 // ---------------------------------------------------------------------------
-#define EG 16
-#define ECAP 512
+#define EG 8
+#define ECAP 64
 #define ERPB (RN_BLOCK / EG)
+#define BCAP 6144
 
 template <bool FILL>
 __global__ __launch_bounds__(RN_BLOCK) void k_expand(int nn, const int32_t *__restrict__ Sp,
@@ -358,7 +363,8 @@ __global__ __launch_bounds__(RN_BLOCK) void k_expand(int nn, const int32_t *__re
                                                     const int32_t *__restrict__ Xp,
                                                     const int32_t *__restrict__ Xj,
                                                     int32_t *__restrict__ cnt_or_ptr,
-                                                    int32_t *__restrict__ Yj, int32_t *__restrict__ flag,
+                                                    int32_t *__restrict__ Yj, int32_t *__restrict__ ovf,
+                                                    int32_t *__restrict__ ovf_n,
                                                     const int32_t *__restrict__ guard) {
   __shared__ int32_t cand[ERPB][ECAP];
   __shared__ uint8_t first[ERPB][ECAP];
@@ -395,8 +401,8 @@ __global__ __launch_bounds__(RN_BLOCK) void k_expand(int nn, const int32_t *__re
       L += tot;
     }
   }
-  __syncthreads();
   const int Lc = L < ECAP ? L : ECAP;
+  __syncthreads();
   for (int c = l; c < Lc; c += EG) {
     const int v = cand[g][c];
     uint8_t f = 1;
@@ -406,10 +412,10 @@ __global__ __launch_bounds__(RN_BLOCK) void k_expand(int nn, const int32_t *__re
   }
   __syncthreads();
   if (!ok) return;
-  if (L > ECAP) {
-    if (l == 0) {
-      atomicOr(flag, GUARD_LIMIT);
-      if (!FILL) cnt_or_ptr[I] = 0;
+  if (L > ECAP) {  // the large-window kernel takes the row
+    if (!FILL && l == 0) {
+      cnt_or_ptr[I] = 0;
+      ovf[atomicAdd(ovf_n, 1)] = I;
     }
     return;
   }
@@ -428,6 +434,91 @@ __global__ __launch_bounds__(RN_BLOCK) void k_expand(int nn, const int32_t *__re
       for (int u = 0; u < Lc; ++u) rank += (first[g][u] && cand[g][u] < v);
       Yj[base + rank] = v;
     }
+  }
+}
+
+// The rows listed by k_expand<false>: one block per row, grid-stride over the
+// list (its length is read on the device, so no host round trip).  A row
+// with more than BCAP candidates sets GUARD_LIMIT.
+template <bool FILL>
+__global__ __launch_bounds__(RN_BLOCK) void k_expand_big(const int32_t *__restrict__ Sp,
+                                                        const int32_t *__restrict__ Sj,
+                                                        const int32_t *__restrict__ Xp,
+                                                        const int32_t *__restrict__ Xj,
+                                                        int32_t *__restrict__ cnt_or_ptr,
+                                                        int32_t *__restrict__ Yj,
+                                                        const int32_t *__restrict__ ovf,
+                                                        const int32_t *__restrict__ ovf_n,
+                                                        int32_t *__restrict__ guard) {
+  __shared__ int32_t cand[BCAP];
+  __shared__ uint8_t first[BCAP];
+  __shared__ int s_len[RN_BLOCK];
+  __shared__ int s_red[RN_BLOCK / RN_WAVE];
+  const int t = threadIdx.x;
+  const int nov = *ovf_n;
+  for (int q = blockIdx.x; q < nov; q += gridDim.x) {
+    const int I = ovf[q];
+    const int s = Sp[I], e = Sp[I + 1];
+    // candidates: rows of the S-neighbours, concatenated in S order
+    int L = 0;
+    for (int c0 = s; c0 < e; c0 += RN_BLOCK) {
+      const int p = c0 + t;
+      int len = 0, xs = 0;
+      if (p < e) {
+        const int J = Sj[p];
+        xs = Xp[J];
+        len = Xp[J + 1] - xs;
+      }
+      __syncthreads();
+      s_len[t] = len;
+      __syncthreads();
+      int excl = 0, tot = 0;  // block-wide exclusive prefix of len (small: RN_BLOCK terms)
+      for (int u = 0; u < RN_BLOCK; ++u) {
+        const int v = s_len[u];
+        if (u < t) excl += v;
+        tot += v;
+      }
+      for (int w = 0; w < len; ++w) {
+        const int pos = L + excl + w;
+        if (pos < BCAP) cand[pos] = Xj[xs + w];
+      }
+      L += tot;
+    }
+    __syncthreads();
+    if (L > BCAP) {
+      if (t == 0) {
+        atomicOr(guard, GUARD_LIMIT);
+        if (!FILL) cnt_or_ptr[I] = 0;
+      }
+      continue;
+    }
+    for (int c = t; c < L; c += RN_BLOCK) {
+      const int v = cand[c];
+      uint8_t f = 1;
+      for (int u = 0; u < c; ++u)
+        if (cand[u] == v) { f = 0; break; }
+      first[c] = f;
+    }
+    __syncthreads();
+    if (!FILL) {
+      int mc = 0;
+      for (int c = t; c < L; c += RN_BLOCK) mc += first[c];
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) mc += __shfl_xor(mc, off, RN_WAVE);
+      if ((t & (RN_WAVE - 1)) == 0) s_red[t / RN_WAVE] = mc;
+      __syncthreads();
+      if (t == 0) cnt_or_ptr[I] = s_red[0] + s_red[1] + s_red[2] + s_red[3];
+    } else {
+      const int base = cnt_or_ptr[I];
+      for (int c = t; c < L; c += RN_BLOCK) {
+        if (!first[c]) continue;
+        const int v = cand[c];
+        int rank = 0;
+        for (int u = 0; u < L; ++u) rank += (first[u] && cand[u] < v);
+        Yj[base + rank] = v;
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -510,6 +601,9 @@ extern "C" rn_status rn_pattern(rn_ctx *ctx, int32_t nn, const int32_t *Sp, cons
   rn_status st = RN_OK;
   int32_t *cnt = (int32_t *)rn_scratch(ctx, SLOT_PAT_CNT, (size_t)(n + 1) * sizeof(int32_t), &st);
   if (!cnt) return st;
+  // rows with more than ECAP candidates: [0] = count, [1..] = node rows
+  int32_t *ovf = (int32_t *)rn_scratch(ctx, SLOT_PAT_OVF, (size_t)(nn + 2) * sizeof(int32_t), &st);
+  if (!ovf) return st;
   int32_t *guard = rn_guard_begin(ctx, &st);
   if (!guard) return st;
   // S is validated against its own last row pointer (nnz = -1)
@@ -537,22 +631,28 @@ extern "C" rn_status rn_pattern(rn_ctx *ctx, int32_t nn, const int32_t *Sp, cons
                                         &st);
     if (!Yp) return st;
     const unsigned g = rn_div_up(nn, ERPB) ? rn_div_up(nn, ERPB) : 1;
+    const unsigned gb = 256;
+    HIP_TRY(ctx, hipMemsetAsync(ovf, 0, sizeof(int32_t), ctx->stream));
     hipLaunchKernelGGL(k_expand<false>, dim3(g), dim3(RN_BLOCK), 0, ctx->stream, nn, Sp, Sj, Xp, Xj, cnt,
-                       (int32_t *)nullptr, guard, guard);
+                       (int32_t *)nullptr, ovf + 1, ovf, guard);
+    hipLaunchKernelGGL(k_expand_big<false>, dim3(gb), dim3(RN_BLOCK), 0, ctx->stream, Sp, Sj, Xp, Xj, cnt,
+                       (int32_t *)nullptr, ovf + 1, ovf, guard);
     LAUNCH_CHECK(ctx);
     RN_TRY(rn_scan_counts(ctx, cnt, Yp, nn, nullptr));
     int64_t total = 0;
     st = rn_read_guard_i64(ctx, guard, ctx->slot[SLOT_SCAN_TOTAL].ptr, &total, "rn_pattern");
     if (st == RN_ELIMIT)
-      return rn_fail(ctx, RN_ELIMIT, "rn_pattern: a node row gathers more than %d candidates in step %d", ECAP,
+      return rn_fail(ctx, RN_ELIMIT, "rn_pattern: a node row gathers more than %d candidates in step %d", BCAP,
                      t + 1);
     RN_TRY(st);
     if (total >= ((int64_t)1 << 31)) return rn_fail(ctx, RN_ELIMIT, "rn_pattern: nodal pattern reaches 2^31");
     int32_t *Yj = (int32_t *)rn_scratch(ctx, cur ? SLOT_PAT_XJ0 : SLOT_PAT_XJ1, (size_t)(total + 1) * sizeof(int32_t),
                                         &st);
     if (!Yj) return st;
-    hipLaunchKernelGGL(k_expand<true>, dim3(g), dim3(RN_BLOCK), 0, ctx->stream, nn, Sp, Sj, Xp, Xj, Yp, Yj, guard,
-                       guard);
+    hipLaunchKernelGGL(k_expand<true>, dim3(g), dim3(RN_BLOCK), 0, ctx->stream, nn, Sp, Sj, Xp, Xj, Yp, Yj,
+                       ovf + 1, ovf, guard);
+    hipLaunchKernelGGL(k_expand_big<true>, dim3(gb), dim3(RN_BLOCK), 0, ctx->stream, Sp, Sj, Xp, Xj, Yp, Yj,
+                       ovf + 1, ovf, guard);
     LAUNCH_CHECK(ctx);
     cur ^= 1;
   }

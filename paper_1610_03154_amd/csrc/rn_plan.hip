@@ -10,20 +10,27 @@ void *rn_plan_ws(rn_plan *pl, int slot, size_t bytes, rn_status *st) {
   RnScratch &s = pl->ws[slot];
   if (bytes == 0) bytes = 16;
   if (s.cap >= bytes) return s.ptr;
-  if (s.ptr) {
-    (void)hipStreamSynchronize(pl->ctx->stream);
-    (void)hipFree(s.ptr);
-    s.ptr = nullptr;
-    s.cap = 0;
+  if (!pl->ctx) {
+    *st = RN_EINVAL;
+    return nullptr;
   }
+  rn_dev_free(pl->ctx, s.ptr);  // stream-ordered reuse: no synchronisation needed
+  s.ptr = nullptr;
+  s.cap = 0;
   const size_t cap = bytes + bytes / 8 + 256;
-  if (hipMalloc(&s.ptr, cap) != hipSuccess) {
-    s.ptr = nullptr;
+  s.ptr = rn_dev_alloc(pl->ctx, cap);
+  if (!s.ptr) {
     *st = rn_fail(pl->ctx, RN_ENOMEM, "plan workspace allocation of %zu bytes failed", cap);
     return nullptr;
   }
   s.cap = cap;
   return s.ptr;
+}
+
+template <class T>
+static bool plan_alloc(rn_plan *pl, T **p, size_t bytes) {
+  *p = (T *)rn_dev_alloc(pl->ctx, bytes);
+  return *p != nullptr;
 }
 
 static __device__ inline int pad4(int x) { return (x + 3) & ~3; }
@@ -147,7 +154,7 @@ __global__ __launch_bounds__(RN_BLOCK) void k_plan_gram(int n, const int32_t *__
 
 // ---- block partition: rows whose first entry lies in [b*chunk, (b+1)*chunk)
 // belong to block b; header = r0, r1, e0, e1, a0, a1 (A entries/blocks) and
-// the longest A row of the block's non-root rows ----
+// (filled in by k_plan_codes) the longest A row of the block's non-root rows ----
 __global__ __launch_bounds__(RN_BLOCK) void k_plan_blocks(int nr, int m, const int32_t *__restrict__ rp,
                                                          const int32_t *__restrict__ Ap,
                                                          const uint8_t *__restrict__ is_root, int nblk, int chunk,
@@ -166,10 +173,7 @@ __global__ __launch_bounds__(RN_BLOCK) void k_plan_blocks(int nr, int m, const i
   h[3] = rp[r1];
   h[4] = Ap[r0];
   h[5] = Ap[r1];
-  int na = 0;
-  for (int r = r0; r < r1; ++r)
-    if (!is_root[m * r]) na = max(na, Ap[r + 1] - Ap[r]);
-  h[6] = na;
+  h[6] = 0;  // longest A row of a non-root row: written by k_plan_codes
   h[7] = 0;
 }
 
@@ -193,7 +197,7 @@ __global__ __launch_bounds__(RN_BLOCK) void k_plan_xoff(int64_t nnzA, int m, con
 // Root entries get CODE_NONE throughout; the record's last byte is the
 // entry's row within the block. ----------------------------------------------
 template <int M>
-__global__ __launch_bounds__(RN_BLOCK) void k_plan_codes(int nblk, const int32_t *__restrict__ hdr,
+__global__ __launch_bounds__(RN_BLOCK) void k_plan_codes(int nblk, int32_t *__restrict__ hdr,
                                                         const int32_t *__restrict__ rp,
                                                         const int32_t *__restrict__ Ap,
                                                         const int32_t *__restrict__ Aj,
@@ -203,12 +207,20 @@ __global__ __launch_bounds__(RN_BLOCK) void k_plan_codes(int nblk, const int32_t
                                                         uint8_t *__restrict__ codes, int32_t *__restrict__ ncol,
                                                         int32_t *__restrict__ terms) {
   __shared__ uint8_t s_row[RN_BLOCK];
+  __shared__ int s_na[RN_BLOCK / RN_WAVE];
   const int t = threadIdx.x;
-  const int32_t *h = hdr + 8 * (int64_t)blockIdx.x;
+  int32_t *h = (int32_t *)hdr + 8 * (int64_t)blockIdx.x;
   const int r0 = h[0], e0 = h[2], ne = h[3] - h[2], nrows = h[1] - h[0];
-  for (int rr = t; rr < nrows; rr += RN_BLOCK)
+  int na_max = 0;
+  for (int rr = t; rr < nrows; rr += RN_BLOCK) {
     for (int q = rp[r0 + rr] - e0; q < rp[r0 + rr + 1] - e0; ++q) s_row[q] = (uint8_t)rr;
+    if (!is_root[M * (r0 + rr)]) na_max = max(na_max, Ap[r0 + rr + 1] - Ap[r0 + rr]);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) na_max = max(na_max, __shfl_xor(na_max, off, RN_WAVE));
+  if ((t & (RN_WAVE - 1)) == 0) s_na[t / RN_WAVE] = na_max;
   __syncthreads();
+  if (t == 0) h[6] = max(max(s_na[0], s_na[1]), max(s_na[2], s_na[3]));
   int hit = 0;
   if (t < ne) {
     const int lr = s_row[t];
@@ -326,11 +338,10 @@ extern "C" rn_status rn_plan_create(rn_ctx *ctx, const rn_matrix *A, int32_t n_c
   int32_t *misc = (int32_t *)rn_scratch(ctx, SLOT_MISC, 64, &st);
   if (!misc) return fail(st);
   if (hipMemsetAsync(misc, 0, 64, ctx->stream) != hipSuccess) return fail(rn_fail(ctx, RN_EHIP, "memset"));
-  if (hipMalloc(&pl->gp, (size_t)(n + 1) * NP * sizeof(double)) != hipSuccess ||
-      hipMalloc(&pl->d_terms, 16) != hipSuccess ||
-      hipMalloc(&pl->xoff, (size_t)(A->nnz + 1) * m * sizeof(int32_t)) != hipSuccess)
+  if (!plan_alloc(pl, &pl->gp, (size_t)(n + 1) * NP * sizeof(double)) || !plan_alloc(pl, &pl->d_terms, 16) ||
+      !plan_alloc(pl, &pl->xoff, (size_t)(A->nnz + 1) * m * sizeof(int32_t)))
     return fail(rn_fail(ctx, RN_ENOMEM, "rn_plan_create: device allocation"));
-  if (m == 2 && hipMalloc(&pl->nodeptr, (size_t)(nr + 1) * sizeof(int32_t)) != hipSuccess)
+  if (m == 2 && !plan_alloc(pl, &pl->nodeptr, (size_t)(nr + 1) * sizeof(int32_t)))
     return fail(rn_fail(ctx, RN_ENOMEM, "rn_plan_create: device allocation"));
   pl->fixed_bytes = (size_t)(nr + 1) * 4 * (m == 2 ? 1 : 0) + (size_t)(n + 1) * NP * 8 +
                     (size_t)(A->nnz + 1) * m * 4;
@@ -405,10 +416,10 @@ extern "C" rn_status rn_plan_create(rn_ctx *ctx, const rn_matrix *A, int32_t n_c
   const int ml = pl->maxlen < 1 ? 1 : pl->maxlen;
   pl->chunk = RN_BLOCK + 1 - ml;
   pl->nblk = (int)((pl->nnzN_node + pl->chunk - 1) / pl->chunk);
-  if ((m == 2 && hipMalloc(&pl->ncol, (size_t)(pl->nnzN_node + 1) * sizeof(int32_t)) != hipSuccess) ||
-      hipMalloc(&pl->codes, (size_t)ncodes + 16) != hipSuccess ||
-      hipMalloc(&pl->blk_row, (size_t)(pl->nblk + 1) * sizeof(int32_t)) != hipSuccess ||
-      hipMalloc(&pl->blk_hdr, (size_t)(pl->nblk + 1) * 8 * sizeof(int32_t)) != hipSuccess)
+  if ((m == 2 && !plan_alloc(pl, &pl->ncol, (size_t)(pl->nnzN_node + 1) * sizeof(int32_t))) ||
+      !plan_alloc(pl, &pl->codes, (size_t)ncodes + 16) ||
+      !plan_alloc(pl, &pl->blk_row, (size_t)(pl->nblk + 1) * sizeof(int32_t)) ||
+      !plan_alloc(pl, &pl->blk_hdr, (size_t)(pl->nblk + 1) * 8 * sizeof(int32_t)))
     return fail(rn_fail(ctx, RN_ENOMEM, "rn_plan_create: code allocation (%lld bytes)", (long long)ncodes));
   pl->fixed_bytes += (size_t)ncodes + (size_t)(pl->nblk + 1) * 36 + (m == 2 ? (size_t)(pl->nnzN_node + 1) * 4 : 0);
   const int32_t *rp = m == 1 ? Np : pl->nodeptr;
@@ -449,8 +460,7 @@ void rn_plan_detach(rn_plan *pl) { pl->ctx = nullptr; }
 
 extern "C" void rn_plan_destroy(rn_plan *pl) {
   if (!pl) return;
-  if (pl->ctx) {
-    (void)hipStreamSynchronize(pl->ctx->stream);
+  if (pl->ctx) {  // buffers go back to the context's cache: reuse is stream-ordered, no wait
     auto &v = pl->ctx->plans;
     for (size_t q = 0; q < v.size(); ++q)
       if (v[q] == pl) {
@@ -462,10 +472,8 @@ extern "C" void rn_plan_destroy(rn_plan *pl) {
     (void)hipDeviceSynchronize();  // its context is gone: wait for any work still reading the plan
   }
   void *bufs[] = {pl->codes, pl->ncol, pl->nodeptr, pl->gp, pl->d_terms, pl->blk_row, pl->blk_hdr, pl->xoff};
-  for (void *b : bufs)
-    if (b) (void)hipFree(b);
-  for (int s = 0; s < WS_COUNT; ++s)
-    if (pl->ws[s].ptr) (void)hipFree(pl->ws[s].ptr);
+  for (void *b : bufs) rn_dev_free(pl->ctx, b);
+  for (int s = 0; s < WS_COUNT; ++s) rn_dev_free(pl->ctx, pl->ws[s].ptr);
   delete pl;
 }
 

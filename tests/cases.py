@@ -28,6 +28,10 @@ CASES = {
     "elastic32": None,
     "elastic512": None,
     "twocand13": None,
+    # 3D 27-point: rows of 27 A entries (the product's generic term loop) and
+    # pattern rows gathering more than 64 candidates (the expansion's
+    # large-window kernel)
+    "lap27_10": (lambda: (W.laplace27(10), W.ones(1000), None, None), 0.0, 2, 4, "cg", 1),
 }
 
 

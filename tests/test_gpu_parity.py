@@ -71,7 +71,7 @@ def run_path(R, ctx, c, precision=None):
 
 
 STRENGTH_CASES = ["laplace1d_8", "poisson32", "poisson37", "aniso40", "aniso512", "upwind64", "elastic7",
-                  "elastic512"]
+                  "elastic512", "lap27_10"]
 
 
 @pytest.mark.parametrize("name", STRENGTH_CASES)
@@ -105,7 +105,7 @@ def test_tentative(R, ctx, name):
     assert CS.rel_max(host(g["T"]), c["T"]) <= FP64_TOL
 
 
-@pytest.mark.parametrize("name", ["poisson37", "aniso40", "twocand13", "elastic7", "elastic32"])
+@pytest.mark.parametrize("name", ["poisson37", "aniso40", "twocand13", "elastic7", "elastic32", "lap27_10"])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_masked_product(R, ctx, name, precision):
     import oracle as O
@@ -129,7 +129,7 @@ def test_masked_product(R, ctx, name, precision):
 
 
 CG_CASES = ["laplace1d_8", "poisson32", "poisson37", "aniso40", "aniso512", "twocand13", "elastic7",
-            "elastic512"]
+            "elastic512", "lap27_10"]
 
 
 @pytest.mark.parametrize("name", CG_CASES)

@@ -31,7 +31,7 @@ import numpy as np
 __all__ = [
     "CSR", "BSR", "stencil_grid", "poisson5", "laplace1d", "q1_stencil",
     "q1_aniso", "upwind_cd", "q1_elasticity", "rbm", "ones",
-    "aniso_batch_params", "aniso_batch", "loss_weights", "config",
+    "aniso_batch_params", "aniso_batch", "loss_weights", "config", "laplace27",
 ]
 
 
@@ -134,6 +134,29 @@ def poisson5(nx: int, ny: int | None = None) -> CSR:
     ny = nx if ny is None else ny
     return stencil_grid(nx, ny, {(0, 0): 4.0, (-1, 0): -1.0, (1, 0): -1.0,
                                  (0, -1): -1.0, (0, 1): -1.0})
+
+
+def laplace27(nx: int) -> CSR:
+    """27-point 3D Laplacian on an nx^3 grid: 26 on the diagonal, -1 to every
+    neighbour of the 3x3x3 box (Dirichlet nodes eliminated)."""
+    n = nx ** 3
+    idx = np.arange(n)
+    x, y, z = idx % nx, (idx // nx) % nx, idx // (nx * nx)
+    rows, cols, vals = [], [], []
+    for dz in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                ok = (x + dx >= 0) & (x + dx < nx) & (y + dy >= 0) & (y + dy < nx) & (z + dz >= 0) & (z + dz < nx)
+                r = idx[ok]
+                rows.append(r)
+                cols.append(r + dx + nx * dy + nx * nx * dz)
+                vals.append(np.full(r.size, 26.0 if (dx, dy, dz) == (0, 0, 0) else -1.0))
+    rows, cols, vals = np.concatenate(rows), np.concatenate(cols), np.concatenate(vals)
+    order = np.lexsort((cols, rows))
+    rows, cols, vals = rows[order], cols[order], vals[order]
+    rowptr = np.zeros(n + 1, dtype=np.int32)
+    np.add.at(rowptr, rows + 1, 1)
+    return CSR(n, n, np.cumsum(rowptr).astype(np.int32), cols.astype(np.int32), vals.astype(np.float64))
 
 
 def laplace1d(n: int = 8) -> CSR:
