@@ -95,8 +95,20 @@ __global__ __launch_bounds__(RN_BLOCK) void k_spgemm(const SpgParams p) {
   const int nw = p.cstride >> 2;
   const int te = valid ? t : 0;
   const uint32_t rec = (uint32_t)(e0 + te) * (uint32_t)nw;
-  const uint32_t w0 = spg_ld(codes, rec), w1 = spg_ld(codes, rec + 1), w2 = spg_ld(codes, rec + 2),
-                 w3 = spg_ld(codes, rec + 3);
+  // records of up to 12 bytes load as one vector (one cache access per line)
+  uint32_t w0, w1, w2, w3;
+  if (nw <= 3) {
+    const uint3 r3 = *(const uint3 *)((const char *)codes + rec * 4u);  // 4-byte aligned
+    w0 = r3.x;
+    w1 = r3.y;
+    w2 = r3.z;
+    w3 = 0xffffffffu;
+  } else {
+    w0 = spg_ld(codes, rec);
+    w1 = spg_ld(codes, rec + 1);
+    w2 = spg_ld(codes, rec + 2);
+    w3 = spg_ld(codes, rec + 3);
+  }
   const uint32_t wl = nw == 1 ? w0 : nw == 2 ? w1 : nw == 3 ? w2 : nw == 4 ? w3 : spg_ld(codes, rec + nw - 1);
   int jc0 = 0;
   if (proj) jc0 = (M == 1) ? spg_ld(p.Nj, (uint32_t)(e0 + te)) : spg_ld(p.ncol, (uint32_t)(e0 + te));
