@@ -79,6 +79,7 @@ struct rn_plan {
                                 // neighbour row (block_m = 2: of rows 2K, 2K+1)
   double *gp = nullptr;         // packed Gram pseudo-inverse per DOF row
   int32_t rank_def = 0, maxlen = 0, chunk = 1, nblk = 0;
+  int32_t bs = RN_BLOCK;        // lanes per product block (block_m = 1: 128 or 256)
   unsigned long long *d_terms = nullptr;  // multiply-add terms of one product
   size_t fixed_bytes = 0;
   RnScratch ws[WS_COUNT];
@@ -88,7 +89,7 @@ void *rn_plan_ws(rn_plan *pl, int slot, size_t bytes, rn_status *st);
 
 // Parameters of one masked-product launch (passed by value).
 struct SpgParams {
-  int32_t n, nr, nblk, k, K, hist_stride, project, scal_stride, cstride;
+  int32_t n, nr, nblk, k, K, hist_stride, project, scal_stride, cstride, bs;
   int32_t accum;  // MODE_PRODUCT: Z += result instead of Z = result
   int32_t kact;   // >= 0: batch entries whose st[ST_ITERS] <= kact do nothing
   int64_t nnzN, strideA, strideX, strideZ, Ubatch;

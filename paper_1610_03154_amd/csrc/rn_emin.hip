@@ -2,9 +2,8 @@
 // (Sec. 3.6 improve; Sec. 4.1 CG form, Sec. 4.2 GMRES form).
 //
 // CG step k:   product (Z = Pi(A D), partials of <D,Z>)
-//              -> update: every block sums the <D,Z> partials itself (same
-//                 fixed order in every block, so every block gets the same
-//                 alpha), P += alpha D, R -= alpha Z, partials of <R,R>
+//              -> alpha: one block per batch entry sums the <D,Z> partials
+//              -> update: P += alpha D, R -= alpha Z, partials of <R,R>
 //              -> direction: every block sums the <R,R> partials, beta,
 //                 D = R + beta D.
 // No inter-block synchronisation and no host round trip inside the loop; the
@@ -40,40 +39,48 @@ __global__ __launch_bounds__(RN_BLOCK) void k_cg_fin_init(int nblk, const double
   else if (g == 0.0) st[ST_DONE] = 1;
 }
 
-__global__ __launch_bounds__(RN_BLOCK) void k_cg_update(int64_t nnz, int64_t stride, int K, int k, int nblk,
-                                                       double *__restrict__ P, double *__restrict__ R,
-                                                       const double *__restrict__ D, const double *__restrict__ Z,
-                                                       const double *__restrict__ part_spg,
-                                                       double *__restrict__ part_ew, double *__restrict__ scal,
-                                                       int scal_stride, int32_t *__restrict__ stv,
-                                                       double *__restrict__ histv, int hist_stride,
-                                                       double *__restrict__ Rrec) {
+// One block per batch entry: delta_k = <D,Z> from the product's per-block
+// partials (fixed order, compensated), the step length alpha_k, the
+// breakdown and finiteness tests.
+__global__ __launch_bounds__(RN_BLOCK) void k_cg_alpha(int K, int k, int nblk, const double *__restrict__ part_spg,
+                                                      double *__restrict__ scal, int scal_stride,
+                                                      int32_t *__restrict__ stv, double *__restrict__ histv,
+                                                      int hist_stride) {
   __shared__ double s_w[8];
-  const int b = blockIdx.y;
+  const int b = blockIdx.x;
   int32_t *st = stv + (int64_t)b * ST_STRIDE;
   if (st[ST_STATUS] || st[ST_DONE]) return;
+  const double dl = rn_reduce_part(part_spg + (int64_t)b * RN_MAXDOT * nblk, nblk, s_w);
+  if (threadIdx.x != 0) return;
   double *sc = scal + (int64_t)b * scal_stride;
   const CgLayout L(K);
-  const double dl = rn_reduce_part(part_spg + (int64_t)b * RN_MAXDOT * nblk, nblk, s_w);
-  const bool first = blockIdx.x == 0 && threadIdx.x == 0;
   double *hist = histv ? histv + (int64_t)b * hist_stride : nullptr;
-  if (first) {
-    sc[L.del + k] = dl;
-    if (hist) hist[1 + K + k] = dl;
-  }
+  sc[L.del + k] = dl;
+  if (hist) hist[1 + K + k] = dl;
   if (!isfinite(dl)) {
-    if (first) st[ST_STATUS] = RN_ENONFINITE;
+    st[ST_STATUS] = RN_ENONFINITE;
     return;
   }
   if (dl <= 0.0) {
-    if (first) st[ST_STATUS] = RN_EBREAKDOWN;
+    st[ST_STATUS] = RN_EBREAKDOWN;
     return;
   }
   const double al = sc[L.gam + k] / dl;
-  if (first) {
-    sc[L.alp + k] = al;
-    if (hist) hist[1 + 2 * K + k] = al;
-  }
+  sc[L.alp + k] = al;
+  if (hist) hist[1 + 2 * K + k] = al;
+}
+
+__global__ __launch_bounds__(RN_BLOCK) void k_cg_update(int64_t nnz, int64_t stride, int K, int k,
+                                                       double *__restrict__ P, double *__restrict__ R,
+                                                       const double *__restrict__ D, const double *__restrict__ Z,
+                                                       double *__restrict__ part_ew, const double *__restrict__ scal,
+                                                       int scal_stride, const int32_t *__restrict__ stv,
+                                                       double *__restrict__ Rrec) {
+  __shared__ double s_w[8];
+  const int b = blockIdx.y;
+  const int32_t *st = stv + (int64_t)b * ST_STRIDE;
+  if (st[ST_STATUS] || st[ST_DONE]) return;
+  const double al = scal[(int64_t)b * scal_stride + CgLayout(K).alp + k];
   const int64_t off = (int64_t)b * stride;
   RnAcc s;
   for (int64_t e = (int64_t)blockIdx.x * RN_BLOCK + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * RN_BLOCK) {
@@ -429,8 +436,10 @@ extern "C" rn_status rn_energy_min(rn_ctx *ctx, rn_plan *pl, const double *A_val
       s.Xown = D;
       s.Z = Z;
       RN_TRY(rn_launch_spgemm(ctx, pl, MODE_CG_STEP, s, batch, mixed));
-      hipLaunchKernelGGL(k_cg_update, g2, blk, 0, ctx->stream, nz, nz, K, k, pl->nblk, P, R, D, Z, part_spg, part_ew,
-                         p.scal, scal_stride, p.st, hist, hist_stride, tape ? rn_tape_R(tape, k + 1) : nullptr);
+      hipLaunchKernelGGL(k_cg_alpha, dim3(batch), blk, 0, ctx->stream, K, k, pl->nblk, part_spg, p.scal, scal_stride,
+                         p.st, hist, hist_stride);
+      hipLaunchKernelGGL(k_cg_update, g2, blk, 0, ctx->stream, nz, nz, K, k, P, R, D, Z, part_ew, p.scal,
+                         scal_stride, p.st, tape ? rn_tape_R(tape, k + 1) : nullptr);
       LAUNCH_CHECK(ctx);
       if (mixed)
         hipLaunchKernelGGL(k_cg_dir<true>, g2, blk, 0, ctx->stream, nz, nz, K, k, (int)gew, R, D, D32, part_ew, p.scal,

@@ -178,11 +178,12 @@ struct RnAcc {
   }
 };
 
-// Deterministic compensated block sum (blockDim.x == 256): a fixed shuffle
-// tree within each wave and a fixed-order combination of the four waves, each
+// Deterministic compensated block sum (NW waves; blockDim.x == 64 NW <= 256):
+// a fixed shuffle tree within each wave and a fixed-order combination of the waves, each
 // addition done with TwoSum so the result is accurate to a few ulp whatever
 // the number of terms.  lds8 holds 8 doubles.  Every thread gets the result.
-__device__ inline double rn_block_sum2(double hi, double lo, double *lds8) {
+template <int NW>
+__device__ inline double rn_block_sum2_w(double hi, double lo, double *lds8) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
     const double oh = __shfl_down(hi, off, RN_WAVE), ol = __shfl_down(lo, off, RN_WAVE);
@@ -200,7 +201,7 @@ __device__ inline double rn_block_sum2(double hi, double lo, double *lds8) {
   __syncthreads();
   double h = lds8[0], l = lds8[4];
 #pragma unroll
-  for (int w = 1; w < 4; ++w) {
+  for (int w = 1; w < NW; ++w) {
     double s, e;
     rn_two_sum(h, lds8[w], s, e);
     h = s;
@@ -209,6 +210,7 @@ __device__ inline double rn_block_sum2(double hi, double lo, double *lds8) {
   __syncthreads();
   return h + l;
 }
+__device__ inline double rn_block_sum2(double hi, double lo, double *lds8) { return rn_block_sum2_w<4>(hi, lo, lds8); }
 __device__ inline double rn_block_sum(double v, double *lds8) { return rn_block_sum2(v, 0.0, lds8); }
 
 // Ticket of the last block to finish: every block's thread 0 calls this

@@ -1,6 +1,7 @@
 // rn_plan.hip -- symbolic part of the energy minimisation (Sec. 3.6): the
 // position codes of the masked product, the per-row least-squares data of the
 // constraint projection and the block partition of the product.
+#include <cstdlib>
 #include <cstring>
 #include <new>
 
@@ -51,7 +52,7 @@ static __device__ inline void block_to_slot(int v, int32_t *out) {
   __syncthreads();
   if (threadIdx.x == 0) {
     int r = s[0];
-    for (int w = 1; w < RN_BLOCK / RN_WAVE; ++w) r = MAX ? max(r, s[w]) : r + s[w];
+    for (int w = 1; w < (int)(blockDim.x / RN_WAVE); ++w) r = MAX ? max(r, s[w]) : r + s[w];
     out[blockIdx.x] = r;
   }
 }
@@ -212,7 +213,7 @@ __global__ __launch_bounds__(RN_BLOCK) void k_plan_codes(int nblk, int32_t *__re
   int32_t *h = (int32_t *)hdr + 8 * (int64_t)blockIdx.x;
   const int r0 = h[0], e0 = h[2], ne = h[3] - h[2], nrows = h[1] - h[0];
   int na_max = 0;
-  for (int rr = t; rr < nrows; rr += RN_BLOCK) {
+  for (int rr = t; rr < nrows; rr += blockDim.x) {
     for (int q = rp[r0 + rr] - e0; q < rp[r0 + rr + 1] - e0; ++q) s_row[q] = (uint8_t)rr;
     if (!is_root[M * (r0 + rr)]) na_max = max(na_max, Ap[r0 + rr + 1] - Ap[r0 + rr]);
   }
@@ -220,7 +221,11 @@ __global__ __launch_bounds__(RN_BLOCK) void k_plan_codes(int nblk, int32_t *__re
   for (int off = 32; off > 0; off >>= 1) na_max = max(na_max, __shfl_xor(na_max, off, RN_WAVE));
   if ((t & (RN_WAVE - 1)) == 0) s_na[t / RN_WAVE] = na_max;
   __syncthreads();
-  if (t == 0) h[6] = max(max(s_na[0], s_na[1]), max(s_na[2], s_na[3]));
+  if (t == 0) {
+    int mx = s_na[0];
+    for (int w = 1; w < (int)(blockDim.x / RN_WAVE); ++w) mx = max(mx, s_na[w]);
+    h[6] = mx;
+  }
   int hit = 0;
   if (t < ne) {
     const int lr = s_row[t];
@@ -414,7 +419,12 @@ extern "C" rn_status rn_plan_create(rn_ctx *ctx, const rn_matrix *A, int32_t n_c
   // product blocks: every block holds at most 256 entries (node entries for
   // block_m = 2): rows starting in a chunk of 257 - maxlen entries
   const int ml = pl->maxlen < 1 ? 1 : pl->maxlen;
-  pl->chunk = RN_BLOCK + 1 - ml;
+  pl->bs = (m == 1 && ml <= 32) ? 128 : RN_BLOCK;
+  if (const char *ev = getenv("RNAMG_PRODUCT_BS")) {
+    const int v = atoi(ev);
+    pl->bs = (m == 1 && (v == 64 || v == 128) && ml <= v / 4) ? v : RN_BLOCK;
+  }
+  pl->chunk = pl->bs + 1 - ml;
   pl->nblk = (int)((pl->nnzN_node + pl->chunk - 1) / pl->chunk);
   if ((m == 2 && !plan_alloc(pl, &pl->ncol, (size_t)(pl->nnzN_node + 1) * sizeof(int32_t))) ||
       !plan_alloc(pl, &pl->codes, (size_t)ncodes + 16) ||
@@ -435,7 +445,7 @@ extern "C" rn_status rn_plan_create(rn_ctx *ctx, const rn_matrix *A, int32_t n_c
   if (pl->nblk > 0) {
     int32_t *blk_hit = (int32_t *)rn_scratch(ctx, SLOT_BLK2, (size_t)(pl->nblk + 1) * sizeof(int32_t), &st);
     if (!blk_hit) return fail(st);
-    const dim3 gc(pl->nblk), bc(RN_BLOCK);
+    const dim3 gc(pl->nblk), bc(pl->bs);  // one thread per entry slot of a product block
     const int nb = pl->nblk;
     if (m == 1)
       hipLaunchKernelGGL((k_plan_codes<1>), gc, bc, 0, ctx->stream, nb, pl->blk_hdr, rp, A->rowptr, A->colind, Np,

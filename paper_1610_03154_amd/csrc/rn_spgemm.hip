@@ -30,30 +30,30 @@ __device__ inline void spg_st(T *base, uint32_t i, T v) {
   *(T *)((char *)base + i * (uint32_t)sizeof(T)) = v;
 }
 
-template <int M, int NB, bool MIXED>
+template <int M, int NB, bool MIXED, int BS>
 struct SpgShape {
   using TV = typename std::conditional<MIXED, float, double>::type;
   static constexpr int NO = M * M;
-  static constexpr int ACAP = M == 1 ? SPG_ACAP : SPG_ACAP / 2;  // staged A entries
-  static constexpr int NIT = ACAP / RN_BLOCK;                    // staging loads per thread
+  static constexpr int ACAP = (M == 1 ? SPG_ACAP : SPG_ACAP / 2) * BS / RN_BLOCK;  // staged A entries
+  static constexpr int NIT = ACAP / BS;                                          // staging loads per thread
   static constexpr size_t P1 = (size_t)ACAP * (sizeof(int) * M + NO * sizeof(TV));
-  static constexpr size_t P2 = (size_t)M * NB * M * RN_BLOCK * sizeof(double);
+  static constexpr size_t P2 = (size_t)M * NB * M * BS * sizeof(double);
   // + 128 bytes: the register path reads up to 15 entries past a row's start
   static constexpr size_t BYTES = (P1 > P2 ? P1 : P2) + 128;
 };
 
-template <int M, int NB, int MODE, bool MIXED>
-__global__ __launch_bounds__(RN_BLOCK) void k_spgemm(const SpgParams p) {
-  using SH = SpgShape<M, NB, MIXED>;
+template <int M, int NB, int MODE, bool MIXED, int BS>
+__global__ __launch_bounds__(BS) void k_spgemm(const SpgParams p) {
+  using SH = SpgShape<M, NB, MIXED, BS>;
   using TV = typename SH::TV;
   constexpr int NP = NB * (NB + 1) / 2;
   constexpr int NO = M * M;
   constexpr int ACAP = SH::ACAP, NIT = SH::NIT;
   constexpr int UMAX = 15;  // terms of the register path (records of <= 16 bytes)
-  __shared__ int s_rp[RN_BLOCK + 1];   // row starts, relative to the block's first entry
-  __shared__ int s_ap[RN_BLOCK + 1];   // row starts in A, relative to the block's first A entry
-  __shared__ int s_np0[M == 2 ? RN_BLOCK : 1], s_np1[M == 2 ? RN_BLOCK : 1];
-  __shared__ uint8_t s_root[RN_BLOCK];
+  __shared__ int s_rp[BS + 1];   // row starts, relative to the block's first entry
+  __shared__ int s_ap[BS + 1];   // row starts in A, relative to the block's first A entry
+  __shared__ int s_np0[M == 2 ? BS : 1], s_np1[M == 2 ? BS : 1];
+  __shared__ uint8_t s_root[BS];
   __shared__ double s_w[8];
   __shared__ __align__(16) unsigned char s_buf[SH::BYTES];
   // phase 1 view: neighbour row starts and A values
@@ -61,7 +61,7 @@ __global__ __launch_bounds__(RN_BLOCK) void k_spgemm(const SpgParams p) {
   int *s_x1 = s_x0 + ACAP;  // block_m = 2 only
   TV *s_ax = (TV *)(s_buf + (size_t)ACAP * sizeof(int) * M);
   // phase 2 view: per-entry projection terms
-  double(*s_red)[NB][M * RN_BLOCK] = (double(*)[NB][M * RN_BLOCK])s_buf;
+  double(*s_red)[NB][M * BS] = (double(*)[NB][M * BS])s_buf;
 
   const int blk = rn_xcd_block(blockIdx.x, p.nblk);
   if (blk < 0) return;
@@ -138,8 +138,8 @@ __global__ __launch_bounds__(RN_BLOCK) void k_spgemm(const SpgParams p) {
       v_x1[it] = 0;
 #pragma unroll
       for (int o = 0; o < NO; ++o) v_ax[it][o] = 0;
-      if (it * RN_BLOCK < naB) {  // uniform
-        const uint32_t q = (uint32_t)(aB + (t + it * RN_BLOCK < naB ? t + it * RN_BLOCK : naB - 1));
+      if (it * BS < naB) {  // uniform
+        const uint32_t q = (uint32_t)(aB + (t + it * BS < naB ? t + it * BS : naB - 1));
         if constexpr (M == 1) {
           v_x0[it] = spg_ld(p.xoff, q);
         } else {
@@ -163,14 +163,14 @@ __global__ __launch_bounds__(RN_BLOCK) void k_spgemm(const SpgParams p) {
       s_np1[t] = v_np1;
     }
   }
-  if (nrows == RN_BLOCK && t == 0) {
-    s_rp[RN_BLOCK] = rp[r0 + RN_BLOCK] - e0;
-    s_ap[RN_BLOCK] = p.Ap[r0 + RN_BLOCK] - aB;
+  if (nrows == BS && t == 0) {
+    s_rp[BS] = rp[r0 + BS] - e0;
+    s_ap[BS] = p.Ap[r0 + BS] - aB;
   }
   if (staged && naB > 0) {
 #pragma unroll
     for (int it = 0; it < NIT; ++it) {
-      const int q = t + it * RN_BLOCK;
+      const int q = t + it * BS;
       if (q < naB) {
         s_x0[q] = v_x0[it];
         if constexpr (M == 2) s_x1[q] = v_x1[it];
@@ -388,7 +388,7 @@ __global__ __launch_bounds__(RN_BLOCK) void k_spgemm(const SpgParams p) {
         if (p.Z2) spg_st(p.Z2 + zb, (uint32_t)zi[o], v);
         d.add(v * v);
       }
-    const double S = rn_block_sum2(d.hi, d.lo, s_w);
+    const double S = rn_block_sum2_w<BS / RN_WAVE>(d.hi, d.lo, s_w);
     if (threadIdx.x == 0) part[blk] = S;
     return;
   }
@@ -400,7 +400,7 @@ __global__ __launch_bounds__(RN_BLOCK) void k_spgemm(const SpgParams p) {
         spg_st(Z, (uint32_t)zi[o], z[o]);
         d.add(ownv[o] * z[o]);
       }
-    const double S = rn_block_sum2(d.hi, d.lo, s_w);
+    const double S = rn_block_sum2_w<BS / RN_WAVE>(d.hi, d.lo, s_w);
     if (threadIdx.x == 0) part[blk] = S;
     return;
   }
@@ -415,7 +415,7 @@ __global__ __launch_bounds__(RN_BLOCK) void k_spgemm(const SpgParams p) {
 #pragma unroll
       for (int o = 0; o < NO; ++o)
         if (zi[o] >= 0) d.add(spg_ld(Uj, (uint32_t)zi[o]) * z[o]);
-      const double S = rn_block_sum2(d.hi, d.lo, s_w);
+      const double S = rn_block_sum2_w<BS / RN_WAVE>(d.hi, d.lo, s_w);
       if (threadIdx.x == 0) part[(int64_t)j * p.nblk + blk] = S;
     }
   }
@@ -423,9 +423,17 @@ __global__ __launch_bounds__(RN_BLOCK) void k_spgemm(const SpgParams p) {
 
 template <int M, int NB, int MODE>
 static void launch_m(const SpgParams &p, int batch, bool mixed, hipStream_t s) {
-  const dim3 grid(rn_xcd_grid((unsigned)p.nblk), (unsigned)batch), block(RN_BLOCK);
-  if (mixed) hipLaunchKernelGGL((k_spgemm<M, NB, MODE, true>), grid, block, 0, s, p);
-  else hipLaunchKernelGGL((k_spgemm<M, NB, MODE, false>), grid, block, 0, s, p);
+  const dim3 grid(rn_xcd_grid((unsigned)p.nblk), (unsigned)batch);
+  if (M == 1 && p.bs == 128) {
+    if (mixed) hipLaunchKernelGGL((k_spgemm<M, NB, MODE, true, 128>), grid, dim3(128), 0, s, p);
+    else hipLaunchKernelGGL((k_spgemm<M, NB, MODE, false, 128>), grid, dim3(128), 0, s, p);
+  } else if (M == 1 && p.bs == 64) {
+    if (mixed) hipLaunchKernelGGL((k_spgemm<M, NB, MODE, true, 64>), grid, dim3(64), 0, s, p);
+    else hipLaunchKernelGGL((k_spgemm<M, NB, MODE, false, 64>), grid, dim3(64), 0, s, p);
+  } else {
+    if (mixed) hipLaunchKernelGGL((k_spgemm<M, NB, MODE, true, RN_BLOCK>), grid, dim3(RN_BLOCK), 0, s, p);
+    else hipLaunchKernelGGL((k_spgemm<M, NB, MODE, false, RN_BLOCK>), grid, dim3(RN_BLOCK), 0, s, p);
+  }
 }
 
 template <int MODE>
@@ -475,6 +483,7 @@ SpgParams rn_spg_params(const rn_plan *pl) {
   p.Np = pl->Np;
   p.Nj = pl->Nj;
   p.cstride = pl->cstride;
+  p.bs = pl->bs;
   p.kact = -1;
   p.ncol = pl->ncol;
   p.nodeptr = pl->nodeptr;
