@@ -297,7 +297,7 @@ __global__ __launch_bounds__(RN_BLOCK) void k_adj_sddmm(int nblk, int64_t nz, in
     const int xo = xoff[a0 + q];
     double acc = 0.0;
     for (int r = Np[i]; r < Np[i + 1]; ++r) {
-      const uint32_t c = codes[(int64_t)r * cstride + u];
+      const uint32_t c = codes[(int64_t)r * cstride + 1 + u];  // byte 0 is the row
       if (c != CODE_NONE) acc += y[r] * x[xo + (int)c];
     }
     ab[a0 + q] += acc;

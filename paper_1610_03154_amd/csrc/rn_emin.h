@@ -9,9 +9,9 @@
 // CODE_ROOT (k is a root node, block_m = 2: its two DOF rows hold one entry
 // each), or CODE_NONE.  Layout: one record per (node) entry with one stride
 // for every entry (the longest A row of a non-root row plus one byte, rounded
-// up to 4 bytes): the codes, CODE_NONE padding, and in the last byte the
-// entry's row within its product block.  A lane finds its record from its
-// entry index alone and reads it as 32-bit words.
+// up to 4 bytes): the entry's row within its product block in byte 0, then
+// the codes, then CODE_NONE padding.  A lane finds its record from its entry
+// index alone and reads it as 32-bit words.
 #define CODE_NONE 255
 #define CODE_ROOT 254
 #define CODE_MAXLEN 253
@@ -19,6 +19,17 @@
 // Block-row A entries staged in LDS by the product kernel (larger blocks read
 // A from global memory directly).
 #define SPG_ACAP 1024
+// Scalar operators: A entries staged per block of bs lanes, and the capacity
+// (elements) of the block's X window.  The window holds the pattern entries
+// of every neighbour row the block's rows touch, as runs of consecutive rows
+// padded to XW_UNIT elements, so the product reads X from LDS after loading
+// it with contiguous 32-bit loads.  Per block the plan stores, for each
+// XW_UNIT-element unit of the window, the global index of its first element.
+#define SPG_ACAP_M1(bs) (3 * (bs))
+#define SPG_XCAP_M1(bs) (4 * (bs))
+#define XW_UNIT 32
+#define XW_GAP 16     // runs closer than this many elements are merged
+#define XW_RUNMAX 15  // more runs: the block reads X from global memory
 
 // per-batch integer state
 enum { ST_STATUS = 0, ST_DONE = 1, ST_ITERS = 2, ST_KD = 3, ST_STRIDE = 8 };
@@ -74,9 +85,14 @@ struct rn_plan {
   int32_t *nodeptr = nullptr;   // block_m = 2: node-entry row pointer
   int32_t *ncol = nullptr;      // block_m = 2: node column of each node entry
   int32_t *blk_row = nullptr;   // product blocks: first row of block b, b = 0..nblk
-  int32_t *blk_hdr = nullptr;   // per block: r0, r1, e0, e1, a0, a1 (8 ints)
+  int32_t *blk_hdr = nullptr;   // per block: r0, r1, e0, e1, a0, a1, longest A row,
+                                // X window units (0: no window) -- 8 ints
   int32_t *xoff = nullptr;      // per stored A entry: first pattern entry of the
                                 // neighbour row (block_m = 2: of rows 2K, 2K+1)
+  int32_t *xl = nullptr;        // block_m = 1, per stored A entry of a block with
+                                // an X window: the neighbour row's offset in it
+  int32_t *xwin = nullptr;      // block_m = 1, per block: bs/8 unit starts
+  double *bce = nullptr;        // block_m = 1, n_B <= 2: Bc row of each entry's column
   double *gp = nullptr;         // packed Gram pseudo-inverse per DOF row
   int32_t rank_def = 0, maxlen = 0, chunk = 1, nblk = 0;
   int32_t bs = RN_BLOCK;        // lanes per product block (block_m = 1: 128 or 256)
@@ -93,9 +109,9 @@ struct SpgParams {
   int32_t accum;  // MODE_PRODUCT: Z += result instead of Z = result
   int32_t kact;   // >= 0: batch entries whose st[ST_ITERS] <= kact do nothing
   int64_t nnzN, strideA, strideX, strideZ, Ubatch;
-  const int32_t *Ap, *Aj, *Np, *Nj, *nodeptr, *ncol, *blk_row, *blk_hdr, *xoff;
+  const int32_t *Ap, *Aj, *Np, *Nj, *nodeptr, *ncol, *blk_row, *blk_hdr, *xoff, *xl, *xwin;
   const uint8_t *codes, *is_root;
-  const double *Bc, *gp;
+  const double *Bc, *gp, *bce;
   const void *Ax;      // double or float, [batch][strideA]
   const void *X;       // double or float, [batch][strideX]
   const double *Xown;  // FP64 own-entry values for the CG dot (D)
@@ -124,7 +140,16 @@ rn_status rn_tape_record_end(rn_ctx *ctx, rn_tape *tape, const double *scal, con
 // partials to threads, compensated, fixed tree).
 __device__ inline double rn_reduce_part(const double *__restrict__ part, int nb, double *lds8) {
   RnAcc a;
-  for (int q = threadIdx.x; q < nb; q += RN_BLOCK) a.add(part[q]);
+  int q = threadIdx.x;
+  // eight loads in flight per thread, then the additions in the same order
+  for (; q + 7 * RN_BLOCK < nb; q += 8 * RN_BLOCK) {
+    double v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = part[q + k * RN_BLOCK];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) a.add(v[k]);
+  }
+  for (; q < nb; q += RN_BLOCK) a.add(part[q]);
   return rn_block_sum2(a.hi, a.lo, lds8);
 }
 

@@ -1,6 +1,7 @@
 // rn_plan.hip -- symbolic part of the energy minimisation (Sec. 3.6): the
 // position codes of the masked product, the per-row least-squares data of the
 // constraint projection and the block partition of the product.
+#include <climits>
 #include <cstdlib>
 #include <cstring>
 #include <new>
@@ -153,6 +154,13 @@ __global__ __launch_bounds__(RN_BLOCK) void k_plan_gram(int n, const int32_t *__
   block_to_slot<false>(bad, rank_def);  // per-block counts
 }
 
+// ---- Bc row of each pattern entry's column (block_m = 1, n_B <= 2) ----------
+__global__ __launch_bounds__(RN_BLOCK) void k_plan_bce(int64_t nnzN, int nB, const int32_t *__restrict__ Nj,
+                                                      const double *__restrict__ Bc, double *__restrict__ bce) {
+  for (int64_t e = (int64_t)blockIdx.x * RN_BLOCK + threadIdx.x; e < nnzN; e += (int64_t)gridDim.x * RN_BLOCK)
+    for (int q = 0; q < nB; ++q) bce[e * nB + q] = Bc[(int64_t)Nj[e] * nB + q];
+}
+
 // ---- block partition: rows whose first entry lies in [b*chunk, (b+1)*chunk)
 // belong to block b; header = r0, r1, e0, e1, a0, a1 (A entries/blocks) and
 // (filled in by k_plan_codes) the longest A row of the block's non-root rows ----
@@ -192,11 +200,184 @@ __global__ __launch_bounds__(RN_BLOCK) void k_plan_xoff(int64_t nnzA, int m, con
   }
 }
 
+// ---- X windows (block_m = 1): one block per product block --------------------
+// The distinct columns k of the block's A rows are marked in an LDS bitmap
+// over [kmin, kmin + XW_SPAN) and listed in ascending order; the pattern rows
+// k form runs of consecutive pattern entries (runs closer than XW_GAP merge);
+// each run is padded to a multiple of XW_UNIT entries and the runs are laid
+// out one after another.  Outputs: the window's unit starts (global index of
+// the first element of every unit, 0 where unused), for each A entry of the
+// block the offset of its neighbour row inside the window, and the unit count
+// in the header (0 when the block has too many A entries or runs, its columns
+// span XW_SPAN or more, or the window does not fit).
+#define XW_SPAN 8192
+// Exclusive prefix of a per-thread count over the block (wave shuffles, then
+// the wave totals through LDS); total = the sum over the block.
+template <int BSZ>
+__device__ inline int xw_scan(int v, int *s_cnt, int &total) {
+  const int t = threadIdx.x, lane = t & (RN_WAVE - 1), w = t / RN_WAVE;
+  int inc = v;
+#pragma unroll
+  for (int off = 1; off < RN_WAVE; off <<= 1) {
+    const int o = __shfl_up(inc, off, RN_WAVE);
+    if (lane >= off) inc += o;
+  }
+  if (lane == RN_WAVE - 1) s_cnt[w] = inc;
+  __syncthreads();
+  int off = 0, tot = 0;
+#pragma unroll
+  for (int ww = 0; ww < BSZ / RN_WAVE; ++ww) {
+    const int c = s_cnt[ww];
+    off += ww < w ? c : 0;
+    tot += c;
+  }
+  __syncthreads();
+  total = tot;
+  return off + inc - v;
+}
+
+template <int BSZ>
+__global__ __launch_bounds__(BSZ) void k_plan_xwin(int32_t *__restrict__ hdr, const int32_t *__restrict__ Aj,
+                                                  const int32_t *__restrict__ Np, int64_t nnzN,
+                                                  int32_t *__restrict__ xl, int32_t *__restrict__ xwin) {
+  constexpr int ACAP = SPG_ACAP_M1(BSZ), XCAP = SPG_XCAP_M1(BSZ), NU = XCAP / XW_UNIT;
+  constexpr int NWORD = XW_SPAN / 32, WPT = NWORD / BSZ;  // bitmap words, per thread
+  static_assert(NWORD % BSZ == 0, "bitmap words split evenly");
+  __shared__ uint32_t s_bits[NWORD];
+  __shared__ int s_v[ACAP];  // distinct columns, ascending
+  __shared__ int s_r[ACAP];  // run of each distinct column
+  __shared__ int s_cnt[BSZ / RN_WAVE];
+  __shared__ int s_mm[2 * (BSZ / RN_WAVE)];
+  __shared__ int s_xs[XW_RUNMAX + 1], s_xe[XW_RUNMAX + 1], s_dst[XW_RUNMAX + 1];
+  __shared__ int s_ok;
+  const int t = threadIdx.x, lane = t & (RN_WAVE - 1), w = t / RN_WAVE;
+  int32_t *h = hdr + 8 * (int64_t)blockIdx.x;
+  const int a0 = h[4], na = h[5] - h[4];
+  int32_t *uw = xwin + (int64_t)blockIdx.x * NU;
+  auto none = [&]() {
+    if (t == 0) h[7] = 0;
+    for (int u = t; u < NU; u += BSZ) uw[u] = 0;
+  };
+  if (na <= 0 || na > ACAP) {  // uniform
+    none();
+    return;
+  }
+  // column range of the block
+  int kmin = INT_MAX, kmax = -1;
+  for (int q = t; q < na; q += BSZ) {
+    const int k = Aj[a0 + q];
+    kmin = min(kmin, k);
+    kmax = max(kmax, k);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    kmin = min(kmin, __shfl_xor(kmin, off, RN_WAVE));
+    kmax = max(kmax, __shfl_xor(kmax, off, RN_WAVE));
+  }
+  if (lane == 0) {
+    s_mm[w] = kmin;
+    s_mm[BSZ / RN_WAVE + w] = kmax;
+  }
+#pragma unroll
+  for (int i = 0; i < WPT; ++i) s_bits[t * WPT + i] = 0u;
+  __syncthreads();
+#pragma unroll
+  for (int ww = 0; ww < BSZ / RN_WAVE; ++ww) {
+    kmin = min(kmin, s_mm[ww]);
+    kmax = max(kmax, s_mm[BSZ / RN_WAVE + ww]);
+  }
+  if (kmax - kmin >= XW_SPAN) {  // uniform
+    none();
+    return;
+  }
+  for (int q = t; q < na; q += BSZ) {
+    const int k = Aj[a0 + q] - kmin;
+    atomicOr(&s_bits[k >> 5], 1u << (k & 31));
+  }
+  __syncthreads();
+  // distinct columns in ascending order: thread t owns words t*WPT ..
+  uint32_t wd[WPT];
+  int c = 0;
+#pragma unroll
+  for (int i = 0; i < WPT; ++i) {
+    wd[i] = s_bits[t * WPT + i];
+    c += __popc(wd[i]);
+  }
+  int nu;
+  int pos = xw_scan<BSZ>(c, s_cnt, nu);
+#pragma unroll
+  for (int i = 0; i < WPT; ++i) {
+    uint32_t m = wd[i];
+    while (m) {
+      const int bit = __ffs(m) - 1;
+      m &= m - 1u;
+      s_v[pos++] = kmin + (t * WPT + i) * 32 + bit;
+    }
+  }
+  __syncthreads();
+  // runs of the neighbour rows' entries
+  int nrun = 0;
+  for (int i0 = 0; i0 < nu; i0 += BSZ) {
+    const int i = i0 + t;
+    bool f = false;
+    if (i < nu) f = i == 0 || (int64_t)Np[s_v[i]] - Np[s_v[i - 1] + 1] > XW_GAP;
+    int tot;
+    const int pre = xw_scan<BSZ>(f ? 1 : 0, s_cnt, tot);
+    // run id of position i: starts at or before i, minus one
+    if (i < nu) {
+      const int rid = nrun + pre + (f ? 1 : 0) - 1;
+      s_r[i] = rid;
+      if (rid <= XW_RUNMAX - 1) {
+        if (f) s_xs[rid] = Np[s_v[i]];
+        // the last column of its run: the next position starts a run or ends the list
+        const bool last = i == nu - 1 || (int64_t)Np[s_v[i + 1]] - Np[s_v[i] + 1] > XW_GAP;
+        if (last) s_xe[rid] = Np[s_v[i] + 1];
+      }
+    }
+    nrun += tot;
+  }
+  __syncthreads();
+  if (t == 0) {
+    bool ok = nrun <= XW_RUNMAX;
+    int dst = 0;
+    for (int r = 0; ok && r < nrun; ++r) {
+      const int len = s_xe[r] - s_xs[r];
+      const int lp = (len + XW_UNIT - 1) / XW_UNIT * XW_UNIT;
+      int64_t xs = s_xs[r];
+      if (xs + lp > nnzN) xs = nnzN - lp;  // keep the padding inside X
+      if (xs < 0) ok = false;
+      s_xs[r] = (int)xs;
+      s_dst[r] = dst;
+      dst += lp;
+    }
+    if (dst > XCAP) ok = false;
+    s_ok = ok ? dst / XW_UNIT : 0;
+    h[7] = s_ok;
+  }
+  __syncthreads();
+  const int nunit = s_ok;
+  if (nunit == 0) {
+    for (int u = t; u < NU; u += BSZ) uw[u] = 0;
+    return;
+  }
+  for (int u = t; u < NU; u += BSZ) {
+    int r = 0;
+    for (int rr = 1; rr < nrun; ++rr)
+      if (s_dst[rr] <= u * XW_UNIT) r = rr;
+    uw[u] = u < nunit ? s_xs[r] + u * XW_UNIT - s_dst[r] : 0;
+  }
+  for (int q = t; q < na; q += BSZ) {
+    const int k = Aj[a0 + q];
+    const int r = s_r[rn_lower_bound(s_v, nu, k)];
+    xl[a0 + q] = s_dst[r] + Np[k] - s_xs[r];
+  }
+}
+
 // ---- position codes: one lane per pattern entry (node entry for block_m = 2),
 // one block per product block.  The column of the entry is searched in every
 // neighbour row; up to 12 searches run in lockstep so their loads overlap.
-// Root entries get CODE_NONE throughout; the record's last byte is the
-// entry's row within the block. ----------------------------------------------
+// Root entries get CODE_NONE throughout; the record's first byte is the
+// entry's row within the block, code u is byte u + 1. ------------------------
 template <int M>
 __global__ __launch_bounds__(RN_BLOCK) void k_plan_codes(int nblk, int32_t *__restrict__ hdr,
                                                         const int32_t *__restrict__ rp,
@@ -234,14 +415,15 @@ __global__ __launch_bounds__(RN_BLOCK) void k_plan_codes(int nblk, int32_t *__re
     uint32_t *cw = (uint32_t *)(codes + (int64_t)(e0 + t) * cstride);
     const int nw = cstride >> 2;
     if (is_root[rdof]) {
-      for (int w = 0; w < nw - 1; ++w) cw[w] = 0xffffffffu;
-      cw[nw - 1] = 0x00ffffffu | ((uint32_t)lr << 24);
+      cw[0] = 0xffffff00u | (uint32_t)lr;
+      for (int w = 1; w < nw; ++w) cw[w] = 0xffffffffu;
       if (M == 2) ncol[e0 + t] = Nj[Np[2 * i]] / 2;
     } else {
       const int r = e0 + t - rp[i];
       const int a0 = Ap[i], na = Ap[i + 1] - a0;
       const int j = M == 1 ? Nj[Np[i] + r] : Nj[Np[2 * i] + 2 * r] / 2;
       if (M == 2) ncol[e0 + t] = j;
+      uint32_t carry = (uint32_t)lr;  // byte 0 of the next word: the row, then the last code of a pass
       for (int w0 = 0; w0 < nw; w0 += 3) {
         constexpr int U = 12;
         int ks[U], lo[U], hi[U], len[U];
@@ -271,7 +453,7 @@ __global__ __launch_bounds__(RN_BLOCK) void k_plan_codes(int nblk, int32_t *__re
             }
           }
         }
-        uint32_t word[3] = {0u, 0u, 0u};
+        uint32_t word[3] = {carry, 0u, 0u};
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           uint32_t code = CODE_NONE;
@@ -284,10 +466,11 @@ __global__ __launch_bounds__(RN_BLOCK) void k_plan_codes(int nblk, int32_t *__re
             }
             hit += code != CODE_NONE;
           }
-          word[u >> 2] |= code << (8 * (u & 3));
+          // code u of the pass sits at byte u + 1 of the pass's 12 bytes; the last one carries over
+          if (u < U - 1) word[(u + 1) >> 2] |= code << (8 * ((u + 1) & 3));
+          else carry = code;
         }
-        for (int w = w0; w < nw && w < w0 + 3; ++w)
-          cw[w] = w == nw - 1 ? (word[w - w0] & 0x00ffffffu) | ((uint32_t)lr << 24) : word[w - w0];
+        for (int w = w0; w < nw && w < w0 + 3; ++w) cw[w] = word[w - w0];
       }
     }
   }
@@ -413,14 +596,14 @@ extern "C" rn_status rn_plan_create(rn_ctx *ctx, const rn_matrix *A, int32_t n_c
   pl->ncodes = ncodes;
   // the product forms element offsets in 32 bits
   const int64_t lim = (int64_t)1 << 29;
-  if (ncodes >= ((int64_t)1 << 31) || nnz_N >= lim || A->nnz * m * m >= lim || (int64_t)(n + 1) * NP >= lim ||
+  if (ncodes >= ((int64_t)1 << 31) || nnz_N * nB >= lim || A->nnz * m * m >= lim || (int64_t)(n + 1) * NP >= lim ||
       (int64_t)n_cols * nB >= lim)
     return fail(rn_fail(ctx, RN_ELIMIT, "rn_plan_create: pattern or operator too large for 32-bit offsets"));
   // product blocks: every block holds at most 256 entries (node entries for
   // block_m = 2): rows starting in a chunk of 257 - maxlen entries
   const int ml = pl->maxlen < 1 ? 1 : pl->maxlen;
-  pl->bs = (m == 1 && ml <= 32) ? 128 : RN_BLOCK;
-  if (const char *ev = getenv("RNAMG_PRODUCT_BS")) {
+  pl->bs = RN_BLOCK;
+  if (const char *ev = getenv("RNAMG_PRODUCT_BS")) {  // 64- and 128-lane blocks for scalar operators
     const int v = atoi(ev);
     pl->bs = (m == 1 && (v == 64 || v == 128) && ml <= v / 4) ? v : RN_BLOCK;
   }
@@ -432,6 +615,21 @@ extern "C" rn_status rn_plan_create(rn_ctx *ctx, const rn_matrix *A, int32_t n_c
       !plan_alloc(pl, &pl->blk_hdr, (size_t)(pl->nblk + 1) * 8 * sizeof(int32_t)))
     return fail(rn_fail(ctx, RN_ENOMEM, "rn_plan_create: code allocation (%lld bytes)", (long long)ncodes));
   pl->fixed_bytes += (size_t)ncodes + (size_t)(pl->nblk + 1) * 36 + (m == 2 ? (size_t)(pl->nnzN_node + 1) * 4 : 0);
+  const int nunit_max = SPG_XCAP_M1(pl->bs) / XW_UNIT;
+  if (m == 1 && (!plan_alloc(pl, &pl->xl, (size_t)(A->nnz + 1) * sizeof(int32_t)) ||
+                 !plan_alloc(pl, &pl->xwin, (size_t)(pl->nblk + 1) * nunit_max * sizeof(int32_t))))
+    return fail(rn_fail(ctx, RN_ENOMEM, "rn_plan_create: device allocation"));
+  if (m == 1) pl->fixed_bytes += (size_t)(A->nnz + 1) * 4 + (size_t)(pl->nblk + 1) * nunit_max * 4;
+  if (m == 1 && nB <= 2) {
+    if (!plan_alloc(pl, &pl->bce, (size_t)(nnz_N + 1) * nB * sizeof(double)))
+      return fail(rn_fail(ctx, RN_ENOMEM, "rn_plan_create: device allocation"));
+    pl->fixed_bytes += (size_t)(nnz_N + 1) * nB * 8;
+    if (nnz_N > 0) {
+      const unsigned g = rn_div_up(nnz_N, RN_BLOCK);
+      hipLaunchKernelGGL(k_plan_bce, dim3(g > 8192 ? 8192 : g), dim3(RN_BLOCK), 0, ctx->stream, nnz_N, nB, Nj, Bc,
+                         pl->bce);
+    }
+  }
   const int32_t *rp = m == 1 ? Np : pl->nodeptr;
   hipLaunchKernelGGL(k_plan_blocks, dim3(rn_div_up(pl->nblk + 1, RN_BLOCK)), dim3(RN_BLOCK), 0, ctx->stream, nr, m,
                      rp, A->rowptr, is_root, pl->nblk, pl->chunk, pl->blk_row, pl->blk_hdr);
@@ -455,6 +653,21 @@ extern "C" rn_status rn_plan_create(rn_ctx *ctx, const rn_matrix *A, int32_t n_c
                          Nj, is_root, pl->cstride, pl->codes, pl->ncol, blk_hit);
     hipLaunchKernelGGL((k_finish_slots<false, unsigned long long>), dim3(1), dim3(RN_BLOCK), 0, ctx->stream, blk_hit,
                        pl->nblk, pl->d_terms);
+    if (m == 1) {
+      switch (pl->bs) {
+        case 64:
+          hipLaunchKernelGGL(k_plan_xwin<64>, gc, dim3(64), 0, ctx->stream, pl->blk_hdr, A->colind, Np, nnz_N, pl->xl,
+                             pl->xwin);
+          break;
+        case 128:
+          hipLaunchKernelGGL(k_plan_xwin<128>, gc, dim3(128), 0, ctx->stream, pl->blk_hdr, A->colind, Np, nnz_N,
+                             pl->xl, pl->xwin);
+          break;
+        default:
+          hipLaunchKernelGGL(k_plan_xwin<RN_BLOCK>, gc, dim3(RN_BLOCK), 0, ctx->stream, pl->blk_hdr, A->colind, Np,
+                             nnz_N, pl->xl, pl->xwin);
+      }
+    }
     if (hipGetLastError() != hipSuccess) return fail(rn_fail(ctx, RN_EHIP, "launch"));
   }
   try {
@@ -481,7 +694,8 @@ extern "C" void rn_plan_destroy(rn_plan *pl) {
   } else {
     (void)hipDeviceSynchronize();  // its context is gone: wait for any work still reading the plan
   }
-  void *bufs[] = {pl->codes, pl->ncol, pl->nodeptr, pl->gp, pl->d_terms, pl->blk_row, pl->blk_hdr, pl->xoff};
+  void *bufs[] = {pl->codes,   pl->ncol,    pl->nodeptr, pl->gp, pl->d_terms,
+                  pl->blk_row, pl->blk_hdr, pl->xoff,    pl->xl, pl->xwin, pl->bce};
   for (void *b : bufs) rn_dev_free(pl->ctx, b);
   for (int s = 0; s < WS_COUNT; ++s) rn_dev_free(pl->ctx, pl->ws[s].ptr);
   delete pl;

@@ -13,6 +13,7 @@
 // order of A's row.  Per-row sums of the projection go through LDS in
 // pattern order.  Krylov dot products are fused into the epilogue as
 // per-block partials (no inter-block synchronisation).
+#include <cstdlib>
 #include <cstring>
 #include <type_traits>
 
@@ -34,12 +35,17 @@ template <int M, int NB, bool MIXED, int BS>
 struct SpgShape {
   using TV = typename std::conditional<MIXED, float, double>::type;
   static constexpr int NO = M * M;
-  static constexpr int ACAP = (M == 1 ? SPG_ACAP : SPG_ACAP / 2) * BS / RN_BLOCK;  // staged A entries
-  static constexpr int NIT = ACAP / BS;                                          // staging loads per thread
-  static constexpr size_t P1 = (size_t)ACAP * (sizeof(int) * M + NO * sizeof(TV));
+  static constexpr int ACAP = M == 1 ? SPG_ACAP_M1(BS) : SPG_ACAP / 2 * BS / RN_BLOCK;  // staged A entries
+  static constexpr int NIT = (ACAP + BS - 1) / BS;                                    // staging loads per thread
+  static constexpr int XCAP = M == 1 ? SPG_XCAP_M1(BS) : 0;                           // X window elements
+  // block_m = 1, n_B <= 2: the rows' G^+ (read before the projection reuses the buffer)
+  static constexpr size_t PG = (M == 1 && NB <= 2) ? (size_t)BS * (NB * (NB + 1) / 2) * sizeof(double) : 0;
+  static constexpr size_t P1 =
+      (size_t)ACAP * (sizeof(int) * M + NO * sizeof(TV)) + (size_t)XCAP * sizeof(TV) + PG;
   static constexpr size_t P2 = (size_t)M * NB * M * BS * sizeof(double);
-  // + 128 bytes: the register path reads up to 15 entries past a row's start
-  static constexpr size_t BYTES = (P1 > P2 ? P1 : P2) + 128;
+  // block_m = 2: + 128 bytes, the term loop reads up to 15 entries past a row's
+  // start (block_m = 1 over-reads land in the next region of the buffer)
+  static constexpr size_t BYTES = (P1 > P2 ? P1 : P2) + (M == 2 ? 128 : 0);
 };
 
 template <int M, int NB, int MODE, bool MIXED, int BS>
@@ -49,7 +55,7 @@ __global__ __launch_bounds__(BS) void k_spgemm(const SpgParams p) {
   constexpr int NP = NB * (NB + 1) / 2;
   constexpr int NO = M * M;
   constexpr int ACAP = SH::ACAP, NIT = SH::NIT;
-  constexpr int UMAX = 15;  // terms of the register path (records of <= 16 bytes)
+  constexpr int UMAX = 11;  // terms of the register path (records of <= 12 bytes)
   __shared__ int s_rp[BS + 1];   // row starts, relative to the block's first entry
   __shared__ int s_ap[BS + 1];   // row starts in A, relative to the block's first A entry
   __shared__ int s_np0[M == 2 ? BS : 1], s_np1[M == 2 ? BS : 1];
@@ -60,29 +66,69 @@ __global__ __launch_bounds__(BS) void k_spgemm(const SpgParams p) {
   int *s_x0 = (int *)s_buf;
   int *s_x1 = s_x0 + ACAP;  // block_m = 2 only
   TV *s_ax = (TV *)(s_buf + (size_t)ACAP * sizeof(int) * M);
+  TV *s_xw = s_ax + ACAP * NO;  // block_m = 1: the X window
+  double *s_gp = (double *)(s_xw + SH::XCAP);  // block_m = 1, n_B <= 2: the rows' G^+
   // phase 2 view: per-entry projection terms
   double(*s_red)[NB][M * BS] = (double(*)[NB][M * BS])s_buf;
+
+  // block_m = 1 with n_B <= 2: each entry's Bc row comes from the plan and
+  // the rows' G^+ are staged with the rest, so the projection data load in
+  // the first round with everything else
+  constexpr bool PRE = M == 1 && NB <= 2;
+  // block_m = 1: A values and the X window as 32-bit words (contiguous 32-bit
+  // loads cost the vector L1 about a third of 64-bit ones per byte); chunk c
+  // of 64 words holds one window unit of doubles or two of floats
+  constexpr int DPE = sizeof(TV) / 4;
+  constexpr int NITD = M == 1 ? (ACAP * DPE + BS - 1) / BS : 1;
+  constexpr int XIT = M == 1 ? SH::XCAP * DPE / BS : 1;
+  constexpr int NUW = M == 1 ? (DPE == 2 ? XIT : 2 * XIT) : 1;
 
   const int blk = rn_xcd_block(blockIdx.x, p.nblk);
   if (blk < 0) return;
   const int b = blockIdx.y;
-  const int32_t *st = p.st + (int64_t)b * ST_STRIDE;
-  const double *sc = p.scal + (int64_t)b * p.scal_stride;
-  if (MODE == MODE_CG_STEP || MODE == MODE_GM_STEP)
-    if (st[ST_STATUS] || st[ST_DONE]) return;
-  if (p.kact >= 0 && st[ST_ITERS] <= p.kact) return;
-
+  const int t = threadIdx.x;
+  // the header and the window's unit starts depend on the block index only:
+  // they load together, before anything else
   const int4 h0 = ((const int4 *)p.blk_hdr)[2 * blk];
   const int4 h1 = ((const int4 *)p.blk_hdr)[2 * blk + 1];
+  const int wv = __builtin_amdgcn_readfirstlane(t / RN_WAVE);
+  int uwv[NUW];
+  if constexpr (M == 1) {
+    const int32_t *uw = p.xwin + (int64_t)blk * (SH::XCAP / XW_UNIT);
+#pragma unroll
+    for (int i = 0; i < XIT; ++i) {
+      const int c = wv + i * (BS / RN_WAVE);
+      if (DPE == 2) {
+        uwv[i] = uw[c];
+      } else {
+        uwv[2 * i] = uw[2 * c];
+        uwv[2 * i + 1] = uw[2 * c + 1];
+      }
+    }
+  }
+  const int32_t *st = p.st + (int64_t)b * ST_STRIDE;
+  const double *sc = p.scal + (int64_t)b * p.scal_stride;
+  const int st_stop = (MODE == MODE_CG_STEP || MODE == MODE_GM_STEP) ? (st[ST_STATUS] | st[ST_DONE]) : 0;
+  const int st_iters = st[ST_ITERS];
+  {
+    // all of these arrive before the exit test (one wait for the lot)
+    int all = h0.x | h1.w | st_stop | st_iters;
+#pragma unroll
+    for (int i = 0; i < NUW; ++i) all |= M == 1 ? uwv[i] : 0;
+    asm volatile("" ::"s"(all));
+  }
+  if (st_stop) return;
+  if (p.kact >= 0 && st_iters <= p.kact) return;
   const int r0 = h0.x, nrows = h0.y - h0.x, e0 = h0.z, ne = h0.w - h0.z;
   const int aB = h1.x, naB = h1.y - h1.x, namax = h1.z;
   const bool staged = naB <= ACAP;
+  const int nunit = M == 1 ? h1.w : 0;  // X window units (the plan keeps naB <= ACAP for these)
+  const bool win = nunit > 0;
   const TV *Ax = (const TV *)p.Ax + (int64_t)b * p.strideA;
   const TV *X = (const TV *)p.X + (int64_t)b * p.strideX;
   const int64_t zb = (int64_t)b * p.strideZ;
   double *Z = p.Z + zb;
   const int32_t *rp = (M == 1) ? p.Np : p.nodeptr;
-  const int t = threadIdx.x;
   const bool valid = t < ne;
   const bool proj = (MODE != MODE_PRODUCT) || p.project;
   const uint32_t *codes = (const uint32_t *)p.codes;
@@ -90,28 +136,25 @@ __global__ __launch_bounds__(BS) void k_spgemm(const SpgParams p) {
   // ---- one round of loads that depend on the header only ----
   // Straight-line code with clamped, always in-bounds indices, so every load
   // is issued before the first wait (a block has >= 1 entry and >= 1 row).
-  // The lane's record: its codes, then CODE_NONE padding, and in the last
-  // byte its row within the block; the code array carries 16 bytes of slack.
+  // The lane's record: byte 0 its row within the block, code u in byte u + 1,
+  // CODE_NONE padding.  Words 0..2 load as one vector whatever the stride
+  // (the code array carries 16 bytes of slack); longer records read the rest
+  // in the term loop.
   const int nw = p.cstride >> 2;
   const int te = valid ? t : 0;
   const uint32_t rec = (uint32_t)(e0 + te) * (uint32_t)nw;
-  // records of up to 12 bytes load as one vector (one cache access per line)
-  uint32_t w0, w1, w2, w3;
-  if (nw <= 3) {
-    const uint3 r3 = *(const uint3 *)((const char *)codes + rec * 4u);  // 4-byte aligned
-    w0 = r3.x;
-    w1 = r3.y;
-    w2 = r3.z;
-    w3 = 0xffffffffu;
-  } else {
-    w0 = spg_ld(codes, rec);
-    w1 = spg_ld(codes, rec + 1);
-    w2 = spg_ld(codes, rec + 2);
-    w3 = spg_ld(codes, rec + 3);
-  }
-  const uint32_t wl = nw == 1 ? w0 : nw == 2 ? w1 : nw == 3 ? w2 : nw == 4 ? w3 : spg_ld(codes, rec + nw - 1);
+  const uint3 r3 = *(const uint3 *)((const char *)codes + rec * 4u);  // 4-byte aligned
+  const uint32_t w0 = r3.x, w1 = r3.y, w2 = r3.z;
   int jc0 = 0;
-  if (proj) jc0 = (M == 1) ? spg_ld(p.Nj, (uint32_t)(e0 + te)) : spg_ld(p.ncol, (uint32_t)(e0 + te));
+  double bcv[PRE ? NB : 1], v_gp[PRE ? NP : 1];
+  if (PRE) {
+    if (proj) {
+#pragma unroll
+      for (int q = 0; q < NB; ++q) bcv[q] = spg_ld(p.bce, (uint32_t)(e0 + te) * NB + q);
+    }
+  } else if (proj) {
+    jc0 = (M == 1) ? spg_ld(p.Nj, (uint32_t)(e0 + te)) : spg_ld(p.ncol, (uint32_t)(e0 + te));
+  }
   double ownv[NO];
 #pragma unroll
   for (int o = 0; o < NO; ++o) ownv[o] = 0.0;
@@ -123,6 +166,10 @@ __global__ __launch_bounds__(BS) void k_spgemm(const SpgParams p) {
   const int v_rp = spg_ld(rp, (uint32_t)(r0 + rt));
   const int v_ap = spg_ld(p.Ap, (uint32_t)(r0 + rt));
   const uint8_t v_root = spg_ld(p.is_root, (uint32_t)((M == 1) ? r0 + rq : 2 * (r0 + rq)));
+  if (PRE && proj) {
+#pragma unroll
+    for (int q = 0; q < NP; ++q) v_gp[q] = spg_ld(p.gp, (uint32_t)(r0 + rq) * NP + q);
+  }
   int v_np0 = 0, v_np1 = 0;
   if constexpr (M == 2) {
     v_np0 = spg_ld(p.Np, (uint32_t)(2 * (r0 + rq)));
@@ -131,7 +178,37 @@ __global__ __launch_bounds__(BS) void k_spgemm(const SpgParams p) {
   // the block's slice of A
   int v_x0[NIT], v_x1[NIT];
   TV v_ax[NIT][NO];
-  if (staged && naB > 0) {
+  uint32_t v_ad[NITD], v_xw[XIT];
+  if (M == 1 && staged && naB > 0) {
+    const int32_t *xsrc = win ? p.xl : p.xoff;
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+      v_x0[it] = 0;
+      if (it * BS < naB) v_x0[it] = spg_ld(xsrc, (uint32_t)(aB + (t + it * BS < naB ? t + it * BS : naB - 1)));
+    }
+    const uint32_t *Axd = (const uint32_t *)Ax;
+    const int nd = naB * DPE;
+#pragma unroll
+    for (int it = 0; it < NITD; ++it) {
+      v_ad[it] = 0;
+      if (it * BS < nd) v_ad[it] = spg_ld(Axd, (uint32_t)(aB * DPE + (t + it * BS < nd ? t + it * BS : nd - 1)));
+    }
+    if (win) {
+      const int lane = t & (RN_WAVE - 1);
+      const uint32_t *Xd = (const uint32_t *)X;
+#pragma unroll
+      for (int i = 0; i < XIT; ++i) {
+        const int c = wv + i * (BS / RN_WAVE);
+        v_xw[i] = 0;
+        if (DPE == 2) {
+          if (c < nunit) v_xw[i] = spg_ld(Xd, (uint32_t)(2 * uwv[i] + lane));
+        } else if (2 * c < nunit) {
+          const int u0 = uwv[2 * i], u1 = 2 * c + 1 < nunit ? uwv[2 * i + 1] : u0;
+          v_xw[i] = spg_ld(Xd, (uint32_t)((lane < 32 ? u0 : u1) + (lane & 31)));
+        }
+      }
+    }
+  } else if (staged && naB > 0) {
 #pragma unroll
     for (int it = 0; it < NIT; ++it) {
       v_x0[it] = 0;
@@ -158,16 +235,36 @@ __global__ __launch_bounds__(BS) void k_spgemm(const SpgParams p) {
   }
   if (t < nrows) {
     s_root[t] = v_root;
+    if (PRE && proj)
+#pragma unroll
+      for (int q = 0; q < NP; ++q) s_gp[t * NP + q] = v_gp[q];
     if constexpr (M == 2) {
       s_np0[t] = v_np0;
       s_np1[t] = v_np1;
     }
   }
-  if (nrows == BS && t == 0) {
-    s_rp[BS] = rp[r0 + BS] - e0;
-    s_ap[BS] = p.Ap[r0 + BS] - aB;
+  if (nrows == BS && t == 0) {  // the end of the last row is in the header
+    s_rp[BS] = ne;
+    s_ap[BS] = naB;
   }
-  if (staged && naB > 0) {
+  if (M == 1 && staged && naB > 0) {
+#pragma unroll
+    for (int it = 0; it < NIT; ++it)
+      if (t + it * BS < naB) s_x0[t + it * BS] = v_x0[it];
+    uint32_t *s_ad = (uint32_t *)s_ax;
+#pragma unroll
+    for (int it = 0; it < NITD; ++it)
+      if (t + it * BS < naB * DPE) s_ad[t + it * BS] = v_ad[it];
+    if (win) {
+      uint32_t *s_xd = (uint32_t *)s_xw;
+      const int wv = t / RN_WAVE, lane = t & (RN_WAVE - 1);
+#pragma unroll
+      for (int i = 0; i < XIT; ++i) {
+        const int c = wv + i * (BS / RN_WAVE);
+        if (c * 64 < nunit * XW_UNIT * DPE) s_xd[c * 64 + lane] = v_xw[i];
+      }
+    }
+  } else if (staged && naB > 0) {
 #pragma unroll
     for (int it = 0; it < NIT; ++it) {
       const int q = t + it * BS;
@@ -197,12 +294,17 @@ __global__ __launch_bounds__(BS) void k_spgemm(const SpgParams p) {
     z[o] = 0.0;
     zi[o] = -1;
   }
-  const int lrow = valid ? (int)(wl >> 24) : 0;
+  const int lrow = valid ? (int)(w0 & 0xffu) : 0;
   const bool froot = !valid || s_root[lrow];
   if (valid) {
     const int la = s_ap[lrow];
     const int r = t - s_rp[lrow];
-    if (proj) {  // root lanes load too (their row and column are in range): no branch
+    if (PRE && proj) {
+#pragma unroll
+      for (int q = 0; q < NP; ++q) gq[0][q] = s_gp[lrow * NP + q];
+#pragma unroll
+      for (int q = 0; q < NB; ++q) bc[0][q] = bcv[q];
+    } else if (proj) {  // root lanes load too (their row and column are in range): no branch
 #pragma unroll
       for (int c = 0; c < M; ++c) {
         const uint32_t grow = (M == 1) ? (uint32_t)(r0 + lrow) : (uint32_t)(2 * (r0 + lrow) + c);
@@ -214,45 +316,70 @@ __global__ __launch_bounds__(BS) void k_spgemm(const SpgParams p) {
     }
     if constexpr (M == 1) {
       zi[0] = e0 + t;
-      if (!froot && staged && nw <= 4) {
+      if (!froot && staged && nw <= 3) {
         // every X load of the row issued before the first multiply-add; the
         // term count is the block's longest row (uniform), a miss (codes past
         // a row's length are CODE_NONE) loads X[0]
-        TV xv[UMAX];
+        // Branch-free within the three code words (terms 0-2, 3-6, 7-10; a
+        // word is skipped when the block's rows are shorter): all index reads,
+        // then all X reads, then the multiply-adds in the order of A's row.
+        // A miss (or a term past the row) reads element 0 and adds nothing.
+        TV xv[UMAX], av[UMAX];
+        uint32_t xi[UMAX];
         uint32_t hitm = 0;
+        const bool g1 = namax > 3, g2 = namax > 7;
+        auto index = [&](const int lo, const int hi, const uint32_t w) {
+#pragma unroll
+          for (int u = lo; u < hi; ++u) {
+            const uint32_t c = __builtin_amdgcn_ubfe(w, 8 * ((u + 1) & 3), 8);
+            const uint32_t hm = (c != CODE_NONE && u < namax) ? 0xffffffffu : 0u;
+            hitm |= hm & (1u << u);
+            av[u] = s_ax[la + u];
+            xi[u] = ((uint32_t)s_x0[la + u] + c) & hm;
+          }
+        };
+        auto gather = [&](const int lo, const int hi) {
+#pragma unroll
+          for (int u = lo; u < hi; ++u) xv[u] = win ? s_xw[xi[u]] : spg_ld(X, xi[u]);
+        };
 #pragma unroll
         for (int u = 0; u < UMAX; ++u) {
           xv[u] = 0;
-          if (u < namax) {  // uniform
-            const uint32_t w = u < 4 ? w0 : (u < 8 ? w1 : (u < 12 ? w2 : w3));
-            const uint32_t c = __builtin_amdgcn_ubfe(w, 8 * (u & 3), 8);
-            const bool hit = c != CODE_NONE;
-            hitm |= (uint32_t)hit << u;
-            xv[u] = spg_ld(X, hit ? (uint32_t)s_x0[la + u] + c : 0u);
-          }
+          av[u] = 0;
+        }
+        index(0, 3, w0);
+        if (g1) index(3, 7, w1);
+        if (g2) index(7, 11, w2);
+        if (win) {  // uniform: X from the block's window in LDS, or from global memory
+          gather(0, 3);
+          if (g1) gather(3, 7);
+          if (g2) gather(7, 11);
+        } else {
+          gather(0, 3);
+          if (g1) gather(3, 7);
+          if (g2) gather(7, 11);
         }
         TV acc = 0;
 #pragma unroll
-        for (int u = 0; u < UMAX; ++u)
-          if (u < namax) acc += ((hitm >> u) & 1u) ? s_ax[la + u] * xv[u] : TV(0);
+        for (int u = 0; u < UMAX; ++u) {
+          const TV pr = av[u] * xv[u];
+          acc += ((hitm >> u) & 1u) ? pr : TV(0);
+        }
         z[0] = (double)acc;
       } else if (!froot) {
         const int na = s_ap[lrow + 1] - la;
         TV acc = 0;
-        for (int t0 = 0; t0 < na; t0 += 4) {
-          const uint32_t w = spg_ld(codes, rec + (t0 >> 2));
-#pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const int tt = t0 + u;
-            if (tt < na) {
-              const uint32_t c = (w >> (8 * u)) & 0xffu;
-              const bool hit = c != CODE_NONE;
-              const TV a = staged ? s_ax[la + tt] : Ax[aB + la + tt];
-              TV x = 0;
-              if (hit) x = X[(staged ? s_x0[la + tt] : p.xoff[aB + la + tt]) + (int)c];
-              acc += hit ? a * x : TV(0);
-            }
-          }
+        uint32_t w = w0;
+        for (int tt = 0; tt < na; ++tt) {
+          const int pb = tt + 1;  // byte of the code in the record
+          if ((pb & 3) == 0) w = pb == 4 ? w1 : (pb == 8 ? w2 : spg_ld(codes, rec + (pb >> 2)));
+          const uint32_t c = (w >> (8 * (pb & 3))) & 0xffu;
+          const bool hit = c != CODE_NONE;
+          const TV a = staged ? s_ax[la + tt] : Ax[aB + la + tt];
+          TV x = 0;
+          if (hit)
+            x = win ? s_xw[s_x0[la + tt] + (int)c] : X[(staged ? s_x0[la + tt] : p.xoff[aB + la + tt]) + (int)c];
+          acc += hit ? a * x : TV(0);
         }
         z[0] = (double)acc;
       }
@@ -274,14 +401,13 @@ __global__ __launch_bounds__(BS) void k_spgemm(const SpgParams p) {
       if (!froot) {
         const int na = s_ap[lrow + 1] - la;
         TV z00 = 0, z01 = 0, z10 = 0, z11 = 0;
-        for (int t0 = 0; t0 < na; t0 += 4) {
-          const uint32_t w = nw <= 4 ? (t0 == 0 ? w0 : (t0 == 4 ? w1 : (t0 == 8 ? w2 : w3)))
-                                     : spg_ld(codes, rec + (t0 >> 2));
-#pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const int tt = t0 + u;
-            const uint32_t c = (w >> (8 * u)) & 0xffu;
-            if (tt >= na || c == CODE_NONE) continue;  // the record's last byte is no code
+        uint32_t w = w0;
+        for (int tt = 0; tt < na; ++tt) {
+          const int pb = tt + 1;  // byte of the code in the record
+          if ((pb & 3) == 0) w = pb == 4 ? w1 : (pb == 8 ? w2 : spg_ld(codes, rec + (pb >> 2)));
+          {
+            const uint32_t c = (w >> (8 * (pb & 3))) & 0xffu;
+            if (c == CODE_NONE) continue;
             int x0, x1;
             const TV *a;
             if (staged) {
@@ -421,8 +547,403 @@ __global__ __launch_bounds__(BS) void k_spgemm(const SpgParams p) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Persistent form for scalar operators (block_m = 1, n_B <= 2, records of at
+// most 12 bytes).  G resident workgroups (a multiple of 8) walk the product
+// blocks of their XCD's range with stride G/8.  While one block is computed
+// from LDS, the header, window table and first-round loads of the next block
+// are in flight, so a block costs its LDS work instead of its chain of memory
+// round trips, and the grid drains in one generation.  Same arithmetic, same
+// order and same per-block partials as k_spgemm.
+// ---------------------------------------------------------------------------
+template <int NB, int MODE, bool MIXED, int BS>
+__global__ __launch_bounds__(BS) void k_spgemm_p(const SpgParams p, const int G) {
+  using SH = SpgShape<1, NB, MIXED, BS>;
+  using TV = typename SH::TV;
+  constexpr int NP = NB * (NB + 1) / 2;
+  constexpr int ACAP = SH::ACAP, NIT = SH::NIT, XCAP = SH::XCAP;
+  constexpr int DPE = sizeof(TV) / 4;
+  constexpr int NITD = (ACAP * DPE + BS - 1) / BS;
+  constexpr int XIT = XCAP * DPE / BS;
+  constexpr int NUW = DPE == 2 ? XIT : 2 * XIT;
+  constexpr int NU = XCAP / XW_UNIT;
+  constexpr int NWV = BS / RN_WAVE;
+  constexpr int UMAX = 11;
+  static_assert(NIT * BS == ACAP && NITD * BS == ACAP * DPE, "staging covers the capacity exactly");
+  __shared__ int s_rp[BS + 1];
+  __shared__ int s_ap[BS + 1];
+  __shared__ double s_w[8];
+  __shared__ __align__(16) unsigned char s_buf[SH::BYTES];
+  int *s_x0 = (int *)s_buf;
+  TV *s_ax = (TV *)(s_buf + (size_t)ACAP * sizeof(int));
+  TV *s_xw = s_ax + ACAP;
+  double *s_gp = (double *)(s_xw + XCAP);
+  double(*s_red)[BS] = (double(*)[BS])s_buf;  // projection terms (phase 2)
+
+  const int b = blockIdx.y, t = threadIdx.x, lane = t & (RN_WAVE - 1);
+  const int wv = __builtin_amdgcn_readfirstlane(t / RN_WAVE);
+  const int32_t *st = p.st + (int64_t)b * ST_STRIDE;
+  const double *sc = p.scal + (int64_t)b * p.scal_stride;
+  if (MODE == MODE_CG_STEP || MODE == MODE_GM_STEP)
+    if (st[ST_STATUS] || st[ST_DONE]) return;
+  if (p.kact >= 0 && st[ST_ITERS] <= p.kact) return;
+  const int per = (p.nblk + 7) >> 3, Gx = G >> 3;
+  const int xcd = blockIdx.x & 7;
+  const int hiB = min(p.nblk, (xcd + 1) * per);
+  int blk = xcd * per + (int)(blockIdx.x >> 3);
+  if (blk >= hiB) return;
+
+  const bool proj = (MODE != MODE_PRODUCT) || p.project;
+  const TV *Ax = (const TV *)p.Ax + (int64_t)b * p.strideA;
+  const TV *X = (const TV *)p.X + (int64_t)b * p.strideX;
+  const int64_t zb = (int64_t)b * p.strideZ;
+  double *Z = p.Z + zb;
+  const uint32_t *codes = (const uint32_t *)p.codes;
+  const uint32_t nw = (uint32_t)(p.cstride >> 2);
+  double *part = p.part + (int64_t)b * RN_MAXDOT * p.nblk;
+
+  // ---- a block's header and window unit starts: loaded (as uniform vector
+  // loads) two blocks ahead, read into scalars once they have arrived ----
+  struct HdV {
+    int4 h0, h1;
+    int uw[NUW];
+  };
+  struct Hd {
+    int r0, nrows, e0, ne, aB, naB, namax, nunit;
+    int uw[NUW];
+  };
+  // buffer loads: always vector-memory instructions (a plain load may become
+  // a scalar one where no store precedes it, and the wait counts of the
+  // pipeline then differ between the first iteration and the others)
+  typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+  const __amdgpu_buffer_rsrc_t rs_h =
+      __builtin_amdgcn_make_buffer_rsrc((void *)p.blk_hdr, (short)0, (p.nblk + 1) * 32, 0x00020000);
+  const __amdgpu_buffer_rsrc_t rs_u =
+      __builtin_amdgcn_make_buffer_rsrc((void *)p.xwin, (short)0, (p.nblk + 1) * NU * 4, 0x00020000);
+  auto load_hdv = [&](const int bb, HdV &v) {
+    const u32x4 a0 = __builtin_amdgcn_raw_buffer_load_b128(rs_h, 0, bb * 32, 0);
+    const u32x4 a1 = __builtin_amdgcn_raw_buffer_load_b128(rs_h, 0, bb * 32 + 16, 0);
+    v.h0 = make_int4((int)a0.x, (int)a0.y, (int)a0.z, (int)a0.w);
+    v.h1 = make_int4((int)a1.x, (int)a1.y, (int)a1.z, (int)a1.w);
+#pragma unroll
+    for (int i = 0; i < XIT; ++i) {
+      const int c = wv + i * NWV;
+      if (DPE == 2) {
+        v.uw[i] = (int)__builtin_amdgcn_raw_buffer_load_b32(rs_u, 0, (bb * NU + c) * 4, 0);
+      } else {
+        v.uw[2 * i] = (int)__builtin_amdgcn_raw_buffer_load_b32(rs_u, 0, (bb * NU + 2 * c) * 4, 0);
+        v.uw[2 * i + 1] = (int)__builtin_amdgcn_raw_buffer_load_b32(rs_u, 0, (bb * NU + 2 * c + 1) * 4, 0);
+      }
+    }
+  };
+  auto to_hd = [&](const HdV &v, Hd &h) {
+    const int r0 = __builtin_amdgcn_readfirstlane(v.h0.x), r1 = __builtin_amdgcn_readfirstlane(v.h0.y);
+    const int e0 = __builtin_amdgcn_readfirstlane(v.h0.z), e1 = __builtin_amdgcn_readfirstlane(v.h0.w);
+    const int a0 = __builtin_amdgcn_readfirstlane(v.h1.x), a1 = __builtin_amdgcn_readfirstlane(v.h1.y);
+    h.r0 = r0;
+    h.nrows = r1 - r0;
+    h.e0 = e0;
+    h.ne = e1 - e0;
+    h.aB = a0;
+    h.naB = a1 - a0;
+    h.namax = __builtin_amdgcn_readfirstlane(v.h1.z);
+    h.nunit = __builtin_amdgcn_readfirstlane(v.h1.w);
+#pragma unroll
+    for (int i = 0; i < NUW; ++i) h.uw[i] = __builtin_amdgcn_readfirstlane(v.uw[i]);
+  };
+  // ---- a block's first round of vector loads (registers) ----
+  struct Rd {
+    uint32_t w0, w1, w2;
+    double bcv[NB], gp[NP], own;
+    int rp, ap;
+    int x0[NIT];
+    uint32_t ad[NITD], xw[XIT];
+  };
+  auto load_rd = [&](const Hd &h, Rd &r) {
+    const int te = t < h.ne ? t : 0;
+    const uint32_t e = (uint32_t)(h.e0 + te);
+    const uint3 r3 = *(const uint3 *)((const char *)codes + e * nw * 4u);  // 16 bytes of slack
+    r.w0 = r3.x;
+    r.w1 = r3.y;
+    r.w2 = r3.z;
+    r.own = 0.0;
+    if (MODE == MODE_CG_STEP) r.own = spg_ld(p.Xown + zb, e);
+    const int rq = t < h.nrows ? t : h.nrows - 1, rt = t < h.nrows ? t : h.nrows;
+    r.rp = spg_ld(p.Np, (uint32_t)(h.r0 + rt));
+    r.ap = spg_ld(p.Ap, (uint32_t)(h.r0 + rt));
+#pragma unroll
+    for (int q = 0; q < NB; ++q) r.bcv[q] = 0.0;
+#pragma unroll
+    for (int q = 0; q < NP; ++q) r.gp[q] = 0.0;
+    if (proj) {
+#pragma unroll
+      for (int q = 0; q < NB; ++q) r.bcv[q] = spg_ld(p.bce, e * NB + q);
+#pragma unroll
+      for (int q = 0; q < NP; ++q) r.gp[q] = spg_ld(p.gp, (uint32_t)(h.r0 + rq) * NP + q);
+    }
+    // Branch-free: every load is issued whatever the block's sizes (indices
+    // clamped into the block's slice; the plan writes every window-table
+    // entry, unused ones point at element 0), so no register of an earlier
+    // round is waited for while this one is issued.
+    {
+      // a block without A entries reads the last one
+      const int nA = h.naB > 0 ? h.naB : 1;
+      const int a0 = h.naB > 0 ? h.aB : (int)p.strideA - 1;
+      const int32_t *xsrc = h.nunit > 0 ? p.xl : p.xoff;
+#pragma unroll
+      for (int it = 0; it < NIT; ++it) r.x0[it] = spg_ld(xsrc, (uint32_t)(a0 + min(t + it * BS, nA - 1)));
+      const uint32_t *Axd = (const uint32_t *)Ax;
+      const int nd = nA * DPE;
+#pragma unroll
+      for (int it = 0; it < NITD; ++it)
+        r.ad[it] = spg_ld(Axd, (uint32_t)(a0 * DPE + min(t + it * BS, nd - 1)));
+      const uint32_t *Xd = (const uint32_t *)X;
+#pragma unroll
+      for (int i = 0; i < XIT; ++i) {
+        if (DPE == 2) {
+          r.xw[i] = spg_ld(Xd, (uint32_t)(2 * h.uw[i] + lane));
+        } else {
+          r.xw[i] = spg_ld(Xd, (uint32_t)((lane < 32 ? h.uw[2 * i] : h.uw[2 * i + 1]) + (lane & 31)));
+        }
+      }
+    }
+  };
+  // ---- registers -> LDS (every position written is inside its region) ----
+  auto stage = [&](const Hd &h, const Rd &r) {
+    if (t <= h.nrows) {
+      s_rp[t] = r.rp - h.e0;
+      s_ap[t] = r.ap - h.aB;
+    }
+    if (h.nrows == BS && t == 0) {  // the end of the last row is in the header
+      s_rp[BS] = h.ne;
+      s_ap[BS] = h.naB;
+    }
+    if (proj && t < h.nrows)
+#pragma unroll
+      for (int q = 0; q < NP; ++q) s_gp[t * NP + q] = r.gp[q];
+    if (h.naB <= ACAP && h.naB > 0) {
+#pragma unroll
+      for (int it = 0; it < NIT; ++it) s_x0[t + it * BS] = r.x0[it];
+      uint32_t *s_ad = (uint32_t *)s_ax;
+#pragma unroll
+      for (int it = 0; it < NITD; ++it) s_ad[t + it * BS] = r.ad[it];
+      if (h.nunit > 0) {
+        uint32_t *s_xd = (uint32_t *)s_xw;
+#pragma unroll
+        for (int i = 0; i < XIT; ++i) s_xd[(wv + i * NWV) * 64 + lane] = r.xw[i];
+      }
+    }
+  };
+
+  // pipeline: at the top of an iteration the block's first round (R) and the
+  // next block's header (V1) are in flight; after staging R the next block's
+  // first round (Rn) and then the header after that (V2) are issued, so a
+  // wait for an Rn register never waits for V2
+  Hd H;
+  Rd R;
+  HdV V1;
+  {
+    HdV V0;
+    load_hdv(blk, V0);
+    to_hd(V0, H);
+  }
+  load_rd(H, R);  // same issue order as in the loop: first round, then the next header
+  // (unconditional, clamped: the wait counts then agree on every path)
+  load_hdv(min(blk + Gx, hiB - 1), V1);
+  for (;;) {
+    const int nxt = blk + Gx;
+    const bool more = nxt < hiB;
+    stage(H, R);
+    __syncthreads();
+    Hd Hn;
+    Rd Rn;
+    HdV V2;
+    if (more) {
+      to_hd(V1, Hn);
+      load_rd(Hn, Rn);  // in flight while this block is computed
+      load_hdv(min(nxt + Gx, hiB - 1), V2);
+    }
+
+    // ---- the product from LDS (root rows: every code is CODE_NONE, z = 0) ----
+    const bool valid = t < H.ne;
+    const bool staged = H.naB <= ACAP, win = H.nunit > 0;
+    const int lrow = valid ? (int)(R.w0 & 0xffu) : 0;
+    double z = 0.0;
+    double gq[NP];
+#pragma unroll
+    for (int q = 0; q < NP; ++q) gq[q] = 0.0;
+    if (valid) {
+      const int la = s_ap[lrow];
+      if (proj)
+#pragma unroll
+        for (int q = 0; q < NP; ++q) gq[q] = s_gp[lrow * NP + q];
+      const bool g1 = H.namax > 3, g2 = H.namax > 7;
+      TV acc = 0;
+      // one code word (terms lo..hi-1): offsets, then A and X, then the
+      // multiply-adds in the order of A's row; A past the block's slice and X
+      // element 0 only meet masked terms.  Separate paths keep every LDS
+      // access an LDS instruction (a generic access would also wait for the
+      // next block's loads in flight).
+      auto word = [&](const int lo, const int hi, const uint32_t w, const int path) {
+        uint32_t xi[4], hm[4];
+        TV av[4], xv[4];
+#pragma unroll
+        for (int u = lo; u < hi; ++u) {
+          const uint32_t c = __builtin_amdgcn_ubfe(w, 8 * ((u + 1) & 3), 8);
+          hm[u - lo] = (c != CODE_NONE && u < H.namax) ? 0xffffffffu : 0u;
+          const uint32_t xo =
+              path < 2 ? (uint32_t)s_x0[la + u] : (uint32_t)p.xoff[H.aB + min(la + u, H.naB - 1)];
+          xi[u - lo] = (xo + c) & hm[u - lo];
+        }
+#pragma unroll
+        for (int u = lo; u < hi; ++u) {
+          if (path < 2) av[u - lo] = s_ax[la + u];
+          else av[u - lo] = Ax[H.aB + min(la + u, H.naB - 1)];
+          if (path == 0) xv[u - lo] = s_xw[xi[u - lo]];
+          else xv[u - lo] = spg_ld(X, xi[u - lo]);
+        }
+#pragma unroll
+        for (int u = lo; u < hi; ++u) {
+          const TV pr = av[u - lo] * xv[u - lo];
+          acc += hm[u - lo] ? pr : TV(0);
+        }
+      };
+      if (staged && win) {
+        word(0, 3, R.w0, 0);
+        if (g1) word(3, 7, R.w1, 0);
+        if (g2) word(7, 11, R.w2, 0);
+      } else if (staged) {
+        word(0, 3, R.w0, 1);
+        if (g1) word(3, 7, R.w1, 1);
+        if (g2) word(7, 11, R.w2, 1);
+      } else {
+        word(0, 3, R.w0, 2);
+        if (g1) word(3, 7, R.w1, 2);
+        if (g2) word(7, 11, R.w2, 2);
+      }
+      z = (double)acc;
+      if (MODE == MODE_GM_STEP) z *= sc[GmLayout(p.K).s + p.k];
+    }
+
+    // ---- projection: every lane sums its row's terms in pattern order ----
+    if (proj) {
+      __syncthreads();  // phase-1 LDS is reused
+      if (valid)
+#pragma unroll
+        for (int q = 0; q < NB; ++q) s_red[q][t] = z * R.bcv[q];
+      __syncthreads();
+      if (valid) {
+        const int rs = s_rp[lrow], re = s_rp[lrow + 1];
+        double sv[NB];
+#pragma unroll
+        for (int q = 0; q < NB; ++q) sv[q] = 0.0;
+        for (int u = rs; u < re; ++u)
+#pragma unroll
+          for (int q = 0; q < NB; ++q) sv[q] += s_red[q][u];
+        double y[NB];
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+          y[q] = 0.0;
+#pragma unroll
+          for (int r2 = 0; r2 < NB; ++r2) y[q] += gq[rn_pk(NB, q, r2)] * sv[r2];
+        }
+        double u = 0.0;
+#pragma unroll
+        for (int q = 0; q < NB; ++q) u += R.bcv[q] * y[q];
+        z -= u;
+      }
+    }
+
+    // ---- epilogue: output and this block's partials ----
+    const uint32_t e = (uint32_t)(H.e0 + t);
+    if (MODE == MODE_PRODUCT) {
+      if (valid) spg_st(Z, e, p.accum ? spg_ld((const double *)Z, e) + z : z);
+    } else if (MODE == MODE_CG_INIT || MODE == MODE_GM_INIT) {
+      RnAcc d;
+      if (valid) {
+        const double v = -z;
+        spg_st(Z, e, v);
+        if (p.Z2) spg_st(p.Z2 + zb, e, v);
+        d.add(v * v);
+      }
+      const double S = rn_block_sum2_w<NWV>(d.hi, d.lo, s_w);
+      if (t == 0) part[blk] = S;
+    } else if (MODE == MODE_CG_STEP) {
+      RnAcc d;
+      if (valid) {
+        spg_st(Z, e, z);
+        d.add(R.own * z);
+      }
+      const double S = rn_block_sum2_w<NWV>(d.hi, d.lo, s_w);
+      if (t == 0) part[blk] = S;
+    } else if (MODE == MODE_GM_STEP) {
+      if (valid) spg_st(Z, e, z);
+      const double *U = p.U + (int64_t)b * p.Ubatch;
+      for (int j = 0; j <= p.k; ++j) {
+        RnAcc d;
+        if (valid) d.add(spg_ld(U + (int64_t)j * p.nnzN, e) * z);
+        const double S = rn_block_sum2_w<NWV>(d.hi, d.lo, s_w);
+        if (t == 0) part[(int64_t)j * p.nblk + blk] = S;
+      }
+    }
+    if (!more) break;
+    __syncthreads();  // every LDS read of this block is done before the next staging
+    blk = nxt;
+    H = Hn;
+    R = Rn;
+    V1 = V2;
+  }
+}
+
+// resident workgroups of one persistent launch: the occupancy of the kernel
+// times the number of compute units, split over the batch, a multiple of 8
+template <int NB, int MODE, bool MIXED, int BS>
+static int persist_grid(int nblk, int batch) {
+  static int cap = -1;
+  if (cap < 0) {
+    int per_cu = 0, dev = 0, ncu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_spgemm_p<NB, MODE, MIXED, BS>, BS, 0) != hipSuccess ||
+        hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      per_cu = 0;
+    cap = per_cu * ncu;
+  }
+  int g = cap / (batch > 0 ? batch : 1);
+  g = g / 8 * 8;
+  const int full = (int)rn_xcd_grid((unsigned)nblk);
+  if (g > full) g = full;
+  return g;
+}
+
+template <int NB, int MODE, int BS>
+static bool launch_p(const SpgParams &p, int batch, bool mixed, hipStream_t s) {
+  const int G = mixed ? persist_grid<NB, MODE, true, BS>(p.nblk, batch) : persist_grid<NB, MODE, false, BS>(p.nblk, batch);
+  if (G < 8) return false;
+  const dim3 grid((unsigned)G, (unsigned)batch);
+  if (mixed) hipLaunchKernelGGL((k_spgemm_p<NB, MODE, true, BS>), grid, dim3(BS), 0, s, p, G);
+  else hipLaunchKernelGGL((k_spgemm_p<NB, MODE, false, BS>), grid, dim3(BS), 0, s, p, G);
+  return true;
+}
+
+// the persistent form serves scalar operators with n_B <= 2 and records of at
+// most 12 bytes (RNAMG_PERSIST=0 turns it off)
+static bool persist_on() {
+  static const int on = [] {
+    const char *e = getenv("RNAMG_PERSIST");
+    return (e && e[0] == '0') ? 0 : 1;
+  }();
+  return on != 0;
+}
+
 template <int M, int NB, int MODE>
 static void launch_m(const SpgParams &p, int batch, bool mixed, hipStream_t s) {
+  if constexpr (M == 1 && NB <= 2) {
+    // (the branch-free first round reads 32 elements of X and one of A whatever the block)
+    if (p.cstride <= 12 && p.nnzN >= 64 && p.strideA >= 1 && persist_on()) {
+      if (p.bs == 128 && launch_p<NB, MODE, 128>(p, batch, mixed, s)) return;
+      if (p.bs == RN_BLOCK && launch_p<NB, MODE, RN_BLOCK>(p, batch, mixed, s)) return;
+    }
+  }
   const dim3 grid(rn_xcd_grid((unsigned)p.nblk), (unsigned)batch);
   if (M == 1 && p.bs == 128) {
     if (mixed) hipLaunchKernelGGL((k_spgemm<M, NB, MODE, true, 128>), grid, dim3(128), 0, s, p);
@@ -490,6 +1011,9 @@ SpgParams rn_spg_params(const rn_plan *pl) {
   p.blk_row = pl->blk_row;
   p.blk_hdr = pl->blk_hdr;
   p.xoff = pl->xoff;
+  p.xl = pl->xl;
+  p.bce = pl->bce;
+  p.xwin = pl->xwin;
   p.codes = pl->codes;
   p.is_root = pl->is_root;
   p.Bc = pl->Bc;
