@@ -570,15 +570,18 @@ __global__ __launch_bounds__(BS) void k_spgemm_p(const SpgParams p, const int G)
   constexpr int NWV = BS / RN_WAVE;
   constexpr int UMAX = 11;
   static_assert(NIT * BS == ACAP && NITD * BS == ACAP * DPE, "staging covers the capacity exactly");
-  __shared__ int s_rp[BS + 1];
+  // row starts double-buffered (the projection of one block reads them while
+  // the next block is staged); the projection terms have their own buffer:
+  // two barriers per block
+  __shared__ int s_rp2[2][BS + 1];
   __shared__ int s_ap[BS + 1];
+  __shared__ double s_red[NB][BS];
   __shared__ double s_w[8];
   __shared__ __align__(16) unsigned char s_buf[SH::BYTES];
   int *s_x0 = (int *)s_buf;
   TV *s_ax = (TV *)(s_buf + (size_t)ACAP * sizeof(int));
   TV *s_xw = s_ax + ACAP;
   double *s_gp = (double *)(s_xw + XCAP);
-  double(*s_red)[BS] = (double(*)[BS])s_buf;  // projection terms (phase 2)
 
   const int b = blockIdx.y, t = threadIdx.x, lane = t & (RN_WAVE - 1);
   const int wv = __builtin_amdgcn_readfirstlane(t / RN_WAVE);
@@ -604,9 +607,10 @@ __global__ __launch_bounds__(BS) void k_spgemm_p(const SpgParams p, const int G)
 
   // ---- a block's header and window unit starts: loaded (as uniform vector
   // loads) two blocks ahead, read into scalars once they have arrived ----
+  // lane i < 8 holds header word i, lane i < NUW the i-th unit start this
+  // wave uses (two registers, read out with readlane)
   struct HdV {
-    int4 h0, h1;
-    int uw[NUW];
+    int h, u;
   };
   struct Hd {
     int r0, nrows, e0, ne, aB, naB, namax, nunit;
@@ -615,41 +619,30 @@ __global__ __launch_bounds__(BS) void k_spgemm_p(const SpgParams p, const int G)
   // buffer loads: always vector-memory instructions (a plain load may become
   // a scalar one where no store precedes it, and the wait counts of the
   // pipeline then differ between the first iteration and the others)
-  typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
   const __amdgpu_buffer_rsrc_t rs_h =
       __builtin_amdgcn_make_buffer_rsrc((void *)p.blk_hdr, (short)0, (p.nblk + 1) * 32, 0x00020000);
   const __amdgpu_buffer_rsrc_t rs_u =
       __builtin_amdgcn_make_buffer_rsrc((void *)p.xwin, (short)0, (p.nblk + 1) * NU * 4, 0x00020000);
+  const int ul = lane < NUW ? lane : 0;
+  const int uidx = DPE == 2 ? wv + ul * NWV : 2 * (wv + (ul >> 1) * NWV) + (ul & 1);  // < NU
   auto load_hdv = [&](const int bb, HdV &v) {
-    const u32x4 a0 = __builtin_amdgcn_raw_buffer_load_b128(rs_h, 0, bb * 32, 0);
-    const u32x4 a1 = __builtin_amdgcn_raw_buffer_load_b128(rs_h, 0, bb * 32 + 16, 0);
-    v.h0 = make_int4((int)a0.x, (int)a0.y, (int)a0.z, (int)a0.w);
-    v.h1 = make_int4((int)a1.x, (int)a1.y, (int)a1.z, (int)a1.w);
-#pragma unroll
-    for (int i = 0; i < XIT; ++i) {
-      const int c = wv + i * NWV;
-      if (DPE == 2) {
-        v.uw[i] = (int)__builtin_amdgcn_raw_buffer_load_b32(rs_u, 0, (bb * NU + c) * 4, 0);
-      } else {
-        v.uw[2 * i] = (int)__builtin_amdgcn_raw_buffer_load_b32(rs_u, 0, (bb * NU + 2 * c) * 4, 0);
-        v.uw[2 * i + 1] = (int)__builtin_amdgcn_raw_buffer_load_b32(rs_u, 0, (bb * NU + 2 * c + 1) * 4, 0);
-      }
-    }
+    v.h = (int)__builtin_amdgcn_raw_buffer_load_b32(rs_h, (lane & 7) * 4, bb * 32, 0);
+    v.u = (int)__builtin_amdgcn_raw_buffer_load_b32(rs_u, uidx * 4, bb * NU * 4, 0);
   };
   auto to_hd = [&](const HdV &v, Hd &h) {
-    const int r0 = __builtin_amdgcn_readfirstlane(v.h0.x), r1 = __builtin_amdgcn_readfirstlane(v.h0.y);
-    const int e0 = __builtin_amdgcn_readfirstlane(v.h0.z), e1 = __builtin_amdgcn_readfirstlane(v.h0.w);
-    const int a0 = __builtin_amdgcn_readfirstlane(v.h1.x), a1 = __builtin_amdgcn_readfirstlane(v.h1.y);
+    const int r0 = __builtin_amdgcn_readlane(v.h, 0), r1 = __builtin_amdgcn_readlane(v.h, 1);
+    const int e0 = __builtin_amdgcn_readlane(v.h, 2), e1 = __builtin_amdgcn_readlane(v.h, 3);
+    const int a0 = __builtin_amdgcn_readlane(v.h, 4), a1 = __builtin_amdgcn_readlane(v.h, 5);
     h.r0 = r0;
     h.nrows = r1 - r0;
     h.e0 = e0;
     h.ne = e1 - e0;
     h.aB = a0;
     h.naB = a1 - a0;
-    h.namax = __builtin_amdgcn_readfirstlane(v.h1.z);
-    h.nunit = __builtin_amdgcn_readfirstlane(v.h1.w);
+    h.namax = __builtin_amdgcn_readlane(v.h, 6);
+    h.nunit = __builtin_amdgcn_readlane(v.h, 7);
 #pragma unroll
-    for (int i = 0; i < NUW; ++i) h.uw[i] = __builtin_amdgcn_readfirstlane(v.uw[i]);
+    for (int i = 0; i < NUW; ++i) h.uw[i] = __builtin_amdgcn_readlane(v.u, i);
   };
   // ---- a block's first round of vector loads (registers) ----
   struct Rd {
@@ -709,7 +702,7 @@ __global__ __launch_bounds__(BS) void k_spgemm_p(const SpgParams p, const int G)
     }
   };
   // ---- registers -> LDS (every position written is inside its region) ----
-  auto stage = [&](const Hd &h, const Rd &r) {
+  auto stage = [&](const Hd &h, const Rd &r, int *s_rp) {
     if (t <= h.nrows) {
       s_rp[t] = r.rp - h.e0;
       s_ap[t] = r.ap - h.aB;
@@ -750,10 +743,12 @@ __global__ __launch_bounds__(BS) void k_spgemm_p(const SpgParams p, const int G)
   load_rd(H, R);  // same issue order as in the loop: first round, then the next header
   // (unconditional, clamped: the wait counts then agree on every path)
   load_hdv(min(blk + Gx, hiB - 1), V1);
+  int par = 0;
   for (;;) {
     const int nxt = blk + Gx;
     const bool more = nxt < hiB;
-    stage(H, R);
+    int *s_rp = s_rp2[par];
+    stage(H, R, s_rp);
     __syncthreads();
     Hd Hn;
     Rd Rn;
@@ -827,7 +822,6 @@ __global__ __launch_bounds__(BS) void k_spgemm_p(const SpgParams p, const int G)
 
     // ---- projection: every lane sums its row's terms in pattern order ----
     if (proj) {
-      __syncthreads();  // phase-1 LDS is reused
       if (valid)
 #pragma unroll
         for (int q = 0; q < NB; ++q) s_red[q][t] = z * R.bcv[q];
@@ -887,7 +881,10 @@ __global__ __launch_bounds__(BS) void k_spgemm_p(const SpgParams p, const int G)
       }
     }
     if (!more) break;
-    __syncthreads();  // every LDS read of this block is done before the next staging
+    // without the projection no barrier separates this block's LDS reads from
+    // the next staging
+    if (!proj) __syncthreads();
+    par ^= 1;
     blk = nxt;
     H = Hn;
     R = Rn;
