@@ -1,6 +1,7 @@
 // rn_pattern.hip -- strength of connection (Sec. 3.2) and the interpolation
 // pattern N = S^d C with unamalgamation and root rows (Sec. 3.4).
 // Integer work: results are bit-exact by construction (sorted, unique rows).
+#include <climits>
 #include "rn_internal.h"
 
 // ---------------------------------------------------------------------------
@@ -403,12 +404,29 @@ __global__ __launch_bounds__(RN_BLOCK) void k_expand(int nn, const int32_t *__re
   }
   const int Lc = L < ECAP ? L : ECAP;
   __syncthreads();
+  // Candidates spanning fewer than 64*EG values: a bitmap, one 64-bit word per
+  // lane, gives the distinct values in ascending order in O(L) per lane.
+  // Wider rows: first occurrences and ranks by comparison.
+  int vmin = INT_MAX, vmax = -1;
   for (int c = l; c < Lc; c += EG) {
     const int v = cand[g][c];
-    uint8_t f = 1;
-    for (int u = 0; u < c; ++u)
-      if (cand[g][u] == v) { f = 0; break; }
-    first[g][c] = f;
+    vmin = min(vmin, v);
+    vmax = max(vmax, v);
+  }
+#pragma unroll
+  for (int off = EG / 2; off > 0; off >>= 1) {
+    vmin = min(vmin, __shfl_xor(vmin, off, EG));
+    vmax = max(vmax, __shfl_xor(vmax, off, EG));
+  }
+  const bool bm = Lc > 0 && vmax - vmin < 64 * EG;  // the same in every lane of the row
+  if (!bm) {
+    for (int c = l; c < Lc; c += EG) {
+      const int v = cand[g][c];
+      uint8_t f = 1;
+      for (int u = 0; u < c; ++u)
+        if (cand[g][u] == v) { f = 0; break; }
+      first[g][c] = f;
+    }
   }
   __syncthreads();
   if (!ok) return;
@@ -416,6 +434,31 @@ __global__ __launch_bounds__(RN_BLOCK) void k_expand(int nn, const int32_t *__re
     if (!FILL && l == 0) {
       cnt_or_ptr[I] = 0;
       ovf[atomicAdd(ovf_n, 1)] = I;
+    }
+    return;
+  }
+  if (bm) {
+    unsigned long long bits = 0ull;
+    for (int c = 0; c < Lc; ++c) {
+      const int v = cand[g][c] - vmin;
+      if ((v >> 6) == l) bits |= 1ull << (v & 63);
+    }
+    const int cl = __popcll(bits);
+    int inc = cl;
+#pragma unroll
+    for (int off = 1; off < EG; off <<= 1) {
+      const int t = __shfl_up(inc, off, EG);
+      if (l >= off) inc += t;
+    }
+    if (!FILL) {
+      if (l == EG - 1) cnt_or_ptr[I] = inc;
+    } else {
+      int pos = cnt_or_ptr[I] + inc - cl;
+      while (bits) {
+        const int bit = __ffsll(bits) - 1;
+        bits &= bits - 1ull;
+        Yj[pos++] = vmin + 64 * l + bit;
+      }
     }
     return;
   }
