@@ -32,8 +32,8 @@ METRIC = "energy-min setup s & masked-SpGEMM HBM GB/s; FP32-mix vs FP64; fwd+bwd
 # runs in profiles/k_spgemm_q1aniso512_traffic.md (FETCH_SIZE and WRITE_SIZE,
 # scaled by the same counters on a copy of known size), valid for the kernel
 # sources they were taken on (sha256 prefix below); otherwise reported as null.
-TRAFFIC_BYTES = 67914271
-TRAFFIC_SRC_SHA = "a4fc12bf94c5a556"
+TRAFFIC_BYTES = 72126828
+TRAFFIC_SRC_SHA = "c3e2999f39c45099"
 TRAFFIC_SRCS = ("paper_1610_03154_amd/csrc/rn_spgemm.hip", "paper_1610_03154_amd/csrc/rn_plan.hip",
                 "paper_1610_03154_amd/csrc/rn_emin.h")
 HBM_PEAK_GBS = 8000.0
@@ -270,14 +270,15 @@ def main():
         "spgemm_us_fp32_mixed": dur32 * 1e6,
         "spgemm_batch4_us_per_problem": dur_b4 * 1e6 / 4,
         "spgemm_batch4_GBps_fp64": 4 * nbytes / dur_b4 / 1e9,
+        "spgemm_batch4_frac_of_peak": 4 * nbytes / dur_b4 / 1e9 / HBM_PEAK_GBS,
         "fwd_bwd_s": t_fb,
         "fwd_bwd_workload": f"16 x q1_aniso 256x256 (eps 10^U(-3,0), angle U(0,pi), seed 0), theta 0, "
                             f"S^2 C (nnz_N {nnz_n5} each), 6 CG steps FP64, loss <W,P>",
         "fwd_only_s": t_f,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_bytes(),
-                     "kernel": "k_spgemm<1,1,MODE_PRODUCT,false>", "bytes_per_launch": nbytes,
-                     "flops_per_launch": flops},
+                     "kernel": "k_spgemm_p<NB=1,MODE_PRODUCT,fp64,256 lanes> (persistent)",
+                     "bytes_per_launch": nbytes, "flops_per_launch": flops},
     }
     if not args.no_cpu:
         med, cnt = cpu_baseline()

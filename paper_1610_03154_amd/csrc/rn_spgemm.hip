@@ -3,16 +3,20 @@
 // dropped, then the projection onto U Bc = 0 with root rows fixed).
 //
 // One lane per pattern entry (per 2x2 block of node entries when A is
-// node-blocked); a block owns the rows whose first entry lies in its chunk,
-// so it holds <= 256 entries and whole rows.  The per-block header (row,
-// entry and A ranges) is the only load the rest depends on: row metadata,
-// the block's slice of A with the first pattern entry of each neighbour row,
-// each lane's record (position codes and its row within the block, fixed
-// stride per entry), its column and its own Krylov value all load in one
-// round; X and the row's projection data are gathered in the next.  Terms are added one at a time in the
-// order of A's row.  Per-row sums of the projection go through LDS in
-// pattern order.  Krylov dot products are fused into the epilogue as
-// per-block partials (no inter-block synchronisation).
+// node-blocked); a product block owns the rows whose first entry lies in its
+// chunk, so it holds <= bs entries and whole rows.  The block's header (row,
+// entry and A ranges) is the only load the rest depends on.  Terms are added
+// one at a time in the order of A's row.  Per-row sums of the projection go
+// through LDS in pattern order.  Krylov dot products are fused into the
+// epilogue as per-block partials (no inter-block synchronisation).
+//
+// k_spgemm (every operator): one product block per workgroup; the block's
+// slice of A and the neighbour offsets are staged in LDS, X is gathered from
+// global memory (from the block's X window in LDS when the plan built one).
+// k_spgemm_p (scalar operators, n_B <= 2, records of <= 12 bytes):
+// persistent workgroups that stage each block's X window, A slice, Bc rows
+// and G^+ in one round of contiguous loads and prefetch the next block while
+// computing the current one from LDS.
 #include <cstdlib>
 #include <cstring>
 #include <type_traits>
