@@ -304,6 +304,106 @@ __global__ __launch_bounds__(RN_BLOCK) void k_adj_sddmm(int nblk, int64_t nz, in
   }
 }
 
+// The same sum for scalar operators with records of at most 16 bytes, with
+// the block's data staged in LDS by contiguous loads: the pattern values Yh
+// and position records of its entries, its row starts, and the block's X
+// window (the neighbour rows' pattern entries; blocks without a window read X
+// from global memory).  Each A entry then reads only LDS; the sum runs over
+// the row's pattern entries in the same order as k_adj_sddmm.
+#define SD_REC 4  // record words staged per entry
+__global__ __launch_bounds__(RN_BLOCK) void k_adj_sddmm_w(int nblk, int64_t nz, int64_t nnzA, int64_t strideX, int k,
+                                                         const int32_t *__restrict__ hdr,
+                                                         const int32_t *__restrict__ Ap,
+                                                         const int32_t *__restrict__ Np,
+                                                         const uint8_t *__restrict__ is_root,
+                                                         const uint8_t *__restrict__ codes, int cstride,
+                                                         const int32_t *__restrict__ xoff,
+                                                         const int32_t *__restrict__ xl,
+                                                         const int32_t *__restrict__ xwin, int nu,
+                                                         const double *__restrict__ Yh, const double *__restrict__ X,
+                                                         double *__restrict__ Abar, const int32_t *__restrict__ tst) {
+  __shared__ int s_ap[RN_BLOCK + 1];
+  __shared__ int s_rp[RN_BLOCK + 1];
+  __shared__ uint8_t s_root[RN_BLOCK];
+  __shared__ double s_y[RN_BLOCK];
+  __shared__ uint32_t s_rec[RN_BLOCK * SD_REC];
+  __shared__ double s_xw[SPG_XCAP_M1(RN_BLOCK)];
+  __shared__ uint8_t s_arow[SPG_ACAP_M1(RN_BLOCK)];  // row of each staged A entry
+  const int b = blockIdx.y, t = threadIdx.x;
+  if (k >= 0 && !adj_active(tst, b, k)) return;
+  if (k < 0 && tst[(int64_t)b * ST_STRIDE + ST_STATUS]) return;
+  const int blk = rn_xcd_block(blockIdx.x, nblk);
+  if (blk < 0) return;
+  // the window's unit starts depend on the block alone: they load with the header
+  const int32_t *uw = xwin + (int64_t)blk * nu;
+  int uwv[SPG_XCAP_M1(RN_BLOCK) / RN_BLOCK];
+#pragma unroll
+  for (int i = 0; i < SPG_XCAP_M1(RN_BLOCK) / RN_BLOCK; ++i) uwv[i] = uw[(t + i * RN_BLOCK) / XW_UNIT];
+  const int4 h0 = ((const int4 *)hdr)[2 * blk];
+  const int4 h1 = ((const int4 *)hdr)[2 * blk + 1];
+  const int r0 = h0.x, nrows = h0.y - h0.x, e0 = h0.z, ne = h0.w - h0.z, a0 = h1.x, na = h1.y - h1.x;
+  const int nunit = h1.w;
+  const bool byrow = na <= SPG_ACAP_M1(RN_BLOCK);  // uniform: A entries find their row in LDS
+  const double *y = Yh + (int64_t)b * nz;
+  const double *x = X + (int64_t)b * strideX;
+  double *ab = Abar + (int64_t)b * nnzA;
+  const int nw = cstride >> 2;
+  for (int rr = t; rr <= nrows; rr += RN_BLOCK) {
+    s_ap[rr] = Ap[r0 + rr] - a0;
+    s_rp[rr] = Np[r0 + rr] - e0;
+    if (rr < nrows) s_root[rr] = is_root[r0 + rr];
+  }
+  for (int q = t; q < ne; q += RN_BLOCK) s_y[q] = y[e0 + q];
+  {
+    const uint32_t *cw = (const uint32_t *)codes + (int64_t)e0 * nw;
+    for (int q = t; q < ne * nw; q += RN_BLOCK) s_rec[(q / nw) * SD_REC + q % nw] = cw[q];
+  }
+  if (nunit > 0) {
+#pragma unroll
+    for (int i = 0; i < SPG_XCAP_M1(RN_BLOCK) / RN_BLOCK; ++i) {
+      const int q = t + i * RN_BLOCK;
+      if (q < nunit * XW_UNIT) s_xw[q] = x[uwv[i] + q % XW_UNIT];
+    }
+  }
+  __syncthreads();
+  if (byrow)
+    for (int rr = t; rr < nrows; rr += RN_BLOCK)
+      for (int q = s_ap[rr]; q < s_ap[rr + 1]; ++q) s_arow[q] = (uint8_t)rr;
+  __syncthreads();
+  for (int q = t; q < na; q += RN_BLOCK) {
+    int lo = 0;
+    if (byrow) {
+      lo = s_arow[q];
+    } else {
+      int hi = nrows;  // row: the largest rr with s_ap[rr] <= q
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (s_ap[mid] <= q) lo = mid; else hi = mid;
+      }
+    }
+    if (s_root[lo]) continue;
+    const int u = q - s_ap[lo];
+    const int pb = u + 1;  // byte of the code in each record
+    const uint32_t *rec = s_rec + (pb >> 2);
+    const int sh = 8 * (pb & 3);
+    double acc = 0.0;
+    if (nunit > 0) {
+      const int xo = xl[a0 + q];
+      for (int r = s_rp[lo]; r < s_rp[lo + 1]; ++r) {
+        const uint32_t c = (rec[r * SD_REC] >> sh) & 0xffu;
+        if (c != CODE_NONE) acc += s_y[r] * s_xw[xo + (int)c];
+      }
+    } else {
+      const int xo = xoff[a0 + q];
+      for (int r = s_rp[lo]; r < s_rp[lo + 1]; ++r) {
+        const uint32_t c = (rec[r * SD_REC] >> sh) & 0xffu;
+        if (c != CODE_NONE) acc += s_y[r] * x[xo + (int)c];
+      }
+    }
+    ab[a0 + q] += acc;
+  }
+}
+
 __global__ __launch_bounds__(RN_BLOCK) void k_adj_gather(const double *__restrict__ src, const int32_t *__restrict__ perm,
                                                         int64_t n, double *__restrict__ dst) {
   const int b = blockIdx.y;
@@ -328,8 +428,13 @@ static rn_status adj_sddmm(rn_ctx *ctx, const rn_plan *pl, int k, rn_tape *t, co
                            double *A_bar) {
   if (pl->nblk == 0) return RN_OK;
   const dim3 g(rn_xcd_grid((unsigned)pl->nblk), (unsigned)t->batch), bl(RN_BLOCK);
-  hipLaunchKernelGGL(k_adj_sddmm, g, bl, 0, ctx->stream, pl->nblk, t->nz, pl->nnzA, strideX, k, pl->blk_hdr, pl->Ap,
-                     pl->Np, pl->is_root, pl->codes, pl->cstride, pl->xoff, t->Yh, X, A_bar, t->st);
+  if (pl->m == 1 && pl->bs == RN_BLOCK && pl->cstride <= 4 * SD_REC && pl->xl && pl->xwin)
+    hipLaunchKernelGGL(k_adj_sddmm_w, g, bl, 0, ctx->stream, pl->nblk, t->nz, pl->nnzA, strideX, k, pl->blk_hdr,
+                       pl->Ap, pl->Np, pl->is_root, pl->codes, pl->cstride, pl->xoff, pl->xl, pl->xwin,
+                       SPG_XCAP_M1(RN_BLOCK) / XW_UNIT, t->Yh, X, A_bar, t->st);
+  else
+    hipLaunchKernelGGL(k_adj_sddmm, g, bl, 0, ctx->stream, pl->nblk, t->nz, pl->nnzA, strideX, k, pl->blk_hdr,
+                       pl->Ap, pl->Np, pl->is_root, pl->codes, pl->cstride, pl->xoff, t->Yh, X, A_bar, t->st);
   LAUNCH_CHECK(ctx);
   return RN_OK;
 }
