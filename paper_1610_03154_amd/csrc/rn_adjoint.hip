@@ -256,6 +256,70 @@ __global__ __launch_bounds__(RN_BLOCK) void k_adj_project(int n, int64_t nz, int
   }
 }
 
+// The same projection entry-parallel over the product's blocks (scalar
+// operators, n_B <= 2, the plan's per-entry Bc rows): one lane per pattern
+// entry; the products y_r Bc[j_r] go through LDS and every lane sums its row's
+// in pattern order, exactly as k_adj_project does.
+template <int NB>
+__global__ __launch_bounds__(RN_BLOCK) void k_adj_project_b(int nblk, int64_t nz, int k, const int32_t *__restrict__ hdr,
+                                                           const int32_t *__restrict__ Np,
+                                                           const uint8_t *__restrict__ is_root,
+                                                           const uint8_t *__restrict__ codes, int cstride,
+                                                           const double *__restrict__ bce,
+                                                           const double *__restrict__ gp,
+                                                           const double *__restrict__ Yb, double *__restrict__ Yh,
+                                                           const int32_t *__restrict__ tst) {
+  constexpr int NP = NB * (NB + 1) / 2;
+  __shared__ int s_rp[RN_BLOCK + 1];
+  __shared__ uint8_t s_root[RN_BLOCK];
+  __shared__ double s_red[NB][RN_BLOCK];
+  const int b = blockIdx.y, t = threadIdx.x;
+  if (k >= 0 && !adj_active(tst, b, k)) return;
+  if (k < 0 && tst[(int64_t)b * ST_STRIDE + ST_STATUS]) return;
+  const int blk = rn_xcd_block(blockIdx.x, nblk);
+  if (blk < 0) return;
+  const int4 h0 = ((const int4 *)hdr)[2 * blk];
+  const int r0 = h0.x, nrows = h0.y - h0.x, e0 = h0.z, ne = h0.w - h0.z;
+  const int64_t off = (int64_t)b * nz;
+  const bool valid = t < ne;
+  const int e = valid ? e0 + t : (ne > 0 ? e0 : 0);  // idle lanes read a valid entry
+  const double y = Yb[off + e];
+  const int lrow = valid ? codes[(int64_t)e * cstride] : 0;  // record byte 0: the row within the block
+  double bc[NB];
+#pragma unroll
+  for (int q = 0; q < NB; ++q) bc[q] = bce[(int64_t)e * NB + q];
+  if (t <= nrows) s_rp[t] = Np[r0 + t] - e0;
+  if (t < nrows) s_root[t] = is_root[r0 + t];
+  if (nrows == RN_BLOCK && t == 0) s_rp[RN_BLOCK] = ne;
+  if (valid)
+#pragma unroll
+    for (int q = 0; q < NB; ++q) s_red[q][t] = y * bc[q];
+  __syncthreads();
+  if (!valid) return;
+  const int i = r0 + lrow;
+  if (s_root[lrow]) {
+    Yh[off + e] = 0.0;
+    return;
+  }
+  double sv[NB];
+#pragma unroll
+  for (int q = 0; q < NB; ++q) sv[q] = 0.0;
+  for (int r = s_rp[lrow]; r < s_rp[lrow + 1]; ++r)
+#pragma unroll
+    for (int q = 0; q < NB; ++q) sv[q] += s_red[q][r];
+  double w[NB];
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    w[q] = 0.0;
+#pragma unroll
+    for (int r2 = 0; r2 < NB; ++r2) w[q] += gp[(int64_t)i * NP + rn_pk(NB, q, r2)] * sv[r2];
+  }
+  double u = 0.0;
+#pragma unroll
+  for (int q = 0; q < NB; ++q) u += bc[q] * w[q];
+  Yh[off + e] = y - u;
+}
+
 // Abar_ik += sum over the pattern entries r of row i of Yh_r X[k, j_r]
 // (X = D_k, or T for the start term).  Organised by the product's blocks:
 // block b owns the stored A entries of its rows, one thread per entry; the
@@ -412,6 +476,18 @@ __global__ __launch_bounds__(RN_BLOCK) void k_adj_gather(const double *__restric
 }
 
 static rn_status adj_project(rn_ctx *ctx, const rn_plan *pl, int k, rn_tape *t) {
+  if (pl->m == 1 && pl->bs == RN_BLOCK && pl->bce && pl->nB <= 2) {
+    if (pl->nblk == 0) return RN_OK;
+    const dim3 gb(rn_xcd_grid((unsigned)pl->nblk), (unsigned)t->batch), bb(RN_BLOCK);
+    if (pl->nB == 1)
+      hipLaunchKernelGGL(k_adj_project_b<1>, gb, bb, 0, ctx->stream, pl->nblk, t->nz, k, pl->blk_hdr, pl->Np,
+                         pl->is_root, pl->codes, pl->cstride, pl->bce, pl->gp, t->Yb, t->Yh, t->st);
+    else
+      hipLaunchKernelGGL(k_adj_project_b<2>, gb, bb, 0, ctx->stream, pl->nblk, t->nz, k, pl->blk_hdr, pl->Np,
+                         pl->is_root, pl->codes, pl->cstride, pl->bce, pl->gp, t->Yb, t->Yh, t->st);
+    LAUNCH_CHECK(ctx);
+    return RN_OK;
+  }
   const dim3 g(rn_div_up(pl->n > 0 ? pl->n : 1, RN_BLOCK), (unsigned)t->batch), bl(RN_BLOCK);
   switch (pl->nB) {
     case 1: hipLaunchKernelGGL(k_adj_project<1>, g, bl, 0, ctx->stream, pl->n, t->nz, k, pl->Np, pl->Nj, pl->is_root, pl->Bc, pl->gp, t->Yb, t->Yh, t->st); break;
