@@ -747,6 +747,12 @@ __global__ __launch_bounds__(BS) void k_spgemm_p(const SpgParams p, const int G)
   load_rd(H, R);  // same issue order as in the loop: first round, then the next header
   // (unconditional, clamped: the wait counts then agree on every path)
   load_hdv(min(blk + Gx, hiB - 1), V1);
+  // single-dot modes: every lane adds its terms over all of this workgroup's
+  // blocks, in block order; one compensated block sum at the end goes to the
+  // partial of the first block and the others get 0 (consumers sum all
+  // nblk partials in a fixed order, so the result stays deterministic)
+  RnAcc dacc;
+  const int blk0 = blk;
   int par = 0;
   for (;;) {
     const int nxt = blk + Gx;
@@ -857,23 +863,19 @@ __global__ __launch_bounds__(BS) void k_spgemm_p(const SpgParams p, const int G)
     if (MODE == MODE_PRODUCT) {
       if (valid) spg_st(Z, e, p.accum ? spg_ld((const double *)Z, e) + z : z);
     } else if (MODE == MODE_CG_INIT || MODE == MODE_GM_INIT) {
-      RnAcc d;
       if (valid) {
         const double v = -z;
         spg_st(Z, e, v);
         if (p.Z2) spg_st(p.Z2 + zb, e, v);
-        d.add(v * v);
+        dacc.add(v * v);
       }
-      const double S = rn_block_sum2_w<NWV>(d.hi, d.lo, s_w);
-      if (t == 0) part[blk] = S;
+      if (t == 0 && blk != blk0) part[blk] = 0.0;
     } else if (MODE == MODE_CG_STEP) {
-      RnAcc d;
       if (valid) {
         spg_st(Z, e, z);
-        d.add(R.own * z);
+        dacc.add(R.own * z);
       }
-      const double S = rn_block_sum2_w<NWV>(d.hi, d.lo, s_w);
-      if (t == 0) part[blk] = S;
+      if (t == 0 && blk != blk0) part[blk] = 0.0;
     } else if (MODE == MODE_GM_STEP) {
       if (valid) spg_st(Z, e, z);
       const double *U = p.U + (int64_t)b * p.Ubatch;
@@ -893,6 +895,10 @@ __global__ __launch_bounds__(BS) void k_spgemm_p(const SpgParams p, const int G)
     H = Hn;
     R = Rn;
     V1 = V2;
+  }
+  if (MODE == MODE_CG_INIT || MODE == MODE_GM_INIT || MODE == MODE_CG_STEP) {
+    const double S = rn_block_sum2_w<NWV>(dacc.hi, dacc.lo, s_w);
+    if (t == 0) part[blk0] = S;
   }
 }
 
