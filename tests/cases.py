@@ -32,6 +32,10 @@ CASES = {
     # pattern rows gathering more than 64 candidates (the expansion's
     # large-window kernel)
     "lap27_10": (lambda: (W.laplace27(10), W.ones(1000), None, None), 0.0, 2, 4, "cg", 1),
+    # irregular structure: neighbour rows far apart in the numbering, so no
+    # product block gets an X window (the persistent product reads X from
+    # global memory)
+    "ring20k": (lambda: (W.ring_graph(20000), W.ones(20000), None, None), 0.0, 1, 4, "cg", 1),
 }
 
 

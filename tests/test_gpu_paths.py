@@ -1,0 +1,116 @@
+"""GPU parity of the masked product's code paths, against the CPU oracle.
+
+The persistent product for scalar operators stages each product block's
+A slice, X window and projection data in LDS; blocks whose neighbour rows do
+not form a window read X from global memory, and blocks with more A entries
+than the LDS capacity read A from global memory too.  These cases make each
+path carry whole launches, plus batches with per-entry values and the
+128-lane block size.  Same bars as test_gpu_parity: FP64 1e-12, FP32-mixed
+1e-5 relative to max|ref|.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from tests import cases as CS
+from tests.test_gpu_parity import R, ctx, dev, host, run_path  # noqa: F401  (fixtures and helpers)
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-12
+MIXED_TOL = 1e-5
+
+
+def _product_refs(A, Np, Nj, nc, is_root, Bc, nB, X):
+    import oracle as O
+    ref = O.masked_product(A.rowptr, A.colind, A.vals, Np, Nj, nc, X)
+    root_e = np.repeat(is_root, np.diff(Np)).astype(bool)
+    return np.where(root_e, 0.0, ref), O.project(Np, Nj, is_root, Bc, nB, ref), root_e
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_irregular_structure_product_and_cg(R, ctx, precision):
+    """Circulant graph with far neighbours: no X windows."""
+    c = CS.case("ring20k")
+    g = run_path(R, ctx, c)
+    prec = R.RN_FP64 if precision == "fp64" else R.RN_FP32_MIXED
+    tol = FP64_TOL if precision == "fp64" else MIXED_TOL
+    X = np.random.default_rng(5).standard_normal(c["Nj"].size)
+    ref_m, refp, root_e = _product_refs(c["A"], c["Np"], c["Nj"], c["nc"], c["is_root"], c["Bc"], 1, X)
+    Z = host(ctx.masked_product(g["plan"], g["A"].vals, dev(X), project=False, precision=prec))
+    Zp = host(ctx.masked_product(g["plan"], g["A"].vals, dev(X), project=True, precision=prec))
+    scale = np.max(np.abs(ref_m))
+    assert np.max(np.abs(Z - ref_m)) <= tol * scale
+    assert np.max(np.abs(Zp - refp)) <= tol * scale
+    P, st, _ = ctx.energy_min(g["plan"], g["A"].vals, g["T"], R.RN_CG, c["iters"], prec)
+    assert CS.rel_max(host(P), c["P"]) <= tol
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batched_product(R, ctx, precision):
+    """Three operators on one structure in one launch: each batch entry has its
+    own A values and X and must match the oracle on its own."""
+    import torch
+    c = CS.case("aniso40")
+    g = run_path(R, ctx, c)
+    A = c["A"]
+    rng = np.random.default_rng(8)
+    scales = np.array([1.0, 0.5, 3.0])
+    vals = np.stack([A.vals * s for s in scales])
+    X = rng.standard_normal((3, c["Nj"].size))
+    prec = R.RN_FP64 if precision == "fp64" else R.RN_FP32_MIXED
+    tol = FP64_TOL if precision == "fp64" else MIXED_TOL
+    Zp = host(ctx.masked_product(g["plan"], dev(vals), dev(X), project=True, precision=prec))
+    for b in range(3):
+        Ab = type(A)(A.n_rows, A.n_cols, A.rowptr, A.colind, vals[b])
+        _, refp, _ = _product_refs(Ab, c["Np"], c["Nj"], c["nc"], c["is_root"], c["Bc"], 1, X[b])
+        assert np.max(np.abs(Zp[b] - refp)) <= tol * np.max(np.abs(refp)), b
+    torch.cuda.synchronize()
+
+
+def test_blocks_beyond_lds_capacity(R, ctx):
+    """One pattern entry per row (the row's aggregate): 256 rows per product
+    block, so every block holds far more A entries than the LDS stages."""
+    import oracle as O
+    c = CS.case("aniso40")
+    A = c["A"]
+    n = A.n_rows
+    agg, is_root = c["agg"], c["is_root"]
+    Np = np.arange(n + 1, dtype=np.int32)
+    Nj = agg.astype(np.int32)
+    nc = int(c["roots"].size)
+    Bc = np.random.default_rng(3).uniform(0.5, 2.0, (nc, 1))
+    dA = R.DeviceCSR.from_host(A.rowptr, A.colind, A.vals)
+    plan = ctx.plan(dA, nc, dev(Np), dev(Nj), dev(is_root), dev(Bc))
+    X = np.random.default_rng(4).standard_normal(n)
+    ref_m, refp, root_e = _product_refs(A, Np, Nj, nc, is_root, Bc, 1, X)
+    Z = host(ctx.masked_product(plan, dA.vals, dev(X), project=False))
+    Zp = host(ctx.masked_product(plan, dA.vals, dev(X), project=True))
+    scale = np.max(np.abs(ref_m))
+    assert np.max(np.abs(Z - ref_m)) <= FP64_TOL * scale
+    assert np.max(np.abs(Zp - refp)) <= FP64_TOL * scale
+    # with one entry per row the projection removes every F entry (G^+ = 1/Bc^2)
+    assert np.max(np.abs(Zp[~root_e])) <= 1e-12 * scale
+    plan.close()
+    del O
+
+
+def test_128_lane_blocks(R, ctx):
+    """Plans built with 128-lane product blocks (RNAMG_PRODUCT_BS=128)."""
+    c = CS.case("aniso40")
+    old = os.environ.get("RNAMG_PRODUCT_BS")
+    os.environ["RNAMG_PRODUCT_BS"] = "128"
+    try:
+        g = run_path(R, ctx, c)
+    finally:
+        if old is None:
+            del os.environ["RNAMG_PRODUCT_BS"]
+        else:
+            os.environ["RNAMG_PRODUCT_BS"] = old
+    X = np.random.default_rng(6).standard_normal(c["Nj"].size)
+    _, refp, _ = _product_refs(c["A"], c["Np"], c["Nj"], c["nc"], c["is_root"], c["Bc"], 1, X)
+    Zp = host(ctx.masked_product(g["plan"], g["A"].vals, dev(X), project=True))
+    assert np.max(np.abs(Zp - refp)) <= FP64_TOL * np.max(np.abs(refp))
+    P, st, _ = ctx.energy_min(g["plan"], g["A"].vals, g["T"], R.RN_CG, c["iters"], R.RN_FP64)
+    assert CS.rel_max(host(P), c["P"]) <= FP64_TOL

@@ -31,7 +31,7 @@ import numpy as np
 __all__ = [
     "CSR", "BSR", "stencil_grid", "poisson5", "laplace1d", "q1_stencil",
     "q1_aniso", "upwind_cd", "q1_elasticity", "rbm", "ones",
-    "aniso_batch_params", "aniso_batch", "loss_weights", "config", "laplace27",
+    "aniso_batch_params", "aniso_batch", "loss_weights", "config", "laplace27", "ring_graph",
 ]
 
 
@@ -155,6 +155,28 @@ def laplace27(nx: int) -> CSR:
     order = np.lexsort((cols, rows))
     rows, cols, vals = rows[order], cols[order], vals[order]
     rowptr = np.zeros(n + 1, dtype=np.int32)
+    np.add.at(rowptr, rows + 1, 1)
+    return CSR(n, n, np.cumsum(rowptr).astype(np.int32), cols.astype(np.int32), vals.astype(np.float64))
+
+
+def ring_graph(n: int, offsets=(1, 4100, 9001, 13007)) -> CSR:
+    """Graph Laplacian of a circulant graph: node i joined to i +- o (mod n) for
+    each offset o, weight -1, diagonal = degree + 1 (symmetric positive
+    definite).  Neighbours far apart in the numbering give an irregular
+    column structure (no short runs of neighbour rows)."""
+    idx = np.arange(n)
+    rows, cols = [idx], [idx]
+    for o in offsets:
+        for s in (o, -o):
+            rows.append(idx)
+            cols.append((idx + s) % n)
+    rows, cols = np.concatenate(rows), np.concatenate(cols)
+    key = np.unique(rows.astype(np.int64) * n + cols)
+    rows, cols = (key // n).astype(np.int64), (key % n).astype(np.int64)
+    vals = np.where(rows == cols, 0.0, -1.0)
+    deg = np.bincount(rows, weights=(rows != cols).astype(np.float64), minlength=n)
+    vals[rows == cols] = deg + 1.0
+    rowptr = np.zeros(n + 1, dtype=np.int64)
     np.add.at(rowptr, rows + 1, 1)
     return CSR(n, n, np.cumsum(rowptr).astype(np.int32), cols.astype(np.int32), vals.astype(np.float64))
 
