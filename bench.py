@@ -190,6 +190,67 @@ def product_batched(inp, aux, batch, reps):
     return ev0.elapsed_time(ev1) / 1e3 / reps
 
 
+def other_configs(reps):
+    """The study's other two configurations at full size on the same GPU path,
+    aggregation precomputed on the host (an input), seconds per setup
+    (strength -> pattern -> T -> plan -> energy minimisation), FP64 and
+    FP32-mixed:
+    upwind1024: first-order upwind convection-diffusion on 1024 x 1024
+      (b at 3pi/16, eps 1e-4), B = B^ = ones, theta 0, S^2 C, P by 8 GMRES
+      steps on A and R^T by 8 GMRES steps on A^T (transpose included);
+    elastic512: Q1 plane-strain elasticity on 512 x 512 nodes, 2 DOFs per node
+      (node-blocked CSR), B = 3 rigid-body modes, theta 0, S^2 C, 6 CG steps."""
+    import torch
+    import workloads as W
+    import paper_1610_03154_amd as R
+    ctx = R.Context()
+    out = {}
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(reps):
+            res = fn()
+        ev1.record()
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1) / 1e3 / reps, res
+
+    def rel(a, b):
+        a, b = a.double(), b.double()
+        return float((a - b).abs().max() / b.abs().max())
+
+    A = W.upwind_cd(1024)
+    dA = R.DeviceCSR.from_host(A.rowptr, A.colind, A.vals)
+    Sp, Sj = ctx.strength(dA, 0.0)
+    a, r = R.aggregate_host(Sp.cpu().numpy(), Sj.cpu().numpy())
+    agg, roots = torch.as_tensor(a, device="cuda"), torch.as_tensor(r, device="cuda")
+    B = torch.ones((A.n_rows, 1), dtype=torch.float64, device="cuda")
+    res = {}
+    for prec, key in ((R.RN_FP64, "fp64"), (R.RN_FP32_MIXED, "fp32_mixed")):
+        t, s = timed(lambda: R.setup(ctx, dA, B, 0.0, 2, 8, R.RN_GMRES, prec, Bhat=B, agg=agg, roots=roots))
+        out["upwind1024_gmres_P_RT_s_" + key] = t
+        res[key] = (s.P.clone(), s.RT.clone())
+        del s
+    out["upwind1024_fp32_mixed_max_rel_dP_dRT_vs_fp64"] = max(rel(res["fp32_mixed"][0], res["fp64"][0]),
+                                                               rel(res["fp32_mixed"][1], res["fp64"][1]))
+    Ab, xy = W.q1_elasticity(512)
+    dA = R.DeviceCSR.from_host(Ab.rowptr, Ab.colind, Ab.vals.reshape(-1), n=Ab.n_nodes * 2, block_m=2)
+    Sp, Sj = ctx.strength(dA, 0.0)
+    a, r = R.aggregate_host(Sp.cpu().numpy(), Sj.cpu().numpy())
+    agg, roots = torch.as_tensor(a, device="cuda"), torch.as_tensor(r, device="cuda")
+    B = torch.as_tensor(W.rbm(xy), device="cuda")
+    res = {}
+    for prec, key in ((R.RN_FP64, "fp64"), (R.RN_FP32_MIXED, "fp32_mixed")):
+        t, s = timed(lambda: R.setup(ctx, dA, B, 0.0, 2, 6, R.RN_CG, prec, agg=agg, roots=roots))
+        out["elastic512_cg_s_" + key] = t
+        res[key] = s.P.clone()
+        del s
+    out["elastic512_fp32_mixed_max_rel_dP_vs_fp64"] = rel(res["fp32_mixed"], res["fp64"])
+    return out
+
+
 def cpu_baseline(budget_s=12.0):
     """The oracle (single-threaded C) on the same step, repeated for ~budget."""
     import oracle as O
@@ -220,6 +281,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--fb-reps", type=int, default=5, help="repetitions of the batched forward+backward")
     ap.add_argument("--roofline-only", action="store_true", help="only the masked-product timing loop")
+    ap.add_argument("--other-reps", type=int, default=3,
+                    help="repetitions of the upwind1024 and elastic512 setups (0 skips them)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the energy-minimisation path here is single-GPU "
@@ -241,6 +304,7 @@ def main():
     dur32, nbytes32, _ = roofline(inp, aux, R.RN_FP32_MIXED, args.reps)
     t_fb, t_f, nnz_n5 = fwd_bwd(args.fb_reps)
     dur_b4 = product_batched(inp, aux, 4, max(args.reps // 4, 10))
+    others = other_configs(args.other_reps) if args.other_reps > 0 else {}
     achieved = nbytes / dur / 1e9
     p64 = P64.cpu().numpy()
     mix_err = float(np.max(np.abs(P32.cpu().numpy() - p64)) / np.max(np.abs(p64)))
@@ -275,6 +339,7 @@ def main():
         "fwd_bwd_workload": f"16 x q1_aniso 256x256 (eps 10^U(-3,0), angle U(0,pi), seed 0), theta 0, "
                             f"S^2 C (nnz_N {nnz_n5} each), 6 CG steps FP64, loss <W,P>",
         "fwd_only_s": t_f,
+        **others,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_bytes(),
                      "kernel": "k_spgemm_p<NB=1,MODE_PRODUCT,fp64,256 lanes> (persistent)",
