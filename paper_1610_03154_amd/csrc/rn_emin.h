@@ -108,7 +108,7 @@ struct SpgParams {
   int32_t n, nr, nblk, k, K, hist_stride, project, scal_stride, cstride, bs;
   int32_t accum;  // MODE_PRODUCT: Z += result instead of Z = result
   int32_t kact;   // >= 0: batch entries whose st[ST_ITERS] <= kact do nothing
-  int64_t nnzN, strideA, strideX, strideZ, Ubatch;
+  int64_t nnzN, strideA, strideX, strideZ;
   const int32_t *Ap, *Aj, *Np, *Nj, *nodeptr, *ncol, *blk_row, *blk_hdr, *xoff, *xl, *xwin;
   const uint8_t *codes, *is_root;
   const double *Bc, *gp, *bce;
@@ -116,7 +116,6 @@ struct SpgParams {
   const void *X;       // double or float, [batch][strideX]
   const double *Xown;  // FP64 own-entry values for the CG dot (D)
   double *Z, *Z2;
-  const double *U;     // GMRES basis: vector j of batch b at U + b*Ubatch + j*nnzN
   double *part;        // [batch][RN_MAXDOT][nblk]
   double *scal;        // [batch][scal_stride]
   int32_t *st;         // [batch][ST_STRIDE]

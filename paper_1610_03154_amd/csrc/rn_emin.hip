@@ -140,7 +140,8 @@ __global__ __launch_bounds__(RN_BLOCK) void k_gm_fin(int nb, const double *__res
                                                     int32_t *__restrict__ stv, double *__restrict__ histv,
                                                     int hist_stride) {
   __shared__ double s_w[8];
-  const int b = blockIdx.x;
+  // stages 1 and 2: one workgroup per coefficient j (blockIdx.x) and batch entry
+  const int b = (STAGE == 1 || STAGE == 2) ? blockIdx.y : blockIdx.x;
   int32_t *st = stv + (int64_t)b * ST_STRIDE;
   if (STAGE > 0 && (st[ST_STATUS] || st[ST_DONE])) return;
   double *sc = scal + (int64_t)b * scal_stride;
@@ -148,10 +149,9 @@ __global__ __launch_bounds__(RN_BLOCK) void k_gm_fin(int nb, const double *__res
   const double *pb = part + (int64_t)b * RN_MAXDOT * nb;
   double *hist = histv ? histv + (int64_t)b * hist_stride : nullptr;
   if (STAGE == 1 || STAGE == 2) {
-    for (int j = 0; j <= k; ++j) {
-      const double tot = rn_reduce_part(pb + (int64_t)j * nb, nb, s_w);
-      if (threadIdx.x == 0) sc[(STAGE == 1 ? L.h1 : L.h2) + j] = sc[L.s + j] * tot;
-    }
+    const int j = blockIdx.x;
+    const double tot = rn_reduce_part(pb + (int64_t)j * nb, nb, s_w);
+    if (threadIdx.x == 0) sc[(STAGE == 1 ? L.h1 : L.h2) + j] = sc[L.s + j] * tot;
     return;
   }
   const double tot = rn_reduce_part(pb, nb, s_w);
@@ -194,7 +194,8 @@ __global__ __launch_bounds__(RN_BLOCK) void k_gm_fin(int nb, const double *__res
   else sc[L.s + k + 1] = 1.0 / hn;
 }
 
-// Re-orthogonalisation passes on the new vector W = U_{k+1}:
+// Gram-Schmidt passes on the new vector W = U_{k+1} (classical, twice):
+// pass 0: partials of <W, U_j> (W untouched)
 // pass 1: W -= sum_j h1_j V_j, partials of <W, U_j>
 // pass 2: W -= sum_j h2_j V_j, partials of ||W||^2 (and the FP32 shadow)
 template <int NJ, int PASS, bool MIXED>
@@ -212,15 +213,17 @@ __global__ __launch_bounds__(RN_BLOCK) void k_gm_orth(int64_t nnz, int64_t ubatc
   double *W = U + (int64_t)(k + 1) * nnz;
   double coef[NJ];
 #pragma unroll
-  for (int j = 0; j < NJ; ++j) coef[j] = j <= k ? sc[(PASS == 1 ? L.h1 : L.h2) + j] * sc[L.s + j] : 0.0;
+  for (int j = 0; j < NJ; ++j) coef[j] = (PASS > 0 && j <= k) ? sc[(PASS == 1 ? L.h1 : L.h2) + j] * sc[L.s + j] : 0.0;
   RnAcc acc[NJ];
   for (int64_t e = (int64_t)blockIdx.x * RN_BLOCK + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * RN_BLOCK) {
     double w = W[e];
+    if (PASS > 0) {
 #pragma unroll
-    for (int j = 0; j < NJ; ++j)
-      if (j <= k) w -= coef[j] * U[(int64_t)j * nnz + e];
-    W[e] = w;
-    if (PASS == 1) {
+      for (int j = 0; j < NJ; ++j)
+        if (j <= k) w -= coef[j] * U[(int64_t)j * nnz + e];
+      W[e] = w;
+    }
+    if (PASS <= 1) {
 #pragma unroll
       for (int j = 0; j < NJ; ++j)
         if (j <= k) acc[j].add(w * U[(int64_t)j * nnz + e]);
@@ -230,13 +233,78 @@ __global__ __launch_bounds__(RN_BLOCK) void k_gm_orth(int64_t nnz, int64_t ubatc
     }
   }
   double *pb = part + (int64_t)b * RN_MAXDOT * gridDim.x;
-  const int nd = PASS == 1 ? k + 1 : 1;
+  const int nd = PASS <= 1 ? k + 1 : 1;
 #pragma unroll
   for (int j = 0; j < NJ; ++j) {
     if (j >= nd) break;
     const double S = rn_block_sum2(acc[j].hi, acc[j].lo, s_w);
     if (threadIdx.x == 0) pb[(int64_t)j * gridDim.x + blockIdx.x] = S;
   }
+}
+
+// The same pass with the number of basis vectors KP = k + 1 fixed at compile
+// time: every load of an element's KP basis values is issued before its
+// first use, and the KP partials of a block come from one reduction.  Same
+// arithmetic and order as k_gm_orth.
+template <int KP, int PASS, bool MIXED>
+__global__ __launch_bounds__(RN_BLOCK) void k_gm_orth_k(int64_t nnz, int64_t ubatch, int K, int k,
+                                                       double *__restrict__ Uall, float *__restrict__ U32all,
+                                                       double *__restrict__ part, const double *__restrict__ scal,
+                                                       int scal_stride, const int32_t *__restrict__ stv) {
+  constexpr int ND = PASS <= 1 ? KP : 1;
+  __shared__ double s_r[2 * ND * (RN_BLOCK / RN_WAVE)];
+  const int b = blockIdx.y;
+  const int32_t *st = stv + (int64_t)b * ST_STRIDE;
+  if (st[ST_STATUS] || st[ST_DONE]) return;
+  const double *sc = scal + (int64_t)b * scal_stride;
+  const GmLayout L(K);
+  double *U = Uall + (int64_t)b * ubatch;
+  double *W = U + (int64_t)(k + 1) * nnz;
+  double coef[KP];
+#pragma unroll
+  for (int j = 0; j < KP; ++j) coef[j] = PASS > 0 ? sc[(PASS == 1 ? L.h1 : L.h2) + j] * sc[L.s + j] : 0.0;
+  RnAcc acc[ND];
+  for (int64_t e = (int64_t)blockIdx.x * RN_BLOCK + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * RN_BLOCK) {
+    double u[KP];
+#pragma unroll
+    for (int j = 0; j < KP; ++j) u[j] = U[(int64_t)j * nnz + e];
+    double w = W[e];
+    if (PASS > 0) {
+#pragma unroll
+      for (int j = 0; j < KP; ++j) w -= coef[j] * u[j];
+      W[e] = w;
+    }
+    if (PASS <= 1) {
+#pragma unroll
+      for (int j = 0; j < KP; ++j) acc[j].add(w * u[j]);
+    } else {
+      acc[0].add(w * w);
+      if (MIXED) U32all[(int64_t)b * ubatch + (int64_t)(k + 1) * nnz + e] = (float)w;
+    }
+  }
+  double hi[ND], lo[ND];
+#pragma unroll
+  for (int j = 0; j < ND; ++j) {
+    hi[j] = acc[j].hi;
+    lo[j] = acc[j].lo;
+  }
+  double *pb = part + (int64_t)b * RN_MAXDOT * gridDim.x;
+  rn_block_sum2_multi<RN_BLOCK / RN_WAVE, ND>(hi, lo, ND, s_r, pb + blockIdx.x, gridDim.x);
+}
+
+template <int PASS, bool MIXED>
+static void gm_orth_k(int kp, dim3 g, dim3 bl, hipStream_t s, int64_t nz, int64_t ub, int K, int k, double *U,
+                      float *U32, double *part, double *scal, int scal_stride, int32_t *st) {
+#define GM_K(KP)                                                                                                   \
+  case KP:                                                                                                         \
+    hipLaunchKernelGGL((k_gm_orth_k<KP, PASS, MIXED>), g, bl, 0, s, nz, ub, K, k, U, U32, part, scal, scal_stride, \
+                       st);                                                                                        \
+    break;
+  switch (kp) {
+    GM_K(1) GM_K(2) GM_K(3) GM_K(4) GM_K(5) GM_K(6) GM_K(7) GM_K(8)
+    GM_K(9) GM_K(10) GM_K(11) GM_K(12) GM_K(13) GM_K(14) GM_K(15) GM_K(16)
+  }
+#undef GM_K
 }
 
 __global__ void k_gm_solve(int K, double *__restrict__ scal, int scal_stride, const int32_t *__restrict__ stv) {
@@ -278,6 +346,45 @@ __global__ __launch_bounds__(RN_BLOCK) void k_gm_combine(int64_t nnz, int64_t ub
   }
 }
 
+// The same combination with K fixed at compile time: vector j is read for
+// every j < K (the index clamped to the last vector the solve used, whose
+// coefficient is zero beyond it), so the K loads of an element are all in
+// flight before the first multiply-add.  Same arithmetic and order.
+template <int KP>
+__global__ __launch_bounds__(RN_BLOCK) void k_gm_combine_k(int64_t nnz, int64_t ubatch, const double *__restrict__ T,
+                                                          const double *__restrict__ Uall, double *__restrict__ P,
+                                                          const double *__restrict__ scal, int scal_stride,
+                                                          const int32_t *__restrict__ stv) {
+  const int b = blockIdx.y;
+  const int32_t *st = stv + (int64_t)b * ST_STRIDE;
+  const double *sc = scal + (int64_t)b * scal_stride;
+  const GmLayout L(KP);
+  const int kd = st[ST_STATUS] ? 0 : st[ST_KD];
+  double *Pb = P + (int64_t)b * nnz;
+  if (kd <= 0) {
+    for (int64_t e = (int64_t)blockIdx.x * RN_BLOCK + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * RN_BLOCK)
+      Pb[e] = T[e];
+    return;
+  }
+  const double *U = Uall + (int64_t)b * ubatch;
+  double c[KP];
+  const double *Uj[KP];
+#pragma unroll
+  for (int j = 0; j < KP; ++j) {
+    c[j] = j < kd ? sc[L.y + j] * sc[L.s + j] : 0.0;
+    Uj[j] = U + (int64_t)(j < kd ? j : kd - 1) * nnz;
+  }
+  for (int64_t e = (int64_t)blockIdx.x * RN_BLOCK + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * RN_BLOCK) {
+    double u[KP];
+#pragma unroll
+    for (int j = 0; j < KP; ++j) u[j] = Uj[j][e];
+    double v = T[e];
+#pragma unroll
+    for (int j = 0; j < KP; ++j) v += c[j] * u[j];
+    Pb[e] = v;
+  }
+}
+
 __global__ __launch_bounds__(RN_BLOCK) void k_to_f32(const double *__restrict__ src, int64_t n,
                                                     float *__restrict__ dst) {
   for (int64_t q = (int64_t)blockIdx.x * RN_BLOCK + threadIdx.x; q < n; q += (int64_t)gridDim.x * RN_BLOCK)
@@ -294,10 +401,12 @@ __global__ __launch_bounds__(RN_BLOCK) void k_bcast(const double *__restrict__ s
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
+// element-wise passes: two elements per lane and up to 2048 workgroups (8
+// per compute unit), enough loads in flight to stream HBM
 static unsigned ew_grid(int64_t n) {
-  unsigned g = rn_div_up(n, RN_BLOCK * 8);
+  unsigned g = rn_div_up(n, RN_BLOCK * 2);
   if (g < 1) g = 1;
-  if (g > 512) g = 512;
+  if (g > 2048) g = 2048;
   return g;
 }
 
@@ -480,12 +589,7 @@ extern "C" rn_status rn_energy_min(rn_ctx *ctx, rn_plan *pl, const double *A_val
       s.strideX = ub;
       s.Z = U + (int64_t)(k + 1) * nz;
       s.strideZ = ub;
-      s.U = U;
-      s.Ubatch = ub;
       RN_TRY(rn_launch_spgemm(ctx, pl, MODE_GM_STEP, s, batch, mixed));
-      hipLaunchKernelGGL(k_gm_fin<1>, dim3(batch), blk, 0, ctx->stream, pl->nblk, part_spg, K, k, p.scal,
-                         scal_stride, p.st, hist, hist_stride);
-      LAUNCH_CHECK(ctx);
 #define GM_ORTH(NJ, PASS)                                                                                       \
   if (mixed)                                                                                                    \
     hipLaunchKernelGGL((k_gm_orth<NJ, PASS, true>), g2, blk, 0, ctx->stream, nz, ub, K, k, U, U32, part_ew,      \
@@ -494,16 +598,29 @@ extern "C" rn_status rn_energy_min(rn_ctx *ctx, rn_plan *pl, const double *A_val
     hipLaunchKernelGGL((k_gm_orth<NJ, PASS, false>), g2, blk, 0, ctx->stream, nz, ub, K, k, U, U32, part_ew,     \
                        p.scal, scal_stride, p.st);                                                              \
   LAUNCH_CHECK(ctx);
-      if (K + 1 <= 16) {
-        GM_ORTH(16, 1);
+      if (k + 1 <= 16) {
+        gm_orth_k<0, false>(k + 1, g2, blk, ctx->stream, nz, ub, K, k, U, U32, part_ew, p.scal, scal_stride, p.st);
+        LAUNCH_CHECK(ctx);
+      } else {
+        GM_ORTH(65, 0);
+      }
+      hipLaunchKernelGGL(k_gm_fin<1>, dim3(k + 1, batch), blk, 0, ctx->stream, (int)gew, part_ew, K, k, p.scal,
+                         scal_stride, p.st, hist, hist_stride);
+      LAUNCH_CHECK(ctx);
+      if (k + 1 <= 16) {
+        if (mixed) gm_orth_k<1, true>(k + 1, g2, blk, ctx->stream, nz, ub, K, k, U, U32, part_ew, p.scal, scal_stride, p.st);
+        else gm_orth_k<1, false>(k + 1, g2, blk, ctx->stream, nz, ub, K, k, U, U32, part_ew, p.scal, scal_stride, p.st);
+        LAUNCH_CHECK(ctx);
       } else {
         GM_ORTH(65, 1);
       }
-      hipLaunchKernelGGL(k_gm_fin<2>, dim3(batch), blk, 0, ctx->stream, (int)gew, part_ew, K, k, p.scal, scal_stride,
+      hipLaunchKernelGGL(k_gm_fin<2>, dim3(k + 1, batch), blk, 0, ctx->stream, (int)gew, part_ew, K, k, p.scal, scal_stride,
                          p.st, hist, hist_stride);
       LAUNCH_CHECK(ctx);
-      if (K + 1 <= 16) {
-        GM_ORTH(16, 2);
+      if (k + 1 <= 16) {
+        if (mixed) gm_orth_k<2, true>(k + 1, g2, blk, ctx->stream, nz, ub, K, k, U, U32, part_ew, p.scal, scal_stride, p.st);
+        else gm_orth_k<2, false>(k + 1, g2, blk, ctx->stream, nz, ub, K, k, U, U32, part_ew, p.scal, scal_stride, p.st);
+        LAUNCH_CHECK(ctx);
       } else {
         GM_ORTH(65, 2);
       }
@@ -514,10 +631,17 @@ extern "C" rn_status rn_energy_min(rn_ctx *ctx, rn_plan *pl, const double *A_val
     }
     hipLaunchKernelGGL(k_gm_solve, dim3(batch), dim3(64), 0, ctx->stream, K, p.scal, scal_stride, p.st);
     LAUNCH_CHECK(ctx);
-    if (K + 1 <= 16)
-      hipLaunchKernelGGL(k_gm_combine<16>, g2, blk, 0, ctx->stream, nz, ub, K, T, U, P, p.scal, scal_stride, p.st);
-    else
-      hipLaunchKernelGGL(k_gm_combine<65>, g2, blk, 0, ctx->stream, nz, ub, K, T, U, P, p.scal, scal_stride, p.st);
+    switch (K) {
+#define GM_C(KP)                                                                                                \
+  case KP:                                                                                                      \
+    hipLaunchKernelGGL(k_gm_combine_k<KP>, g2, blk, 0, ctx->stream, nz, ub, T, U, P, p.scal, scal_stride, p.st); \
+    break;
+      GM_C(1) GM_C(2) GM_C(3) GM_C(4) GM_C(5) GM_C(6) GM_C(7) GM_C(8)
+      GM_C(9) GM_C(10) GM_C(11) GM_C(12) GM_C(13) GM_C(14) GM_C(15) GM_C(16)
+#undef GM_C
+      default:
+        hipLaunchKernelGGL(k_gm_combine<65>, g2, blk, 0, ctx->stream, nz, ub, K, T, U, P, p.scal, scal_stride, p.st);
+    }
     LAUNCH_CHECK(ctx);
   }
   // read back the device status of every batch entry and batch 0's scalars

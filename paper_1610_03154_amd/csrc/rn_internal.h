@@ -211,6 +211,45 @@ __device__ inline double rn_block_sum2_w(double hi, double lo, double *lds8) {
   return h + l;
 }
 __device__ inline double rn_block_sum2(double hi, double lo, double *lds8) { return rn_block_sum2_w<4>(hi, lo, lds8); }
+
+// NJ compensated block sums at once, each with the arithmetic of
+// rn_block_sum2_w (the same shuffle tree per wave, the waves combined in
+// order), one barrier for all: thread j < nd writes total j to out[j * ostride].
+// lds holds 2 * NJ * NW doubles.
+template <int NW, int NJ>
+__device__ inline void rn_block_sum2_multi(const double (&hi0)[NJ], const double (&lo0)[NJ], int nd, double *lds,
+                                           double *out, int64_t ostride) {
+  const int lane = threadIdx.x & (RN_WAVE - 1), wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) {
+    double hi = hi0[j], lo = lo0[j];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const double oh = __shfl_down(hi, off, RN_WAVE), ol = __shfl_down(lo, off, RN_WAVE);
+      double s, e;
+      rn_two_sum(hi, oh, s, e);
+      hi = s;
+      lo = lo + ol + e;
+    }
+    if (lane == 0) {
+      lds[(j * NW + wid) * 2] = hi;
+      lds[(j * NW + wid) * 2 + 1] = lo;
+    }
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < nd && (int)threadIdx.x < NJ) {
+    const int j = threadIdx.x;
+    double h = lds[(j * NW) * 2], l = lds[(j * NW) * 2 + 1];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) {
+      double s, e;
+      rn_two_sum(h, lds[(j * NW + w) * 2], s, e);
+      h = s;
+      l = l + lds[(j * NW + w) * 2 + 1] + e;
+    }
+    out[j * ostride] = h + l;
+  }
+}
 __device__ inline double rn_block_sum(double v, double *lds8) { return rn_block_sum2(v, 0.0, lds8); }
 
 // Ticket of the last block to finish: every block's thread 0 calls this

@@ -7,8 +7,10 @@
 // chunk, so it holds <= bs entries and whole rows.  The block's header (row,
 // entry and A ranges) is the only load the rest depends on.  Terms are added
 // one at a time in the order of A's row.  Per-row sums of the projection go
-// through LDS in pattern order.  Krylov dot products are fused into the
-// epilogue as per-block partials (no inter-block synchronisation).
+// through LDS in pattern order.  The CG dot products are fused into the
+// epilogue as per-block partials (no inter-block synchronisation); the GMRES
+// step only scales and stores its vector (its Gram-Schmidt dots run in their
+// own streaming passes).
 //
 // k_spgemm (every operator): one product block per workgroup; the block's
 // slice of A and the neighbour offsets are staged in LDS, X is gathered from
@@ -538,16 +540,6 @@ __global__ __launch_bounds__(BS) void k_spgemm(const SpgParams p) {
 #pragma unroll
     for (int o = 0; o < NO; ++o)
       if (zi[o] >= 0) spg_st(Z, (uint32_t)zi[o], z[o]);
-    const double *U = p.U + (int64_t)b * p.Ubatch;
-    for (int j = 0; j <= p.k; ++j) {
-      const double *Uj = U + (int64_t)j * p.nnzN;
-      RnAcc d;
-#pragma unroll
-      for (int o = 0; o < NO; ++o)
-        if (zi[o] >= 0) d.add(spg_ld(Uj, (uint32_t)zi[o]) * z[o]);
-      const double S = rn_block_sum2_w<BS / RN_WAVE>(d.hi, d.lo, s_w);
-      if (threadIdx.x == 0) part[(int64_t)j * p.nblk + blk] = S;
-    }
   }
 }
 
@@ -878,13 +870,6 @@ __global__ __launch_bounds__(BS) void k_spgemm_p(const SpgParams p, const int G)
       if (t == 0 && blk != blk0) part[blk] = 0.0;
     } else if (MODE == MODE_GM_STEP) {
       if (valid) spg_st(Z, e, z);
-      const double *U = p.U + (int64_t)b * p.Ubatch;
-      for (int j = 0; j <= p.k; ++j) {
-        RnAcc d;
-        if (valid) d.add(spg_ld(U + (int64_t)j * p.nnzN, e) * z);
-        const double S = rn_block_sum2_w<NWV>(d.hi, d.lo, s_w);
-        if (t == 0) part[(int64_t)j * p.nblk + blk] = S;
-      }
     }
     if (!more) break;
     // without the projection no barrier separates this block's LDS reads from
