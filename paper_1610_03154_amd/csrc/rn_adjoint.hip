@@ -530,11 +530,11 @@ extern "C" rn_status rn_energy_min_bwd(rn_ctx *ctx, rn_plan *pl, rn_plan *plT, c
   const int64_t nz = t->nz;
   // the forward's status and step count of every batch entry
   const size_t stb = (size_t)B * ST_STRIDE * 4;
-  void *hbuf = nullptr;
-  if (!(hbuf = rn_pinned(ctx, stb)))
-    return rn_fail(ctx, RN_ENOMEM, "rn_energy_min_bwd: pinned staging");
-  HIP_TRY(ctx, hipMemcpyAsync(hbuf, t->st, stb, hipMemcpyDeviceToHost, ctx->stream));
-  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  const RnFetch it[1] = {{t->st, stb}};
+  const unsigned char *hb = nullptr;
+  size_t off[1];
+  RN_TRY(rn_fetch(ctx, 1, it, &hb, off));
+  const void *hbuf = hb + off[0];
   int kmax = 0, bad = -1;
   for (int b = 0; b < B; ++b) {
     const int32_t *s = (const int32_t *)hbuf + b * ST_STRIDE;

@@ -86,23 +86,6 @@ void rn_dev_free(rn_ctx *ctx, void *p) {
   }
 }
 
-void *rn_pinned(rn_ctx *ctx, size_t bytes) {
-  if (ctx->pinned_big_cap >= bytes) return ctx->pinned_big;
-  if (ctx->pinned_big) {
-    (void)hipStreamSynchronize(ctx->stream);
-    (void)hipHostFree(ctx->pinned_big);
-    ctx->pinned_big = nullptr;
-    ctx->pinned_big_cap = 0;
-  }
-  const size_t cap = bytes + bytes / 2 + 256;
-  if (hipHostMalloc(&ctx->pinned_big, cap, hipHostMallocDefault) != hipSuccess) {
-    ctx->pinned_big = nullptr;
-    return nullptr;
-  }
-  ctx->pinned_big_cap = cap;
-  return ctx->pinned_big;
-}
-
 void *rn_scratch(rn_ctx *ctx, int slot, size_t bytes, rn_status *st) {
   RnScratch &s = ctx->slot[slot];
   if (bytes == 0) bytes = 16;
@@ -123,10 +106,78 @@ void *rn_scratch(rn_ctx *ctx, int slot, size_t bytes, rn_status *st) {
   return s.ptr;
 }
 
-rn_status rn_read_i64(rn_ctx *ctx, const void *dev, int64_t *out) {
-  HIP_TRY(ctx, hipMemcpyAsync(ctx->pinned, dev, sizeof(int64_t), hipMemcpyDeviceToHost, ctx->stream));
+struct FetchArgs {
+  const uint32_t *src[RN_FETCH_MAX];
+  int32_t words[RN_FETCH_MAX];
+  int32_t off[RN_FETCH_MAX];  // in 4-byte words
+  int n;
+};
+
+__global__ __launch_bounds__(RN_BLOCK) void k_fetch(const FetchArgs a, uint32_t *__restrict__ dst) {
+  for (int i = 0; i < a.n; ++i)
+    for (int q = threadIdx.x; q < a.words[i]; q += RN_BLOCK) dst[a.off[i] + q] = a.src[i][q];
+}
+
+rn_status rn_fetch(rn_ctx *ctx, int n, const RnFetch *items, const unsigned char **host, size_t *off) {
+  if (n < 0 || n > RN_FETCH_MAX) return rn_fail(ctx, RN_EINVAL, "rn_fetch: %d items", n);
+  size_t total = 0;
+  for (int i = 0; i < n; ++i) {
+    if (((uintptr_t)items[i].src & 3) || (items[i].bytes & 3) || items[i].bytes >= ((size_t)1 << 31))
+      return rn_fail(ctx, RN_EINVAL, "rn_fetch: misaligned item");
+    off[i] = total;
+    total += (items[i].bytes + 7) & ~(size_t)7;
+  }
+  if (total > ctx->rb_cap) {
+    if (ctx->rb_host) {
+      HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+      (void)hipHostFree(ctx->rb_host);
+      ctx->rb_host = nullptr;
+      ctx->rb_dev = nullptr;
+      ctx->rb_cap = 0;
+    }
+    const size_t cap = total < 4096 ? 4096 : total + total / 2;
+    if (hipHostMalloc((void **)&ctx->rb_host, cap, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
+      (void)hipGetLastError();
+      ctx->rb_host = nullptr;
+      return rn_fail(ctx, RN_ENOMEM, "rn_fetch: pinned read-back area of %zu bytes", cap);
+    }
+    ctx->rb_cap = cap;
+    void *d = nullptr;
+    if (hipHostGetDevicePointer(&d, ctx->rb_host, 0) != hipSuccess) {
+      (void)hipGetLastError();
+      d = nullptr;
+    }
+    ctx->rb_dev = d;
+  }
+  if (ctx->rb_dev) {
+    FetchArgs a{};
+    a.n = n;
+    for (int i = 0; i < n; ++i) {
+      a.src[i] = (const uint32_t *)items[i].src;
+      a.words[i] = (int32_t)(items[i].bytes / 4);
+      a.off[i] = (int32_t)(off[i] / 4);
+    }
+    if (n > 0) {
+      hipLaunchKernelGGL(k_fetch, dim3(1), dim3(RN_BLOCK), 0, ctx->stream, a, (uint32_t *)ctx->rb_dev);
+      LAUNCH_CHECK(ctx);
+    }
+  } else {
+    for (int i = 0; i < n; ++i)
+      if (items[i].bytes)
+        HIP_TRY(ctx, hipMemcpyAsync(ctx->rb_host + off[i], items[i].src, items[i].bytes, hipMemcpyDeviceToHost,
+                                    ctx->stream));
+  }
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-  *out = ctx->pinned[0];
+  *host = ctx->rb_host;
+  return RN_OK;
+}
+
+rn_status rn_read_i64(rn_ctx *ctx, const void *dev, int64_t *out) {
+  const RnFetch it[1] = {{dev, sizeof(int64_t)}};
+  const unsigned char *h = nullptr;
+  size_t off[1];
+  RN_TRY(rn_fetch(ctx, 1, it, &h, off));
+  memcpy(out, h + off[0], sizeof(int64_t));
   return RN_OK;
 }
 
@@ -316,10 +367,6 @@ extern "C" rn_status rn_create(rn_ctx **out, void *stream) {
     delete ctx;
     return RN_EHIP;
   }
-  if (hipHostMalloc((void **)&ctx->pinned, 64 * sizeof(int64_t), hipHostMallocDefault) != hipSuccess) {
-    delete ctx;
-    return RN_ENOMEM;
-  }
   *out = ctx;
   return RN_OK;
 }
@@ -334,8 +381,7 @@ extern "C" void rn_destroy(rn_ctx *ctx) {
   cache_release(ctx, 0);
   for (int s = 0; s < SLOT_COUNT; ++s)
     if (ctx->slot[s].ptr) (void)hipFree(ctx->slot[s].ptr);
-  if (ctx->pinned) (void)hipHostFree(ctx->pinned);
-  if (ctx->pinned_big) (void)hipHostFree(ctx->pinned_big);
+  if (ctx->rb_host) (void)hipHostFree(ctx->rb_host);
   delete ctx;
 }
 
@@ -462,16 +508,25 @@ static rn_status guard_message(rn_ctx *ctx, int32_t g, const char *what) {
                  (g & GUARD_ROOTS) ? "roots" : "");
 }
 
+rn_status rn_guard_status(rn_ctx *ctx, int32_t g, const char *what) { return guard_message(ctx, g, what); }
+
 rn_status rn_check_guard(rn_ctx *ctx, const int32_t *guard, const char *what) {
-  HIP_TRY(ctx, hipMemcpyAsync(ctx->pinned, guard, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
-  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-  return guard_message(ctx, ((int32_t *)ctx->pinned)[0], what);
+  const RnFetch it[1] = {{guard, sizeof(int32_t)}};
+  const unsigned char *h = nullptr;
+  size_t off[1];
+  RN_TRY(rn_fetch(ctx, 1, it, &h, off));
+  int32_t g;
+  memcpy(&g, h + off[0], sizeof(g));
+  return guard_message(ctx, g, what);
 }
 
 rn_status rn_read_guard_i64(rn_ctx *ctx, const int32_t *guard, const void *dev, int64_t *out, const char *what) {
-  HIP_TRY(ctx, hipMemcpyAsync(ctx->pinned, dev, sizeof(int64_t), hipMemcpyDeviceToHost, ctx->stream));
-  HIP_TRY(ctx, hipMemcpyAsync(ctx->pinned + 1, guard, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
-  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-  *out = ctx->pinned[0];
-  return guard_message(ctx, ((int32_t *)(ctx->pinned + 1))[0], what);
+  const RnFetch it[2] = {{dev, sizeof(int64_t)}, {guard, sizeof(int32_t)}};
+  const unsigned char *h = nullptr;
+  size_t off[2];
+  RN_TRY(rn_fetch(ctx, 2, it, &h, off));
+  memcpy(out, h + off[0], sizeof(int64_t));
+  int32_t g;
+  memcpy(&g, h + off[1], sizeof(g));
+  return guard_message(ctx, g, what);
 }

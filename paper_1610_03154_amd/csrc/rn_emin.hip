@@ -646,21 +646,13 @@ extern "C" rn_status rn_energy_min(rn_ctx *ctx, rn_plan *pl, const double *A_val
   }
   // read back the device status of every batch entry and batch 0's scalars
   const size_t stb = (size_t)batch * ST_STRIDE * 4;
-  const size_t need = stb + (size_t)scal_stride * 8 + 16;
-  int64_t *hp = ctx->pinned;
-  void *big = nullptr;
-  if (need > 64 * sizeof(int64_t)) {
-    if (!(big = rn_pinned(ctx, need)))
-      return rn_fail(ctx, RN_ENOMEM, "rn_energy_min: pinned staging");
-    hp = (int64_t *)big;
-  }
-  unsigned long long *hterms = (unsigned long long *)((char *)hp + stb + (size_t)scal_stride * 8);
-  HIP_TRY(ctx, hipMemcpyAsync(hp, p.st, stb, hipMemcpyDeviceToHost, ctx->stream));
-  HIP_TRY(ctx, hipMemcpyAsync((char *)hp + stb, p.scal, (size_t)scal_stride * 8, hipMemcpyDeviceToHost, ctx->stream));
-  HIP_TRY(ctx, hipMemcpyAsync(hterms, pl->d_terms, 8, hipMemcpyDeviceToHost, ctx->stream));
-  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-  const int32_t *hst = (const int32_t *)hp;
-  const double *hsc = (const double *)((const char *)hp + stb);
+  const RnFetch it[3] = {{p.st, stb}, {p.scal, (size_t)scal_stride * 8}, {pl->d_terms, 8}};
+  const unsigned char *hb = nullptr;
+  size_t off[3];
+  RN_TRY(rn_fetch(ctx, 3, it, &hb, off));
+  const int32_t *hst = (const int32_t *)(hb + off[0]);
+  const double *hsc = (const double *)(hb + off[1]);
+  const unsigned long long *hterms = (const unsigned long long *)(hb + off[2]);
   rn_status res = RN_OK;
   int bad = -1;
   for (int b = 0; b < batch; ++b)

@@ -55,20 +55,31 @@ struct RnScratch {
   size_t cap = 0;
 };
 
+// One level of the pattern expansion: CSR (row pointers p) or padded (row J
+// at J * stride, its length in c[J], or 1 when c is NULL).
+struct XRows {
+  const int32_t *p;
+  const int32_t *v;
+  const int32_t *c;
+  int stride;
+};
+
 struct rn_ctx {
   hipStream_t stream = nullptr;
   int device = 0;
   std::string err;
   RnScratch slot[SLOT_COUNT];
-  int64_t *pinned = nullptr;  // small pinned host staging area (64 x int64)
-  void *pinned_big = nullptr;  // grow-only pinned staging for larger read-backs
-  size_t pinned_big_cap = 0;
+  // read-back area (rn_fetch): host-coherent pinned memory the device writes
+  // directly (rb_dev = its device address, NULL when it cannot be mapped)
+  unsigned char *rb_host = nullptr;
+  void *rb_dev = nullptr;
+  size_t rb_cap = 0;
   // two-phase caches
   int64_t str_nnz = -1;
   int32_t str_nodes = -1;
   int64_t pat_nnz = -1;        // nnz of the DOF pattern
   int32_t pat_n = -1;          // rows of the DOF pattern
-  int pat_buf = 0;             // which of XP0/XP1 holds the final nodal pattern
+  XRows pat_x{};               // the final nodal level (read by phase 2)
   int32_t pat_m = 1;
   // live plans made on this context: rn_destroy detaches them, so a plan
   // destroyed after its context frees its memory without touching the context
@@ -111,8 +122,20 @@ rn_status rn_fail(rn_ctx *ctx, rn_status st, const char *fmt, ...);
 void *rn_dev_alloc(rn_ctx *ctx, size_t bytes);
 void rn_dev_free(rn_ctx *ctx, void *p);
 
-// Grow-only pinned host staging of at least `bytes` (NULL on failure).
-void *rn_pinned(rn_ctx *ctx, size_t bytes);
+// Read-back of small device values at a synchronisation point: n <= 6 items
+// (device address, size in bytes, both multiples of 4) copied by one kernel
+// into the context's host read-back area, then the stream is synchronised.
+// Item i lands at (*host) + off[i]; offsets are 8-byte aligned and in order.
+// The area is valid until the next rn_fetch on the context.
+#define RN_FETCH_MAX 6
+struct RnFetch {
+  const void *src;
+  size_t bytes;
+};
+rn_status rn_fetch(rn_ctx *ctx, int n, const RnFetch *items, const unsigned char **host, size_t *off);
+
+// The error of a guard word read back from the device (RN_OK when 0).
+rn_status rn_guard_status(rn_ctx *ctx, int32_t g, const char *what);
 
 // Grow-only scratch; contents are not preserved on growth.
 void *rn_scratch(rn_ctx *ctx, int slot, size_t bytes, rn_status *st);

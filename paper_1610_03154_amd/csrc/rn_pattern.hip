@@ -1,6 +1,7 @@
 // rn_pattern.hip -- strength of connection (Sec. 3.2) and the interpolation
 // pattern N = S^d C with unamalgamation and root rows (Sec. 3.4).
 // Integer work: results are bit-exact by construction (sorted, unique rows).
+#include <cstring>
 #include <climits>
 #include "rn_internal.h"
 
@@ -137,65 +138,130 @@ static unsigned grid_for(int64_t n, unsigned cap = 8192) {
   return g > cap ? cap : g;
 }
 
+// Row-wise kernels below give each row a group of SG lanes that read the
+// row's entries side by side (SG consecutive entries per load instead of one
+// entry of SG different rows).
+#define SG 8
+#define SRPB (RN_BLOCK / SG)
+
+// diagonal of a scalar CSR matrix (0 where it is not stored)
+__global__ __launch_bounds__(RN_BLOCK) void k_diag_csr_g(int n, const int32_t *__restrict__ Ap,
+                                                        const int32_t *__restrict__ Aj,
+                                                        const double *__restrict__ Ax, double *__restrict__ diag,
+                                                        const int32_t *__restrict__ guard) {
+  const int g = threadIdx.x / SG, l = threadIdx.x % SG;
+  const int i = blockIdx.x * SRPB + g;
+  if (i >= n || *guard) return;
+  double d = 0.0;
+  bool hit = false;
+  for (int p = Ap[i] + l; p < Ap[i + 1]; p += SG)
+    if (Aj[p] == i) {
+      d = Ax[p];
+      hit = true;
+    }
+  // a stored diagonal is unique in its (sorted, duplicate-free) row
+  const unsigned long long who = __ballot(hit);
+  const int base = threadIdx.x & (RN_WAVE - 1) & ~(SG - 1);
+  const unsigned long long mine = (who >> base) & ((1ull << SG) - 1);
+  if (l == 0 && !mine) diag[i] = 0.0;
+  if (hit) diag[i] = d;
+}
+
 // Strong set of node row I made symmetric through A's own structure: entry
 // (I,J) is kept when it or its partner (J,I) is strong.  Valid when A is
 // structurally symmetric; a missing partner sets *asym (the caller then takes
 // the transpose path).  cnt[I] counts the kept entries plus the diagonal when
-// it is not stored.
-__global__ __launch_bounds__(RN_BLOCK) void k_partner_mask(int nn, const int32_t *__restrict__ Ap,
-                                                          const int32_t *__restrict__ Aj,
-                                                          const uint8_t *__restrict__ mask,
-                                                          uint8_t *__restrict__ symmask, int32_t *__restrict__ cnt,
-                                                          int32_t *__restrict__ asym,
-                                                          const int32_t *__restrict__ guard) {
-  const int I = blockIdx.x * RN_BLOCK + threadIdx.x;
+// it is not stored.  INL: block_m = 1, the strength tested inline from A's
+// values and diagonal (no mask array); otherwise the node mask of
+// k_strong_bsr.
+template <bool INL>
+__global__ __launch_bounds__(RN_BLOCK) void k_partner_g(int nn, const int32_t *__restrict__ Ap,
+                                                       const int32_t *__restrict__ Aj,
+                                                       const double *__restrict__ Ax,
+                                                       const double *__restrict__ diag, double th2,
+                                                       const uint8_t *__restrict__ mask,
+                                                       uint8_t *__restrict__ symmask, int32_t *__restrict__ cnt,
+                                                       int32_t *__restrict__ asym,
+                                                       const int32_t *__restrict__ guard) {
+  const int g = threadIdx.x / SG, l = threadIdx.x % SG;
+  const int I = blockIdx.x * SRPB + g;
   if (*guard) {
-    if (I < nn) cnt[I] = 0;
+    if (I < nn && l == 0) cnt[I] = 0;
     return;
   }
-  bool missing = false;
+  bool missing = false, hasd = false;
+  int c = 0;
   if (I < nn) {
-    int c = 0;
-    bool diag = false;
-    for (int p = Ap[I]; p < Ap[I + 1]; ++p) {
+    const double di = INL ? diag[I] : 0.0;
+    for (int p = Ap[I] + l; p < Ap[I + 1]; p += SG) {
       const int J = Aj[p];
-      bool s = mask[p];
+      bool s;
       if (J == I) {
-        diag = true;
+        hasd = true;
+        s = INL ? true : mask[p];
       } else {
+        const double dj = INL ? diag[J] : 0.0;
+        s = INL ? rn_is_strong(Ax[p], di, dj, th2, false) : mask[p];
         int lo = Ap[J], hi = Ap[J + 1];
         while (lo < hi) {
           const int mid = (lo + hi) >> 1;
           if (Aj[mid] < I) lo = mid + 1; else hi = mid;
         }
-        if (lo < Ap[J + 1] && Aj[lo] == I) s = s || mask[lo];
+        if (lo < Ap[J + 1] && Aj[lo] == I) s = s || (INL ? rn_is_strong(Ax[lo], dj, di, th2, false) : mask[lo]);
         else missing = true;
       }
       symmask[p] = s;
       c += s;
     }
-    cnt[I] = c + (diag ? 0 : 1);
   }
+#pragma unroll
+  for (int off = SG / 2; off > 0; off >>= 1) c += __shfl_xor(c, off, SG);
+  const unsigned long long dh = __ballot(hasd);
+  const int base = threadIdx.x & (RN_WAVE - 1) & ~(SG - 1);
+  const bool rowd = ((dh >> base) & ((1ull << SG) - 1)) != 0;
+  if (I < nn && l == 0) cnt[I] = c + (rowd ? 0 : 1);
   if (__any(missing) && (threadIdx.x & (RN_WAVE - 1)) == 0) atomicOr(asym, 1);
 }
 
-__global__ __launch_bounds__(RN_BLOCK) void k_partner_fill(int nn, const int32_t *__restrict__ Ap,
-                                                          const int32_t *__restrict__ Aj,
-                                                          const uint8_t *__restrict__ symmask,
-                                                          const int32_t *__restrict__ Sp, int32_t *__restrict__ Sj) {
-  const int I = blockIdx.x * RN_BLOCK + threadIdx.x;
-  if (I >= nn) return;
-  int w = Sp[I];
-  bool placed = false;
-  for (int p = Ap[I]; p < Ap[I + 1]; ++p) {
-    const int J = Aj[p];
-    if (!placed && J >= I) {
-      if (J != I) Sj[w++] = I;  // diagonal not stored: insert it in order
-      placed = true;
+// Row I of S: the kept entries in order, the diagonal inserted before the
+// first column above I when A does not store it.
+__global__ __launch_bounds__(RN_BLOCK) void k_partner_fill_g(int nn, const int32_t *__restrict__ Ap,
+                                                            const int32_t *__restrict__ Aj,
+                                                            const uint8_t *__restrict__ symmask,
+                                                            const int32_t *__restrict__ Sp,
+                                                            int32_t *__restrict__ Sj) {
+  const int g = threadIdx.x / SG, l = threadIdx.x % SG;
+  const int I = blockIdx.x * SRPB + g;
+  const bool ok = I < nn;
+  const int s = ok ? Ap[I] : 0, e = ok ? Ap[I + 1] : 0;
+  const int base = threadIdx.x & (RN_WAVE - 1) & ~(SG - 1);
+  const unsigned long long gm = ((1ull << SG) - 1) << base;
+  // is the diagonal stored?
+  bool hd = false;
+  for (int p = s + l; p < e; p += SG) hd = hd || Aj[p] == I;
+  const bool rowd = (__ballot(hd) & gm) != 0;
+  int w = ok ? Sp[I] : 0;
+  int nless = 0;  // kept entries below the diagonal (where the missing one goes)
+  for (int c0 = s; c0 < e; c0 += SG) {
+    const int p = c0 + l;
+    int J = 0;
+    bool keep = false;
+    if (p < e) {
+      J = Aj[p];
+      keep = symmask[p] || J == I;
     }
-    if (symmask[p] || J == I) Sj[w++] = J;
+    const unsigned long long kb = __ballot(keep) & gm;
+    const int before = __popcll(kb & ((1ull << (base + l)) - 1) & gm);
+    if (keep) {
+      const int ins = (!rowd && J > I) ? 1 : 0;
+      Sj[w + before + ins] = J;
+      if (J < I) ++nless;
+    }
+    w += __popcll(kb);
   }
-  if (!placed) Sj[w++] = I;
+#pragma unroll
+  for (int off = SG / 2; off > 0; off >>= 1) nless += __shfl_xor(nless, off, SG);
+  if (ok && !rowd && l == 0) Sj[Sp[I] + nless] = I;
 }
 
 static rn_status strength_transpose_path(rn_ctx *ctx, const rn_matrix *A, double theta, int32_t *S_rowptr,
@@ -227,31 +293,38 @@ extern "C" rn_status rn_strength(rn_ctx *ctx, const rn_matrix *A, double theta, 
   RN_TRY(rn_validate_csr(ctx, nn, nn, nz, A->rowptr, A->colind, guard, GUARD_A));
   const double th2 = theta * theta;
   const dim3 g(rn_div_up(nn > 0 ? nn : 1, RN_BLOCK)), b(RN_BLOCK);
+  const dim3 gg(rn_div_up(nn > 0 ? nn : 1, SRPB));
   if (nn > 0) {
     if (m == 1) {
-      hipLaunchKernelGGL(k_diag_csr, g, b, 0, ctx->stream, nn, A->rowptr, A->colind, A->vals, diag, guard);
-      hipLaunchKernelGGL(k_strong_csr, g, b, 0, ctx->stream, nn, A->rowptr, A->colind, A->vals, diag, th2, mask,
-                         guard);
+      hipLaunchKernelGGL(k_diag_csr_g, gg, b, 0, ctx->stream, nn, A->rowptr, A->colind, A->vals, diag, guard);
+      hipLaunchKernelGGL(k_partner_g<true>, gg, b, 0, ctx->stream, nn, A->rowptr, A->colind,
+                         (const double *)A->vals, diag, th2, (const uint8_t *)nullptr, symmask, cnt, asym, guard);
     } else {
       hipLaunchKernelGGL(k_diag_bsr, g, b, 0, ctx->stream, nn, A->rowptr, A->colind, A->vals, diag, guard);
       hipLaunchKernelGGL(k_strong_bsr, g, b, 0, ctx->stream, nn, A->rowptr, A->colind, A->vals, diag, th2, mask,
                          guard);
+      hipLaunchKernelGGL(k_partner_g<false>, gg, b, 0, ctx->stream, nn, A->rowptr, A->colind,
+                         (const double *)nullptr, (const double *)nullptr, th2, mask, symmask, cnt, asym, guard);
     }
-    hipLaunchKernelGGL(k_partner_mask, g, b, 0, ctx->stream, nn, A->rowptr, A->colind, mask, symmask, cnt, asym,
-                       guard);
     LAUNCH_CHECK(ctx);
   }
   RN_TRY(rn_scan_counts(ctx, cnt, S_rowptr, nn, nullptr));
   // one synchronisation: total, guard and the structural-asymmetry flag
-  int32_t *hasym = (int32_t *)(ctx->pinned + 6);
-  HIP_TRY(ctx, hipMemcpyAsync(hasym, asym, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
+  const RnFetch it[3] = {{ctx->slot[SLOT_SCAN_TOTAL].ptr, sizeof(int64_t)}, {guard, 4}, {asym, 4}};
+  const unsigned char *hb = nullptr;
+  size_t off[3];
+  RN_TRY(rn_fetch(ctx, 3, it, &hb, off));
   int64_t total = 0;
-  RN_TRY(rn_read_guard_i64(ctx, guard, ctx->slot[SLOT_SCAN_TOTAL].ptr, &total, "rn_strength"));
-  if (*hasym) return strength_transpose_path(ctx, A, theta, S_rowptr, nullptr, nnz_S);
+  int32_t gword = 0, hasym = 0;
+  memcpy(&total, hb + off[0], 8);
+  memcpy(&gword, hb + off[1], 4);
+  memcpy(&hasym, hb + off[2], 4);
+  RN_TRY(rn_guard_status(ctx, gword, "rn_strength"));
+  if (hasym) return strength_transpose_path(ctx, A, theta, S_rowptr, nullptr, nnz_S);
   int32_t *Sj = (int32_t *)rn_scratch(ctx, SLOT_STR_SJ, (size_t)(total + 1) * sizeof(int32_t), &st);
   if (!Sj) return st;
   if (nn > 0) {
-    hipLaunchKernelGGL(k_partner_fill, g, b, 0, ctx->stream, nn, A->rowptr, A->colind, symmask, S_rowptr, Sj);
+    hipLaunchKernelGGL(k_partner_fill_g, gg, b, 0, ctx->stream, nn, A->rowptr, A->colind, symmask, S_rowptr, Sj);
     LAUNCH_CHECK(ctx);
   }
   ctx->str_nnz = total;
@@ -350,19 +423,35 @@ static rn_status strength_transpose_path(rn_ctx *ctx, const rn_matrix *A, double
 // rows X_t(J)) are staged in an LDS window of ECAP entries, deduplicated by
 // first occurrence and placed by rank.  Rows with more candidates go to a
 // device-side list that a second kernel works through with one block per
-// row and a window of BCAP entries.  COUNT passes write row sizes, FILL
-// passes the sorted columns.
+// row and a window of BCAP entries.
+// A level is held either as CSR (row pointers) or padded: row J at J * PCAP
+// with its length in a count array (level 0, C itself, is the aggregate map:
+// stride 1, length 1).  Modes: EX_COUNT writes row sizes, EX_FILL the sorted
+// columns of a CSR level whose row pointers are known, EX_PAD the sorted
+// columns and the size of a padded level in one pass (no host round trip
+// between levels); a padded row longer than PCAP raises *pflag and the
+// caller redoes the expansion with CSR levels.
 // ---------------------------------------------------------------------------
 #define EG 8
 #define ECAP 64
 #define ERPB (RN_BLOCK / EG)
 #define BCAP 6144
+#define PCAP 64
+enum { EX_COUNT = 0, EX_FILL = 1, EX_PAD = 2 };
 
-template <bool FILL>
+__device__ inline void x_row(const XRows &X, int J, int64_t &s, int &len) {
+  if (X.p) {
+    s = X.p[J];
+    len = X.p[J + 1] - (int)s;
+  } else {
+    s = (int64_t)J * X.stride;
+    len = X.c ? X.c[J] : 1;
+  }
+}
+
+template <int MODE>
 __global__ __launch_bounds__(RN_BLOCK) void k_expand(int nn, const int32_t *__restrict__ Sp,
-                                                    const int32_t *__restrict__ Sj,
-                                                    const int32_t *__restrict__ Xp,
-                                                    const int32_t *__restrict__ Xj,
+                                                    const int32_t *__restrict__ Sj, const XRows X,
                                                     int32_t *__restrict__ cnt_or_ptr,
                                                     int32_t *__restrict__ Yj, int32_t *__restrict__ ovf,
                                                     int32_t *__restrict__ ovf_n,
@@ -372,7 +461,7 @@ __global__ __launch_bounds__(RN_BLOCK) void k_expand(int nn, const int32_t *__re
   const int g = threadIdx.x / EG, l = threadIdx.x % EG;
   const int I = blockIdx.x * ERPB + g;
   if (*guard) {
-    if (!FILL && I < nn && l == 0) cnt_or_ptr[I] = 0;
+    if (MODE != EX_FILL && I < nn && l == 0) cnt_or_ptr[I] = 0;
     return;
   }
   const bool ok = I < nn;
@@ -381,12 +470,9 @@ __global__ __launch_bounds__(RN_BLOCK) void k_expand(int nn, const int32_t *__re
     const int s = Sp[I], e = Sp[I + 1];
     for (int c0 = s; c0 < e; c0 += EG) {
       const int p = c0 + l;
-      int len = 0, xs = 0;
-      if (p < e) {
-        const int J = Sj[p];
-        xs = Xp[J];
-        len = Xp[J + 1] - xs;
-      }
+      int len = 0;
+      int64_t xs = 0;
+      if (p < e) x_row(X, Sj[p], xs, len);
       int inc = len;
 #pragma unroll
       for (int off = 1; off < EG; off <<= 1) {
@@ -397,7 +483,7 @@ __global__ __launch_bounds__(RN_BLOCK) void k_expand(int nn, const int32_t *__re
       const int tot = __shfl(inc, EG - 1, EG);
       for (int q = 0; q < len; ++q) {
         const int pos = excl + q;
-        if (pos < ECAP) cand[g][pos] = Xj[xs + q];
+        if (pos < ECAP) cand[g][pos] = X.v[xs + q];
       }
       L += tot;
     }
@@ -431,12 +517,13 @@ __global__ __launch_bounds__(RN_BLOCK) void k_expand(int nn, const int32_t *__re
   __syncthreads();
   if (!ok) return;
   if (L > ECAP) {  // the large-window kernel takes the row
-    if (!FILL && l == 0) {
+    if (MODE != EX_FILL && l == 0) {
       cnt_or_ptr[I] = 0;
       ovf[atomicAdd(ovf_n, 1)] = I;
     }
     return;
   }
+  // (a padded row here holds at most L <= ECAP = PCAP columns)
   if (bm) {
     unsigned long long bits = 0ull;
     for (int c = 0; c < Lc; ++c) {
@@ -450,10 +537,9 @@ __global__ __launch_bounds__(RN_BLOCK) void k_expand(int nn, const int32_t *__re
       const int t = __shfl_up(inc, off, EG);
       if (l >= off) inc += t;
     }
-    if (!FILL) {
-      if (l == EG - 1) cnt_or_ptr[I] = inc;
-    } else {
-      int pos = cnt_or_ptr[I] + inc - cl;
+    if (MODE != EX_FILL && l == EG - 1) cnt_or_ptr[I] = inc;
+    if (MODE != EX_COUNT) {
+      int64_t pos = (MODE == EX_FILL ? (int64_t)cnt_or_ptr[I] : (int64_t)I * PCAP) + inc - cl;
       while (bits) {
         const int bit = __ffsll(bits) - 1;
         bits &= bits - 1ull;
@@ -462,14 +548,15 @@ __global__ __launch_bounds__(RN_BLOCK) void k_expand(int nn, const int32_t *__re
     }
     return;
   }
-  if (!FILL) {
+  if (MODE != EX_FILL) {
     int mc = 0;
     for (int c = l; c < Lc; c += EG) mc += first[g][c];
 #pragma unroll
     for (int off = EG / 2; off > 0; off >>= 1) mc += __shfl_xor(mc, off, EG);
     if (l == 0) cnt_or_ptr[I] = mc;
-  } else {
-    const int base = cnt_or_ptr[I];
+  }
+  if (MODE != EX_COUNT) {
+    const int64_t base = MODE == EX_FILL ? (int64_t)cnt_or_ptr[I] : (int64_t)I * PCAP;
     for (int c = l; c < Lc; c += EG) {
       if (!first[g][c]) continue;
       const int v = cand[g][c];
@@ -480,19 +567,18 @@ __global__ __launch_bounds__(RN_BLOCK) void k_expand(int nn, const int32_t *__re
   }
 }
 
-// The rows listed by k_expand<false>: one block per row, grid-stride over the
-// list (its length is read on the device, so no host round trip).  A row
-// with more than BCAP candidates sets GUARD_LIMIT.
-template <bool FILL>
+// The rows listed by k_expand: one block per row, grid-stride over the list
+// (its length is read on the device, so no host round trip).  A row with
+// more than BCAP candidates sets GUARD_LIMIT (CSR levels) or *pflag (padded
+// levels, which are then redone as CSR).
+template <int MODE>
 __global__ __launch_bounds__(RN_BLOCK) void k_expand_big(const int32_t *__restrict__ Sp,
-                                                        const int32_t *__restrict__ Sj,
-                                                        const int32_t *__restrict__ Xp,
-                                                        const int32_t *__restrict__ Xj,
+                                                        const int32_t *__restrict__ Sj, const XRows X,
                                                         int32_t *__restrict__ cnt_or_ptr,
                                                         int32_t *__restrict__ Yj,
                                                         const int32_t *__restrict__ ovf,
                                                         const int32_t *__restrict__ ovf_n,
-                                                        int32_t *__restrict__ guard) {
+                                                        int32_t *__restrict__ guard, int32_t *__restrict__ pflag) {
   __shared__ int32_t cand[BCAP];
   __shared__ uint8_t first[BCAP];
   __shared__ int s_len[RN_BLOCK];
@@ -506,12 +592,9 @@ __global__ __launch_bounds__(RN_BLOCK) void k_expand_big(const int32_t *__restri
     int L = 0;
     for (int c0 = s; c0 < e; c0 += RN_BLOCK) {
       const int p = c0 + t;
-      int len = 0, xs = 0;
-      if (p < e) {
-        const int J = Sj[p];
-        xs = Xp[J];
-        len = Xp[J + 1] - xs;
-      }
+      int len = 0;
+      int64_t xs = 0;
+      if (p < e) x_row(X, Sj[p], xs, len);
       __syncthreads();
       s_len[t] = len;
       __syncthreads();
@@ -523,15 +606,16 @@ __global__ __launch_bounds__(RN_BLOCK) void k_expand_big(const int32_t *__restri
       }
       for (int w = 0; w < len; ++w) {
         const int pos = L + excl + w;
-        if (pos < BCAP) cand[pos] = Xj[xs + w];
+        if (pos < BCAP) cand[pos] = X.v[xs + w];
       }
       L += tot;
     }
     __syncthreads();
     if (L > BCAP) {
       if (t == 0) {
-        atomicOr(guard, GUARD_LIMIT);
-        if (!FILL) cnt_or_ptr[I] = 0;
+        if (MODE == EX_PAD) atomicOr(pflag, 1);
+        else atomicOr(guard, GUARD_LIMIT);
+        if (MODE != EX_FILL) cnt_or_ptr[I] = 0;
       }
       continue;
     }
@@ -543,16 +627,20 @@ __global__ __launch_bounds__(RN_BLOCK) void k_expand_big(const int32_t *__restri
       first[c] = f;
     }
     __syncthreads();
-    if (!FILL) {
+    int total = 0;
+    if (MODE != EX_FILL) {
       int mc = 0;
       for (int c = t; c < L; c += RN_BLOCK) mc += first[c];
 #pragma unroll
       for (int off = 32; off > 0; off >>= 1) mc += __shfl_xor(mc, off, RN_WAVE);
       if ((t & (RN_WAVE - 1)) == 0) s_red[t / RN_WAVE] = mc;
       __syncthreads();
-      if (t == 0) cnt_or_ptr[I] = s_red[0] + s_red[1] + s_red[2] + s_red[3];
-    } else {
-      const int base = cnt_or_ptr[I];
+      total = s_red[0] + s_red[1] + s_red[2] + s_red[3];
+      if (t == 0) cnt_or_ptr[I] = (MODE == EX_PAD && total > PCAP) ? 0 : total;
+      if (MODE == EX_PAD && total > PCAP && t == 0) atomicOr(pflag, 1);
+    }
+    if (MODE == EX_FILL || (MODE == EX_PAD && total <= PCAP)) {
+      const int64_t base = MODE == EX_FILL ? (int64_t)cnt_or_ptr[I] : (int64_t)I * PCAP;
       for (int c = t; c < L; c += RN_BLOCK) {
         if (!first[c]) continue;
         const int v = cand[c];
@@ -570,8 +658,7 @@ __global__ __launch_bounds__(RN_BLOCK) void k_iota(int n, int32_t *__restrict__ 
   if (i <= n) out[i] = i;
 }
 
-__global__ __launch_bounds__(RN_BLOCK) void k_dof_count(int n, int m, const int32_t *__restrict__ Xp,
-                                                       const int32_t *__restrict__ agg,
+__global__ __launch_bounds__(RN_BLOCK) void k_dof_count(int n, int m, const XRows X, const int32_t *__restrict__ agg,
                                                        const int32_t *__restrict__ roots, int n_agg,
                                                        int32_t *__restrict__ cnt, uint8_t *__restrict__ is_root,
                                                        int32_t *__restrict__ flag,
@@ -592,26 +679,96 @@ __global__ __launch_bounds__(RN_BLOCK) void k_dof_count(int n, int m, const int3
   }
   const bool root = roots[a] == I;
   is_root[i] = root;
-  cnt[i] = root ? 1 : m * (Xp[I + 1] - Xp[I]);
+  int64_t s;
+  int len;
+  x_row(X, I, s, len);
+  cnt[i] = root ? 1 : m * len;
 }
 
-__global__ __launch_bounds__(RN_BLOCK) void k_dof_fill(int n, int m, const int32_t *__restrict__ Xp,
-                                                      const int32_t *__restrict__ Xj,
-                                                      const int32_t *__restrict__ agg,
+// one group of SG lanes per DOF row, the lanes over the row's node columns
+__global__ __launch_bounds__(RN_BLOCK) void k_dof_fill(int n, int m, const XRows X, const int32_t *__restrict__ agg,
                                                       const int32_t *__restrict__ Np,
                                                       const uint8_t *__restrict__ is_root,
                                                       int32_t *__restrict__ Nj) {
   // runs only after phase 1 reported success, so its inputs were validated
-  const int i = blockIdx.x * RN_BLOCK + threadIdx.x;
+  const int g = threadIdx.x / SG, l = threadIdx.x % SG;
+  const int i = blockIdx.x * SRPB + g;
   if (i >= n) return;
   const int I = i / m, c = i % m;
-  int w = Np[i];
+  const int w = Np[i];
   if (is_root[i]) {
-    Nj[w] = m * agg[I] + c;
+    if (l == 0) Nj[w] = m * agg[I] + c;
     return;
   }
-  for (int p = Xp[I]; p < Xp[I + 1]; ++p)
-    for (int cc = 0; cc < m; ++cc) Nj[w++] = m * Xj[p] + cc;
+  int64_t s;
+  int len;
+  x_row(X, I, s, len);
+  for (int q = l; q < len; q += SG) {
+    const int v = X.v[s + q];
+    for (int cc = 0; cc < m; ++cc) Nj[w + m * q + cc] = m * v + cc;
+  }
+}
+
+// padded levels unless RNAMG_PATTERN_PAD=0
+static bool pattern_pad_on() {
+  static const int on = [] {
+    const char *e = getenv("RNAMG_PATTERN_PAD");
+    return (e && e[0] == '0') ? 0 : 1;
+  }();
+  return on != 0;
+}
+
+// Expansion with padded levels (no host round trip between levels), then the
+// DOF row sizes and their scan.  *ok is false when a padded row outgrew PCAP
+// (nothing is published then).
+static rn_status pattern_padded(rn_ctx *ctx, int nn, int n, int m, const int32_t *Sp, const int32_t *Sj,
+                                const int32_t *agg, const int32_t *roots, int n_agg, int degree, int32_t *Np,
+                                uint8_t *is_root, int32_t *cnt, int32_t *ovf, int32_t *guard, int64_t *total,
+                                bool *ok) {
+  rn_status st = RN_OK;
+  *ok = false;
+  int32_t *pflag = (int32_t *)rn_scratch(ctx, SLOT_PAT_FLAG, 64, &st);
+  if (!pflag) return st;
+  HIP_TRY(ctx, hipMemsetAsync(pflag, 0, sizeof(int32_t), ctx->stream));
+  XRows X{nullptr, agg, nullptr, 1};  // X_0 = C
+  int cur = 0;
+  const unsigned g = rn_div_up(nn, ERPB) ? rn_div_up(nn, ERPB) : 1;
+  for (int t = 0; t < degree; ++t) {
+    const size_t vb = (size_t)nn * PCAP * sizeof(int32_t) + 16;
+    int32_t *Yv = (int32_t *)rn_scratch(ctx, cur ? SLOT_PAT_XJ0 : SLOT_PAT_XJ1, vb, &st);
+    if (!Yv) return st;
+    int32_t *Yc = (int32_t *)rn_scratch(ctx, cur ? SLOT_PAT_XP0 : SLOT_PAT_XP1, (size_t)(nn + 1) * sizeof(int32_t),
+                                        &st);
+    if (!Yc) return st;
+    HIP_TRY(ctx, hipMemsetAsync(ovf, 0, sizeof(int32_t), ctx->stream));
+    hipLaunchKernelGGL(k_expand<EX_PAD>, dim3(g), dim3(RN_BLOCK), 0, ctx->stream, nn, Sp, Sj, X, Yc, Yv, ovf + 1,
+                       ovf, guard);
+    hipLaunchKernelGGL(k_expand_big<EX_PAD>, dim3(256), dim3(RN_BLOCK), 0, ctx->stream, Sp, Sj, X, Yc, Yv,
+                       ovf + 1, ovf, guard, pflag);
+    LAUNCH_CHECK(ctx);
+    X = XRows{nullptr, Yv, Yc, PCAP};
+    cur ^= 1;
+  }
+  if (n > 0) {
+    hipLaunchKernelGGL(k_dof_count, dim3(rn_div_up(n, RN_BLOCK)), dim3(RN_BLOCK), 0, ctx->stream, n, m, X, agg,
+                       roots, n_agg, cnt, is_root, guard, guard);
+    LAUNCH_CHECK(ctx);
+  }
+  RN_TRY(rn_scan_counts(ctx, cnt, Np, n, nullptr));
+  // one synchronisation: total, guard, padded overflow
+  const RnFetch it[3] = {{ctx->slot[SLOT_SCAN_TOTAL].ptr, sizeof(int64_t)}, {guard, 4}, {pflag, 4}};
+  const unsigned char *hb = nullptr;
+  size_t off[3];
+  RN_TRY(rn_fetch(ctx, 3, it, &hb, off));
+  int32_t gword = 0, pf = 0;
+  memcpy(total, hb + off[0], 8);
+  memcpy(&gword, hb + off[1], 4);
+  memcpy(&pf, hb + off[2], 4);
+  RN_TRY(rn_guard_status(ctx, gword, "rn_pattern"));
+  if (pf) return RN_OK;
+  ctx->pat_x = X;
+  *ok = true;
+  return RN_OK;
 }
 
 extern "C" rn_status rn_pattern(rn_ctx *ctx, int32_t nn, const int32_t *Sp, const int32_t *Sj, const int32_t *agg,
@@ -629,12 +786,11 @@ extern "C" rn_status rn_pattern(rn_ctx *ctx, int32_t nn, const int32_t *Sp, cons
   if (Nj) {  // phase 2
     if (ctx->pat_nnz < 0 || ctx->pat_n != n || ctx->pat_m != m)
       return rn_fail(ctx, RN_EINVAL, "rn_pattern: phase 2 without a matching phase 1");
-    const int b = ctx->pat_buf;
-    const int32_t *Xp = (const int32_t *)ctx->slot[b ? SLOT_PAT_XP1 : SLOT_PAT_XP0].ptr;
-    const int32_t *Xj = (const int32_t *)ctx->slot[b ? SLOT_PAT_XJ1 : SLOT_PAT_XJ0].ptr;
+    XRows X = ctx->pat_x;
+    if (!X.p && !X.c) X.v = agg;  // degree 0 on padded levels: the aggregate map itself
     if (n > 0) {
-      hipLaunchKernelGGL(k_dof_fill, dim3(rn_div_up(n, RN_BLOCK)), dim3(RN_BLOCK), 0, ctx->stream, n, m, Xp, Xj,
-                         agg, Np, is_root, Nj);
+      hipLaunchKernelGGL(k_dof_fill, dim3(rn_div_up(n, SRPB)), dim3(RN_BLOCK), 0, ctx->stream, n, m, X, agg, Np,
+                         is_root, Nj);
       LAUNCH_CHECK(ctx);
     }
     *nnz_N = ctx->pat_nnz;
@@ -653,7 +809,22 @@ extern "C" rn_status rn_pattern(rn_ctx *ctx, int32_t nn, const int32_t *Sp, cons
   RN_TRY(rn_validate_csr(ctx, nn, nn, -1, Sp, Sj, guard, GUARD_S));
   RN_TRY(rn_validate_range(ctx, nn, agg, 0, n_agg, guard, GUARD_AGG));
   RN_TRY(rn_validate_range(ctx, n_agg, roots, 0, nn, guard, GUARD_ROOTS));
-  // X_0 = C: row I holds agg[I]
+  int64_t total = 0;
+  if ((int64_t)nn * PCAP < ((int64_t)1 << 31) && pattern_pad_on()) {
+    bool ok = false;
+    RN_TRY(pattern_padded(ctx, nn, n, m, Sp, Sj, agg, roots, n_agg, degree, Np, is_root, cnt, ovf, guard, &total,
+                          &ok));
+    if (ok) {
+      if (total >= ((int64_t)1 << 31)) return rn_fail(ctx, RN_ELIMIT, "rn_pattern: pattern nnz reaches 2^31");
+      ctx->pat_nnz = total;
+      ctx->pat_n = n;
+      ctx->pat_m = m;
+      *nnz_N = total;
+      return RN_OK;
+    }
+  }
+  // CSR levels: each level's row sizes, a scan and a host round trip for its
+  // length, then its columns
   int cur = 0;
   {
     int32_t *Xp = (int32_t *)rn_scratch(ctx, SLOT_PAT_XP0, (size_t)(nn + 1) * sizeof(int32_t), &st);
@@ -668,51 +839,51 @@ extern "C" rn_status rn_pattern(rn_ctx *ctx, int32_t nn, const int32_t *Sp, cons
     }
   }
   for (int t = 0; t < degree; ++t) {
-    const int32_t *Xp = (const int32_t *)ctx->slot[cur ? SLOT_PAT_XP1 : SLOT_PAT_XP0].ptr;
-    const int32_t *Xj = (const int32_t *)ctx->slot[cur ? SLOT_PAT_XJ1 : SLOT_PAT_XJ0].ptr;
+    const XRows X{(const int32_t *)ctx->slot[cur ? SLOT_PAT_XP1 : SLOT_PAT_XP0].ptr,
+                  (const int32_t *)ctx->slot[cur ? SLOT_PAT_XJ1 : SLOT_PAT_XJ0].ptr, nullptr, 0};
     int32_t *Yp = (int32_t *)rn_scratch(ctx, cur ? SLOT_PAT_XP0 : SLOT_PAT_XP1, (size_t)(nn + 1) * sizeof(int32_t),
                                         &st);
     if (!Yp) return st;
     const unsigned g = rn_div_up(nn, ERPB) ? rn_div_up(nn, ERPB) : 1;
     const unsigned gb = 256;
     HIP_TRY(ctx, hipMemsetAsync(ovf, 0, sizeof(int32_t), ctx->stream));
-    hipLaunchKernelGGL(k_expand<false>, dim3(g), dim3(RN_BLOCK), 0, ctx->stream, nn, Sp, Sj, Xp, Xj, cnt,
+    hipLaunchKernelGGL(k_expand<EX_COUNT>, dim3(g), dim3(RN_BLOCK), 0, ctx->stream, nn, Sp, Sj, X, cnt,
                        (int32_t *)nullptr, ovf + 1, ovf, guard);
-    hipLaunchKernelGGL(k_expand_big<false>, dim3(gb), dim3(RN_BLOCK), 0, ctx->stream, Sp, Sj, Xp, Xj, cnt,
-                       (int32_t *)nullptr, ovf + 1, ovf, guard);
+    hipLaunchKernelGGL(k_expand_big<EX_COUNT>, dim3(gb), dim3(RN_BLOCK), 0, ctx->stream, Sp, Sj, X, cnt,
+                       (int32_t *)nullptr, ovf + 1, ovf, guard, (int32_t *)nullptr);
     LAUNCH_CHECK(ctx);
     RN_TRY(rn_scan_counts(ctx, cnt, Yp, nn, nullptr));
-    int64_t total = 0;
-    st = rn_read_guard_i64(ctx, guard, ctx->slot[SLOT_SCAN_TOTAL].ptr, &total, "rn_pattern");
+    int64_t lt = 0;
+    st = rn_read_guard_i64(ctx, guard, ctx->slot[SLOT_SCAN_TOTAL].ptr, &lt, "rn_pattern");
     if (st == RN_ELIMIT)
       return rn_fail(ctx, RN_ELIMIT, "rn_pattern: a node row gathers more than %d candidates in step %d", BCAP,
                      t + 1);
     RN_TRY(st);
-    if (total >= ((int64_t)1 << 31)) return rn_fail(ctx, RN_ELIMIT, "rn_pattern: nodal pattern reaches 2^31");
-    int32_t *Yj = (int32_t *)rn_scratch(ctx, cur ? SLOT_PAT_XJ0 : SLOT_PAT_XJ1, (size_t)(total + 1) * sizeof(int32_t),
+    if (lt >= ((int64_t)1 << 31)) return rn_fail(ctx, RN_ELIMIT, "rn_pattern: nodal pattern reaches 2^31");
+    int32_t *Yj = (int32_t *)rn_scratch(ctx, cur ? SLOT_PAT_XJ0 : SLOT_PAT_XJ1, (size_t)(lt + 1) * sizeof(int32_t),
                                         &st);
     if (!Yj) return st;
-    hipLaunchKernelGGL(k_expand<true>, dim3(g), dim3(RN_BLOCK), 0, ctx->stream, nn, Sp, Sj, Xp, Xj, Yp, Yj,
-                       ovf + 1, ovf, guard);
-    hipLaunchKernelGGL(k_expand_big<true>, dim3(gb), dim3(RN_BLOCK), 0, ctx->stream, Sp, Sj, Xp, Xj, Yp, Yj,
-                       ovf + 1, ovf, guard);
+    hipLaunchKernelGGL(k_expand<EX_FILL>, dim3(g), dim3(RN_BLOCK), 0, ctx->stream, nn, Sp, Sj, X, Yp, Yj, ovf + 1,
+                       ovf, guard);
+    hipLaunchKernelGGL(k_expand_big<EX_FILL>, dim3(gb), dim3(RN_BLOCK), 0, ctx->stream, Sp, Sj, X, Yp, Yj, ovf + 1,
+                       ovf, guard, (int32_t *)nullptr);
     LAUNCH_CHECK(ctx);
     cur ^= 1;
   }
-  const int32_t *Xp = (const int32_t *)ctx->slot[cur ? SLOT_PAT_XP1 : SLOT_PAT_XP0].ptr;
+  const XRows X{(const int32_t *)ctx->slot[cur ? SLOT_PAT_XP1 : SLOT_PAT_XP0].ptr,
+                (const int32_t *)ctx->slot[cur ? SLOT_PAT_XJ1 : SLOT_PAT_XJ0].ptr, nullptr, 0};
   if (n > 0) {
-    hipLaunchKernelGGL(k_dof_count, dim3(rn_div_up(n, RN_BLOCK)), dim3(RN_BLOCK), 0, ctx->stream, n, m, Xp, agg,
+    hipLaunchKernelGGL(k_dof_count, dim3(rn_div_up(n, RN_BLOCK)), dim3(RN_BLOCK), 0, ctx->stream, n, m, X, agg,
                        roots, n_agg, cnt, is_root, guard, guard);
     LAUNCH_CHECK(ctx);
   }
   RN_TRY(rn_scan_counts(ctx, cnt, Np, n, nullptr));
-  int64_t total = 0;
   RN_TRY(rn_read_guard_i64(ctx, guard, ctx->slot[SLOT_SCAN_TOTAL].ptr, &total, "rn_pattern"));
   if (total >= ((int64_t)1 << 31)) return rn_fail(ctx, RN_ELIMIT, "rn_pattern: pattern nnz reaches 2^31");
   ctx->pat_nnz = total;
   ctx->pat_n = n;
   ctx->pat_m = m;
-  ctx->pat_buf = cur;
+  ctx->pat_x = X;
   *nnz_N = total;
   return RN_OK;
 }

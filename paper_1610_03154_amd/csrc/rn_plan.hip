@@ -574,11 +574,17 @@ extern "C" rn_status rn_plan_create(rn_ctx *ctx, const rn_matrix *A, int32_t n_c
     if (hipGetLastError() != hipSuccess) return fail(rn_fail(ctx, RN_EHIP, "launch"));
   }
   // one synchronisation: guard, maxlen, rank_def, longest A row, node-entry total
-  int64_t *hp = ctx->pinned;
-  if (hipMemcpyAsync(hp + 2, misc, 16, hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
-      hipMemcpyAsync(hp + 4, misc + 8, 8, hipMemcpyDeviceToHost, ctx->stream) != hipSuccess)
-    return fail(rn_fail(ctx, RN_EHIP, "copy"));
-  st = rn_check_guard(ctx, guard, "rn_plan_create");
+  const RnFetch it[3] = {{misc, 16}, {misc + 8, 8}, {guard, 4}};
+  const unsigned char *hb = nullptr;
+  size_t off[3];
+  st = rn_fetch(ctx, 3, it, &hb, off);
+  if (st != RN_OK) return fail(st);
+  int64_t hp[5];
+  int32_t gword = 0;
+  memcpy(hp + 2, hb + off[0], 16);
+  memcpy(hp + 4, hb + off[1], 8);
+  memcpy(&gword, hb + off[2], 4);
+  st = rn_guard_status(ctx, gword, "rn_plan_create");
   if (st != RN_OK) {
     if (st == RN_ELIMIT)
       rn_fail(ctx, RN_ELIMIT, "rn_plan_create: a pattern row holds more than %d entries", CODE_MAXLEN);

@@ -1,6 +1,7 @@
 // rn_tentative.hip -- inject (Sec. 3.6): coarse candidates by injection at
 // the root DOFs, the root-node tentative operator of Eq. root-nodeform, and
 // the minimum-norm row update of Eq. Tproj for candidates beyond the first m.
+#include <cstring>
 #include "rn_gram.h"
 #include "rn_internal.h"
 
@@ -151,10 +152,15 @@ extern "C" rn_status rn_tentative(rn_ctx *ctx, int32_t n, int32_t m, const int32
       LAUNCH_CHECK(ctx);
     }
   }
-  // flags land in pinned[4..]; rn_check_guard uses pinned[0] and synchronises
-  const int32_t *hf = (const int32_t *)(ctx->pinned + 4);
-  HIP_TRY(ctx, hipMemcpyAsync((void *)hf, flags, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
-  RN_TRY(rn_check_guard(ctx, guard, "rn_tentative"));
+  // one synchronisation: guard and the two flags
+  const RnFetch it[2] = {{guard, 4}, {flags, 2 * sizeof(int32_t)}};
+  const unsigned char *hb = nullptr;
+  size_t off[2];
+  RN_TRY(rn_fetch(ctx, 2, it, &hb, off));
+  int32_t gword = 0, hf[2] = {0, 0};
+  memcpy(&gword, hb + off[0], 4);
+  memcpy(hf, hb + off[1], 8);
+  RN_TRY(rn_guard_status(ctx, gword, "rn_tentative"));
   if (hf[0]) return rn_fail(ctx, RN_ESINGULAR, "rn_tentative: singular root block of B");
   if (rank_deficient) *rank_deficient = hf[1];
   return RN_OK;

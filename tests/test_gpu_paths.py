@@ -114,3 +114,33 @@ def test_128_lane_blocks(R, ctx):
     assert np.max(np.abs(Zp - refp)) <= FP64_TOL * np.max(np.abs(refp))
     P, st, _ = ctx.energy_min(g["plan"], g["A"].vals, g["T"], R.RN_CG, c["iters"], R.RN_FP64)
     assert CS.rel_max(host(P), c["P"]) <= FP64_TOL
+
+
+def _banded(n, hb):
+    """Symmetric banded graph |i - j| <= hb (diagonal included), CSR."""
+    rows = [np.arange(max(0, i - hb), min(n, i + hb + 1), dtype=np.int32) for i in range(n)]
+    Sp = np.zeros(n + 1, dtype=np.int32)
+    Sp[1:] = np.cumsum([r.size for r in rows])
+    return Sp, np.concatenate(rows).astype(np.int32)
+
+
+@pytest.mark.parametrize("hb,d", [(20, 1), (8, 2), (35, 2), (0, 0)])
+def test_pattern_row_widths(R, ctx, hb, d):
+    """Pattern levels of every width: rows gathered in the small window
+    (hb 20, d 1), rows gathered by the large-window kernel whose distinct
+    columns still fit a padded row (hb 8, d 2), rows with more than 64
+    distinct columns (hb 35, d 2: the expansion is redone with CSR levels),
+    and degree 0.  Aggregates are node pairs, so odd nodes keep their
+    expanded rows."""
+    import oracle as O
+    n = 300
+    Sp, Sj = _banded(n, hb)
+    agg = (np.arange(n) // 2).astype(np.int32)
+    roots = np.arange(0, n, 2, dtype=np.int32)
+    Np, Nj, is_root = ctx.pattern(dev(Sp), dev(Sj), dev(agg), dev(roots), d, 1)
+    Npn, Njn = O.pattern_nodes(Sp, Sj, agg, roots.size, d)
+    Np_o, Nj_o, ir_o = O.pattern_dofs(Npn, Njn, agg, roots, 1)
+    widest = int(np.diff(Npn).max())
+    assert (widest > 64) == ((hb, d) == (35, 2))
+    assert np.array_equal(host(Np), Np_o) and np.array_equal(host(Nj), Nj_o)
+    assert np.array_equal(host(is_root), ir_o)
