@@ -32,6 +32,7 @@
 #define XW_RUNMAX 15  // more runs: the block reads X from global memory
 
 // per-batch integer state
+// per batch entry: status, converged flag, steps done, GMRES basis size
 enum { ST_STATUS = 0, ST_DONE = 1, ST_ITERS = 2, ST_KD = 3, ST_STRIDE = 8 };
 
 // per-batch double scalars
@@ -121,8 +122,12 @@ struct SpgParams {
   int32_t *st;         // [batch][ST_STRIDE]
 };
 
-// Launch the masked product in one of the modes (rn_spgemm.hip).
-rn_status rn_launch_spgemm(rn_ctx *ctx, const rn_plan *pl, int mode, const SpgParams &p, int batch, bool mixed);
+// Launch the masked product in one of the modes (rn_spgemm.hip).  Single-dot
+// modes (CG_INIT, CG_STEP, GM_INIT) leave per-workgroup partials at the start
+// of each batch entry's partial row; *npart (when given) receives their
+// number (the grid of the persistent form, else one per product block).
+rn_status rn_launch_spgemm(rn_ctx *ctx, const rn_plan *pl, int mode, const SpgParams &p, int batch, bool mixed,
+                           int *npart = nullptr);
 SpgParams rn_spg_params(const rn_plan *pl);
 
 // tape hooks called by rn_energy_min (CG, FP64) -- implemented with the adjoint
@@ -135,24 +140,81 @@ double *rn_tape_D(rn_tape *tape, int k);
 // after the last step: the per-batch scalars and status
 rn_status rn_tape_record_end(rn_ctx *ctx, rn_tape *tape, const double *scal, const int32_t *st, int32_t batch);
 
-// Deterministic sum of nb partials by the whole block (fixed assignment of
-// partials to threads, compensated, fixed tree).
-__device__ inline double rn_reduce_part(const double *__restrict__ part, int nb, double *lds8) {
+// Deterministic sum of nb partials by a block of NT threads (fixed
+// assignment of partials to threads, compensated, fixed tree).
+template <int NT>
+__device__ inline double rn_reduce_part_w(const double *part, int nb, double *lds8) {
   RnAcc a;
   int q = threadIdx.x;
   // eight loads in flight per thread, then the additions in the same order
-  for (; q + 7 * RN_BLOCK < nb; q += 8 * RN_BLOCK) {
+  for (; q + 7 * NT < nb; q += 8 * NT) {
     double v[8];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) v[k] = part[q + k * RN_BLOCK];
+    for (int k = 0; k < 8; ++k) v[k] = part[q + k * NT];
 #pragma unroll
     for (int k = 0; k < 8; ++k) a.add(v[k]);
   }
-  for (; q < nb; q += RN_BLOCK) a.add(part[q]);
-  return rn_block_sum2(a.hi, a.lo, lds8);
+  for (; q < nb; q += NT) a.add(part[q]);
+  return rn_block_sum2_w<NT / RN_WAVE>(a.hi, a.lo, lds8);
+}
+__device__ inline double rn_reduce_part(const double *part, int nb, double *lds8) {
+  return rn_reduce_part_w<RN_BLOCK>(part, nb, lds8);
 }
 
 // Krylov stopping rules (converged to round-off): CG once <R,R> <= 1e-24
 // <R0,R0>, GMRES once the residual estimate is <= 1e-12 ||R0||.
 #define RN_CG_STOP 1e-24
 #define RN_GM_STOP 1e-12
+
+// Scalar steps of one batch entry (one thread), from the step's reduced dot:
+// gamma_0 = <R_0,R_0> (Sec. 4.1): stop at once when it is zero
+__device__ inline void rn_cg_init_fin(double g, double *sc, int32_t *st, double *hist, int K) {
+  const CgLayout L(K);
+  sc[SC_GAMMA0] = g;
+  sc[L.gam] = g;
+  if (hist) hist[0] = g;
+  if (!isfinite(g)) st[ST_STATUS] = RN_ENONFINITE;
+  else if (g == 0.0) st[ST_DONE] = 1;
+}
+// delta_k = <D_k, Pi(A D_k)> and alpha_k = gamma_k / delta_k; breakdown when
+// the curvature is not positive
+__device__ inline void rn_cg_alpha_fin(double dl, double *sc, int32_t *st, double *hist, int K, int k) {
+  const CgLayout L(K);
+  sc[L.del + k] = dl;
+  if (hist) hist[1 + K + k] = dl;
+  if (!isfinite(dl)) {
+    st[ST_STATUS] = RN_ENONFINITE;
+    return;
+  }
+  if (dl <= 0.0) {
+    st[ST_STATUS] = RN_EBREAKDOWN;
+    return;
+  }
+  const double al = sc[L.gam + k] / dl;
+  sc[L.alp + k] = al;
+  if (hist) hist[1 + 2 * K + k] = al;
+}
+// gamma_{k+1} = <R_{k+1}, R_{k+1}>, beta_k = gamma_{k+1} / gamma_k, the step
+// count and the stopping test
+__device__ inline double rn_cg_beta_fin(double g, double *sc, int32_t *st, double *hist, int K, int k) {
+  const CgLayout L(K);
+  const double be = g / sc[L.gam + k];
+  sc[L.gam + k + 1] = g;
+  sc[L.bet + k] = be;
+  if (hist) hist[k + 1] = g;
+  st[ST_ITERS] = k + 1;
+  if (!isfinite(g)) st[ST_STATUS] = RN_ENONFINITE;
+  else if (g <= RN_CG_STOP * sc[SC_GAMMA0]) st[ST_DONE] = 1;
+  return be;
+}
+// GMRES: beta_0 = ||R_0|| and the scale of the first basis vector
+__device__ inline void rn_gm_init_fin(double tot, double *sc, int32_t *st, double *hist, int K) {
+  const GmLayout L(K);
+  const double beta = sqrt(tot);
+  sc[SC_BETA0] = beta;
+  sc[L.g] = beta;
+  if (hist) hist[0] = beta;
+  if (!isfinite(beta)) st[ST_STATUS] = RN_ENONFINITE;
+  else if (beta == 0.0) st[ST_DONE] = 1;
+  else sc[L.s] = 1.0 / beta;
+}

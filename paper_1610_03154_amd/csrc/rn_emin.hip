@@ -9,10 +9,14 @@
 // No inter-block synchronisation and no host round trip inside the loop; the
 // scalars of step k are kept per step so no kernel overwrites a value another
 // block of the same kernel still reads.
-// GMRES step k: product with the first Gram-Schmidt pass fused (partials of
-// <W, V_j>), then two element-wise passes (classical Gram-Schmidt twice), each
-// followed by a one-block kernel that sums the partials; the Hessenberg
-// column, Givens rotations and the stopping test run on the device.
+// GMRES step k: product W = A V_k, then three streaming passes (partials of
+// <W, V_j>; classical Gram-Schmidt twice), each followed by a kernel that
+// sums the partials; the Hessenberg column, Givens rotations and the
+// stopping test run on the device.
+// (Each finishing step is its own small kernel: a last-workgroup finish
+// inside the producing kernel needs a device-scope release per workgroup,
+// which writes back the compute die's L2 and made those kernels several
+// times slower.)
 #include <cstring>
 #include <new>
 
@@ -21,55 +25,37 @@
 // ---------------------------------------------------------------------------
 // CG
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(RN_BLOCK) void k_cg_fin_init(int nblk, const double *__restrict__ part,
+// (part: np partials per batch entry, batch entries pstride apart)
+__global__ __launch_bounds__(RN_BLOCK) void k_cg_fin_init(int np, int64_t pstride, const double *__restrict__ part,
                                                          double *__restrict__ scal, int scal_stride, int K,
                                                          int32_t *__restrict__ stv, double *__restrict__ histv,
                                                          int hist_stride) {
   __shared__ double s_w[8];
   const int b = blockIdx.x;
-  const double g = rn_reduce_part(part + (int64_t)b * RN_MAXDOT * nblk, nblk, s_w);
+  const double g = rn_reduce_part(part + (int64_t)b * pstride, np, s_w);
   if (threadIdx.x != 0) return;
-  double *sc = scal + (int64_t)b * scal_stride;
-  int32_t *st = stv + (int64_t)b * ST_STRIDE;
-  const CgLayout L(K);
-  sc[SC_GAMMA0] = g;
-  sc[L.gam] = g;
-  if (histv) histv[(int64_t)b * hist_stride] = g;
-  if (!isfinite(g)) st[ST_STATUS] = RN_ENONFINITE;
-  else if (g == 0.0) st[ST_DONE] = 1;
+  rn_cg_init_fin(g, scal + (int64_t)b * scal_stride, stv + (int64_t)b * ST_STRIDE,
+                 histv ? histv + (int64_t)b * hist_stride : nullptr, K);
 }
 
 // One block per batch entry: delta_k = <D,Z> from the product's per-block
 // partials (fixed order, compensated), the step length alpha_k, the
 // breakdown and finiteness tests.
-__global__ __launch_bounds__(RN_BLOCK) void k_cg_alpha(int K, int k, int nblk, const double *__restrict__ part_spg,
-                                                      double *__restrict__ scal, int scal_stride,
-                                                      int32_t *__restrict__ stv, double *__restrict__ histv,
-                                                      int hist_stride) {
+__global__ __launch_bounds__(RN_BLOCK) void k_cg_alpha(int K, int k, int np, int64_t pstride,
+                                                      const double *__restrict__ part_spg, double *__restrict__ scal,
+                                                      int scal_stride, int32_t *__restrict__ stv,
+                                                      double *__restrict__ histv, int hist_stride) {
   __shared__ double s_w[8];
   const int b = blockIdx.x;
   int32_t *st = stv + (int64_t)b * ST_STRIDE;
   if (st[ST_STATUS] || st[ST_DONE]) return;
-  const double dl = rn_reduce_part(part_spg + (int64_t)b * RN_MAXDOT * nblk, nblk, s_w);
+  const double dl = rn_reduce_part(part_spg + (int64_t)b * pstride, np, s_w);
   if (threadIdx.x != 0) return;
-  double *sc = scal + (int64_t)b * scal_stride;
-  const CgLayout L(K);
-  double *hist = histv ? histv + (int64_t)b * hist_stride : nullptr;
-  sc[L.del + k] = dl;
-  if (hist) hist[1 + K + k] = dl;
-  if (!isfinite(dl)) {
-    st[ST_STATUS] = RN_ENONFINITE;
-    return;
-  }
-  if (dl <= 0.0) {
-    st[ST_STATUS] = RN_EBREAKDOWN;
-    return;
-  }
-  const double al = sc[L.gam + k] / dl;
-  sc[L.alp + k] = al;
-  if (hist) hist[1 + 2 * K + k] = al;
+  rn_cg_alpha_fin(dl, scal + (int64_t)b * scal_stride, st, histv ? histv + (int64_t)b * hist_stride : nullptr, K,
+                  k);
 }
 
+// P += alpha D, R -= alpha Z, partials of <R,R>.
 __global__ __launch_bounds__(RN_BLOCK) void k_cg_update(int64_t nnz, int64_t stride, int K, int k,
                                                        double *__restrict__ P, double *__restrict__ R,
                                                        const double *__restrict__ D, const double *__restrict__ Z,
@@ -94,6 +80,9 @@ __global__ __launch_bounds__(RN_BLOCK) void k_cg_update(int64_t nnz, int64_t str
   if (threadIdx.x == 0) part_ew[(int64_t)b * RN_MAXDOT * gridDim.x + blockIdx.x] = S;
 }
 
+// Every block sums the <R,R> partials (same fixed order, same scalars), block
+// 0 stores gamma_{k+1}, beta_k and the stopping test; D = R + beta_k D (and
+// its FP32 shadow).
 template <bool MIXED>
 __global__ __launch_bounds__(RN_BLOCK) void k_cg_dir(int64_t nnz, int64_t stride, int K, int k, int nb_ew,
                                                     const double *__restrict__ R, double *__restrict__ D,
@@ -109,14 +98,8 @@ __global__ __launch_bounds__(RN_BLOCK) void k_cg_dir(int64_t nnz, int64_t stride
   const CgLayout L(K);
   const double g = rn_reduce_part(part_ew + (int64_t)b * RN_MAXDOT * nb_ew, nb_ew, s_w);
   const double be = g / sc[L.gam + k];
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    sc[L.gam + k + 1] = g;
-    sc[L.bet + k] = be;
-    if (histv) histv[(int64_t)b * hist_stride + k + 1] = g;
-    st[ST_ITERS] = k + 1;
-    if (!isfinite(g)) st[ST_STATUS] = RN_ENONFINITE;
-    else if (g <= RN_CG_STOP * sc[SC_GAMMA0]) st[ST_DONE] = 1;
-  }
+  if (blockIdx.x == 0 && threadIdx.x == 0)
+    rn_cg_beta_fin(g, sc, st, histv ? histv + (int64_t)b * hist_stride : nullptr, K, k);
   if (!isfinite(g)) return;
   const int64_t off = (int64_t)b * stride;
   for (int64_t e = (int64_t)blockIdx.x * RN_BLOCK + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * RN_BLOCK) {
@@ -135,7 +118,8 @@ __global__ __launch_bounds__(RN_BLOCK) void k_cg_dir(int64_t nnz, int64_t stride
 // coefficients h1_j = s_j <W, U_j>; 2: second-pass h2_j; 3: ||W||, column k
 // of H, Givens rotation, residual estimate, next scale, stopping test.
 template <int STAGE>
-__global__ __launch_bounds__(RN_BLOCK) void k_gm_fin(int nb, const double *__restrict__ part, int K, int k,
+__global__ __launch_bounds__(RN_BLOCK) void k_gm_fin(int nb, int64_t pstride, const double *__restrict__ part, int K,
+                                                    int k,
                                                     double *__restrict__ scal, int scal_stride,
                                                     int32_t *__restrict__ stv, double *__restrict__ histv,
                                                     int hist_stride) {
@@ -146,7 +130,7 @@ __global__ __launch_bounds__(RN_BLOCK) void k_gm_fin(int nb, const double *__res
   if (STAGE > 0 && (st[ST_STATUS] || st[ST_DONE])) return;
   double *sc = scal + (int64_t)b * scal_stride;
   const GmLayout L(K);
-  const double *pb = part + (int64_t)b * RN_MAXDOT * nb;
+  const double *pb = part + (int64_t)b * pstride;
   double *hist = histv ? histv + (int64_t)b * hist_stride : nullptr;
   if (STAGE == 1 || STAGE == 2) {
     const int j = blockIdx.x;
@@ -157,13 +141,7 @@ __global__ __launch_bounds__(RN_BLOCK) void k_gm_fin(int nb, const double *__res
   const double tot = rn_reduce_part(pb, nb, s_w);
   if (threadIdx.x != 0) return;
   if (STAGE == 0) {
-    const double beta = sqrt(tot);
-    sc[SC_BETA0] = beta;
-    sc[L.g] = beta;
-    if (hist) hist[0] = beta;
-    if (!isfinite(beta)) st[ST_STATUS] = RN_ENONFINITE;
-    else if (beta == 0.0) st[ST_DONE] = 1;
-    else sc[L.s] = 1.0 / beta;
+    rn_gm_init_fin(tot, sc, st, hist, K);
     return;
   }
   double *H = sc + L.H;
@@ -492,6 +470,7 @@ extern "C" rn_status rn_energy_min(rn_ctx *ctx, rn_plan *pl, const double *A_val
   p.K = K;
   double *part_spg = p.part;
   double *part_ew = p.part + (int64_t)batch * RN_MAXDOT * pl->nblk;
+  const int64_t pstride_spg = (int64_t)RN_MAXDOT * pl->nblk, pstride_ew = (int64_t)RN_MAXDOT * gew;
   HIP_TRY(ctx, hipMemsetAsync(p.st, 0, (size_t)batch * ST_STRIDE * 4, ctx->stream));
   HIP_TRY(ctx, hipMemsetAsync(p.scal, 0, (size_t)batch * scal_stride * 8, ctx->stream));
   if (hist) HIP_TRY(ctx, hipMemsetAsync(hist, 0, (size_t)batch * hist_stride * 8, ctx->stream));
@@ -525,9 +504,10 @@ extern "C" rn_status rn_energy_min(rn_ctx *ctx, rn_plan *pl, const double *A_val
     q.strideX = 0;
     q.Z = R;
     q.Z2 = D;
-    RN_TRY(rn_launch_spgemm(ctx, pl, MODE_CG_INIT, q, batch, mixed));
-    hipLaunchKernelGGL(k_cg_fin_init, dim3(batch), blk, 0, ctx->stream, pl->nblk, part_spg, p.scal, scal_stride, K,
-                       p.st, hist, hist_stride);
+    int np = 0;
+    RN_TRY(rn_launch_spgemm(ctx, pl, MODE_CG_INIT, q, batch, mixed, &np));
+    hipLaunchKernelGGL(k_cg_fin_init, dim3(batch), blk, 0, ctx->stream, np, pstride_spg, part_spg, p.scal,
+                       scal_stride, K, p.st, hist, hist_stride);
     LAUNCH_CHECK(ctx);
     if (mixed) {
       hipLaunchKernelGGL(k_to_f32, dim3(ew_grid(nzb)), blk, 0, ctx->stream, D, nzb, D32);
@@ -544,9 +524,10 @@ extern "C" rn_status rn_energy_min(rn_ctx *ctx, rn_plan *pl, const double *A_val
       s.X = mixed ? (const void *)D32 : (const void *)D;
       s.Xown = D;
       s.Z = Z;
-      RN_TRY(rn_launch_spgemm(ctx, pl, MODE_CG_STEP, s, batch, mixed));
-      hipLaunchKernelGGL(k_cg_alpha, dim3(batch), blk, 0, ctx->stream, K, k, pl->nblk, part_spg, p.scal, scal_stride,
-                         p.st, hist, hist_stride);
+      int np = 0;
+      RN_TRY(rn_launch_spgemm(ctx, pl, MODE_CG_STEP, s, batch, mixed, &np));
+      hipLaunchKernelGGL(k_cg_alpha, dim3(batch), blk, 0, ctx->stream, K, k, np, pstride_spg, part_spg, p.scal,
+                         scal_stride, p.st, hist, hist_stride);
       hipLaunchKernelGGL(k_cg_update, g2, blk, 0, ctx->stream, nz, nz, K, k, P, R, D, Z, part_ew, p.scal,
                          scal_stride, p.st, tape ? rn_tape_R(tape, k + 1) : nullptr);
       LAUNCH_CHECK(ctx);
@@ -571,9 +552,10 @@ extern "C" rn_status rn_energy_min(rn_ctx *ctx, rn_plan *pl, const double *A_val
     q.strideX = 0;
     q.Z = U;
     q.strideZ = ub;
-    RN_TRY(rn_launch_spgemm(ctx, pl, MODE_GM_INIT, q, batch, mixed));
-    hipLaunchKernelGGL(k_gm_fin<0>, dim3(batch), blk, 0, ctx->stream, pl->nblk, part_spg, K, 0, p.scal, scal_stride,
-                       p.st, hist, hist_stride);
+    int np = 0;
+    RN_TRY(rn_launch_spgemm(ctx, pl, MODE_GM_INIT, q, batch, mixed, &np));
+    hipLaunchKernelGGL(k_gm_fin<0>, dim3(batch), blk, 0, ctx->stream, np, pstride_spg, part_spg, K, 0, p.scal,
+                       scal_stride, p.st, hist, hist_stride);
     LAUNCH_CHECK(ctx);
     if (mixed) {
       for (int b = 0; b < batch; ++b)
@@ -604,8 +586,8 @@ extern "C" rn_status rn_energy_min(rn_ctx *ctx, rn_plan *pl, const double *A_val
       } else {
         GM_ORTH(65, 0);
       }
-      hipLaunchKernelGGL(k_gm_fin<1>, dim3(k + 1, batch), blk, 0, ctx->stream, (int)gew, part_ew, K, k, p.scal,
-                         scal_stride, p.st, hist, hist_stride);
+      hipLaunchKernelGGL(k_gm_fin<1>, dim3(k + 1, batch), blk, 0, ctx->stream, (int)gew, pstride_ew, part_ew, K, k,
+                         p.scal, scal_stride, p.st, hist, hist_stride);
       LAUNCH_CHECK(ctx);
       if (k + 1 <= 16) {
         if (mixed) gm_orth_k<1, true>(k + 1, g2, blk, ctx->stream, nz, ub, K, k, U, U32, part_ew, p.scal, scal_stride, p.st);
@@ -614,8 +596,8 @@ extern "C" rn_status rn_energy_min(rn_ctx *ctx, rn_plan *pl, const double *A_val
       } else {
         GM_ORTH(65, 1);
       }
-      hipLaunchKernelGGL(k_gm_fin<2>, dim3(k + 1, batch), blk, 0, ctx->stream, (int)gew, part_ew, K, k, p.scal, scal_stride,
-                         p.st, hist, hist_stride);
+      hipLaunchKernelGGL(k_gm_fin<2>, dim3(k + 1, batch), blk, 0, ctx->stream, (int)gew, pstride_ew, part_ew, K, k,
+                         p.scal, scal_stride, p.st, hist, hist_stride);
       LAUNCH_CHECK(ctx);
       if (k + 1 <= 16) {
         if (mixed) gm_orth_k<2, true>(k + 1, g2, blk, ctx->stream, nz, ub, K, k, U, U32, part_ew, p.scal, scal_stride, p.st);
@@ -625,8 +607,8 @@ extern "C" rn_status rn_energy_min(rn_ctx *ctx, rn_plan *pl, const double *A_val
         GM_ORTH(65, 2);
       }
 #undef GM_ORTH
-      hipLaunchKernelGGL(k_gm_fin<3>, dim3(batch), blk, 0, ctx->stream, (int)gew, part_ew, K, k, p.scal, scal_stride,
-                         p.st, hist, hist_stride);
+      hipLaunchKernelGGL(k_gm_fin<3>, dim3(batch), blk, 0, ctx->stream, (int)gew, pstride_ew, part_ew, K, k, p.scal,
+                         scal_stride, p.st, hist, hist_stride);
       LAUNCH_CHECK(ctx);
     }
     hipLaunchKernelGGL(k_gm_solve, dim3(batch), dim3(64), 0, ctx->stream, K, p.scal, scal_stride, p.st);

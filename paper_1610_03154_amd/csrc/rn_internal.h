@@ -275,30 +275,6 @@ __device__ inline void rn_block_sum2_multi(const double (&hi0)[NJ], const double
 }
 __device__ inline double rn_block_sum(double v, double *lds8) { return rn_block_sum2(v, 0.0, lds8); }
 
-// Ticket of the last block to finish: every block's thread 0 calls this
-// after its partial results are stored.  Release/acquire at agent scope
-// make all blocks' partials visible to the last one (works across XCDs).
-__device__ inline bool rn_last_block(unsigned *counter, unsigned nblocks) {
-  __shared__ int s_last;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned t = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL,
-                                        __HIP_MEMORY_SCOPE_AGENT);
-    s_last = (t == nblocks - 1);
-    if (s_last)
-      __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
-  __syncthreads();
-  const bool last = s_last != 0;
-  if (last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-  return last;
-}
-
-// Release the partial results written by this block before taking a ticket.
-__device__ inline void rn_release() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-}
-
 // First index i in [0, n] with a[i] >= x (a non-decreasing, a[n] exists).
 __device__ inline int rn_lower_bound(const int32_t *a, int n, int64_t x) {
   int lo = 0, hi = n;

@@ -590,7 +590,12 @@ __global__ __launch_bounds__(BS) void k_spgemm_p(const SpgParams p, const int G)
   const int xcd = blockIdx.x & 7;
   const int hiB = min(p.nblk, (xcd + 1) * per);
   int blk = xcd * per + (int)(blockIdx.x >> 3);
-  if (blk >= hiB) return;
+  // single-dot modes: one partial per workgroup (slot blockIdx.x)
+  double *pcw = p.part + (int64_t)b * RN_MAXDOT * p.nblk;
+  if (blk >= hiB) {
+    if ((MODE == MODE_CG_INIT || MODE == MODE_GM_INIT || MODE == MODE_CG_STEP) && t == 0) pcw[blockIdx.x] = 0.0;
+    return;
+  }
 
   const bool proj = (MODE != MODE_PRODUCT) || p.project;
   const TV *Ax = (const TV *)p.Ax + (int64_t)b * p.strideA;
@@ -740,11 +745,8 @@ __global__ __launch_bounds__(BS) void k_spgemm_p(const SpgParams p, const int G)
   // (unconditional, clamped: the wait counts then agree on every path)
   load_hdv(min(blk + Gx, hiB - 1), V1);
   // single-dot modes: every lane adds its terms over all of this workgroup's
-  // blocks, in block order; one compensated block sum at the end goes to the
-  // partial of the first block and the others get 0 (consumers sum all
-  // nblk partials in a fixed order, so the result stays deterministic)
+  // blocks, in block order; one compensated block sum at the end
   RnAcc dacc;
-  const int blk0 = blk;
   int par = 0;
   for (;;) {
     const int nxt = blk + Gx;
@@ -861,13 +863,11 @@ __global__ __launch_bounds__(BS) void k_spgemm_p(const SpgParams p, const int G)
         if (p.Z2) spg_st(p.Z2 + zb, e, v);
         dacc.add(v * v);
       }
-      if (t == 0 && blk != blk0) part[blk] = 0.0;
     } else if (MODE == MODE_CG_STEP) {
       if (valid) {
         spg_st(Z, e, z);
         dacc.add(R.own * z);
       }
-      if (t == 0 && blk != blk0) part[blk] = 0.0;
     } else if (MODE == MODE_GM_STEP) {
       if (valid) spg_st(Z, e, z);
     }
@@ -883,7 +883,7 @@ __global__ __launch_bounds__(BS) void k_spgemm_p(const SpgParams p, const int G)
   }
   if (MODE == MODE_CG_INIT || MODE == MODE_GM_INIT || MODE == MODE_CG_STEP) {
     const double S = rn_block_sum2_w<NWV>(dacc.hi, dacc.lo, s_w);
-    if (t == 0) part[blk0] = S;
+    if (t == 0) pcw[blockIdx.x] = S;
   }
 }
 
@@ -907,14 +907,15 @@ static int persist_grid(int nblk, int batch) {
   return g;
 }
 
+// the grid of the persistent launch, or 0 when it cannot run
 template <int NB, int MODE, int BS>
-static bool launch_p(const SpgParams &p, int batch, bool mixed, hipStream_t s) {
+static int launch_p(const SpgParams &p, int batch, bool mixed, hipStream_t s) {
   const int G = mixed ? persist_grid<NB, MODE, true, BS>(p.nblk, batch) : persist_grid<NB, MODE, false, BS>(p.nblk, batch);
-  if (G < 8) return false;
+  if (G < 8) return 0;
   const dim3 grid((unsigned)G, (unsigned)batch);
   if (mixed) hipLaunchKernelGGL((k_spgemm_p<NB, MODE, true, BS>), grid, dim3(BS), 0, s, p, G);
   else hipLaunchKernelGGL((k_spgemm_p<NB, MODE, false, BS>), grid, dim3(BS), 0, s, p, G);
-  return true;
+  return G;
 }
 
 // the persistent form serves scalar operators with n_B <= 2 and records of at
@@ -927,13 +928,15 @@ static bool persist_on() {
   return on != 0;
 }
 
+// the number of per-workgroup partials a single-dot mode leaves
 template <int M, int NB, int MODE>
-static void launch_m(const SpgParams &p, int batch, bool mixed, hipStream_t s) {
+static int launch_m(const SpgParams &p, int batch, bool mixed, hipStream_t s) {
   if constexpr (M == 1 && NB <= 2) {
     // (the branch-free first round reads 32 elements of X and one of A whatever the block)
     if (p.cstride <= 12 && p.nnzN >= 64 && p.strideA >= 1 && persist_on()) {
-      if (p.bs == 128 && launch_p<NB, MODE, 128>(p, batch, mixed, s)) return;
-      if (p.bs == RN_BLOCK && launch_p<NB, MODE, RN_BLOCK>(p, batch, mixed, s)) return;
+      int G = 0;
+      if (p.bs == 128 && (G = launch_p<NB, MODE, 128>(p, batch, mixed, s)) > 0) return G;
+      if (p.bs == RN_BLOCK && (G = launch_p<NB, MODE, RN_BLOCK>(p, batch, mixed, s)) > 0) return G;
     }
   }
   const dim3 grid(rn_xcd_grid((unsigned)p.nblk), (unsigned)batch);
@@ -947,24 +950,25 @@ static void launch_m(const SpgParams &p, int batch, bool mixed, hipStream_t s) {
     if (mixed) hipLaunchKernelGGL((k_spgemm<M, NB, MODE, true, RN_BLOCK>), grid, dim3(RN_BLOCK), 0, s, p);
     else hipLaunchKernelGGL((k_spgemm<M, NB, MODE, false, RN_BLOCK>), grid, dim3(RN_BLOCK), 0, s, p);
   }
+  return p.nblk;
 }
 
 template <int MODE>
-static rn_status launch_mode(rn_ctx *ctx, const rn_plan *pl, const SpgParams &p, int batch, bool mixed) {
+static rn_status launch_mode(rn_ctx *ctx, const rn_plan *pl, const SpgParams &p, int batch, bool mixed, int *np) {
   hipStream_t s = ctx->stream;
   if (pl->m == 1) {
     switch (pl->nB) {
-      case 1: launch_m<1, 1, MODE>(p, batch, mixed, s); break;
-      case 2: launch_m<1, 2, MODE>(p, batch, mixed, s); break;
-      case 3: launch_m<1, 3, MODE>(p, batch, mixed, s); break;
-      case 4: launch_m<1, 4, MODE>(p, batch, mixed, s); break;
+      case 1: *np = launch_m<1, 1, MODE>(p, batch, mixed, s); break;
+      case 2: *np = launch_m<1, 2, MODE>(p, batch, mixed, s); break;
+      case 3: *np = launch_m<1, 3, MODE>(p, batch, mixed, s); break;
+      case 4: *np = launch_m<1, 4, MODE>(p, batch, mixed, s); break;
       default: return rn_fail(ctx, RN_EINVAL, "nB out of range");
     }
   } else {
     switch (pl->nB) {
-      case 2: launch_m<2, 2, MODE>(p, batch, mixed, s); break;
-      case 3: launch_m<2, 3, MODE>(p, batch, mixed, s); break;
-      case 4: launch_m<2, 4, MODE>(p, batch, mixed, s); break;
+      case 2: *np = launch_m<2, 2, MODE>(p, batch, mixed, s); break;
+      case 3: *np = launch_m<2, 3, MODE>(p, batch, mixed, s); break;
+      case 4: *np = launch_m<2, 4, MODE>(p, batch, mixed, s); break;
       default: return rn_fail(ctx, RN_EINVAL, "nB out of range for block_m = 2");
     }
   }
@@ -972,16 +976,22 @@ static rn_status launch_mode(rn_ctx *ctx, const rn_plan *pl, const SpgParams &p,
   return RN_OK;
 }
 
-rn_status rn_launch_spgemm(rn_ctx *ctx, const rn_plan *pl, int mode, const SpgParams &p, int batch, bool mixed) {
-  if (p.nblk == 0) return RN_OK;
-  switch (mode) {
-    case MODE_PRODUCT: return launch_mode<MODE_PRODUCT>(ctx, pl, p, batch, mixed);
-    case MODE_CG_INIT: return launch_mode<MODE_CG_INIT>(ctx, pl, p, batch, mixed);
-    case MODE_CG_STEP: return launch_mode<MODE_CG_STEP>(ctx, pl, p, batch, mixed);
-    case MODE_GM_INIT: return launch_mode<MODE_GM_INIT>(ctx, pl, p, batch, mixed);
-    case MODE_GM_STEP: return launch_mode<MODE_GM_STEP>(ctx, pl, p, batch, mixed);
+rn_status rn_launch_spgemm(rn_ctx *ctx, const rn_plan *pl, int mode, const SpgParams &p, int batch, bool mixed,
+                           int *npart) {
+  int np = 0;
+  rn_status st = RN_OK;
+  if (p.nblk > 0) {
+    switch (mode) {
+      case MODE_PRODUCT: st = launch_mode<MODE_PRODUCT>(ctx, pl, p, batch, mixed, &np); break;
+      case MODE_CG_INIT: st = launch_mode<MODE_CG_INIT>(ctx, pl, p, batch, mixed, &np); break;
+      case MODE_CG_STEP: st = launch_mode<MODE_CG_STEP>(ctx, pl, p, batch, mixed, &np); break;
+      case MODE_GM_INIT: st = launch_mode<MODE_GM_INIT>(ctx, pl, p, batch, mixed, &np); break;
+      case MODE_GM_STEP: st = launch_mode<MODE_GM_STEP>(ctx, pl, p, batch, mixed, &np); break;
+      default: return rn_fail(ctx, RN_EINVAL, "bad product mode");
+    }
   }
-  return rn_fail(ctx, RN_EINVAL, "bad product mode");
+  if (npart) *npart = np;
+  return st;
 }
 
 SpgParams rn_spg_params(const rn_plan *pl) {
