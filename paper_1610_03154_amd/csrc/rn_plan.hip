@@ -246,6 +246,7 @@ __global__ __launch_bounds__(BSZ) void k_plan_xwin(int32_t *__restrict__ hdr, co
   __shared__ uint32_t s_bits[NWORD];
   __shared__ int s_v[ACAP];  // distinct columns, ascending
   __shared__ int s_r[ACAP];  // run of each distinct column
+  __shared__ int s_np0[ACAP], s_np1[ACAP];  // first and end pattern entry of each distinct column's row
   __shared__ int s_cnt[BSZ / RN_WAVE];
   __shared__ int s_mm[2 * (BSZ / RN_WAVE)];
   __shared__ int s_xs[XW_RUNMAX + 1], s_xe[XW_RUNMAX + 1], s_dst[XW_RUNMAX + 1];
@@ -262,13 +263,19 @@ __global__ __launch_bounds__(BSZ) void k_plan_xwin(int32_t *__restrict__ hdr, co
     none();
     return;
   }
+  // the block's A columns, loaded once (na <= ACAP = KPT * BSZ)
+  constexpr int KPT = ACAP / BSZ;
+  int kr[KPT];
+#pragma unroll
+  for (int i = 0; i < KPT; ++i) kr[i] = t + i * BSZ < na ? Aj[a0 + t + i * BSZ] : -1;
   // column range of the block
   int kmin = INT_MAX, kmax = -1;
-  for (int q = t; q < na; q += BSZ) {
-    const int k = Aj[a0 + q];
-    kmin = min(kmin, k);
-    kmax = max(kmax, k);
-  }
+#pragma unroll
+  for (int i = 0; i < KPT; ++i)
+    if (kr[i] >= 0) {
+      kmin = min(kmin, kr[i]);
+      kmax = max(kmax, kr[i]);
+    }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
     kmin = min(kmin, __shfl_xor(kmin, off, RN_WAVE));
@@ -290,10 +297,12 @@ __global__ __launch_bounds__(BSZ) void k_plan_xwin(int32_t *__restrict__ hdr, co
     none();
     return;
   }
-  for (int q = t; q < na; q += BSZ) {
-    const int k = Aj[a0 + q] - kmin;
-    atomicOr(&s_bits[k >> 5], 1u << (k & 31));
-  }
+#pragma unroll
+  for (int i = 0; i < KPT; ++i)
+    if (kr[i] >= 0) {
+      const int k = kr[i] - kmin;
+      atomicOr(&s_bits[k >> 5], 1u << (k & 31));
+    }
   __syncthreads();
   // distinct columns in ascending order: thread t owns words t*WPT ..
   uint32_t wd[WPT];
@@ -315,12 +324,17 @@ __global__ __launch_bounds__(BSZ) void k_plan_xwin(int32_t *__restrict__ hdr, co
     }
   }
   __syncthreads();
+  for (int i = t; i < nu; i += BSZ) {
+    s_np0[i] = Np[s_v[i]];
+    s_np1[i] = Np[s_v[i] + 1];
+  }
+  __syncthreads();
   // runs of the neighbour rows' entries
   int nrun = 0;
   for (int i0 = 0; i0 < nu; i0 += BSZ) {
     const int i = i0 + t;
     bool f = false;
-    if (i < nu) f = i == 0 || (int64_t)Np[s_v[i]] - Np[s_v[i - 1] + 1] > XW_GAP;
+    if (i < nu) f = i == 0 || (int64_t)s_np0[i] - s_np1[i - 1] > XW_GAP;
     int tot;
     const int pre = xw_scan<BSZ>(f ? 1 : 0, s_cnt, tot);
     // run id of position i: starts at or before i, minus one
@@ -328,10 +342,10 @@ __global__ __launch_bounds__(BSZ) void k_plan_xwin(int32_t *__restrict__ hdr, co
       const int rid = nrun + pre + (f ? 1 : 0) - 1;
       s_r[i] = rid;
       if (rid <= XW_RUNMAX - 1) {
-        if (f) s_xs[rid] = Np[s_v[i]];
+        if (f) s_xs[rid] = s_np0[i];
         // the last column of its run: the next position starts a run or ends the list
-        const bool last = i == nu - 1 || (int64_t)Np[s_v[i + 1]] - Np[s_v[i] + 1] > XW_GAP;
-        if (last) s_xe[rid] = Np[s_v[i] + 1];
+        const bool last = i == nu - 1 || (int64_t)s_np0[i + 1] - s_np1[i] > XW_GAP;
+        if (last) s_xe[rid] = s_np1[i];
       }
     }
     nrun += tot;
@@ -366,11 +380,13 @@ __global__ __launch_bounds__(BSZ) void k_plan_xwin(int32_t *__restrict__ hdr, co
       if (s_dst[rr] <= u * XW_UNIT) r = rr;
     uw[u] = u < nunit ? s_xs[r] + u * XW_UNIT - s_dst[r] : 0;
   }
-  for (int q = t; q < na; q += BSZ) {
-    const int k = Aj[a0 + q];
-    const int r = s_r[rn_lower_bound(s_v, nu, k)];
-    xl[a0 + q] = s_dst[r] + Np[k] - s_xs[r];
-  }
+#pragma unroll
+  for (int i = 0; i < KPT; ++i)
+    if (kr[i] >= 0) {
+      const int idx = rn_lower_bound(s_v, nu, kr[i]);
+      const int r = s_r[idx];
+      xl[a0 + t + i * BSZ] = s_dst[r] + s_np0[idx] - s_xs[r];
+    }
 }
 
 // ---- position codes: one lane per pattern entry (node entry for block_m = 2),
@@ -378,6 +394,9 @@ __global__ __launch_bounds__(BSZ) void k_plan_xwin(int32_t *__restrict__ hdr, co
 // neighbour row; up to 12 searches run in lockstep so their loads overlap.
 // Root entries get CODE_NONE throughout; the record's first byte is the
 // entry's row within the block, code u is byte u + 1. ------------------------
+// Blocks with an X window (block_m = 1, the window built by k_plan_xwin)
+// search in LDS: the window's column indices, and per A entry of the block
+// the window offset and length of its row of N, are staged first.
 template <int M>
 __global__ __launch_bounds__(RN_BLOCK) void k_plan_codes(int nblk, int32_t *__restrict__ hdr,
                                                         const int32_t *__restrict__ rp,
@@ -387,16 +406,43 @@ __global__ __launch_bounds__(RN_BLOCK) void k_plan_codes(int nblk, int32_t *__re
                                                         const int32_t *__restrict__ Nj,
                                                         const uint8_t *__restrict__ is_root, int cstride,
                                                         uint8_t *__restrict__ codes, int32_t *__restrict__ ncol,
-                                                        int32_t *__restrict__ terms) {
+                                                        int32_t *__restrict__ terms, const int32_t *__restrict__ xl,
+                                                        const int32_t *__restrict__ xwin, int nu_stride, int acap,
+                                                        int nit) {
+  constexpr int WCAP = SPG_XCAP_M1(RN_BLOCK), ACAPX = SPG_ACAP_M1(RN_BLOCK);
   __shared__ uint8_t s_row[RN_BLOCK];
   __shared__ int s_na[RN_BLOCK / RN_WAVE];
+  __shared__ int32_t s_nw[M == 1 ? WCAP : 1];
+  __shared__ int32_t s_xl[M == 1 ? ACAPX : 1], s_len[M == 1 ? ACAPX : 1];
   const int t = threadIdx.x;
   int32_t *h = (int32_t *)hdr + 8 * (int64_t)blockIdx.x;
   const int r0 = h[0], e0 = h[2], ne = h[3] - h[2], nrows = h[1] - h[0];
+  const int a0b = h[4], nab = h[5] - h[4];
+  const int nunit = M == 1 && xl ? h[7] : 0;
+  const bool win = M == 1 && nunit > 0 && nab <= acap && nunit * XW_UNIT <= WCAP && nab <= ACAPX;  // uniform
+  if (win) {
+    const int32_t *uw = xwin + (int64_t)blockIdx.x * nu_stride;
+    for (int q = t; q < nunit * XW_UNIT; q += blockDim.x) s_nw[q] = Nj[uw[q / XW_UNIT] + q % XW_UNIT];
+    for (int q = t; q < nab; q += blockDim.x) {
+      const int k = Aj[a0b + q];
+      s_xl[q] = xl[a0b + q];
+      s_len[q] = Np[k + 1] - Np[k];
+    }
+  }
+  // per row of the block: its A range and root flag, staged with the row map
+  // (the lanes then read them from LDS instead of waiting on more loads)
+  __shared__ int32_t s_ra[RN_BLOCK], s_rn[RN_BLOCK];
+  __shared__ uint8_t s_rr[RN_BLOCK];
+  const int jpre = (M == 1 && t < ne) ? Nj[e0 + t] : 0;  // block_m = 1: the entry's column
   int na_max = 0;
   for (int rr = t; rr < nrows; rr += blockDim.x) {
     for (int q = rp[r0 + rr] - e0; q < rp[r0 + rr + 1] - e0; ++q) s_row[q] = (uint8_t)rr;
-    if (!is_root[M * (r0 + rr)]) na_max = max(na_max, Ap[r0 + rr + 1] - Ap[r0 + rr]);
+    const int a = Ap[r0 + rr], an = Ap[r0 + rr + 1] - a;
+    const uint8_t rt = is_root[M * (r0 + rr)];
+    s_ra[rr] = a;
+    s_rn[rr] = an;
+    s_rr[rr] = rt;
+    if (!rt) na_max = max(na_max, an);
   }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) na_max = max(na_max, __shfl_xor(na_max, off, RN_WAVE));
@@ -411,45 +457,73 @@ __global__ __launch_bounds__(RN_BLOCK) void k_plan_codes(int nblk, int32_t *__re
   if (t < ne) {
     const int lr = s_row[t];
     const int i = r0 + lr;
-    const int rdof = M == 1 ? i : 2 * i;
     uint32_t *cw = (uint32_t *)(codes + (int64_t)(e0 + t) * cstride);
     const int nw = cstride >> 2;
-    if (is_root[rdof]) {
+    if (s_rr[lr]) {
       cw[0] = 0xffffff00u | (uint32_t)lr;
       for (int w = 1; w < nw; ++w) cw[w] = 0xffffffffu;
       if (M == 2) ncol[e0 + t] = Nj[Np[2 * i]] / 2;
     } else {
-      const int r = e0 + t - rp[i];
-      const int a0 = Ap[i], na = Ap[i + 1] - a0;
-      const int j = M == 1 ? Nj[Np[i] + r] : Nj[Np[2 * i] + 2 * r] / 2;
+      const int a0 = s_ra[lr], na = s_rn[lr];
+      const int j = M == 1 ? jpre : Nj[Np[2 * i] + 2 * (e0 + t - rp[i])] / 2;
       if (M == 2) ncol[e0 + t] = j;
       uint32_t carry = (uint32_t)lr;  // byte 0 of the next word: the row, then the last code of a pass
       for (int w0 = 0; w0 < nw; w0 += 3) {
         constexpr int U = 12;
         int ks[U], lo[U], hi[U], len[U];
         bool live[U], kroot[U];
+        // a neighbour row of N: its start (in the LDS window or in Nj) and length
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const int tt = 4 * w0 + u;
           live[u] = tt < na;
-          const int k = live[u] ? Aj[a0 + tt] : 0;
-          ks[u] = Np[M * k];
+          if (win) {
+            const int q = live[u] ? a0 - a0b + tt : 0;
+            ks[u] = s_xl[q];
+            len[u] = s_len[q];
+            kroot[u] = false;
+          } else {
+            const int k = live[u] ? Aj[a0 + tt] : 0;
+            ks[u] = Np[M * k];
+            len[u] = (Np[M * k + 1] - ks[u]) / M;
+            kroot[u] = M == 2 && is_root[2 * k];
+          }
           lo[u] = 0;
-          len[u] = (Np[M * k + 1] - ks[u]) / M;
           hi[u] = len[u];
-          kroot[u] = M == 2 && is_root[2 * k];
         }
-        // lockstep binary search for j among the (node) columns of each row
-        bool more = true;
-        while (more) {
-          more = false;
+        auto col = [&](int u, int pos) -> int {
+          if (win) return s_nw[ks[u] + pos];
+          return M == 1 ? Nj[ks[u] + pos] : Nj[ks[u] + 2 * pos] / 2;
+        };
+        if (win) {
+          // in LDS: nit halvings cover every row (len <= maxlen < 2^nit),
+          // branch-free with clamped reads
+          const int wl = nunit * XW_UNIT - 1;
 #pragma unroll
-          for (int u = 0; u < U; ++u) {
-            if (live[u] && !kroot[u] && lo[u] < hi[u]) {
+          for (int u = 0; u < U; ++u)
+            if (!live[u]) hi[u] = 0;
+          for (int it = 0; it < nit; ++it) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
               const int mid = (lo[u] + hi[u]) >> 1;
-              const int c = M == 1 ? Nj[ks[u] + mid] : Nj[ks[u] + 2 * mid] / 2;
-              if (c < j) lo[u] = mid + 1; else hi[u] = mid;
-              more = more || lo[u] < hi[u];
+              const bool lt = s_nw[min(ks[u] + mid, wl)] < j, go = lo[u] < hi[u];
+              lo[u] = (go && lt) ? mid + 1 : lo[u];
+              hi[u] = (go && !lt) ? mid : hi[u];
+            }
+          }
+        } else {
+          // lockstep binary search for j among the (node) columns of each row
+          bool more = true;
+          while (more) {
+            more = false;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+              if (live[u] && !kroot[u] && lo[u] < hi[u]) {
+                const int mid = (lo[u] + hi[u]) >> 1;
+                const int c = col(u, mid);
+                if (c < j) lo[u] = mid + 1; else hi[u] = mid;
+                more = more || lo[u] < hi[u];
+              }
             }
           }
         }
@@ -457,12 +531,15 @@ __global__ __launch_bounds__(RN_BLOCK) void k_plan_codes(int nblk, int32_t *__re
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           uint32_t code = CODE_NONE;
-          if (live[u]) {
+          if (win) {
+            const bool f = live[u] && lo[u] < len[u] && s_nw[min(ks[u] + lo[u], nunit * XW_UNIT - 1)] == j;
+            code = f ? (uint32_t)lo[u] : CODE_NONE;
+            hit += f;
+          } else if (live[u]) {
             if (kroot[u]) {
               code = (Nj[ks[u]] / 2 == j) ? CODE_ROOT : CODE_NONE;
             } else if (lo[u] < len[u]) {
-              const int c = M == 1 ? Nj[ks[u] + lo[u]] : Nj[ks[u] + 2 * lo[u]] / 2;
-              if (c == j) code = (uint32_t)lo[u];
+              if (col(u, lo[u]) == j) code = (uint32_t)lo[u];
             }
             hit += code != CODE_NONE;
           }
@@ -651,14 +728,7 @@ extern "C" rn_status rn_plan_create(rn_ctx *ctx, const rn_matrix *A, int32_t n_c
     if (!blk_hit) return fail(st);
     const dim3 gc(pl->nblk), bc(pl->bs);  // one thread per entry slot of a product block
     const int nb = pl->nblk;
-    if (m == 1)
-      hipLaunchKernelGGL((k_plan_codes<1>), gc, bc, 0, ctx->stream, nb, pl->blk_hdr, rp, A->rowptr, A->colind, Np,
-                         Nj, is_root, pl->cstride, pl->codes, pl->ncol, blk_hit);
-    else
-      hipLaunchKernelGGL((k_plan_codes<2>), gc, bc, 0, ctx->stream, nb, pl->blk_hdr, rp, A->rowptr, A->colind, Np,
-                         Nj, is_root, pl->cstride, pl->codes, pl->ncol, blk_hit);
-    hipLaunchKernelGGL((k_finish_slots<false, unsigned long long>), dim3(1), dim3(RN_BLOCK), 0, ctx->stream, blk_hit,
-                       pl->nblk, pl->d_terms);
+    // X windows first: the codes of a block with a window are searched in LDS
     if (m == 1) {
       switch (pl->bs) {
         case 64:
@@ -674,6 +744,17 @@ extern "C" rn_status rn_plan_create(rn_ctx *ctx, const rn_matrix *A, int32_t n_c
                              nnz_N, pl->xl, pl->xwin);
       }
     }
+    const int nu_stride = SPG_XCAP_M1(pl->bs) / XW_UNIT, acap = SPG_ACAP_M1(pl->bs);
+    if (m == 1)
+      hipLaunchKernelGGL((k_plan_codes<1>), gc, bc, 0, ctx->stream, nb, pl->blk_hdr, rp, A->rowptr, A->colind, Np,
+                         Nj, is_root, pl->cstride, pl->codes, pl->ncol, blk_hit, pl->xl, pl->xwin, nu_stride, acap,
+                         32 - __builtin_clz((unsigned)(pl->maxlen > 0 ? pl->maxlen : 1)));
+    else
+      hipLaunchKernelGGL((k_plan_codes<2>), gc, bc, 0, ctx->stream, nb, pl->blk_hdr, rp, A->rowptr, A->colind, Np,
+                         Nj, is_root, pl->cstride, pl->codes, pl->ncol, blk_hit, (const int32_t *)nullptr,
+                         (const int32_t *)nullptr, 0, 0, 0);
+    hipLaunchKernelGGL((k_finish_slots<false, unsigned long long>), dim3(1), dim3(RN_BLOCK), 0, ctx->stream, blk_hit,
+                       pl->nblk, pl->d_terms);
     if (hipGetLastError() != hipSuccess) return fail(rn_fail(ctx, RN_EHIP, "launch"));
   }
   try {
