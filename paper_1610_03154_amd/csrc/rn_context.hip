@@ -500,6 +500,50 @@ rn_status rn_validate_range(rn_ctx *ctx, int64_t n, const int32_t *a, int32_t lo
   return RN_OK;
 }
 
+// Several checks in one launch: thread i takes row i of each CSR structure
+// and element i of each index array.
+__global__ __launch_bounds__(RN_BLOCK) void k_validate_all(const RnChecks v, int32_t *__restrict__ guard) {
+  const int64_t i = (int64_t)blockIdx.x * RN_BLOCK + threadIdx.x;
+  int32_t bad = 0;
+  for (int q = 0; q < v.ncsr; ++q) {
+    const RnCsrCheck &c = v.csr[q];
+    if (i > c.rows) continue;
+    const int64_t nnz = c.nnz < 0 ? c.Ap[c.rows] : c.nnz;
+    const int64_t s = c.Ap[i];
+    bool b = (i == 0 && s != 0) || (i == c.rows && s != nnz) || s < 0 || s > nnz;
+    if (!b && i < c.rows) {
+      const int64_t e = c.Ap[i + 1];
+      if (e < s || e > nnz) {
+        b = true;
+      } else {
+        int prev = -1;
+        for (int64_t p = s; p < e; ++p) {
+          const int j = c.Aj[p];
+          if (j <= prev || j >= c.cols) { b = true; break; }
+          prev = j;
+        }
+      }
+    }
+    if (b) bad |= c.bit;
+  }
+  for (int q = 0; q < v.nrange; ++q) {
+    const RnRangeCheck &r = v.range[q];
+    if (i < r.n && (r.a[i] < r.lo || r.a[i] >= r.hi)) bad |= r.bit;
+  }
+  if (bad) atomicOr(guard, bad);
+}
+
+rn_status rn_validate(rn_ctx *ctx, const RnChecks &v, int32_t *guard) {
+  int64_t m = 0;
+  for (int q = 0; q < v.ncsr; ++q) m = v.csr[q].rows + 1 > m ? v.csr[q].rows + 1 : m;
+  for (int q = 0; q < v.nrange; ++q) m = v.range[q].n > m ? v.range[q].n : m;
+  if (m <= 0) return RN_OK;
+  if (m >= ((int64_t)1 << 31)) return rn_fail(ctx, RN_ELIMIT, "rn_validate: %lld elements", (long long)m);
+  hipLaunchKernelGGL(k_validate_all, dim3(rn_div_up(m, RN_BLOCK)), dim3(RN_BLOCK), 0, ctx->stream, v, guard);
+  LAUNCH_CHECK(ctx);
+  return RN_OK;
+}
+
 static rn_status guard_message(rn_ctx *ctx, int32_t g, const char *what) {
   if (!g) return RN_OK;
   if (g & GUARD_LIMIT) return rn_fail(ctx, RN_ELIMIT, "%s: a documented size limit was exceeded", what);

@@ -77,6 +77,7 @@ struct rn_ctx {
   // two-phase caches
   int64_t str_nnz = -1;
   int32_t str_nodes = -1;
+  bool str_direct = false;     // phase 2 of the strength fills S from the kept-entry mask
   int64_t pat_nnz = -1;        // nnz of the DOF pattern
   int32_t pat_n = -1;          // rows of the DOF pattern
   XRows pat_x{};               // the final nodal level (read by phase 2)
@@ -158,6 +159,25 @@ enum RnGuardBits { GUARD_A = 1, GUARD_S = 2, GUARD_N = 4, GUARD_AGG = 8, GUARD_R
 int32_t *rn_guard_begin(rn_ctx *ctx, rn_status *st);
 // rows x cols CSR: rowptr[0] = 0, non-decreasing, rowptr[rows] = nnz,
 // columns in [0, cols) and strictly increasing within a row.
+// Up to two CSR structures and two index arrays checked in one launch (the
+// same tests as rn_validate_csr / rn_validate_range).
+struct RnCsrCheck {
+  int32_t rows, cols;
+  int64_t nnz;  // < 0: the structure's own last row pointer
+  const int32_t *Ap, *Aj;
+  int32_t bit;
+};
+struct RnRangeCheck {
+  int64_t n;
+  const int32_t *a;
+  int32_t lo, hi, bit;
+};
+struct RnChecks {
+  RnCsrCheck csr[2];
+  RnRangeCheck range[2];
+  int ncsr, nrange;
+};
+rn_status rn_validate(rn_ctx *ctx, const RnChecks &v, int32_t *guard);
 rn_status rn_validate_csr(rn_ctx *ctx, int32_t rows, int32_t cols, int64_t nnz, const int32_t *Ap,
                           const int32_t *Aj, int32_t *guard, int32_t bit);
 // every a[q] in [lo, hi)

@@ -277,6 +277,20 @@ extern "C" rn_status rn_strength(rn_ctx *ctx, const rn_matrix *A, double theta, 
     return rn_fail(ctx, RN_EINVAL, "rn_strength: bad matrix descriptor");
   if (!(theta >= 0.0)) return rn_fail(ctx, RN_EINVAL, "rn_strength: theta must be >= 0");
   if (A->nnz >= ((int64_t)1 << 31)) return rn_fail(ctx, RN_ELIMIT, "rn_strength: nnz >= 2^31");
+  if (S_colind && ctx->str_direct) {  // phase 2, symmetric structure: fill S from the kept-entry mask
+    const int nn = A->n / m;
+    if (ctx->str_nnz < 0 || ctx->str_nodes != nn)
+      return rn_fail(ctx, RN_EINVAL, "rn_strength: phase 2 without a matching phase 1");
+    if (nn > 0) {
+      hipLaunchKernelGGL(k_partner_fill_g, dim3(rn_div_up(nn, SRPB)), dim3(RN_BLOCK), 0, ctx->stream, nn, A->rowptr,
+                         A->colind, (const uint8_t *)ctx->slot[SLOT_STR_TMASK].ptr, S_rowptr, S_colind);
+      LAUNCH_CHECK(ctx);
+    }
+    *nnz_S = ctx->str_nnz;
+    ctx->str_nnz = -1;
+    ctx->str_direct = false;
+    return RN_OK;
+  }
   if (S_colind) return strength_transpose_path(ctx, A, theta, S_rowptr, S_colind, nnz_S);  // phase 2 copy
   const int nn = A->n / m;
   const int64_t nz = A->nnz;
@@ -321,14 +335,10 @@ extern "C" rn_status rn_strength(rn_ctx *ctx, const rn_matrix *A, double theta, 
   memcpy(&hasym, hb + off[2], 4);
   RN_TRY(rn_guard_status(ctx, gword, "rn_strength"));
   if (hasym) return strength_transpose_path(ctx, A, theta, S_rowptr, nullptr, nnz_S);
-  int32_t *Sj = (int32_t *)rn_scratch(ctx, SLOT_STR_SJ, (size_t)(total + 1) * sizeof(int32_t), &st);
-  if (!Sj) return st;
-  if (nn > 0) {
-    hipLaunchKernelGGL(k_partner_fill_g, gg, b, 0, ctx->stream, nn, A->rowptr, A->colind, symmask, S_rowptr, Sj);
-    LAUNCH_CHECK(ctx);
-  }
+  // the columns are written by phase 2 straight into the caller's array
   ctx->str_nnz = total;
   ctx->str_nodes = nn;
+  ctx->str_direct = true;
   *nnz_S = total;
   return RN_OK;
 }
@@ -413,6 +423,7 @@ static rn_status strength_transpose_path(rn_ctx *ctx, const rn_matrix *A, double
   }
   ctx->str_nnz = total;
   ctx->str_nodes = nn;
+  ctx->str_direct = false;
   *nnz_S = total;
   return RN_OK;
 }
@@ -806,9 +817,15 @@ extern "C" rn_status rn_pattern(rn_ctx *ctx, int32_t nn, const int32_t *Sp, cons
   int32_t *guard = rn_guard_begin(ctx, &st);
   if (!guard) return st;
   // S is validated against its own last row pointer (nnz = -1)
-  RN_TRY(rn_validate_csr(ctx, nn, nn, -1, Sp, Sj, guard, GUARD_S));
-  RN_TRY(rn_validate_range(ctx, nn, agg, 0, n_agg, guard, GUARD_AGG));
-  RN_TRY(rn_validate_range(ctx, n_agg, roots, 0, nn, guard, GUARD_ROOTS));
+  {
+    RnChecks v{};
+    v.csr[0] = {nn, nn, -1, Sp, Sj, GUARD_S};
+    v.ncsr = 1;
+    v.range[0] = {nn, agg, 0, n_agg, GUARD_AGG};
+    v.range[1] = {n_agg, roots, 0, nn, GUARD_ROOTS};
+    v.nrange = 2;
+    RN_TRY(rn_validate(ctx, v, guard));
+  }
   int64_t total = 0;
   if ((int64_t)nn * PCAP < ((int64_t)1 << 31) && pattern_pad_on()) {
     bool ok = false;

@@ -595,9 +595,13 @@ extern "C" rn_status rn_plan_create(rn_ctx *ctx, const rn_matrix *A, int32_t n_c
   const int NP = nB * (nB + 1) / 2;
   int32_t *guard = rn_guard_begin(ctx, &st);
   if (!guard) return fail(st);
-  if (rn_validate_csr(ctx, nr, nr, A->nnz, A->rowptr, A->colind, guard, GUARD_A) != RN_OK ||
-      rn_validate_csr(ctx, n, n_cols, nnz_N, Np, Nj, guard, GUARD_N) != RN_OK)
-    return fail(RN_EHIP);
+  {
+    RnChecks v{};
+    v.csr[0] = {nr, nr, A->nnz, A->rowptr, A->colind, GUARD_A};
+    v.csr[1] = {n, n_cols, nnz_N, Np, Nj, GUARD_N};
+    v.ncsr = 2;
+    if (rn_validate(ctx, v, guard) != RN_OK) return fail(RN_EHIP);
+  }
   // scratch: [0] maxlen, [1] rank_def, [2] longest A row of a non-root row,
   // [8..9] node-entry total (int64)
   int32_t *misc = (int32_t *)rn_scratch(ctx, SLOT_MISC, 64, &st);

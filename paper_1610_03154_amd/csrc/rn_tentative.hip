@@ -127,9 +127,15 @@ extern "C" rn_status rn_tentative(rn_ctx *ctx, int32_t n, int32_t m, const int32
   HIP_TRY(ctx, hipMemsetAsync(flags, 0, 4 * sizeof(int32_t), ctx->stream));
   int32_t *guard = rn_guard_begin(ctx, &st);
   if (!guard) return st;
-  RN_TRY(rn_validate_csr(ctx, n, nc, nnz_N, Np, Nj, guard, GUARD_N));
-  RN_TRY(rn_validate_range(ctx, nn, agg, 0, n_agg, guard, GUARD_AGG));
-  RN_TRY(rn_validate_range(ctx, n_agg, roots, 0, nn, guard, GUARD_ROOTS));
+  {
+    RnChecks v{};
+    v.csr[0] = {n, nc, nnz_N, Np, Nj, GUARD_N};
+    v.ncsr = 1;
+    v.range[0] = {nn, agg, 0, n_agg, GUARD_AGG};
+    v.range[1] = {n_agg, roots, 0, nn, GUARD_ROOTS};
+    v.nrange = 2;
+    RN_TRY(rn_validate(ctx, v, guard));
+  }
   if (nc > 0) {
     hipLaunchKernelGGL(k_inject_bc, dim3(rn_div_up(nc, RN_BLOCK)), dim3(RN_BLOCK), 0, ctx->stream, n_agg, m, nB,
                        roots, B, Bc, guard);
