@@ -391,7 +391,7 @@ __global__ __launch_bounds__(BSZ) void k_plan_xwin(int32_t *__restrict__ hdr, co
 
 // ---- position codes: one lane per pattern entry (node entry for block_m = 2),
 // one block per product block.  The column of the entry is searched in every
-// neighbour row; up to 12 searches run in lockstep so their loads overlap.
+// neighbour row; the searches of one record word run in lockstep so their loads overlap.
 // Root entries get CODE_NONE throughout; the record's first byte is the
 // entry's row within the block, code u is byte u + 1. ------------------------
 // Blocks with an X window (block_m = 1, the window built by k_plan_xwin)
@@ -467,48 +467,41 @@ __global__ __launch_bounds__(RN_BLOCK) void k_plan_codes(int nblk, int32_t *__re
       const int a0 = s_ra[lr], na = s_rn[lr];
       const int j = M == 1 ? jpre : Nj[Np[2 * i] + 2 * (e0 + t - rp[i])] / 2;
       if (M == 2) ncol[e0 + t] = j;
-      uint32_t carry = (uint32_t)lr;  // byte 0 of the next word: the row, then the last code of a pass
-      for (int w0 = 0; w0 < nw; w0 += 3) {
-        constexpr int U = 12;
+      // one record word at a time: byte b of word w holds code u = 4w + b - 1
+      // (byte 0 of word 0 is the row); its four searches run in lockstep
+      for (int w = 0; w < nw; ++w) {
+        constexpr int U = 4;
         int ks[U], lo[U], hi[U], len[U];
         bool live[U], kroot[U];
-        // a neighbour row of N: its start (in the LDS window or in Nj) and length
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int tt = 4 * w0 + u;
-          live[u] = tt < na;
+        for (int q = 0; q < U; ++q) {
+          const int u = 4 * w + q - 1;
+          live[q] = u >= 0 && u < na;
           if (win) {
-            const int q = live[u] ? a0 - a0b + tt : 0;
-            ks[u] = s_xl[q];
-            len[u] = s_len[q];
-            kroot[u] = false;
+            const int x = live[q] ? a0 - a0b + u : 0;
+            ks[q] = s_xl[x];
+            len[q] = live[q] ? s_len[x] : 0;
+            kroot[q] = false;
           } else {
-            const int k = live[u] ? Aj[a0 + tt] : 0;
-            ks[u] = Np[M * k];
-            len[u] = (Np[M * k + 1] - ks[u]) / M;
-            kroot[u] = M == 2 && is_root[2 * k];
+            const int k = live[q] ? Aj[a0 + u] : 0;
+            ks[q] = Np[M * k];
+            len[q] = live[q] ? (Np[M * k + 1] - ks[q]) / M : 0;
+            kroot[q] = live[q] && M == 2 && is_root[2 * k];
           }
-          lo[u] = 0;
-          hi[u] = len[u];
+          lo[q] = 0;
+          hi[q] = len[q];
         }
-        auto col = [&](int u, int pos) -> int {
-          if (win) return s_nw[ks[u] + pos];
-          return M == 1 ? Nj[ks[u] + pos] : Nj[ks[u] + 2 * pos] / 2;
-        };
         if (win) {
           // in LDS: nit halvings cover every row (len <= maxlen < 2^nit),
           // branch-free with clamped reads
           const int wl = nunit * XW_UNIT - 1;
-#pragma unroll
-          for (int u = 0; u < U; ++u)
-            if (!live[u]) hi[u] = 0;
           for (int it = 0; it < nit; ++it) {
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-              const int mid = (lo[u] + hi[u]) >> 1;
-              const bool lt = s_nw[min(ks[u] + mid, wl)] < j, go = lo[u] < hi[u];
-              lo[u] = (go && lt) ? mid + 1 : lo[u];
-              hi[u] = (go && !lt) ? mid : hi[u];
+            for (int q = 0; q < U; ++q) {
+              const int mid = (lo[q] + hi[q]) >> 1;
+              const bool lt = s_nw[min(ks[q] + mid, wl)] < j, go = lo[q] < hi[q];
+              lo[q] = (go && lt) ? mid + 1 : lo[q];
+              hi[q] = (go && !lt) ? mid : hi[q];
             }
           }
         } else {
@@ -517,37 +510,35 @@ __global__ __launch_bounds__(RN_BLOCK) void k_plan_codes(int nblk, int32_t *__re
           while (more) {
             more = false;
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-              if (live[u] && !kroot[u] && lo[u] < hi[u]) {
-                const int mid = (lo[u] + hi[u]) >> 1;
-                const int c = col(u, mid);
-                if (c < j) lo[u] = mid + 1; else hi[u] = mid;
-                more = more || lo[u] < hi[u];
+            for (int q = 0; q < U; ++q) {
+              if (!kroot[q] && lo[q] < hi[q]) {
+                const int mid = (lo[q] + hi[q]) >> 1;
+                const int c = M == 1 ? Nj[ks[q] + mid] : Nj[ks[q] + 2 * mid] / 2;
+                if (c < j) lo[q] = mid + 1; else hi[q] = mid;
+                more = more || lo[q] < hi[q];
               }
             }
           }
         }
-        uint32_t word[3] = {carry, 0u, 0u};
+        uint32_t word = w == 0 ? (uint32_t)lr : 0u;
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
+        for (int q = 0; q < U; ++q) {
           uint32_t code = CODE_NONE;
           if (win) {
-            const bool f = live[u] && lo[u] < len[u] && s_nw[min(ks[u] + lo[u], nunit * XW_UNIT - 1)] == j;
-            code = f ? (uint32_t)lo[u] : CODE_NONE;
-            hit += f;
-          } else if (live[u]) {
-            if (kroot[u]) {
-              code = (Nj[ks[u]] / 2 == j) ? CODE_ROOT : CODE_NONE;
-            } else if (lo[u] < len[u]) {
-              if (col(u, lo[u]) == j) code = (uint32_t)lo[u];
+            const bool f = live[q] && lo[q] < len[q] && s_nw[min(ks[q] + lo[q], nunit * XW_UNIT - 1)] == j;
+            code = f ? (uint32_t)lo[q] : CODE_NONE;
+          } else if (live[q]) {
+            if (kroot[q]) {
+              code = (Nj[ks[q]] / 2 == j) ? CODE_ROOT : CODE_NONE;
+            } else if (lo[q] < len[q]) {
+              const int c = M == 1 ? Nj[ks[q] + lo[q]] : Nj[ks[q] + 2 * lo[q]] / 2;
+              if (c == j) code = (uint32_t)lo[q];
             }
-            hit += code != CODE_NONE;
           }
-          // code u of the pass sits at byte u + 1 of the pass's 12 bytes; the last one carries over
-          if (u < U - 1) word[(u + 1) >> 2] |= code << (8 * ((u + 1) & 3));
-          else carry = code;
+          hit += live[q] && code != CODE_NONE;
+          if (w > 0 || q > 0) word |= code << (8 * q);
         }
-        for (int w = w0; w < nw && w < w0 + 3; ++w) cw[w] = word[w - w0];
+        cw[w] = word;
       }
     }
   }
