@@ -133,7 +133,7 @@ rn_status rn_aggregate_host(int32_t n_nodes, const int32_t *S_rowptr_host,
  * coarse DOF m*agg + c).  Output: DOF pattern, n = m*n_nodes rows, m*n_agg
  * columns, sorted rows; is_root[i] = 1 for root DOF rows.
  * TWO-PHASE.  Phase 1 writes N_rowptr (n+1), is_root (n) and *nnz_N;
- * phase 2 writes N_colind.  Limit: a nodal row may gather at most 512
+ * phase 2 writes N_colind.  Limit: a nodal row may gather at most 6144
  * candidate entries in one expansion step (RN_ELIMIT). */
 rn_status rn_pattern(rn_ctx *ctx, int32_t n_nodes, const int32_t *S_rowptr,
                      const int32_t *S_colind, const int32_t *agg,
@@ -234,6 +234,39 @@ rn_status rn_energy_min_bwd(rn_ctx *ctx, rn_plan *plan, rn_plan *plan_T,
                             const int32_t *perm, rn_tape *tape,
                             const double *A_vals, const double *P_bar,
                             double *A_bar);
+
+/* ---- one-shot set-up of one level (Alg. root_node_setup) ---------------
+ * strength -> pattern -> tentative -> plan -> energy minimisation of P, and
+ * with Bhat (nullable, scalar CSR only) the transpose of A and the same
+ * minimisation of R^T on A^T from T-hat = inject(Bhat) (Sec. 4: R^T for a
+ * non-symmetric A; without Bhat R = P^T is left to the caller).  Inputs as
+ * for the stage calls: A (device, with values), agg (n/block_m) and roots
+ * (n_agg) device arrays from the caller's aggregation, B and Bhat (n x nB,
+ * row-major, device).  Every stage runs inside the library, one call; the
+ * outputs are device arrays owned by *out until rn_setup_destroy, which
+ * must come before rn_destroy of ctx.  A's arrays must stay valid while
+ * *out lives (its plans keep them).  On failure *out is NULL and nothing is
+ * kept.  stats / stats_RT (host, nullable) as for rn_energy_min. */
+typedef struct rn_setup_out rn_setup_out;
+typedef struct {
+  int32_t n, n_cols, nB, rank_deficient;
+  int64_t nnz_S, nnz_N;
+  const int32_t *S_rowptr, *S_colind; /* node graph S (n/block_m rows)         */
+  const int32_t *N_rowptr, *N_colind; /* pattern N (n rows, n_cols columns)   */
+  const uint8_t *is_root;             /* n                                     */
+  const double *T, *Bc, *P;           /* nnz_N, n_cols x nB, nnz_N             */
+  const double *That, *Bchat, *RT;    /* as T, Bc, P for B-hat on A^T, or NULL */
+  const rn_plan *plan, *plan_T;       /* plan_T NULL without Bhat              */
+} rn_setup_view;
+rn_status rn_setup(rn_ctx *ctx, const rn_matrix *A, const int32_t *agg,
+                   const int32_t *roots, int32_t n_agg, const double *B,
+                   const double *Bhat, int32_t nB, int32_t degree,
+                   int32_t iters, double theta, rn_method method,
+                   rn_precision precision, rn_setup_out **out,
+                   rn_emin_stats *stats, rn_emin_stats *stats_RT);
+/* Device pointers and sizes of the results (host struct). */
+rn_status rn_setup_view_get(const rn_setup_out *s, rn_setup_view *view);
+void rn_setup_destroy(rn_setup_out *s);
 
 #ifdef __cplusplus
 }

@@ -18,13 +18,14 @@ import numpy as np
 from . import _lib as L
 from ._lib import RN_CG, RN_GMRES, RN_FP64, RN_FP32_MIXED  # noqa: F401
 
-__all__ = ["RnError", "DeviceCSR", "Context", "Plan", "Tape", "EnergyMinOperator", "aggregate_host", "setup",
-           "RN_CG", "RN_GMRES", "RN_FP64", "RN_FP32_MIXED"]
+__all__ = ["RnError", "DeviceCSR", "Context", "Plan", "Tape", "NativeSetup", "EnergyMinOperator", "aggregate_host",
+           "setup", "RN_CG", "RN_GMRES", "RN_FP64", "RN_FP32_MIXED"]
 
 
 _LIVE_PLANS: "weakref.WeakSet" = weakref.WeakSet()
 _LIVE_CTX: "weakref.WeakSet" = weakref.WeakSet()
 _LIVE_TAPES: "weakref.WeakSet" = weakref.WeakSet()
+_LIVE_SETUPS: "weakref.WeakSet" = weakref.WeakSet()
 
 
 _EXIT_HOOK = []
@@ -35,6 +36,8 @@ def _close_all():
     # then the contexts they were made on
     for t in list(_LIVE_TAPES):
         t.close()
+    for s in list(_LIVE_SETUPS):
+        s.close()
     for p in list(_LIVE_PLANS):
         p.close()
     for c in list(_LIVE_CTX):
@@ -117,6 +120,70 @@ class Plan:
             pass
 
 
+_HIP = []
+
+
+def _d2d(dst: int, src: int, nbytes: int, stream) -> None:
+    """Stream-ordered device-to-device copy (the HIP runtime torch loaded)."""
+    if not _HIP:
+        h = C.CDLL("libamdhip64.so")
+        h.hipMemcpyAsync.restype = C.c_int
+        h.hipMemcpyAsync.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int, C.c_void_p]
+        _HIP.append(h)
+    if nbytes and _HIP[0].hipMemcpyAsync(dst, src, nbytes, 3, stream) != 0:  # 3: device to device
+        raise RuntimeError("hipMemcpyAsync failed")
+
+
+class NativeSetup:
+    """Results of rn_setup: the whole level set up by one library call.  The
+    arrays live in the library (device memory owned by the handle); tensor()
+    copies one of them into a new torch tensor."""
+
+    def __init__(self, ctx: "Context", handle, block_m: int, keep, stats, stats_RT):
+        self.ctx = ctx
+        self.handle = handle
+        self.block_m = block_m
+        self._keep = keep  # A's arrays: the set-up's plans hold their pointers
+        self.stats = stats
+        self.stats_RT = stats_RT
+        self.view = L.rn_setup_view()
+        ctx._check(L.lib().rn_setup_view_get(handle, C.byref(self.view)), "rn_setup_view_get")
+        _LIVE_SETUPS.add(self)
+
+    def _spec(self, name):
+        v, torch = self.view, self.ctx.torch
+        sizes = {"S_rowptr": (torch.int32, v.n // self.block_m + 1), "S_colind": (torch.int32, v.nnz_S),
+                 "N_rowptr": (torch.int32, v.n + 1), "N_colind": (torch.int32, v.nnz_N),
+                 "is_root": (torch.uint8, v.n), "T": (torch.float64, v.nnz_N), "P": (torch.float64, v.nnz_N),
+                 "Bc": (torch.float64, v.n_cols * v.nB), "That": (torch.float64, v.nnz_N),
+                 "RT": (torch.float64, v.nnz_N), "Bchat": (torch.float64, v.n_cols * v.nB)}
+        return sizes[name]
+
+    def tensor(self, name: str):
+        if not self.handle:
+            raise RuntimeError("the set-up was closed")
+        dtype, n = self._spec(name)
+        src = getattr(self.view, name)
+        if not src:
+            return None
+        t = self.ctx.torch.empty(max(int(n), 1), dtype=dtype, device="cuda")[:int(n)]
+        _d2d(t.data_ptr(), src, t.numel() * t.element_size(), C.c_void_p(self.ctx.stream.cuda_stream))
+        return t
+
+    def close(self):
+        if self.handle:
+            L.lib().rn_setup_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        if sys is None or sys.is_finalizing():
+            return
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Tape:
     """An rn_tape: the recorded CG iterates of one forward run, for the adjoint."""
 
@@ -160,7 +227,10 @@ class Context:
 
     def close(self):
         if getattr(self, "h", None):
-            for p in list(_LIVE_PLANS):  # plans made on this context go first
+            for s in list(_LIVE_SETUPS):  # set-ups and plans made on this context go first
+                if s.ctx is self:
+                    s.close()
+            for p in list(_LIVE_PLANS):
                 if p.ctx is self:
                     p.close()
             L.lib().rn_destroy(self.h)
@@ -222,6 +292,21 @@ class Context:
         return T[:Nj.numel()], Bc[:block_m * n_agg], rd.value
 
     # -- transpose -----------------------------------------------------------
+    def setup_native(self, A: DeviceCSR, B, agg, roots, theta=0.0, degree=2, iters=4, method=RN_CG,
+                     precision=RN_FP64, Bhat=None) -> NativeSetup:
+        """One rn_setup call: strength -> pattern -> T -> plan -> P (and R^T on
+        A^T when Bhat is given), every stage inside the library."""
+        h = C.c_void_p()
+        d = A.desc()
+        st, st_rt = L.rn_emin_stats(), L.rn_emin_stats()
+        B = B.to(self.torch.float64).contiguous()
+        Bhat = None if Bhat is None else Bhat.to(self.torch.float64).contiguous()
+        nB = int(B.shape[1]) if B.dim() == 2 else 1
+        self._check(L.lib().rn_setup(self.h, C.byref(d), _ptr(agg), _ptr(roots), int(roots.numel()), _ptr(B),
+                                     _ptr(Bhat), nB, degree, iters, C.c_double(theta), method, precision,
+                                     C.byref(h), C.byref(st), C.byref(st_rt)), "rn_setup")
+        return NativeSetup(self, h, A.block_m, (A, agg, roots, B, Bhat), st, st_rt if Bhat is not None else None)
+
     def transpose(self, A: DeviceCSR):
         torch = self.torch
         ATp = torch.empty(A.n + 1, dtype=torch.int32, device="cuda")

@@ -30,6 +30,16 @@ class rn_emin_stats(C.Structure):
                 ("spgemm_bytes", C.c_double), ("spgemm_flops", C.c_double)]
 
 
+class rn_setup_view(C.Structure):
+    _fields_ = [("n", C.c_int32), ("n_cols", C.c_int32), ("nB", C.c_int32), ("rank_deficient", C.c_int32),
+                ("nnz_S", C.c_int64), ("nnz_N", C.c_int64),
+                ("S_rowptr", C.c_void_p), ("S_colind", C.c_void_p),
+                ("N_rowptr", C.c_void_p), ("N_colind", C.c_void_p), ("is_root", C.c_void_p),
+                ("T", C.c_void_p), ("Bc", C.c_void_p), ("P", C.c_void_p),
+                ("That", C.c_void_p), ("Bchat", C.c_void_p), ("RT", C.c_void_p),
+                ("plan", C.c_void_p), ("plan_T", C.c_void_p)]
+
+
 # name -> (restype, argtypes); every declaration of include/rnamg.h
 _vp, _i32, _i64, _d = C.c_void_p, C.c_int32, C.c_int64, C.c_double
 _pi32, _pi64 = C.POINTER(C.c_int32), C.POINTER(C.c_int64)
@@ -54,6 +64,10 @@ SIGNATURES = {
     "rn_tape_create": (_i32, [_vp, _vp, _i32, _i32, C.POINTER(C.c_void_p)]),
     "rn_tape_destroy": (None, [_vp]),
     "rn_energy_min_bwd": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "rn_setup": (_i32, [_vp, C.POINTER(rn_matrix), _vp, _vp, _i32, _vp, _vp, _i32, _i32, _i32, _d, _i32, _i32,
+                        C.POINTER(C.c_void_p), C.POINTER(rn_emin_stats), C.POINTER(rn_emin_stats)]),
+    "rn_setup_view_get": (_i32, [_vp, C.POINTER(rn_setup_view)]),
+    "rn_setup_destroy": (None, [_vp]),
 }
 
 _lib = None

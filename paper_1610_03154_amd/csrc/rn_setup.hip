@@ -1,0 +1,134 @@
+// rn_setup.hip -- one-shot set-up of one level (Alg. root_node_setup): the
+// stage entry points run back to back inside the library, their outputs in
+// device memory owned by the returned handle (drawn from the context's
+// allocation cache, so repeated set-ups allocate nothing new).
+#include <cstring>
+#include <new>
+
+#include "rn_emin.h"
+
+struct rn_setup_out {
+  rn_ctx *ctx = nullptr;
+  rn_setup_view v{};
+  rn_plan *plan = nullptr, *plan_T = nullptr;
+  int32_t *AT_rowptr = nullptr, *AT_colind = nullptr;
+  double *AT_vals = nullptr;
+  void *bufs[16] = {};
+  int nbuf = 0;
+};
+
+static void *setup_alloc(rn_setup_out *s, size_t bytes) {
+  void *p = rn_dev_alloc(s->ctx, bytes ? bytes : 16);
+  if (p) s->bufs[s->nbuf++] = p;
+  return p;
+}
+
+extern "C" void rn_setup_destroy(rn_setup_out *s) {
+  if (!s) return;
+  if (s->plan) rn_plan_destroy(s->plan);
+  if (s->plan_T) rn_plan_destroy(s->plan_T);
+  for (int i = 0; i < s->nbuf; ++i) rn_dev_free(s->ctx, s->bufs[i]);
+  delete s;
+}
+
+extern "C" rn_status rn_setup_view_get(const rn_setup_out *s, rn_setup_view *view) {
+  if (!s || !view) return RN_EINVAL;
+  *view = s->v;
+  return RN_OK;
+}
+
+extern "C" rn_status rn_setup(rn_ctx *ctx, const rn_matrix *A, const int32_t *agg, const int32_t *roots,
+                              int32_t n_agg, const double *B, const double *Bhat, int32_t nB, int32_t degree,
+                              int32_t iters, double theta, rn_method method, rn_precision precision,
+                              rn_setup_out **out, rn_emin_stats *stats, rn_emin_stats *stats_RT) {
+  if (!ctx) return RN_EINVAL;
+  ctx->err.clear();
+  if (!out || !A || !B || (A->n > 0 && (!agg || !A->vals)) || (n_agg > 0 && !roots))
+    return rn_fail(ctx, RN_EINVAL, "rn_setup: null argument");
+  *out = nullptr;
+  const int m = A->block_m;
+  if ((m != 1 && m != 2) || A->n < 0 || A->n % m) return rn_fail(ctx, RN_EINVAL, "rn_setup: bad matrix descriptor");
+  if (Bhat && m != 1) return rn_fail(ctx, RN_EINVAL, "rn_setup: R^T on A^T needs a scalar CSR operator");
+  rn_setup_out *s = new (std::nothrow) rn_setup_out();
+  if (!s) return rn_fail(ctx, RN_ENOMEM, "rn_setup: host allocation");
+  s->ctx = ctx;
+  rn_setup_view &v = s->v;
+  const int nn = A->n / m, n = A->n, nc = m * n_agg;
+  v.n = n;
+  v.n_cols = nc;
+  v.nB = nB;
+  rn_status st = RN_OK;
+  auto fail = [&](rn_status e) {
+    rn_setup_destroy(s);
+    return e;
+  };
+  auto nomem = [&]() { return fail(rn_fail(ctx, RN_ENOMEM, "rn_setup: device allocation")); };
+  // a1/a2: strength (two phases: the size of S, then its columns)
+  int32_t *Sp = (int32_t *)setup_alloc(s, (size_t)(nn + 1) * 4);
+  if (!Sp) return nomem();
+  int64_t nnzS = 0;
+  if ((st = rn_strength(ctx, A, theta, Sp, nullptr, &nnzS)) != RN_OK) return fail(st);
+  int32_t *Sj = (int32_t *)setup_alloc(s, (size_t)nnzS * 4);
+  if (!Sj) return nomem();
+  if ((st = rn_strength(ctx, A, theta, Sp, Sj, &nnzS)) != RN_OK) return fail(st);
+  v.S_rowptr = Sp;
+  v.S_colind = Sj;
+  v.nnz_S = nnzS;
+  // a3/a4: pattern
+  int32_t *Np = (int32_t *)setup_alloc(s, (size_t)(n + 1) * 4);
+  uint8_t *is_root = (uint8_t *)setup_alloc(s, (size_t)n + 1);
+  if (!Np || !is_root) return nomem();
+  int64_t nnzN = 0;
+  if ((st = rn_pattern(ctx, nn, Sp, Sj, agg, roots, n_agg, degree, m, Np, nullptr, is_root, &nnzN)) != RN_OK)
+    return fail(st);
+  int32_t *Nj = (int32_t *)setup_alloc(s, (size_t)nnzN * 4);
+  if (!Nj) return nomem();
+  if ((st = rn_pattern(ctx, nn, Sp, Sj, agg, roots, n_agg, degree, m, Np, Nj, is_root, &nnzN)) != RN_OK)
+    return fail(st);
+  v.N_rowptr = Np;
+  v.N_colind = Nj;
+  v.is_root = is_root;
+  v.nnz_N = nnzN;
+  // a5/a6: T and Bc
+  double *T = (double *)setup_alloc(s, (size_t)nnzN * 8);
+  double *Bc = (double *)setup_alloc(s, (size_t)nc * nB * 8);
+  double *P = (double *)setup_alloc(s, (size_t)nnzN * 8);
+  if (!T || !Bc || !P) return nomem();
+  if ((st = rn_tentative(ctx, n, m, Np, Nj, nnzN, is_root, agg, roots, n_agg, B, nB, T, Bc, &v.rank_deficient)) !=
+      RN_OK)
+    return fail(st);
+  v.T = T;
+  v.Bc = Bc;
+  // a7-a11: plan and energy minimisation of P
+  if ((st = rn_plan_create(ctx, A, nc, Np, Nj, nnzN, is_root, Bc, nB, &s->plan)) != RN_OK) return fail(st);
+  if ((st = rn_energy_min(ctx, s->plan, A->vals, 1, T, method, iters, precision, P, nullptr, stats, nullptr)) !=
+      RN_OK)
+    return fail(st);
+  v.P = P;
+  v.plan = s->plan;
+  if (Bhat) {
+    // a10: R^T by the same minimisation on A^T with T-hat from B-hat
+    s->AT_rowptr = (int32_t *)setup_alloc(s, (size_t)(n + 1) * 4);
+    s->AT_colind = (int32_t *)setup_alloc(s, (size_t)A->nnz * 4);
+    s->AT_vals = (double *)setup_alloc(s, (size_t)A->nnz * 8);
+    double *That = (double *)setup_alloc(s, (size_t)nnzN * 8);
+    double *Bch = (double *)setup_alloc(s, (size_t)nc * nB * 8);
+    double *RT = (double *)setup_alloc(s, (size_t)nnzN * 8);
+    if (!s->AT_rowptr || !s->AT_colind || !s->AT_vals || !That || !Bch || !RT) return nomem();
+    if ((st = rn_transpose(ctx, A, s->AT_rowptr, s->AT_colind, s->AT_vals, nullptr)) != RN_OK) return fail(st);
+    const rn_matrix AT = {n, 1, A->nnz, s->AT_rowptr, s->AT_colind, s->AT_vals};
+    if ((st = rn_tentative(ctx, n, m, Np, Nj, nnzN, is_root, agg, roots, n_agg, Bhat, nB, That, Bch, nullptr)) !=
+        RN_OK)
+      return fail(st);
+    if ((st = rn_plan_create(ctx, &AT, nc, Np, Nj, nnzN, is_root, Bch, nB, &s->plan_T)) != RN_OK) return fail(st);
+    if ((st = rn_energy_min(ctx, s->plan_T, s->AT_vals, 1, That, method, iters, precision, RT, nullptr, stats_RT,
+                            nullptr)) != RN_OK)
+      return fail(st);
+    v.That = That;
+    v.Bchat = Bch;
+    v.RT = RT;
+    v.plan_T = s->plan_T;
+  }
+  *out = s;
+  return RN_OK;
+}

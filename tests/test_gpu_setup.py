@@ -1,0 +1,63 @@
+"""The one-shot set-up (rn_setup): every stage inside one library call.
+
+It runs the same kernels as the stage calls, so its outputs must equal the
+staged path's bit for bit (integer arrays, T, Bc, P, R^T), and P / R^T must
+match the oracle to the parity bars (FP64 1e-12, FP32-mixed 1e-5).
+"""
+import numpy as np
+import pytest
+
+from tests import cases as CS
+from tests.test_gpu_parity import R, ctx, dev, dev_matrix, host, run_path  # noqa: F401  (fixtures and helpers)
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-12
+MIXED_TOL = 1e-5
+
+
+@pytest.mark.parametrize("name,precision", [("aniso40", "fp64"), ("aniso40", "mixed"), ("upwind64", "fp64"),
+                                            ("elastic7", "fp64"), ("twocand13", "fp64")])
+def test_setup_matches_stages_and_oracle(R, ctx, name, precision):
+    c = CS.case(name)
+    prec = R.RN_FP64 if precision == "fp64" else R.RN_FP32_MIXED
+    tol = FP64_TOL if precision == "fp64" else MIXED_TOL
+    method = R.RN_GMRES if c["method"] == "gmres" else R.RN_CG
+    gm = c["method"] == "gmres"
+    A = dev_matrix(R, c)
+    agg, roots, B = dev(c["agg"]), dev(c["roots"]), dev(c["B"])
+    Bhat = dev(c["Bhat"]) if gm else None
+    s = ctx.setup_native(A, B, agg, roots, c["theta"], c["degree"], c["iters"], method, prec, Bhat=Bhat)
+    try:
+        g = run_path(R, ctx, c)
+        for key, ref in (("S_rowptr", g["Sp"]), ("S_colind", g["Sj"]), ("N_rowptr", g["Np"]),
+                         ("N_colind", g["Nj"]), ("is_root", g["is_root"]), ("T", g["T"]), ("Bc", g["Bc"])):
+            assert np.array_equal(host(s.tensor(key)), host(ref).reshape(-1)), key
+        assert s.view.rank_deficient == g["rd"]
+        P_ref, _, _ = ctx.energy_min(g["plan"], g["A"].vals, g["T"], method, c["iters"], prec)
+        P = host(s.tensor("P"))
+        assert np.array_equal(P, host(P_ref))
+        assert CS.rel_max(P, c["P"]) <= tol
+        assert s.stats.iters_done == c["iters"] or gm
+        if gm:
+            RT = host(s.tensor("RT"))
+            assert CS.rel_max(RT, c["RT"]) <= tol
+            assert s.stats_RT is not None and s.stats_RT.iters_done >= 1
+        else:
+            assert s.tensor("RT") is None
+        g["plan"].close()
+    finally:
+        s.close()
+
+
+def test_setup_reports_bad_input(R, ctx):
+    """A malformed aggregation (an index past n_agg) is an RN_EINVAL of the
+    call, and nothing is kept."""
+    c = CS.case("poisson32")
+    A = dev_matrix(R, c)
+    bad = c["agg"].copy()
+    bad[5] = c["roots"].size + 3
+    with pytest.raises(R.RnError) as e:
+        ctx.setup_native(A, dev(c["B"]), dev(bad), dev(c["roots"]), c["theta"], 2, 2)
+    from paper_1610_03154_amd import _lib
+    assert e.value.status == _lib.RN_EINVAL
