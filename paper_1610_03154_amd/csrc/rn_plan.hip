@@ -550,6 +550,12 @@ extern "C" rn_status rn_plan_create(rn_ctx *ctx, const rn_matrix *A, int32_t n_c
                                     int32_t nB, rn_plan **out) {
   if (!ctx) return RN_EINVAL;
   ctx->err.clear();
+  return rn_plan_create_ex(ctx, A, n_cols, Np, Nj, nnz_N, is_root, Bc, nB, out, nullptr, nullptr, nullptr);
+}
+
+rn_status rn_plan_create_ex(rn_ctx *ctx, const rn_matrix *A, int32_t n_cols, const int32_t *Np, const int32_t *Nj,
+                            int64_t nnz_N, const uint8_t *is_root, const double *Bc, int32_t nB, rn_plan **out,
+                            int32_t *guard_in, const RnFetch *extra, unsigned char *extra_out) {
   if (!A || !out) return rn_fail(ctx, RN_EINVAL, "rn_plan_create: null argument");
   *out = nullptr;
   const int m = A->block_m;
@@ -584,7 +590,7 @@ extern "C" rn_status rn_plan_create(rn_ctx *ctx, const rn_matrix *A, int32_t n_c
   };
   const int n = pl->n, nr = pl->nr;
   const int NP = nB * (nB + 1) / 2;
-  int32_t *guard = rn_guard_begin(ctx, &st);
+  int32_t *guard = guard_in ? guard_in : rn_guard_begin(ctx, &st);
   if (!guard) return fail(st);
   {
     RnChecks v{};
@@ -646,11 +652,13 @@ extern "C" rn_status rn_plan_create(rn_ctx *ctx, const rn_matrix *A, int32_t n_c
     if (hipGetLastError() != hipSuccess) return fail(rn_fail(ctx, RN_EHIP, "launch"));
   }
   // one synchronisation: guard, maxlen, rank_def, longest A row, node-entry total
-  const RnFetch it[3] = {{misc, 16}, {misc + 8, 8}, {guard, 4}};
+  // (and the caller's extra item, read at the same synchronisation)
+  const RnFetch it[4] = {{misc, 16}, {misc + 8, 8}, {guard, 4}, extra ? *extra : RnFetch{nullptr, 0}};
   const unsigned char *hb = nullptr;
-  size_t off[3];
-  st = rn_fetch(ctx, 3, it, &hb, off);
+  size_t off[4];
+  st = rn_fetch(ctx, extra ? 4 : 3, it, &hb, off);
   if (st != RN_OK) return fail(st);
+  if (extra) memcpy(extra_out, hb + off[3], extra->bytes);
   int64_t hp[5];
   int32_t gword = 0;
   memcpy(hp + 2, hb + off[0], 16);

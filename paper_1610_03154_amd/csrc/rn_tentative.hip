@@ -106,12 +106,13 @@ __global__ __launch_bounds__(RN_BLOCK) void k_tproj(int n, const int32_t *__rest
   }
 }
 
-extern "C" rn_status rn_tentative(rn_ctx *ctx, int32_t n, int32_t m, const int32_t *Np, const int32_t *Nj,
-                                  int64_t nnz_N, const uint8_t *is_root, const int32_t *agg, const int32_t *roots,
-                                  int32_t n_agg, const double *B, int32_t nB, double *T, double *Bc,
-                                  int32_t *rank_deficient) {
-  if (!ctx) return RN_EINVAL;
-  ctx->err.clear();
+// Everything of rn_tentative up to its synchronisation: validation into
+// guard (not reset here) and the kernels; *flags receives the device flags
+// (singular root block, rank-deficient rows).
+rn_status rn_tentative_launch(rn_ctx *ctx, int32_t n, int32_t m, const int32_t *Np, const int32_t *Nj,
+                              int64_t nnz_N, const uint8_t *is_root, const int32_t *agg, const int32_t *roots,
+                              int32_t n_agg, const double *B, int32_t nB, double *T, double *Bc, int32_t *guard,
+                              const int32_t **flags_out) {
   if ((m != 1 && m != 2) || n < 0 || n % m || n_agg < 0 || nnz_N < 0 || nB < m || nB > RN_NBMAX)
     return rn_fail(ctx, RN_EINVAL, "rn_tentative: bad sizes (n %d, m %d, n_agg %d, nB %d; need m <= nB <= %d)", n,
                    m, n_agg, nB, RN_NBMAX);
@@ -125,8 +126,6 @@ extern "C" rn_status rn_tentative(rn_ctx *ctx, int32_t n, int32_t m, const int32
   int32_t *flags = (int32_t *)rn_scratch(ctx, SLOT_TEN_FLAG, 4 * sizeof(int32_t), &st);
   if (!flags) return st;
   HIP_TRY(ctx, hipMemsetAsync(flags, 0, 4 * sizeof(int32_t), ctx->stream));
-  int32_t *guard = rn_guard_begin(ctx, &st);
-  if (!guard) return st;
   {
     RnChecks v{};
     v.csr[0] = {n, nc, nnz_N, Np, Nj, GUARD_N};
@@ -158,6 +157,28 @@ extern "C" rn_status rn_tentative(rn_ctx *ctx, int32_t n, int32_t m, const int32
       LAUNCH_CHECK(ctx);
     }
   }
+  *flags_out = flags;
+  return RN_OK;
+}
+
+// The tentative's flags as read back: a singular root block is an error.
+rn_status rn_tentative_flags(rn_ctx *ctx, const int32_t hf[2], int32_t *rank_deficient) {
+  if (hf[0]) return rn_fail(ctx, RN_ESINGULAR, "rn_tentative: singular root block of B");
+  if (rank_deficient) *rank_deficient = hf[1];
+  return RN_OK;
+}
+
+extern "C" rn_status rn_tentative(rn_ctx *ctx, int32_t n, int32_t m, const int32_t *Np, const int32_t *Nj,
+                                  int64_t nnz_N, const uint8_t *is_root, const int32_t *agg, const int32_t *roots,
+                                  int32_t n_agg, const double *B, int32_t nB, double *T, double *Bc,
+                                  int32_t *rank_deficient) {
+  if (!ctx) return RN_EINVAL;
+  ctx->err.clear();
+  rn_status st = RN_OK;
+  int32_t *guard = rn_guard_begin(ctx, &st);
+  if (!guard) return st;
+  const int32_t *flags = nullptr;
+  RN_TRY(rn_tentative_launch(ctx, n, m, Np, Nj, nnz_N, is_root, agg, roots, n_agg, B, nB, T, Bc, guard, &flags));
   // one synchronisation: guard and the two flags
   const RnFetch it[2] = {{guard, 4}, {flags, 2 * sizeof(int32_t)}};
   const unsigned char *hb = nullptr;
@@ -167,7 +188,5 @@ extern "C" rn_status rn_tentative(rn_ctx *ctx, int32_t n, int32_t m, const int32
   memcpy(&gword, hb + off[0], 4);
   memcpy(hf, hb + off[1], 8);
   RN_TRY(rn_guard_status(ctx, gword, "rn_tentative"));
-  if (hf[0]) return rn_fail(ctx, RN_ESINGULAR, "rn_tentative: singular root block of B");
-  if (rank_deficient) *rank_deficient = hf[1];
-  return RN_OK;
+  return rn_tentative_flags(ctx, hf, rank_deficient);
 }
