@@ -135,6 +135,14 @@ struct RnFetch {
 };
 rn_status rn_fetch(rn_ctx *ctx, int n, const RnFetch *items, const unsigned char **host, size_t *off);
 
+// rn_strength and phase 1 of rn_pattern with one synchronisation (rn_setup);
+// Sj has room for nnz(A) + n/block_m entries.  *done false: run the stage
+// calls instead (A not structurally symmetric, or a pattern row too long for
+// the padded levels).
+rn_status rn_strength_pattern(rn_ctx *ctx, const rn_matrix *A, double theta, int32_t *Sp, int32_t *Sj,
+                              const int32_t *agg, const int32_t *roots, int32_t n_agg, int32_t degree, int32_t *Np,
+                              uint8_t *is_root, int64_t *nnz_S, int64_t *nnz_N, bool *done);
+
 // The error of a guard word read back from the device (RN_OK when 0).
 rn_status rn_guard_status(rn_ctx *ctx, int32_t g, const char *what);
 

@@ -229,7 +229,9 @@ __global__ __launch_bounds__(RN_BLOCK) void k_partner_fill_g(int nn, const int32
                                                             const int32_t *__restrict__ Aj,
                                                             const uint8_t *__restrict__ symmask,
                                                             const int32_t *__restrict__ Sp,
-                                                            int32_t *__restrict__ Sj) {
+                                                            int32_t *__restrict__ Sj,
+                                                            const int32_t *__restrict__ guard) {
+  if (guard && *guard) return;  // (queued before the checks were read back)
   const int g = threadIdx.x / SG, l = threadIdx.x % SG;
   const int I = blockIdx.x * SRPB + g;
   const bool ok = I < nn;
@@ -266,6 +268,8 @@ __global__ __launch_bounds__(RN_BLOCK) void k_partner_fill_g(int nn, const int32
 
 static rn_status strength_transpose_path(rn_ctx *ctx, const rn_matrix *A, double theta, int32_t *S_rowptr,
                                          int32_t *S_colind, int64_t *nnz_S);
+static rn_status strength_sym_launch(rn_ctx *ctx, const rn_matrix *A, double theta, int32_t *S_rowptr,
+                                     int32_t *guard, int32_t **asym_out);
 
 extern "C" rn_status rn_strength(rn_ctx *ctx, const rn_matrix *A, double theta, int32_t *S_rowptr,
                                  int32_t *S_colind, int64_t *nnz_S) {
@@ -283,7 +287,8 @@ extern "C" rn_status rn_strength(rn_ctx *ctx, const rn_matrix *A, double theta, 
       return rn_fail(ctx, RN_EINVAL, "rn_strength: phase 2 without a matching phase 1");
     if (nn > 0) {
       hipLaunchKernelGGL(k_partner_fill_g, dim3(rn_div_up(nn, SRPB)), dim3(RN_BLOCK), 0, ctx->stream, nn, A->rowptr,
-                         A->colind, (const uint8_t *)ctx->slot[SLOT_STR_TMASK].ptr, S_rowptr, S_colind);
+                         A->colind, (const uint8_t *)ctx->slot[SLOT_STR_TMASK].ptr, S_rowptr, S_colind,
+                         (const int32_t *)nullptr);
       LAUNCH_CHECK(ctx);
     }
     *nnz_S = ctx->str_nnz;
@@ -292,6 +297,39 @@ extern "C" rn_status rn_strength(rn_ctx *ctx, const rn_matrix *A, double theta, 
     return RN_OK;
   }
   if (S_colind) return strength_transpose_path(ctx, A, theta, S_rowptr, S_colind, nnz_S);  // phase 2 copy
+  const int nn = A->n / m;
+  rn_status st = RN_OK;
+  int32_t *guard = rn_guard_begin(ctx, &st);
+  if (!guard) return st;
+  int32_t *asym = nullptr;
+  RN_TRY(strength_sym_launch(ctx, A, theta, S_rowptr, guard, &asym));
+  // one synchronisation: total, guard and the structural-asymmetry flag
+  const RnFetch it[3] = {{ctx->slot[SLOT_SCAN_TOTAL].ptr, sizeof(int64_t)}, {guard, 4}, {asym, 4}};
+  const unsigned char *hb = nullptr;
+  size_t off[3];
+  RN_TRY(rn_fetch(ctx, 3, it, &hb, off));
+  int64_t total = 0;
+  int32_t gword = 0, hasym = 0;
+  memcpy(&total, hb + off[0], 8);
+  memcpy(&gword, hb + off[1], 4);
+  memcpy(&hasym, hb + off[2], 4);
+  RN_TRY(rn_guard_status(ctx, gword, "rn_strength"));
+  if (hasym) return strength_transpose_path(ctx, A, theta, S_rowptr, nullptr, nnz_S);
+  // the columns are written by phase 2 straight into the caller's array
+  ctx->str_nnz = total;
+  ctx->str_nodes = nn;
+  ctx->str_direct = true;
+  *nnz_S = total;
+  return RN_OK;
+}
+
+// Phase 1 of the strength for a structurally symmetric A, queued on guard
+// (not reset here): diagonal, kept-entry mask (SLOT_STR_TMASK), row sizes
+// and their scan into S_rowptr; *asym_out receives the device flag set when
+// an entry has no partner (A not structurally symmetric).
+static rn_status strength_sym_launch(rn_ctx *ctx, const rn_matrix *A, double theta, int32_t *S_rowptr,
+                                     int32_t *guard, int32_t **asym_out) {
+  const int m = A->block_m;
   const int nn = A->n / m;
   const int64_t nz = A->nnz;
   rn_status st = RN_OK;
@@ -302,8 +340,6 @@ extern "C" rn_status rn_strength(rn_ctx *ctx, const rn_matrix *A, double theta, 
   int32_t *asym = (int32_t *)rn_scratch(ctx, SLOT_BLK0, 64, &st);
   if (!diag || !mask || !symmask || !cnt || !asym) return st;
   HIP_TRY(ctx, hipMemsetAsync(asym, 0, sizeof(int32_t), ctx->stream));
-  int32_t *guard = rn_guard_begin(ctx, &st);
-  if (!guard) return st;
   RN_TRY(rn_validate_csr(ctx, nn, nn, nz, A->rowptr, A->colind, guard, GUARD_A));
   const double th2 = theta * theta;
   const dim3 g(rn_div_up(nn > 0 ? nn : 1, RN_BLOCK)), b(RN_BLOCK);
@@ -323,23 +359,7 @@ extern "C" rn_status rn_strength(rn_ctx *ctx, const rn_matrix *A, double theta, 
     LAUNCH_CHECK(ctx);
   }
   RN_TRY(rn_scan_counts(ctx, cnt, S_rowptr, nn, nullptr));
-  // one synchronisation: total, guard and the structural-asymmetry flag
-  const RnFetch it[3] = {{ctx->slot[SLOT_SCAN_TOTAL].ptr, sizeof(int64_t)}, {guard, 4}, {asym, 4}};
-  const unsigned char *hb = nullptr;
-  size_t off[3];
-  RN_TRY(rn_fetch(ctx, 3, it, &hb, off));
-  int64_t total = 0;
-  int32_t gword = 0, hasym = 0;
-  memcpy(&total, hb + off[0], 8);
-  memcpy(&gword, hb + off[1], 4);
-  memcpy(&hasym, hb + off[2], 4);
-  RN_TRY(rn_guard_status(ctx, gword, "rn_strength"));
-  if (hasym) return strength_transpose_path(ctx, A, theta, S_rowptr, nullptr, nnz_S);
-  // the columns are written by phase 2 straight into the caller's array
-  ctx->str_nnz = total;
-  ctx->str_nodes = nn;
-  ctx->str_direct = true;
-  *nnz_S = total;
+  *asym_out = asym;
   return RN_OK;
 }
 
@@ -730,14 +750,14 @@ static bool pattern_pad_on() {
 }
 
 // Expansion with padded levels (no host round trip between levels), then the
-// DOF row sizes and their scan.  *ok is false when a padded row outgrew PCAP
-// (nothing is published then).
-static rn_status pattern_padded(rn_ctx *ctx, int nn, int n, int m, const int32_t *Sp, const int32_t *Sj,
-                                const int32_t *agg, const int32_t *roots, int n_agg, int degree, int32_t *Np,
-                                uint8_t *is_root, int32_t *cnt, int32_t *ovf, int32_t *guard, int64_t *total,
-                                bool *ok) {
+// DOF row sizes and their scan into Np, queued on guard; *pflag_out
+// receives the device flag raised when a padded row outgrew PCAP, *xout the
+// final level.
+static rn_status pattern_padded_launch(rn_ctx *ctx, int nn, int n, int m, const int32_t *Sp, const int32_t *Sj,
+                                       const int32_t *agg, const int32_t *roots, int n_agg, int degree, int32_t *Np,
+                                       uint8_t *is_root, int32_t *cnt, int32_t *ovf, int32_t *guard,
+                                       int32_t **pflag_out, XRows *xout) {
   rn_status st = RN_OK;
-  *ok = false;
   int32_t *pflag = (int32_t *)rn_scratch(ctx, SLOT_PAT_FLAG, 64, &st);
   if (!pflag) return st;
   HIP_TRY(ctx, hipMemsetAsync(pflag, 0, sizeof(int32_t), ctx->stream));
@@ -766,6 +786,22 @@ static rn_status pattern_padded(rn_ctx *ctx, int nn, int n, int m, const int32_t
     LAUNCH_CHECK(ctx);
   }
   RN_TRY(rn_scan_counts(ctx, cnt, Np, n, nullptr));
+  *pflag_out = pflag;
+  *xout = X;
+  return RN_OK;
+}
+
+// The same with its synchronisation: *ok is false when a padded row outgrew
+// PCAP (nothing is published then).
+static rn_status pattern_padded(rn_ctx *ctx, int nn, int n, int m, const int32_t *Sp, const int32_t *Sj,
+                                const int32_t *agg, const int32_t *roots, int n_agg, int degree, int32_t *Np,
+                                uint8_t *is_root, int32_t *cnt, int32_t *ovf, int32_t *guard, int64_t *total,
+                                bool *ok) {
+  *ok = false;
+  int32_t *pflag = nullptr;
+  XRows X{};
+  RN_TRY(pattern_padded_launch(ctx, nn, n, m, Sp, Sj, agg, roots, n_agg, degree, Np, is_root, cnt, ovf, guard,
+                               &pflag, &X));
   // one synchronisation: total, guard, padded overflow
   const RnFetch it[3] = {{ctx->slot[SLOT_SCAN_TOTAL].ptr, sizeof(int64_t)}, {guard, 4}, {pflag, 4}};
   const unsigned char *hb = nullptr;
@@ -902,5 +938,74 @@ extern "C" rn_status rn_pattern(rn_ctx *ctx, int32_t nn, const int32_t *Sp, cons
   ctx->pat_m = m;
   ctx->pat_x = X;
   *nnz_N = total;
+  return RN_OK;
+}
+
+// Strength and phase 1 of the pattern with one synchronisation (for
+// rn_setup): the strength assumes a structurally symmetric A and fills S
+// into Sj (room for nnz(A) + n/block_m entries) before its checks are read
+// back, then the pattern expands with padded levels.  *done is false when A
+// turned out not to be structurally symmetric or a padded row outgrew its
+// room: the caller then runs rn_strength and rn_pattern.  With *done true,
+// S is complete, Np / is_root hold the pattern's phase 1 and rn_pattern's
+// phase 2 fills N's columns.
+rn_status rn_strength_pattern(rn_ctx *ctx, const rn_matrix *A, double theta, int32_t *Sp, int32_t *Sj,
+                              const int32_t *agg, const int32_t *roots, int32_t n_agg, int32_t degree, int32_t *Np,
+                              uint8_t *is_root, int64_t *nnz_S, int64_t *nnz_N, bool *done) {
+  *done = false;
+  const int m = A->block_m;
+  if ((m != 1 && m != 2) || A->n < 0 || A->n % m || A->nnz < 0 || !A->rowptr || (A->nnz && (!A->colind || !A->vals)))
+    return rn_fail(ctx, RN_EINVAL, "rn_strength: bad matrix descriptor");
+  if (!(theta >= 0.0)) return rn_fail(ctx, RN_EINVAL, "rn_strength: theta must be >= 0");
+  if (A->nnz >= ((int64_t)1 << 31)) return rn_fail(ctx, RN_ELIMIT, "rn_strength: nnz >= 2^31");
+  const int nn = A->n / m, n = A->n;
+  if (n_agg < 0 || degree < 0) return rn_fail(ctx, RN_EINVAL, "rn_pattern: bad size");
+  if ((int64_t)nn * PCAP >= ((int64_t)1 << 31) || !pattern_pad_on()) return RN_OK;
+  rn_status st = RN_OK;
+  int32_t *cnt = (int32_t *)rn_scratch(ctx, SLOT_PAT_CNT, (size_t)(n + 1) * sizeof(int32_t), &st);
+  int32_t *ovf = (int32_t *)rn_scratch(ctx, SLOT_PAT_OVF, (size_t)(nn + 2) * sizeof(int32_t), &st);
+  if (!cnt || !ovf) return st;
+  int32_t *guard = rn_guard_begin(ctx, &st);
+  if (!guard) return st;
+  int32_t *asym = nullptr;
+  RN_TRY(strength_sym_launch(ctx, A, theta, Sp, guard, &asym));
+  if (nn > 0) {
+    hipLaunchKernelGGL(k_partner_fill_g, dim3(rn_div_up(nn, SRPB)), dim3(RN_BLOCK), 0, ctx->stream, nn, A->rowptr,
+                       A->colind, (const uint8_t *)ctx->slot[SLOT_STR_TMASK].ptr, Sp, Sj, guard);
+    LAUNCH_CHECK(ctx);
+  }
+  {
+    RnChecks v{};
+    v.range[0] = {nn, agg, 0, n_agg, GUARD_AGG};
+    v.range[1] = {n_agg, roots, 0, nn, GUARD_ROOTS};
+    v.nrange = 2;
+    RN_TRY(rn_validate(ctx, v, guard));
+  }
+  int32_t *pflag = nullptr;
+  XRows X{};
+  RN_TRY(pattern_padded_launch(ctx, nn, n, m, Sp, Sj, agg, roots, n_agg, degree, Np, is_root, cnt, ovf, guard,
+                               &pflag, &X));
+  // one synchronisation: nnz(S), guard, asymmetry, nnz(N), padded overflow
+  const RnFetch it[5] = {{Sp + nn, 4}, {guard, 4}, {asym, 4}, {ctx->slot[SLOT_SCAN_TOTAL].ptr, 8}, {pflag, 4}};
+  const unsigned char *hb = nullptr;
+  size_t off[5];
+  RN_TRY(rn_fetch(ctx, 5, it, &hb, off));
+  int32_t ns = 0, gword = 0, hasym = 0, pf = 0;
+  int64_t total = 0;
+  memcpy(&ns, hb + off[0], 4);
+  memcpy(&gword, hb + off[1], 4);
+  memcpy(&hasym, hb + off[2], 4);
+  memcpy(&total, hb + off[3], 8);
+  memcpy(&pf, hb + off[4], 4);
+  RN_TRY(rn_guard_status(ctx, gword, "rn_setup (strength, pattern)"));
+  if (hasym || pf) return RN_OK;
+  if (total >= ((int64_t)1 << 31)) return rn_fail(ctx, RN_ELIMIT, "rn_pattern: pattern nnz reaches 2^31");
+  ctx->pat_nnz = total;
+  ctx->pat_n = n;
+  ctx->pat_m = m;
+  ctx->pat_x = X;
+  *nnz_S = ns;
+  *nnz_N = total;
+  *done = true;
   return RN_OK;
 }

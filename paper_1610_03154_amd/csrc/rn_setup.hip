@@ -2,6 +2,7 @@
 // stage entry points run back to back inside the library, their outputs in
 // device memory owned by the returned handle (drawn from the context's
 // allocation cache, so repeated set-ups allocate nothing new).
+#include <cstdlib>
 #include <cstring>
 #include <new>
 
@@ -13,7 +14,7 @@ struct rn_setup_out {
   rn_plan *plan = nullptr, *plan_T = nullptr;
   int32_t *AT_rowptr = nullptr, *AT_colind = nullptr;
   double *AT_vals = nullptr;
-  void *bufs[16] = {};
+  void *bufs[24] = {};
   int nbuf = 0;
 };
 
@@ -63,24 +64,31 @@ extern "C" rn_status rn_setup(rn_ctx *ctx, const rn_matrix *A, const int32_t *ag
     return e;
   };
   auto nomem = [&]() { return fail(rn_fail(ctx, RN_ENOMEM, "rn_setup: device allocation")); };
-  // a1/a2: strength (two phases: the size of S, then its columns)
+  // a1-a4: strength and pattern.  First with one synchronisation for both
+  // (S filled into room for nnz(A) + n/m entries on the assumption of a
+  // structurally symmetric A); otherwise the two-phase stage calls.
   int32_t *Sp = (int32_t *)setup_alloc(s, (size_t)(nn + 1) * 4);
-  if (!Sp) return nomem();
-  int64_t nnzS = 0;
-  if ((st = rn_strength(ctx, A, theta, Sp, nullptr, &nnzS)) != RN_OK) return fail(st);
-  int32_t *Sj = (int32_t *)setup_alloc(s, (size_t)nnzS * 4);
-  if (!Sj) return nomem();
-  if ((st = rn_strength(ctx, A, theta, Sp, Sj, &nnzS)) != RN_OK) return fail(st);
+  int32_t *Sj = (int32_t *)setup_alloc(s, (size_t)(A->nnz + nn + 1) * 4);
+  int32_t *Np = (int32_t *)setup_alloc(s, (size_t)(n + 1) * 4);
+  uint8_t *is_root = (uint8_t *)setup_alloc(s, (size_t)n + 1);
+  if (!Sp || !Sj || !Np || !is_root) return nomem();
+  int64_t nnzS = 0, nnzN = 0;
+  bool done = false;
+  const char *fe = getenv("RNAMG_SETUP_FUSE");  // 0: the stage calls only
+  if (!(fe && fe[0] == '0') &&
+      (st = rn_strength_pattern(ctx, A, theta, Sp, Sj, agg, roots, n_agg, degree, Np, is_root, &nnzS, &nnzN,
+                                &done)) != RN_OK)
+    return fail(st);
+  if (!done) {
+    if ((st = rn_strength(ctx, A, theta, Sp, nullptr, &nnzS)) != RN_OK) return fail(st);
+    if (nnzS > A->nnz + nn && !(Sj = (int32_t *)setup_alloc(s, (size_t)nnzS * 4))) return nomem();
+    if ((st = rn_strength(ctx, A, theta, Sp, Sj, &nnzS)) != RN_OK) return fail(st);
+    if ((st = rn_pattern(ctx, nn, Sp, Sj, agg, roots, n_agg, degree, m, Np, nullptr, is_root, &nnzN)) != RN_OK)
+      return fail(st);
+  }
   v.S_rowptr = Sp;
   v.S_colind = Sj;
   v.nnz_S = nnzS;
-  // a3/a4: pattern
-  int32_t *Np = (int32_t *)setup_alloc(s, (size_t)(n + 1) * 4);
-  uint8_t *is_root = (uint8_t *)setup_alloc(s, (size_t)n + 1);
-  if (!Np || !is_root) return nomem();
-  int64_t nnzN = 0;
-  if ((st = rn_pattern(ctx, nn, Sp, Sj, agg, roots, n_agg, degree, m, Np, nullptr, is_root, &nnzN)) != RN_OK)
-    return fail(st);
   int32_t *Nj = (int32_t *)setup_alloc(s, (size_t)nnzN * 4);
   if (!Nj) return nomem();
   if ((st = rn_pattern(ctx, nn, Sp, Sj, agg, roots, n_agg, degree, m, Np, Nj, is_root, &nnzN)) != RN_OK)

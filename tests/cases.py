@@ -36,6 +36,11 @@ CASES = {
     # product block gets an X window (the persistent product reads X from
     # global memory)
     "ring20k": (lambda: (W.ring_graph(20000), W.ones(20000), None, None), 0.0, 1, 4, "cg", 1),
+    # structurally non-symmetric stencil (entries at (+1,+1) and (0,-1) with no mirror): the
+    # strength symmetrises through an explicit transpose
+    "asym20": (lambda: (W.stencil_grid(20, 20, {(0, 0): 4.0, (-1, 0): -1.0, (1, 0): -0.5, (0, -1): -1.0,
+                                                (1, 1): -0.6}), W.ones(400), W.ones(400), None),
+               0.25, 2, 4, "gmres", 1),
 }
 
 

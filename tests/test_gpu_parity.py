@@ -71,7 +71,7 @@ def run_path(R, ctx, c, precision=None):
 
 
 STRENGTH_CASES = ["laplace1d_8", "poisson32", "poisson37", "aniso40", "aniso512", "upwind64", "elastic7",
-                  "elastic512", "lap27_10"]
+                  "elastic512", "lap27_10", "asym20"]
 
 
 @pytest.mark.parametrize("name", STRENGTH_CASES)

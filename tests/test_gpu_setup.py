@@ -17,7 +17,7 @@ MIXED_TOL = 1e-5
 
 
 @pytest.mark.parametrize("name,precision", [("aniso40", "fp64"), ("aniso40", "mixed"), ("upwind64", "fp64"),
-                                            ("elastic7", "fp64"), ("twocand13", "fp64")])
+                                            ("elastic7", "fp64"), ("twocand13", "fp64"), ("asym20", "fp64")])
 def test_setup_matches_stages_and_oracle(R, ctx, name, precision):
     c = CS.case(name)
     prec = R.RN_FP64 if precision == "fp64" else R.RN_FP32_MIXED
@@ -61,3 +61,29 @@ def test_setup_reports_bad_input(R, ctx):
         ctx.setup_native(A, dev(c["B"]), dev(bad), dev(c["roots"]), c["theta"], 2, 2)
     from paper_1610_03154_amd import _lib
     assert e.value.status == _lib.RN_EINVAL
+
+
+def test_setup_wide_pattern_rows(R, ctx):
+    """A banded operator (|i - j| <= 35) with node-pair aggregates: the
+    distance-2 pattern rows hold 71 aggregates, more than a padded level
+    row takes, so the set-up redoes the pattern with exact CSR levels."""
+    import oracle as O
+    import workloads as W
+    n, hb = 300, 35
+    offs = [(d, 0) for d in range(-hb, hb + 1)]
+    A = W._csr_from_offsets(n, 1, offs, [2.0 * hb + 10.0 if d == 0 else -1.0 for d, _ in offs])
+    agg = (np.arange(n) // 2).astype(np.int32)
+    roots = np.arange(0, n, 2, dtype=np.int32)
+    B = np.ones((n, 1))
+    ref = O.setup(A, B, 1, 0.0, 2, agg=agg, roots=roots)
+    assert int(np.diff(ref["Npn"]).max()) > 64
+    P_ref, _ = O.emin_cg(A.rowptr, A.colind, A.vals, ref["Np"], ref["Nj"], ref["is_root"], ref["nc"], ref["Bc"], 1,
+                         ref["T"], 2)
+    dA = R.DeviceCSR.from_host(A.rowptr, A.colind, A.vals)
+    s = ctx.setup_native(dA, dev(B), dev(agg), dev(roots), 0.0, 2, 2)
+    try:
+        assert np.array_equal(host(s.tensor("N_rowptr")), ref["Np"])
+        assert np.array_equal(host(s.tensor("N_colind")), ref["Nj"])
+        assert CS.rel_max(host(s.tensor("P")), P_ref) <= FP64_TOL
+    finally:
+        s.close()
