@@ -442,7 +442,8 @@ rn_status rn_gather_values(rn_ctx *ctx, const double *src, const int32_t *idx, i
 int32_t *rn_guard_begin(rn_ctx *ctx, rn_status *st) {
   int32_t *g = (int32_t *)rn_scratch(ctx, SLOT_GUARD, 64, st);
   if (!g) return nullptr;
-  if (hipMemsetAsync(g, 0, sizeof(int32_t), ctx->stream) != hipSuccess) {
+  // the whole slot: the guard word and the stage flags beside it
+  if (hipMemsetAsync(g, 0, 64, ctx->stream) != hipSuccess) {
     *st = rn_fail(ctx, RN_EHIP, "guard reset failed");
     return nullptr;
   }

@@ -133,16 +133,17 @@ SpgParams rn_spg_params(const rn_plan *pl);
 // rn_plan_create on the caller's guard word (not reset; NULL: a fresh one),
 // with one extra device item (nullable) read back at the plan's
 // synchronisation into extra_out (host, extra->bytes).
+// validate = false: A and N were checked (or made) by the caller.
 rn_status rn_plan_create_ex(rn_ctx *ctx, const rn_matrix *A, int32_t n_cols, const int32_t *Np, const int32_t *Nj,
                             int64_t nnz_N, const uint8_t *is_root, const double *Bc, int32_t nB, rn_plan **out,
-                            int32_t *guard_in, const RnFetch *extra, unsigned char *extra_out);
+                            int32_t *guard_in, const RnFetch *extra, unsigned char *extra_out, bool validate);
 // rn_tentative without its synchronisation: kernels queued on guard, the
 // device flags (singular root block, rank-deficient rows) in *flags; then
 // rn_tentative_flags on the flags as read back.
 rn_status rn_tentative_launch(rn_ctx *ctx, int32_t n, int32_t m, const int32_t *Np, const int32_t *Nj,
                               int64_t nnz_N, const uint8_t *is_root, const int32_t *agg, const int32_t *roots,
                               int32_t n_agg, const double *B, int32_t nB, double *T, double *Bc, int32_t *guard,
-                              const int32_t **flags);
+                              const int32_t **flags, bool validate);
 rn_status rn_tentative_flags(rn_ctx *ctx, const int32_t hf[2], int32_t *rank_deficient);
 
 // tape hooks called by rn_energy_min (CG, FP64) -- implemented with the adjoint

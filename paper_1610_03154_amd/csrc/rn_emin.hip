@@ -363,6 +363,14 @@ __global__ __launch_bounds__(RN_BLOCK) void k_gm_combine_k(int64_t nnz, int64_t 
   }
 }
 
+__global__ __launch_bounds__(RN_BLOCK) void k_zero3(int32_t *__restrict__ a, int64_t na, double *__restrict__ b,
+                                                   int64_t nb, double *__restrict__ c, int64_t nc) {
+  const int64_t s = (int64_t)gridDim.x * RN_BLOCK;
+  for (int64_t q = (int64_t)blockIdx.x * RN_BLOCK + threadIdx.x; q < na; q += s) a[q] = 0;
+  for (int64_t q = (int64_t)blockIdx.x * RN_BLOCK + threadIdx.x; q < nb; q += s) b[q] = 0.0;
+  for (int64_t q = (int64_t)blockIdx.x * RN_BLOCK + threadIdx.x; q < nc; q += s) c[q] = 0.0;
+}
+
 __global__ __launch_bounds__(RN_BLOCK) void k_to_f32(const double *__restrict__ src, int64_t n,
                                                     float *__restrict__ dst) {
   for (int64_t q = (int64_t)blockIdx.x * RN_BLOCK + threadIdx.x; q < n; q += (int64_t)gridDim.x * RN_BLOCK)
@@ -471,9 +479,10 @@ extern "C" rn_status rn_energy_min(rn_ctx *ctx, rn_plan *pl, const double *A_val
   double *part_spg = p.part;
   double *part_ew = p.part + (int64_t)batch * RN_MAXDOT * pl->nblk;
   const int64_t pstride_spg = (int64_t)RN_MAXDOT * pl->nblk, pstride_ew = (int64_t)RN_MAXDOT * gew;
-  HIP_TRY(ctx, hipMemsetAsync(p.st, 0, (size_t)batch * ST_STRIDE * 4, ctx->stream));
-  HIP_TRY(ctx, hipMemsetAsync(p.scal, 0, (size_t)batch * scal_stride * 8, ctx->stream));
-  if (hist) HIP_TRY(ctx, hipMemsetAsync(hist, 0, (size_t)batch * hist_stride * 8, ctx->stream));
+  // status, scalars and history start at zero (one launch for the three)
+  hipLaunchKernelGGL(k_zero3, dim3(64), dim3(RN_BLOCK), 0, ctx->stream, p.st, (int64_t)batch * ST_STRIDE, p.scal,
+                     (int64_t)batch * scal_stride, hist, hist ? (int64_t)batch * hist_stride : 0);
+  LAUNCH_CHECK(ctx);
   const float *A32 = nullptr, *T32 = nullptr;
   if (mixed) {
     const int64_t na = (int64_t)batch * p.strideA;

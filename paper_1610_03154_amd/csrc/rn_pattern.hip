@@ -337,9 +337,8 @@ static rn_status strength_sym_launch(rn_ctx *ctx, const rn_matrix *A, double the
   uint8_t *mask = (uint8_t *)rn_scratch(ctx, SLOT_STR_MASK, (size_t)(nz + 1), &st);
   uint8_t *symmask = (uint8_t *)rn_scratch(ctx, SLOT_STR_TMASK, (size_t)(nz + 1), &st);
   int32_t *cnt = (int32_t *)rn_scratch(ctx, SLOT_STR_CNT, (size_t)(nn + 1) * sizeof(int32_t), &st);
-  int32_t *asym = (int32_t *)rn_scratch(ctx, SLOT_BLK0, 64, &st);
-  if (!diag || !mask || !symmask || !cnt || !asym) return st;
-  HIP_TRY(ctx, hipMemsetAsync(asym, 0, sizeof(int32_t), ctx->stream));
+  int32_t *asym = guard + GS_ASYM;
+  if (!diag || !mask || !symmask || !cnt) return st;
   RN_TRY(rn_validate_csr(ctx, nn, nn, nz, A->rowptr, A->colind, guard, GUARD_A));
   const double th2 = theta * theta;
   const dim3 g(rn_div_up(nn > 0 ? nn : 1, RN_BLOCK)), b(RN_BLOCK);
@@ -758,9 +757,7 @@ static rn_status pattern_padded_launch(rn_ctx *ctx, int nn, int n, int m, const 
                                        uint8_t *is_root, int32_t *cnt, int32_t *ovf, int32_t *guard,
                                        int32_t **pflag_out, XRows *xout) {
   rn_status st = RN_OK;
-  int32_t *pflag = (int32_t *)rn_scratch(ctx, SLOT_PAT_FLAG, 64, &st);
-  if (!pflag) return st;
-  HIP_TRY(ctx, hipMemsetAsync(pflag, 0, sizeof(int32_t), ctx->stream));
+  int32_t *pflag = guard + GS_PFLAG;
   XRows X{nullptr, agg, nullptr, 1};  // X_0 = C
   int cur = 0;
   const unsigned g = rn_div_up(nn, ERPB) ? rn_div_up(nn, ERPB) : 1;

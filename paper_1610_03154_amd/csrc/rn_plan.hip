@@ -550,12 +550,12 @@ extern "C" rn_status rn_plan_create(rn_ctx *ctx, const rn_matrix *A, int32_t n_c
                                     int32_t nB, rn_plan **out) {
   if (!ctx) return RN_EINVAL;
   ctx->err.clear();
-  return rn_plan_create_ex(ctx, A, n_cols, Np, Nj, nnz_N, is_root, Bc, nB, out, nullptr, nullptr, nullptr);
+  return rn_plan_create_ex(ctx, A, n_cols, Np, Nj, nnz_N, is_root, Bc, nB, out, nullptr, nullptr, nullptr, true);
 }
 
 rn_status rn_plan_create_ex(rn_ctx *ctx, const rn_matrix *A, int32_t n_cols, const int32_t *Np, const int32_t *Nj,
                             int64_t nnz_N, const uint8_t *is_root, const double *Bc, int32_t nB, rn_plan **out,
-                            int32_t *guard_in, const RnFetch *extra, unsigned char *extra_out) {
+                            int32_t *guard_in, const RnFetch *extra, unsigned char *extra_out, bool validate) {
   if (!A || !out) return rn_fail(ctx, RN_EINVAL, "rn_plan_create: null argument");
   *out = nullptr;
   const int m = A->block_m;
@@ -592,7 +592,7 @@ rn_status rn_plan_create_ex(rn_ctx *ctx, const rn_matrix *A, int32_t n_cols, con
   const int NP = nB * (nB + 1) / 2;
   int32_t *guard = guard_in ? guard_in : rn_guard_begin(ctx, &st);
   if (!guard) return fail(st);
-  {
+  if (validate) {
     RnChecks v{};
     v.csr[0] = {nr, nr, A->nnz, A->rowptr, A->colind, GUARD_A};
     v.csr[1] = {n, n_cols, nnz_N, Np, Nj, GUARD_N};
@@ -600,10 +600,12 @@ rn_status rn_plan_create_ex(rn_ctx *ctx, const rn_matrix *A, int32_t n_cols, con
     if (rn_validate(ctx, v, guard) != RN_OK) return fail(RN_EHIP);
   }
   // scratch: [0] maxlen, [1] rank_def, [2] longest A row of a non-root row,
-  // [8..9] node-entry total (int64)
+  // [8..9] node-entry total (int64); written by the finishing kernels below
+  // (zeroed here only when there are none)
   int32_t *misc = (int32_t *)rn_scratch(ctx, SLOT_MISC, 64, &st);
   if (!misc) return fail(st);
-  if (hipMemsetAsync(misc, 0, 64, ctx->stream) != hipSuccess) return fail(rn_fail(ctx, RN_EHIP, "memset"));
+  if (nr == 0 && hipMemsetAsync(misc, 0, 64, ctx->stream) != hipSuccess)
+    return fail(rn_fail(ctx, RN_EHIP, "memset"));
   if (!plan_alloc(pl, &pl->gp, (size_t)(n + 1) * NP * sizeof(double)) || !plan_alloc(pl, &pl->d_terms, 16) ||
       !plan_alloc(pl, &pl->xoff, (size_t)(A->nnz + 1) * m * sizeof(int32_t)))
     return fail(rn_fail(ctx, RN_ENOMEM, "rn_plan_create: device allocation"));
@@ -611,7 +613,6 @@ rn_status rn_plan_create_ex(rn_ctx *ctx, const rn_matrix *A, int32_t n_cols, con
     return fail(rn_fail(ctx, RN_ENOMEM, "rn_plan_create: device allocation"));
   pl->fixed_bytes = (size_t)(nr + 1) * 4 * (m == 2 ? 1 : 0) + (size_t)(n + 1) * NP * 8 +
                     (size_t)(A->nnz + 1) * m * 4;
-  if (hipMemsetAsync(pl->d_terms, 0, 16, ctx->stream) != hipSuccess) return fail(rn_fail(ctx, RN_EHIP, "memset"));
   // per-block partial results of the counting kernels
   const int nbn = (int)rn_div_up(n > 0 ? n : 1, RN_BLOCK);
   int32_t *blk_max = (int32_t *)rn_scratch(ctx, SLOT_BLK0, (size_t)(nbn + 1) * sizeof(int32_t), &st);
@@ -759,6 +760,8 @@ rn_status rn_plan_create_ex(rn_ctx *ctx, const rn_matrix *A, int32_t n_cols, con
     hipLaunchKernelGGL((k_finish_slots<false, unsigned long long>), dim3(1), dim3(RN_BLOCK), 0, ctx->stream, blk_hit,
                        pl->nblk, pl->d_terms);
     if (hipGetLastError() != hipSuccess) return fail(rn_fail(ctx, RN_EHIP, "launch"));
+  } else if (hipMemsetAsync(pl->d_terms, 0, 16, ctx->stream) != hipSuccess) {  // no blocks: no terms
+    return fail(rn_fail(ctx, RN_EHIP, "memset"));
   }
   try {
     ctx->plans.push_back(pl);

@@ -103,12 +103,13 @@ extern "C" rn_status rn_setup(rn_ctx *ctx, const rn_matrix *A, const int32_t *ag
   double *P = (double *)setup_alloc(s, (size_t)nnzN * 8);
   if (!T || !Bc || !P) return nomem();
   // the tentative's checks are read at the plan's synchronisation (one
-  // guard word for both stages)
+  // guard word for both stages); A, agg and roots were checked by the first
+  // stage and N was made here, so neither stage validates again
   int32_t *guard = rn_guard_begin(ctx, &st);
   if (!guard) return fail(st);
   const int32_t *tflags = nullptr;
   if ((st = rn_tentative_launch(ctx, n, m, Np, Nj, nnzN, is_root, agg, roots, n_agg, B, nB, T, Bc, guard,
-                                &tflags)) != RN_OK)
+                                &tflags, false)) != RN_OK)
     return fail(st);
   v.T = T;
   v.Bc = Bc;
@@ -116,7 +117,7 @@ extern "C" rn_status rn_setup(rn_ctx *ctx, const rn_matrix *A, const int32_t *ag
   int32_t hf[2] = {0, 0};
   const RnFetch fl = {tflags, sizeof hf};
   if ((st = rn_plan_create_ex(ctx, A, nc, Np, Nj, nnzN, is_root, Bc, nB, &s->plan, guard, &fl,
-                              (unsigned char *)hf)) != RN_OK)
+                              (unsigned char *)hf, false)) != RN_OK)
     return fail(st);
   if ((st = rn_tentative_flags(ctx, hf, &v.rank_deficient)) != RN_OK) return fail(st);
   if ((st = rn_energy_min(ctx, s->plan, A->vals, 1, T, method, iters, precision, P, nullptr, stats, nullptr)) !=
@@ -138,11 +139,11 @@ extern "C" rn_status rn_setup(rn_ctx *ctx, const rn_matrix *A, const int32_t *ag
     int32_t *g2 = rn_guard_begin(ctx, &st);
     if (!g2) return fail(st);
     if ((st = rn_tentative_launch(ctx, n, m, Np, Nj, nnzN, is_root, agg, roots, n_agg, Bhat, nB, That, Bch, g2,
-                                  &tflags)) != RN_OK)
+                                  &tflags, false)) != RN_OK)
       return fail(st);
     const RnFetch fl2 = {tflags, sizeof hf};
     if ((st = rn_plan_create_ex(ctx, &AT, nc, Np, Nj, nnzN, is_root, Bch, nB, &s->plan_T, g2, &fl2,
-                                (unsigned char *)hf)) != RN_OK)
+                                (unsigned char *)hf, false)) != RN_OK)
       return fail(st);
     if ((st = rn_tentative_flags(ctx, hf, nullptr)) != RN_OK) return fail(st);
     if ((st = rn_energy_min(ctx, s->plan_T, s->AT_vals, 1, That, method, iters, precision, RT, nullptr, stats_RT,

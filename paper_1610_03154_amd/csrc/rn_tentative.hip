@@ -107,12 +107,14 @@ __global__ __launch_bounds__(RN_BLOCK) void k_tproj(int n, const int32_t *__rest
 }
 
 // Everything of rn_tentative up to its synchronisation: validation into
-// guard (not reset here) and the kernels; *flags receives the device flags
-// (singular root block, rank-deficient rows).
+// guard (not reset here; skipped when the caller made N, agg and roots
+// itself and checked them) and the kernels; *flags receives the device
+// flags (singular root block, rank-deficient rows), which sit in the guard
+// slot.
 rn_status rn_tentative_launch(rn_ctx *ctx, int32_t n, int32_t m, const int32_t *Np, const int32_t *Nj,
                               int64_t nnz_N, const uint8_t *is_root, const int32_t *agg, const int32_t *roots,
                               int32_t n_agg, const double *B, int32_t nB, double *T, double *Bc, int32_t *guard,
-                              const int32_t **flags_out) {
+                              const int32_t **flags_out, bool validate) {
   if ((m != 1 && m != 2) || n < 0 || n % m || n_agg < 0 || nnz_N < 0 || nB < m || nB > RN_NBMAX)
     return rn_fail(ctx, RN_EINVAL, "rn_tentative: bad sizes (n %d, m %d, n_agg %d, nB %d; need m <= nB <= %d)", n,
                    m, n_agg, nB, RN_NBMAX);
@@ -123,10 +125,8 @@ rn_status rn_tentative_launch(rn_ctx *ctx, int32_t n, int32_t m, const int32_t *
   const int nn = n / m, nc = m * n_agg;
   double *binv = (double *)rn_scratch(ctx, SLOT_TEN_BINV, (size_t)(n_agg + 1) * m * m * sizeof(double), &st);
   if (!binv) return st;
-  int32_t *flags = (int32_t *)rn_scratch(ctx, SLOT_TEN_FLAG, 4 * sizeof(int32_t), &st);
-  if (!flags) return st;
-  HIP_TRY(ctx, hipMemsetAsync(flags, 0, 4 * sizeof(int32_t), ctx->stream));
-  {
+  int32_t *flags = guard + GS_TFLAGS;  // zeroed with the guard
+  if (validate) {
     RnChecks v{};
     v.csr[0] = {n, nc, nnz_N, Np, Nj, GUARD_N};
     v.ncsr = 1;
@@ -178,7 +178,8 @@ extern "C" rn_status rn_tentative(rn_ctx *ctx, int32_t n, int32_t m, const int32
   int32_t *guard = rn_guard_begin(ctx, &st);
   if (!guard) return st;
   const int32_t *flags = nullptr;
-  RN_TRY(rn_tentative_launch(ctx, n, m, Np, Nj, nnz_N, is_root, agg, roots, n_agg, B, nB, T, Bc, guard, &flags));
+  RN_TRY(rn_tentative_launch(ctx, n, m, Np, Nj, nnz_N, is_root, agg, roots, n_agg, B, nB, T, Bc, guard, &flags,
+                             true));
   // one synchronisation: guard and the two flags
   const RnFetch it[2] = {{guard, 4}, {flags, 2 * sizeof(int32_t)}};
   const unsigned char *hb = nullptr;
