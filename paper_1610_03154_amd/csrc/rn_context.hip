@@ -257,6 +257,55 @@ __global__ __launch_bounds__(RN_BLOCK) void k_scan_apply(const int32_t *__restri
   if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = (int32_t)*total;
 }
 
+// Tile scan with the prefix of the preceding tiles summed by each block
+// itself (for up to SCAN_FUSED_TILES tiles: two launches instead of three);
+// the last block writes the total.
+#define SCAN_FUSED_TILES 4096
+__global__ __launch_bounds__(RN_BLOCK) void k_scan_apply_pre(const int32_t *__restrict__ cnt, int64_t n,
+                                                            const int64_t *__restrict__ bsum,
+                                                            int64_t *__restrict__ total,
+                                                            int32_t *__restrict__ out) {
+  __shared__ int64_t lds[RN_BLOCK];
+  __shared__ int64_t s_pre;
+  int64_t p = 0;
+  for (int64_t q = threadIdx.x; q < blockIdx.x; q += RN_BLOCK) p += bsum[q];
+  lds[threadIdx.x] = p;
+  __syncthreads();
+  for (int w = RN_BLOCK / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) lds[threadIdx.x] += lds[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) s_pre = lds[0];
+  __syncthreads();
+  const int64_t pre = s_pre;
+  const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
+  int32_t v[SCAN_ITEMS];
+  int64_t s = 0;
+#pragma unroll
+  for (int q = 0; q < SCAN_ITEMS; ++q) {
+    v[q] = base + q < n ? cnt[base + q] : 0;
+    s += v[q];
+  }
+  lds[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 1; off < RN_BLOCK; off <<= 1) {
+    int64_t t = threadIdx.x >= (unsigned)off ? lds[threadIdx.x - off] : 0;
+    __syncthreads();
+    lds[threadIdx.x] += t;
+    __syncthreads();
+  }
+  int64_t run = pre + lds[threadIdx.x] - s;
+#pragma unroll
+  for (int q = 0; q < SCAN_ITEMS; ++q) {
+    if (base + q < n) out[base + q] = (int32_t)run;
+    run += v[q];
+  }
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == RN_BLOCK - 1) {
+    *total = run;
+    out[n] = (int32_t)run;
+  }
+}
+
 rn_status rn_scan_counts(rn_ctx *ctx, const int32_t *counts, int32_t *out, int64_t n,
                          int64_t *total_host) {
   rn_status st = RN_OK;
@@ -267,10 +316,15 @@ rn_status rn_scan_counts(rn_ctx *ctx, const int32_t *counts, int32_t *out, int64
   if (!total) return st;
   hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)nb), dim3(RN_BLOCK), 0, ctx->stream, counts, n, bsum);
   LAUNCH_CHECK(ctx);
-  hipLaunchKernelGGL(k_scan_bsum, dim3(1), dim3(1024), 0, ctx->stream, bsum, nb, total);
-  LAUNCH_CHECK(ctx);
-  hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(RN_BLOCK), 0, ctx->stream, counts, n, bsum,
-                     total, out);
+  if (nb <= SCAN_FUSED_TILES) {
+    hipLaunchKernelGGL(k_scan_apply_pre, dim3((unsigned)nb), dim3(RN_BLOCK), 0, ctx->stream, counts, n, bsum,
+                       total, out);
+  } else {
+    hipLaunchKernelGGL(k_scan_bsum, dim3(1), dim3(1024), 0, ctx->stream, bsum, nb, total);
+    LAUNCH_CHECK(ctx);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(RN_BLOCK), 0, ctx->stream, counts, n, bsum,
+                       total, out);
+  }
   LAUNCH_CHECK(ctx);
   if (total_host) {
     RN_TRY(rn_read_i64(ctx, total, total_host));

@@ -58,10 +58,16 @@ static __device__ inline void block_to_slot(int v, int32_t *out) {
   }
 }
 
-// one block: out = max or sum of in[0..n)
+// one block: out = max or sum of in[0..n); with a second pair (in2, out2)
+// a second block does the same for it
 template <bool MAX, typename TO>
 __global__ __launch_bounds__(RN_BLOCK) void k_finish_slots(const int32_t *__restrict__ in, int n,
-                                                          TO *__restrict__ out) {
+                                                          TO *__restrict__ out, const int32_t *__restrict__ in2 = nullptr,
+                                                          TO *__restrict__ out2 = nullptr) {
+  if (blockIdx.x == 1) {
+    in = in2;
+    out = out2;
+  }
   __shared__ long long s[RN_BLOCK];
   long long v = 0;
   for (int q = threadIdx.x; q < n; q += RN_BLOCK) v = MAX ? (v > in[q] ? v : in[q]) : v + in[q];
@@ -164,26 +170,43 @@ __global__ __launch_bounds__(RN_BLOCK) void k_plan_bce(int64_t nnzN, int nB, con
 // ---- block partition: rows whose first entry lies in [b*chunk, (b+1)*chunk)
 // belong to block b; header = r0, r1, e0, e1, a0, a1 (A entries/blocks) and
 // (filled in by k_plan_codes) the longest A row of the block's non-root rows ----
-__global__ __launch_bounds__(RN_BLOCK) void k_plan_blocks(int nr, int m, const int32_t *__restrict__ rp,
-                                                         const int32_t *__restrict__ Ap,
-                                                         const uint8_t *__restrict__ is_root, int nblk, int chunk,
-                                                         int32_t *__restrict__ blk_row,
-                                                         int32_t *__restrict__ hdr) {
-  const int b = blockIdx.x * RN_BLOCK + threadIdx.x;
-  if (b > nblk) return;
-  const int r0 = rn_lower_bound(rp, nr, (int64_t)b * chunk);
-  blk_row[b] = b == nblk ? nr : r0;
-  if (b == nblk) return;
-  const int r1 = b + 1 == nblk ? nr : rn_lower_bound(rp, nr, (int64_t)(b + 1) * chunk);
-  int32_t *h = hdr + 8 * (int64_t)b;
-  h[0] = r0;
-  h[1] = r1;
-  h[2] = rp[r0];
-  h[3] = rp[r1];
-  h[4] = Ap[r0];
-  h[5] = Ap[r1];
-  h[6] = 0;  // longest A row of a non-root row: written by k_plan_codes
-  h[7] = 0;
+// Row-parallel: thread r is the first row of every block b with
+// rp[r-1] < b*chunk <= rp[r] (the lower bound of b*chunk) and so also the
+// end row of block b-1; thread nr closes the last block.
+__global__ __launch_bounds__(RN_BLOCK) void k_plan_blocks_rows(int nr, const int32_t *__restrict__ rp,
+                                                              const int32_t *__restrict__ Ap, int nblk, int chunk,
+                                                              int32_t *__restrict__ blk_row,
+                                                              int32_t *__restrict__ hdr) {
+  const int r = blockIdx.x * RN_BLOCK + threadIdx.x;
+  if (r > nr) return;
+  const int64_t hi = rp[r];
+  const int64_t lo = r > 0 ? (int64_t)rp[r - 1] : -1;
+  const int a = Ap[r];
+  if (r == nr) {
+    blk_row[nblk] = nr;
+    if (nblk > 0) {
+      int32_t *h = hdr + 8 * (int64_t)(nblk - 1);
+      h[1] = nr;
+      h[3] = (int32_t)hi;
+      h[5] = a;
+    }
+  }
+  // blocks b in (lo / chunk, hi / chunk] (b = 0 for r = 0), below nblk
+  const int64_t b0 = lo < 0 ? 0 : lo / chunk + 1;
+  for (int64_t b = b0; b * chunk <= hi && b < nblk; ++b) {
+    blk_row[b] = r;
+    int32_t *h = hdr + 8 * b;
+    h[0] = r;
+    h[2] = (int32_t)hi;
+    h[4] = a;
+    h[6] = 0;
+    h[7] = 0;
+    if (b > 0) {
+      h[-8 + 1] = r;
+      h[-8 + 3] = (int32_t)hi;
+      h[-8 + 5] = a;
+    }
+  }
 }
 
 // ---- first pattern entry of each stored entry's neighbour row -------------
@@ -638,9 +661,8 @@ rn_status rn_plan_create_ex(rn_ctx *ctx, const rn_matrix *A, int32_t n_cols, con
         return fail(rn_fail(ctx, RN_EHIP, "copy"));
     }
     if (hipGetLastError() != hipSuccess) return fail(rn_fail(ctx, RN_EHIP, "launch"));
-    hipLaunchKernelGGL((k_finish_slots<true, int32_t>), dim3(1), dim3(RN_BLOCK), 0, ctx->stream, blk_max, nbc, misc);
-    hipLaunchKernelGGL((k_finish_slots<true, int32_t>), dim3(1), dim3(RN_BLOCK), 0, ctx->stream, blk_na, nbc,
-                       misc + 2);
+    hipLaunchKernelGGL((k_finish_slots<true, int32_t>), dim3(2), dim3(RN_BLOCK), 0, ctx->stream, blk_max, nbc, misc,
+                       (const int32_t *)blk_na, misc + 2);
     const dim3 g(nbn), bl(RN_BLOCK);
     switch (nB) {
       case 1: hipLaunchKernelGGL(k_plan_gram<1>, g, bl, 0, ctx->stream, n, Np, Nj, is_root, Bc, pl->gp, blk_bad, guard); break;
@@ -718,8 +740,8 @@ rn_status rn_plan_create_ex(rn_ctx *ctx, const rn_matrix *A, int32_t n_cols, con
     }
   }
   const int32_t *rp = m == 1 ? Np : pl->nodeptr;
-  hipLaunchKernelGGL(k_plan_blocks, dim3(rn_div_up(pl->nblk + 1, RN_BLOCK)), dim3(RN_BLOCK), 0, ctx->stream, nr, m,
-                     rp, A->rowptr, is_root, pl->nblk, pl->chunk, pl->blk_row, pl->blk_hdr);
+  hipLaunchKernelGGL(k_plan_blocks_rows, dim3(rn_div_up(nr + 1, RN_BLOCK)), dim3(RN_BLOCK), 0, ctx->stream, nr, rp,
+                     A->rowptr, pl->nblk, pl->chunk, pl->blk_row, pl->blk_hdr);
   if (hipGetLastError() != hipSuccess) return fail(rn_fail(ctx, RN_EHIP, "launch"));
   if (A->nnz > 0) {
     unsigned g = rn_div_up(A->nnz, RN_BLOCK);
