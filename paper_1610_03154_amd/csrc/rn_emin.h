@@ -94,6 +94,7 @@ struct rn_plan {
                                 // an X window: the neighbour row's offset in it
   int32_t *xwin = nullptr;      // block_m = 1, per block: bs/8 unit starts
   double *bce = nullptr;        // block_m = 1, n_B <= 2: Bc row of each entry's column
+  bool unit_bc = false;         // block_m = 1 and every entry of Bc is 1
   double *gp = nullptr;         // packed Gram pseudo-inverse per DOF row
   int32_t rank_def = 0, maxlen = 0, chunk = 1, nblk = 0;
   int32_t bs = RN_BLOCK;        // lanes per product block (block_m = 1: 128 or 256)
@@ -109,6 +110,7 @@ struct SpgParams {
   int32_t n, nr, nblk, k, K, hist_stride, project, scal_stride, cstride, bs;
   int32_t accum;  // MODE_PRODUCT: Z += result instead of Z = result
   int32_t kact;   // >= 0: batch entries whose st[ST_ITERS] <= kact do nothing
+  int32_t unit_bc;  // every entry of Bc is 1: the projection's Bc rows are 1 (no per-entry loads)
   int64_t nnzN, strideA, strideX, strideZ;
   const int32_t *Ap, *Aj, *Np, *Nj, *nodeptr, *ncol, *blk_row, *blk_hdr, *xoff, *xl, *xwin;
   const uint8_t *codes, *is_root;

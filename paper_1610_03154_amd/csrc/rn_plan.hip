@@ -83,13 +83,19 @@ __global__ __launch_bounds__(RN_BLOCK) void k_finish_slots(const int32_t *__rest
 
 // ---- sizes: longest pattern row and longest A row of a non-root row
 // (block_m = 1: DOF rows, 2: node rows), as per-block maxima ---------------
+// (and *bcflag = 1 where an entry of Bc differs from 1: with Bc = 1 the
+// product needs no per-entry Bc rows)
 __global__ __launch_bounds__(RN_BLOCK) void k_plan_count_m1(int n, const int32_t *__restrict__ Ap,
                                                            const int32_t *__restrict__ Np,
                                                            const uint8_t *__restrict__ is_root,
                                                            int32_t *__restrict__ maxlen, int32_t *__restrict__ maxna,
-                                                           int32_t *__restrict__ guard) {
+                                                           int32_t *__restrict__ guard, const double *__restrict__ Bc,
+                                                           int64_t nbcv, int32_t *__restrict__ bcflag) {
   const int i = blockIdx.x * RN_BLOCK + threadIdx.x;
   if (*guard) return;
+  bool other = false;
+  for (int64_t q = i; q < nbcv; q += (int64_t)gridDim.x * RN_BLOCK) other = other || Bc[q] != 1.0;
+  if (other) *bcflag = 1;  // every writer stores the same value
   int len = 0, na = 0;
   if (i < n) {
     len = Np[i + 1] - Np[i];
@@ -647,7 +653,7 @@ rn_status rn_plan_create_ex(rn_ctx *ctx, const rn_matrix *A, int32_t n_cols, con
     if (m == 1) {
       nbc = (int)rn_div_up(n, RN_BLOCK);
       hipLaunchKernelGGL(k_plan_count_m1, dim3(nbc), dim3(RN_BLOCK), 0, ctx->stream, n, A->rowptr, Np, is_root,
-                         blk_max, blk_na, guard);
+                         blk_max, blk_na, guard, Bc, (int64_t)n_cols * nB, guard + GS_BCNU);
     } else {
       int32_t *ncnt = (int32_t *)rn_scratch(ctx, SLOT_STR_CNT, (size_t)(nr + 1) * sizeof(int32_t), &st);
       if (!ncnt) return fail(st);
@@ -676,17 +682,19 @@ rn_status rn_plan_create_ex(rn_ctx *ctx, const rn_matrix *A, int32_t n_cols, con
   }
   // one synchronisation: guard, maxlen, rank_def, longest A row, node-entry total
   // (and the caller's extra item, read at the same synchronisation)
-  const RnFetch it[4] = {{misc, 16}, {misc + 8, 8}, {guard, 4}, extra ? *extra : RnFetch{nullptr, 0}};
+  const RnFetch it[4] = {{misc, 16}, {misc + 8, 8}, {guard, 4 * (GS_BCNU + 1)}, extra ? *extra : RnFetch{nullptr, 0}};
   const unsigned char *hb = nullptr;
   size_t off[4];
   st = rn_fetch(ctx, extra ? 4 : 3, it, &hb, off);
   if (st != RN_OK) return fail(st);
   if (extra) memcpy(extra_out, hb + off[3], extra->bytes);
   int64_t hp[5];
-  int32_t gword = 0;
+  int32_t gword = 0, bcnu = 1;
   memcpy(hp + 2, hb + off[0], 16);
   memcpy(hp + 4, hb + off[1], 8);
   memcpy(&gword, hb + off[2], 4);
+  memcpy(&bcnu, hb + off[2] + 4 * GS_BCNU, 4);
+  pl->unit_bc = m == 1 && nr > 0 && bcnu == 0;
   st = rn_guard_status(ctx, gword, "rn_plan_create");
   if (st != RN_OK) {
     if (st == RN_ELIMIT)

@@ -670,8 +670,12 @@ __global__ __launch_bounds__(BS) void k_spgemm_p(const SpgParams p, const int G)
 #pragma unroll
     for (int q = 0; q < NP; ++q) r.gp[q] = 0.0;
     if (proj) {
+      // Bc = 1: every lane reads the same first row (no traffic) and uses 1
 #pragma unroll
-      for (int q = 0; q < NB; ++q) r.bcv[q] = spg_ld(p.bce, e * NB + q);
+      for (int q = 0; q < NB; ++q) r.bcv[q] = spg_ld(p.bce, p.unit_bc ? (uint32_t)q : e * NB + q);
+      if (p.unit_bc)
+#pragma unroll
+        for (int q = 0; q < NB; ++q) r.bcv[q] = 1.0;
 #pragma unroll
       for (int q = 0; q < NP; ++q) r.gp[q] = spg_ld(p.gp, (uint32_t)(h.r0 + rq) * NP + q);
     }
@@ -1023,5 +1027,6 @@ SpgParams rn_spg_params(const rn_plan *pl) {
   p.strideZ = pl->nnzN;
   p.strideX = pl->nnzN;
   p.strideA = pl->nnzA * pl->m * pl->m;
+  p.unit_bc = pl->unit_bc ? 1 : 0;
   return p;
 }
