@@ -15,6 +15,13 @@
 #define CODE_NONE 255
 #define CODE_ROOT 254
 #define CODE_MAXLEN 253
+// Compact record (block_m = 1, at most 11 A entries per row, rows of N of at
+// most 31 entries): one 64-bit word, the row in bits 0-7 and code u in bits
+// 8 + 5u .. 12 + 5u, CCODE_NONE where there is none.  The persistent product
+// reads these; the 12-byte records stay for the other kernels.
+#define CCODE_NONE 31u
+#define CCODE_MAXLEN 31
+#define CCODE_MAXNA 11
 
 // Block-row A entries staged in LDS by the product kernel (larger blocks read
 // A from global memory directly).
@@ -81,6 +88,7 @@ struct rn_plan {
   const uint8_t *is_root = nullptr;
   const double *Bc = nullptr;
   uint8_t *codes = nullptr;     // [entries][cstride]
+  uint64_t *ccodes = nullptr;   // [entries] compact records, or NULL
   int64_t ncodes = 0;
   int32_t cstride = 4;          // code bytes per (node) entry, multiple of 4
   int32_t *nodeptr = nullptr;   // block_m = 2: node-entry row pointer
@@ -114,6 +122,7 @@ struct SpgParams {
   int64_t nnzN, strideA, strideX, strideZ;
   const int32_t *Ap, *Aj, *Np, *Nj, *nodeptr, *ncol, *blk_row, *blk_hdr, *xoff, *xl, *xwin;
   const uint8_t *codes, *is_root;
+  const uint64_t *ccodes;  // compact records (the persistent product's condition)
   const double *Bc, *gp, *bce;
   const void *Ax;      // double or float, [batch][strideA]
   const void *X;       // double or float, [batch][strideX]

@@ -437,7 +437,7 @@ __global__ __launch_bounds__(RN_BLOCK) void k_plan_codes(int nblk, int32_t *__re
                                                         uint8_t *__restrict__ codes, int32_t *__restrict__ ncol,
                                                         int32_t *__restrict__ terms, const int32_t *__restrict__ xl,
                                                         const int32_t *__restrict__ xwin, int nu_stride, int acap,
-                                                        int nit) {
+                                                        int nit, uint64_t *__restrict__ ccodes) {
   constexpr int WCAP = SPG_XCAP_M1(RN_BLOCK), ACAPX = SPG_ACAP_M1(RN_BLOCK);
   __shared__ uint8_t s_row[RN_BLOCK];
   __shared__ int s_na[RN_BLOCK / RN_WAVE];
@@ -488,6 +488,7 @@ __global__ __launch_bounds__(RN_BLOCK) void k_plan_codes(int nblk, int32_t *__re
     const int i = r0 + lr;
     uint32_t *cw = (uint32_t *)(codes + (int64_t)(e0 + t) * cstride);
     const int nw = cstride >> 2;
+    uint64_t cc = (uint64_t)lr | ~(uint64_t)0xff;  // compact record: every code "none" so far
     if (s_rr[lr]) {
       cw[0] = 0xffffff00u | (uint32_t)lr;
       for (int w = 1; w < nw; ++w) cw[w] = 0xffffffffu;
@@ -566,10 +567,14 @@ __global__ __launch_bounds__(RN_BLOCK) void k_plan_codes(int nblk, int32_t *__re
           }
           hit += live[q] && code != CODE_NONE;
           if (w > 0 || q > 0) word |= code << (8 * q);
+          const int u = 4 * w + q - 1;
+          if (u >= 0 && u < CCODE_MAXNA && code != CODE_NONE)
+            cc &= ~((uint64_t)(CCODE_NONE - code) << (8 + 5 * u));
         }
         cw[w] = word;
       }
     }
+    if (M == 1 && ccodes) ccodes[e0 + t] = cc;
   }
   block_to_slot<false>(hit, terms);  // per-workgroup term counts
 }
@@ -737,6 +742,12 @@ rn_status rn_plan_create_ex(rn_ctx *ctx, const rn_matrix *A, int32_t n_cols, con
                  !plan_alloc(pl, &pl->xwin, (size_t)(pl->nblk + 1) * nunit_max * sizeof(int32_t))))
     return fail(rn_fail(ctx, RN_ENOMEM, "rn_plan_create: device allocation"));
   if (m == 1) pl->fixed_bytes += (size_t)(A->nnz + 1) * 4 + (size_t)(pl->nblk + 1) * nunit_max * 4;
+  // compact records where every code fits 5 bits and a row's codes 56 bits
+  if (m == 1 && maxna <= CCODE_MAXNA && pl->maxlen <= CCODE_MAXLEN && nnz_N > 0) {
+    if (!plan_alloc(pl, &pl->ccodes, (size_t)(nnz_N + 1) * sizeof(uint64_t)))
+      return fail(rn_fail(ctx, RN_ENOMEM, "rn_plan_create: device allocation"));
+    pl->fixed_bytes += (size_t)(nnz_N + 1) * 8;
+  }
   if (m == 1 && nB <= 2) {
     if (!plan_alloc(pl, &pl->bce, (size_t)(nnz_N + 1) * nB * sizeof(double)))
       return fail(rn_fail(ctx, RN_ENOMEM, "rn_plan_create: device allocation"));
@@ -782,11 +793,11 @@ rn_status rn_plan_create_ex(rn_ctx *ctx, const rn_matrix *A, int32_t n_cols, con
     if (m == 1)
       hipLaunchKernelGGL((k_plan_codes<1>), gc, bc, 0, ctx->stream, nb, pl->blk_hdr, rp, A->rowptr, A->colind, Np,
                          Nj, is_root, pl->cstride, pl->codes, pl->ncol, blk_hit, pl->xl, pl->xwin, nu_stride, acap,
-                         32 - __builtin_clz((unsigned)(pl->maxlen > 0 ? pl->maxlen : 1)));
+                         32 - __builtin_clz((unsigned)(pl->maxlen > 0 ? pl->maxlen : 1)), pl->ccodes);
     else
       hipLaunchKernelGGL((k_plan_codes<2>), gc, bc, 0, ctx->stream, nb, pl->blk_hdr, rp, A->rowptr, A->colind, Np,
                          Nj, is_root, pl->cstride, pl->codes, pl->ncol, blk_hit, (const int32_t *)nullptr,
-                         (const int32_t *)nullptr, 0, 0, 0);
+                         (const int32_t *)nullptr, 0, 0, 0, (uint64_t *)nullptr);
     hipLaunchKernelGGL((k_finish_slots<false, unsigned long long>), dim3(1), dim3(RN_BLOCK), 0, ctx->stream, blk_hit,
                        pl->nblk, pl->d_terms);
     if (hipGetLastError() != hipSuccess) return fail(rn_fail(ctx, RN_EHIP, "launch"));
@@ -818,7 +829,7 @@ extern "C" void rn_plan_destroy(rn_plan *pl) {
     (void)hipDeviceSynchronize();  // its context is gone: wait for any work still reading the plan
   }
   void *bufs[] = {pl->codes,   pl->ncol,    pl->nodeptr, pl->gp, pl->d_terms,
-                  pl->blk_row, pl->blk_hdr, pl->xoff,    pl->xl, pl->xwin, pl->bce};
+                  pl->blk_row, pl->blk_hdr, pl->xoff,    pl->xl, pl->xwin, pl->bce, pl->ccodes};
   for (void *b : bufs) rn_dev_free(pl->ctx, b);
   for (int s = 0; s < WS_COUNT; ++s) rn_dev_free(pl->ctx, pl->ws[s].ptr);
   delete pl;

@@ -544,8 +544,9 @@ __global__ __launch_bounds__(BS) void k_spgemm(const SpgParams p) {
 }
 
 // ---------------------------------------------------------------------------
-// Persistent form for scalar operators (block_m = 1, n_B <= 2, records of at
-// most 12 bytes).  G resident workgroups (a multiple of 8) walk the product
+// Persistent form for scalar operators (block_m = 1, n_B <= 2, plans with
+// compact 8-byte records: at most 11 A terms per row and neighbour pattern
+// rows of at most 30 entries).  G resident workgroups (a multiple of 8) walk the product
 // blocks of their XCD's range with stride G/8.  While one block is computed
 // from LDS, the header, window table and first-round loads of the next block
 // are in flight, so a block costs its LDS work instead of its chain of memory
@@ -602,8 +603,6 @@ __global__ __launch_bounds__(BS) void k_spgemm_p(const SpgParams p, const int G)
   const TV *X = (const TV *)p.X + (int64_t)b * p.strideX;
   const int64_t zb = (int64_t)b * p.strideZ;
   double *Z = p.Z + zb;
-  const uint32_t *codes = (const uint32_t *)p.codes;
-  const uint32_t nw = (uint32_t)(p.cstride >> 2);
   double *part = p.part + (int64_t)b * RN_MAXDOT * p.nblk;
 
   // ---- a block's header and window unit starts: loaded (as uniform vector
@@ -647,7 +646,7 @@ __global__ __launch_bounds__(BS) void k_spgemm_p(const SpgParams p, const int G)
   };
   // ---- a block's first round of vector loads (registers) ----
   struct Rd {
-    uint32_t w0, w1, w2;
+    uint32_t w0, w1;  // compact record (row, 5-bit codes)
     double bcv[NB], gp[NP], own;
     int rp, ap;
     int x0[NIT];
@@ -656,10 +655,9 @@ __global__ __launch_bounds__(BS) void k_spgemm_p(const SpgParams p, const int G)
   auto load_rd = [&](const Hd &h, Rd &r) {
     const int te = t < h.ne ? t : 0;
     const uint32_t e = (uint32_t)(h.e0 + te);
-    const uint3 r3 = *(const uint3 *)((const char *)codes + e * nw * 4u);  // 16 bytes of slack
-    r.w0 = r3.x;
-    r.w1 = r3.y;
-    r.w2 = r3.z;
+    const uint2 r2 = *(const uint2 *)((const char *)p.ccodes + e * 8u);  // compact record
+    r.w0 = r2.x;
+    r.w1 = r2.y;
     r.own = 0.0;
     if (MODE == MODE_CG_STEP) r.own = spg_ld(p.Xown + zb, e);
     const int rq = t < h.nrows ? t : h.nrows - 1, rt = t < h.nrows ? t : h.nrows;
@@ -787,13 +785,14 @@ __global__ __launch_bounds__(BS) void k_spgemm_p(const SpgParams p, const int G)
       // element 0 only meet masked terms.  Separate paths keep every LDS
       // access an LDS instruction (a generic access would also wait for the
       // next block's loads in flight).
-      auto word = [&](const int lo, const int hi, const uint32_t w, const int path) {
+      const uint64_t rec = (uint64_t)R.w0 | ((uint64_t)R.w1 << 32);
+      auto word = [&](const int lo, const int hi, const int path) {
         uint32_t xi[4], hm[4];
         TV av[4], xv[4];
 #pragma unroll
         for (int u = lo; u < hi; ++u) {
-          const uint32_t c = __builtin_amdgcn_ubfe(w, 8 * ((u + 1) & 3), 8);
-          hm[u - lo] = (c != CODE_NONE && u < H.namax) ? 0xffffffffu : 0u;
+          const uint32_t c = (uint32_t)(rec >> (8 + 5 * u)) & CCODE_NONE;
+          hm[u - lo] = (c != CCODE_NONE && u < H.namax) ? 0xffffffffu : 0u;
           const uint32_t xo =
               path < 2 ? (uint32_t)s_x0[la + u] : (uint32_t)p.xoff[H.aB + min(la + u, H.naB - 1)];
           xi[u - lo] = (xo + c) & hm[u - lo];
@@ -812,17 +811,17 @@ __global__ __launch_bounds__(BS) void k_spgemm_p(const SpgParams p, const int G)
         }
       };
       if (staged && win) {
-        word(0, 3, R.w0, 0);
-        if (g1) word(3, 7, R.w1, 0);
-        if (g2) word(7, 11, R.w2, 0);
+        word(0, 3, 0);
+        if (g1) word(3, 7, 0);
+        if (g2) word(7, 11, 0);
       } else if (staged) {
-        word(0, 3, R.w0, 1);
-        if (g1) word(3, 7, R.w1, 1);
-        if (g2) word(7, 11, R.w2, 1);
+        word(0, 3, 1);
+        if (g1) word(3, 7, 1);
+        if (g2) word(7, 11, 1);
       } else {
-        word(0, 3, R.w0, 2);
-        if (g1) word(3, 7, R.w1, 2);
-        if (g2) word(7, 11, R.w2, 2);
+        word(0, 3, 2);
+        if (g1) word(3, 7, 2);
+        if (g2) word(7, 11, 2);
       }
       z = (double)acc;
       if (MODE == MODE_GM_STEP) z *= sc[GmLayout(p.K).s + p.k];
@@ -937,7 +936,7 @@ template <int M, int NB, int MODE>
 static int launch_m(const SpgParams &p, int batch, bool mixed, hipStream_t s) {
   if constexpr (M == 1 && NB <= 2) {
     // (the branch-free first round reads 32 elements of X and one of A whatever the block)
-    if (p.cstride <= 12 && p.nnzN >= 64 && p.strideA >= 1 && persist_on()) {
+    if (p.ccodes && p.nnzN >= 64 && p.strideA >= 1 && persist_on()) {
       int G = 0;
       if (p.bs == 128 && (G = launch_p<NB, MODE, 128>(p, batch, mixed, s)) > 0) return G;
       if (p.bs == RN_BLOCK && (G = launch_p<NB, MODE, RN_BLOCK>(p, batch, mixed, s)) > 0) return G;
@@ -1021,6 +1020,7 @@ SpgParams rn_spg_params(const rn_plan *pl) {
   p.bce = pl->bce;
   p.xwin = pl->xwin;
   p.codes = pl->codes;
+  p.ccodes = pl->ccodes;
   p.is_root = pl->is_root;
   p.Bc = pl->Bc;
   p.gp = pl->gp;

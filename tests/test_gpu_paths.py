@@ -124,6 +124,40 @@ def _banded(n, hb):
     return Sp, np.concatenate(rows).astype(np.int32)
 
 
+@pytest.mark.parametrize("hb,d", [(5, 6), (5, 7), (6, 5)])
+def test_compact_record_limits(R, ctx, hb, d):
+    """The persistent product's 8-byte records hold 11 A terms of 5-bit
+    codes.  Banded operators |i - j| <= hb with node-pair aggregates: hb 5,
+    degree 6 sits on both limits (11 A entries per row, neighbour rows of
+    31 entries: code 30 is used); hb 5, degree 7 has longer rows and hb 6
+    more A entries per row, so those plans keep the 12-byte records only."""
+    import oracle as O
+    import workloads as W
+    n = 300
+    offs = [(k, 0) for k in range(-hb, hb + 1)]
+    A = W._csr_from_offsets(n, 1, offs, [2.0 * hb + 1.5 if k == 0 else -1.0 + 0.05 * k for k, _ in offs])
+    Sp, Sj = _banded(n, hb)
+    agg = (np.arange(n) // 2).astype(np.int32)
+    roots = np.arange(0, n, 2, dtype=np.int32)
+    Npn, Njn = O.pattern_nodes(Sp, Sj, agg, roots.size, d)
+    Np, Nj, is_root = O.pattern_dofs(Npn, Njn, agg, roots, 1)
+    assert int(np.diff(Np).max()) == {(5, 6): 31, (5, 7): 36, (6, 5): 31}[(hb, d)]
+    nc = int(roots.size)
+    Bc = np.random.default_rng(11).uniform(0.5, 2.0, (nc, 1))
+    dA = R.DeviceCSR.from_host(A.rowptr, A.colind, A.vals)
+    plan = ctx.plan(dA, nc, dev(Np), dev(Nj), dev(is_root), dev(Bc))
+    try:
+        X = np.random.default_rng(12).standard_normal(Nj.size)
+        ref_m, refp, _ = _product_refs(A, Np, Nj, nc, is_root, Bc, 1, X)
+        Z = host(ctx.masked_product(plan, dA.vals, dev(X), project=False))
+        Zp = host(ctx.masked_product(plan, dA.vals, dev(X), project=True))
+        scale = np.max(np.abs(ref_m))
+        assert np.max(np.abs(Z - ref_m)) <= FP64_TOL * scale
+        assert np.max(np.abs(Zp - refp)) <= FP64_TOL * scale
+    finally:
+        plan.close()
+
+
 @pytest.mark.parametrize("hb,d", [(20, 1), (8, 2), (35, 2), (0, 0)])
 def test_pattern_row_widths(R, ctx, hb, d):
     """Pattern levels of every width: rows gathered in the small window
