@@ -778,15 +778,15 @@ __global__ __launch_bounds__(BS) void k_spgemm_p(const SpgParams p, const int G)
       if (proj)
 #pragma unroll
         for (int q = 0; q < NP; ++q) gq[q] = s_gp[lrow * NP + q];
-      const bool g1 = H.namax > 3, g2 = H.namax > 7;
+      const bool g1 = H.namax > 3, g2 = H.namax > 5, g3 = H.namax > 7, g4 = H.namax > 9;
       TV acc = 0;
-      // one code word (terms lo..hi-1): offsets, then A and X, then the
+      // one group of terms (lo..hi-1): offsets, then A and X, then the
       // multiply-adds in the order of A's row; A past the block's slice and X
       // element 0 only meet masked terms.  Separate paths keep every LDS
       // access an LDS instruction (a generic access would also wait for the
       // next block's loads in flight).
       const uint64_t rec = (uint64_t)R.w0 | ((uint64_t)R.w1 << 32);
-      auto word = [&](const int lo, const int hi, const int path) {
+      auto group = [&](const int lo, const int hi, const int path) {
         uint32_t xi[4], hm[4];
         TV av[4], xv[4];
 #pragma unroll
@@ -810,18 +810,26 @@ __global__ __launch_bounds__(BS) void k_spgemm_p(const SpgParams p, const int G)
           acc += hm[u - lo] ? pr : TV(0);
         }
       };
+      // terms in groups of 3, 2, 2, 2 and 2 (groups past the block's longest
+      // A row skipped): rows of 5, 7 or 9 A entries take no masked term
       if (staged && win) {
-        word(0, 3, 0);
-        if (g1) word(3, 7, 0);
-        if (g2) word(7, 11, 0);
+        group(0, 3, 0);
+        if (g1) group(3, 5, 0);
+        if (g2) group(5, 7, 0);
+        if (g3) group(7, 9, 0);
+        if (g4) group(9, 11, 0);
       } else if (staged) {
-        word(0, 3, 1);
-        if (g1) word(3, 7, 1);
-        if (g2) word(7, 11, 1);
+        group(0, 3, 1);
+        if (g1) group(3, 5, 1);
+        if (g2) group(5, 7, 1);
+        if (g3) group(7, 9, 1);
+        if (g4) group(9, 11, 1);
       } else {
-        word(0, 3, 2);
-        if (g1) word(3, 7, 2);
-        if (g2) word(7, 11, 2);
+        group(0, 3, 2);
+        if (g1) group(3, 5, 2);
+        if (g2) group(5, 7, 2);
+        if (g3) group(7, 9, 2);
+        if (g4) group(9, 11, 2);
       }
       z = (double)acc;
       if (MODE == MODE_GM_STEP) z *= sc[GmLayout(p.K).s + p.k];
