@@ -205,7 +205,8 @@ __device__ inline void rn_cg_init_fin(double g, double *sc, int32_t *st, double 
 }
 // delta_k = <D_k, Pi(A D_k)> and alpha_k = gamma_k / delta_k; breakdown when
 // the curvature is not positive
-__device__ inline void rn_cg_alpha_fin(double dl, double *sc, int32_t *st, double *hist, int K, int k) {
+// (gam = gamma_k, read by the caller together with its other loads)
+__device__ inline void rn_cg_alpha_fin(double dl, double gam, double *sc, int32_t *st, double *hist, int K, int k) {
   const CgLayout L(K);
   sc[L.del + k] = dl;
   if (hist) hist[1 + K + k] = dl;
@@ -217,21 +218,23 @@ __device__ inline void rn_cg_alpha_fin(double dl, double *sc, int32_t *st, doubl
     st[ST_STATUS] = RN_EBREAKDOWN;
     return;
   }
-  const double al = sc[L.gam + k] / dl;
+  const double al = gam / dl;
   sc[L.alp + k] = al;
   if (hist) hist[1 + 2 * K + k] = al;
 }
 // gamma_{k+1} = <R_{k+1}, R_{k+1}>, beta_k = gamma_{k+1} / gamma_k, the step
 // count and the stopping test
-__device__ inline double rn_cg_beta_fin(double g, double *sc, int32_t *st, double *hist, int K, int k) {
+// (gam = gamma_k and gam0 = gamma_0, read by the caller with its other loads)
+__device__ inline double rn_cg_beta_fin(double g, double gam, double gam0, double *sc, int32_t *st, double *hist,
+                                        int K, int k) {
   const CgLayout L(K);
-  const double be = g / sc[L.gam + k];
+  const double be = g / gam;
   sc[L.gam + k + 1] = g;
   sc[L.bet + k] = be;
   if (hist) hist[k + 1] = g;
   st[ST_ITERS] = k + 1;
   if (!isfinite(g)) st[ST_STATUS] = RN_ENONFINITE;
-  else if (g <= RN_CG_STOP * sc[SC_GAMMA0]) st[ST_DONE] = 1;
+  else if (g <= RN_CG_STOP * gam0) st[ST_DONE] = 1;
   return be;
 }
 // GMRES: beta_0 = ||R_0|| and the scale of the first basis vector

@@ -48,11 +48,14 @@ __global__ __launch_bounds__(RN_BLOCK) void k_cg_alpha(int K, int k, int np, int
   __shared__ double s_w[8];
   const int b = blockIdx.x;
   int32_t *st = stv + (int64_t)b * ST_STRIDE;
-  if (st[ST_STATUS] || st[ST_DONE]) return;
+  double *sc = scal + (int64_t)b * scal_stride;
+  // status, gamma_k and the partials are loaded together (one memory round
+  // trip); a stopped entry's partials are read and not used
+  const int32_t s0 = st[ST_STATUS], s1 = st[ST_DONE];
+  const double gam = sc[CgLayout(K).gam + k];
   const double dl = rn_reduce_part(part_spg + (int64_t)b * pstride, np, s_w);
-  if (threadIdx.x != 0) return;
-  rn_cg_alpha_fin(dl, scal + (int64_t)b * scal_stride, st, histv ? histv + (int64_t)b * hist_stride : nullptr, K,
-                  k);
+  if (s0 || s1 || threadIdx.x != 0) return;
+  rn_cg_alpha_fin(dl, gam, sc, st, histv ? histv + (int64_t)b * hist_stride : nullptr, K, k);
 }
 
 // P += alpha D, R -= alpha Z, partials of <R,R>.
@@ -65,16 +68,40 @@ __global__ __launch_bounds__(RN_BLOCK) void k_cg_update(int64_t nnz, int64_t str
   __shared__ double s_w[8];
   const int b = blockIdx.y;
   const int32_t *st = stv + (int64_t)b * ST_STRIDE;
-  if (st[ST_STATUS] || st[ST_DONE]) return;
+  const int64_t off = (int64_t)b * stride, gs = (int64_t)gridDim.x * RN_BLOCK;
+  // the first element's loads go out with the status and alpha loads (one
+  // memory round trip before the first store); then one element ahead
+  int64_t e = (int64_t)blockIdx.x * RN_BLOCK + threadIdx.x;
+  double p = 0.0, d = 0.0, r = 0.0, z = 0.0;
+  if (e < nnz) {
+    p = P[off + e];
+    d = D[off + e];
+    r = R[off + e];
+    z = Z[off + e];
+  }
+  const int32_t s0 = st[ST_STATUS], s1 = st[ST_DONE];
   const double al = scal[(int64_t)b * scal_stride + CgLayout(K).alp + k];
-  const int64_t off = (int64_t)b * stride;
+  if (s0 || s1) return;
   RnAcc s;
-  for (int64_t e = (int64_t)blockIdx.x * RN_BLOCK + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * RN_BLOCK) {
-    P[off + e] += al * D[off + e];
-    const double r = R[off + e] - al * Z[off + e];
-    R[off + e] = r;
-    if (Rrec) Rrec[off + e] = r;
-    s.add(r * r);
+  while (e < nnz) {
+    const int64_t en = e + gs;
+    double pn = 0.0, dn = 0.0, rn = 0.0, zn = 0.0;
+    if (en < nnz) {
+      pn = P[off + en];
+      dn = D[off + en];
+      rn = R[off + en];
+      zn = Z[off + en];
+    }
+    P[off + e] = p + al * d;
+    const double rr = r - al * z;
+    R[off + e] = rr;
+    if (Rrec) Rrec[off + e] = rr;
+    s.add(rr * rr);
+    e = en;
+    p = pn;
+    d = dn;
+    r = rn;
+    z = zn;
   }
   const double S = rn_block_sum2(s.hi, s.lo, s_w);
   if (threadIdx.x == 0) part_ew[(int64_t)b * RN_MAXDOT * gridDim.x + blockIdx.x] = S;
@@ -93,20 +120,39 @@ __global__ __launch_bounds__(RN_BLOCK) void k_cg_dir(int64_t nnz, int64_t stride
   __shared__ double s_w[8];
   const int b = blockIdx.y;
   int32_t *st = stv + (int64_t)b * ST_STRIDE;
-  if (st[ST_STATUS] || st[ST_DONE]) return;
   double *sc = scal + (int64_t)b * scal_stride;
   const CgLayout L(K);
+  const int64_t off = (int64_t)b * stride, gs = (int64_t)gridDim.x * RN_BLOCK;
+  // status, gamma_k, gamma_0, the partials and the first element go out
+  // together (one memory round trip); then one element ahead
+  int64_t e = (int64_t)blockIdx.x * RN_BLOCK + threadIdx.x;
+  double r = 0.0, d = 0.0;
+  if (e < nnz) {
+    r = R[off + e];
+    d = D[off + e];
+  }
+  const int32_t s0 = st[ST_STATUS], s1 = st[ST_DONE];
+  const double gam = sc[L.gam + k], gam0 = sc[SC_GAMMA0];
   const double g = rn_reduce_part(part_ew + (int64_t)b * RN_MAXDOT * nb_ew, nb_ew, s_w);
-  const double be = g / sc[L.gam + k];
+  if (s0 || s1) return;
+  const double be = g / gam;
   if (blockIdx.x == 0 && threadIdx.x == 0)
-    rn_cg_beta_fin(g, sc, st, histv ? histv + (int64_t)b * hist_stride : nullptr, K, k);
+    rn_cg_beta_fin(g, gam, gam0, sc, st, histv ? histv + (int64_t)b * hist_stride : nullptr, K, k);
   if (!isfinite(g)) return;
-  const int64_t off = (int64_t)b * stride;
-  for (int64_t e = (int64_t)blockIdx.x * RN_BLOCK + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * RN_BLOCK) {
-    const double d = R[off + e] + be * D[off + e];
-    D[off + e] = d;
-    if (Drec) Drec[off + e] = d;
-    if (MIXED) D32[off + e] = (float)d;
+  while (e < nnz) {
+    const int64_t en = e + gs;
+    double rn = 0.0, dn = 0.0;
+    if (en < nnz) {
+      rn = R[off + en];
+      dn = D[off + en];
+    }
+    const double dd = r + be * d;
+    D[off + e] = dd;
+    if (Drec) Drec[off + e] = dd;
+    if (MIXED) D32[off + e] = (float)dd;
+    e = en;
+    r = rn;
+    d = dn;
   }
 }
 
