@@ -304,7 +304,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the energy-minimisation path here is single-GPU "
-              "(see DESIGN.md for how it would shard); use --gpus 1", file=sys.stderr)
+              "(no sharded path is built); use --gpus 1", file=sys.stderr)
         sys.exit(2)
     import torch
     import paper_1610_03154_amd as R
