@@ -38,39 +38,26 @@ __global__ __launch_bounds__(RN_BLOCK) void k_cg_fin_init(int np, int64_t pstrid
                  histv ? histv + (int64_t)b * hist_stride : nullptr, K);
 }
 
-// One block per batch entry: delta_k = <D,Z> from the product's per-block
-// partials (fixed order, compensated), the step length alpha_k, the
-// breakdown and finiteness tests.
-__global__ __launch_bounds__(RN_BLOCK) void k_cg_alpha(int K, int k, int np, int64_t pstride,
-                                                      const double *__restrict__ part_spg, double *__restrict__ scal,
-                                                      int scal_stride, int32_t *__restrict__ stv,
-                                                      double *__restrict__ histv, int hist_stride) {
-  __shared__ double s_w[8];
-  const int b = blockIdx.x;
-  int32_t *st = stv + (int64_t)b * ST_STRIDE;
-  double *sc = scal + (int64_t)b * scal_stride;
-  // status, gamma_k and the partials are loaded together (one memory round
-  // trip); a stopped entry's partials are read and not used
-  const int32_t s0 = st[ST_STATUS], s1 = st[ST_DONE];
-  const double gam = sc[CgLayout(K).gam + k];
-  const double dl = rn_reduce_part(part_spg + (int64_t)b * pstride, np, s_w);
-  if (s0 || s1 || threadIdx.x != 0) return;
-  rn_cg_alpha_fin(dl, gam, sc, st, histv ? histv + (int64_t)b * hist_stride : nullptr, K, k);
-}
-
-// P += alpha D, R -= alpha Z, partials of <R,R>.
-__global__ __launch_bounds__(RN_BLOCK) void k_cg_update(int64_t nnz, int64_t stride, int K, int k,
+// delta_k = <D, Pi(A D)> from the product's per-workgroup partials: every
+// block sums them in the same fixed order (compensated), so all blocks get
+// the same delta_k and alpha_k; block 0 stores them with the breakdown and
+// finiteness tests.  Then P += alpha D, R -= alpha Z and partials of <R,R>.
+__global__ __launch_bounds__(RN_BLOCK) void k_cg_update(int64_t nnz, int64_t stride, int K, int k, int np,
+                                                       int64_t pstride, const double *__restrict__ part_spg,
                                                        double *__restrict__ P, double *__restrict__ R,
                                                        const double *__restrict__ D, const double *__restrict__ Z,
-                                                       double *__restrict__ part_ew, const double *__restrict__ scal,
-                                                       int scal_stride, const int32_t *__restrict__ stv,
+                                                       double *__restrict__ part_ew, double *__restrict__ scal,
+                                                       int scal_stride, int32_t *__restrict__ stv,
+                                                       double *__restrict__ histv, int hist_stride,
                                                        double *__restrict__ Rrec) {
   __shared__ double s_w[8];
   const int b = blockIdx.y;
-  const int32_t *st = stv + (int64_t)b * ST_STRIDE;
+  int32_t *st = stv + (int64_t)b * ST_STRIDE;
+  double *sc = scal + (int64_t)b * scal_stride;
   const int64_t off = (int64_t)b * stride, gs = (int64_t)gridDim.x * RN_BLOCK;
-  // the first element's loads go out with the status and alpha loads (one
-  // memory round trip before the first store); then one element ahead
+  // the first element's loads go out with the status, gamma_k and partial
+  // loads (one memory round trip before the first store); then one element
+  // ahead.  A stopped entry's loads are made and not used.
   int64_t e = (int64_t)blockIdx.x * RN_BLOCK + threadIdx.x;
   double p = 0.0, d = 0.0, r = 0.0, z = 0.0;
   if (e < nnz) {
@@ -80,8 +67,13 @@ __global__ __launch_bounds__(RN_BLOCK) void k_cg_update(int64_t nnz, int64_t str
     z = Z[off + e];
   }
   const int32_t s0 = st[ST_STATUS], s1 = st[ST_DONE];
-  const double al = scal[(int64_t)b * scal_stride + CgLayout(K).alp + k];
+  const double gam = sc[CgLayout(K).gam + k];
+  const double dl = rn_reduce_part(part_spg + (int64_t)b * pstride, np, s_w);
   if (s0 || s1) return;
+  if (blockIdx.x == 0 && threadIdx.x == 0)
+    rn_cg_alpha_fin(dl, gam, sc, st, histv ? histv + (int64_t)b * hist_stride : nullptr, K, k);
+  if (!isfinite(dl) || dl <= 0.0) return;  // breakdown: nothing is updated
+  const double al = gam / dl;
   RnAcc s;
   while (e < nnz) {
     const int64_t en = e + gs;
@@ -581,10 +573,9 @@ extern "C" rn_status rn_energy_min(rn_ctx *ctx, rn_plan *pl, const double *A_val
       s.Z = Z;
       int np = 0;
       RN_TRY(rn_launch_spgemm(ctx, pl, MODE_CG_STEP, s, batch, mixed, &np));
-      hipLaunchKernelGGL(k_cg_alpha, dim3(batch), blk, 0, ctx->stream, K, k, np, pstride_spg, part_spg, p.scal,
-                         scal_stride, p.st, hist, hist_stride);
-      hipLaunchKernelGGL(k_cg_update, g2, blk, 0, ctx->stream, nz, nz, K, k, P, R, D, Z, part_ew, p.scal,
-                         scal_stride, p.st, tape ? rn_tape_R(tape, k + 1) : nullptr);
+      hipLaunchKernelGGL(k_cg_update, g2, blk, 0, ctx->stream, nz, nz, K, k, np, pstride_spg, part_spg, P, R, D, Z,
+                         part_ew, p.scal, scal_stride, p.st, hist, hist_stride,
+                         tape ? rn_tape_R(tape, k + 1) : nullptr);
       LAUNCH_CHECK(ctx);
       if (mixed)
         hipLaunchKernelGGL(k_cg_dir<true>, g2, blk, 0, ctx->stream, nz, nz, K, k, (int)gew, R, D, D32, part_ew, p.scal,
