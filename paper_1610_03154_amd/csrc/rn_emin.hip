@@ -20,6 +20,8 @@
 #include <cstring>
 #include <new>
 
+#include <algorithm>
+
 #include "rn_emin.h"
 
 // ---------------------------------------------------------------------------
@@ -508,7 +510,9 @@ extern "C" rn_status rn_energy_min(rn_ctx *ctx, rn_plan *pl, const double *A_val
   const int K = iters;
   const int64_t nz = pl->nnzN, nzb = (int64_t)batch * nz;
   rn_status st = RN_OK;
-  const unsigned gew = ew_grid(nz);
+  // CG: at most 1024 workgroups for its element-wise kernels (every block of
+  // the update and direction kernels sums the previous kernel's partials)
+  const unsigned gew = gm ? ew_grid(nz) : std::min(ew_grid(nz), 1024u);
   const int scal_stride = gm ? GmLayout(K).total : CgLayout(K).total;
   const int hist_stride = 3 * K + 1;
   SpgParams p = rn_spg_params(pl);
