@@ -72,6 +72,8 @@ __global__ __launch_bounds__(RN_BLOCK) void k_cg_update(int64_t nnz, int64_t str
   const double gam = sc[CgLayout(K).gam + k];
   const double dl = rn_reduce_part(part_spg + (int64_t)b * pstride, np, s_w);
   if (s0 || s1) return;
+  // (another block may read the status before or after block 0 sets a
+  // breakdown here; either way it stops on the same delta_k)
   if (blockIdx.x == 0 && threadIdx.x == 0)
     rn_cg_alpha_fin(dl, gam, sc, st, histv ? histv + (int64_t)b * hist_stride : nullptr, K, k);
   if (!isfinite(dl) || dl <= 0.0) return;  // breakdown: nothing is updated
@@ -130,6 +132,8 @@ __global__ __launch_bounds__(RN_BLOCK) void k_cg_dir(int64_t nnz, int64_t stride
   const double g = rn_reduce_part(part_ew + (int64_t)b * RN_MAXDOT * nb_ew, nb_ew, s_w);
   if (s0 || s1) return;
   const double be = g / gam;
+  // (a block that reads the stop flag block 0 sets here skips its part of
+  // D_{k+1}, which no later step reads once the iteration has stopped)
   if (blockIdx.x == 0 && threadIdx.x == 0)
     rn_cg_beta_fin(g, gam, gam0, sc, st, histv ? histv + (int64_t)b * hist_stride : nullptr, K, k);
   if (!isfinite(g)) return;
