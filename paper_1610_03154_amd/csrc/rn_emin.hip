@@ -421,11 +421,20 @@ __global__ __launch_bounds__(RN_BLOCK) void k_to_f32(const double *__restrict__ 
     dst[q] = (float)src[q];
 }
 
-__global__ __launch_bounds__(RN_BLOCK) void k_bcast(const double *__restrict__ src, int64_t n, int64_t stride,
-                                                   double *__restrict__ dst) {
+// P = T for every batch entry (grid.y), and, by the blocks of entry 0, the
+// status, scalar and history blocks zeroed: the CG set-up in one launch
+__global__ __launch_bounds__(RN_BLOCK) void k_cg_start(const double *__restrict__ src, int64_t n, int64_t stride,
+                                                      double *__restrict__ dst, int32_t *__restrict__ za, int64_t na,
+                                                      double *__restrict__ zb, int64_t nb, double *__restrict__ zc,
+                                                      int64_t nc) {
   const int b = blockIdx.y;
-  for (int64_t q = (int64_t)blockIdx.x * RN_BLOCK + threadIdx.x; q < n; q += (int64_t)gridDim.x * RN_BLOCK)
-    dst[(int64_t)b * stride + q] = src[q];
+  const int64_t s = (int64_t)gridDim.x * RN_BLOCK, q0 = (int64_t)blockIdx.x * RN_BLOCK + threadIdx.x;
+  if (b == 0) {
+    for (int64_t q = q0; q < na; q += s) za[q] = 0;
+    for (int64_t q = q0; q < nb; q += s) zb[q] = 0.0;
+    for (int64_t q = q0; q < nc; q += s) zc[q] = 0.0;
+  }
+  for (int64_t q = q0; q < n; q += s) dst[(int64_t)b * stride + q] = src[q];
 }
 
 // ---------------------------------------------------------------------------
@@ -525,10 +534,14 @@ extern "C" rn_status rn_energy_min(rn_ctx *ctx, rn_plan *pl, const double *A_val
   double *part_spg = p.part;
   double *part_ew = p.part + (int64_t)batch * RN_MAXDOT * pl->nblk;
   const int64_t pstride_spg = (int64_t)RN_MAXDOT * pl->nblk, pstride_ew = (int64_t)RN_MAXDOT * gew;
-  // status, scalars and history start at zero (one launch for the three)
-  hipLaunchKernelGGL(k_zero3, dim3(64), dim3(RN_BLOCK), 0, ctx->stream, p.st, (int64_t)batch * ST_STRIDE, p.scal,
-                     (int64_t)batch * scal_stride, hist, hist ? (int64_t)batch * hist_stride : 0);
-  LAUNCH_CHECK(ctx);
+  // status, scalars and history start at zero (one launch for the three;
+  // for CG the launch that sets P = T does it)
+  const int64_t n_st = (int64_t)batch * ST_STRIDE, n_sc = (int64_t)batch * scal_stride,
+                n_hist = hist ? (int64_t)batch * hist_stride : 0;
+  if (gm) {
+    hipLaunchKernelGGL(k_zero3, dim3(64), dim3(RN_BLOCK), 0, ctx->stream, p.st, n_st, p.scal, n_sc, hist, n_hist);
+    LAUNCH_CHECK(ctx);
+  }
   const float *A32 = nullptr, *T32 = nullptr;
   if (mixed) {
     const int64_t na = (int64_t)batch * p.strideA;
@@ -550,7 +563,7 @@ extern "C" rn_status rn_energy_min(rn_ctx *ctx, rn_plan *pl, const double *A_val
     double *Z = (double *)rn_plan_ws(pl, WS_Z, (size_t)nzb * 8, &st);
     float *D32 = mixed ? (float *)rn_plan_ws(pl, WS_D32, (size_t)nzb * 4, &st) : nullptr;
     if (!R || !D || !Z || (mixed && !D32)) return st;
-    hipLaunchKernelGGL(k_bcast, g2, blk, 0, ctx->stream, T, nz, nz, P);
+    hipLaunchKernelGGL(k_cg_start, g2, blk, 0, ctx->stream, T, nz, nz, P, p.st, n_st, p.scal, n_sc, hist, n_hist);
     LAUNCH_CHECK(ctx);
     // R_0 = D_0 = -Pi(A T), gamma_0
     SpgParams q = p;
