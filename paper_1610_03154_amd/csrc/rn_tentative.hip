@@ -5,25 +5,19 @@
 #include "rn_gram.h"
 #include "rn_internal.h"
 
-__global__ __launch_bounds__(RN_BLOCK) void k_inject_bc(int n_agg, int m, int nB, const int32_t *__restrict__ roots,
-                                                       const double *__restrict__ B, double *__restrict__ Bc,
-                                                       const int32_t *__restrict__ guard) {
-  const int q = blockIdx.x * RN_BLOCK + threadIdx.x;  // coarse DOF m*a + c
-  if (q >= n_agg * m || *guard) return;
-  const int a = q / m, c = q % m;
-  const int64_t src = (int64_t)(m * roots[a] + c) * nB;
-  for (int k = 0; k < nB; ++k) Bc[(int64_t)q * nB + k] = B[src + k];
-}
-
-// inverse of the m x m root block of the first m candidates (m <= 2 here)
-__global__ __launch_bounds__(RN_BLOCK) void k_root_inverse(int n_agg, int m, int nB,
-                                                          const int32_t *__restrict__ roots,
-                                                          const double *__restrict__ B, double *__restrict__ binv,
-                                                          int32_t *__restrict__ flags,
-                                                          const int32_t *__restrict__ guard) {
+// One thread per aggregate a: the injected rows Bc[m*a + c, :] = B[m*root + c, :]
+// (c < m) and the inverse of the m x m root block of the first m candidates
+// (m <= 2 here); a zero or singular root block raises flag bit 0.
+__global__ __launch_bounds__(RN_BLOCK) void k_inject_root(int n_agg, int m, int nB,
+                                                         const int32_t *__restrict__ roots,
+                                                         const double *__restrict__ B, double *__restrict__ Bc,
+                                                         double *__restrict__ binv, int32_t *__restrict__ flags,
+                                                         const int32_t *__restrict__ guard) {
   const int a = blockIdx.x * RN_BLOCK + threadIdx.x;
   if (a >= n_agg || *guard) return;
   const int64_t r0 = (int64_t)m * roots[a];
+  for (int c = 0; c < m; ++c)
+    for (int k = 0; k < nB; ++k) Bc[((int64_t)m * a + c) * nB + k] = B[(r0 + c) * nB + k];
   if (m == 1) {
     const double b = B[r0 * nB];
     if (b == 0.0) atomicOr(flags, 1);
@@ -136,11 +130,8 @@ rn_status rn_tentative_launch(rn_ctx *ctx, int32_t n, int32_t m, const int32_t *
     RN_TRY(rn_validate(ctx, v, guard));
   }
   if (nc > 0) {
-    hipLaunchKernelGGL(k_inject_bc, dim3(rn_div_up(nc, RN_BLOCK)), dim3(RN_BLOCK), 0, ctx->stream, n_agg, m, nB,
-                       roots, B, Bc, guard);
-    LAUNCH_CHECK(ctx);
-    hipLaunchKernelGGL(k_root_inverse, dim3(rn_div_up(n_agg, RN_BLOCK)), dim3(RN_BLOCK), 0, ctx->stream, n_agg, m,
-                       nB, roots, B, binv, flags, guard);
+    hipLaunchKernelGGL(k_inject_root, dim3(rn_div_up(n_agg, RN_BLOCK)), dim3(RN_BLOCK), 0, ctx->stream, n_agg, m,
+                       nB, roots, B, Bc, binv, flags, guard);
     LAUNCH_CHECK(ctx);
   }
   if (n > 0) {

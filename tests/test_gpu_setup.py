@@ -87,3 +87,26 @@ def test_setup_wide_pattern_rows(R, ctx):
         assert CS.rel_max(host(s.tensor("P")), P_ref) <= FP64_TOL
     finally:
         s.close()
+
+
+@pytest.mark.parametrize("name", ["poisson32", "elastic7"])
+def test_singular_root_block_is_reported(R, ctx, name):
+    """A zero root value of B (m = 1), or a singular 2x2 root block of the
+    first two candidates (m = 2: both translations zeroed at one root node),
+    cannot normalise T: the tentative stage and the one-call set-up return
+    RN_ESINGULAR and keep nothing."""
+    from paper_1610_03154_amd import _lib
+    c = CS.case(name)
+    m = c["m"]
+    B = c["B"].copy()
+    r = int(c["roots"][3])
+    B[m * r:m * r + m, :m] = 0.0
+    g = run_path(R, ctx, c)
+    with pytest.raises(R.RnError) as e:
+        ctx.tentative(g["Np"], g["Nj"], g["is_root"], dev(c["agg"]), dev(c["roots"]), m, dev(B))
+    assert e.value.status == _lib.RN_ESINGULAR
+    g["plan"].close()
+    with pytest.raises(R.RnError) as e:
+        ctx.setup_native(dev_matrix(R, c), dev(B), dev(c["agg"]), dev(c["roots"]), c["theta"], c["degree"],
+                         c["iters"])
+    assert e.value.status == _lib.RN_ESINGULAR
