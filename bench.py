@@ -32,8 +32,8 @@ METRIC = "energy-min setup s & masked-SpGEMM HBM GB/s; FP32-mix vs FP64; fwd+bwd
 # runs in profiles/k_spgemm_q1aniso512_traffic.md (FETCH_SIZE and WRITE_SIZE,
 # scaled by the same counters on a copy of known size), valid for the kernel
 # sources they were taken on (sha256 prefix below); otherwise reported as null.
-TRAFFIC_BYTES = 59249850
-TRAFFIC_SRC_SHA = "8ffcdd02da9640dd"
+TRAFFIC_BYTES = 59249868
+TRAFFIC_SRC_SHA = "402451266b617fc8"
 TRAFFIC_SRCS = ("paper_1610_03154_amd/csrc/rn_spgemm.hip", "paper_1610_03154_amd/csrc/rn_plan.hip",
                 "paper_1610_03154_amd/csrc/rn_emin.h")
 HBM_PEAK_GBS = 8000.0

@@ -166,11 +166,27 @@ __global__ __launch_bounds__(RN_BLOCK) void k_plan_gram(int n, const int32_t *__
   block_to_slot<false>(bad, rank_def);  // per-block counts
 }
 
-// ---- Bc row of each pattern entry's column (block_m = 1, n_B <= 2) ----------
-__global__ __launch_bounds__(RN_BLOCK) void k_plan_bce(int64_t nnzN, int nB, const int32_t *__restrict__ Nj,
-                                                      const double *__restrict__ Bc, double *__restrict__ bce) {
-  for (int64_t e = (int64_t)blockIdx.x * RN_BLOCK + threadIdx.x; e < nnzN; e += (int64_t)gridDim.x * RN_BLOCK)
-    for (int q = 0; q < nB; ++q) bce[e * nB + q] = Bc[(int64_t)Nj[e] * nB + q];
+// ---- one element-wise launch for two per-entry tables: the Bc row of each
+// pattern entry's column (block_m = 1, n_B <= 2; bce may be NULL) and the
+// first pattern entry of each stored A entry's neighbour row (xoff) ----------
+__global__ __launch_bounds__(RN_BLOCK) void k_plan_bce_xoff(int64_t nnzN, int nB, const int32_t *__restrict__ Nj,
+                                                           const double *__restrict__ Bc, double *__restrict__ bce,
+                                                           int64_t nnzA, int m, const int32_t *__restrict__ Aj,
+                                                           const int32_t *__restrict__ Np,
+                                                           int32_t *__restrict__ xoff) {
+  const int64_t s = (int64_t)gridDim.x * RN_BLOCK, q0 = (int64_t)blockIdx.x * RN_BLOCK + threadIdx.x;
+  if (bce)
+    for (int64_t e = q0; e < nnzN; e += s)
+      for (int q = 0; q < nB; ++q) bce[e * nB + q] = Bc[(int64_t)Nj[e] * nB + q];
+  for (int64_t q = q0; q < nnzA; q += s) {
+    const int k = Aj[q];
+    if (m == 1) {
+      xoff[q] = Np[k];
+    } else {
+      xoff[2 * q] = Np[2 * k];
+      xoff[2 * q + 1] = Np[2 * k + 1];
+    }
+  }
 }
 
 // ---- block partition: rows whose first entry lies in [b*chunk, (b+1)*chunk)
@@ -211,20 +227,6 @@ __global__ __launch_bounds__(RN_BLOCK) void k_plan_blocks_rows(int nr, const int
       h[-8 + 1] = r;
       h[-8 + 3] = (int32_t)hi;
       h[-8 + 5] = a;
-    }
-  }
-}
-
-// ---- first pattern entry of each stored entry's neighbour row -------------
-__global__ __launch_bounds__(RN_BLOCK) void k_plan_xoff(int64_t nnzA, int m, const int32_t *__restrict__ Aj,
-                                                       const int32_t *__restrict__ Np, int32_t *__restrict__ xoff) {
-  for (int64_t q = (int64_t)blockIdx.x * RN_BLOCK + threadIdx.x; q < nnzA; q += (int64_t)gridDim.x * RN_BLOCK) {
-    const int k = Aj[q];
-    if (m == 1) {
-      xoff[q] = Np[k];
-    } else {
-      xoff[2 * q] = Np[2 * k];
-      xoff[2 * q + 1] = Np[2 * k + 1];
     }
   }
 }
@@ -752,20 +754,16 @@ rn_status rn_plan_create_ex(rn_ctx *ctx, const rn_matrix *A, int32_t n_cols, con
     if (!plan_alloc(pl, &pl->bce, (size_t)(nnz_N + 1) * nB * sizeof(double)))
       return fail(rn_fail(ctx, RN_ENOMEM, "rn_plan_create: device allocation"));
     pl->fixed_bytes += (size_t)(nnz_N + 1) * nB * 8;
-    if (nnz_N > 0) {
-      const unsigned g = rn_div_up(nnz_N, RN_BLOCK);
-      hipLaunchKernelGGL(k_plan_bce, dim3(g > 8192 ? 8192 : g), dim3(RN_BLOCK), 0, ctx->stream, nnz_N, nB, Nj, Bc,
-                         pl->bce);
-    }
   }
   const int32_t *rp = m == 1 ? Np : pl->nodeptr;
   hipLaunchKernelGGL(k_plan_blocks_rows, dim3(rn_div_up(nr + 1, RN_BLOCK)), dim3(RN_BLOCK), 0, ctx->stream, nr, rp,
                      A->rowptr, pl->nblk, pl->chunk, pl->blk_row, pl->blk_hdr);
   if (hipGetLastError() != hipSuccess) return fail(rn_fail(ctx, RN_EHIP, "launch"));
-  if (A->nnz > 0) {
-    unsigned g = rn_div_up(A->nnz, RN_BLOCK);
-    hipLaunchKernelGGL(k_plan_xoff, dim3(g > 8192 ? 8192 : g), dim3(RN_BLOCK), 0, ctx->stream, A->nnz, m, A->colind,
-                       Np, pl->xoff);
+  const int64_t n_bce = pl->bce ? nnz_N : 0;
+  if (A->nnz > 0 || n_bce > 0) {
+    unsigned g = rn_div_up(A->nnz > n_bce ? A->nnz : n_bce, RN_BLOCK);
+    hipLaunchKernelGGL(k_plan_bce_xoff, dim3(g > 8192 ? 8192 : g), dim3(RN_BLOCK), 0, ctx->stream, n_bce, nB, Nj, Bc,
+                       pl->bce, A->nnz, m, A->colind, Np, pl->xoff);
     if (hipGetLastError() != hipSuccess) return fail(rn_fail(ctx, RN_EHIP, "launch"));
   }
   if (pl->nblk > 0) {
