@@ -165,7 +165,10 @@ enum RnGuardBits { GUARD_A = 1, GUARD_S = 2, GUARD_N = 4, GUARD_AGG = 8, GUARD_R
 // rn_guard_begin zeroes 64 bytes: the guard word and, beside it, the stage
 // flags (so they need no reset of their own): strength asymmetry, padded
 // pattern overflow, the tentative's two flags, an entry of Bc other than 1.
-enum RnGuardSlot { GS_ASYM = 1, GS_PFLAG = 2, GS_TFLAGS = 4, GS_BCNU = 8 };
+enum RnGuardSlot { GS_ASYM = 1, GS_PFLAG = 2, GS_TFLAGS = 4, GS_BCNU = 8, GS_POW0 = 10 };
+// the pattern expansion's wide-row counters of its first GS_NPOW powers sit in
+// guard slots GS_POW0 .. GS_POW0 + GS_NPOW - 1 (zeroed with the guard)
+#define GS_NPOW 6
 int32_t *rn_guard_begin(rn_ctx *ctx, rn_status *st);
 // rows x cols CSR: rowptr[0] = 0, non-decreasing, rowptr[rows] = nnz,
 // columns in [0, cols) and strictly increasing within a row.

@@ -768,11 +768,14 @@ static rn_status pattern_padded_launch(rn_ctx *ctx, int nn, int n, int m, const 
     int32_t *Yc = (int32_t *)rn_scratch(ctx, cur ? SLOT_PAT_XP0 : SLOT_PAT_XP1, (size_t)(nn + 1) * sizeof(int32_t),
                                         &st);
     if (!Yc) return st;
-    HIP_TRY(ctx, hipMemsetAsync(ovf, 0, sizeof(int32_t), ctx->stream));
+    // wide-row counter of this power: a guard slot (already zero) for the
+    // first GS_NPOW powers, else cleared here
+    int32_t *ctr = t < GS_NPOW ? guard + GS_POW0 + t : ovf;
+    if (t >= GS_NPOW) HIP_TRY(ctx, hipMemsetAsync(ovf, 0, sizeof(int32_t), ctx->stream));
     hipLaunchKernelGGL(k_expand<EX_PAD>, dim3(g), dim3(RN_BLOCK), 0, ctx->stream, nn, Sp, Sj, X, Yc, Yv, ovf + 1,
-                       ovf, guard);
+                       ctr, guard);
     hipLaunchKernelGGL(k_expand_big<EX_PAD>, dim3(256), dim3(RN_BLOCK), 0, ctx->stream, Sp, Sj, X, Yc, Yv,
-                       ovf + 1, ovf, guard, pflag);
+                       ovf + 1, ctr, guard, pflag);
     LAUNCH_CHECK(ctx);
     X = XRows{nullptr, Yv, Yc, PCAP};
     cur ^= 1;
