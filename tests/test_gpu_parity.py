@@ -16,16 +16,12 @@ pytestmark = pytest.mark.gpu
 
 FP64_TOL = 1e-12
 MIXED_TOL = 1e-5
-# The node-blocked elasticity workload (three rigid-body candidates, one side
-# clamped) is ill-conditioned for the CG iterate: changing ONE step length by
-# one ulp in the oracle moves P by 1.4e-11 (measured on the 512 x 512 case),
-# so any two FP64 evaluations that round a single inner product differently
-# differ at that level.  Its FP64 bar is 1e-10 (about 7x that sensitivity).
-FP64_TOL_ILLCOND = 1e-10
 
 
 def fp64_tol(name):
-    return FP64_TOL_ILLCOND if name.startswith("elastic") else FP64_TOL
+    # node-blocked elasticity: two correct FP64 evaluations of the minimisation
+    # differ by up to 5e-11 (tests/test_fp64_spread.py); the bar is derived there
+    return CS.ELASTIC_FP64_TOL if name.startswith("elastic") else FP64_TOL
 
 
 @pytest.fixture(scope="module")
@@ -71,7 +67,7 @@ def run_path(R, ctx, c, precision=None):
 
 
 STRENGTH_CASES = ["laplace1d_8", "poisson32", "poisson37", "aniso40", "aniso512", "upwind64", "elastic7",
-                  "elastic512", "lap27_10", "asym20"]
+                  "elastic7_t03", "elastic32_t03", "elastic512", "lap27_10", "asym20"]
 
 
 @pytest.mark.parametrize("name", STRENGTH_CASES)
@@ -129,7 +125,7 @@ def test_masked_product(R, ctx, name, precision):
 
 
 CG_CASES = ["laplace1d_8", "poisson32", "poisson37", "aniso40", "aniso512", "twocand13", "elastic7",
-            "elastic512", "lap27_10"]
+            "elastic32_t03", "elastic512", "lap27_10"]
 
 
 @pytest.mark.parametrize("name", CG_CASES)
@@ -139,7 +135,9 @@ def test_cg_fp64(R, ctx, name):
     K = c["iters"]
     P, st, hist = ctx.energy_min(g["plan"], g["A"].vals, g["T"], R.RN_CG, K, R.RN_FP64, want_hist=True)
     P = host(P)
-    assert CS.rel_max(P, c["P"]) <= fp64_tol(name), CS.rel_max(P, c["P"])
+    err = CS.rel_max(P, c["P"])
+    print(f"{name}: FP64 max|dP|/max|P| = {err:.3e} (bar {fp64_tol(name):.0e})")
+    assert err <= fp64_tol(name), f"{name}: max|dP|/max|P| = {err:.3e} > {fp64_tol(name):.0e}"
     h = host(hist)[0]
     info = c["info"]
     assert st.iters_done == info["iters"]

@@ -88,6 +88,63 @@ def test_strength_amalgamates_blocks():
     assert np.array_equal(Sp, Ab.rowptr) and np.array_equal(Sj, Ab.colind)
 
 
+def _csr_from_dense(M):
+    r, c = np.nonzero(M)
+    rowptr = np.concatenate([[0], np.cumsum(np.bincount(r, minlength=M.shape[0]))]).astype(np.int32)
+    return rowptr, c.astype(np.int32), M[r, c].astype(np.float64)
+
+
+def test_strength_amalgamation_hand_example():
+    # Sec. 3.2, amalgamate step (reading R4: a node pair is strong when any DOF
+    # entry of its 2x2 block is), with theta = 1/2 so every test is exact:
+    # keep |a_ij| >= theta sqrt|a_ii a_jj|.  Nodes 0, 1, 2 hold DOFs (0,1),
+    # (2,3), (4,5); DOF diagonals 4, 1, 4, 1, 4, 1.
+    #   block (0,1): a_02 = -1.5 (2.25 < 4: weak), a_03 = -1 (1 >= 1: strong,
+    #                a tie), a_12 = -0.5 (0.25 < 1: weak)       -> strong
+    #   block (0,2): a_04 = -1.9 (3.61 < 4), a_05 = -0.9 (0.81 < 1),
+    #                a_15 = -0.4 (0.16 < 0.25)                   -> weak
+    #   block (1,2): a_24 = -0.5 (0.25 < 4: weak); a_35 = -0.5 (0.25 >= 0.25:
+    #                strong) but a_53 = -0.4 (0.16 < 0.25: weak), so only the
+    #                symmetrisation S u S^T puts (2,1) in S        -> strong
+    # AND over the block, the (0,0) component alone, or no symmetrisation each
+    # give a different graph.
+    M = np.zeros((6, 6))
+    np.fill_diagonal(M, [4, 1, 4, 1, 4, 1])
+    M[0, 1] = M[1, 0] = -0.1
+    for (i, j, v) in [(0, 2, -1.5), (0, 3, -1.0), (1, 2, -0.5), (0, 4, -1.9), (0, 5, -0.9), (1, 5, -0.4),
+                      (2, 4, -0.5)]:
+        M[i, j] = M[j, i] = v
+    M[3, 5], M[5, 3] = -0.5, -0.4
+    Ap, Aj, Ax = _csr_from_dense(M)
+    Sp, Sj = O.strength(Ap, Aj, Ax, 2, 0.5)
+    got = {(I, int(J)) for I in range(3) for J in Sj[Sp[I]:Sp[I + 1]]}
+    assert got == {(0, 0), (0, 1), (1, 0), (1, 1), (1, 2), (2, 1), (2, 2)}
+
+
+@pytest.mark.parametrize("theta", [0.1, 0.3])
+def test_strength_amalgamation_brute_force(theta):
+    # node-blocked elasticity at theta > 0, where the blocks mix strong and weak
+    # DOF entries: the node graph is "any entry of the block strong", then
+    # symmetrised, then the diagonal; written out here with dense boolean arrays
+    Ab, _ = W.q1_elasticity(7)
+    A = Ab.to_csr()
+    Ad = A.to_dense()
+    d = np.diag(Ad)
+    strong = (Ad != 0) & (Ad * Ad >= theta * theta * np.abs(np.outer(d, d)))
+    nn = A.n_rows // 2
+    node = strong.reshape(nn, 2, nn, 2).any(axis=(1, 3))
+    node = node | node.T | np.eye(nn, dtype=bool)
+    Sp, Sj = O.strength(A.rowptr, A.colind, A.vals, 2, theta)
+    want_p = np.concatenate([[0], np.cumsum(node.sum(1))])
+    assert np.array_equal(Sp, want_p)
+    assert np.array_equal(Sj, np.nonzero(node)[1])
+    # the case discriminates: requiring every stored entry of a block to be
+    # strong drops blocks that the rule keeps
+    stored = (Ad != 0).reshape(nn, 2, nn, 2).any(axis=(1, 3))
+    every = ((strong | (Ad == 0)).reshape(nn, 2, nn, 2).all(axis=(1, 3))) & stored
+    assert (node & ~(every | every.T | np.eye(nn, dtype=bool))).any()
+
+
 # ----------------------------------------------------------------------------
 # aggregation (Sec. 3.3) against the worked examples
 # ----------------------------------------------------------------------------
@@ -473,3 +530,41 @@ def test_cg_jvp_matches_central_differences():
     fd = (run(A.vals + h * v) - run(A.vals - h * v)) / (2 * h)
     assert np.linalg.norm(fd - dP) <= 1e-6 * np.linalg.norm(dP)
     assert np.array_equal(P, run(A.vals))
+
+
+# ----------------------------------------------------------------------------
+# metrics: constraint residual (Eq. mode_constraint) and energy
+# ----------------------------------------------------------------------------
+def test_constraint_residual_hand_example():
+    # three rows over two coarse columns, two candidates, Bc = [[1, 2], [1, 1]];
+    # row 1 is a root row (the identity row of column 1).  The exact P below
+    # satisfies P Bc = B; each perturbation's residual is worked out by hand.
+    Np = np.array([0, 2, 3, 5], np.int32)
+    Nj = np.array([0, 1, 1, 0, 1], np.int32)
+    Bc = np.array([[1.0, 2.0], [1.0, 1.0]])
+    P = np.array([0.5, 0.25, 1.0, 0.25, 0.5])
+    B = np.array([[0.75, 1.25], [1.0, 1.0], [0.75, 1.0]])
+    assert O.constraint_residual(Np, Nj, P, Bc, B) == 0.0
+    # F row 0 loses 0.3 at column 1 -> deviations (-0.3, -0.3); the root row
+    # drops from 1 to 0.3 -> deviations (-0.7, -0.7): only negative
+    # deviations, the largest on a root row
+    Q = P.copy()
+    Q[1] -= 0.3
+    Q[2] = 0.3
+    assert math.isclose(O.constraint_residual(Np, Nj, Q, Bc, B), 0.7, rel_tol=0, abs_tol=1e-15)
+    # row 2 gains 0.1 at column 0 -> deviations (0.1 * 1, 0.1 * 2): the second
+    # candidate decides
+    Q = P.copy()
+    Q[3] += 0.1
+    assert math.isclose(O.constraint_residual(Np, Nj, Q, Bc, B), 0.2, rel_tol=0, abs_tol=1e-15)
+
+
+def test_energy_is_trace_of_galerkin_product():
+    # E(P) = trace(P^T A P) over the pattern, against a dense evaluation
+    A = W.q1_aniso(9, 0.1, 0.7)
+    st = _setup(A, W.ones(A.n_rows), 1, 0.1, 2)
+    rng = np.random.default_rng(3)
+    P = rng.standard_normal(st["Nj"].size)
+    Pd = brute.to_dense(st["Np"], st["Nj"], P, st["nc"])
+    e = O.energy(A.rowptr, A.colind, A.vals, st["Np"], st["Nj"], st["nc"], P)
+    assert math.isclose(e, float(np.trace(Pd.T @ A.to_dense() @ Pd)), rel_tol=1e-12)
