@@ -92,10 +92,48 @@ typedef struct {
 /* Create a context bound to hip_stream (a hipStream_t; NULL = the null
  * stream) on the current device.  The context owns grow-only scratch. */
 rn_status rn_create(rn_ctx **ctx, void *hip_stream);
-/* Free all scratch owned by the context.  Plans made on it must be
- * destroyed first. */
+/* Free all device memory owned by the context, including that of plans and
+ * tapes made on it that are still alive (their destroy calls then free only
+ * the host object; such a plan or tape can no longer be used).  Set-ups
+ * (rn_setup) made on it must be destroyed first. */
 void rn_destroy(rn_ctx *ctx);
 rn_status rn_set_stream(rn_ctx *ctx, void *hip_stream);
+/* Device memory from the caller's allocator (for instance a framework's
+ * caching allocator), for everything the context allocates: scratch, plans,
+ * tapes, set-up results.  alloc(bytes, user) returns a device pointer usable
+ * by work queued on the context's stream, or NULL (then RN_ENOMEM); release(
+ * ptr, user) gives a block back while work queued before the call on that
+ * stream may still read it (the allocator must order its reuse after that
+ * work, as a stream-ordered caching allocator does).  Both NULL: hipMalloc /
+ * hipFree with the context's own cache (the default).  RN_EINVAL when exactly
+ * one is NULL, or when the context already holds device memory (set the
+ * allocator before the first call that allocates).  The pinned host area used
+ * to read results back is not device memory and still comes from HIP. */
+rn_status rn_set_allocator(rn_ctx *ctx, void *(*alloc)(size_t bytes, void *user),
+                           void (*release)(void *ptr, void *user), void *user);
+/* Alternative kernel paths.  Every value computes the same result to the
+ * stated tolerances; the options exist so that each path can be tested and
+ * timed.  RN_EINVAL for an unknown option or value. */
+typedef enum {
+  /* 1 (default): products of plans for scalar operators with nB <= 2, at
+   * most 11 A entries per row and pattern rows of at most 31 entries run as
+   * persistent pipelined workgroups; 0: one workgroup per product block.
+   * Read when a plan is made. */
+  RN_OPT_PERSISTENT_PRODUCT = 0,
+  /* 1 (default): the pattern expansion keeps each power in padded rows of 64
+   * columns (no host round trip between powers; rows that outgrow it are
+   * redone with exact CSR powers); 0: exact CSR powers throughout. */
+  RN_OPT_PADDED_PATTERN = 1,
+  /* 1 (default): rn_setup runs strength and the first phase of the pattern
+   * with one synchronisation when A is structurally symmetric; 0: it chains
+   * the two-phase stage calls. */
+  RN_OPT_FUSED_SETUP = 2,
+  /* 256 (default), 128 or 64: lanes (pattern entries) per product block for
+   * plans of scalar operators whose pattern rows hold at most lanes/4
+   * entries (other plans use 256).  Read when a plan is made. */
+  RN_OPT_PRODUCT_LANES = 3
+} rn_option;
+rn_status rn_set_option(rn_ctx *ctx, rn_option opt, int32_t value);
 /* Message of the last failure on ctx ("" if none).  Valid until the next
  * call on ctx. */
 const char *rn_last_error(const rn_ctx *ctx);
@@ -180,6 +218,8 @@ rn_status rn_plan_create(rn_ctx *ctx, const rn_matrix *A, int32_t n_cols,
                          const int32_t *N_rowptr, const int32_t *N_colind,
                          int64_t nnz_N, const uint8_t *is_root,
                          const double *Bc, int32_t nB, rn_plan **plan);
+/* Destroying a plan queues no wait: its memory is reused only by work queued
+ * after the call on the context's stream. */
 void rn_plan_destroy(rn_plan *plan);
 /* Bytes of device memory held by the plan (codes, Gram data, workspace). */
 size_t rn_plan_bytes(const rn_plan *plan);

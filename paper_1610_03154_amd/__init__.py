@@ -67,6 +67,10 @@ def _ptr(t):
     return C.c_void_p(0 if t is None else t.data_ptr())
 
 
+def torch_device(torch):
+    return torch.cuda.current_device()
+
+
 @dataclass
 class DeviceCSR:
     """Device matrix: block_m = 1 scalar CSR, block_m = 2 node-blocked BSR."""
@@ -233,6 +237,9 @@ class Context:
             for p in list(_LIVE_PLANS):
                 if p.ctx is self:
                     p.close()
+            for t in list(_LIVE_TAPES):
+                if t.plan.ctx is self:
+                    t.close()
             L.lib().rn_destroy(self.h)
             self.h = None
 
@@ -247,6 +254,36 @@ class Context:
     def _check(self, st, what):
         if st != L.RN_OK:
             raise RnError(st, f"{what}: {L.lib().rn_last_error(self.h).decode()}")
+
+    def set_option(self, opt: int, value: int):
+        """rn_set_option: select one of the alternative kernel paths."""
+        self._check(L.lib().rn_set_option(self.h, int(opt), int(value)), "rn_set_option")
+
+    def use_torch_allocator(self, on_alloc=None, on_release=None):
+        """rn_set_allocator with torch's caching allocator on this context's
+        stream: every device buffer the library allocates then comes from
+        torch.  on_alloc(bytes) / on_release() (optional) observe the calls.
+        Must come before the first call that allocates."""
+        torch, dev, stream = self.torch, torch_device(self.torch), self.stream
+
+        def alloc(nbytes, user):
+            try:
+                p = torch.cuda.caching_allocator_alloc(int(nbytes), dev, stream)
+            except Exception:  # out of memory: the library reports RN_ENOMEM
+                return None
+            if on_alloc is not None:
+                on_alloc(int(nbytes))
+            return p
+
+        def release(ptr, user):
+            torch.cuda.caching_allocator_delete(ptr)
+            if on_release is not None:
+                on_release()
+
+        cbs = (L.ALLOC_FN(alloc), L.RELEASE_FN(release))
+        self._check(L.lib().rn_set_allocator(self.h, C.cast(cbs[0], C.c_void_p), C.cast(cbs[1], C.c_void_p),
+                                             None), "rn_set_allocator")
+        self._alloc_cbs = cbs  # the library holds these function pointers
 
     # -- a1/a2 ---------------------------------------------------------------
     def strength(self, A: DeviceCSR, theta: float):

@@ -14,6 +14,10 @@ LIB_PATH = os.path.join(HERE, "librnamg.so")
 RN_OK, RN_EINVAL, RN_ENOMEM, RN_ESINGULAR, RN_EBREAKDOWN, RN_ENONFINITE, RN_EHIP, RN_ELIMIT = range(8)
 RN_CG, RN_GMRES = 0, 1
 RN_FP64, RN_FP32_MIXED = 0, 1
+RN_OPT_PERSISTENT_PRODUCT, RN_OPT_PADDED_PATTERN, RN_OPT_FUSED_SETUP, RN_OPT_PRODUCT_LANES = range(4)
+# rn_set_allocator callbacks: void *alloc(size_t bytes, void *user); void release(void *ptr, void *user)
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+RELEASE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
 STATUS_NAMES = {0: "RN_OK", 1: "RN_EINVAL", 2: "RN_ENOMEM", 3: "RN_ESINGULAR", 4: "RN_EBREAKDOWN",
                 5: "RN_ENONFINITE", 6: "RN_EHIP", 7: "RN_ELIMIT"}
 
@@ -47,6 +51,8 @@ SIGNATURES = {
     "rn_create": (_i32, [C.POINTER(C.c_void_p), _vp]),
     "rn_destroy": (None, [_vp]),
     "rn_set_stream": (_i32, [_vp, _vp]),
+    "rn_set_allocator": (_i32, [_vp, _vp, _vp, _vp]),
+    "rn_set_option": (_i32, [_vp, _i32, _i32]),
     "rn_last_error": (C.c_char_p, [_vp]),
     "rn_version": (C.c_char_p, []),
     "rn_strength": (_i32, [_vp, C.POINTER(rn_matrix), _d, _vp, _vp, _pi64]),

@@ -27,10 +27,12 @@
 // recorded D_k (the tape keeps R_k and D_k of every step).
 #include <cstring>
 #include <new>
+#include <type_traits>
 
 #include "rn_emin.h"
 
 struct rn_tape {
+  rn_ctx *ctx = nullptr;  // owner of the device memory (NULL once released)
   const rn_plan *pl = nullptr;
   int32_t batch = 0, K = 0, scal_stride = 0;
   int64_t nz = 0, nzb = 0;
@@ -54,13 +56,33 @@ static unsigned adj_grid(int64_t n) {
   return (unsigned)g;
 }
 
+// The tape's device memory back to its context (stream-ordered reuse: work
+// queued on the context's stream that still reads it runs first).
+void rn_tape_release(rn_tape *t) {
+  if (!t->ctx) return;
+  void **bufs[] = {(void **)&t->R,  (void **)&t->D,  (void **)&t->T,  (void **)&t->scal, (void **)&t->st,
+                   (void **)&t->Rb, (void **)&t->Db, (void **)&t->Zk, (void **)&t->Yb,   (void **)&t->Yh,
+                   (void **)&t->gbar, (void **)&t->part, (void **)&t->ATv};
+  for (void **b : bufs) {
+    rn_dev_free(t->ctx, *b);
+    *b = nullptr;
+  }
+  t->ctx = nullptr;
+  t->recorded = false;
+}
+
 extern "C" void rn_tape_destroy(rn_tape *tape) {
   if (!tape) return;
-  (void)hipDeviceSynchronize();  // the tape may still be read by queued work
-  void *bufs[] = {tape->R, tape->D, tape->T, tape->scal, tape->st, tape->Rb, tape->Db,
-                  tape->Zk, tape->Yb, tape->Yh, tape->gbar, tape->part, tape->ATv};
-  for (void *b : bufs)
-    if (b) (void)hipFree(b);
+  if (tape->ctx) {  // (a tape whose context was destroyed first holds no device memory)
+    auto &v = tape->ctx->tapes;
+    for (size_t q = 0; q < v.size(); ++q)
+      if (v[q] == tape) {
+        v[q] = v.back();
+        v.pop_back();
+        break;
+      }
+    rn_tape_release(tape);
+  }
   delete tape;
 }
 
@@ -73,6 +95,13 @@ extern "C" rn_status rn_tape_create(rn_ctx *ctx, rn_plan *pl, int32_t batch, int
   if (pl->m != 1) return rn_fail(ctx, RN_EINVAL, "rn_tape_create: the adjoint takes scalar CSR operators (block_m = 1)");
   rn_tape *t = new (std::nothrow) rn_tape();
   if (!t) return rn_fail(ctx, RN_ENOMEM, "rn_tape_create: host allocation");
+  try {
+    ctx->tapes.push_back(t);
+  } catch (...) {
+    delete t;
+    return rn_fail(ctx, RN_ENOMEM, "rn_tape_create: host allocation");
+  }
+  t->ctx = ctx;
   t->pl = pl;
   t->batch = batch;
   t->K = iters;
@@ -82,16 +111,16 @@ extern "C" rn_status rn_tape_create(rn_ctx *ctx, rn_plan *pl, int32_t batch, int
   t->scal_stride = CgLayout(iters).total;
   const size_t v = (size_t)(t->nzb + 1) * 8;
   const size_t slots = (size_t)(iters + 1) * v;
-  bool ok = hipMalloc(&t->R, slots) == hipSuccess && hipMalloc(&t->D, slots) == hipSuccess &&
-            hipMalloc(&t->T, (size_t)(t->nz + 1) * 8) == hipSuccess &&
-            hipMalloc(&t->scal, (size_t)batch * t->scal_stride * 8) == hipSuccess &&
-            hipMalloc(&t->st, (size_t)batch * ST_STRIDE * 4) == hipSuccess &&
-            hipMalloc(&t->Rb, v) == hipSuccess && hipMalloc(&t->Db, v) == hipSuccess &&
-            hipMalloc(&t->Zk, v) == hipSuccess && hipMalloc(&t->Yb, v) == hipSuccess &&
-            hipMalloc(&t->Yh, v) == hipSuccess &&
-            hipMalloc(&t->gbar, (size_t)batch * (iters + 1) * 8) == hipSuccess &&
-            hipMalloc(&t->part, (size_t)batch * RN_MAXDOT * (adj_grid(t->nz) + 2) * 8) == hipSuccess &&
-            hipMalloc(&t->ATv, (size_t)batch * (pl->nnzA + 1) * 8) == hipSuccess;
+  auto get = [&](auto **p, size_t bytes) {
+    *p = (std::remove_reference_t<decltype(**p)> *)rn_dev_alloc(ctx, bytes);
+    return *p != nullptr;
+  };
+  bool ok = get(&t->R, slots) && get(&t->D, slots) && get(&t->T, (size_t)(t->nz + 1) * 8) &&
+            get(&t->scal, (size_t)batch * t->scal_stride * 8) && get(&t->st, (size_t)batch * ST_STRIDE * 4) &&
+            get(&t->Rb, v) && get(&t->Db, v) && get(&t->Zk, v) && get(&t->Yb, v) && get(&t->Yh, v) &&
+            get(&t->gbar, (size_t)batch * (iters + 1) * 8) &&
+            get(&t->part, (size_t)batch * RN_MAXDOT * (adj_grid(t->nz) + 2) * 8) &&
+            get(&t->ATv, (size_t)batch * (pl->nnzA + 1) * 8);
   if (!ok) {
     rn_tape_destroy(t);
     return rn_fail(ctx, RN_ENOMEM, "rn_tape_create: device allocation (%zu bytes of iterates)", 2 * slots);
@@ -104,6 +133,7 @@ rn_status rn_tape_record_begin(rn_ctx *ctx, rn_plan *pl, rn_tape *tape, int32_t 
                                rn_method method, rn_precision prec, const double *T) {
   if (method != RN_CG || prec != RN_FP64)
     return rn_fail(ctx, RN_EINVAL, "rn_energy_min: a tape records the FP64 CG form only");
+  if (!tape->ctx) return rn_fail(ctx, RN_EINVAL, "rn_energy_min: the tape's context was destroyed");
   if (tape->pl != pl || tape->batch != batch || tape->K != iters)
     return rn_fail(ctx, RN_EINVAL, "rn_energy_min: tape made for another plan, batch or iteration count");
   tape->recorded = false;

@@ -31,6 +31,12 @@ static void cache_release(rn_ctx *ctx, size_t keep) {
 void *rn_dev_alloc(rn_ctx *ctx, size_t bytes) {
   bytes = bytes == 0 ? 256 : (bytes + 255) & ~(size_t)255;
   try {
+    if (ctx->alloc_fn) {
+      void *p = ctx->alloc_fn(bytes, ctx->alloc_user);
+      if (!p) return nullptr;
+      ctx->live[p] = bytes;
+      return p;
+    }
     // the smallest cached block that fits and wastes at most half of itself
     int best = -1;
     for (int i = 0; i < (int)ctx->cache.size(); ++i) {
@@ -72,6 +78,11 @@ void rn_dev_free(rn_ctx *ctx, void *p) {
     (void)hipFree(p);
     return;
   }
+  if (ctx->free_fn) {  // stream-ordered reuse is the caller's allocator's business
+    ctx->live.erase(it);
+    ctx->free_fn(p, ctx->alloc_user);
+    return;
+  }
   try {
     ctx->cache.push_back({p, it->second});
     ctx->cached_bytes += it->second;
@@ -91,14 +102,23 @@ void *rn_scratch(rn_ctx *ctx, int slot, size_t bytes, rn_status *st) {
   if (bytes == 0) bytes = 16;
   if (s.cap >= bytes) return s.ptr;
   if (s.ptr) {
-    (void)hipStreamSynchronize(ctx->stream);
-    (void)hipFree(s.ptr);
+    if (ctx->free_fn) {
+      ctx->free_fn(s.ptr, ctx->alloc_user);
+    } else {
+      (void)hipStreamSynchronize(ctx->stream);
+      (void)hipFree(s.ptr);
+    }
     s.ptr = nullptr;
     s.cap = 0;
   }
   size_t cap = bytes + bytes / 4 + 256;
-  if (hipMalloc(&s.ptr, cap) != hipSuccess) {
+  if (ctx->alloc_fn) {
+    s.ptr = ctx->alloc_fn(cap, ctx->alloc_user);
+  } else if (hipMalloc(&s.ptr, cap) != hipSuccess) {
+    (void)hipGetLastError();
     s.ptr = nullptr;
+  }
+  if (!s.ptr) {
     *st = rn_fail(ctx, RN_ENOMEM, "scratch allocation of %zu bytes failed", cap);
     return nullptr;
   }
@@ -425,18 +445,59 @@ extern "C" rn_status rn_create(rn_ctx **out, void *stream) {
   return RN_OK;
 }
 
-void rn_plan_detach(rn_plan *pl);
-
 extern "C" void rn_destroy(rn_ctx *ctx) {
   if (!ctx) return;
   (void)hipStreamSynchronize(ctx->stream);
-  for (rn_plan *pl : ctx->plans) rn_plan_detach(pl);
+  // plans and tapes still alive give their device memory back now
+  for (rn_plan *pl : ctx->plans) rn_plan_release(pl);
   ctx->plans.clear();
+  for (rn_tape *t : ctx->tapes) rn_tape_release(t);
+  ctx->tapes.clear();
   cache_release(ctx, 0);
   for (int s = 0; s < SLOT_COUNT; ++s)
-    if (ctx->slot[s].ptr) (void)hipFree(ctx->slot[s].ptr);
+    if (ctx->slot[s].ptr) {
+      if (ctx->free_fn) ctx->free_fn(ctx->slot[s].ptr, ctx->alloc_user);
+      else (void)hipFree(ctx->slot[s].ptr);
+    }
   if (ctx->rb_host) (void)hipHostFree(ctx->rb_host);
   delete ctx;
+}
+
+extern "C" rn_status rn_set_allocator(rn_ctx *ctx, void *(*alloc)(size_t bytes, void *user),
+                                      void (*release)(void *ptr, void *user), void *user) {
+  if (!ctx) return RN_EINVAL;
+  ctx->err.clear();
+  if ((alloc == nullptr) != (release == nullptr))
+    return rn_fail(ctx, RN_EINVAL, "rn_set_allocator: give both functions or neither");
+  bool holds = !ctx->live.empty() || !ctx->cache.empty();
+  for (int s = 0; s < SLOT_COUNT; ++s) holds = holds || ctx->slot[s].ptr != nullptr;
+  if (holds)
+    return rn_fail(ctx, RN_EINVAL, "rn_set_allocator: the context already holds device memory (set the allocator "
+                                   "before the first call that allocates)");
+  ctx->alloc_fn = alloc;
+  ctx->free_fn = release;
+  ctx->alloc_user = user;
+  return RN_OK;
+}
+
+extern "C" rn_status rn_set_option(rn_ctx *ctx, rn_option opt, int32_t value) {
+  if (!ctx) return RN_EINVAL;
+  ctx->err.clear();
+  switch (opt) {
+    case RN_OPT_PERSISTENT_PRODUCT:
+    case RN_OPT_PADDED_PATTERN:
+    case RN_OPT_FUSED_SETUP:
+      if (value != 0 && value != 1) return rn_fail(ctx, RN_EINVAL, "rn_set_option: value must be 0 or 1");
+      break;
+    case RN_OPT_PRODUCT_LANES:
+      if (value != 64 && value != 128 && value != 256)
+        return rn_fail(ctx, RN_EINVAL, "rn_set_option: product lanes must be 64, 128 or 256");
+      break;
+    default:
+      return rn_fail(ctx, RN_EINVAL, "rn_set_option: unknown option %d", (int)opt);
+  }
+  ctx->opt[opt] = value;
+  return RN_OK;
 }
 
 extern "C" rn_status rn_set_stream(rn_ctx *ctx, void *stream) {

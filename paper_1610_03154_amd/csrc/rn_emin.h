@@ -105,7 +105,8 @@ struct rn_plan {
   bool unit_bc = false;         // block_m = 1 and every entry of Bc is 1
   double *gp = nullptr;         // packed Gram pseudo-inverse per DOF row
   int32_t rank_def = 0, maxlen = 0, chunk = 1, nblk = 0;
-  int32_t bs = RN_BLOCK;        // lanes per product block (block_m = 1: 128 or 256)
+  int32_t bs = RN_BLOCK;        // lanes per product block (block_m = 1: 64, 128 or 256)
+  bool persist = true;          // the persistent product may serve this plan
   unsigned long long *d_terms = nullptr;  // multiply-add terms of one product
   size_t fixed_bytes = 0;
   RnScratch ws[WS_COUNT];
@@ -119,6 +120,7 @@ struct SpgParams {
   int32_t accum;  // MODE_PRODUCT: Z += result instead of Z = result
   int32_t kact;   // >= 0: batch entries whose st[ST_ITERS] <= kact do nothing
   int32_t unit_bc;  // every entry of Bc is 1: the projection's Bc rows are 1 (no per-entry loads)
+  int32_t persist;  // the persistent product may serve the launch
   int64_t nnzN, strideA, strideX, strideZ;
   const int32_t *Ap, *Aj, *Np, *Nj, *nodeptr, *ncol, *blk_row, *blk_hdr, *xoff, *xl, *xwin;
   const uint8_t *codes, *is_root;

@@ -62,10 +62,20 @@ struct XRows {
   int stride;
 };
 
+// Context options (rn_set_option), indexed by rn_option.
+#define RN_OPT_COUNT 4
+
 struct rn_ctx {
   hipStream_t stream = nullptr;
   int device = 0;
   std::string err;
+  int32_t opt[RN_OPT_COUNT] = {1, 1, 1, RN_BLOCK};
+  // device allocator of the caller (rn_set_allocator); NULL: hipMalloc/hipFree
+  void *(*alloc_fn)(size_t, void *) = nullptr;
+  void (*free_fn)(void *, void *) = nullptr;
+  void *alloc_user = nullptr;
+  // live tapes made on this context (rn_destroy releases their device memory)
+  std::vector<rn_tape *> tapes;
   RnScratch slot[SLOT_COUNT];
   // read-back area (rn_fetch): host-coherent pinned memory the device writes
   // directly (rb_dev = its device address, NULL when it cannot be mapped)
@@ -118,8 +128,14 @@ rn_status rn_fail(rn_ctx *ctx, rn_status st, const char *fmt, ...);
 // ordered by the context's stream (a block is handed out again only to work
 // queued after the work that used it).  rn_dev_free with ctx = NULL frees
 // the block outright.  rn_dev_alloc returns NULL when the device is full.
+// With a caller's allocator (rn_set_allocator) blocks come from it and go
+// straight back to it (it does its own caching).
 void *rn_dev_alloc(rn_ctx *ctx, size_t bytes);
 void rn_dev_free(rn_ctx *ctx, void *p);
+// Device memory of a plan or tape goes back to its context when the context is
+// destroyed first (the later destroy call then frees only the host object).
+void rn_plan_release(rn_plan *pl);
+void rn_tape_release(rn_tape *tape);
 
 // Read-back of small device values at a synchronisation point: n <= 6 items
 // (device address, size in bytes, both multiples of 4) copied by one kernel

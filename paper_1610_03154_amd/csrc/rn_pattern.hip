@@ -739,14 +739,8 @@ __global__ __launch_bounds__(RN_BLOCK) void k_dof_fill(int n, int m, const XRows
   }
 }
 
-// padded levels unless RNAMG_PATTERN_PAD=0
-static bool pattern_pad_on() {
-  static const int on = [] {
-    const char *e = getenv("RNAMG_PATTERN_PAD");
-    return (e && e[0] == '0') ? 0 : 1;
-  }();
-  return on != 0;
-}
+// padded levels unless the context's RN_OPT_PADDED_PATTERN is 0
+static bool pattern_pad_on(const rn_ctx *ctx) { return ctx->opt[RN_OPT_PADDED_PATTERN] != 0; }
 
 // Expansion with padded levels (no host round trip between levels), then the
 // DOF row sizes and their scan into Np, queued on guard; *pflag_out
@@ -863,7 +857,7 @@ extern "C" rn_status rn_pattern(rn_ctx *ctx, int32_t nn, const int32_t *Sp, cons
     RN_TRY(rn_validate(ctx, v, guard));
   }
   int64_t total = 0;
-  if ((int64_t)nn * PCAP < ((int64_t)1 << 31) && pattern_pad_on()) {
+  if ((int64_t)nn * PCAP < ((int64_t)1 << 31) && pattern_pad_on(ctx)) {
     bool ok = false;
     RN_TRY(pattern_padded(ctx, nn, n, m, Sp, Sj, agg, roots, n_agg, degree, Np, is_root, cnt, ovf, guard, &total,
                           &ok));
@@ -960,7 +954,7 @@ rn_status rn_strength_pattern(rn_ctx *ctx, const rn_matrix *A, double theta, int
   if (A->nnz >= ((int64_t)1 << 31)) return rn_fail(ctx, RN_ELIMIT, "rn_strength: nnz >= 2^31");
   const int nn = A->n / m, n = A->n;
   if (n_agg < 0 || degree < 0) return rn_fail(ctx, RN_EINVAL, "rn_pattern: bad size");
-  if ((int64_t)nn * PCAP >= ((int64_t)1 << 31) || !pattern_pad_on()) return RN_OK;
+  if ((int64_t)nn * PCAP >= ((int64_t)1 << 31) || !pattern_pad_on(ctx)) return RN_OK;
   rn_status st = RN_OK;
   int32_t *cnt = (int32_t *)rn_scratch(ctx, SLOT_PAT_CNT, (size_t)(n + 1) * sizeof(int32_t), &st);
   int32_t *ovf = (int32_t *)rn_scratch(ctx, SLOT_PAT_OVF, (size_t)(nn + 2) * sizeof(int32_t), &st);

@@ -726,11 +726,11 @@ rn_status rn_plan_create_ex(rn_ctx *ctx, const rn_matrix *A, int32_t n_cols, con
   // product blocks: every block holds at most 256 entries (node entries for
   // block_m = 2): rows starting in a chunk of 257 - maxlen entries
   const int ml = pl->maxlen < 1 ? 1 : pl->maxlen;
-  pl->bs = RN_BLOCK;
-  if (const char *ev = getenv("RNAMG_PRODUCT_BS")) {  // 64- and 128-lane blocks for scalar operators
-    const int v = atoi(ev);
-    pl->bs = (m == 1 && (v == 64 || v == 128) && ml <= v / 4) ? v : RN_BLOCK;
-  }
+  // 64- and 128-lane blocks for scalar operators with short pattern rows
+  // (RN_OPT_PRODUCT_LANES)
+  const int lanes = ctx->opt[RN_OPT_PRODUCT_LANES];
+  pl->bs = (m == 1 && (lanes == 64 || lanes == 128) && ml <= lanes / 4) ? lanes : RN_BLOCK;
+  pl->persist = ctx->opt[RN_OPT_PERSISTENT_PRODUCT] != 0;
   pl->chunk = pl->bs + 1 - ml;
   pl->nblk = (int)((pl->nnzN_node + pl->chunk - 1) / pl->chunk);
   if ((m == 2 && !plan_alloc(pl, &pl->ncol, (size_t)(pl->nnzN_node + 1) * sizeof(int32_t))) ||
@@ -811,11 +811,28 @@ rn_status rn_plan_create_ex(rn_ctx *ctx, const rn_matrix *A, int32_t n_cols, con
   return RN_OK;
 }
 
-void rn_plan_detach(rn_plan *pl) { pl->ctx = nullptr; }
+// The plan's device memory back to its context (stream-ordered reuse, no
+// wait); the plan keeps only its host object.
+void rn_plan_release(rn_plan *pl) {
+  if (!pl->ctx) return;
+  void **bufs[] = {(void **)&pl->codes,   (void **)&pl->ncol,    (void **)&pl->nodeptr, (void **)&pl->gp,
+                   (void **)&pl->d_terms, (void **)&pl->blk_row, (void **)&pl->blk_hdr, (void **)&pl->xoff,
+                   (void **)&pl->xl,      (void **)&pl->xwin,    (void **)&pl->bce,     (void **)&pl->ccodes};
+  for (void **b : bufs) {
+    rn_dev_free(pl->ctx, *b);
+    *b = nullptr;
+  }
+  for (int s = 0; s < WS_COUNT; ++s) {
+    rn_dev_free(pl->ctx, pl->ws[s].ptr);
+    pl->ws[s].ptr = nullptr;
+    pl->ws[s].cap = 0;
+  }
+  pl->ctx = nullptr;
+}
 
 extern "C" void rn_plan_destroy(rn_plan *pl) {
   if (!pl) return;
-  if (pl->ctx) {  // buffers go back to the context's cache: reuse is stream-ordered, no wait
+  if (pl->ctx) {  // (a plan whose context was destroyed first holds no device memory)
     auto &v = pl->ctx->plans;
     for (size_t q = 0; q < v.size(); ++q)
       if (v[q] == pl) {
@@ -823,13 +840,8 @@ extern "C" void rn_plan_destroy(rn_plan *pl) {
         v.pop_back();
         break;
       }
-  } else {
-    (void)hipDeviceSynchronize();  // its context is gone: wait for any work still reading the plan
+    rn_plan_release(pl);
   }
-  void *bufs[] = {pl->codes,   pl->ncol,    pl->nodeptr, pl->gp, pl->d_terms,
-                  pl->blk_row, pl->blk_hdr, pl->xoff,    pl->xl, pl->xwin, pl->bce, pl->ccodes};
-  for (void *b : bufs) rn_dev_free(pl->ctx, b);
-  for (int s = 0; s < WS_COUNT; ++s) rn_dev_free(pl->ctx, pl->ws[s].ptr);
   delete pl;
 }
 

@@ -74,8 +74,7 @@ extern "C" rn_status rn_setup(rn_ctx *ctx, const rn_matrix *A, const int32_t *ag
   if (!Sp || !Sj || !Np || !is_root) return nomem();
   int64_t nnzS = 0, nnzN = 0;
   bool done = false;
-  const char *fe = getenv("RNAMG_SETUP_FUSE");  // 0: the stage calls only
-  if (!(fe && fe[0] == '0') &&
+  if (ctx->opt[RN_OPT_FUSED_SETUP] &&  // 0: the stage calls only
       (st = rn_strength_pattern(ctx, A, theta, Sp, Sj, agg, roots, n_agg, degree, Np, is_root, &nnzS, &nnzN,
                                 &done)) != RN_OK)
     return fail(st);

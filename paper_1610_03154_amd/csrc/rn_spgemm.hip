@@ -929,22 +929,14 @@ static int launch_p(const SpgParams &p, int batch, bool mixed, hipStream_t s) {
   return G;
 }
 
-// the persistent form serves scalar operators with n_B <= 2 and records of at
-// most 12 bytes (RNAMG_PERSIST=0 turns it off)
-static bool persist_on() {
-  static const int on = [] {
-    const char *e = getenv("RNAMG_PERSIST");
-    return (e && e[0] == '0') ? 0 : 1;
-  }();
-  return on != 0;
-}
-
 // the number of per-workgroup partials a single-dot mode leaves
 template <int M, int NB, int MODE>
 static int launch_m(const SpgParams &p, int batch, bool mixed, hipStream_t s) {
   if constexpr (M == 1 && NB <= 2) {
+    // the persistent form serves scalar operators with n_B <= 2 and compact
+    // records, unless the plan was made with RN_OPT_PERSISTENT_PRODUCT = 0
     // (the branch-free first round reads 32 elements of X and one of A whatever the block)
-    if (p.ccodes && p.nnzN >= 64 && p.strideA >= 1 && persist_on()) {
+    if (p.ccodes && p.nnzN >= 64 && p.strideA >= 1 && p.persist) {
       int G = 0;
       if (p.bs == 128 && (G = launch_p<NB, MODE, 128>(p, batch, mixed, s)) > 0) return G;
       if (p.bs == RN_BLOCK && (G = launch_p<NB, MODE, RN_BLOCK>(p, batch, mixed, s)) > 0) return G;
@@ -1036,5 +1028,6 @@ SpgParams rn_spg_params(const rn_plan *pl) {
   p.strideX = pl->nnzN;
   p.strideA = pl->nnzA * pl->m * pl->m;
   p.unit_bc = pl->unit_bc ? 1 : 0;
+  p.persist = pl->persist ? 1 : 0;
   return p;
 }

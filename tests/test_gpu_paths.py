@@ -4,12 +4,10 @@ The persistent product for scalar operators stages each product block's
 A slice, X window and projection data in LDS; blocks whose neighbour rows do
 not form a window read X from global memory, and blocks with more A entries
 than the LDS capacity read A from global memory too.  These cases make each
-path carry whole launches, plus batches with per-entry values and the
-128-lane block size.  Same bars as test_gpu_parity: FP64 1e-12, FP32-mixed
+path carry whole launches, plus batches with per-entry values.  (The
+selectable block sizes and paths are in test_gpu_options.)  Same bars as test_gpu_parity: FP64 1e-12, FP32-mixed
 1e-5 relative to max|ref|.
 """
-import os
-
 import numpy as np
 import pytest
 
@@ -94,26 +92,6 @@ def test_blocks_beyond_lds_capacity(R, ctx):
     assert np.max(np.abs(Zp[~root_e])) <= 1e-12 * scale
     plan.close()
     del O
-
-
-def test_128_lane_blocks(R, ctx):
-    """Plans built with 128-lane product blocks (RNAMG_PRODUCT_BS=128)."""
-    c = CS.case("aniso40")
-    old = os.environ.get("RNAMG_PRODUCT_BS")
-    os.environ["RNAMG_PRODUCT_BS"] = "128"
-    try:
-        g = run_path(R, ctx, c)
-    finally:
-        if old is None:
-            del os.environ["RNAMG_PRODUCT_BS"]
-        else:
-            os.environ["RNAMG_PRODUCT_BS"] = old
-    X = np.random.default_rng(6).standard_normal(c["Nj"].size)
-    _, refp, _ = _product_refs(c["A"], c["Np"], c["Nj"], c["nc"], c["is_root"], c["Bc"], 1, X)
-    Zp = host(ctx.masked_product(g["plan"], g["A"].vals, dev(X), project=True))
-    assert np.max(np.abs(Zp - refp)) <= FP64_TOL * np.max(np.abs(refp))
-    P, st, _ = ctx.energy_min(g["plan"], g["A"].vals, g["T"], R.RN_CG, c["iters"], R.RN_FP64)
-    assert CS.rel_max(host(P), c["P"]) <= FP64_TOL
 
 
 def _banded(n, hb):
