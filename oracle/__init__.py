@@ -35,6 +35,8 @@ def lib():
             _build.build()
         L = C.CDLL(_build.LIB)
         i, d, vp = C.c_int, C.c_double, C.c_void_p
+        L.orc_set_threads.argtypes = [i]
+        L.orc_threads.restype = i
         L.orc_strength.argtypes = [i, _i32p, _i32p, _f64p, i, d, _i32p, _i32p, i]
         L.orc_aggregate.argtypes = [i, _i32p, _i32p, _i32p, _i32p]
         L.orc_pattern_nodes.argtypes = [i, _i32p, _i32p, _i32p, i, i, _i32p, _i32p, i]
@@ -65,6 +67,15 @@ def _i32(a):
 
 def _f64(a):
     return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's row and entry loops (results do not depend on it)."""
+    lib().orc_set_threads(int(n))
+
+
+def threads() -> int:
+    return int(lib().orc_threads())
 
 
 def strength(Ap, Aj, Ax, m, theta):

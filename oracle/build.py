@@ -11,7 +11,7 @@ LIB = os.path.join(HERE, "liboracle.so")
 
 
 def build(verbose: bool = False) -> str:
-    cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
+    cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
            "-fPIC", "-shared", "-Wall", "-Wextra", "-Wno-unused-parameter",
            os.path.join(HERE, "oracle.c"), "-o", LIB + ".tmp", "-lm"]
     if verbose:

@@ -11,8 +11,31 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define NBMAX 8
+
+/* Threads: the loops over rows and over entries that are independent run
+ * under OpenMP with a static schedule; every sum is split into fixed chunks
+ * whose boundaries do not depend on the thread count, so results are
+ * identical for any number of threads. */
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+  omp_set_num_threads(n > 0 ? n : 1);
+#else
+  (void)n;
+#endif
+}
+
+int orc_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
 
 /* ------------------------------------------------------------------------ */
 /* small helpers                                                             */
@@ -30,14 +53,32 @@ static int cmp_int(const void *a, const void *b) {
  * 10^6 terms carries a relative error of ~1e-12 into P, which is larger than
  * the FP64 parity tolerance, while the compensated sum is accurate to a few
  * units in the last place whatever the length. */
+#define DOT_CHUNK 4096
+/* add v to the compensated pair (s, c) (Neumaier) */
+static void comp_add(double *s, double *c, double v) {
+  const double t = *s + v;
+  *c += (fabs(*s) >= fabs(v)) ? (*s - t) + v : (v - t) + *s;
+  *s = t;
+}
+/* Chunks of DOT_CHUNK terms are summed on their own, then the chunk sums (and
+ * their corrections) in chunk order. */
 static double dot(long len, const double *x, const double *y) {
-  double s = 0.0, c = 0.0;
-  for (long p = 0; p < len; ++p) {
-    const double v = x[p] * y[p];
-    const double t = s + v;
-    c += (fabs(s) >= fabs(v)) ? (s - t) + v : (v - t) + s;
-    s = t;
+  const long nch = (len + DOT_CHUNK - 1) / DOT_CHUNK;
+  double *cs = (double *)malloc((size_t)(nch > 0 ? nch : 1) * 2 * sizeof(double));
+#pragma omp parallel for schedule(static)
+  for (long ch = 0; ch < nch; ++ch) {
+    double s = 0.0, c = 0.0;
+    const long e = (ch + 1) * DOT_CHUNK < len ? (ch + 1) * DOT_CHUNK : len;
+    for (long p = ch * DOT_CHUNK; p < e; ++p) comp_add(&s, &c, x[p] * y[p]);
+    cs[2 * ch] = s;
+    cs[2 * ch + 1] = c;
   }
+  double s = 0.0, c = 0.0;
+  for (long ch = 0; ch < nch; ++ch) {
+    comp_add(&s, &c, cs[2 * ch]);
+    c += cs[2 * ch + 1];
+  }
+  free(cs);
   return s + c;
 }
 
@@ -406,14 +447,18 @@ int orc_gram_rows(int n, const int *Np, const int *Nj,
                   double *Gp) {
   int bad = 0, maxlen = 1;
   for (int i = 0; i < n; ++i) maxlen = Np[i + 1] - Np[i] > maxlen ? Np[i + 1] - Np[i] : maxlen;
-  double *W = (double *)malloc((size_t)maxlen * (nB > 0 ? nB : 1) * sizeof(double));
-  for (int i = 0; i < n; ++i) {
-    double *gi = Gp + (long)i * nB * nB;
-    for (int q = 0; q < nB * nB; ++q) gi[q] = 0.0;
-    if (is_root[i] || nB == 0) continue;
-    bad += row_pinv(Np[i + 1] - Np[i], Nj + Np[i], Bc, nB, W, gi);
+#pragma omp parallel reduction(+ : bad)
+  {
+    double *W = (double *)malloc((size_t)maxlen * (nB > 0 ? nB : 1) * sizeof(double));
+#pragma omp for schedule(static)
+    for (int i = 0; i < n; ++i) {
+      double *gi = Gp + (long)i * nB * nB;
+      for (int q = 0; q < nB * nB; ++q) gi[q] = 0.0;
+      if (is_root[i] || nB == 0) continue;
+      bad += row_pinv(Np[i + 1] - Np[i], Nj + Np[i], Bc, nB, W, gi);
+    }
+    free(W);
   }
-  free(W);
   return bad;
 }
 
@@ -425,8 +470,9 @@ int orc_gram_rows(int n, const int *Np, const int *Nj,
 void orc_project(int n, const int *Np, const int *Nj,
                  const unsigned char *is_root, const double *Bc, int nB,
                  const double *Gp, double *X) {
-  double s[NBMAX], y[NBMAX];
+#pragma omp parallel for schedule(static)
   for (int i = 0; i < n; ++i) {
+    double s[NBMAX], y[NBMAX];
     if (is_root[i]) {
       for (int p = Np[i]; p < Np[i + 1]; ++p) X[p] = 0.0;
       continue;
@@ -456,19 +502,23 @@ void orc_project(int n, const int *Np, const int *Nj,
 void orc_masked_product(int n, int nc, const int *Ap, const int *Aj,
                         const double *Ax, const int *Np, const int *Nj,
                         const double *X, double *Z) {
-  double *acc = (double *)calloc((size_t)(nc > 0 ? nc : 1), sizeof(double));
-  for (int i = 0; i < n; ++i) {
-    for (int t = Ap[i]; t < Ap[i + 1]; ++t) {
-      int k = Aj[t];
-      for (int q = Np[k]; q < Np[k + 1]; ++q) acc[Nj[q]] += Ax[t] * X[q];
+#pragma omp parallel
+  {
+    double *acc = (double *)calloc((size_t)(nc > 0 ? nc : 1), sizeof(double));
+#pragma omp for schedule(static)
+    for (int i = 0; i < n; ++i) {
+      for (int t = Ap[i]; t < Ap[i + 1]; ++t) {
+        int k = Aj[t];
+        for (int q = Np[k]; q < Np[k + 1]; ++q) acc[Nj[q]] += Ax[t] * X[q];
+      }
+      for (int p = Np[i]; p < Np[i + 1]; ++p) Z[p] = acc[Nj[p]];
+      for (int t = Ap[i]; t < Ap[i + 1]; ++t) {
+        int k = Aj[t];
+        for (int q = Np[k]; q < Np[k + 1]; ++q) acc[Nj[q]] = 0.0;
+      }
     }
-    for (int p = Np[i]; p < Np[i + 1]; ++p) Z[p] = acc[Nj[p]];
-    for (int t = Ap[i]; t < Ap[i + 1]; ++t) {
-      int k = Aj[t];
-      for (int q = Np[k]; q < Np[k + 1]; ++q) acc[Nj[q]] = 0.0;
-    }
+    free(acc);
   }
-  free(acc);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -608,13 +658,17 @@ int orc_emin_cg(int n, int nc, const int *Ap, const int *Aj, const double *Ax,
     if (dl <= 0.0) { rc = ORC_EBREAKDOWN; break; }
     double al = g / dl;
     if (alp) alp[k] = al;
-    for (long p = 0; p < nz; ++p) P[p] += al * D[p];
-    for (long p = 0; p < nz; ++p) R[p] -= al * Z[p];
+#pragma omp parallel for schedule(static)
+    for (long p = 0; p < nz; ++p) {
+      P[p] += al * D[p];
+      R[p] -= al * Z[p];
+    }
     double gn = dot(nz, R, R);
     if (gam) gam[k + 1] = gn;
     if (!isfinite(gn)) { rc = ORC_ENONFINITE; break; }
     double be = gn / g;
     g = gn;
+#pragma omp parallel for schedule(static)
     for (long p = 0; p < nz; ++p) D[p] = R[p] + be * D[p];
     ++it;
   }
@@ -728,7 +782,9 @@ int orc_emin_gmres(int n, int nc, const int *Ap, const int *Aj,
       for (int j = 0; j <= k; ++j) {
         double h = dot(nz, W, V[j]);
         HH(j, k) = h;
-        for (long p = 0; p < nz; ++p) W[p] -= h * V[j][p];
+        const double *Vj = V[j];
+#pragma omp parallel for schedule(static)
+        for (long p = 0; p < nz; ++p) W[p] -= h * Vj[p];
       }
       double hn = sqrt(dot(nz, W, W));
       if (!isfinite(hn)) { rc = ORC_ENONFINITE; break; }
@@ -751,7 +807,9 @@ int orc_emin_gmres(int n, int nc, const int *Ap, const int *Aj,
       kd = k + 1;
       /* invariant Krylov space, or converged to round-off */
       if (hn == 0.0 || fabs(gv[k + 1]) <= GM_STOP * beta) break;
-      for (long p = 0; p < nz; ++p) V[k + 1][p] = W[p] / hn;
+      double *Vn = V[k + 1];
+#pragma omp parallel for schedule(static)
+      for (long p = 0; p < nz; ++p) Vn[p] = W[p] / hn;
     }
     if (rc == ORC_OK) {
       double *y = (double *)calloc((size_t)(kd > 0 ? kd : 1), sizeof(double));
@@ -760,8 +818,11 @@ int orc_emin_gmres(int n, int nc, const int *Ap, const int *Aj,
         for (int l = j + 1; l < kd; ++l) s -= HH(j, l) * y[l];
         y[j] = s / HH(j, j);
       }
-      for (int j = 0; j < kd; ++j)
-        for (long p = 0; p < nz; ++p) P[p] += y[j] * V[j][p];
+      for (int j = 0; j < kd; ++j) {
+        const double yj = y[j], *Vj = V[j];
+#pragma omp parallel for schedule(static)
+        for (long p = 0; p < nz; ++p) P[p] += yj * Vj[p];
+      }
       free(y);
     }
   }

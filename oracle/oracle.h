@@ -19,6 +19,7 @@
  *   orc_tentative, orc_gram_pinv, orc_project, orc_masked_product,
  *   orc_emin_cg, orc_emin_gmres, orc_transpose, orc_energy,
  *   orc_constraint_residual, orc_emin_cg_jvp            -- pinned.
+ *   orc_set_threads, orc_threads: thread control, no arithmetic.
  */
 #ifndef RN_ORACLE_H
 #define RN_ORACLE_H
@@ -33,6 +34,11 @@ extern "C" {
 #define ORC_EBREAKDOWN -3 /* CG curvature <D, Pi(A D)> <= 0                */
 #define ORC_ENONFINITE -4 /* NaN or Inf in a Krylov scalar                 */
 #define ORC_EINVAL    -5  /* malformed input                               */
+
+/* Threads of the loops over rows and entries (OpenMP); the results do not
+ * depend on the number (fixed summation chunks). */
+void orc_set_threads(int n);
+int orc_threads(void);
 
 /* Symmetric strength of connection (Sec. 3.2, Alg. root_node_setup strength
  * and amalgamate steps).  Keeps (i,i) and stored (i,j) with

@@ -568,3 +568,26 @@ def test_energy_is_trace_of_galerkin_product():
     Pd = brute.to_dense(st["Np"], st["Nj"], P, st["nc"])
     e = O.energy(A.rowptr, A.colind, A.vals, st["Np"], st["Nj"], st["nc"], P)
     assert math.isclose(e, float(np.trace(Pd.T @ A.to_dense() @ Pd)), rel_tol=1e-12)
+
+
+# ----------------------------------------------------------------------------
+# threads: the oracle's results do not depend on the number of threads
+# ----------------------------------------------------------------------------
+def test_results_identical_across_thread_counts():
+    A = W.q1_aniso(96)
+    st = _setup(A, W.ones(A.n_rows), 1, 0.1, 2)
+    Au = W.upwind_cd(64)
+    su = _setup(Au, W.ones(Au.n_rows), 1, 0.0, 2)
+    n0 = O.threads()
+    out = []
+    try:
+        for t in (1, 3, 8):
+            O.set_threads(t)
+            P, info = _cg(A, st, 6)
+            Q, qinfo = _gmres(Au, su, 8)
+            out.append((P, info["gamma"], Q, qinfo["resid"]))
+    finally:
+        O.set_threads(n0)
+    for r in out[1:]:
+        for a, b in zip(out[0], r):
+            assert np.array_equal(a, b)
