@@ -258,6 +258,31 @@ rn_status rn_energy_min(rn_ctx *ctx, rn_plan *plan, const double *A_vals,
                         int32_t iters, rn_precision precision, double *P,
                         double *hist, rn_emin_stats *stats, rn_tape *tape);
 
+/* ---- the same minimisation without allocation ---------------------------
+ * For callers that cannot allocate device memory during the call (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation).  Same arguments, results and errors as rn_energy_min without
+ * a tape; the Krylov vectors, scalars, partial sums and FP32 copies live in
+ * one library-owned device array of RN_NOALLOC_SCRATCH_BYTES per GPU
+ * (reserved when the library's code is loaded, held until the process ends)
+ * instead of the plan's workspace.  The call allocates nothing: no hipMalloc,
+ * no hipFree, no caller allocator, no pinned host memory (the read-back area
+ * is reserved by rn_create).  RN_ELIMIT, before any launch, when the call
+ * needs more than that array: CG needs about (3 + 1.5 [FP32-mixed]) x 8 x
+ * batch x nnz_N bytes plus 520 x (product blocks + 1026) x batch, GMRES
+ * (iters + 1) x (8 [+ 4]) x batch x nnz_N plus the same partials.  Every call
+ * on one GPU, from any context, shares that GPU's array, and each call
+ * overwrites it (its state is set at the start of the call): calls that
+ * overlap in time on one GPU race and give wrong results.  RN_EHIP when
+ * the array's device address could not be obtained when ctx was created. */
+#define RN_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+rn_status rn_energy_min_noalloc(rn_ctx *ctx, rn_plan *plan,
+                                const double *A_vals, int32_t batch,
+                                const double *T, rn_method method,
+                                int32_t iters, rn_precision precision,
+                                double *P, double *hist,
+                                rn_emin_stats *stats);
+
 /* ---- a12: adjoint of the CG energy minimisation (map A values -> P) -----
  * Tape for `batch` problems of `iters` CG steps on `plan`; holds the Krylov
  * scalars and the iterates R_k, D_k of every step (checkpoint interval 1;

@@ -390,6 +390,18 @@ class Context:
                     "rn_energy_min")
         return P, stats, hist
 
+    def energy_min_noalloc(self, plan: Plan, A_vals, T, P, method=RN_CG, iters=4, precision=RN_FP64,
+                           batch=None, hist=None):
+        """rn_energy_min_noalloc: the minimisation into the caller's P (and
+        hist) without any device allocation inside the call."""
+        if batch is None:
+            batch = 1 if A_vals.dim() == 1 else A_vals.shape[0]
+        stats = L.rn_emin_stats()
+        self._check(L.lib().rn_energy_min_noalloc(self.h, plan.handle, _ptr(A_vals), batch, _ptr(T), method, iters,
+                                                  precision, _ptr(P), _ptr(hist), C.byref(stats)),
+                    "rn_energy_min_noalloc")
+        return stats
+
     # -- a12 -----------------------------------------------------------------
     def tape(self, plan: Plan, batch: int, iters: int) -> Tape:
         h = C.c_void_p()

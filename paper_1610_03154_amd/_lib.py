@@ -18,6 +18,8 @@ RN_OPT_PERSISTENT_PRODUCT, RN_OPT_PADDED_PATTERN, RN_OPT_FUSED_SETUP, RN_OPT_PRO
 # rn_set_allocator callbacks: void *alloc(size_t bytes, void *user); void release(void *ptr, void *user)
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
 RELEASE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+# bytes of the allocation-free entry point's scratch array per GPU
+NOALLOC_SCRATCH_BYTES = 64 << 20
 STATUS_NAMES = {0: "RN_OK", 1: "RN_EINVAL", 2: "RN_ENOMEM", 3: "RN_ESINGULAR", 4: "RN_EBREAKDOWN",
                 5: "RN_ENONFINITE", 6: "RN_EHIP", 7: "RN_ELIMIT"}
 
@@ -67,6 +69,8 @@ SIGNATURES = {
     "rn_masked_product": (_i32, [_vp, _vp, _vp, _i32, _vp, _i32, _i32, _vp]),
     "rn_energy_min": (_i32, [_vp, _vp, _vp, _i32, _vp, _i32, _i32, _i32, _vp, _vp,
                              C.POINTER(rn_emin_stats), _vp]),
+    "rn_energy_min_noalloc": (_i32, [_vp, _vp, _vp, _i32, _vp, _i32, _i32, _i32, _vp, _vp,
+                                     C.POINTER(rn_emin_stats)]),
     "rn_tape_create": (_i32, [_vp, _vp, _i32, _i32, C.POINTER(C.c_void_p)]),
     "rn_tape_destroy": (None, [_vp]),
     "rn_energy_min_bwd": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),

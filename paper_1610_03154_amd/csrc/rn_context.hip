@@ -3,6 +3,7 @@
 
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 rn_status rn_fail(rn_ctx *ctx, rn_status st, const char *fmt, ...) {
@@ -126,6 +127,31 @@ void *rn_scratch(rn_ctx *ctx, int slot, size_t bytes, rn_status *st) {
   return s.ptr;
 }
 
+// (Re)allocate the pinned read-back area with room for cap bytes.
+static rn_status readback_reserve(rn_ctx *ctx, size_t cap) {
+  if (ctx->rb_host) {
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    (void)hipHostFree(ctx->rb_host);
+    ctx->rb_host = nullptr;
+    ctx->rb_dev = nullptr;
+    ctx->rb_cap = 0;
+  }
+  if (cap < 4096) cap = 4096;
+  if (hipHostMalloc((void **)&ctx->rb_host, cap, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
+    (void)hipGetLastError();
+    ctx->rb_host = nullptr;
+    return rn_fail(ctx, RN_ENOMEM, "rn_fetch: pinned read-back area of %zu bytes", cap);
+  }
+  ctx->rb_cap = cap;
+  void *d = nullptr;
+  if (hipHostGetDevicePointer(&d, ctx->rb_host, 0) != hipSuccess) {
+    (void)hipGetLastError();
+    d = nullptr;
+  }
+  ctx->rb_dev = d;
+  return RN_OK;
+}
+
 struct FetchArgs {
   const uint32_t *src[RN_FETCH_MAX];
   int32_t words[RN_FETCH_MAX];
@@ -147,28 +173,7 @@ rn_status rn_fetch(rn_ctx *ctx, int n, const RnFetch *items, const unsigned char
     off[i] = total;
     total += (items[i].bytes + 7) & ~(size_t)7;
   }
-  if (total > ctx->rb_cap) {
-    if (ctx->rb_host) {
-      HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-      (void)hipHostFree(ctx->rb_host);
-      ctx->rb_host = nullptr;
-      ctx->rb_dev = nullptr;
-      ctx->rb_cap = 0;
-    }
-    const size_t cap = total < 4096 ? 4096 : total + total / 2;
-    if (hipHostMalloc((void **)&ctx->rb_host, cap, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
-      (void)hipGetLastError();
-      ctx->rb_host = nullptr;
-      return rn_fail(ctx, RN_ENOMEM, "rn_fetch: pinned read-back area of %zu bytes", cap);
-    }
-    ctx->rb_cap = cap;
-    void *d = nullptr;
-    if (hipHostGetDevicePointer(&d, ctx->rb_host, 0) != hipSuccess) {
-      (void)hipGetLastError();
-      d = nullptr;
-    }
-    ctx->rb_dev = d;
-  }
+  if (total > ctx->rb_cap) RN_TRY(readback_reserve(ctx, total + total / 2));
   if (ctx->rb_dev) {
     FetchArgs a{};
     a.n = n;
@@ -431,6 +436,33 @@ rn_status rn_transpose_structure(rn_ctx *ctx, int32_t rows, int32_t cols, int64_
 // ---------------------------------------------------------------------------
 // public: context
 // ---------------------------------------------------------------------------
+// The scratch array of the allocation-free entry point (rn_energy_min_noalloc).
+// In host code `scratch` names a host-side stand-in, not device memory: its
+// device address on each GPU comes from hipGetSymbolAddress, looked up once
+// per device (the first rn_create with that device current) and kept below.
+static __device__ __align__(256) unsigned char scratch[RN_NOALLOC_SCRATCH_BYTES];
+
+#define RN_MAX_DEVICES 64
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[RN_MAX_DEVICES];
+static bool g_scratch_tried[RN_MAX_DEVICES];
+
+static void *noalloc_scratch_lookup(int device) {
+  if (device < 0 || device >= RN_MAX_DEVICES) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_tried[device]) {
+    g_scratch_tried[device] = true;
+    void *ptr = nullptr;
+    if (hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch)) == hipSuccess) {
+      g_scratch_ptr[device] = ptr;
+    } else {
+      (void)hipGetLastError();
+      g_scratch_ptr[device] = nullptr;
+    }
+  }
+  return g_scratch_ptr[device];
+}
+
 extern "C" rn_status rn_create(rn_ctx **out, void *stream) {
   if (!out) return RN_EINVAL;
   *out = nullptr;
@@ -441,6 +473,11 @@ extern "C" rn_status rn_create(rn_ctx **out, void *stream) {
     delete ctx;
     return RN_EHIP;
   }
+  // set-up for the allocation-free entry point: this device's scratch array
+  // and a read-back area large enough that it never has to grow there (a
+  // failure here only disables that entry point)
+  ctx->noalloc_scratch = noalloc_scratch_lookup(ctx->device);
+  if (readback_reserve(ctx, RN_READBACK_RESERVE) != RN_OK) ctx->err.clear();
   *out = ctx;
   return RN_OK;
 }

@@ -110,6 +110,10 @@ struct rn_plan {
   unsigned long long *d_terms = nullptr;  // multiply-add terms of one product
   size_t fixed_bytes = 0;
   RnScratch ws[WS_COUNT];
+  // While set, workspace requests are carved from this caller-provided area
+  // (the allocation-free scratch array) instead of the slots above.
+  unsigned char *arena = nullptr;
+  size_t arena_cap = 0, arena_used = 0;
 };
 
 void *rn_plan_ws(rn_plan *pl, int slot, size_t bytes, rn_status *st);

@@ -506,18 +506,93 @@ extern "C" rn_status rn_masked_product(rn_ctx *ctx, rn_plan *pl, const double *A
   return rn_launch_spgemm(ctx, pl, MODE_PRODUCT, p, batch, mixed);
 }
 
-extern "C" rn_status rn_energy_min(rn_ctx *ctx, rn_plan *pl, const double *A_vals, int32_t batch, const double *T,
-                                   rn_method method, int32_t iters, rn_precision prec, double *P, double *hist,
-                                   rn_emin_stats *stats, rn_tape *tape) {
-  if (!ctx) return RN_EINVAL;
-  ctx->err.clear();
+// Arguments of rn_energy_min checked on the host.
+static rn_status emin_check(rn_ctx *ctx, rn_plan *pl, const double *A_vals, int32_t batch, const double *T,
+                            rn_method method, int32_t iters, rn_precision prec, double *P) {
   if (!pl || !A_vals || !T || !P || batch < 1 || iters < 0)
     return rn_fail(ctx, RN_EINVAL, "rn_energy_min: bad argument");
   if (method != RN_CG && method != RN_GMRES) return rn_fail(ctx, RN_EINVAL, "rn_energy_min: bad method");
   if (prec != RN_FP64 && prec != RN_FP32_MIXED) return rn_fail(ctx, RN_EINVAL, "rn_energy_min: bad precision");
   if (method == RN_GMRES && iters > RN_MAXDOT - 1)
     return rn_fail(ctx, RN_ELIMIT, "rn_energy_min: GMRES supports at most %d iterations", RN_MAXDOT - 1);
+  return RN_OK;
+}
+
+static rn_status emin_run(rn_ctx *ctx, rn_plan *pl, const double *A_vals, int32_t batch, const double *T,
+                          rn_method method, int32_t iters, rn_precision prec, double *P, double *hist,
+                          rn_emin_stats *stats, rn_tape *tape);
+
+extern "C" rn_status rn_energy_min(rn_ctx *ctx, rn_plan *pl, const double *A_vals, int32_t batch, const double *T,
+                                   rn_method method, int32_t iters, rn_precision prec, double *P, double *hist,
+                                   rn_emin_stats *stats, rn_tape *tape) {
+  if (!ctx) return RN_EINVAL;
+  ctx->err.clear();
+  RN_TRY(emin_check(ctx, pl, A_vals, batch, T, method, iters, prec, P));
   if (tape) RN_TRY(rn_tape_record_begin(ctx, pl, tape, batch, iters, method, prec, T));
+  return emin_run(ctx, pl, A_vals, batch, T, method, iters, prec, P, hist, stats, tape);
+}
+
+// Workspace bytes emin_run requests (each piece rounded to 256 bytes, as the
+// arena carves them), and the bytes of its one read-back.
+static size_t emin_ws_need(const rn_plan *pl, int32_t batch, bool gm, int K, bool mixed, size_t *fetch) {
+  auto r = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  const int64_t nz = pl->nnzN, nzb = (int64_t)batch * nz;
+  const unsigned gew = gm ? ew_grid(nz) : std::min(ew_grid(nz), 1024u);
+  const int scal_stride = gm ? GmLayout(K).total : CgLayout(K).total;
+  const SpgParams p = rn_spg_params(pl);
+  size_t need = r((size_t)batch * ST_STRIDE * 4) + r((size_t)batch * scal_stride * 8) +
+                r((size_t)batch * RN_MAXDOT * ((size_t)pl->nblk + gew + 2) * 8);
+  if (mixed) need += r((size_t)batch * p.strideA * 4) + r((size_t)nz * 4);
+  if (!gm) {
+    need += 3 * r((size_t)nzb * 8) + (mixed ? r((size_t)nzb * 4) : 0);
+  } else {
+    const size_t ub = (size_t)(K + 1) * nz;
+    need += r((size_t)batch * ub * 8) + (mixed ? r((size_t)batch * ub * 4) : 0);
+  }
+  auto a8 = [](size_t b) { return (b + 7) & ~(size_t)7; };
+  *fetch = a8((size_t)batch * ST_STRIDE * 4) + a8((size_t)scal_stride * 8) + 8;
+  return need;
+}
+
+extern "C" rn_status rn_energy_min_noalloc(rn_ctx *ctx, rn_plan *pl, const double *A_vals, int32_t batch,
+                                           const double *T, rn_method method, int32_t iters, rn_precision prec,
+                                           double *P, double *hist, rn_emin_stats *stats) {
+  if (!ctx) return RN_EINVAL;
+  ctx->err.clear();
+  RN_TRY(emin_check(ctx, pl, A_vals, batch, T, method, iters, prec, P));
+  if (!ctx->noalloc_scratch)
+    return rn_fail(ctx, RN_EHIP, "rn_energy_min_noalloc: no device address for the scratch array on device %d",
+                   ctx->device);
+  if (!ctx->rb_host) return rn_fail(ctx, RN_ENOMEM, "rn_energy_min_noalloc: no read-back area");
+  size_t fetch = 0;
+  const size_t need = emin_ws_need(pl, batch, method == RN_GMRES, iters, prec == RN_FP32_MIXED, &fetch);
+  if (need > RN_NOALLOC_SCRATCH_BYTES)
+    return rn_fail(ctx, RN_ELIMIT,
+                   "rn_energy_min_noalloc: the call needs %zu bytes of scratch, the allocation-free limit is %zu",
+                   need, (size_t)RN_NOALLOC_SCRATCH_BYTES);
+  if (fetch > ctx->rb_cap)
+    return rn_fail(ctx, RN_ELIMIT, "rn_energy_min_noalloc: read-back of %zu bytes beyond the reserved %zu", fetch,
+                   ctx->rb_cap);
+  // the plan's workspace requests are carved from the scratch array for the
+  // duration of this call
+  struct ArenaScope {
+    rn_plan *pl;
+    ArenaScope(rn_plan *p, void *base) : pl(p) {
+      pl->arena = (unsigned char *)base;
+      pl->arena_cap = RN_NOALLOC_SCRATCH_BYTES;
+      pl->arena_used = 0;
+    }
+    ~ArenaScope() {
+      pl->arena = nullptr;
+      pl->arena_cap = pl->arena_used = 0;
+    }
+  } scope(pl, ctx->noalloc_scratch);
+  return emin_run(ctx, pl, A_vals, batch, T, method, iters, prec, P, hist, stats, nullptr);
+}
+
+static rn_status emin_run(rn_ctx *ctx, rn_plan *pl, const double *A_vals, int32_t batch, const double *T,
+                          rn_method method, int32_t iters, rn_precision prec, double *P, double *hist,
+                          rn_emin_stats *stats, rn_tape *tape) {
   const bool mixed = prec == RN_FP32_MIXED;
   const bool gm = method == RN_GMRES;
   const int K = iters;

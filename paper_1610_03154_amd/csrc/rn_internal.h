@@ -74,6 +74,9 @@ struct rn_ctx {
   void *(*alloc_fn)(size_t, void *) = nullptr;
   void (*free_fn)(void *, void *) = nullptr;
   void *alloc_user = nullptr;
+  // device address of this GPU's allocation-free scratch array (looked up by
+  // rn_create; NULL when the lookup failed)
+  void *noalloc_scratch = nullptr;
   // live tapes made on this context (rn_destroy releases their device memory)
   std::vector<rn_tape *> tapes;
   RnScratch slot[SLOT_COUNT];
@@ -102,6 +105,10 @@ struct rn_ctx {
   std::unordered_map<void *, size_t> live;   // blocks handed out
   size_t cached_bytes = 0;
 };
+
+// Bytes of the pinned read-back area rn_create reserves (rn_fetch grows it
+// on demand; the allocation-free entry point must fit in it).
+#define RN_READBACK_RESERVE ((size_t)64 << 10)
 
 // Error helpers -------------------------------------------------------------
 rn_status rn_fail(rn_ctx *ctx, rn_status st, const char *fmt, ...);

@@ -11,6 +11,15 @@
 void *rn_plan_ws(rn_plan *pl, int slot, size_t bytes, rn_status *st) {
   RnScratch &s = pl->ws[slot];
   if (bytes == 0) bytes = 16;
+  if (pl->arena) {  // allocation-free call: consecutive 256-byte aligned pieces of the arena
+    const size_t off = (pl->arena_used + 255) & ~(size_t)255;
+    if (off > pl->arena_cap || bytes > pl->arena_cap - off) {
+      *st = rn_fail(pl->ctx, RN_ELIMIT, "workspace of %zu bytes beyond the allocation-free scratch", bytes);
+      return nullptr;
+    }
+    pl->arena_used = off + bytes;
+    return pl->arena + off;
+  }
   if (s.cap >= bytes) return s.ptr;
   if (!pl->ctx) {
     *st = RN_EINVAL;
