@@ -57,6 +57,9 @@ def lib():
         L.orc_energy.restype = d
         L.orc_constraint_residual.argtypes = [i, _i32p, _i32p, _f64p, _f64p, _f64p, i]
         L.orc_constraint_residual.restype = d
+        L.orc_enforce.argtypes = [i, _i32p, _i32p, _u8p, _f64p, i, _f64p, _f64p]
+        L.orc_filter.argtypes = [i, i, _i32p, _i32p, _f64p, vp, _i32p, i, d, _u8p]
+        L.orc_compact.argtypes = [i, _i32p, _i32p, vp, _u8p, _i32p, _i32p, vp]
         _lib = L
     return _lib
 
@@ -251,3 +254,54 @@ def setup(A, B, m=1, theta=0.0, degree=2, agg=None, roots=None):
     T, Bc, rd = tentative(Np, Nj, is_root, agg, roots, m, B)
     return dict(Sp=Sp, Sj=Sj, agg=agg, roots=roots, Npn=Npn, Njn=Njn, Np=Np, Nj=Nj,
                 is_root=is_root, T=T, Bc=Bc, nc=m * roots.size, rank_def=rd)
+
+
+def enforce(Np, Nj, is_root, Bc, B, V):
+    """Eq. Tproj on every F row of a copy of V: (values, rank-deficient rows)."""
+    B = _f64(B)
+    V = _f64(V).copy()
+    rc = lib().orc_enforce(Np.size - 1, _i32(Np), _i32(Nj), np.ascontiguousarray(is_root, np.uint8),
+                           _f64(Bc).ravel(), B.shape[1], B.ravel(), V)
+    if rc < 0:
+        raise OracleError(rc, "enforce")
+    return V, rc
+
+
+def filter_keep(Np, Nj, G, agg, m=1, k=0, theta=0.0, is_root=None):
+    """Alg. filter on node blocks: the keep mask of every stored entry."""
+    Np, Nj = _i32(Np), _i32(Nj)
+    keep = np.zeros(max(int(Np[-1]), 1), np.uint8)
+    ir = None if is_root is None else np.ascontiguousarray(is_root, np.uint8)
+    rc = lib().orc_filter(Np.size - 1, int(m), Np, Nj, _f64(G), None if ir is None else ir.ctypes.data,
+                          _i32(agg), int(k), float(theta), keep)
+    if rc < 0:
+        raise OracleError(rc, "filter")
+    return keep[:int(Np[-1])].astype(bool)
+
+
+def compact(Np, Nj, keep, V=None):
+    """(Np2, Nj2, V2) of the kept entries."""
+    Np, Nj = _i32(Np), _i32(Nj)
+    kp = np.ascontiguousarray(keep, np.uint8)
+    Np2 = np.zeros(Np.size, np.int32)
+    Nj2 = np.zeros(max(int(kp.sum()), 1), np.int32)
+    V2 = np.zeros(max(int(kp.sum()), 1)) if V is not None else None
+    Vin = None if V is None else _f64(V)
+    w = lib().orc_compact(Np.size - 1, Np, Nj, None if Vin is None else Vin.ctypes.data, kp, Np2, Nj2,
+                          None if V2 is None else V2.ctypes.data)
+    return Np2, Nj2[:w].copy(), (V2[:w].copy() if V2 is not None else None)
+
+
+def postfilter(Ap, Aj, Ax, Np, Nj, is_root, agg, m, nc, Bc, B, P, k=0, theta=0.0, method="cg", iters=1):
+    """The post-filter lines of Alg. root_node_setup (Sec. 3.7): filter P,
+    enforce P Bc = B with Eq. Tproj, then `iters` more energy-minimisation
+    steps from the enforced P on the filtered pattern.  Returns
+    (Np2, Nj2, P_filtered_enforced, P_final, info)."""
+    keep = filter_keep(Np, Nj, P, agg, m, k, theta, is_root)
+    Np2, Nj2, Pf = compact(Np, Nj, keep, P)
+    Pe, rd = enforce(Np2, Nj2, is_root, Bc, B, Pf)
+    nB = _f64(B).shape[1]
+    fn = emin_cg if method == "cg" else emin_gmres
+    Pn, info = fn(Ap, Aj, Ax, Np2, Nj2, is_root, nc, Bc, nB, Pe, iters)
+    info["rank_def"] = rd
+    return Np2, Nj2, Pe, Pn, info

@@ -594,34 +594,121 @@ int orc_tentative(int n, int m, const int *Np, const int *Nj,
   }
   free(binv);
   int bad = 0;
-  if (nB > m) {
-    double Gp[NBMAX * NBMAX], r[NBMAX], y[NBMAX];
-    int maxlen = 1;
-    for (int i = 0; i < n; ++i) maxlen = Np[i + 1] - Np[i] > maxlen ? Np[i + 1] - Np[i] : maxlen;
-    double *W = (double *)malloc((size_t)maxlen * nB * sizeof(double));
-    for (int i = 0; i < n; ++i) {
-      if (is_root[i]) continue;
-      bad += row_pinv(Np[i + 1] - Np[i], Nj + Np[i], Bc, nB, W, Gp);
-      for (int q = 0; q < nB; ++q) {
-        double s = 0.0;
-        for (int p = Np[i]; p < Np[i + 1]; ++p) s += T[p] * Bc[(long)Nj[p] * nB + q];
-        r[q] = B[(long)i * nB + q] - s;
-      }
-      for (int q = 0; q < nB; ++q) {
-        y[q] = 0.0;
-        for (int u = 0; u < nB; ++u) y[q] += Gp[q * nB + u] * r[u];
-      }
-      for (int p = Np[i]; p < Np[i + 1]; ++p) {
-        double u = 0.0;
-        for (int q = 0; q < nB; ++q) u += Bc[(long)Nj[p] * nB + q] * y[q];
-        T[p] += u;
-      }
-    }
-    free(W);
-  }
+  if (nB > m) bad = orc_enforce(n, Np, Nj, is_root, Bc, nB, B, T);
   (void)nc;
   if (rank_def) *rank_def = bad;
   return ORC_OK;
+}
+
+/* Eq. Tproj on every F row: the minimum-norm update u of the row's entries
+ * t (on its pattern J) such that (t + u) Bc_J = B_i, u = (B_i - t Bc_J) G^+
+ * Bc_J^T with G = Bc_J^T Bc_J.  Root rows are left alone.  Used by inject
+ * for the candidates beyond the first m, and as enforce after a post-filter
+ * (Sec. 3.7).  Returns the number of rows that took the pseudo-inverse. */
+int orc_enforce(int n, const int *Np, const int *Nj, const unsigned char *is_root,
+                const double *Bc, int nB, const double *B, double *V) {
+  if (nB < 1 || nB > NBMAX) return ORC_EINVAL;
+  double Gp[NBMAX * NBMAX], r[NBMAX], y[NBMAX];
+  int maxlen = 1, bad = 0;
+  for (int i = 0; i < n; ++i) maxlen = Np[i + 1] - Np[i] > maxlen ? Np[i + 1] - Np[i] : maxlen;
+  double *W = (double *)malloc((size_t)maxlen * nB * sizeof(double));
+  for (int i = 0; i < n; ++i) {
+    if (is_root[i]) continue;
+    bad += row_pinv(Np[i + 1] - Np[i], Nj + Np[i], Bc, nB, W, Gp);
+    for (int q = 0; q < nB; ++q) {
+      double s = 0.0;
+      for (int p = Np[i]; p < Np[i + 1]; ++p) s += V[p] * Bc[(long)Nj[p] * nB + q];
+      r[q] = B[(long)i * nB + q] - s;
+    }
+    for (int q = 0; q < nB; ++q) {
+      y[q] = 0.0;
+      for (int u = 0; u < nB; ++u) y[q] += Gp[q * nB + u] * r[u];
+    }
+    for (int p = Np[i]; p < Np[i + 1]; ++p) {
+      double u = 0.0;
+      for (int q = 0; q < nB; ++q) u += Bc[(long)Nj[p] * nB + q] * y[q];
+      V[p] += u;
+    }
+  }
+  free(W);
+  return bad;
+}
+
+/* ------------------------------------------------------------------------ */
+/* filter, Alg. filter (Sec. 3.5 pre-filter of N, Sec. 3.7 post-filter of   */
+/* P).  The rows of an n x (m n_agg) matrix G stored on a pattern whose DOF */
+/* rows m I + c (c < m) share the node structure of node row I.  Each node  */
+/* entry (I, a) has the magnitude g = max |G| over its m x m block.  The    */
+/* entry in the row's own aggregate (a = agg[I]) plays the diagonal: it is  */
+/* always kept and is not an "off-diagonal" entry.  With k > 0, off entries */
+/* below the k-th largest off magnitude of the row are dropped; with        */
+/* theta > 0, off entries below theta times the largest off magnitude.      */
+/* Ties are kept.  Rows flagged in is_root (nullable) keep everything.      */
+/* keep[p] is written for every stored DOF entry.                           */
+/* ------------------------------------------------------------------------ */
+static int cmp_desc(const void *a, const void *b) {
+  double x = *(const double *)a, y = *(const double *)b;
+  return (x < y) - (x > y);
+}
+
+int orc_filter(int n, int m, const int *Np, const int *Nj, const double *G,
+               const unsigned char *is_root, const int *agg, int k, double theta,
+               unsigned char *keep) {
+  if (m < 1 || n % m || k < 0 || !(theta >= 0.0)) return ORC_EINVAL;
+  int maxlen = 1;
+  for (int i = 0; i < n; ++i) maxlen = Np[i + 1] - Np[i] > maxlen ? Np[i + 1] - Np[i] : maxlen;
+  double *g = (double *)malloc((size_t)maxlen * sizeof(double));
+  double *srt = (double *)malloc((size_t)maxlen * sizeof(double));
+  for (int I = 0; I < n / m; ++I) {
+    const int i0 = m * I;
+    const int len = (Np[i0 + 1] - Np[i0]) / m;  /* node entries of row I */
+    int root = 0;
+    for (int c = 0; c < m; ++c) root |= is_root ? is_root[i0 + c] : 0;
+    if (root) {
+      for (int c = 0; c < m; ++c)
+        for (int p = Np[i0 + c]; p < Np[i0 + c + 1]; ++p) keep[p] = 1;
+      continue;
+    }
+    int noff = 0;
+    for (int q = 0; q < len; ++q) {
+      double v = 0.0;
+      for (int c = 0; c < m; ++c)
+        for (int cc = 0; cc < m; ++cc) v = fmax(v, fabs(G[Np[i0 + c] + m * q + cc]));
+      g[q] = v;
+      if (Nj[Np[i0] + m * q] / m != agg[I]) srt[noff++] = v;
+    }
+    qsort(srt, (size_t)noff, sizeof(double), cmp_desc);
+    for (int q = 0; q < len; ++q) {
+      int kp = 1;
+      if (Nj[Np[i0] + m * q] / m != agg[I]) {
+        if (k > 0 && noff >= k && g[q] < srt[k - 1]) kp = 0;
+        if (theta > 0.0 && noff > 0 && g[q] < theta * srt[0]) kp = 0;
+      }
+      for (int c = 0; c < m; ++c)
+        for (int cc = 0; cc < m; ++cc) keep[Np[i0 + c] + m * q + cc] = (unsigned char)kp;
+    }
+  }
+  free(g);
+  free(srt);
+  return ORC_OK;
+}
+
+/* The entries of (Np, Nj, V) with keep[p] set, in order: the compacted
+ * pattern and values.  Returns the kept count. */
+int orc_compact(int n, const int *Np, const int *Nj, const double *V,
+                const unsigned char *keep, int *Np2, int *Nj2, double *V2) {
+  int w = 0;
+  Np2[0] = 0;
+  for (int i = 0; i < n; ++i) {
+    for (int p = Np[i]; p < Np[i + 1]; ++p)
+      if (keep[p]) {
+        Nj2[w] = Nj[p];
+        if (V2) V2[w] = V ? V[p] : 0.0;
+        ++w;
+      }
+    Np2[i + 1] = w;
+  }
+  return w;
 }
 
 /* ------------------------------------------------------------------------ */

@@ -126,6 +126,29 @@ double orc_constraint_residual(int n, const int *Np, const int *Nj,
                                const double *P, const double *Bc,
                                const double *B, int nB);
 
+/* Eq. Tproj as enforce (Sec. 3.7): on every F row of V (values on the
+ * pattern Np/Nj), the minimum-norm update that restores V Bc = B.  Root rows
+ * untouched.  Returns the count of rows whose Gram matrix took the eigen
+ * pseudo-inverse, or ORC_EINVAL. */
+int orc_enforce(int n, const int *Np, const int *Nj, const unsigned char *is_root,
+                const double *Bc, int nB, const double *B, double *V);
+
+/* Alg. filter on node blocks (Sec. 3.5 pre-filter, Sec. 3.7 post-filter):
+ * keep[p] for every stored entry of G (n DOF rows, m DOFs per node, DOF rows
+ * of one node sharing its node structure).  Block magnitude = max |G| over
+ * the m x m block; the own-aggregate entry (node column agg[I]) is the row's
+ * diagonal and always kept; off entries below the k-th largest off
+ * magnitude (k > 0) or below theta times the largest (theta > 0) dropped;
+ * rows with is_root set (nullable) kept whole. */
+int orc_filter(int n, int m, const int *Np, const int *Nj, const double *G,
+               const unsigned char *is_root, const int *agg, int k, double theta,
+               unsigned char *keep);
+
+/* Kept entries of a pattern and its values (V, V2 nullable); returns the
+ * kept count. */
+int orc_compact(int n, const int *Np, const int *Nj, const double *V,
+                const unsigned char *keep, int *Np2, int *Nj2, double *V2);
+
 /* Tangent-linear (forward-mode) derivative of orc_emin_cg with respect to
  * the stored values of A in direction dAx.  Pattern, T and Bc are constants.
  * Writes P (as orc_emin_cg) and dP.  Returns as orc_emin_cg. */
