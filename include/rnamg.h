@@ -196,6 +196,42 @@ rn_status rn_tentative(rn_ctx *ctx, int32_t n, int32_t block_m,
                        const double *B, int32_t nB, double *T, double *Bc,
                        int32_t *rank_deficient);
 
+/* ---- filter (Alg. filter; Sec. 3.5 pre-filter, Sec. 3.7 post-filter) ----
+ * Drops small entries of a matrix G stored on a pattern (n DOF rows; for
+ * block_m = 2 the two DOF rows of a node share its node structure, DOF
+ * column 2a + c' in node column a).  A node entry's magnitude is the largest
+ * |G| of its block_m x block_m block.  The entry of the row's own aggregate
+ * (node column agg[I], agg: n/block_m node aggregates) plays the diagonal:
+ * it is always kept and is not an off entry.  With k > 0, off entries below
+ * the k-th largest off magnitude of the row are dropped; with theta > 0, off
+ * entries below theta times the largest (both: either rule drops); ties
+ * are kept.  Rows of nodes with is_root set are kept whole.
+ * TWO-PHASE.  Phase 1 (F_colind NULL) writes F_rowptr (n+1) and *nnz_F
+ * (host); phase 2 (same arguments, F_colind non-NULL) writes the kept
+ * columns into F_colind and, when F_vals is non-NULL, their values, in
+ * order.  k >= 0, theta >= 0.  RN_EINVAL for a malformed pattern or DOF
+ * rows of one node with different structures. */
+rn_status rn_filter(rn_ctx *ctx, int32_t n, int32_t block_m,
+                    const int32_t *N_rowptr, const int32_t *N_colind,
+                    int64_t nnz_N, const uint8_t *is_root, const int32_t *agg,
+                    const double *vals, int32_t k, double theta,
+                    int32_t *F_rowptr, int32_t *F_colind, double *F_vals,
+                    int64_t *nnz_F);
+
+/* ---- enforce (Sec. 3.7, Eq. Tproj) ---------------------------------------
+ * In place on vals (values on the pattern N, n rows, n_cols columns): every
+ * F row takes the minimum-norm update of its stored entries that restores
+ * vals Bc = B (least squares through the Gram pseudo-inverse of Bc on the
+ * row's columns where the row cannot carry every candidate); root rows are
+ * untouched.  Bc: n_cols x nB, B: n x nB, row-major; 1 <= nB <= 4.
+ * *rank_deficient (host, nullable) counts rows that took the eigen
+ * pseudo-inverse.  Synchronises the stream. */
+rn_status rn_enforce(rn_ctx *ctx, int32_t n, int32_t n_cols,
+                     const int32_t *N_rowptr, const int32_t *N_colind,
+                     int64_t nnz_N, const uint8_t *is_root, const double *Bc,
+                     const double *B, int32_t nB, double *vals,
+                     int32_t *rank_deficient);
+
 /* ---- transpose (needed for R^T on A^T, Alg. root_node_setup non-symmetric
  * branch, and for the adjoint) ------------------------------------------
  * Scalar CSR only (block_m = 1).  AT_rowptr: n+1, AT_colind/AT_vals: nnz

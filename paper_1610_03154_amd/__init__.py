@@ -328,6 +328,43 @@ class Context:
                                          C.byref(rd)), "rn_tentative")
         return T[:Nj.numel()], Bc[:block_m * n_agg], rd.value
 
+    # -- filter / enforce (Sec. 3.5, Sec. 3.7) ---------------------------------
+    def filter(self, Np, Nj, is_root, agg, vals, block_m=1, k=0, theta=0.0):
+        """rn_filter: (F_rowptr, F_colind, F_vals) of the kept entries."""
+        torch = self.torch
+        n = Np.numel() - 1
+        Fp = torch.empty(n + 1, dtype=torch.int32, device="cuda")
+        nnz = C.c_int64()
+        args = (self.h, n, block_m, _ptr(Np), _ptr(Nj), Nj.numel(), _ptr(is_root), _ptr(agg), _ptr(vals), int(k),
+                C.c_double(theta))
+        self._check(L.lib().rn_filter(*args, _ptr(Fp), None, None, C.byref(nnz)), "rn_filter")
+        Fj = torch.empty(max(nnz.value, 1), dtype=torch.int32, device="cuda")
+        Fv = torch.empty(max(nnz.value, 1), dtype=torch.float64, device="cuda")
+        self._check(L.lib().rn_filter(*args, _ptr(Fp), _ptr(Fj), _ptr(Fv), C.byref(nnz)), "rn_filter")
+        return Fp, Fj[:nnz.value], Fv[:nnz.value]
+
+    def enforce(self, Np, Nj, is_root, Bc, B, vals, n_cols=None):
+        """rn_enforce in place on vals; returns the rank-deficient row count."""
+        n = Np.numel() - 1
+        nB = int(Bc.shape[1])
+        rd = C.c_int32()
+        self._check(L.lib().rn_enforce(self.h, n, int(Bc.shape[0] if n_cols is None else n_cols), _ptr(Np), _ptr(Nj),
+                                       Nj.numel(), _ptr(is_root), _ptr(Bc), _ptr(B), nB, _ptr(vals), C.byref(rd)),
+                    "rn_enforce")
+        return rd.value
+
+    def postfilter(self, A: DeviceCSR, Np, Nj, is_root, agg, Bc, B, P, k=0, theta=0.0, method=RN_CG, iters=1,
+                   precision=RN_FP64):
+        """The post-filter lines of Alg. root_node_setup (Sec. 3.7): filter P,
+        enforce P Bc = B, then `iters` more energy-minimisation steps from the
+        enforced P on the filtered pattern.  Returns (F_rowptr, F_colind,
+        P_enforced, P_final, stats, plan on the filtered pattern)."""
+        Fp, Fj, Pf = self.filter(Np, Nj, is_root, agg, P, A.block_m, k, theta)
+        self.enforce(Fp, Fj, is_root, Bc, B.to(self.torch.float64).contiguous(), Pf)
+        plan = self.plan(A, int(Bc.shape[0]), Fp, Fj, is_root, Bc)
+        Pn, st, _ = self.energy_min(plan, A.vals, Pf, method, iters, precision)
+        return Fp, Fj, Pf, Pn, st, plan
+
     # -- transpose -----------------------------------------------------------
     def setup_native(self, A: DeviceCSR, B, agg, roots, theta=0.0, degree=2, iters=4, method=RN_CG,
                      precision=RN_FP64, Bhat=None) -> NativeSetup:

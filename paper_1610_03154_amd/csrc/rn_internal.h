@@ -45,6 +45,8 @@ enum RnSlot {
   SLOT_BLK0,
   SLOT_BLK1,
   SLOT_BLK2,
+  SLOT_FLT_KEEP,
+  SLOT_FLT_CNT,
   SLOT_COUNT
 };
 
@@ -93,6 +95,8 @@ struct rn_ctx {
   int32_t pat_n = -1;          // rows of the DOF pattern
   XRows pat_x{};               // the final nodal level (read by phase 2)
   int32_t pat_m = 1;
+  int32_t flt_n = -1;          // rn_filter: rows and input entries of phase 1, kept count
+  int64_t flt_nnz_in = -1, flt_nnz = -1;
   // live plans made on this context: rn_destroy detaches them, so a plan
   // destroyed after its context frees its memory without touching the context
   std::vector<rn_plan *> plans;

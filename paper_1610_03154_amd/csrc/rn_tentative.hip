@@ -182,3 +182,45 @@ extern "C" rn_status rn_tentative(rn_ctx *ctx, int32_t n, int32_t m, const int32
   RN_TRY(rn_guard_status(ctx, gword, "rn_tentative"));
   return rn_tentative_flags(ctx, hf, rank_deficient);
 }
+
+// enforce (Sec. 3.7): Eq. Tproj on every F row of the caller's values.
+extern "C" rn_status rn_enforce(rn_ctx *ctx, int32_t n, int32_t n_cols, const int32_t *N_rowptr,
+                                const int32_t *N_colind, int64_t nnz_N, const uint8_t *is_root, const double *Bc,
+                                const double *B, int32_t nB, double *vals, int32_t *rank_deficient) {
+  if (!ctx) return RN_EINVAL;
+  ctx->err.clear();
+  if (n < 0 || n_cols < 0 || nnz_N < 0 || nB < 1 || nB > RN_NBMAX)
+    return rn_fail(ctx, RN_EINVAL, "rn_enforce: bad sizes (n %d, n_cols %d, nB %d; need 1 <= nB <= %d)", n, n_cols,
+                   nB, RN_NBMAX);
+  if (nnz_N >= ((int64_t)1 << 31)) return rn_fail(ctx, RN_ELIMIT, "rn_enforce: nnz_N >= 2^31");
+  if (n > 0 && (!N_rowptr || !is_root || !B)) return rn_fail(ctx, RN_EINVAL, "rn_enforce: null argument");
+  if (nnz_N > 0 && (!N_colind || !vals || !Bc)) return rn_fail(ctx, RN_EINVAL, "rn_enforce: null argument");
+  rn_status st = RN_OK;
+  int32_t *guard = rn_guard_begin(ctx, &st);
+  if (!guard) return st;
+  int32_t *flags = guard + GS_TFLAGS;  // flags[1]: rank-deficient rows (zeroed with the guard)
+  RnChecks v{};
+  v.csr[0] = {n, n_cols, nnz_N, N_rowptr, N_colind, GUARD_N};
+  v.ncsr = 1;
+  RN_TRY(rn_validate(ctx, v, guard));
+  if (n > 0) {
+    const dim3 g(rn_div_up(n, RN_BLOCK)), b(RN_BLOCK);
+    switch (nB) {
+      case 1: hipLaunchKernelGGL(k_tproj<1>, g, b, 0, ctx->stream, n, N_rowptr, N_colind, is_root, B, Bc, vals, flags + 1, guard); break;
+      case 2: hipLaunchKernelGGL(k_tproj<2>, g, b, 0, ctx->stream, n, N_rowptr, N_colind, is_root, B, Bc, vals, flags + 1, guard); break;
+      case 3: hipLaunchKernelGGL(k_tproj<3>, g, b, 0, ctx->stream, n, N_rowptr, N_colind, is_root, B, Bc, vals, flags + 1, guard); break;
+      case 4: hipLaunchKernelGGL(k_tproj<4>, g, b, 0, ctx->stream, n, N_rowptr, N_colind, is_root, B, Bc, vals, flags + 1, guard); break;
+    }
+    LAUNCH_CHECK(ctx);
+  }
+  const RnFetch it[2] = {{guard, 4}, {flags, 2 * sizeof(int32_t)}};
+  const unsigned char *hb = nullptr;
+  size_t off[2];
+  RN_TRY(rn_fetch(ctx, 2, it, &hb, off));
+  int32_t gword = 0, hf[2] = {0, 0};
+  memcpy(&gword, hb + off[0], 4);
+  memcpy(hf, hb + off[1], 8);
+  RN_TRY(rn_guard_status(ctx, gword, "rn_enforce"));
+  if (rank_deficient) *rank_deficient = hf[1];
+  return RN_OK;
+}
