@@ -60,6 +60,7 @@ def lib():
         L.orc_enforce.argtypes = [i, _i32p, _i32p, _u8p, _f64p, i, _f64p, _f64p]
         L.orc_filter.argtypes = [i, i, _i32p, _i32p, _f64p, vp, _i32p, i, d, _u8p]
         L.orc_compact.argtypes = [i, _i32p, _i32p, vp, _u8p, _i32p, _i32p, vp]
+        L.orc_spgemm.argtypes = [i, i, i, _i32p, _i32p, vp, _i32p, _i32p, vp, _i32p, _i32p, vp, C.c_long]
         _lib = L
     return _lib
 
@@ -305,3 +306,36 @@ def postfilter(Ap, Aj, Ax, Np, Nj, is_root, agg, m, nc, Bc, B, P, k=0, theta=0.0
     Pn, info = fn(Ap, Aj, Ax, Np2, Nj2, is_root, nc, Bc, nB, Pe, iters)
     info["rank_def"] = rd
     return Np2, Nj2, Pe, Pn, info
+
+
+def spgemm(Xp, Xj, Xx, Yp, Yj, Yx, cols):
+    """C = X Y (CSR): (Cp, Cj, Cx); Xx or Yx None gives the structure only."""
+    Xp, Xj, Yp, Yj = _i32(Xp), _i32(Xj), _i32(Yp), _i32(Yj)
+    rows = Xp.size - 1
+    xv = None if Xx is None else _f64(Xx)
+    yv = None if Yx is None else _f64(Yx)
+    cap = 1024
+    while True:
+        Cp = np.zeros(rows + 1, np.int32)
+        Cj = np.zeros(cap, np.int32)
+        Cx = np.zeros(cap)
+        rc = lib().orc_spgemm(rows, Yp.size - 1, int(cols), Xp, Xj, None if xv is None else xv.ctypes.data, Yp, Yj,
+                              None if yv is None else yv.ctypes.data, Cp, Cj,
+                              Cx.ctypes.data if (xv is not None and yv is not None) else None, cap)
+        if rc == ORC_ECAP:
+            cap *= 4
+            continue
+        if rc < 0:
+            raise OracleError(rc, "spgemm")
+        return Cp, Cj[:rc].copy(), (Cx[:rc].copy() if (xv is not None and yv is not None) else None)
+
+
+def galerkin(Ap, Aj, Ax, Pp, Pj, Px, nc, RTp=None, RTj=None, RTx=None):
+    """The coarse operator of Sec. 3.8, A_c = R (A P), with R = P^T for a
+    symmetric A, or R = (R^T)^T from the given R^T (n x nc, CSR)."""
+    n = Pp.size - 1
+    APp, APj, APx = spgemm(Ap, Aj, Ax, Pp, Pj, Px, nc)
+    if RTp is None:
+        RTp, RTj, RTx = Pp, Pj, Px
+    Rp, Rj, Rx = transpose(RTp, RTj, RTx, n_cols=nc)
+    return spgemm(Rp, Rj, Rx, APp, APj, APx, nc)

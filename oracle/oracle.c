@@ -961,3 +961,53 @@ double orc_constraint_residual(int n, const int *Np, const int *Nj,
     }
   return mx;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Sparse product C = X Y (Gustavson, row by row): the Galerkin product of  */
+/* Sec. 3.8 as two such products, and the pattern powers of Sec. 3.4 with   */
+/* values.  Each row of C holds the union of the columns of the rows of Y   */
+/* that the row of X selects, sorted; each value is accumulated in the      */
+/* order of X's row (terms of one column added in that order from 0).       */
+/* Returns nnz(C), or ORC_ECAP when it exceeds cap (Cj, Cx not written past */
+/* cap).  Xx, Yx, Cx nullable: structure only.                              */
+/* ------------------------------------------------------------------------ */
+int orc_spgemm(int rows, int inner, int cols, const int *Xp, const int *Xj,
+               const double *Xx, const int *Yp, const int *Yj, const double *Yx,
+               int *Cp, int *Cj, double *Cx, long cap) {
+  (void)inner;
+  int *mark = (int *)malloc((size_t)(cols > 0 ? cols : 1) * sizeof(int));
+  double *acc = (double *)calloc((size_t)(cols > 0 ? cols : 1), sizeof(double));
+  for (int j = 0; j < cols; ++j) mark[j] = -1;
+  long w = 0;
+  int rc = 0;
+  Cp[0] = 0;
+  for (int i = 0; i < rows; ++i) {
+    const long r0 = w;
+    for (int t = Xp[i]; t < Xp[i + 1]; ++t) {
+      const int k = Xj[t];
+      for (int q = Yp[k]; q < Yp[k + 1]; ++q) {
+        const int j = Yj[q];
+        if (mark[j] != i) {
+          mark[j] = i;
+          if (w < cap) Cj[w] = j;
+          ++w;
+        }
+        if (Xx && Yx) acc[j] += Xx[t] * Yx[q];
+      }
+    }
+    if (w <= cap) {
+      qsort(Cj + r0, (size_t)(w - r0), sizeof(int), cmp_int);
+      for (long p = r0; p < w; ++p) {
+        if (Cx) Cx[p] = acc[Cj[p]];
+        acc[Cj[p]] = 0.0;
+      }
+    } else {
+      rc = ORC_ECAP;
+      for (int j = 0; j < cols; ++j) acc[j] = 0.0;
+    }
+    Cp[i + 1] = (int)(w < cap ? w : cap);
+  }
+  free(mark);
+  free(acc);
+  return rc < 0 ? rc : (int)w;
+}

@@ -149,6 +149,13 @@ int orc_filter(int n, int m, const int *Np, const int *Nj, const double *G,
 int orc_compact(int n, const int *Np, const int *Nj, const double *V,
                 const unsigned char *keep, int *Np2, int *Nj2, double *V2);
 
+/* C = X Y for CSR X (rows x inner) and Y (inner x cols): rows of C sorted,
+ * values accumulated in the order of X's row (Sec. 3.8 Galerkin product,
+ * Sec. 3.4 valued pattern powers).  Returns nnz(C) or ORC_ECAP (> cap). */
+int orc_spgemm(int rows, int inner, int cols, const int *Xp, const int *Xj,
+               const double *Xx, const int *Yp, const int *Yj, const double *Yx,
+               int *Cp, int *Cj, double *Cx, long cap);
+
 /* Tangent-linear (forward-mode) derivative of orc_emin_cg with respect to
  * the stored values of A in direction dAx.  Pattern, T and Bc are constants.
  * Writes P (as orc_emin_cg) and dP.  Returns as orc_emin_cg. */
