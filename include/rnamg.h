@@ -232,6 +232,33 @@ rn_status rn_enforce(rn_ctx *ctx, int32_t n, int32_t n_cols,
                      const double *B, int32_t nB, double *vals,
                      int32_t *rank_deficient);
 
+/* ---- sparse product and Galerkin coarse operator (Sec. 3.8) ------------
+ * C = X Y for CSR X (rows x inner) and Y (inner x cols): each row of C holds
+ * the sorted union of the columns of the rows of Y that the row of X
+ * selects (entries whose terms cancel stay, with value 0); C_ij is the sum
+ * over the row of X, in its order, of X_it Y_(k_t) j.  TWO-PHASE: phase 1
+ * (C_colind NULL) writes C_rowptr (rows+1) and *nnz_C; phase 2 (same
+ * arguments) writes C_colind and, when C_vals is non-NULL, the values
+ * (X_vals, Y_vals may be NULL when C_vals is). */
+rn_status rn_spgemm(rn_ctx *ctx, int32_t rows, int32_t inner, int32_t cols,
+                    const int32_t *X_rowptr, const int32_t *X_colind,
+                    const double *X_vals, int64_t nnz_X,
+                    const int32_t *Y_rowptr, const int32_t *Y_colind,
+                    const double *Y_vals, int64_t nnz_Y, int32_t *C_rowptr,
+                    int32_t *C_colind, double *C_vals, int64_t *nnz_C);
+/* A_c = R A P (the last line of Alg. root_node_setup): P (n x n_cols) given
+ * by its values on the pattern N; R = P^T when RT is NULL (symmetric A),
+ * else R = (R^T)^T with R^T on the same pattern (non-symmetric A, Sec. 3.8).
+ * A scalar CSR or node-blocked (its scalar entries are used).  Computed as
+ * R (A P) with two rn_spgemm products.  TWO-PHASE as rn_spgemm: phase 1
+ * writes Ac_rowptr (n_cols + 1) and *nnz_Ac and keeps A P and R in the
+ * context; phase 2 (same arguments) writes Ac_colind and Ac_vals. */
+rn_status rn_galerkin(rn_ctx *ctx, const rn_matrix *A, int32_t n_cols,
+                      const int32_t *N_rowptr, const int32_t *N_colind,
+                      int64_t nnz_N, const double *P, const double *RT,
+                      int32_t *Ac_rowptr, int32_t *Ac_colind, double *Ac_vals,
+                      int64_t *nnz_Ac);
+
 /* ---- transpose (needed for R^T on A^T, Alg. root_node_setup non-symmetric
  * branch, and for the adjoint) ------------------------------------------
  * Scalar CSR only (block_m = 1).  AT_rowptr: n+1, AT_colind/AT_vals: nnz

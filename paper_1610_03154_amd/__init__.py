@@ -365,6 +365,35 @@ class Context:
         Pn, st, _ = self.energy_min(plan, A.vals, Pf, method, iters, precision)
         return Fp, Fj, Pf, Pn, st, plan
 
+    # -- sparse product, Galerkin (Sec. 3.8) ------------------------------------
+    def spgemm(self, Xp, Xj, Xv, Yp, Yj, Yv, cols: int):
+        """rn_spgemm: (Cp, Cj, Cv) of C = X Y (Cv None when Xv or Yv is)."""
+        torch = self.torch
+        rows, inner = Xp.numel() - 1, Yp.numel() - 1
+        Cp = torch.empty(rows + 1, dtype=torch.int32, device="cuda")
+        nnz = C.c_int64()
+        args = (self.h, rows, inner, int(cols), _ptr(Xp), _ptr(Xj), _ptr(Xv), Xj.numel(), _ptr(Yp), _ptr(Yj), _ptr(Yv),
+                Yj.numel())
+        self._check(L.lib().rn_spgemm(*args, _ptr(Cp), None, None, C.byref(nnz)), "rn_spgemm")
+        Cj = torch.empty(max(nnz.value, 1), dtype=torch.int32, device="cuda")
+        Cv = None if (Xv is None or Yv is None) else torch.empty(max(nnz.value, 1), dtype=torch.float64,
+                                                               device="cuda")
+        self._check(L.lib().rn_spgemm(*args, _ptr(Cp), _ptr(Cj), _ptr(Cv), C.byref(nnz)), "rn_spgemm")
+        return Cp, Cj[:nnz.value], (Cv[:nnz.value] if Cv is not None else None)
+
+    def galerkin(self, A: DeviceCSR, n_cols: int, Np, Nj, P, RT=None):
+        """rn_galerkin: (Ac_rowptr, Ac_colind, Ac_vals) of A_c = R A P."""
+        torch = self.torch
+        Acp = torch.empty(n_cols + 1, dtype=torch.int32, device="cuda")
+        nnz = C.c_int64()
+        d = A.desc()
+        args = (self.h, C.byref(d), int(n_cols), _ptr(Np), _ptr(Nj), Nj.numel(), _ptr(P), _ptr(RT))
+        self._check(L.lib().rn_galerkin(*args, _ptr(Acp), None, None, C.byref(nnz)), "rn_galerkin")
+        Acj = torch.empty(max(nnz.value, 1), dtype=torch.int32, device="cuda")
+        Acv = torch.empty(max(nnz.value, 1), dtype=torch.float64, device="cuda")
+        self._check(L.lib().rn_galerkin(*args, _ptr(Acp), _ptr(Acj), _ptr(Acv), C.byref(nnz)), "rn_galerkin")
+        return Acp, Acj[:nnz.value], Acv[:nnz.value]
+
     # -- transpose -----------------------------------------------------------
     def setup_native(self, A: DeviceCSR, B, agg, roots, theta=0.0, degree=2, iters=4, method=RN_CG,
                      precision=RN_FP64, Bhat=None) -> NativeSetup:

@@ -63,6 +63,8 @@ SIGNATURES = {
     "rn_tentative": (_i32, [_vp, _i32, _i32, _vp, _vp, _i64, _vp, _vp, _vp, _i32, _vp, _i32, _vp, _vp, _pi32]),
     "rn_filter": (_i32, [_vp, _i32, _i32, _vp, _vp, _i64, _vp, _vp, _vp, _i32, _d, _vp, _vp, _vp, _pi64]),
     "rn_enforce": (_i32, [_vp, _i32, _i32, _vp, _vp, _i64, _vp, _vp, _vp, _i32, _vp, _pi32]),
+    "rn_spgemm": (_i32, [_vp, _i32, _i32, _i32, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _pi64]),
+    "rn_galerkin": (_i32, [_vp, C.POINTER(rn_matrix), _i32, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _pi64]),
     "rn_transpose": (_i32, [_vp, C.POINTER(rn_matrix), _vp, _vp, _vp, _vp]),
     "rn_plan_create": (_i32, [_vp, C.POINTER(rn_matrix), _i32, _vp, _vp, _i64, _vp, _vp, _i32,
                               C.POINTER(C.c_void_p)]),

@@ -47,6 +47,18 @@ enum RnSlot {
   SLOT_BLK2,
   SLOT_FLT_KEEP,
   SLOT_FLT_CNT,
+  SLOT_PRD_CNT,
+  SLOT_PRD_CUR,
+  SLOT_GAL_ASP,
+  SLOT_GAL_ASJ,
+  SLOT_GAL_ASV,
+  SLOT_GAL_APP,
+  SLOT_GAL_APJ,
+  SLOT_GAL_APV,
+  SLOT_GAL_RP,
+  SLOT_GAL_RJ,
+  SLOT_GAL_RV,
+  SLOT_GAL_PERM,
   SLOT_COUNT
 };
 
@@ -97,6 +109,12 @@ struct rn_ctx {
   int32_t pat_m = 1;
   int32_t flt_n = -1;          // rn_filter: rows and input entries of phase 1, kept count
   int64_t flt_nnz_in = -1, flt_nnz = -1;
+  int32_t prd_rows = -1;       // rn_spgemm: rows and nnz of phase 1
+  int64_t prd_nnz = -1;
+  int32_t gal_n = -1, gal_nc = -1;  // rn_galerkin: phase 1's sizes and intermediates (scratch)
+  int64_t gal_nnz = -1;
+  const int32_t *gal_R[2] = {nullptr, nullptr}, *gal_AP[2] = {nullptr, nullptr};
+  const double *gal_Rv = nullptr, *gal_APv = nullptr;
   // live plans made on this context: rn_destroy detaches them, so a plan
   // destroyed after its context frees its memory without touching the context
   std::vector<rn_plan *> plans;
