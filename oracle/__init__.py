@@ -60,6 +60,7 @@ def lib():
         L.orc_enforce.argtypes = [i, _i32p, _i32p, _u8p, _f64p, i, _f64p, _f64p]
         L.orc_filter.argtypes = [i, i, _i32p, _i32p, _f64p, vp, _i32p, i, d, _u8p]
         L.orc_compact.argtypes = [i, _i32p, _i32p, vp, _u8p, _i32p, _i32p, vp]
+        L.orc_strength_values.argtypes = [i, _i32p, _i32p, _f64p, i, d, _i32p, _i32p, _f64p]
         L.orc_spgemm.argtypes = [i, i, i, _i32p, _i32p, vp, _i32p, _i32p, vp, _i32p, _i32p, vp, C.c_long]
         _lib = L
     return _lib
@@ -339,3 +340,41 @@ def galerkin(Ap, Aj, Ax, Pp, Pj, Px, nc, RTp=None, RTj=None, RTx=None):
         RTp, RTj, RTx = Pp, Pj, Px
     Rp, Rj, Rx = transpose(RTp, RTj, RTx, n_cols=nc)
     return spgemm(Rp, Rj, Rx, APp, APj, APx, nc)
+
+
+def strength_values(Ap, Aj, Ax, m, theta, Sp, Sj):
+    """Eq. soc values of the node graph S (Sp, Sj) from orc_strength."""
+    Sx = np.zeros(max(int(Sp[-1]), 1))
+    rc = lib().orc_strength_values(_i32(Ap).size - 1, _i32(Ap), _i32(Aj), _f64(Ax), int(m), float(theta), _i32(Sp),
+                                   _i32(Sj), Sx)
+    if rc < 0:
+        raise OracleError(rc, "strength_values")
+    return Sx[:int(Sp[-1])].copy()
+
+
+def pattern_values(Sp, Sj, Sx, agg, n_agg, d):
+    """N = S^d C with values (Sec. 3.4 with the normalised S of Eq. soc): X_0 = C,
+    X_{t+1} = S X_t as sparse products.  Returns (Np, Nj, Nx) on node rows."""
+    nn = _i32(Sp).size - 1
+    Xp, Xj, Xx = np.arange(nn + 1, dtype=np.int32), _i32(agg).copy(), np.ones(nn)
+    for _ in range(d):
+        Xp, Xj, Xx = spgemm(Sp, Sj, Sx, Xp, Xj, Xx, n_agg)
+    return Xp, Xj, Xx
+
+
+def prefilter_setup(A, B, m, theta, degree, k=0, theta_f=0.0, agg=None, roots=None):
+    """The lines of Alg. root_node_setup up to inject with the pre-filter
+    (Sec. 3.5): strength, aggregation, N = S^d C with Eq. soc values, filter
+    of N (node rows, own aggregate as the diagonal), unamalgamate, root rows,
+    tentative.  Returns the dict of setup() plus the nodal valued pattern."""
+    Sp, Sj = strength(A.rowptr, A.colind, A.vals, m, theta)
+    if agg is None:
+        agg, roots = aggregate(Sp, Sj)
+    Sx = strength_values(A.rowptr, A.colind, A.vals, m, theta, Sp, Sj)
+    Vp, Vj, Vx = pattern_values(Sp, Sj, Sx, agg, roots.size, degree)
+    keep = filter_keep(Vp, Vj, Vx, agg, 1, k, theta_f)
+    Npn, Njn, _ = compact(Vp, Vj, keep, Vx)
+    Np, Nj, is_root = pattern_dofs(Npn, Njn, agg, roots, m)
+    T, Bc, rd = tentative(Np, Nj, is_root, agg, roots, m, B)
+    return dict(Sp=Sp, Sj=Sj, Sx=Sx, agg=agg, roots=roots, Vp=Vp, Vj=Vj, Vx=Vx, Npn=Npn, Njn=Njn, Np=Np, Nj=Nj,
+                is_root=is_root, T=T, Bc=Bc, nc=m * roots.size, rank_def=rd)

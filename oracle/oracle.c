@@ -1011,3 +1011,56 @@ int orc_spgemm(int rows, int inner, int cols, const int *Xp, const int *Xj,
   free(acc);
   return rc < 0 ? rc : (int)w;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Strength values normalised as Eq. soc (Sec. 3.2), on the node graph S   */
+/* made by orc_strength with the same A, m and theta.  The value of node    */
+/* entry (I, J), J != I, is the largest |a_ij| over the strong DOF entries  */
+/* of block (I, J) and over those of block (J, I) (S u S^T taken as the     */
+/* entry-wise maximum; amalgamation takes the block's largest entry).  Each */
+/* row is then divided by its largest off-diagonal value and its diagonal   */
+/* set to 1, so that both equal 1 (rows whose off values are all 0 keep 0). */
+/* ------------------------------------------------------------------------ */
+static int find_col(const int *Sj, int s, int e, int J) {
+  for (int p = s; p < e; ++p)
+    if (Sj[p] == J) return p;
+  return -1;
+}
+
+int orc_strength_values(int n, const int *Ap, const int *Aj, const double *Ax, int m,
+                        double theta, const int *Sp, const int *Sj, double *Sx) {
+  if (m < 1 || n % m) return ORC_EINVAL;
+  const int nn = n / m;
+  double *diag = (double *)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
+  for (int i = 0; i < n; ++i)
+    for (int p = Ap[i]; p < Ap[i + 1]; ++p)
+      if (Aj[p] == i) diag[i] = Ax[p];
+  for (long q = 0; q < Sp[nn]; ++q) Sx[q] = 0.0;
+  const double th2 = theta * theta;
+  for (int i = 0; i < n; ++i) {
+    for (int p = Ap[i]; p < Ap[i + 1]; ++p) {
+      const int j = Aj[p];
+      const int I = i / m, J = j / m;
+      if (I == J) continue;
+      const double lhs = Ax[p] * Ax[p];
+      const double rhs = th2 * fabs(diag[i] * diag[j]);
+      if (!(lhs >= rhs)) continue;
+      const double v = fabs(Ax[p]);
+      const int q1 = find_col(Sj, Sp[I], Sp[I + 1], J), q2 = find_col(Sj, Sp[J], Sp[J + 1], I);
+      if (q1 < 0 || q2 < 0) { free(diag); return ORC_EINVAL; }
+      Sx[q1] = fmax(Sx[q1], v);
+      Sx[q2] = fmax(Sx[q2], v);
+    }
+  }
+  for (int I = 0; I < nn; ++I) {
+    double mx = 0.0;
+    for (int q = Sp[I]; q < Sp[I + 1]; ++q)
+      if (Sj[q] != I) mx = fmax(mx, Sx[q]);
+    for (int q = Sp[I]; q < Sp[I + 1]; ++q) {
+      if (Sj[q] == I) Sx[q] = 1.0;
+      else if (mx > 0.0) Sx[q] = Sx[q] / mx;
+    }
+  }
+  free(diag);
+  return ORC_OK;
+}

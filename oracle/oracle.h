@@ -156,6 +156,12 @@ int orc_spgemm(int rows, int inner, int cols, const int *Xp, const int *Xj,
                const double *Xx, const int *Yp, const int *Yj, const double *Yx,
                int *Cp, int *Cj, double *Cx, long cap);
 
+/* Eq. soc values on the node graph S of orc_strength (same A, m, theta):
+ * off entry (I, J) = largest |a_ij| over strong DOF entries of blocks (I, J)
+ * and (J, I); each row divided by its largest off value; diagonal 1. */
+int orc_strength_values(int n, const int *Ap, const int *Aj, const double *Ax, int m,
+                        double theta, const int *Sp, const int *Sj, double *Sx);
+
 /* Tangent-linear (forward-mode) derivative of orc_emin_cg with respect to
  * the stored values of A in direction dAx.  Pattern, T and Bc are constants.
  * Writes P (as orc_emin_cg) and dP.  Returns as orc_emin_cg. */
