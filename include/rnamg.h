@@ -22,7 +22,8 @@
  *     known after the computation are TWO-PHASE: the first call (output
  *     index array NULL) computes the result into the context, writes the
  *     row pointer array and the host-side count; the second call (same
- *     context, same arguments, output array non-NULL) copies it out.
+ *     context, same arguments, output array non-NULL) copies it out; no
+ *     other call that computes into the context may come between the two.
  *   - All device work is queued on the context's HIP stream.  Calls that
  *     return a size, a status found on the device or host statistics read
  *     back from the device and therefore synchronise that stream.
@@ -152,6 +153,17 @@ const char *rn_version(void);
 rn_status rn_strength(rn_ctx *ctx, const rn_matrix *A, double theta,
                       int32_t *S_rowptr, int32_t *S_colind, int64_t *nnz_S);
 
+/* Strength values normalised as Eq. soc (Sec. 3.2), for the pre-filter of
+ * Sec. 3.5: on the node graph S that rn_strength made from the same A and
+ * theta, S_vals[q] for node entry (I, J), J != I, is the largest |a_ij| over
+ * the strong DOF entries of blocks (I, J) and (J, I) of A (S u S^T as the
+ * entry-wise maximum, amalgamation by the block's largest entry); each row
+ * is then divided by its largest off-diagonal value (left at 0 when that is
+ * 0) and its diagonal set to 1.  Synchronises the stream. */
+rn_status rn_strength_values(rn_ctx *ctx, const rn_matrix *A, double theta,
+                             const int32_t *S_rowptr, const int32_t *S_colind,
+                             int64_t nnz_S, double *S_vals);
+
 /* ---- aggregation (Sec. 3.3), host helper --------------------------------
  * Standard greedy aggregation on the HOST (host pointers): sweep 1 makes a
  * node whose strong neighbours are all free the root of a new aggregate
@@ -179,6 +191,31 @@ rn_status rn_pattern(rn_ctx *ctx, int32_t n_nodes, const int32_t *S_rowptr,
                      int32_t block_m, int32_t *N_rowptr, int32_t *N_colind,
                      uint8_t *is_root, int64_t *nnz_N);
 
+/* Valued nodal pattern N = S^d C (Sec. 3.4 with the values of Eq. soc, the
+ * matrix the pre-filter of Sec. 3.5 reads): X_0 = C (row I holds 1 at
+ * column agg[I]), X_t = S X_(t-1) as sparse products (rn_spgemm's order of
+ * summation).  Node rows, n_agg columns, no root-row replacement.
+ * TWO-PHASE: phase 1 writes Nn_rowptr (nn + 1) and *nnz_Nn, phase 2 (same
+ * arguments) Nn_colind and Nn_vals (nullable). */
+rn_status rn_pattern_values(rn_ctx *ctx, int32_t n_nodes,
+                            const int32_t *S_rowptr, const int32_t *S_colind,
+                            const double *S_vals, int64_t nnz_S,
+                            const int32_t *agg, int32_t n_agg, int32_t degree,
+                            int32_t *Nn_rowptr, int32_t *Nn_colind,
+                            double *Nn_vals, int64_t *nnz_Nn);
+
+/* DOF pattern of a given nodal pattern (the unamalgamate and
+ * root_node_pattern lines of Alg. root_node_setup): as the second half of
+ * rn_pattern, for a nodal pattern made elsewhere (for instance one that
+ * rn_filter pre-filtered).  Nn: n_nodes x n_agg CSR.  TWO-PHASE as
+ * rn_pattern: phase 1 writes N_rowptr, is_root and *nnz_N, phase 2 N_colind. */
+rn_status rn_pattern_dofs(rn_ctx *ctx, int32_t n_nodes,
+                          const int32_t *Nn_rowptr, const int32_t *Nn_colind,
+                          int64_t nnz_Nn, const int32_t *agg,
+                          const int32_t *roots, int32_t n_agg, int32_t block_m,
+                          int32_t *N_rowptr, int32_t *N_colind,
+                          uint8_t *is_root, int64_t *nnz_N);
+
 /* ---- a5/a6: inject (Sec. 3.6, Eq. root-nodeform, Eq. Tproj) -------------
  * Bc[m*a + c, :] = B[m*roots[a] + c, :] (n_agg*m x nB, row-major).
  * T (aligned with N): root rows exactly 1; F row i in aggregate a gets
@@ -205,7 +242,8 @@ rn_status rn_tentative(rn_ctx *ctx, int32_t n, int32_t block_m,
  * it is always kept and is not an off entry.  With k > 0, off entries below
  * the k-th largest off magnitude of the row are dropped; with theta > 0, off
  * entries below theta times the largest (both: either rule drops); ties
- * are kept.  Rows of nodes with is_root set are kept whole.
+ * are kept.  Rows of nodes with is_root set are kept whole (is_root may be
+ * NULL: no such rows, as for the nodal pattern of the pre-filter).
  * TWO-PHASE.  Phase 1 (F_colind NULL) writes F_rowptr (n+1) and *nnz_F
  * (host); phase 2 (same arguments, F_colind non-NULL) writes the kept
  * columns into F_colind and, when F_vals is non-NULL, their values, in

@@ -328,6 +328,51 @@ class Context:
                                          C.byref(rd)), "rn_tentative")
         return T[:Nj.numel()], Bc[:block_m * n_agg], rd.value
 
+    # -- pre-filter (Sec. 3.5): valued strength and pattern ---------------------
+    def strength_values(self, A: DeviceCSR, theta: float, Sp, Sj):
+        """rn_strength_values: Eq. soc values on the node graph (Sp, Sj)."""
+        Sv = self.torch.empty(max(Sj.numel(), 1), dtype=self.torch.float64, device="cuda")
+        d = A.desc()
+        self._check(L.lib().rn_strength_values(self.h, C.byref(d), C.c_double(theta), _ptr(Sp), _ptr(Sj), Sj.numel(),
+                                               _ptr(Sv)), "rn_strength_values")
+        return Sv[:Sj.numel()]
+
+    def pattern_values(self, Sp, Sj, Sv, agg, n_agg: int, degree: int):
+        """rn_pattern_values: (Np, Nj, Nv) of the valued nodal N = S^d C."""
+        torch = self.torch
+        nn = Sp.numel() - 1
+        Np = torch.empty(nn + 1, dtype=torch.int32, device="cuda")
+        nnz = C.c_int64()
+        args = (self.h, nn, _ptr(Sp), _ptr(Sj), _ptr(Sv), Sj.numel(), _ptr(agg), int(n_agg), int(degree))
+        self._check(L.lib().rn_pattern_values(*args, _ptr(Np), None, None, C.byref(nnz)), "rn_pattern_values")
+        Nj = torch.empty(max(nnz.value, 1), dtype=torch.int32, device="cuda")
+        Nv = torch.empty(max(nnz.value, 1), dtype=torch.float64, device="cuda")
+        self._check(L.lib().rn_pattern_values(*args, _ptr(Np), _ptr(Nj), _ptr(Nv), C.byref(nnz)), "rn_pattern_values")
+        return Np, Nj[:nnz.value], Nv[:nnz.value]
+
+    def pattern_dofs(self, Nnp, Nnj, agg, roots, block_m: int):
+        """rn_pattern_dofs: (Np, Nj, is_root) of a given nodal pattern."""
+        torch = self.torch
+        nn = Nnp.numel() - 1
+        n = nn * block_m
+        Np = torch.empty(n + 1, dtype=torch.int32, device="cuda")
+        is_root = torch.empty(max(n, 1), dtype=torch.uint8, device="cuda")
+        nnz = C.c_int64()
+        args = (self.h, nn, _ptr(Nnp), _ptr(Nnj), Nnj.numel(), _ptr(agg), _ptr(roots), int(roots.numel()), block_m)
+        self._check(L.lib().rn_pattern_dofs(*args, _ptr(Np), None, _ptr(is_root), C.byref(nnz)), "rn_pattern_dofs")
+        Nj = torch.empty(max(nnz.value, 1), dtype=torch.int32, device="cuda")
+        self._check(L.lib().rn_pattern_dofs(*args, _ptr(Np), _ptr(Nj), _ptr(is_root), C.byref(nnz)), "rn_pattern_dofs")
+        return Np, Nj[:nnz.value], is_root[:n]
+
+    def prefiltered_pattern(self, A: DeviceCSR, theta: float, Sp, Sj, agg, roots, degree: int, k=0, theta_f=0.0):
+        """The pattern lines of Alg. root_node_setup with the pre-filter (Sec. 3.5):
+        N = S^d C with Eq. soc values, filter on node rows, unamalgamate, root rows.
+        Returns (Np, Nj, is_root)."""
+        Sv = self.strength_values(A, theta, Sp, Sj)
+        Vp, Vj, Vv = self.pattern_values(Sp, Sj, Sv, agg, int(roots.numel()), degree)
+        Fp, Fj, _ = self.filter(Vp, Vj, None, agg, Vv, 1, k, theta_f)
+        return self.pattern_dofs(Fp, Fj, agg, roots, A.block_m)
+
     # -- filter / enforce (Sec. 3.5, Sec. 3.7) ---------------------------------
     def filter(self, Np, Nj, is_root, agg, vals, block_m=1, k=0, theta=0.0):
         """rn_filter: (F_rowptr, F_colind, F_vals) of the kept entries."""

@@ -58,6 +58,9 @@ SIGNATURES = {
     "rn_last_error": (C.c_char_p, [_vp]),
     "rn_version": (C.c_char_p, []),
     "rn_strength": (_i32, [_vp, C.POINTER(rn_matrix), _d, _vp, _vp, _pi64]),
+    "rn_strength_values": (_i32, [_vp, C.POINTER(rn_matrix), _d, _vp, _vp, _i64, _vp]),
+    "rn_pattern_values": (_i32, [_vp, _i32, _vp, _vp, _vp, _i64, _vp, _i32, _i32, _vp, _vp, _vp, _pi64]),
+    "rn_pattern_dofs": (_i32, [_vp, _i32, _vp, _vp, _i64, _vp, _vp, _i32, _i32, _vp, _vp, _vp, _pi64]),
     "rn_aggregate_host": (_i32, [_i32, _vp, _vp, _vp, _vp, _pi32]),
     "rn_pattern": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp, _i32, _i32, _i32, _vp, _vp, _vp, _pi64]),
     "rn_tentative": (_i32, [_vp, _i32, _i32, _vp, _vp, _i64, _vp, _vp, _vp, _i32, _vp, _i32, _vp, _vp, _pi32]),

@@ -50,8 +50,9 @@ __global__ __launch_bounds__(RN_BLOCK) void k_filter_mark(int32_t n, int64_t nnz
   }
   const int i = lo, I = i / M, i0 = M * I;
   bool root = false;
+  if (is_root)
 #pragma unroll
-  for (int c = 0; c < M; ++c) root = root || is_root[i0 + c] != 0;
+    for (int c = 0; c < M; ++c) root = root || is_root[i0 + c] != 0;
   const int q = (int)(e - Np[i]) / M;
   const int own = agg[I];
   if (root || Nj[(int64_t)Np[i0] + (int64_t)M * q] / M == own) {
@@ -83,7 +84,8 @@ __global__ __launch_bounds__(RN_BLOCK) void k_filter_check_blocks(int32_t nn, in
   const int I = blockIdx.x * RN_BLOCK + threadIdx.x;
   if (I >= nn || *guard) return;
   bool root = false;
-  for (int c = 0; c < m; ++c) root = root || is_root[m * I + c] != 0;
+  if (is_root)
+    for (int c = 0; c < m; ++c) root = root || is_root[m * I + c] != 0;
   if (root) return;
   const int l0 = Np[m * I + 1] - Np[m * I];
   bool bad = l0 % m != 0;
@@ -135,7 +137,7 @@ extern "C" rn_status rn_filter(rn_ctx *ctx, int32_t n, int32_t block_m, const in
   if ((m != 1 && m != 2) || n < 0 || n % m || nnz_N < 0 || k < 0 || !(theta >= 0.0) || !nnz_F)
     return rn_fail(ctx, RN_EINVAL, "rn_filter: bad argument (n %d, block_m %d, k %d, theta %g)", n, m, k, theta);
   if (nnz_N >= ((int64_t)1 << 31)) return rn_fail(ctx, RN_ELIMIT, "rn_filter: nnz_N >= 2^31");
-  if (n > 0 && (!N_rowptr || !is_root || !agg || !F_rowptr)) return rn_fail(ctx, RN_EINVAL, "rn_filter: null argument");
+  if (n > 0 && (!N_rowptr || !agg || !F_rowptr)) return rn_fail(ctx, RN_EINVAL, "rn_filter: null argument");
   if (nnz_N > 0 && (!N_colind || !vals)) return rn_fail(ctx, RN_EINVAL, "rn_filter: null argument");
   rn_status st = RN_OK;
   uint8_t *keep = (uint8_t *)rn_scratch(ctx, SLOT_FLT_KEEP, (size_t)nnz_N + 1, &st);

@@ -115,6 +115,10 @@ struct rn_ctx {
   int64_t gal_nnz = -1;
   const int32_t *gal_R[2] = {nullptr, nullptr}, *gal_AP[2] = {nullptr, nullptr};
   const double *gal_Rv = nullptr, *gal_APv = nullptr;
+  int32_t pv_nn = -1;          // rn_pattern_values: phase 1's last level (scratch)
+  int64_t pv_nnz = -1;
+  const int32_t *pv_j = nullptr;
+  const double *pv_v = nullptr;
   // live plans made on this context: rn_destroy detaches them, so a plan
   // destroyed after its context frees its memory without touching the context
   std::vector<rn_plan *> plans;

@@ -1003,3 +1003,177 @@ rn_status rn_strength_pattern(rn_ctx *ctx, const rn_matrix *A, double theta, int
   *done = true;
   return RN_OK;
 }
+
+// ---------------------------------------------------------------------------
+// strength values (Eq. soc) and the DOF pattern of a given nodal pattern
+// ---------------------------------------------------------------------------
+// position of column c in the sorted row [s, e) of Aj, or -1
+__device__ inline int find_sorted(const int32_t *__restrict__ Aj, int s, int e, int c) {
+  int a = s, b = e;
+  while (a < b) {
+    const int mid = (a + b) >> 1;
+    if (Aj[mid] < c) a = mid + 1; else b = mid;
+  }
+  return (a < e && Aj[a] == c) ? a : -1;
+}
+
+// One lane per entry (I, J) of S: the largest |a| over the strong DOF
+// entries of blocks (I, J) and (J, I) of A (M x M blocks, row-major); the
+// diagonal entry gets 1.  Rows are normalised by k_sval_norm.
+template <int M>
+__global__ __launch_bounds__(RN_BLOCK) void k_sval(int32_t nn, int64_t nnzS, const int32_t *__restrict__ Sp,
+                                                  const int32_t *__restrict__ Sj, const int32_t *__restrict__ Ap,
+                                                  const int32_t *__restrict__ Aj, const double *__restrict__ Ax,
+                                                  const double *__restrict__ diag, double th2,
+                                                  double *__restrict__ Sv, const int32_t *__restrict__ guard) {
+  const int64_t e = (int64_t)blockIdx.x * RN_BLOCK + threadIdx.x;
+  if (e >= nnzS || *guard) return;
+  int lo = 0, hi = nn;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if ((int64_t)Sp[mid] <= e) lo = mid; else hi = mid;
+  }
+  const int I = lo, J = Sj[e];
+  if (I == J) {
+    Sv[e] = 1.0;
+    return;
+  }
+  double v = 0.0;
+  const int p = find_sorted(Aj, Ap[I], Ap[I + 1], J);
+  if (p >= 0)
+#pragma unroll
+    for (int r = 0; r < M; ++r)
+#pragma unroll
+      for (int c = 0; c < M; ++c) {
+        const double a = Ax[(int64_t)p * M * M + r * M + c];
+        if (rn_is_strong(a, diag[M * I + r], diag[M * J + c], th2, false)) v = fmax(v, fabs(a));
+      }
+  const int q = find_sorted(Aj, Ap[J], Ap[J + 1], I);
+  if (q >= 0)
+#pragma unroll
+    for (int r = 0; r < M; ++r)
+#pragma unroll
+      for (int c = 0; c < M; ++c) {
+        const double a = Ax[(int64_t)q * M * M + r * M + c];
+        if (rn_is_strong(a, diag[M * J + r], diag[M * I + c], th2, false)) v = fmax(v, fabs(a));
+      }
+  Sv[e] = v;
+}
+
+// Eq. soc: each row divided by its largest off-diagonal value (rows whose off
+// values are all 0 keep them), diagonal 1.
+__global__ __launch_bounds__(RN_BLOCK) void k_sval_norm(int32_t nn, const int32_t *__restrict__ Sp,
+                                                       const int32_t *__restrict__ Sj, double *__restrict__ Sv,
+                                                       const int32_t *__restrict__ guard) {
+  const int I = blockIdx.x * RN_BLOCK + threadIdx.x;
+  if (I >= nn || *guard) return;
+  double mx = 0.0;
+  for (int q = Sp[I]; q < Sp[I + 1]; ++q)
+    if (Sj[q] != I) mx = fmax(mx, Sv[q]);
+  for (int q = Sp[I]; q < Sp[I + 1]; ++q)
+    if (Sj[q] != I && mx > 0.0) Sv[q] = Sv[q] / mx;
+}
+
+extern "C" rn_status rn_strength_values(rn_ctx *ctx, const rn_matrix *A, double theta, const int32_t *S_rowptr,
+                                        const int32_t *S_colind, int64_t nnz_S, double *S_vals) {
+  if (!ctx) return RN_EINVAL;
+  ctx->err.clear();
+  if (!A || !S_rowptr) return rn_fail(ctx, RN_EINVAL, "rn_strength_values: null argument");
+  const int m = A->block_m;
+  if ((m != 1 && m != 2) || A->n < 0 || A->n % m || A->nnz < 0 || !A->rowptr || (A->nnz && (!A->colind || !A->vals)))
+    return rn_fail(ctx, RN_EINVAL, "rn_strength_values: bad matrix descriptor");
+  if (!(theta >= 0.0) || nnz_S < 0 || (nnz_S > 0 && (!S_colind || !S_vals)))
+    return rn_fail(ctx, RN_EINVAL, "rn_strength_values: bad argument");
+  if (A->nnz >= ((int64_t)1 << 31) || nnz_S >= ((int64_t)1 << 31))
+    return rn_fail(ctx, RN_ELIMIT, "rn_strength_values: 2^31 entries or more");
+  const int nn = A->n / m;
+  rn_status st = RN_OK;
+  int32_t *guard = rn_guard_begin(ctx, &st);
+  if (!guard) return st;
+  double *diag = (double *)rn_scratch(ctx, SLOT_STR_DIAG, (size_t)(A->n + 1) * sizeof(double), &st);
+  if (!diag) return st;
+  RnChecks v{};
+  v.csr[0] = {nn, nn, A->nnz, A->rowptr, A->colind, GUARD_A};
+  v.csr[1] = {nn, nn, nnz_S, S_rowptr, S_colind, GUARD_S};
+  v.ncsr = 2;
+  RN_TRY(rn_validate(ctx, v, guard));
+  if (nn > 0) {
+    if (m == 1)
+      hipLaunchKernelGGL(k_diag_csr, dim3(rn_div_up(nn, RN_BLOCK)), dim3(RN_BLOCK), 0, ctx->stream, nn, A->rowptr,
+                         A->colind, A->vals, diag, guard);
+    else
+      hipLaunchKernelGGL(k_diag_bsr, dim3(rn_div_up(nn, RN_BLOCK)), dim3(RN_BLOCK), 0, ctx->stream, nn, A->rowptr,
+                         A->colind, A->vals, diag, guard);
+    LAUNCH_CHECK(ctx);
+  }
+  const double th2 = theta * theta;
+  if (nnz_S > 0) {
+    const dim3 g(rn_div_up(nnz_S, RN_BLOCK)), b(RN_BLOCK);
+    if (m == 1)
+      hipLaunchKernelGGL(k_sval<1>, g, b, 0, ctx->stream, nn, nnz_S, S_rowptr, S_colind, A->rowptr, A->colind,
+                         A->vals, diag, th2, S_vals, guard);
+    else
+      hipLaunchKernelGGL(k_sval<2>, g, b, 0, ctx->stream, nn, nnz_S, S_rowptr, S_colind, A->rowptr, A->colind,
+                         A->vals, diag, th2, S_vals, guard);
+    LAUNCH_CHECK(ctx);
+    hipLaunchKernelGGL(k_sval_norm, dim3(rn_div_up(nn, RN_BLOCK)), dim3(RN_BLOCK), 0, ctx->stream, nn, S_rowptr,
+                       S_colind, S_vals, guard);
+    LAUNCH_CHECK(ctx);
+  }
+  return rn_check_guard(ctx, guard, "rn_strength_values");
+}
+
+extern "C" rn_status rn_pattern_dofs(rn_ctx *ctx, int32_t nn, const int32_t *Nn_rowptr, const int32_t *Nn_colind,
+                                     int64_t nnz_Nn, const int32_t *agg, const int32_t *roots, int32_t n_agg,
+                                     int32_t m, int32_t *N_rowptr, int32_t *N_colind, uint8_t *is_root,
+                                     int64_t *nnz_N) {
+  if (!ctx) return RN_EINVAL;
+  ctx->err.clear();
+  if (!nnz_N || !N_rowptr || (nn > 0 && (!Nn_rowptr || !agg || !is_root)) || (n_agg > 0 && !roots) ||
+      (nnz_Nn > 0 && !Nn_colind))
+    return rn_fail(ctx, RN_EINVAL, "rn_pattern_dofs: null argument");
+  if (nn < 0 || n_agg < 0 || nnz_Nn < 0 || (m != 1 && m != 2))
+    return rn_fail(ctx, RN_EINVAL, "rn_pattern_dofs: bad size (n_nodes %d, n_agg %d, m %d)", nn, n_agg, m);
+  if ((int64_t)nn * m >= ((int64_t)1 << 31) || nnz_Nn >= ((int64_t)1 << 31))
+    return rn_fail(ctx, RN_ELIMIT, "rn_pattern_dofs: 2^31 rows or entries");
+  const int n = nn * m;
+  XRows X{Nn_rowptr, Nn_colind, nullptr, 0};
+  if (N_colind) {  // phase 2
+    if (ctx->pat_nnz < 0 || ctx->pat_n != n || ctx->pat_m != m)
+      return rn_fail(ctx, RN_EINVAL, "rn_pattern_dofs: phase 2 without a matching phase 1");
+    if (n > 0) {
+      hipLaunchKernelGGL(k_dof_fill, dim3(rn_div_up(n, SRPB)), dim3(RN_BLOCK), 0, ctx->stream, n, m, X, agg,
+                         N_rowptr, is_root, N_colind);
+      LAUNCH_CHECK(ctx);
+    }
+    *nnz_N = ctx->pat_nnz;
+    ctx->pat_nnz = -1;
+    return RN_OK;
+  }
+  rn_status st = RN_OK;
+  int32_t *cnt = (int32_t *)rn_scratch(ctx, SLOT_PAT_CNT, (size_t)(n + 1) * sizeof(int32_t), &st);
+  if (!cnt) return st;
+  int32_t *guard = rn_guard_begin(ctx, &st);
+  if (!guard) return st;
+  RnChecks v{};
+  v.csr[0] = {nn, n_agg, nnz_Nn, Nn_rowptr, Nn_colind, GUARD_N};
+  v.ncsr = 1;
+  v.range[0] = {nn, agg, 0, n_agg, GUARD_AGG};
+  v.range[1] = {n_agg, roots, 0, nn, GUARD_ROOTS};
+  v.nrange = 2;
+  RN_TRY(rn_validate(ctx, v, guard));
+  if (n > 0) {
+    hipLaunchKernelGGL(k_dof_count, dim3(rn_div_up(n, RN_BLOCK)), dim3(RN_BLOCK), 0, ctx->stream, n, m, X, agg, roots,
+                       n_agg, cnt, is_root, guard, guard);
+    LAUNCH_CHECK(ctx);
+  }
+  RN_TRY(rn_scan_counts(ctx, cnt, N_rowptr, n, nullptr));
+  int64_t total = 0;
+  RN_TRY(rn_read_guard_i64(ctx, guard, ctx->slot[SLOT_SCAN_TOTAL].ptr, &total, "rn_pattern_dofs"));
+  if (total >= ((int64_t)1 << 31)) return rn_fail(ctx, RN_ELIMIT, "rn_pattern_dofs: pattern nnz reaches 2^31");
+  ctx->pat_nnz = total;
+  ctx->pat_n = n;
+  ctx->pat_m = m;
+  *nnz_N = total;
+  return RN_OK;
+}

@@ -314,3 +314,87 @@ extern "C" rn_status rn_galerkin(rn_ctx *ctx, const rn_matrix *A, int32_t n_cols
   ctx->gal_APv = APv;
   return RN_OK;
 }
+
+// ---------------------------------------------------------------------------
+// valued pattern N = S^d C (Sec. 3.4 with the values of Eq. soc)
+// ---------------------------------------------------------------------------
+// C as CSR: row I holds (agg[I], 1).
+__global__ __launch_bounds__(RN_BLOCK) void k_agg_csr(int32_t nn, const int32_t *__restrict__ agg,
+                                                     int32_t *__restrict__ Cp, int32_t *__restrict__ Cj,
+                                                     double *__restrict__ Cv) {
+  const int I = blockIdx.x * RN_BLOCK + threadIdx.x;
+  if (I > nn) return;
+  Cp[I] = I;
+  if (I < nn) {
+    Cj[I] = agg[I];
+    Cv[I] = 1.0;
+  }
+}
+
+extern "C" rn_status rn_pattern_values(rn_ctx *ctx, int32_t nn, const int32_t *S_rowptr, const int32_t *S_colind,
+                                       const double *S_vals, int64_t nnz_S, const int32_t *agg, int32_t n_agg,
+                                       int32_t degree, int32_t *Nn_rowptr, int32_t *Nn_colind, double *Nn_vals,
+                                       int64_t *nnz_Nn) {
+  if (!ctx) return RN_EINVAL;
+  ctx->err.clear();
+  if (nn < 0 || n_agg < 0 || degree < 0 || nnz_S < 0 || !nnz_Nn || !Nn_rowptr)
+    return rn_fail(ctx, RN_EINVAL, "rn_pattern_values: bad argument");
+  if ((nn > 0 && (!S_rowptr || !agg)) || (nnz_S > 0 && (!S_colind || !S_vals)))
+    return rn_fail(ctx, RN_EINVAL, "rn_pattern_values: null argument");
+  if (nnz_S >= ((int64_t)1 << 31)) return rn_fail(ctx, RN_ELIMIT, "rn_pattern_values: nnz_S >= 2^31");
+  rn_status st = RN_OK;
+  if (Nn_colind) {  // phase 2: copy out the last level phase 1 left
+    if (ctx->pv_nn != nn || !ctx->pv_j) return rn_fail(ctx, RN_EINVAL, "rn_pattern_values: phase 2 without phase 1");
+    if (ctx->pv_nnz > 0) {
+      HIP_TRY(ctx, hipMemcpyAsync(Nn_colind, ctx->pv_j, (size_t)ctx->pv_nnz * sizeof(int32_t),
+                                  hipMemcpyDeviceToDevice, ctx->stream));
+      if (Nn_vals)
+        HIP_TRY(ctx, hipMemcpyAsync(Nn_vals, ctx->pv_v, (size_t)ctx->pv_nnz * sizeof(double),
+                                    hipMemcpyDeviceToDevice, ctx->stream));
+    }
+    *nnz_Nn = ctx->pv_nnz;
+    ctx->pv_nn = -1;
+    return RN_OK;
+  }
+  int32_t *guard = rn_guard_begin(ctx, &st);
+  if (!guard) return st;
+  RnChecks v{};
+  v.csr[0] = {nn, nn, nnz_S, S_rowptr, S_colind, GUARD_S};
+  v.ncsr = 1;
+  v.range[0] = {nn, agg, 0, n_agg, GUARD_AGG};
+  v.nrange = 1;
+  RN_TRY(rn_validate(ctx, v, guard));
+  // X_0 = C, then X_t = S X_(t-1) in alternating scratch slots
+  int32_t *Xp = (int32_t *)rn_scratch(ctx, SLOT_GAL_RP, (size_t)(nn + 1) * sizeof(int32_t), &st);
+  int32_t *Xj = (int32_t *)rn_scratch(ctx, SLOT_GAL_RJ, (size_t)(nn + 1) * sizeof(int32_t), &st);
+  double *Xv = (double *)rn_scratch(ctx, SLOT_GAL_RV, (size_t)(nn + 1) * sizeof(double), &st);
+  if (!Xp || !Xj || !Xv) return st;
+  hipLaunchKernelGGL(k_agg_csr, dim3(rn_div_up(nn + 1, RN_BLOCK)), dim3(RN_BLOCK), 0, ctx->stream, nn, agg, Xp, Xj,
+                     Xv);
+  LAUNCH_CHECK(ctx);
+  int64_t nnzX = nn;
+  const int slots[2][3] = {{SLOT_GAL_APP, SLOT_GAL_APJ, SLOT_GAL_APV}, {SLOT_GAL_RP, SLOT_GAL_RJ, SLOT_GAL_RV}};
+  for (int t = 0; t < degree; ++t) {
+    const int *sl = slots[t % 2];
+    int32_t *Yp = nullptr, *Yj = nullptr;
+    double *Yv = nullptr;
+    int64_t nnzY = 0;
+    RN_TRY(sg_full(ctx, nn, nnz_S, S_rowptr, S_colind, S_vals, Xp, Xj, Xv, sl[0], sl[1], sl[2], &Yp, &Yj, &Yv,
+                   &nnzY, guard, "rn_pattern_values"));
+    Xp = Yp;
+    Xj = Yj;
+    Xv = Yv;
+    nnzX = nnzY;
+  }
+  if (degree == 0) RN_TRY(rn_check_guard(ctx, guard, "rn_pattern_values"));
+  if (nnzX >= ((int64_t)1 << 31)) return rn_fail(ctx, RN_ELIMIT, "rn_pattern_values: pattern nnz reaches 2^31");
+  if (nn >= 0)
+    HIP_TRY(ctx, hipMemcpyAsync(Nn_rowptr, Xp, (size_t)(nn + 1) * sizeof(int32_t), hipMemcpyDeviceToDevice,
+                                ctx->stream));
+  ctx->pv_nn = nn;
+  ctx->pv_nnz = nnzX;
+  ctx->pv_j = Xj;
+  ctx->pv_v = Xv;
+  *nnz_Nn = nnzX;
+  return RN_OK;
+}

@@ -90,3 +90,30 @@ def test_elastic512_spread_of_correct_fp64_evaluations():
     assert s_pair > 2e-12 and s_normal > 2e-12 and s_ulp > 2e-12
     # ... and the elasticity bar sits within a small multiple of the spread
     assert 1.5 * spread <= CS.ELASTIC_FP64_TOL <= 10 * spread
+
+
+@pytest.mark.slow
+def test_elastic512_prefiltered_spread_of_correct_fp64_evaluations():
+    """The same measurement on the pattern pre-filtered with theta_f = 0.2
+    (Sec. 3.5), where two rows become rank-deficient: the least squares of
+    those rows (pseudo-inverse through the cutoff) differ between the
+    Householder and normal-equation evaluations."""
+    c0 = CS.case("elastic512")
+    A = c0["A"]
+    st = O.prefilter_setup(A, c0["B"], 2, c0["theta"], 2, theta_f=0.2, agg=c0["agg"], roots=c0["roots"])
+    K = c0["iters"]
+    P, info = O.emin_cg(A.rowptr, A.colind, A.vals, st["Np"], st["Nj"], st["is_root"], st["nc"], st["Bc"], 3,
+                        st["T"], K)
+    c = dict(A=A, Np=st["Np"], Nj=st["Nj"], nc=st["nc"], is_root=st["is_root"], Bc=st["Bc"], T=st["T"], P=P)
+    Gq, rd = O.gram_rows(c["Np"], c["Nj"], c["is_root"], c["Bc"], 3)
+    assert rd == 2
+    scale = float(np.max(np.abs(P)))
+    shift = lambda Q: float(np.max(np.abs(Q - P))) / scale
+    pairwise = lambda x, y: float(np.sum(x * y))
+    s_pair = shift(_driver(c, Gq, pairwise)(K))
+    s_normal = shift(_driver(c, _normal_equation_pinv(c), pairwise)(K))
+    s_ulp = shift(_driver(c, Gq, pairwise)(K, bump_alpha0=True))
+    spread = max(s_pair, s_normal, s_ulp)
+    print(f"pre-filtered elastic512 FP64 spread: pairwise {s_pair:.3e}, normal equations {s_normal:.3e}, "
+          f"alpha_0 + 1 ulp {s_ulp:.3e}; bar {CS.ELASTIC_PREFILTER_FP64_TOL:.1e}")
+    assert 1.5 * spread <= CS.ELASTIC_PREFILTER_FP64_TOL <= 10 * spread
