@@ -61,6 +61,9 @@ def lib():
         L.orc_filter.argtypes = [i, i, _i32p, _i32p, _f64p, vp, _i32p, i, d, _u8p]
         L.orc_compact.argtypes = [i, _i32p, _i32p, vp, _u8p, _i32p, _i32p, vp]
         L.orc_strength_values.argtypes = [i, _i32p, _i32p, _f64p, i, d, _i32p, _i32p, _f64p]
+        L.orc_smooth_candidates.argtypes = [i, _i32p, _i32p, _f64p, _f64p, i, i, d]
+        L.orc_emin_pcg.argtypes = L.orc_emin_cg.argtypes
+        L.orc_emin_cgnr.argtypes = L.orc_emin_cg.argtypes
         L.orc_spgemm.argtypes = [i, i, i, _i32p, _i32p, vp, _i32p, _i32p, vp, _i32p, _i32p, vp, C.c_long]
         _lib = L
     return _lib
@@ -183,15 +186,17 @@ def masked_product(Ap, Aj, Ax, Np, Nj, nc, X):
     return Z
 
 
-def emin_cg(Ap, Aj, Ax, Np, Nj, is_root, nc, Bc, nB, T, K):
-    """K CG steps; returns (P, info) with gamma/delta/alpha histories."""
+def emin_cg(Ap, Aj, Ax, Np, Nj, is_root, nc, Bc, nB, T, K, variant="cg"):
+    """K CG steps (variant "cg", Jacobi-preconditioned "pcg", or the normal
+    equations "cgnr"); returns (P, info) with gamma/delta/alpha histories."""
+    fn = {"cg": lib().orc_emin_cg, "pcg": lib().orc_emin_pcg, "cgnr": lib().orc_emin_cgnr}[variant]
     n = Np.size - 1
     P = np.zeros(int(Np[-1]))
     gam = np.zeros(K + 1)
     dl = np.zeros(max(K, 1))
     al = np.zeros(max(K, 1))
     it = C.c_int(0)
-    rc = lib().orc_emin_cg(n, int(nc), _i32(Ap), _i32(Aj), _f64(Ax), _i32(Np), _i32(Nj),
+    rc = fn(n, int(nc), _i32(Ap), _i32(Aj), _f64(Ax), _i32(Np), _i32(Nj),
                            np.ascontiguousarray(is_root, np.uint8),
                            _f64(Bc).ravel() if nB else np.zeros(1), nB, _f64(T), int(K), P,
                            gam, dl, al, C.byref(it))
@@ -378,3 +383,23 @@ def prefilter_setup(A, B, m, theta, degree, k=0, theta_f=0.0, agg=None, roots=No
     T, Bc, rd = tentative(Np, Nj, is_root, agg, roots, m, B)
     return dict(Sp=Sp, Sj=Sj, Sx=Sx, agg=agg, roots=roots, Vp=Vp, Vj=Vj, Vx=Vx, Npn=Npn, Njn=Njn, Np=Np, Nj=Nj,
                 is_root=is_root, T=T, Bc=Bc, nc=m * roots.size, rank_def=rd)
+
+
+def smooth_candidates(Ap, Aj, Ax, B, sweeps, omega):
+    """`sweeps` damped Jacobi sweeps on A B = 0 applied to a copy of B."""
+    B = _f64(B).copy()
+    if B.ndim == 1:
+        B = B[:, None].copy()
+    rc = lib().orc_smooth_candidates(_i32(Ap).size - 1, _i32(Ap), _i32(Aj), _f64(Ax), B, B.shape[1], int(sweeps),
+                                     float(omega))
+    if rc < 0:
+        raise OracleError(rc, "smooth_candidates")
+    return B
+
+
+def emin_pcg(Ap, Aj, Ax, Np, Nj, is_root, nc, Bc, nB, T, K):
+    return emin_cg(Ap, Aj, Ax, Np, Nj, is_root, nc, Bc, nB, T, K, variant="pcg")
+
+
+def emin_cgnr(Ap, Aj, Ax, Np, Nj, is_root, nc, Bc, nB, T, K):
+    return emin_cg(Ap, Aj, Ax, Np, Nj, is_root, nc, Bc, nB, T, K, variant="cgnr")

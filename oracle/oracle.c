@@ -1064,3 +1064,193 @@ int orc_strength_values(int n, const int *Ap, const int *Aj, const double *Ax, i
   free(diag);
   return ORC_OK;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Candidate smoothing, the smooth line of Alg. root_node_setup (Sec. 3.1): */
+/* relaxation sweeps on A B = 0, here damped Jacobi (reading R28):          */
+/* B <- B - omega D^-1 A B, all nB columns, the row sums of A B taken in    */
+/* the order of A's row.  A is scalar CSR; D its diagonal.                  */
+/* ------------------------------------------------------------------------ */
+int orc_smooth_candidates(int n, const int *Ap, const int *Aj, const double *Ax,
+                          double *B, int nB, int sweeps, double omega) {
+  if (nB < 1 || sweeps < 0) return ORC_EINVAL;
+  double *d = (double *)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
+  double *Bn = (double *)malloc((size_t)(n > 0 ? n : 1) * nB * sizeof(double));
+  for (int i = 0; i < n; ++i)
+    for (int p = Ap[i]; p < Ap[i + 1]; ++p)
+      if (Aj[p] == i) d[i] = Ax[p];
+  for (int i = 0; i < n; ++i)
+    if (d[i] == 0.0) { free(d); free(Bn); return ORC_ESINGULAR; }
+  for (int sw = 0; sw < sweeps; ++sw) {
+    for (int i = 0; i < n; ++i)
+      for (int q = 0; q < nB; ++q) {
+        double y = 0.0;
+        for (int p = Ap[i]; p < Ap[i + 1]; ++p) y += Ax[p] * B[(long)Aj[p] * nB + q];
+        Bn[(long)i * nB + q] = B[(long)i * nB + q] - omega * (y / d[i]);
+      }
+    memcpy(B, Bn, (size_t)n * nB * sizeof(double));
+  }
+  free(d);
+  free(Bn);
+  return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* improve by Jacobi-preconditioned CG (reading R29): CG on the same energy */
+/* with the preconditioner Y = Pi(D^-1 R), D = diag(A) scaling each row of  */
+/* the residual (Pi D^-1 Pi is symmetric positive definite on V when A's    */
+/* diagonal is positive, so the iteration minimises the same E(P) over the */
+/* preconditioned Krylov space).  gam holds <R_k, Y_k>.                     */
+/* ------------------------------------------------------------------------ */
+static void precondition(int n, const int *Ap, const int *Aj, const double *Ax, const int *Np,
+                         const int *Nj, const unsigned char *is_root, const double *Bc, int nB,
+                         const double *Gp, const double *R, double *Y) {
+  for (int i = 0; i < n; ++i) {
+    double d = 0.0;
+    for (int p = Ap[i]; p < Ap[i + 1]; ++p)
+      if (Aj[p] == i) d = Ax[p];
+    for (int p = Np[i]; p < Np[i + 1]; ++p) Y[p] = R[p] / d;
+  }
+  orc_project(n, Np, Nj, is_root, Bc, nB, Gp, Y);
+}
+
+int orc_emin_pcg(int n, int nc, const int *Ap, const int *Aj, const double *Ax,
+                 const int *Np, const int *Nj, const unsigned char *is_root,
+                 const double *Bc, int nB, const double *T, int K, double *P,
+                 double *gam, double *del, double *alp, int *iters) {
+  long nz = Np[n];
+  size_t sz = (size_t)(nz > 0 ? nz : 1) * sizeof(double);
+  double *R = (double *)malloc(sz), *D = (double *)malloc(sz), *Z = (double *)malloc(sz);
+  double *Y = (double *)malloc(sz);
+  double *Gp = (double *)malloc((size_t)n * (nB > 0 ? nB * nB : 1) * sizeof(double));
+  orc_gram_rows(n, Np, Nj, is_root, Bc, nB, Gp);
+  memcpy(P, T, (size_t)nz * sizeof(double));
+  orc_masked_product(n, nc, Ap, Aj, Ax, Np, Nj, P, Z);
+  orc_project(n, Np, Nj, is_root, Bc, nB, Gp, Z);
+  for (long p = 0; p < nz; ++p) R[p] = -Z[p];
+  precondition(n, Ap, Aj, Ax, Np, Nj, is_root, Bc, nB, Gp, R, Y);
+  memcpy(D, Y, (size_t)nz * sizeof(double));
+  double g = dot(nz, R, Y);
+  const double g0 = g;
+  if (gam) gam[0] = g;
+  int rc = ORC_OK, it = 0;
+  if (!isfinite(g)) rc = ORC_ENONFINITE;
+  for (int k = 0; k < K && rc == ORC_OK; ++k) {
+    if (g <= CG_STOP * g0) break;
+    orc_masked_product(n, nc, Ap, Aj, Ax, Np, Nj, D, Z);
+    orc_project(n, Np, Nj, is_root, Bc, nB, Gp, Z);
+    double dl = dot(nz, D, Z);
+    if (del) del[k] = dl;
+    if (!isfinite(dl)) { rc = ORC_ENONFINITE; break; }
+    if (dl <= 0.0) { rc = ORC_EBREAKDOWN; break; }
+    double al = g / dl;
+    if (alp) alp[k] = al;
+    for (long p = 0; p < nz; ++p) {
+      P[p] += al * D[p];
+      R[p] -= al * Z[p];
+    }
+    precondition(n, Ap, Aj, Ax, Np, Nj, is_root, Bc, nB, Gp, R, Y);
+    double gn = dot(nz, R, Y);
+    if (gam) gam[k + 1] = gn;
+    if (!isfinite(gn)) { rc = ORC_ENONFINITE; break; }
+    double be = gn / g;
+    g = gn;
+    for (long p = 0; p < nz; ++p) D[p] = Y[p] + be * D[p];
+    ++it;
+  }
+  if (iters) *iters = it;
+  free(R); free(D); free(Z); free(Y); free(Gp);
+  return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* improve by CGNR (Sec. 4.2: energy minimisation in the A*A norm for a     */
+/* non-symmetric A): minimise ||A P||_F^2 = trace(P^T A^T A P), the product */
+/* A P taken whole (not kept to N), over P in T + V.  The gradient          */
+/* direction is -Pi(A^T (A P)) kept to N; CG on Pi A^T A Pi.                */
+/* ------------------------------------------------------------------------ */
+/* Z = (A^T W) on the pattern N, W a CSR matrix on any pattern. */
+static void masked_product_gen(int n, int nc, const int *Tp, const int *Tj, const double *Tx,
+                               const int *Wp, const int *Wj, const double *Wx, const int *Np,
+                               const int *Nj, double *Z) {
+  double *acc = (double *)calloc((size_t)(nc > 0 ? nc : 1), sizeof(double));
+  for (int i = 0; i < n; ++i) {
+    for (int t = Tp[i]; t < Tp[i + 1]; ++t) {
+      const int k = Tj[t];
+      for (int q = Wp[k]; q < Wp[k + 1]; ++q) acc[Wj[q]] += Tx[t] * Wx[q];
+    }
+    for (int p = Np[i]; p < Np[i + 1]; ++p) Z[p] = acc[Nj[p]];
+    for (int t = Tp[i]; t < Tp[i + 1]; ++t) {
+      const int k = Tj[t];
+      for (int q = Wp[k]; q < Wp[k + 1]; ++q) acc[Wj[q]] = 0.0;
+    }
+  }
+  free(acc);
+}
+
+/* Z = Pi(A^T (A X)): the full product W = A X (orc_spgemm), then A^T W kept
+ * to N, then the projection. */
+static void normal_product(int n, int nc, const int *Ap, const int *Aj, const double *Ax,
+                           const int *Tp, const int *Tj, const double *Tx, const int *Np,
+                           const int *Nj, const unsigned char *is_root, const double *Bc, int nB,
+                           const double *Gp, const double *X, int *Wp, int *Wj, double *Wx,
+                           long wcap, double *Z) {
+  orc_spgemm(n, n, nc, Ap, Aj, Ax, Np, Nj, X, Wp, Wj, Wx, wcap);
+  masked_product_gen(n, nc, Tp, Tj, Tx, Wp, Wj, Wx, Np, Nj, Z);
+  orc_project(n, Np, Nj, is_root, Bc, nB, Gp, Z);
+}
+
+int orc_emin_cgnr(int n, int nc, const int *Ap, const int *Aj, const double *Ax,
+                  const int *Np, const int *Nj, const unsigned char *is_root,
+                  const double *Bc, int nB, const double *T, int K, double *P,
+                  double *gam, double *del, double *alp, int *iters) {
+  long nz = Np[n];
+  size_t sz = (size_t)(nz > 0 ? nz : 1) * sizeof(double);
+  double *R = (double *)malloc(sz), *D = (double *)malloc(sz), *Z = (double *)malloc(sz);
+  double *Gp = (double *)malloc((size_t)n * (nB > 0 ? nB * nB : 1) * sizeof(double));
+  const long nzA = Ap[n];
+  int *Tp = (int *)malloc((size_t)(n + 1) * sizeof(int));
+  int *Tj = (int *)malloc((size_t)(nzA > 0 ? nzA : 1) * sizeof(int));
+  double *Tx = (double *)malloc((size_t)(nzA > 0 ? nzA : 1) * sizeof(double));
+  orc_transpose(n, n, Ap, Aj, Ax, Tp, Tj, Tx);
+  /* the pattern of A X has at most nnz(A) max-row(N) entries per row sum */
+  int maxr = 1;
+  for (int i = 0; i < n; ++i) maxr = Np[i + 1] - Np[i] > maxr ? Np[i + 1] - Np[i] : maxr;
+  const long wcap = nzA * (long)maxr + 1;
+  int *Wp = (int *)malloc((size_t)(n + 1) * sizeof(int));
+  int *Wj = (int *)malloc((size_t)wcap * sizeof(int));
+  double *Wx = (double *)malloc((size_t)wcap * sizeof(double));
+  orc_gram_rows(n, Np, Nj, is_root, Bc, nB, Gp);
+  memcpy(P, T, (size_t)nz * sizeof(double));
+  normal_product(n, nc, Ap, Aj, Ax, Tp, Tj, Tx, Np, Nj, is_root, Bc, nB, Gp, P, Wp, Wj, Wx, wcap, Z);
+  for (long p = 0; p < nz; ++p) { R[p] = -Z[p]; D[p] = R[p]; }
+  double g = dot(nz, R, R);
+  const double g0 = g;
+  if (gam) gam[0] = g;
+  int rc = ORC_OK, it = 0;
+  if (!isfinite(g)) rc = ORC_ENONFINITE;
+  for (int k = 0; k < K && rc == ORC_OK; ++k) {
+    if (g <= CG_STOP * g0) break;
+    normal_product(n, nc, Ap, Aj, Ax, Tp, Tj, Tx, Np, Nj, is_root, Bc, nB, Gp, D, Wp, Wj, Wx, wcap, Z);
+    double dl = dot(nz, D, Z);
+    if (del) del[k] = dl;
+    if (!isfinite(dl)) { rc = ORC_ENONFINITE; break; }
+    if (dl <= 0.0) { rc = ORC_EBREAKDOWN; break; }
+    double al = g / dl;
+    if (alp) alp[k] = al;
+    for (long p = 0; p < nz; ++p) {
+      P[p] += al * D[p];
+      R[p] -= al * Z[p];
+    }
+    double gn = dot(nz, R, R);
+    if (gam) gam[k + 1] = gn;
+    if (!isfinite(gn)) { rc = ORC_ENONFINITE; break; }
+    double be = gn / g;
+    g = gn;
+    for (long p = 0; p < nz; ++p) D[p] = R[p] + be * D[p];
+    ++it;
+  }
+  if (iters) *iters = it;
+  free(R); free(D); free(Z); free(Gp); free(Tp); free(Tj); free(Tx); free(Wp); free(Wj); free(Wx);
+  return rc;
+}

@@ -162,6 +162,26 @@ int orc_spgemm(int rows, int inner, int cols, const int *Xp, const int *Xj,
 int orc_strength_values(int n, const int *Ap, const int *Aj, const double *Ax, int m,
                         double theta, const int *Sp, const int *Sj, double *Sx);
 
+/* Candidate smoothing (the smooth line of Alg. root_node_setup): `sweeps`
+ * damped Jacobi sweeps B <- B - omega D^-1 A B on A B = 0 (B: n x nB,
+ * row-major, in place).  ORC_ESINGULAR for a zero diagonal entry. */
+int orc_smooth_candidates(int n, const int *Ap, const int *Aj, const double *Ax,
+                          double *B, int nB, int sweeps, double omega);
+
+/* Jacobi-preconditioned CG energy minimisation: as orc_emin_cg with the
+ * preconditioner Y = Pi(D^-1 R); gam holds <R_k, Y_k>. */
+int orc_emin_pcg(int n, int nc, const int *Ap, const int *Aj, const double *Ax,
+                 const int *Np, const int *Nj, const unsigned char *is_root,
+                 const double *Bc, int nB, const double *T, int K, double *P,
+                 double *gam, double *del, double *alp, int *iters);
+
+/* CGNR energy minimisation (Sec. 4.2, A*A norm): minimises ||A P||_F^2 with
+ * A P taken whole; direction -Pi(A^T (A P)) kept to N. */
+int orc_emin_cgnr(int n, int nc, const int *Ap, const int *Aj, const double *Ax,
+                  const int *Np, const int *Nj, const unsigned char *is_root,
+                  const double *Bc, int nB, const double *T, int K, double *P,
+                  double *gam, double *del, double *alp, int *iters);
+
 /* Tangent-linear (forward-mode) derivative of orc_emin_cg with respect to
  * the stored values of A in direction dAx.  Pattern, T and Bc are constants.
  * Writes P (as orc_emin_cg) and dP.  Returns as orc_emin_cg. */
