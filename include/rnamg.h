@@ -55,7 +55,14 @@ typedef enum {
   RN_ELIMIT = 7       /* a documented size limit was exceeded              */
 } rn_status;
 
-typedef enum { RN_CG = 0, RN_GMRES = 1 } rn_method;
+/* RN_CG: conjugate gradients on the energy trace(P^T A P) (Sec. 4.1, SPD A).
+ * RN_GMRES: unrestarted GMRES on ||Pi(A P)||_F (Sec. 4.2, non-symmetric A).
+ * RN_PCG_JACOBI: RN_CG with the Jacobi preconditioner Y = Pi(D^-1 R), D the
+ *   diagonal of A (positive; RN_ESINGULAR otherwise); FP64.
+ * RN_CGNR: conjugate gradients on ||A P||_F^2 with A P taken whole (the A*A
+ *   norm of Sec. 4.2, CGNR): direction -Pi(A^T (A P)) kept to N; FP64, one
+ *   problem (batch 1); builds the pattern of A N and A^T in the context. */
+typedef enum { RN_CG = 0, RN_GMRES = 1, RN_PCG_JACOBI = 2, RN_CGNR = 3 } rn_method;
 typedef enum { RN_FP64 = 0, RN_FP32_MIXED = 1 } rn_precision;
 
 typedef struct rn_ctx rn_ctx;
@@ -216,6 +223,15 @@ rn_status rn_pattern_dofs(rn_ctx *ctx, int32_t n_nodes,
                           int32_t *N_rowptr, int32_t *N_colind,
                           uint8_t *is_root, int64_t *nnz_N);
 
+/* ---- candidate smoothing (the smooth line of Alg. root_node_setup, Sec. 3.1)
+ * `sweeps` damped Jacobi sweeps on A B = 0, in place on B (n x nB,
+ * row-major, device): B <- B - omega D^-1 A B with D the diagonal of A (the
+ * scalar diagonal for block_m = 2), the sums of A B in the order of A's
+ * rows.  RN_ESINGULAR when a diagonal entry is zero.  Synchronises the
+ * stream. */
+rn_status rn_smooth_candidates(rn_ctx *ctx, const rn_matrix *A, double *B,
+                               int32_t nB, int32_t sweeps, double omega);
+
 /* ---- a5/a6: inject (Sec. 3.6, Eq. root-nodeform, Eq. Tproj) -------------
  * Bc[m*a + c, :] = B[m*roots[a] + c, :] (n_agg*m x nB, row-major).
  * T (aligned with N): root rows exactly 1; F row i in aggregate a gets
@@ -344,14 +360,16 @@ rn_status rn_masked_product(rn_ctx *ctx, rn_plan *plan, const double *A_vals,
  * least-squares component along B_J (so U Bc = 0 and root rows stay 1).
  * A_vals: [batch][nnz(A) * m * m] values for the plan's structure (batch
  * entries share structure, T and Bc).  T: [nnz_N].  P: [batch][nnz_N].
- * RN_FP32_MIXED: the masked products read FP32 copies of A and of the
- * search direction and accumulate in FP32; projection, inner products,
- * step lengths and the P, R, D iterates stay FP64 (RN_CG only).
+ * RN_FP32_MIXED (RN_CG and RN_GMRES): the masked products read FP32 copies
+ * of A and of the search direction (GMRES: of the basis vector) and
+ * accumulate in FP32; projection, inner products, step lengths and the
+ * iterates stay FP64.
  * hist (device, nullable): [batch][3*iters + 1] doubles: CG: gamma_0..K,
  * delta_0..K-1, alpha_0..K-1; GMRES: residual estimates 0..K then zeros.
  * stats (host, nullable).  The call synchronises the stream to read the
  * device status: RN_EBREAKDOWN / RN_ENONFINITE report the first failing
  * batch entry (its P holds the last good iterate).
+ * hist for RN_PCG_JACOBI holds gamma_k = <R_k, Y_k>.
  * tape (nullable, RN_CG + RN_FP64 only): records what rn_energy_min_bwd
  * needs (scalars and the iterates R_k, D_k). */
 rn_status rn_energy_min(rn_ctx *ctx, rn_plan *plan, const double *A_vals,

@@ -16,10 +16,10 @@ from dataclasses import dataclass
 import numpy as np
 
 from . import _lib as L
-from ._lib import RN_CG, RN_GMRES, RN_FP64, RN_FP32_MIXED  # noqa: F401
+from ._lib import RN_CG, RN_GMRES, RN_PCG_JACOBI, RN_CGNR, RN_FP64, RN_FP32_MIXED  # noqa: F401
 
 __all__ = ["RnError", "DeviceCSR", "Context", "Plan", "Tape", "NativeSetup", "EnergyMinOperator", "aggregate_host",
-           "setup", "RN_CG", "RN_GMRES", "RN_FP64", "RN_FP32_MIXED"]
+           "setup", "RN_CG", "RN_GMRES", "RN_PCG_JACOBI", "RN_CGNR", "RN_FP64", "RN_FP32_MIXED"]
 
 
 _LIVE_PLANS: "weakref.WeakSet" = weakref.WeakSet()
@@ -327,6 +327,15 @@ class Context:
                                          _ptr(agg), _ptr(roots), n_agg, _ptr(B), nB, _ptr(T), _ptr(Bc),
                                          C.byref(rd)), "rn_tentative")
         return T[:Nj.numel()], Bc[:block_m * n_agg], rd.value
+
+    # -- candidate smoothing --------------------------------------------------
+    def smooth_candidates(self, A: DeviceCSR, B, sweeps: int, omega: float):
+        """rn_smooth_candidates in place on B (n x nB, float64, contiguous)."""
+        nB = 1 if B.dim() == 1 else int(B.shape[1])
+        d = A.desc()
+        self._check(L.lib().rn_smooth_candidates(self.h, C.byref(d), _ptr(B), nB, int(sweeps), C.c_double(omega)),
+                    "rn_smooth_candidates")
+        return B
 
     # -- pre-filter (Sec. 3.5): valued strength and pattern ---------------------
     def strength_values(self, A: DeviceCSR, theta: float, Sp, Sj):

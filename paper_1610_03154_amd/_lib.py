@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "librnamg.so")
 
 RN_OK, RN_EINVAL, RN_ENOMEM, RN_ESINGULAR, RN_EBREAKDOWN, RN_ENONFINITE, RN_EHIP, RN_ELIMIT = range(8)
-RN_CG, RN_GMRES = 0, 1
+RN_CG, RN_GMRES, RN_PCG_JACOBI, RN_CGNR = 0, 1, 2, 3
 RN_FP64, RN_FP32_MIXED = 0, 1
 RN_OPT_PERSISTENT_PRODUCT, RN_OPT_PADDED_PATTERN, RN_OPT_FUSED_SETUP, RN_OPT_PRODUCT_LANES = range(4)
 # rn_set_allocator callbacks: void *alloc(size_t bytes, void *user); void release(void *ptr, void *user)
@@ -63,6 +63,7 @@ SIGNATURES = {
     "rn_pattern_dofs": (_i32, [_vp, _i32, _vp, _vp, _i64, _vp, _vp, _i32, _i32, _vp, _vp, _vp, _pi64]),
     "rn_aggregate_host": (_i32, [_i32, _vp, _vp, _vp, _vp, _pi32]),
     "rn_pattern": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp, _i32, _i32, _i32, _vp, _vp, _vp, _pi64]),
+    "rn_smooth_candidates": (_i32, [_vp, C.POINTER(rn_matrix), _vp, _i32, _i32, _d]),
     "rn_tentative": (_i32, [_vp, _i32, _i32, _vp, _vp, _i64, _vp, _vp, _vp, _i32, _vp, _i32, _vp, _vp, _pi32]),
     "rn_filter": (_i32, [_vp, _i32, _i32, _vp, _vp, _i64, _vp, _vp, _vp, _i32, _d, _vp, _vp, _vp, _pi64]),
     "rn_enforce": (_i32, [_vp, _i32, _i32, _vp, _vp, _i64, _vp, _vp, _vp, _i32, _vp, _pi32]),

@@ -40,7 +40,8 @@
 
 // per-batch integer state
 // per batch entry: status, converged flag, steps done, GMRES basis size
-enum { ST_STATUS = 0, ST_DONE = 1, ST_ITERS = 2, ST_KD = 3, ST_STRIDE = 8 };
+// (ST_PREC: the Jacobi preconditioner met a diagonal entry that is not positive)
+enum { ST_STATUS = 0, ST_DONE = 1, ST_ITERS = 2, ST_KD = 3, ST_PREC = 4, ST_STRIDE = 8 };
 
 // per-batch double scalars
 enum { SC_GAMMA0 = 0, SC_BETA0, SC_BASE = 4 };
@@ -77,7 +78,7 @@ enum { MODE_PRODUCT = 0, MODE_CG_INIT, MODE_CG_STEP, MODE_GM_INIT, MODE_GM_STEP 
 
 enum RnWs {
   WS_R = 0, WS_D, WS_Z, WS_D32, WS_A32, WS_T32, WS_U, WS_U32, WS_PART, WS_SCAL, WS_ST, WS_CNT,
-  WS_TAPE_TMP0, WS_TAPE_TMP1, WS_TAPE_TMP2, WS_TAPE_TMP3, WS_COUNT
+  WS_TAPE_TMP0, WS_TAPE_TMP1, WS_TAPE_TMP2, WS_TAPE_TMP3, WS_Y, WS_DIAG, WS_COUNT
 };
 
 struct rn_plan {

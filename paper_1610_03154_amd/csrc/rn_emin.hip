@@ -438,6 +438,125 @@ __global__ __launch_bounds__(RN_BLOCK) void k_cg_start(const double *__restrict_
 }
 
 // ---------------------------------------------------------------------------
+// preconditioned and normal-equation CG: row-wise projection passes
+// ---------------------------------------------------------------------------
+// Diagonal of A per DOF row and batch entry (M x M blocks), for the Jacobi
+// preconditioner; a diagonal entry that is not positive raises st[ST_PREC].
+template <int M>
+__global__ __launch_bounds__(RN_BLOCK) void k_row_diag(int n, const int32_t *__restrict__ Ap,
+                                                      const int32_t *__restrict__ Aj, const double *__restrict__ Ax,
+                                                      int64_t strideA, double *__restrict__ dg,
+                                                      int32_t *__restrict__ stv) {
+  const int i = blockIdx.x * RN_BLOCK + threadIdx.x, b = blockIdx.y;
+  if (i >= n) return;
+  const int I = i / M, c = i % M;
+  double d = 0.0;
+  for (int p = Ap[I]; p < Ap[I + 1]; ++p)
+    if (Aj[p] == I) d = Ax[(int64_t)b * strideA + (int64_t)p * M * M + c * M + c];
+  dg[(int64_t)b * n + i] = d;
+  if (!(d > 0.0)) stv[(int64_t)b * ST_STRIDE + ST_PREC] = 1;
+}
+
+enum { RP_PREC = 0, RP_PLAIN = 1, RP_INIT = 2 };
+
+// One thread per DOF row (grid-stride over rows, grid.y = batch entry): the
+// row of X (RP_PREC: scaled by 1 / a_ii) projected, Pi (Sec. 3.6: root rows
+// zero, the least-squares component along Bc_J removed), into Y, with
+// per-block compensated partials of one inner product:
+//   RP_PREC  Y = Pi(D^-1 X), partial of <X, Y>    (Jacobi preconditioner)
+//   RP_PLAIN Y = Pi(X),      partial of <V, Y>    (Y may be X)
+//   RP_INIT  Y = Y2 = -Pi(X), partial of <Y, Y>.
+// With check set, a stopped batch entry does nothing (the test is uniform per
+// block).
+template <int NB, int MODE>
+__global__ __launch_bounds__(RN_BLOCK) void k_row_proj(int n, int64_t nnz, const int32_t *__restrict__ Np,
+                                                      const int32_t *__restrict__ Nj,
+                                                      const uint8_t *__restrict__ is_root,
+                                                      const double *__restrict__ Bc, const double *__restrict__ gp,
+                                                      const double *__restrict__ dg, const double *X,
+                                                      double *Y, double *__restrict__ Y2,
+                                                      const double *__restrict__ V, double *__restrict__ part,
+                                                      int64_t pstride, const int32_t *__restrict__ stv, int check) {
+  constexpr int NP = NB * (NB + 1) / 2;
+  __shared__ double s_w[8];
+  const int b = blockIdx.y;
+  if (check) {
+    const int32_t *st = stv + (int64_t)b * ST_STRIDE;
+    if (st[ST_STATUS] || st[ST_DONE]) return;
+  }
+  const int64_t off = (int64_t)b * nnz;
+  RnAcc acc;
+  for (int i = blockIdx.x * RN_BLOCK + threadIdx.x; i < n; i += gridDim.x * RN_BLOCK) {
+    const int s = Np[i], e = Np[i + 1];
+    if (is_root[i]) {
+      for (int p = s; p < e; ++p) {
+        Y[off + p] = 0.0;
+        if (MODE == RP_INIT) Y2[off + p] = 0.0;
+      }
+      continue;
+    }
+    const double d = MODE == RP_PREC ? dg[(int64_t)b * n + i] : 1.0;
+    double sv[NB];
+#pragma unroll
+    for (int q = 0; q < NB; ++q) sv[q] = 0.0;
+    for (int p = s; p < e; ++p) {
+      const double x = MODE == RP_PREC ? X[off + p] / d : X[off + p];
+      const double *bc = Bc + (int64_t)Nj[p] * NB;
+#pragma unroll
+      for (int q = 0; q < NB; ++q) sv[q] += x * bc[q];
+    }
+    double y[NB];
+    const double *g = gp + (int64_t)i * NP;
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      double t = 0.0;
+#pragma unroll
+      for (int r = 0; r < NB; ++r) t += g[rn_pk(NB, q, r)] * sv[r];
+      y[q] = t;
+    }
+    for (int p = s; p < e; ++p) {
+      const double xr = X[off + p];
+      const double x = MODE == RP_PREC ? xr / d : xr;
+      const double *bc = Bc + (int64_t)Nj[p] * NB;
+      double u = 0.0;
+#pragma unroll
+      for (int q = 0; q < NB; ++q) u += bc[q] * y[q];
+      const double z = x - u;
+      if (MODE == RP_PREC) {
+        Y[off + p] = z;
+        acc.add(xr * z);
+      } else if (MODE == RP_PLAIN) {
+        const double v = V[off + p];
+        Y[off + p] = z;
+        acc.add(v * z);
+      } else {
+        Y[off + p] = -z;
+        Y2[off + p] = -z;
+        acc.add(z * z);
+      }
+    }
+  }
+  const double S = rn_block_sum2(acc.hi, acc.lo, s_w);
+  if (threadIdx.x == 0) part[(int64_t)b * pstride + blockIdx.x] = S;
+}
+
+template <int MODE>
+static void row_proj(int nB, dim3 g, hipStream_t stream, const rn_plan *pl, const double *dg, const double *X,
+                     double *Y, double *Y2, const double *V, double *part, int64_t pstride, const int32_t *st,
+                     int check) {
+  const dim3 blk(RN_BLOCK);
+  switch (nB) {
+#define RP_CASE(NB)                                                                                                   \
+  case NB:                                                                                                            \
+    hipLaunchKernelGGL((k_row_proj<NB, MODE>), g, blk, 0, stream, pl->n, pl->nnzN, pl->Np, pl->Nj, pl->is_root,    \
+                       pl->Bc, pl->gp, dg, X, Y, Y2, V, part, pstride, st, check);                                   \
+    break;
+    RP_CASE(1) RP_CASE(2) RP_CASE(3) RP_CASE(4)
+#undef RP_CASE
+  }
+}
+
+// ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
 // element-wise passes: two elements per lane and up to 2048 workgroups (8
@@ -511,8 +630,12 @@ static rn_status emin_check(rn_ctx *ctx, rn_plan *pl, const double *A_vals, int3
                             rn_method method, int32_t iters, rn_precision prec, double *P) {
   if (!pl || !A_vals || !T || !P || batch < 1 || iters < 0)
     return rn_fail(ctx, RN_EINVAL, "rn_energy_min: bad argument");
-  if (method != RN_CG && method != RN_GMRES) return rn_fail(ctx, RN_EINVAL, "rn_energy_min: bad method");
+  if (method != RN_CG && method != RN_GMRES && method != RN_PCG_JACOBI && method != RN_CGNR)
+    return rn_fail(ctx, RN_EINVAL, "rn_energy_min: bad method");
   if (prec != RN_FP64 && prec != RN_FP32_MIXED) return rn_fail(ctx, RN_EINVAL, "rn_energy_min: bad precision");
+  if ((method == RN_PCG_JACOBI || method == RN_CGNR) && prec != RN_FP64)
+    return rn_fail(ctx, RN_EINVAL, "rn_energy_min: the preconditioned and normal-equation forms run in FP64");
+  if (method == RN_CGNR && batch != 1) return rn_fail(ctx, RN_EINVAL, "rn_energy_min: CGNR takes one problem");
   if (method == RN_GMRES && iters > RN_MAXDOT - 1)
     return rn_fail(ctx, RN_ELIMIT, "rn_energy_min: GMRES supports at most %d iterations", RN_MAXDOT - 1);
   return RN_OK;
@@ -528,13 +651,14 @@ extern "C" rn_status rn_energy_min(rn_ctx *ctx, rn_plan *pl, const double *A_val
   if (!ctx) return RN_EINVAL;
   ctx->err.clear();
   RN_TRY(emin_check(ctx, pl, A_vals, batch, T, method, iters, prec, P));
+  if (tape && method != RN_CG) return rn_fail(ctx, RN_EINVAL, "rn_energy_min: a tape records CG only");
   if (tape) RN_TRY(rn_tape_record_begin(ctx, pl, tape, batch, iters, method, prec, T));
   return emin_run(ctx, pl, A_vals, batch, T, method, iters, prec, P, hist, stats, tape);
 }
 
 // Workspace bytes emin_run requests (each piece rounded to 256 bytes, as the
 // arena carves them), and the bytes of its one read-back.
-static size_t emin_ws_need(const rn_plan *pl, int32_t batch, bool gm, int K, bool mixed, size_t *fetch) {
+static size_t emin_ws_need(const rn_plan *pl, int32_t batch, bool gm, bool pcg, int K, bool mixed, size_t *fetch) {
   auto r = [](size_t b) { return (b + 255) & ~(size_t)255; };
   const int64_t nz = pl->nnzN, nzb = (int64_t)batch * nz;
   const unsigned gew = gm ? ew_grid(nz) : std::min(ew_grid(nz), 1024u);
@@ -545,6 +669,7 @@ static size_t emin_ws_need(const rn_plan *pl, int32_t batch, bool gm, int K, boo
   if (mixed) need += r((size_t)batch * p.strideA * 4) + r((size_t)nz * 4);
   if (!gm) {
     need += 3 * r((size_t)nzb * 8) + (mixed ? r((size_t)nzb * 4) : 0);
+    if (pcg) need += r((size_t)nzb * 8) + r((size_t)batch * (pl->n + 1) * 8);
   } else {
     const size_t ub = (size_t)(K + 1) * nz;
     need += r((size_t)batch * ub * 8) + (mixed ? r((size_t)batch * ub * 4) : 0);
@@ -560,12 +685,15 @@ extern "C" rn_status rn_energy_min_noalloc(rn_ctx *ctx, rn_plan *pl, const doubl
   if (!ctx) return RN_EINVAL;
   ctx->err.clear();
   RN_TRY(emin_check(ctx, pl, A_vals, batch, T, method, iters, prec, P));
+  if (method == RN_CGNR)
+    return rn_fail(ctx, RN_EINVAL, "rn_energy_min_noalloc: CGNR builds the pattern of A N and needs allocation");
   if (!ctx->noalloc_scratch)
     return rn_fail(ctx, RN_EHIP, "rn_energy_min_noalloc: no device address for the scratch array on device %d",
                    ctx->device);
   if (!ctx->rb_host) return rn_fail(ctx, RN_ENOMEM, "rn_energy_min_noalloc: no read-back area");
   size_t fetch = 0;
-  const size_t need = emin_ws_need(pl, batch, method == RN_GMRES, iters, prec == RN_FP32_MIXED, &fetch);
+  const size_t need = emin_ws_need(pl, batch, method == RN_GMRES, method == RN_PCG_JACOBI, iters,
+                                   prec == RN_FP32_MIXED, &fetch);
   if (need > RN_NOALLOC_SCRATCH_BYTES)
     return rn_fail(ctx, RN_ELIMIT,
                    "rn_energy_min_noalloc: the call needs %zu bytes of scratch, the allocation-free limit is %zu",
@@ -632,7 +760,109 @@ static rn_status emin_run(rn_ctx *ctx, rn_plan *pl, const double *A_vals, int32_
   const void *Aop = mixed ? (const void *)A32 : (const void *)A_vals;
   const void *Top = mixed ? (const void *)T32 : (const void *)T;
   const dim3 g2(gew, (unsigned)batch), blk(RN_BLOCK);
-  if (!gm) {
+  const int64_t pstride_row = (int64_t)RN_MAXDOT * gew;  // partials of the row passes, per batch entry
+  if (method == RN_PCG_JACOBI) {
+    // Jacobi-preconditioned CG: Y = Pi(D^-1 R) replaces R in gamma = <R, Y>
+    // and in the direction D = Y + beta D; products and updates as for CG
+    double *R = (double *)rn_plan_ws(pl, WS_R, (size_t)nzb * 8, &st);
+    double *D = (double *)rn_plan_ws(pl, WS_D, (size_t)nzb * 8, &st);
+    double *Z = (double *)rn_plan_ws(pl, WS_Z, (size_t)nzb * 8, &st);
+    double *Y = (double *)rn_plan_ws(pl, WS_Y, (size_t)nzb * 8, &st);
+    double *dg = (double *)rn_plan_ws(pl, WS_DIAG, (size_t)batch * (pl->n + 1) * 8, &st);
+    if (!R || !D || !Z || !Y || !dg) return st;
+    hipLaunchKernelGGL(k_cg_start, g2, blk, 0, ctx->stream, T, nz, nz, P, p.st, n_st, p.scal, n_sc, hist, n_hist);
+    LAUNCH_CHECK(ctx);
+    if (pl->n > 0) {
+      const dim3 gd(rn_div_up(pl->n, RN_BLOCK), (unsigned)batch);
+      if (pl->m == 1)
+        hipLaunchKernelGGL(k_row_diag<1>, gd, blk, 0, ctx->stream, pl->n, pl->Ap, pl->Aj, A_vals, p.strideA, dg,
+                           p.st);
+      else
+        hipLaunchKernelGGL(k_row_diag<2>, gd, blk, 0, ctx->stream, pl->n, pl->Ap, pl->Aj, A_vals, p.strideA, dg,
+                           p.st);
+      LAUNCH_CHECK(ctx);
+    }
+    // R_0 = -Pi(A T), D_0 = Y_0 = Pi(D^-1 R_0), gamma_0 = <R_0, Y_0>
+    SpgParams q = p;
+    q.Ax = A_vals;
+    q.X = T;
+    q.strideX = 0;
+    q.Z = R;
+    q.Z2 = D;
+    RN_TRY(rn_launch_spgemm(ctx, pl, MODE_CG_INIT, q, batch, false));
+    row_proj<RP_PREC>(pl->nB, g2, ctx->stream, pl, dg, R, D, nullptr, nullptr, part_ew, pstride_row, p.st, 0);
+    LAUNCH_CHECK(ctx);
+    hipLaunchKernelGGL(k_cg_fin_init, dim3(batch), blk, 0, ctx->stream, (int)gew, pstride_row, part_ew, p.scal,
+                       scal_stride, K, p.st, hist, hist_stride);
+    LAUNCH_CHECK(ctx);
+    for (int k = 0; k < K; ++k) {
+      SpgParams s = p;
+      s.k = k;
+      s.Ax = A_vals;
+      s.X = D;
+      s.Xown = D;
+      s.Z = Z;
+      int np = 0;
+      RN_TRY(rn_launch_spgemm(ctx, pl, MODE_CG_STEP, s, batch, false, &np));
+      hipLaunchKernelGGL(k_cg_update, g2, blk, 0, ctx->stream, nz, nz, K, k, np, pstride_spg, part_spg, P, R, D, Z,
+                         part_ew, p.scal, scal_stride, p.st, hist, hist_stride, (double *)nullptr);
+      LAUNCH_CHECK(ctx);
+      row_proj<RP_PREC>(pl->nB, g2, ctx->stream, pl, dg, R, Y, nullptr, nullptr, part_ew, pstride_row, p.st, 1);
+      LAUNCH_CHECK(ctx);
+      hipLaunchKernelGGL(k_cg_dir<false>, g2, blk, 0, ctx->stream, nz, nz, K, k, (int)gew, Y, D, (float *)nullptr,
+                         part_ew, p.scal, scal_stride, p.st, hist, hist_stride, (double *)nullptr);
+      LAUNCH_CHECK(ctx);
+    }
+  } else if (method == RN_CGNR) {
+    // CGNR (one problem): W = A X on the pattern of A N, Pi(A^T W) kept to N
+    int32_t *guard = rn_guard_begin(ctx, &st);
+    if (!guard) return st;
+    const rn_matrix Am = {pl->n, pl->m, pl->nnzA, pl->Ap, pl->Aj, A_vals};
+    const int32_t *Sp = nullptr, *Sj = nullptr;
+    const double *Sv = nullptr;
+    RN_TRY(rn_scalar_view(ctx, &Am, &Sp, &Sj, &Sv, guard));
+    const int64_t nzA = pl->nnzA * pl->m * pl->m;
+    const int32_t n = pl->n;
+    int32_t *ATp = (int32_t *)rn_scratch(ctx, SLOT_NRM_TP, (size_t)(n + 1) * 4, &st);
+    int32_t *ATj = (int32_t *)rn_scratch(ctx, SLOT_NRM_TJ, (size_t)(nzA + 1) * 4, &st);
+    double *ATv = (double *)rn_scratch(ctx, SLOT_NRM_TV, (size_t)(nzA + 1) * 8, &st);
+    int32_t *perm = (int32_t *)rn_scratch(ctx, SLOT_NRM_PERM, (size_t)(nzA + 1) * 4, &st);
+    if (!ATp || !ATj || !ATv || !perm) return st;
+    RN_TRY(rn_transpose_structure(ctx, n, n, nzA, Sp, Sj, ATp, ATj, perm, guard));
+    RN_TRY(rn_gather_values(ctx, Sv, perm, nzA, ATv));
+    int32_t *Wp = nullptr, *Wj = nullptr;
+    int64_t nzW = 0;
+    RN_TRY(rn_sg_pattern(ctx, n, nzA, Sp, Sj, pl->Np, pl->Nj, SLOT_NRM_WP, SLOT_NRM_WJ, &Wp, &Wj, &nzW, guard,
+                         "rn_energy_min (CGNR)"));
+    double *Wv = (double *)rn_scratch(ctx, SLOT_NRM_WV, (size_t)(nzW + 1) * 8, &st);
+    double *R = (double *)rn_plan_ws(pl, WS_R, (size_t)nz * 8, &st);
+    double *D = (double *)rn_plan_ws(pl, WS_D, (size_t)nz * 8, &st);
+    double *Z = (double *)rn_plan_ws(pl, WS_Z, (size_t)nz * 8, &st);
+    if (!Wv || !R || !D || !Z) return st;
+    hipLaunchKernelGGL(k_cg_start, g2, blk, 0, ctx->stream, T, nz, nz, P, p.st, n_st, p.scal, n_sc, hist, n_hist);
+    LAUNCH_CHECK(ctx);
+    // R_0 = D_0 = -Pi(A^T (A T)), gamma_0 = <R_0, R_0>
+    RN_TRY(rn_sg_values(ctx, n, nzW, Sp, Sj, Sv, pl->Np, pl->Nj, T, Wp, Wj, Wv, guard));
+    RN_TRY(rn_sg_values(ctx, n, nz, ATp, ATj, ATv, Wp, Wj, Wv, pl->Np, pl->Nj, Z, guard));
+    row_proj<RP_INIT>(pl->nB, g2, ctx->stream, pl, nullptr, Z, R, D, nullptr, part_ew, pstride_row, p.st, 0);
+    LAUNCH_CHECK(ctx);
+    hipLaunchKernelGGL(k_cg_fin_init, dim3(1), blk, 0, ctx->stream, (int)gew, pstride_row, part_ew, p.scal,
+                       scal_stride, K, p.st, hist, hist_stride);
+    LAUNCH_CHECK(ctx);
+    double *part_dz = part_ew + gew;  // <D, Z> partials (the update writes <R, R> at part_ew)
+    for (int k = 0; k < K; ++k) {
+      RN_TRY(rn_sg_values(ctx, n, nzW, Sp, Sj, Sv, pl->Np, pl->Nj, D, Wp, Wj, Wv, guard));
+      RN_TRY(rn_sg_values(ctx, n, nz, ATp, ATj, ATv, Wp, Wj, Wv, pl->Np, pl->Nj, Z, guard));
+      row_proj<RP_PLAIN>(pl->nB, g2, ctx->stream, pl, nullptr, Z, Z, nullptr, D, part_dz, pstride_row, p.st, 1);
+      LAUNCH_CHECK(ctx);
+      hipLaunchKernelGGL(k_cg_update, g2, blk, 0, ctx->stream, nz, nz, K, k, (int)gew, pstride_row, part_dz, P, R,
+                         D, Z, part_ew, p.scal, scal_stride, p.st, hist, hist_stride, (double *)nullptr);
+      LAUNCH_CHECK(ctx);
+      hipLaunchKernelGGL(k_cg_dir<false>, g2, blk, 0, ctx->stream, nz, nz, K, k, (int)gew, R, D, (float *)nullptr,
+                         part_ew, p.scal, scal_stride, p.st, hist, hist_stride, (double *)nullptr);
+      LAUNCH_CHECK(ctx);
+    }
+  } else if (!gm) {
     double *R = (double *)rn_plan_ws(pl, WS_R, (size_t)nzb * 8, &st);
     double *D = (double *)rn_plan_ws(pl, WS_D, (size_t)nzb * 8, &st);
     double *Z = (double *)rn_plan_ws(pl, WS_Z, (size_t)nzb * 8, &st);
@@ -779,12 +1009,18 @@ static rn_status emin_run(rn_ctx *ctx, rn_plan *pl, const double *A_vals, int32_
   const unsigned long long *hterms = (const unsigned long long *)(hb + off[2]);
   rn_status res = RN_OK;
   int bad = -1;
-  for (int b = 0; b < batch; ++b)
+  for (int b = 0; b < batch; ++b) {
+    if (method == RN_PCG_JACOBI && hst[b * ST_STRIDE + ST_PREC]) {
+      res = RN_ESINGULAR;
+      bad = b;
+      break;
+    }
     if (hst[b * ST_STRIDE + ST_STATUS]) {
       res = (rn_status)hst[b * ST_STRIDE + ST_STATUS];
       bad = b;
       break;
     }
+  }
   if (stats) {
     stats->iters_done = hst[gm ? ST_KD : ST_ITERS];
     stats->rank_deficient_rows = pl->rank_def;
@@ -800,6 +1036,9 @@ static rn_status emin_run(rn_ctx *ctx, rn_plan *pl, const double *A_vals, int32_
     }
     product_cost(pl, mixed, *hterms, &stats->spgemm_bytes, &stats->spgemm_flops);
   }
+  if (res == RN_ESINGULAR)
+    return rn_fail(ctx, res, "rn_energy_min: Jacobi preconditioner: a diagonal entry of A is not positive (batch "
+                             "entry %d)", bad);
   if (res == RN_EBREAKDOWN)
     return rn_fail(ctx, res, "rn_energy_min: CG curvature <D, Pi(A D)> <= 0 (batch entry %d)", bad);
   if (res != RN_OK) return rn_fail(ctx, res, "rn_energy_min: non-finite Krylov scalar (batch entry %d)", bad);

@@ -59,6 +59,13 @@ enum RnSlot {
   SLOT_GAL_RJ,
   SLOT_GAL_RV,
   SLOT_GAL_PERM,
+  SLOT_NRM_TP,
+  SLOT_NRM_TJ,
+  SLOT_NRM_TV,
+  SLOT_NRM_PERM,
+  SLOT_NRM_WP,
+  SLOT_NRM_WJ,
+  SLOT_NRM_WV,
   SLOT_COUNT
 };
 
@@ -250,6 +257,20 @@ rn_status rn_check_guard(rn_ctx *ctx, const int32_t *guard, const char *what);
 // Reads the guard and one int64 with a single synchronisation.
 rn_status rn_read_guard_i64(rn_ctx *ctx, const int32_t *guard, const void *dev, int64_t *out, const char *what);
 rn_status rn_gather_values(rn_ctx *ctx, const double *src, const int32_t *idx, int64_t n, double *dst);
+
+// General sparse product pieces (rn_product.hip).  rn_sg_pattern: the
+// structure of C = X Y into two scratch slots (one synchronisation, guard
+// read with it); rn_sg_values: C's values on a given pattern of C, each the
+// sum over X's row in its order (asynchronous).  rn_scalar_view: the scalar
+// CSR of A (block_m = 2: built into scratch).
+rn_status rn_sg_pattern(rn_ctx *ctx, int32_t rows, int64_t nnzX, const int32_t *Xp, const int32_t *Xj,
+                        const int32_t *Yp, const int32_t *Yj, int slot_p, int slot_j, int32_t **Cp, int32_t **Cj,
+                        int64_t *nnz, int32_t *guard, const char *what);
+rn_status rn_sg_values(rn_ctx *ctx, int32_t rows, int64_t nnzC, const int32_t *Xp, const int32_t *Xj,
+                       const double *Xv, const int32_t *Yp, const int32_t *Yj, const double *Yv, const int32_t *Cp,
+                       const int32_t *Cj, double *Cv, const int32_t *guard);
+rn_status rn_scalar_view(rn_ctx *ctx, const rn_matrix *A, const int32_t **Sp, const int32_t **Sj, const double **Sv,
+                         int32_t *guard);
 
 // Internal transpose of a CSR structure with a permutation (used by the
 // strength symmetrisation and by rn_transpose).  rows x cols -> cols x rows.

@@ -220,6 +220,9 @@ extern "C" rn_status rn_spgemm(rn_ctx *ctx, int32_t rows, int32_t inner, int32_t
   return rn_check_guard(ctx, guard, "rn_spgemm");
 }
 
+rn_status rn_scalar_view(rn_ctx *ctx, const rn_matrix *A, const int32_t **Sp_out, const int32_t **Sj_out,
+                         const double **Sv_out, int32_t *guard);
+
 extern "C" rn_status rn_galerkin(rn_ctx *ctx, const rn_matrix *A, int32_t n_cols, const int32_t *N_rowptr,
                                  const int32_t *N_colind, int64_t nnz_N, const double *P, const double *RT,
                                  int32_t *Ac_rowptr, int32_t *Ac_colind, double *Ac_vals, int64_t *nnz_Ac) {
@@ -258,29 +261,9 @@ extern "C" rn_status rn_galerkin(rn_ctx *ctx, const rn_matrix *A, int32_t n_cols
   v.ncsr = 2;
   RN_TRY(rn_validate(ctx, v, guard));
   // scalar CSR of A
-  const int32_t *Sp = A->rowptr, *Sj = A->colind;
-  const double *Sv = A->vals;
-  if (A->block_m == 2) {
-    int32_t *cnt = (int32_t *)rn_scratch(ctx, SLOT_PRD_CNT, (size_t)(n + 1) * sizeof(int32_t), &st);
-    int32_t *p = (int32_t *)rn_scratch(ctx, SLOT_GAL_ASP, (size_t)(n + 1) * sizeof(int32_t), &st);
-    int32_t *j = (int32_t *)rn_scratch(ctx, SLOT_GAL_ASJ, (size_t)(A->nnz * 4 + 1) * sizeof(int32_t), &st);
-    double *x = (double *)rn_scratch(ctx, SLOT_GAL_ASV, (size_t)(A->nnz * 4 + 1) * sizeof(double), &st);
-    if (!cnt || !p || !j || !x) return st;
-    if (nn > 0) {
-      hipLaunchKernelGGL(k_bsr2_rows, dim3(rn_div_up(nn, RN_BLOCK)), dim3(RN_BLOCK), 0, ctx->stream, nn, A->rowptr,
-                         cnt);
-      LAUNCH_CHECK(ctx);
-    }
-    RN_TRY(rn_scan_counts(ctx, cnt, p, n, nullptr));
-    if (nn > 0) {
-      hipLaunchKernelGGL(k_bsr2_fill, dim3(rn_div_up(nn, RN_BLOCK)), dim3(RN_BLOCK), 0, ctx->stream, nn, A->rowptr,
-                         A->colind, A->vals, p, j, x, guard);
-      LAUNCH_CHECK(ctx);
-    }
-    Sp = p;
-    Sj = j;
-    Sv = x;
-  }
+  const int32_t *Sp = nullptr, *Sj = nullptr;
+  const double *Sv = nullptr;
+  RN_TRY(rn_scalar_view(ctx, A, &Sp, &Sj, &Sv, guard));
   // A P (n x n_cols)
   int32_t *APp = nullptr, *APj = nullptr;
   double *APv = nullptr;
@@ -396,5 +379,53 @@ extern "C" rn_status rn_pattern_values(rn_ctx *ctx, int32_t nn, const int32_t *S
   ctx->pv_j = Xj;
   ctx->pv_v = Xv;
   *nnz_Nn = nnzX;
+  return RN_OK;
+}
+
+// ---------------------------------------------------------------------------
+// helpers for the normal-equation minimisation (rn_emin.hip)
+// ---------------------------------------------------------------------------
+rn_status rn_sg_pattern(rn_ctx *ctx, int32_t rows, int64_t nnzX, const int32_t *Xp, const int32_t *Xj,
+                        const int32_t *Yp, const int32_t *Yj, int slot_p, int slot_j, int32_t **Cp, int32_t **Cj,
+                        int64_t *nnz, int32_t *guard, const char *what) {
+  return sg_full(ctx, rows, nnzX, Xp, Xj, nullptr, Yp, Yj, nullptr, slot_p, slot_j, -1, Cp, Cj, nullptr, nnz, guard,
+                 what);
+}
+
+rn_status rn_sg_values(rn_ctx *ctx, int32_t rows, int64_t nnzC, const int32_t *Xp, const int32_t *Xj,
+                       const double *Xv, const int32_t *Yp, const int32_t *Yj, const double *Yv, const int32_t *Cp,
+                       const int32_t *Cj, double *Cv, const int32_t *guard) {
+  return sg_numeric(ctx, rows, nnzC, Xp, Xj, Xv, Yp, Yj, Yv, Cp, Cj, Cv, guard);
+}
+
+rn_status rn_scalar_view(rn_ctx *ctx, const rn_matrix *A, const int32_t **Sp_out, const int32_t **Sj_out,
+                         const double **Sv_out, int32_t *guard) {
+  if (A->block_m == 1) {
+    *Sp_out = A->rowptr;
+    *Sj_out = A->colind;
+    *Sv_out = A->vals;
+    return RN_OK;
+  }
+  rn_status st = RN_OK;
+  const int32_t n = A->n, nn = n / 2;
+  int32_t *cnt = (int32_t *)rn_scratch(ctx, SLOT_PRD_CNT, (size_t)(n + 1) * sizeof(int32_t), &st);
+  int32_t *p = (int32_t *)rn_scratch(ctx, SLOT_GAL_ASP, (size_t)(n + 1) * sizeof(int32_t), &st);
+  int32_t *j = (int32_t *)rn_scratch(ctx, SLOT_GAL_ASJ, (size_t)(A->nnz * 4 + 1) * sizeof(int32_t), &st);
+  double *x = (double *)rn_scratch(ctx, SLOT_GAL_ASV, (size_t)(A->nnz * 4 + 1) * sizeof(double), &st);
+  if (!cnt || !p || !j || !x) return st;
+  if (nn > 0) {
+    hipLaunchKernelGGL(k_bsr2_rows, dim3(rn_div_up(nn, RN_BLOCK)), dim3(RN_BLOCK), 0, ctx->stream, nn, A->rowptr,
+                       cnt);
+    LAUNCH_CHECK(ctx);
+  }
+  RN_TRY(rn_scan_counts(ctx, cnt, p, n, nullptr));
+  if (nn > 0) {
+    hipLaunchKernelGGL(k_bsr2_fill, dim3(rn_div_up(nn, RN_BLOCK)), dim3(RN_BLOCK), 0, ctx->stream, nn, A->rowptr,
+                       A->colind, A->vals, p, j, x, guard);
+    LAUNCH_CHECK(ctx);
+  }
+  *Sp_out = p;
+  *Sj_out = j;
+  *Sv_out = x;
   return RN_OK;
 }

@@ -1,6 +1,7 @@
 // rn_tentative.hip -- inject (Sec. 3.6): coarse candidates by injection at
 // the root DOFs, the root-node tentative operator of Eq. root-nodeform, and
 // the minimum-norm row update of Eq. Tproj for candidates beyond the first m.
+#include <cmath>
 #include <cstring>
 #include "rn_gram.h"
 #include "rn_internal.h"
@@ -222,5 +223,85 @@ extern "C" rn_status rn_enforce(rn_ctx *ctx, int32_t n, int32_t n_cols, const in
   memcpy(hf, hb + off[1], 8);
   RN_TRY(rn_guard_status(ctx, gword, "rn_enforce"));
   if (rank_deficient) *rank_deficient = hf[1];
+  return RN_OK;
+}
+
+// ---------------------------------------------------------------------------
+// candidate smoothing: damped Jacobi on A B = 0
+// ---------------------------------------------------------------------------
+// One thread per DOF row: Bn = Bs - omega (A Bs)_i / a_ii for every column,
+// the row sum in the order of A's row (blocks in order, their columns in
+// order for M = 2); a zero diagonal raises flag[0].
+template <int M>
+__global__ __launch_bounds__(RN_BLOCK) void k_jacobi_sweep(int n, int nB, const int32_t *__restrict__ Ap,
+                                                          const int32_t *__restrict__ Aj,
+                                                          const double *__restrict__ Ax, double omega,
+                                                          const double *__restrict__ Bs, double *__restrict__ Bn,
+                                                          int32_t *__restrict__ flag,
+                                                          const int32_t *__restrict__ guard) {
+  const int i = blockIdx.x * RN_BLOCK + threadIdx.x;
+  if (i >= n || *guard) return;
+  const int I = i / M, r = i % M;
+  double d = 0.0;
+  for (int p = Ap[I]; p < Ap[I + 1]; ++p)
+    if (Aj[p] == I) d = Ax[(int64_t)p * M * M + r * M + r];
+  if (d == 0.0) atomicOr(flag, 1);
+  for (int q = 0; q < nB; ++q) {
+    double y = 0.0;
+    for (int p = Ap[I]; p < Ap[I + 1]; ++p) {
+      const int J = Aj[p];
+#pragma unroll
+      for (int c = 0; c < M; ++c) y += Ax[(int64_t)p * M * M + r * M + c] * Bs[((int64_t)M * J + c) * nB + q];
+    }
+    Bn[(int64_t)i * nB + q] = Bs[(int64_t)i * nB + q] - omega * (y / d);
+  }
+}
+
+extern "C" rn_status rn_smooth_candidates(rn_ctx *ctx, const rn_matrix *A, double *B, int32_t nB, int32_t sweeps,
+                                          double omega) {
+  if (!ctx) return RN_EINVAL;
+  ctx->err.clear();
+  if (!A || nB < 1 || sweeps < 0 || !std::isfinite(omega) || (A->block_m != 1 && A->block_m != 2) || A->n < 0 ||
+      A->n % A->block_m || A->nnz < 0)
+    return rn_fail(ctx, RN_EINVAL, "rn_smooth_candidates: bad argument");
+  if (A->n > 0 && (!A->rowptr || !B || (A->nnz > 0 && (!A->colind || !A->vals))))
+    return rn_fail(ctx, RN_EINVAL, "rn_smooth_candidates: null argument");
+  if (A->nnz >= ((int64_t)1 << 31)) return rn_fail(ctx, RN_ELIMIT, "rn_smooth_candidates: nnz >= 2^31");
+  if (sweeps == 0 || A->n == 0) return RN_OK;
+  const int m = A->block_m, n = A->n, nn = n / m;
+  rn_status st = RN_OK;
+  int32_t *guard = rn_guard_begin(ctx, &st);
+  if (!guard) return st;
+  double *tmp = (double *)rn_scratch(ctx, SLOT_MISC, (size_t)n * nB * sizeof(double), &st);
+  if (!tmp) return st;
+  int32_t *flag = guard + GS_TFLAGS;  // zeroed with the guard
+  RnChecks v{};
+  v.csr[0] = {nn, nn, A->nnz, A->rowptr, A->colind, GUARD_A};
+  v.ncsr = 1;
+  RN_TRY(rn_validate(ctx, v, guard));
+  double *src = B, *dst = tmp;
+  for (int s = 0; s < sweeps; ++s) {
+    if (m == 1)
+      hipLaunchKernelGGL(k_jacobi_sweep<1>, dim3(rn_div_up(n, RN_BLOCK)), dim3(RN_BLOCK), 0, ctx->stream, n, nB,
+                         A->rowptr, A->colind, A->vals, omega, src, dst, flag, guard);
+    else
+      hipLaunchKernelGGL(k_jacobi_sweep<2>, dim3(rn_div_up(n, RN_BLOCK)), dim3(RN_BLOCK), 0, ctx->stream, n, nB,
+                         A->rowptr, A->colind, A->vals, omega, src, dst, flag, guard);
+    LAUNCH_CHECK(ctx);
+    double *t = src;
+    src = dst;
+    dst = t;
+  }
+  if (src != B)
+    HIP_TRY(ctx, hipMemcpyAsync(B, src, (size_t)n * nB * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+  const RnFetch it[2] = {{guard, 4}, {flag, 4}};
+  const unsigned char *hb = nullptr;
+  size_t off[2];
+  RN_TRY(rn_fetch(ctx, 2, it, &hb, off));
+  int32_t gword = 0, fl = 0;
+  memcpy(&gword, hb + off[0], 4);
+  memcpy(&fl, hb + off[1], 4);
+  RN_TRY(rn_guard_status(ctx, gword, "rn_smooth_candidates"));
+  if (fl) return rn_fail(ctx, RN_ESINGULAR, "rn_smooth_candidates: a diagonal entry of A is zero");
   return RN_OK;
 }
