@@ -92,8 +92,23 @@ typedef struct {
   int32_t reserved;
   double first;                /* CG: <R0,R0>; GMRES: ||Pi(A T)||_F         */
   double last;                 /* CG: last <R,R>; GMRES: last residual      */
-  double spgemm_bytes;         /* algorithmic bytes of one masked product   */
+  double spgemm_bytes;         /* algorithmic bytes of one masked product:
+                                  A's indices and values, A's and N's row
+                                  pointers, N's indices, X in, Z out (FP64),
+                                  the Gram data when nB > block_m          */
   double spgemm_flops;         /* 2 x multiply-adds of one masked product   */
+  /* work units of the call (Sec. 2.4, Table sc: cost in multiples of one
+   * product with A, 2 nnz(A) flops): the masked products it ran times
+   * spgemm_flops / (2 nnz(A)), scalar entries of A; CGNR's two products per
+   * step are each counted as one masked product                            */
+  double work_units;
+  /* with RN_OPT_METRICS set (else NaN), for batch entry 0 of the result:
+   * energy = E(P) = sum over N of P_ij (A P)_ij (trace(P^T A P), Sec. 4.1);
+   * proj_residual = ||Pi(A P)||_F over N (what GMRES minimises, Sec. 4.2);
+   * constraint_residual = max |P Bc - B| over rows and candidates (Eq.
+   * mode_constraint); rn_energy_min, which has no B, takes T Bc for B (equal
+   * to B for a T made by rn_tentative), rn_setup takes B itself            */
+  double energy, proj_residual, constraint_residual;
 } rn_emin_stats;
 
 /* ---- context ----------------------------------------------------------- */
@@ -139,7 +154,11 @@ typedef enum {
   /* 256 (default), 128 or 64: lanes (pattern entries) per product block for
    * plans of scalar operators whose pattern rows hold at most lanes/4
    * entries (other plans use 256).  Read when a plan is made. */
-  RN_OPT_PRODUCT_LANES = 3
+  RN_OPT_PRODUCT_LANES = 3,
+  /* 0 (default) or 1: rn_energy_min and rn_setup also compute the energy,
+   * the projected residual and the constraint residual of their result into
+   * rn_emin_stats (one more product and two reductions per call). */
+  RN_OPT_METRICS = 4
 } rn_option;
 rn_status rn_set_option(rn_ctx *ctx, rn_option opt, int32_t value);
 /* Message of the last failure on ctx ("" if none).  Valid until the next
@@ -401,6 +420,20 @@ rn_status rn_energy_min_noalloc(rn_ctx *ctx, rn_plan *plan,
                                 int32_t iters, rn_precision precision,
                                 double *P, double *hist,
                                 rn_emin_stats *stats);
+
+/* ---- metrics (Sec. 4.1 energy, Sec. 4.2 residual, Eq. mode_constraint) --
+ * rn_energy: for values P on the plan's pattern (one problem), *energy =
+ * sum over N of P_ij (A P)_ij and *proj_residual = ||Pi(M(A P))||_F (either
+ * pointer, host, may be NULL).  rn_constraint_residual: *res = max over rows
+ * i and candidates q of |(V Bc)_iq - B_iq|, V on the pattern N (n rows,
+ * n_cols columns), Bc n_cols x nB, B n x nB.  Both synchronise the stream. */
+rn_status rn_energy(rn_ctx *ctx, rn_plan *plan, const double *A_vals,
+                    const double *P, double *energy, double *proj_residual);
+rn_status rn_constraint_residual(rn_ctx *ctx, int32_t n, int32_t n_cols,
+                                 const int32_t *N_rowptr, const int32_t *N_colind,
+                                 int64_t nnz_N, const double *vals,
+                                 const double *Bc, const double *B, int32_t nB,
+                                 double *res);
 
 /* ---- a12: adjoint of the CG energy minimisation (map A values -> P) -----
  * Tape for `batch` problems of `iters` CG steps on `plan`; holds the Krylov

@@ -522,6 +522,23 @@ class Context:
                     "rn_energy_min_noalloc")
         return stats
 
+    # -- metrics -------------------------------------------------------------
+    def energy(self, plan: Plan, A_vals, P):
+        """rn_energy: (E(P), ||Pi(A P)||_F) of one problem."""
+        e, r = C.c_double(), C.c_double()
+        self._check(L.lib().rn_energy(self.h, plan.handle, _ptr(A_vals), _ptr(P), C.byref(e), C.byref(r)),
+                    "rn_energy")
+        return e.value, r.value
+
+    def constraint_residual(self, Np, Nj, vals, Bc, B, n_cols=None):
+        """rn_constraint_residual: max |vals Bc - B|."""
+        r = C.c_double()
+        n = Np.numel() - 1
+        self._check(L.lib().rn_constraint_residual(self.h, n, int(Bc.shape[0] if n_cols is None else n_cols), _ptr(Np),
+                                                   _ptr(Nj), Nj.numel(), _ptr(vals), _ptr(Bc), _ptr(B),
+                                                   int(Bc.shape[1]), C.byref(r)), "rn_constraint_residual")
+        return r.value
+
     # -- a12 -----------------------------------------------------------------
     def tape(self, plan: Plan, batch: int, iters: int) -> Tape:
         h = C.c_void_p()

@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(HERE, "librnamg.so")
 RN_OK, RN_EINVAL, RN_ENOMEM, RN_ESINGULAR, RN_EBREAKDOWN, RN_ENONFINITE, RN_EHIP, RN_ELIMIT = range(8)
 RN_CG, RN_GMRES, RN_PCG_JACOBI, RN_CGNR = 0, 1, 2, 3
 RN_FP64, RN_FP32_MIXED = 0, 1
-RN_OPT_PERSISTENT_PRODUCT, RN_OPT_PADDED_PATTERN, RN_OPT_FUSED_SETUP, RN_OPT_PRODUCT_LANES = range(4)
+RN_OPT_PERSISTENT_PRODUCT, RN_OPT_PADDED_PATTERN, RN_OPT_FUSED_SETUP, RN_OPT_PRODUCT_LANES, RN_OPT_METRICS = range(5)
 # rn_set_allocator callbacks: void *alloc(size_t bytes, void *user); void release(void *ptr, void *user)
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
 RELEASE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
@@ -33,7 +33,9 @@ class rn_emin_stats(C.Structure):
     _fields_ = [("iters_done", C.c_int32), ("rank_deficient_rows", C.c_int32),
                 ("status_code", C.c_int32), ("reserved", C.c_int32),
                 ("first", C.c_double), ("last", C.c_double),
-                ("spgemm_bytes", C.c_double), ("spgemm_flops", C.c_double)]
+                ("spgemm_bytes", C.c_double), ("spgemm_flops", C.c_double),
+                ("work_units", C.c_double), ("energy", C.c_double), ("proj_residual", C.c_double),
+                ("constraint_residual", C.c_double)]
 
 
 class rn_setup_view(C.Structure):
@@ -79,6 +81,9 @@ SIGNATURES = {
                              C.POINTER(rn_emin_stats), _vp]),
     "rn_energy_min_noalloc": (_i32, [_vp, _vp, _vp, _i32, _vp, _i32, _i32, _i32, _vp, _vp,
                                      C.POINTER(rn_emin_stats)]),
+    "rn_energy": (_i32, [_vp, _vp, _vp, _vp, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "rn_constraint_residual": (_i32, [_vp, _i32, _i32, _vp, _vp, _i64, _vp, _vp, _vp, _i32,
+                                      C.POINTER(C.c_double)]),
     "rn_tape_create": (_i32, [_vp, _vp, _i32, _i32, C.POINTER(C.c_void_p)]),
     "rn_tape_destroy": (None, [_vp]),
     "rn_energy_min_bwd": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),

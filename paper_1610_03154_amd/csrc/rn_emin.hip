@@ -17,6 +17,7 @@
 // inside the producing kernel needs a device-scope release per workgroup,
 // which writes back the compute die's L2 and made those kernels several
 // times slower.)
+#include <cmath>
 #include <cstring>
 #include <new>
 
@@ -557,6 +558,101 @@ static void row_proj(int nB, dim3 g, hipStream_t stream, const rn_plan *pl, cons
 }
 
 // ---------------------------------------------------------------------------
+// metrics: inner products and the constraint residual
+// ---------------------------------------------------------------------------
+// Per-block compensated partials of <x, y> (grid-stride).
+__global__ __launch_bounds__(RN_BLOCK) void k_dot_part(int64_t n, const double *__restrict__ x,
+                                                      const double *__restrict__ y, double *__restrict__ part) {
+  __shared__ double s_w[8];
+  RnAcc a;
+  for (int64_t q = (int64_t)blockIdx.x * RN_BLOCK + threadIdx.x; q < n; q += (int64_t)gridDim.x * RN_BLOCK)
+    a.add(x[q] * y[q]);
+  const double S = rn_block_sum2(a.hi, a.lo, s_w);
+  if (threadIdx.x == 0) part[blockIdx.x] = S;
+}
+
+// Per-block maxima of |(V Bc)_iq - ref_iq| with ref = B when given, else
+// (T Bc)_iq (then (V - T) Bc is formed entry by entry); one thread per row.
+template <int NB>
+__global__ __launch_bounds__(RN_BLOCK) void k_cres_part(int n, const int32_t *__restrict__ Np,
+                                                       const int32_t *__restrict__ Nj, const double *__restrict__ V,
+                                                       const double *__restrict__ T, const double *__restrict__ Bc,
+                                                       const double *__restrict__ B, double *__restrict__ part) {
+  __shared__ double s_m[RN_BLOCK / RN_WAVE];
+  double mx = 0.0;
+  for (int i = blockIdx.x * RN_BLOCK + threadIdx.x; i < n; i += gridDim.x * RN_BLOCK) {
+    double s[NB];
+#pragma unroll
+    for (int q = 0; q < NB; ++q) s[q] = 0.0;
+    for (int p = Np[i]; p < Np[i + 1]; ++p) {
+      const double v = T ? V[p] - T[p] : V[p];
+      const double *bc = Bc + (int64_t)Nj[p] * NB;
+#pragma unroll
+      for (int q = 0; q < NB; ++q) s[q] += v * bc[q];
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q) mx = fmax(mx, fabs(B ? s[q] - B[(int64_t)i * NB + q] : s[q]));
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, RN_WAVE));
+  if ((threadIdx.x & (RN_WAVE - 1)) == 0) s_m[threadIdx.x / RN_WAVE] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = s_m[0];
+    for (int w = 1; w < RN_BLOCK / RN_WAVE; ++w) m = fmax(m, s_m[w]);
+    part[blockIdx.x] = m;
+  }
+}
+
+// (A P) at the one entry of each root row (the masked product leaves root
+// rows at zero): a thread per DOF row, the terms in the order of A's row (M x M
+// blocks), P_kj found by binary search in row k of N.
+template <int M>
+__global__ __launch_bounds__(RN_BLOCK) void k_root_ap(int n, const int32_t *__restrict__ Ap,
+                                                     const int32_t *__restrict__ Aj, const double *__restrict__ Ax,
+                                                     const int32_t *__restrict__ Np, const int32_t *__restrict__ Nj,
+                                                     const uint8_t *__restrict__ is_root,
+                                                     const double *__restrict__ P, double *__restrict__ Y) {
+  const int i = blockIdx.x * RN_BLOCK + threadIdx.x;
+  if (i >= n || !is_root[i] || Np[i + 1] == Np[i]) return;
+  const int I = i / M, c = i % M, p0 = Np[i], j = Nj[p0];
+  double s = 0.0;
+  for (int b = Ap[I]; b < Ap[I + 1]; ++b) {
+    const int J = Aj[b];
+#pragma unroll
+    for (int cc = 0; cc < M; ++cc) {
+      const int k = M * J + cc;
+      int lo = Np[k], hi = Np[k + 1];
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (Nj[mid] < j) lo = mid + 1; else hi = mid;
+      }
+      if (lo < Np[k + 1] && Nj[lo] == j) s += Ax[(int64_t)b * M * M + c * M + cc] * P[lo];
+    }
+  }
+  Y[p0] = s;
+}
+
+// One block: out[0] = the sum (MAX = false) or the maximum of np partials.
+template <bool MAX>
+__global__ __launch_bounds__(RN_BLOCK) void k_fin_part(int np, const double *__restrict__ part,
+                                                      double *__restrict__ out) {
+  __shared__ double s_w[8];
+  if (MAX) {
+    double m = 0.0;
+    for (int q = threadIdx.x; q < np; q += RN_BLOCK) m = fmax(m, part[q]);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, RN_WAVE));
+    if ((threadIdx.x & (RN_WAVE - 1)) == 0) s_w[threadIdx.x / RN_WAVE] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) out[0] = fmax(fmax(s_w[0], s_w[1]), fmax(s_w[2], s_w[3]));
+  } else {
+    const double S = rn_reduce_part(part, np, s_w);
+    if (threadIdx.x == 0) out[0] = S;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
 // element-wise passes: two elements per lane and up to 2048 workgroups (8
@@ -594,6 +690,116 @@ static rn_status common_ws(rn_plan *pl, int batch, int scal_stride, unsigned gew
   p.part = (double *)rn_plan_ws(pl, WS_PART, (size_t)batch * RN_MAXDOT * ((size_t)pl->nblk + gew + 2) * 8, &st);
   if (!p.st || !p.scal || !p.part) return st;
   p.scal_stride = scal_stride;
+  return RN_OK;
+}
+
+static constexpr unsigned METRIC_GRID = 512;
+
+// Constraint residual of V (one problem) against B, or against T Bc when B is
+// NULL, into out (device double); res (device, 2 * METRIC_GRID doubles) holds
+// the partials.
+static rn_status cres_launch(rn_ctx *ctx, int32_t n, const int32_t *Np, const int32_t *Nj, const double *V,
+                             const double *T, const double *Bc, const double *B, int nB, double *part, double *out) {
+  const dim3 g(METRIC_GRID), blk(RN_BLOCK);
+  switch (nB) {
+    case 1: hipLaunchKernelGGL(k_cres_part<1>, g, blk, 0, ctx->stream, n, Np, Nj, V, T, Bc, B, part); break;
+    case 2: hipLaunchKernelGGL(k_cres_part<2>, g, blk, 0, ctx->stream, n, Np, Nj, V, T, Bc, B, part); break;
+    case 3: hipLaunchKernelGGL(k_cres_part<3>, g, blk, 0, ctx->stream, n, Np, Nj, V, T, Bc, B, part); break;
+    case 4: hipLaunchKernelGGL(k_cres_part<4>, g, blk, 0, ctx->stream, n, Np, Nj, V, T, Bc, B, part); break;
+    default: return rn_fail(ctx, RN_EINVAL, "constraint residual: nB %d", nB);
+  }
+  LAUNCH_CHECK(ctx);
+  hipLaunchKernelGGL(k_fin_part<true>, dim3(1), blk, 0, ctx->stream, (int)METRIC_GRID, part, out);
+  LAUNCH_CHECK(ctx);
+  return RN_OK;
+}
+
+// E(P) = <P, A P> over N (root rows included) and <Y, Pi(Y)> = ||Pi(Y)||^2
+// for Y = A P kept to N into out[0], out[1] (device); Y in the plan's Z
+// workspace (projected in place).
+static rn_status energy_launch(rn_ctx *ctx, rn_plan *pl, const double *A_vals, const double *P, double *part,
+                               double *out) {
+  rn_status st = RN_OK;
+  double *Y = (double *)rn_plan_ws(pl, WS_Z, (size_t)pl->nnzN * 8, &st);
+  if (!Y) return st;
+  SpgParams q = rn_spg_params(pl);
+  RN_TRY(common_ws(pl, 1, SC_BASE, 1, q));
+  q.project = 0;
+  q.Z = Y;
+  q.Ax = A_vals;
+  q.X = P;
+  RN_TRY(rn_launch_spgemm(ctx, pl, MODE_PRODUCT, q, 1, false));
+  const dim3 g(METRIC_GRID), blk(RN_BLOCK);
+  if (pl->n > 0) {
+    if (pl->m == 1)
+      hipLaunchKernelGGL(k_root_ap<1>, dim3(rn_div_up(pl->n, RN_BLOCK)), blk, 0, ctx->stream, pl->n, pl->Ap, pl->Aj,
+                         A_vals, pl->Np, pl->Nj, pl->is_root, P, Y);
+    else
+      hipLaunchKernelGGL(k_root_ap<2>, dim3(rn_div_up(pl->n, RN_BLOCK)), blk, 0, ctx->stream, pl->n, pl->Ap, pl->Aj,
+                         A_vals, pl->Np, pl->Nj, pl->is_root, P, Y);
+    LAUNCH_CHECK(ctx);
+  }
+  hipLaunchKernelGGL(k_dot_part, g, blk, 0, ctx->stream, pl->nnzN, P, Y, part);
+  LAUNCH_CHECK(ctx);
+  hipLaunchKernelGGL(k_fin_part<false>, dim3(1), blk, 0, ctx->stream, (int)METRIC_GRID, part, out);
+  LAUNCH_CHECK(ctx);
+  // the status block must read "running" for the projection pass
+  row_proj<RP_PLAIN>(pl->nB, dim3(METRIC_GRID), ctx->stream, pl, nullptr, Y, Y, nullptr, Y, part + METRIC_GRID,
+                     0, q.st, 0);
+  LAUNCH_CHECK(ctx);
+  hipLaunchKernelGGL(k_fin_part<false>, dim3(1), blk, 0, ctx->stream, (int)METRIC_GRID, part + METRIC_GRID, out + 1);
+  LAUNCH_CHECK(ctx);
+  return RN_OK;
+}
+
+extern "C" rn_status rn_energy(rn_ctx *ctx, rn_plan *pl, const double *A_vals, const double *P, double *energy,
+                               double *proj_residual) {
+  if (!ctx) return RN_EINVAL;
+  ctx->err.clear();
+  if (!pl || !A_vals || !P) return rn_fail(ctx, RN_EINVAL, "rn_energy: null argument");
+  rn_status st = RN_OK;
+  double *part = (double *)rn_scratch(ctx, SLOT_MISC, (2 * METRIC_GRID + 4) * sizeof(double), &st);
+  if (!part) return st;
+  double *out = part + 2 * METRIC_GRID;
+  RN_TRY(energy_launch(ctx, pl, A_vals, P, part, out));
+  const RnFetch it[1] = {{out, 2 * sizeof(double)}};
+  const unsigned char *hb = nullptr;
+  size_t off[1];
+  RN_TRY(rn_fetch(ctx, 1, it, &hb, off));
+  double v[2];
+  memcpy(v, hb + off[0], sizeof v);
+  if (energy) *energy = v[0];
+  if (proj_residual) *proj_residual = sqrt(fmax(v[1], 0.0));
+  return RN_OK;
+}
+
+extern "C" rn_status rn_constraint_residual(rn_ctx *ctx, int32_t n, int32_t n_cols, const int32_t *Np,
+                                            const int32_t *Nj, int64_t nnz_N, const double *vals, const double *Bc,
+                                            const double *B, int32_t nB, double *res) {
+  if (!ctx) return RN_EINVAL;
+  ctx->err.clear();
+  if (!res || n < 0 || n_cols < 0 || nnz_N < 0 || nB < 1 || nB > RN_NBMAX || (n > 0 && (!Np || !B)) ||
+      (nnz_N > 0 && (!Nj || !vals || !Bc)))
+    return rn_fail(ctx, RN_EINVAL, "rn_constraint_residual: bad argument");
+  if (nnz_N >= ((int64_t)1 << 31)) return rn_fail(ctx, RN_ELIMIT, "rn_constraint_residual: nnz_N >= 2^31");
+  rn_status st = RN_OK;
+  int32_t *guard = rn_guard_begin(ctx, &st);
+  if (!guard) return st;
+  double *part = (double *)rn_scratch(ctx, SLOT_MISC, (2 * METRIC_GRID + 4) * sizeof(double), &st);
+  if (!part) return st;
+  RnChecks v{};
+  v.csr[0] = {n, n_cols, nnz_N, Np, Nj, GUARD_N};
+  v.ncsr = 1;
+  RN_TRY(rn_validate(ctx, v, guard));
+  // kernels run only on a valid pattern: read the guard first
+  RN_TRY(rn_check_guard(ctx, guard, "rn_constraint_residual"));
+  double *out = part + 2 * METRIC_GRID;
+  RN_TRY(cres_launch(ctx, n, Np, Nj, vals, nullptr, Bc, B, nB, part, out));
+  const RnFetch it[1] = {{out, sizeof(double)}};
+  const unsigned char *hb = nullptr;
+  size_t off[1];
+  RN_TRY(rn_fetch(ctx, 1, it, &hb, off));
+  memcpy(res, hb + off[0], sizeof(double));
   return RN_OK;
 }
 
@@ -1022,6 +1228,7 @@ static rn_status emin_run(rn_ctx *ctx, rn_plan *pl, const double *A_vals, int32_
     }
   }
   if (stats) {
+    stats->energy = stats->proj_residual = stats->constraint_residual = NAN;
     stats->iters_done = hst[gm ? ST_KD : ST_ITERS];
     stats->rank_deficient_rows = pl->rank_def;
     stats->status_code = hst[ST_STATUS];
@@ -1035,6 +1242,28 @@ static rn_status emin_run(rn_ctx *ctx, rn_plan *pl, const double *A_vals, int32_
       stats->last = hsc[L.gam + hst[ST_ITERS]];
     }
     product_cost(pl, mixed, *hterms, &stats->spgemm_bytes, &stats->spgemm_flops);
+    const double nprod = (double)(stats->iters_done + 1) * (method == RN_CGNR ? 2.0 : 1.0);
+    stats->work_units = nprod * stats->spgemm_flops / (2.0 * (double)pl->nnzA * pl->m * pl->m);
+  }
+  // (not in an allocation-free call: the metrics use the context's scratch)
+  if (stats && res == RN_OK && ctx->opt[RN_OPT_METRICS] && !pl->arena) {
+    // E(P), ||Pi(A P)|| and max |(P - T) Bc| of batch entry 0 (one more
+    // product, one synchronisation)
+    double *part = (double *)rn_scratch(ctx, SLOT_MISC, (2 * METRIC_GRID + 4) * sizeof(double), &st);
+    if (!part) return st;
+    double *out = part + 2 * METRIC_GRID;
+    RN_TRY(energy_launch(ctx, pl, A_vals, P, part, out));
+    RN_TRY(cres_launch(ctx, pl->n, pl->Np, pl->Nj, P, T, pl->Bc, nullptr, pl->nB, part, out + 2));
+    const RnFetch it2[1] = {{out, 3 * sizeof(double)}};
+    const unsigned char *hb2 = nullptr;
+    size_t off2[1];
+    RN_TRY(rn_fetch(ctx, 1, it2, &hb2, off2));
+    double v[3];
+    memcpy(v, hb2 + off2[0], sizeof v);
+    stats->energy = v[0];
+    stats->proj_residual = sqrt(fmax(v[1], 0.0));
+    stats->constraint_residual = v[2];
+    stats->work_units += stats->spgemm_flops / (2.0 * (double)pl->nnzA * pl->m * pl->m);
   }
   if (res == RN_ESINGULAR)
     return rn_fail(ctx, res, "rn_energy_min: Jacobi preconditioner: a diagonal entry of A is not positive (batch "

@@ -124,6 +124,9 @@ extern "C" rn_status rn_setup(rn_ctx *ctx, const rn_matrix *A, const int32_t *ag
     return fail(st);
   v.P = P;
   v.plan = s->plan;
+  if (stats && ctx->opt[RN_OPT_METRICS] &&
+      (st = rn_constraint_residual(ctx, n, nc, Np, Nj, nnzN, P, Bc, B, nB, &stats->constraint_residual)) != RN_OK)
+    return fail(st);
   if (Bhat) {
     // a10: R^T by the same minimisation on A^T with T-hat from B-hat
     s->AT_rowptr = (int32_t *)setup_alloc(s, (size_t)(n + 1) * 4);
@@ -147,6 +150,10 @@ extern "C" rn_status rn_setup(rn_ctx *ctx, const rn_matrix *A, const int32_t *ag
     if ((st = rn_tentative_flags(ctx, hf, nullptr)) != RN_OK) return fail(st);
     if ((st = rn_energy_min(ctx, s->plan_T, s->AT_vals, 1, That, method, iters, precision, RT, nullptr, stats_RT,
                             nullptr)) != RN_OK)
+      return fail(st);
+    if (stats_RT && ctx->opt[RN_OPT_METRICS] &&
+        (st = rn_constraint_residual(ctx, n, nc, Np, Nj, nnzN, RT, Bch, Bhat, nB,
+                                     &stats_RT->constraint_residual)) != RN_OK)
       return fail(st);
     v.That = That;
     v.Bchat = Bch;
