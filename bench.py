@@ -510,6 +510,8 @@ def main():
     ap.add_argument("--fb-reps", type=int, default=5, help="repetitions of the batched forward+backward")
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the cold launches of the headline product (the roofline's own loop)")
+    ap.add_argument("--steps-only", action="store_true",
+                    help="only the timed FP64 set-up steps (for a kernel trace of the step)")
     ap.add_argument("--other-reps", type=int, default=3,
                     help="repetitions of the upwind1024 and elastic512 setups (0 skips them)")
     args = ap.parse_args()
@@ -529,6 +531,9 @@ def main():
         print(json.dumps(r))
         return
     wall64, ev64, P64, st64, aux = time_steps(inp, R.RN_FP64, args.steps, args.warmup)
+    if args.steps_only:
+        print(json.dumps({"value": ev64, "unit": "s", "wall_s_per_step": wall64, "steps": args.steps}))
+        return
     wall32, ev32, P32, st32, _ = time_steps(inp, R.RN_FP32_MIXED, args.steps, args.warmup)
     head = headline_roofline(inp, aux, args.reps, args.cold_reps, flush)
     others = other_rooflines(args.reps, args.cold_reps, flush)

@@ -89,7 +89,8 @@ typedef struct {
   int32_t rank_deficient_rows; /* F rows whose Gram matrix took the
                                   pseudo-inverse fallback                   */
   int32_t status_code;         /* device-side status (an rn_status value)   */
-  int32_t reserved;
+  int32_t fused_cg;            /* 1: each CG direction was formed inside
+                                  the next product (RN_OPT_FUSED_CG)        */
   double first;                /* CG: <R0,R0>; GMRES: ||Pi(A T)||_F         */
   double last;                 /* CG: last <R,R>; GMRES: last residual      */
   double spgemm_bytes;         /* algorithmic bytes of one masked product:
@@ -158,7 +159,13 @@ typedef enum {
   /* 0 (default) or 1: rn_energy_min and rn_setup also compute the energy,
    * the projected residual and the constraint residual of their result into
    * rn_emin_stats (one more product and two reductions per call). */
-  RN_OPT_METRICS = 4
+  RN_OPT_METRICS = 4,
+  /* 1 (default): FP64 CG (RN_CG) without a tape, on plans whose products run
+   * as persistent workgroups of 256 lanes, forms the direction D = R + beta D
+   * while the next product stages its X window (two launches per step, two D
+   * buffers); 0: a separate direction pass (three launches per step).  The
+   * two give the same result bit for bit. */
+  RN_OPT_FUSED_CG = 5
 } rn_option;
 rn_status rn_set_option(rn_ctx *ctx, rn_option opt, int32_t value);
 /* Message of the last failure on ctx ("" if none).  Valid until the next

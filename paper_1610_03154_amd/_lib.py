@@ -14,7 +14,8 @@ LIB_PATH = os.path.join(HERE, "librnamg.so")
 RN_OK, RN_EINVAL, RN_ENOMEM, RN_ESINGULAR, RN_EBREAKDOWN, RN_ENONFINITE, RN_EHIP, RN_ELIMIT = range(8)
 RN_CG, RN_GMRES, RN_PCG_JACOBI, RN_CGNR = 0, 1, 2, 3
 RN_FP64, RN_FP32_MIXED = 0, 1
-RN_OPT_PERSISTENT_PRODUCT, RN_OPT_PADDED_PATTERN, RN_OPT_FUSED_SETUP, RN_OPT_PRODUCT_LANES, RN_OPT_METRICS = range(5)
+RN_OPT_PERSISTENT_PRODUCT, RN_OPT_PADDED_PATTERN, RN_OPT_FUSED_SETUP, RN_OPT_PRODUCT_LANES, RN_OPT_METRICS, \
+    RN_OPT_FUSED_CG = range(6)
 # rn_set_allocator callbacks: void *alloc(size_t bytes, void *user); void release(void *ptr, void *user)
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
 RELEASE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
@@ -31,7 +32,7 @@ class rn_matrix(C.Structure):
 
 class rn_emin_stats(C.Structure):
     _fields_ = [("iters_done", C.c_int32), ("rank_deficient_rows", C.c_int32),
-                ("status_code", C.c_int32), ("reserved", C.c_int32),
+                ("status_code", C.c_int32), ("fused_cg", C.c_int32),
                 ("first", C.c_double), ("last", C.c_double),
                 ("spgemm_bytes", C.c_double), ("spgemm_flops", C.c_double),
                 ("work_units", C.c_double), ("energy", C.c_double), ("proj_residual", C.c_double),

@@ -525,6 +525,7 @@ extern "C" rn_status rn_set_option(rn_ctx *ctx, rn_option opt, int32_t value) {
     case RN_OPT_PADDED_PATTERN:
     case RN_OPT_FUSED_SETUP:
     case RN_OPT_METRICS:
+    case RN_OPT_FUSED_CG:
       if (value != 0 && value != 1) return rn_fail(ctx, RN_EINVAL, "rn_set_option: value must be 0 or 1");
       break;
     case RN_OPT_PRODUCT_LANES:

@@ -72,13 +72,16 @@ struct GmLayout {
   }
 };
 
-enum { MODE_PRODUCT = 0, MODE_CG_INIT, MODE_CG_STEP, MODE_GM_INIT, MODE_GM_STEP };
+// MODE_CG_FSTEP: CG step k >= 1 that first finishes beta_{k-1} from the
+// <R,R> partials of the previous update and forms D_k = R + beta_{k-1}
+// D_{k-1} (X = D_{k-1}, Rres = R, Dnew = D_k) as it stages X
+enum { MODE_PRODUCT = 0, MODE_CG_INIT, MODE_CG_STEP, MODE_GM_INIT, MODE_GM_STEP, MODE_CG_FSTEP };
 
 #define RN_MAXDOT 65  // GMRES iterations <= 64
 
 enum RnWs {
   WS_R = 0, WS_D, WS_Z, WS_D32, WS_A32, WS_T32, WS_U, WS_U32, WS_PART, WS_SCAL, WS_ST, WS_CNT,
-  WS_TAPE_TMP0, WS_TAPE_TMP1, WS_TAPE_TMP2, WS_TAPE_TMP3, WS_Y, WS_DIAG, WS_COUNT
+  WS_TAPE_TMP0, WS_TAPE_TMP1, WS_TAPE_TMP2, WS_TAPE_TMP3, WS_Y, WS_DIAG, WS_D2, WS_COUNT
 };
 
 struct rn_plan {
@@ -138,6 +141,15 @@ struct SpgParams {
   double *part;        // [batch][RN_MAXDOT][nblk]
   double *scal;        // [batch][scal_stride]
   int32_t *st;         // [batch][ST_STRIDE]
+  // MODE_CG_FSTEP: the residual R_k, the direction written (D_k), the
+  // update's <R,R> partials (np_rr per batch entry, pstride_rr apart) and
+  // the history (nullable, hist_stride per batch entry)
+  const double *Rres;
+  double *Dnew;
+  const double *part_rr;
+  int32_t np_rr;
+  int64_t pstride_rr;
+  double *hist;
 };
 
 // Launch the masked product in one of the modes (rn_spgemm.hip).  Single-dot
@@ -147,6 +159,8 @@ struct SpgParams {
 rn_status rn_launch_spgemm(rn_ctx *ctx, const rn_plan *pl, int mode, const SpgParams &p, int batch, bool mixed,
                            int *npart = nullptr);
 SpgParams rn_spg_params(const rn_plan *pl);
+// the persistent product can serve MODE_CG_FSTEP launches of this plan
+bool rn_spgemm_fused_ok(const rn_plan *pl, int batch);
 
 // rn_plan_create on the caller's guard word (not reset; NULL: a fresh one),
 // with one extra device item (nullable) read back at the plan's
@@ -179,16 +193,16 @@ rn_status rn_tape_record_end(rn_ctx *ctx, rn_tape *tape, const double *scal, con
 template <int NT>
 __device__ inline double rn_reduce_part_w(const double *part, int nb, double *lds8) {
   RnAcc a;
-  int q = threadIdx.x;
-  // eight loads in flight per thread, then the additions in the same order
-  for (; q + 7 * NT < nb; q += 8 * NT) {
+  // up to eight loads in flight per thread (predicated, so a short tail is
+  // not loaded one round trip at a time), then the additions in index order
+  for (int q = threadIdx.x; q < nb; q += 8 * NT) {
     double v[8];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) v[k] = part[q + k * NT];
+    for (int k = 0; k < 8; ++k) v[k] = q + k * NT < nb ? part[q + k * NT] : 0.0;
 #pragma unroll
-    for (int k = 0; k < 8; ++k) a.add(v[k]);
+    for (int k = 0; k < 8; ++k)
+      if (q + k * NT < nb) a.add(v[k]);
   }
-  for (; q < nb; q += NT) a.add(part[q]);
   return rn_block_sum2_w<NT / RN_WAVE>(a.hi, a.lo, lds8);
 }
 __device__ inline double rn_reduce_part(const double *part, int nb, double *lds8) {

@@ -41,6 +41,14 @@ __global__ __launch_bounds__(RN_BLOCK) void k_cg_fin_init(int np, int64_t pstrid
                  histv ? histv + (int64_t)b * hist_stride : nullptr, K);
 }
 
+// Elements per lane whose loads the CG element-wise kernels issue together
+// (one memory round trip for up to U * grid * RN_BLOCK elements); each lane
+// still visits its elements in the order e, e + grid, e + 2 grid, ...  The
+// update holds four vectors per element: five elements keep it at four
+// workgroups per compute unit, so all 1024 of its workgroups are resident.
+#define CG_UPD_U 5
+#define CG_DIR_U 8
+
 // delta_k = <D, Pi(A D)> from the product's per-workgroup partials: every
 // block sums them in the same fixed order (compensated), so all blocks get
 // the same delta_k and alpha_k; block 0 stores them with the breakdown and
@@ -58,17 +66,25 @@ __global__ __launch_bounds__(RN_BLOCK) void k_cg_update(int64_t nnz, int64_t str
   int32_t *st = stv + (int64_t)b * ST_STRIDE;
   double *sc = scal + (int64_t)b * scal_stride;
   const int64_t off = (int64_t)b * stride, gs = (int64_t)gridDim.x * RN_BLOCK;
-  // the first element's loads go out with the status, gamma_k and partial
-  // loads (one memory round trip before the first store); then one element
-  // ahead.  A stopped entry's loads are made and not used.
-  int64_t e = (int64_t)blockIdx.x * RN_BLOCK + threadIdx.x;
-  double p = 0.0, d = 0.0, r = 0.0, z = 0.0;
-  if (e < nnz) {
-    p = P[off + e];
-    d = D[off + e];
-    r = R[off + e];
-    z = Z[off + e];
-  }
+  const int64_t e0 = (int64_t)blockIdx.x * RN_BLOCK + threadIdx.x;
+  double p[CG_UPD_U], d[CG_UPD_U], r[CG_UPD_U], z[CG_UPD_U];
+  auto load = [&](int64_t base) {
+#pragma unroll
+    for (int u = 0; u < CG_UPD_U; ++u) {
+      const int64_t e = base + u * gs;
+      p[u] = d[u] = r[u] = z[u] = 0.0;
+      if (e < nnz) {
+        p[u] = P[off + e];
+        d[u] = D[off + e];
+        r[u] = R[off + e];
+        z[u] = Z[off + e];
+      }
+    }
+  };
+  // the first round's loads go out with the status, gamma_k and partial
+  // loads (one memory round trip before the first store).  A stopped
+  // entry's loads are made and not used.
+  load(e0);
   const int32_t s0 = st[ST_STATUS], s1 = st[ST_DONE];
   const double gam = sc[CgLayout(K).gam + k];
   const double dl = rn_reduce_part(part_spg + (int64_t)b * pstride, np, s_w);
@@ -80,25 +96,19 @@ __global__ __launch_bounds__(RN_BLOCK) void k_cg_update(int64_t nnz, int64_t str
   if (!isfinite(dl) || dl <= 0.0) return;  // breakdown: nothing is updated
   const double al = gam / dl;
   RnAcc s;
-  while (e < nnz) {
-    const int64_t en = e + gs;
-    double pn = 0.0, dn = 0.0, rn = 0.0, zn = 0.0;
-    if (en < nnz) {
-      pn = P[off + en];
-      dn = D[off + en];
-      rn = R[off + en];
-      zn = Z[off + en];
+  for (int64_t base = e0; base < nnz; base += CG_UPD_U * gs) {
+    if (base != e0) load(base);
+#pragma unroll
+    for (int u = 0; u < CG_UPD_U; ++u) {
+      const int64_t e = base + u * gs;
+      if (e < nnz) {
+        P[off + e] = p[u] + al * d[u];
+        const double rr = r[u] - al * z[u];
+        R[off + e] = rr;
+        if (Rrec) Rrec[off + e] = rr;
+        s.add(rr * rr);
+      }
     }
-    P[off + e] = p + al * d;
-    const double rr = r - al * z;
-    R[off + e] = rr;
-    if (Rrec) Rrec[off + e] = rr;
-    s.add(rr * rr);
-    e = en;
-    p = pn;
-    d = dn;
-    r = rn;
-    z = zn;
   }
   const double S = rn_block_sum2(s.hi, s.lo, s_w);
   if (threadIdx.x == 0) part_ew[(int64_t)b * RN_MAXDOT * gridDim.x + blockIdx.x] = S;
@@ -120,14 +130,22 @@ __global__ __launch_bounds__(RN_BLOCK) void k_cg_dir(int64_t nnz, int64_t stride
   double *sc = scal + (int64_t)b * scal_stride;
   const CgLayout L(K);
   const int64_t off = (int64_t)b * stride, gs = (int64_t)gridDim.x * RN_BLOCK;
-  // status, gamma_k, gamma_0, the partials and the first element go out
-  // together (one memory round trip); then one element ahead
-  int64_t e = (int64_t)blockIdx.x * RN_BLOCK + threadIdx.x;
-  double r = 0.0, d = 0.0;
-  if (e < nnz) {
-    r = R[off + e];
-    d = D[off + e];
-  }
+  const int64_t e0 = (int64_t)blockIdx.x * RN_BLOCK + threadIdx.x;
+  double r[CG_DIR_U], d[CG_DIR_U];
+  auto load = [&](int64_t base) {
+#pragma unroll
+    for (int u = 0; u < CG_DIR_U; ++u) {
+      const int64_t e = base + u * gs;
+      r[u] = d[u] = 0.0;
+      if (e < nnz) {
+        r[u] = R[off + e];
+        d[u] = D[off + e];
+      }
+    }
+  };
+  // status, gamma_k, gamma_0, the partials and the first round go out
+  // together (one memory round trip)
+  load(e0);
   const int32_t s0 = st[ST_STATUS], s1 = st[ST_DONE];
   const double gam = sc[L.gam + k], gam0 = sc[SC_GAMMA0];
   const double g = rn_reduce_part(part_ew + (int64_t)b * RN_MAXDOT * nb_ew, nb_ew, s_w);
@@ -138,21 +156,38 @@ __global__ __launch_bounds__(RN_BLOCK) void k_cg_dir(int64_t nnz, int64_t stride
   if (blockIdx.x == 0 && threadIdx.x == 0)
     rn_cg_beta_fin(g, gam, gam0, sc, st, histv ? histv + (int64_t)b * hist_stride : nullptr, K, k);
   if (!isfinite(g)) return;
-  while (e < nnz) {
-    const int64_t en = e + gs;
-    double rn = 0.0, dn = 0.0;
-    if (en < nnz) {
-      rn = R[off + en];
-      dn = D[off + en];
+  for (int64_t base = e0; base < nnz; base += CG_DIR_U * gs) {
+    if (base != e0) load(base);
+#pragma unroll
+    for (int u = 0; u < CG_DIR_U; ++u) {
+      const int64_t e = base + u * gs;
+      if (e < nnz) {
+        const double dd = r[u] + be * d[u];
+        D[off + e] = dd;
+        if (Drec) Drec[off + e] = dd;
+        if (MIXED) D32[off + e] = (float)dd;
+      }
     }
-    const double dd = r + be * d;
-    D[off + e] = dd;
-    if (Drec) Drec[off + e] = dd;
-    if (MIXED) D32[off + e] = (float)dd;
-    e = en;
-    r = rn;
-    d = dn;
   }
+}
+
+// After the last fused step: gamma_K, beta_{K-1}, the step count and the
+// stopping test from the last update's <R,R> partials (one block per batch
+// entry; the direction D_K is not formed)
+__global__ __launch_bounds__(RN_BLOCK) void k_cg_last(int nb_ew, const double *__restrict__ part_ew, int K,
+                                                     double *__restrict__ scal, int scal_stride,
+                                                     int32_t *__restrict__ stv, double *__restrict__ histv,
+                                                     int hist_stride) {
+  __shared__ double s_w[8];
+  const int b = blockIdx.x;
+  int32_t *st = stv + (int64_t)b * ST_STRIDE;
+  double *sc = scal + (int64_t)b * scal_stride;
+  const CgLayout L(K);
+  const int32_t s0 = st[ST_STATUS], s1 = st[ST_DONE];
+  const double gam = sc[L.gam + K - 1], gam0 = sc[SC_GAMMA0];
+  const double g = rn_reduce_part(part_ew + (int64_t)b * RN_MAXDOT * nb_ew, nb_ew, s_w);
+  if (s0 || s1 || threadIdx.x != 0) return;
+  rn_cg_beta_fin(g, gam, gam0, sc, st, histv ? histv + (int64_t)b * hist_stride : nullptr, K, K - 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -864,7 +899,15 @@ extern "C" rn_status rn_energy_min(rn_ctx *ctx, rn_plan *pl, const double *A_val
 
 // Workspace bytes emin_run requests (each piece rounded to 256 bytes, as the
 // arena carves them), and the bytes of its one read-back.
-static size_t emin_ws_need(const rn_plan *pl, int32_t batch, bool gm, bool pcg, int K, bool mixed, size_t *fetch) {
+// plain FP64 CG without a tape forms each direction inside the next product
+// when the context allows it and the persistent product serves the plan
+static bool cg_fused(const rn_ctx *ctx, const rn_plan *pl, int32_t batch, rn_method method, rn_precision prec,
+                     bool tape) {
+  return ctx->opt[RN_OPT_FUSED_CG] && method == RN_CG && prec == RN_FP64 && !tape && rn_spgemm_fused_ok(pl, batch);
+}
+
+static size_t emin_ws_need(const rn_plan *pl, int32_t batch, bool gm, bool pcg, int K, bool mixed, bool fused,
+                           size_t *fetch) {
   auto r = [](size_t b) { return (b + 255) & ~(size_t)255; };
   const int64_t nz = pl->nnzN, nzb = (int64_t)batch * nz;
   const unsigned gew = gm ? ew_grid(nz) : std::min(ew_grid(nz), 1024u);
@@ -874,7 +917,7 @@ static size_t emin_ws_need(const rn_plan *pl, int32_t batch, bool gm, bool pcg, 
                 r((size_t)batch * RN_MAXDOT * ((size_t)pl->nblk + gew + 2) * 8);
   if (mixed) need += r((size_t)batch * p.strideA * 4) + r((size_t)nz * 4);
   if (!gm) {
-    need += 3 * r((size_t)nzb * 8) + (mixed ? r((size_t)nzb * 4) : 0);
+    need += (fused ? 4 : 3) * r((size_t)nzb * 8) + (mixed ? r((size_t)nzb * 4) : 0);
     if (pcg) need += r((size_t)nzb * 8) + r((size_t)batch * (pl->n + 1) * 8);
   } else {
     const size_t ub = (size_t)(K + 1) * nz;
@@ -899,7 +942,7 @@ extern "C" rn_status rn_energy_min_noalloc(rn_ctx *ctx, rn_plan *pl, const doubl
   if (!ctx->rb_host) return rn_fail(ctx, RN_ENOMEM, "rn_energy_min_noalloc: no read-back area");
   size_t fetch = 0;
   const size_t need = emin_ws_need(pl, batch, method == RN_GMRES, method == RN_PCG_JACOBI, iters,
-                                   prec == RN_FP32_MIXED, &fetch);
+                                   prec == RN_FP32_MIXED, cg_fused(ctx, pl, batch, method, prec, false), &fetch);
   if (need > RN_NOALLOC_SCRATCH_BYTES)
     return rn_fail(ctx, RN_ELIMIT,
                    "rn_energy_min_noalloc: the call needs %zu bytes of scratch, the allocation-free limit is %zu",
@@ -929,6 +972,7 @@ static rn_status emin_run(rn_ctx *ctx, rn_plan *pl, const double *A_vals, int32_
                           rn_emin_stats *stats, rn_tape *tape) {
   const bool mixed = prec == RN_FP32_MIXED;
   const bool gm = method == RN_GMRES;
+  const bool fuse = cg_fused(ctx, pl, batch, method, prec, tape != nullptr);
   const int K = iters;
   const int64_t nz = pl->nnzN, nzb = (int64_t)batch * nz;
   rn_status st = RN_OK;
@@ -1069,11 +1113,14 @@ static rn_status emin_run(rn_ctx *ctx, rn_plan *pl, const double *A_vals, int32_
       LAUNCH_CHECK(ctx);
     }
   } else if (!gm) {
+    // fused: D_k alternates between D and D2 (product k reads D_{k-1} from
+    // one and writes D_k to the other while other workgroups still read)
     double *R = (double *)rn_plan_ws(pl, WS_R, (size_t)nzb * 8, &st);
     double *D = (double *)rn_plan_ws(pl, WS_D, (size_t)nzb * 8, &st);
     double *Z = (double *)rn_plan_ws(pl, WS_Z, (size_t)nzb * 8, &st);
     float *D32 = mixed ? (float *)rn_plan_ws(pl, WS_D32, (size_t)nzb * 4, &st) : nullptr;
-    if (!R || !D || !Z || (mixed && !D32)) return st;
+    double *D2 = fuse ? (double *)rn_plan_ws(pl, WS_D2, (size_t)nzb * 8, &st) : nullptr;
+    if (!R || !D || !Z || (mixed && !D32) || (fuse && !D2)) return st;
     hipLaunchKernelGGL(k_cg_start, g2, blk, 0, ctx->stream, T, nz, nz, P, p.st, n_st, p.scal, n_sc, hist, n_hist);
     LAUNCH_CHECK(ctx);
     // R_0 = D_0 = -Pi(A T), gamma_0
@@ -1100,15 +1147,30 @@ static rn_status emin_run(rn_ctx *ctx, rn_plan *pl, const double *A_vals, int32_
       SpgParams s = p;
       s.k = k;
       s.Ax = Aop;
-      s.X = mixed ? (const void *)D32 : (const void *)D;
-      s.Xown = D;
       s.Z = Z;
+      double *Dk = (fuse && (k & 1)) ? D2 : D;
       int np = 0;
-      RN_TRY(rn_launch_spgemm(ctx, pl, MODE_CG_STEP, s, batch, mixed, &np));
-      hipLaunchKernelGGL(k_cg_update, g2, blk, 0, ctx->stream, nz, nz, K, k, np, pstride_spg, part_spg, P, R, D, Z,
+      if (fuse && k > 0) {
+        // beta_{k-1}, the stopping test and D_k in the product's staging
+        s.X = (k & 1) ? D : D2;
+        s.Rres = R;
+        s.Dnew = Dk;
+        s.part_rr = part_ew;
+        s.np_rr = (int)gew;
+        s.pstride_rr = pstride_ew;
+        s.hist = hist;
+        s.hist_stride = hist_stride;
+        RN_TRY(rn_launch_spgemm(ctx, pl, MODE_CG_FSTEP, s, batch, false, &np));
+      } else {
+        s.X = mixed ? (const void *)D32 : (const void *)D;
+        s.Xown = D;
+        RN_TRY(rn_launch_spgemm(ctx, pl, MODE_CG_STEP, s, batch, mixed, &np));
+      }
+      hipLaunchKernelGGL(k_cg_update, g2, blk, 0, ctx->stream, nz, nz, K, k, np, pstride_spg, part_spg, P, R, Dk, Z,
                          part_ew, p.scal, scal_stride, p.st, hist, hist_stride,
                          tape ? rn_tape_R(tape, k + 1) : nullptr);
       LAUNCH_CHECK(ctx);
+      if (fuse) continue;
       if (mixed)
         hipLaunchKernelGGL(k_cg_dir<true>, g2, blk, 0, ctx->stream, nz, nz, K, k, (int)gew, R, D, D32, part_ew, p.scal,
                            scal_stride, p.st, hist, hist_stride, (double *)nullptr);
@@ -1116,6 +1178,11 @@ static rn_status emin_run(rn_ctx *ctx, rn_plan *pl, const double *A_vals, int32_
         hipLaunchKernelGGL(k_cg_dir<false>, g2, blk, 0, ctx->stream, nz, nz, K, k, (int)gew, R, D, (float *)nullptr,
                            part_ew, p.scal, scal_stride, p.st, hist, hist_stride,
                            tape ? rn_tape_D(tape, k + 1) : nullptr);
+      LAUNCH_CHECK(ctx);
+    }
+    if (fuse && K > 0) {
+      hipLaunchKernelGGL(k_cg_last, dim3(batch), blk, 0, ctx->stream, (int)gew, part_ew, K, p.scal, scal_stride, p.st,
+                         hist, hist_stride);
       LAUNCH_CHECK(ctx);
     }
     if (tape) RN_TRY(rn_tape_record_end(ctx, tape, p.scal, p.st, batch));
@@ -1231,6 +1298,7 @@ static rn_status emin_run(rn_ctx *ctx, rn_plan *pl, const double *A_vals, int32_
     stats->energy = stats->proj_residual = stats->constraint_residual = NAN;
     stats->iters_done = hst[gm ? ST_KD : ST_ITERS];
     stats->rank_deficient_rows = pl->rank_def;
+    stats->fused_cg = fuse ? 1 : 0;
     stats->status_code = hst[ST_STATUS];
     if (gm) {
       const GmLayout L(K);

@@ -566,6 +566,15 @@ __global__ __launch_bounds__(BS) void k_spgemm_p(const SpgParams p, const int G)
   constexpr int NU = XCAP / XW_UNIT;
   constexpr int NWV = BS / RN_WAVE;
   constexpr int UMAX = 11;
+  // CG step with the direction formed in the staging: X is D_{k-1} and each
+  // window element is R + beta D_{k-1}, loaded as whole doubles, two units
+  // (one per half wave) per load
+  constexpr bool FUSE = MODE == MODE_CG_FSTEP;
+  constexpr bool CGS = MODE == MODE_CG_STEP || FUSE;
+  constexpr int XF = FUSE ? XIT / 2 : 1;
+  // (256 lanes: the partials of beta are summed in the order the separate
+  // direction pass uses)
+  static_assert(!FUSE || (!MIXED && XIT % 2 == 0 && BS == RN_BLOCK), "fused step: FP64, units in pairs");
   static_assert(NIT * BS == ACAP && NITD * BS == ACAP * DPE, "staging covers the capacity exactly");
   // row starts double-buffered (the projection of one block reads them while
   // the next block is staged); the projection terms have their own buffer:
@@ -584,7 +593,7 @@ __global__ __launch_bounds__(BS) void k_spgemm_p(const SpgParams p, const int G)
   const int wv = __builtin_amdgcn_readfirstlane(t / RN_WAVE);
   const int32_t *st = p.st + (int64_t)b * ST_STRIDE;
   const double *sc = p.scal + (int64_t)b * p.scal_stride;
-  if (MODE == MODE_CG_STEP || MODE == MODE_GM_STEP)
+  if (CGS || MODE == MODE_GM_STEP)
     if (st[ST_STATUS] || st[ST_DONE]) return;
   if (p.kact >= 0 && st[ST_ITERS] <= p.kact) return;
   const int per = (p.nblk + 7) >> 3, Gx = G >> 3;
@@ -594,13 +603,15 @@ __global__ __launch_bounds__(BS) void k_spgemm_p(const SpgParams p, const int G)
   // single-dot modes: one partial per workgroup (slot blockIdx.x)
   double *pcw = p.part + (int64_t)b * RN_MAXDOT * p.nblk;
   if (blk >= hiB) {
-    if ((MODE == MODE_CG_INIT || MODE == MODE_GM_INIT || MODE == MODE_CG_STEP) && t == 0) pcw[blockIdx.x] = 0.0;
+    if ((MODE == MODE_CG_INIT || MODE == MODE_GM_INIT || CGS) && t == 0) pcw[blockIdx.x] = 0.0;
     return;
   }
 
   const bool proj = (MODE != MODE_PRODUCT) || p.project;
   const TV *Ax = (const TV *)p.Ax + (int64_t)b * p.strideA;
   const TV *X = (const TV *)p.X + (int64_t)b * p.strideX;
+  const double *Rr = FUSE ? p.Rres + (int64_t)b * p.strideX : nullptr;
+  double be = 0.0;  // fused step: beta_{k-1}, set before the first staging
   const int64_t zb = (int64_t)b * p.strideZ;
   double *Z = p.Z + zb;
   double *part = p.part + (int64_t)b * RN_MAXDOT * p.nblk;
@@ -647,10 +658,11 @@ __global__ __launch_bounds__(BS) void k_spgemm_p(const SpgParams p, const int G)
   // ---- a block's first round of vector loads (registers) ----
   struct Rd {
     uint32_t w0, w1;  // compact record (row, 5-bit codes)
-    double bcv[NB], gp[NP], own;
+    double bcv[NB], gp[NP], own, ownr;
     int rp, ap;
     int x0[NIT];
     uint32_t ad[NITD], xw[XIT];
+    double fr[XF], fd[XF];  // fused step: the window's R and D_{k-1}
   };
   auto load_rd = [&](const Hd &h, Rd &r) {
     const int te = t < h.ne ? t : 0;
@@ -658,8 +670,12 @@ __global__ __launch_bounds__(BS) void k_spgemm_p(const SpgParams p, const int G)
     const uint2 r2 = *(const uint2 *)((const char *)p.ccodes + e * 8u);  // compact record
     r.w0 = r2.x;
     r.w1 = r2.y;
-    r.own = 0.0;
+    r.own = r.ownr = 0.0;
     if (MODE == MODE_CG_STEP) r.own = spg_ld(p.Xown + zb, e);
+    if (FUSE) {  // this lane's R and D_{k-1} (D_k is formed in the epilogue)
+      r.ownr = spg_ld(Rr, e);
+      r.own = spg_ld((const double *)X, e);
+    }
     const int rq = t < h.nrows ? t : h.nrows - 1, rt = t < h.nrows ? t : h.nrows;
     r.rp = spg_ld(p.Np, (uint32_t)(h.r0 + rt));
     r.ap = spg_ld(p.Ap, (uint32_t)(h.r0 + rt));
@@ -694,8 +710,16 @@ __global__ __launch_bounds__(BS) void k_spgemm_p(const SpgParams p, const int G)
       for (int it = 0; it < NITD; ++it)
         r.ad[it] = spg_ld(Axd, (uint32_t)(a0 * DPE + min(t + it * BS, nd - 1)));
       const uint32_t *Xd = (const uint32_t *)X;
+      if (FUSE) {
 #pragma unroll
-      for (int i = 0; i < XIT; ++i) {
+        for (int j = 0; j < XF; ++j) {
+          const uint32_t xi = (uint32_t)((lane < 32 ? h.uw[2 * j] : h.uw[2 * j + 1]) + (lane & 31));
+          r.fr[j] = spg_ld(Rr, xi);
+          r.fd[j] = spg_ld((const double *)X, xi);
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < (FUSE ? 0 : XIT); ++i) {
         if (DPE == 2) {
           r.xw[i] = spg_ld(Xd, (uint32_t)(2 * h.uw[i] + lane));
         } else {
@@ -724,9 +748,17 @@ __global__ __launch_bounds__(BS) void k_spgemm_p(const SpgParams p, const int G)
 #pragma unroll
       for (int it = 0; it < NITD; ++it) s_ad[t + it * BS] = r.ad[it];
       if (h.nunit > 0) {
-        uint32_t *s_xd = (uint32_t *)s_xw;
+        if (FUSE) {
+          // unit wv + i NWV at element (wv + i NWV) XW_UNIT; the same
+          // rounding as the separate direction pass (no contraction)
 #pragma unroll
-        for (int i = 0; i < XIT; ++i) s_xd[(wv + i * NWV) * 64 + lane] = r.xw[i];
+          for (int j = 0; j < XF; ++j)
+            ((double *)s_xw)[(wv + (2 * j + (lane >> 5)) * NWV) * XW_UNIT + (lane & 31)] = r.fr[j] + be * r.fd[j];
+        } else {
+          uint32_t *s_xd = (uint32_t *)s_xw;
+#pragma unroll
+          for (int i = 0; i < XIT; ++i) s_xd[(wv + i * NWV) * 64 + lane] = r.xw[i];
+        }
       }
     }
   };
@@ -746,6 +778,21 @@ __global__ __launch_bounds__(BS) void k_spgemm_p(const SpgParams p, const int G)
   load_rd(H, R);  // same issue order as in the loop: first round, then the next header
   // (unconditional, clamped: the wait counts then agree on every path)
   load_hdv(min(blk + Gx, hiB - 1), V1);
+  if (FUSE) {
+    // beta_{k-1} = gamma_k / gamma_{k-1} from the update's <R,R> partials,
+    // loaded behind the first round (one wait for both): every workgroup
+    // sums them in the same fixed order, so all get the same gamma_k and
+    // take the same stopping decision; workgroup 0 stores the scalars and
+    // the test.  The window is combined with beta at the first staging.
+    const CgLayout L(p.K);
+    const double gam = sc[L.gam + p.k - 1], gam0 = sc[SC_GAMMA0];
+    const double g = rn_reduce_part_w<BS>(p.part_rr + (int64_t)b * p.pstride_rr, p.np_rr, s_w);
+    if (blockIdx.x == 0 && t == 0)
+      rn_cg_beta_fin(g, gam, gam0, p.scal + (int64_t)b * p.scal_stride, p.st + (int64_t)b * ST_STRIDE,
+                     p.hist ? p.hist + (int64_t)b * p.hist_stride : nullptr, p.K, p.k - 1);
+    if (!isfinite(g) || g <= RN_CG_STOP * gam0) return;  // stopped: no D_k, no product
+    be = g / gam;
+  }
   // single-dot modes: every lane adds its terms over all of this workgroup's
   // blocks, in block order; one compensated block sum at the end
   RnAcc dacc;
@@ -802,6 +849,7 @@ __global__ __launch_bounds__(BS) void k_spgemm_p(const SpgParams p, const int G)
           if (path < 2) av[u - lo] = s_ax[la + u];
           else av[u - lo] = Ax[H.aB + min(la + u, H.naB - 1)];
           if (path == 0) xv[u - lo] = s_xw[xi[u - lo]];
+          else if (FUSE) xv[u - lo] = spg_ld(Rr, xi[u - lo]) + be * spg_ld((const double *)X, xi[u - lo]);
           else xv[u - lo] = spg_ld(X, xi[u - lo]);
         }
 #pragma unroll
@@ -879,6 +927,13 @@ __global__ __launch_bounds__(BS) void k_spgemm_p(const SpgParams p, const int G)
         spg_st(Z, e, z);
         dacc.add(R.own * z);
       }
+    } else if (FUSE) {
+      if (valid) {
+        const double dk = R.ownr + be * R.own;
+        spg_st(p.Dnew + zb, e, dk);
+        spg_st(Z, e, z);
+        dacc.add(dk * z);
+      }
     } else if (MODE == MODE_GM_STEP) {
       if (valid) spg_st(Z, e, z);
     }
@@ -892,7 +947,7 @@ __global__ __launch_bounds__(BS) void k_spgemm_p(const SpgParams p, const int G)
     R = Rn;
     V1 = V2;
   }
-  if (MODE == MODE_CG_INIT || MODE == MODE_GM_INIT || MODE == MODE_CG_STEP) {
+  if (MODE == MODE_CG_INIT || MODE == MODE_GM_INIT || CGS) {
     const double S = rn_block_sum2_w<NWV>(dacc.hi, dacc.lo, s_w);
     if (t == 0) pcw[blockIdx.x] = S;
   }
@@ -929,31 +984,49 @@ static int launch_p(const SpgParams &p, int batch, bool mixed, hipStream_t s) {
   return G;
 }
 
-// the number of per-workgroup partials a single-dot mode leaves
+// the fused CG step runs only as the persistent FP64 product of 256 lanes
+static bool fused_plan(const SpgParams &p) {
+  return p.ccodes && p.nnzN >= 64 && p.strideA >= 1 && p.persist && p.bs == RN_BLOCK;
+}
+
+// the number of per-workgroup partials a single-dot mode leaves (0: the
+// fused step cannot run)
 template <int M, int NB, int MODE>
 static int launch_m(const SpgParams &p, int batch, bool mixed, hipStream_t s) {
-  if constexpr (M == 1 && NB <= 2) {
-    // the persistent form serves scalar operators with n_B <= 2 and compact
-    // records, unless the plan was made with RN_OPT_PERSISTENT_PRODUCT = 0
-    // (the branch-free first round reads 32 elements of X and one of A whatever the block)
-    if (p.ccodes && p.nnzN >= 64 && p.strideA >= 1 && p.persist) {
-      int G = 0;
-      if (p.bs == 128 && (G = launch_p<NB, MODE, 128>(p, batch, mixed, s)) > 0) return G;
-      if (p.bs == RN_BLOCK && (G = launch_p<NB, MODE, RN_BLOCK>(p, batch, mixed, s)) > 0) return G;
+  if constexpr (MODE == MODE_CG_FSTEP) {
+    if constexpr (M == 1 && NB <= 2) {
+      if (mixed || !fused_plan(p)) return 0;
+      const int G = persist_grid<NB, MODE, false, RN_BLOCK>(p.nblk, batch);
+      if (G < 8) return 0;
+      hipLaunchKernelGGL((k_spgemm_p<NB, MODE, false, RN_BLOCK>), dim3((unsigned)G, (unsigned)batch),
+                         dim3(RN_BLOCK), 0, s, p, G);
+      return G;
     }
-  }
-  const dim3 grid(rn_xcd_grid((unsigned)p.nblk), (unsigned)batch);
-  if (M == 1 && p.bs == 128) {
-    if (mixed) hipLaunchKernelGGL((k_spgemm<M, NB, MODE, true, 128>), grid, dim3(128), 0, s, p);
-    else hipLaunchKernelGGL((k_spgemm<M, NB, MODE, false, 128>), grid, dim3(128), 0, s, p);
-  } else if (M == 1 && p.bs == 64) {
-    if (mixed) hipLaunchKernelGGL((k_spgemm<M, NB, MODE, true, 64>), grid, dim3(64), 0, s, p);
-    else hipLaunchKernelGGL((k_spgemm<M, NB, MODE, false, 64>), grid, dim3(64), 0, s, p);
+    return 0;
   } else {
-    if (mixed) hipLaunchKernelGGL((k_spgemm<M, NB, MODE, true, RN_BLOCK>), grid, dim3(RN_BLOCK), 0, s, p);
-    else hipLaunchKernelGGL((k_spgemm<M, NB, MODE, false, RN_BLOCK>), grid, dim3(RN_BLOCK), 0, s, p);
+    if constexpr (M == 1 && NB <= 2) {
+      // the persistent form serves scalar operators with n_B <= 2 and compact
+      // records, unless the plan was made with RN_OPT_PERSISTENT_PRODUCT = 0
+      // (the branch-free first round reads 32 elements of X and one of A whatever the block)
+      if (p.ccodes && p.nnzN >= 64 && p.strideA >= 1 && p.persist) {
+        int G = 0;
+        if (p.bs == 128 && (G = launch_p<NB, MODE, 128>(p, batch, mixed, s)) > 0) return G;
+        if (p.bs == RN_BLOCK && (G = launch_p<NB, MODE, RN_BLOCK>(p, batch, mixed, s)) > 0) return G;
+      }
+    }
+    const dim3 grid(rn_xcd_grid((unsigned)p.nblk), (unsigned)batch);
+    if (M == 1 && p.bs == 128) {
+      if (mixed) hipLaunchKernelGGL((k_spgemm<M, NB, MODE, true, 128>), grid, dim3(128), 0, s, p);
+      else hipLaunchKernelGGL((k_spgemm<M, NB, MODE, false, 128>), grid, dim3(128), 0, s, p);
+    } else if (M == 1 && p.bs == 64) {
+      if (mixed) hipLaunchKernelGGL((k_spgemm<M, NB, MODE, true, 64>), grid, dim3(64), 0, s, p);
+      else hipLaunchKernelGGL((k_spgemm<M, NB, MODE, false, 64>), grid, dim3(64), 0, s, p);
+    } else {
+      if (mixed) hipLaunchKernelGGL((k_spgemm<M, NB, MODE, true, RN_BLOCK>), grid, dim3(RN_BLOCK), 0, s, p);
+      else hipLaunchKernelGGL((k_spgemm<M, NB, MODE, false, RN_BLOCK>), grid, dim3(RN_BLOCK), 0, s, p);
+    }
+    return p.nblk;
   }
-  return p.nblk;
 }
 
 template <int MODE>
@@ -975,8 +1048,17 @@ static rn_status launch_mode(rn_ctx *ctx, const rn_plan *pl, const SpgParams &p,
       default: return rn_fail(ctx, RN_EINVAL, "nB out of range for block_m = 2");
     }
   }
+  if (MODE == MODE_CG_FSTEP && *np == 0)
+    return rn_fail(ctx, RN_EINVAL, "fused CG step requested for a plan the persistent product cannot serve");
   LAUNCH_CHECK(ctx);
   return RN_OK;
+}
+
+bool rn_spgemm_fused_ok(const rn_plan *pl, int batch) {
+  const SpgParams p = rn_spg_params(pl);
+  if (pl->m != 1 || pl->nB > 2 || p.nblk <= 0 || !fused_plan(p)) return false;
+  return (pl->nB == 1 ? persist_grid<1, MODE_CG_FSTEP, false, RN_BLOCK>(p.nblk, batch)
+                      : persist_grid<2, MODE_CG_FSTEP, false, RN_BLOCK>(p.nblk, batch)) >= 8;
 }
 
 rn_status rn_launch_spgemm(rn_ctx *ctx, const rn_plan *pl, int mode, const SpgParams &p, int batch, bool mixed,
@@ -990,6 +1072,7 @@ rn_status rn_launch_spgemm(rn_ctx *ctx, const rn_plan *pl, int mode, const SpgPa
       case MODE_CG_STEP: st = launch_mode<MODE_CG_STEP>(ctx, pl, p, batch, mixed, &np); break;
       case MODE_GM_INIT: st = launch_mode<MODE_GM_INIT>(ctx, pl, p, batch, mixed, &np); break;
       case MODE_GM_STEP: st = launch_mode<MODE_GM_STEP>(ctx, pl, p, batch, mixed, &np); break;
+      case MODE_CG_FSTEP: st = launch_mode<MODE_CG_FSTEP>(ctx, pl, p, batch, mixed, &np); break;
       default: return rn_fail(ctx, RN_EINVAL, "bad product mode");
     }
   }
