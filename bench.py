@@ -430,7 +430,11 @@ def mixed_vs_oracle_elastic(Ab, Bh, agg, roots, res):
     st = O.setup(A, Bh, 2, 0.0, 2, agg=agg, roots=roots)
     Pref, _ = O.emin_cg(A.rowptr, A.colind, A.vals, st["Np"], st["Nj"], st["is_root"], st["nc"], st["Bc"], 3,
                         st["T"], 6)
-    out = {}
+    # rows whose Bc rows do not span the candidates (rank-deficient Gram)
+    # cannot meet P Bc = B exactly: the oracle's own residual is the reference
+    out = {"elastic512_oracle_constraint_residual": O.constraint_residual(st["Np"], st["Nj"], Pref,
+                                                                          st["Bc"].reshape(-1, 3), Bh),
+           "elastic512_rank_deficient_rows": int(st["rank_def"])}
     for key in ("fp64", "fp32_mixed"):
         P, Np, Nj, Bc = res[key]
         assert np.array_equal(Nj, st["Nj"])

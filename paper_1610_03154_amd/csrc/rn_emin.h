@@ -129,6 +129,7 @@ struct SpgParams {
   int32_t kact;   // >= 0: batch entries whose st[ST_ITERS] <= kact do nothing
   int32_t unit_bc;  // every entry of Bc is 1: the projection's Bc rows are 1 (no per-entry loads)
   int32_t persist;  // the persistent product may serve the launch
+  int32_t grid;     // > 0: the persistent launch's workgroups per batch entry (a multiple of 8)
   int64_t nnzN, strideA, strideX, strideZ;
   const int32_t *Ap, *Aj, *Np, *Nj, *nodeptr, *ncol, *blk_row, *blk_hdr, *xoff, *xl, *xwin;
   const uint8_t *codes, *is_root;
@@ -159,8 +160,11 @@ struct SpgParams {
 rn_status rn_launch_spgemm(rn_ctx *ctx, const rn_plan *pl, int mode, const SpgParams &p, int batch, bool mixed,
                            int *npart = nullptr);
 SpgParams rn_spg_params(const rn_plan *pl);
-// the persistent product can serve MODE_CG_FSTEP launches of this plan
-bool rn_spgemm_fused_ok(const rn_plan *pl, int batch);
+// Workgroups per batch entry of the persistent MODE_CG_FSTEP launch for this
+// plan, or 0 when it cannot run.  FP64 CG passes it as SpgParams::grid to
+// every step product (MODE_CG_STEP too), so the <D, Pi(A D)> partials are
+// grouped alike whichever path forms the direction.
+int rn_spgemm_fused_grid(const rn_plan *pl, int batch);
 
 // rn_plan_create on the caller's guard word (not reset; NULL: a fresh one),
 // with one extra device item (nullable) read back at the plan's

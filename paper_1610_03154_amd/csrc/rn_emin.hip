@@ -903,7 +903,8 @@ extern "C" rn_status rn_energy_min(rn_ctx *ctx, rn_plan *pl, const double *A_val
 // when the context allows it and the persistent product serves the plan
 static bool cg_fused(const rn_ctx *ctx, const rn_plan *pl, int32_t batch, rn_method method, rn_precision prec,
                      bool tape) {
-  return ctx->opt[RN_OPT_FUSED_CG] && method == RN_CG && prec == RN_FP64 && !tape && rn_spgemm_fused_ok(pl, batch);
+  return ctx->opt[RN_OPT_FUSED_CG] && method == RN_CG && prec == RN_FP64 && !tape &&
+         rn_spgemm_fused_grid(pl, batch) > 0;
 }
 
 static size_t emin_ws_need(const rn_plan *pl, int32_t batch, bool gm, bool pcg, int K, bool mixed, bool fused,
@@ -1143,11 +1144,15 @@ static rn_status emin_run(rn_ctx *ctx, rn_plan *pl, const double *A_vals, int32_
       HIP_TRY(ctx, hipMemcpyAsync(rn_tape_R(tape, 0), R, (size_t)nzb * 8, hipMemcpyDeviceToDevice, ctx->stream));
       HIP_TRY(ctx, hipMemcpyAsync(rn_tape_D(tape, 0), D, (size_t)nzb * 8, hipMemcpyDeviceToDevice, ctx->stream));
     }
+    // FP64: every step product on the fused kernel's grid (the same
+    // grouping of the <D, Z> partials with or without fusion and tape)
+    const int step_grid = mixed ? 0 : rn_spgemm_fused_grid(pl, batch);
     for (int k = 0; k < K; ++k) {
       SpgParams s = p;
       s.k = k;
       s.Ax = Aop;
       s.Z = Z;
+      s.grid = step_grid;
       double *Dk = (fuse && (k & 1)) ? D2 : D;
       int np = 0;
       if (fuse && k > 0) {

@@ -976,7 +976,9 @@ static int persist_grid(int nblk, int batch) {
 // the grid of the persistent launch, or 0 when it cannot run
 template <int NB, int MODE, int BS>
 static int launch_p(const SpgParams &p, int batch, bool mixed, hipStream_t s) {
-  const int G = mixed ? persist_grid<NB, MODE, true, BS>(p.nblk, batch) : persist_grid<NB, MODE, false, BS>(p.nblk, batch);
+  const int G = p.grid > 0 ? p.grid
+                           : mixed ? persist_grid<NB, MODE, true, BS>(p.nblk, batch)
+                                   : persist_grid<NB, MODE, false, BS>(p.nblk, batch);
   if (G < 8) return 0;
   const dim3 grid((unsigned)G, (unsigned)batch);
   if (mixed) hipLaunchKernelGGL((k_spgemm_p<NB, MODE, true, BS>), grid, dim3(BS), 0, s, p, G);
@@ -996,7 +998,7 @@ static int launch_m(const SpgParams &p, int batch, bool mixed, hipStream_t s) {
   if constexpr (MODE == MODE_CG_FSTEP) {
     if constexpr (M == 1 && NB <= 2) {
       if (mixed || !fused_plan(p)) return 0;
-      const int G = persist_grid<NB, MODE, false, RN_BLOCK>(p.nblk, batch);
+      const int G = p.grid > 0 ? p.grid : persist_grid<NB, MODE, false, RN_BLOCK>(p.nblk, batch);
       if (G < 8) return 0;
       hipLaunchKernelGGL((k_spgemm_p<NB, MODE, false, RN_BLOCK>), dim3((unsigned)G, (unsigned)batch),
                          dim3(RN_BLOCK), 0, s, p, G);
@@ -1054,11 +1056,12 @@ static rn_status launch_mode(rn_ctx *ctx, const rn_plan *pl, const SpgParams &p,
   return RN_OK;
 }
 
-bool rn_spgemm_fused_ok(const rn_plan *pl, int batch) {
+int rn_spgemm_fused_grid(const rn_plan *pl, int batch) {
   const SpgParams p = rn_spg_params(pl);
-  if (pl->m != 1 || pl->nB > 2 || p.nblk <= 0 || !fused_plan(p)) return false;
-  return (pl->nB == 1 ? persist_grid<1, MODE_CG_FSTEP, false, RN_BLOCK>(p.nblk, batch)
-                      : persist_grid<2, MODE_CG_FSTEP, false, RN_BLOCK>(p.nblk, batch)) >= 8;
+  if (pl->m != 1 || pl->nB > 2 || p.nblk <= 0 || !fused_plan(p)) return 0;
+  const int G = pl->nB == 1 ? persist_grid<1, MODE_CG_FSTEP, false, RN_BLOCK>(p.nblk, batch)
+                            : persist_grid<2, MODE_CG_FSTEP, false, RN_BLOCK>(p.nblk, batch);
+  return G >= 8 ? G : 0;
 }
 
 rn_status rn_launch_spgemm(rn_ctx *ctx, const rn_plan *pl, int mode, const SpgParams &p, int batch, bool mixed,
