@@ -339,8 +339,9 @@ def traffic_bytes():
 
 def other_configs(reps, check_oracle):
     """The study's other two configurations at full size on the same GPU path,
-    aggregation precomputed on the host (an input), seconds per setup
-    (strength -> pattern -> T -> plan -> energy minimisation), FP64 and
+    aggregation precomputed on the host (an input), seconds per one-call
+    set-up (rn_setup: strength -> pattern -> T -> plan -> energy
+    minimisation), FP64 and
     FP32-mixed, and the FP32-mixed results against the FP64 oracle:
     upwind1024: first-order upwind convection-diffusion on 1024 x 1024
       (b at 3pi/16, eps 1e-4), B = B^ = ones, theta 0, S^2 C, P by 8 GMRES
@@ -371,12 +372,14 @@ def other_configs(reps, check_oracle):
     agg, roots = torch.as_tensor(a, device="cuda"), torch.as_tensor(r, device="cuda")
     B = torch.ones((A.n_rows, 1), dtype=torch.float64, device="cuda")
     res = {}
+    def host(s, name):
+        return s.tensor(name).cpu().numpy()
+
     for prec, key in ((R.RN_FP64, "fp64"), (R.RN_FP32_MIXED, "fp32_mixed")):
-        t, s = timed(lambda: R.setup(ctx, dA, B, 0.0, 2, 8, R.RN_GMRES, prec, Bhat=B, agg=agg, roots=roots))
+        t, s = timed(lambda: ctx.setup_native(dA, B, agg, roots, 0.0, 2, 8, R.RN_GMRES, prec, Bhat=B))
         out["upwind1024_gmres_P_RT_s_" + key] = t
-        res[key] = (s.P.cpu().numpy(), s.RT.cpu().numpy(), s.N[0].cpu().numpy(), s.N[1].cpu().numpy(),
-                    s.Bc.cpu().numpy())
-        del s
+        res[key] = (host(s, "P"), host(s, "RT"), host(s, "N_rowptr"), host(s, "N_colind"), host(s, "Bc"))
+        s.close()
     if check_oracle:
         out.update(mixed_vs_oracle_upwind(A, a, r, res))
     Ab, xy = W.q1_elasticity(512)
@@ -388,10 +391,10 @@ def other_configs(reps, check_oracle):
     B = torch.as_tensor(Bh, device="cuda")
     res = {}
     for prec, key in ((R.RN_FP64, "fp64"), (R.RN_FP32_MIXED, "fp32_mixed")):
-        t, s = timed(lambda: R.setup(ctx, dA, B, 0.0, 2, 6, R.RN_CG, prec, agg=agg, roots=roots))
+        t, s = timed(lambda: ctx.setup_native(dA, B, agg, roots, 0.0, 2, 6, R.RN_CG, prec))
         out["elastic512_cg_s_" + key] = t
-        res[key] = (s.P.cpu().numpy(), s.N[0].cpu().numpy(), s.N[1].cpu().numpy(), s.Bc.cpu().numpy())
-        del s
+        res[key] = (host(s, "P"), host(s, "N_rowptr"), host(s, "N_colind"), host(s, "Bc"))
+        s.close()
     if check_oracle:
         out.update(mixed_vs_oracle_elastic(Ab, Bh, a, r, res))
     ctx.close()

@@ -111,6 +111,7 @@ struct rn_plan {
   int32_t rank_def = 0, maxlen = 0, chunk = 1, nblk = 0;
   int32_t bs = RN_BLOCK;        // lanes per product block (block_m = 1: 64, 128 or 256)
   bool persist = true;          // the persistent product may serve this plan
+  bool gp_ext = false;          // gp is the caller's array (not freed with the plan)
   unsigned long long *d_terms = nullptr;  // multiply-add terms of one product
   size_t fixed_bytes = 0;
   RnScratch ws[WS_COUNT];
@@ -170,16 +171,21 @@ int rn_spgemm_fused_grid(const rn_plan *pl, int batch);
 // with one extra device item (nullable) read back at the plan's
 // synchronisation into extra_out (host, extra->bytes).
 // validate = false: A and N were checked (or made) by the caller.
+// gp_in (nullable): every row's G^+ as Eq. Tproj formed it (packed, root
+// rows zero, the same row group as the plan's own Gram kernel); the plan
+// uses that array in place of computing its own (the caller keeps it alive
+// for the plan's lifetime) and reports no rank-deficient rows itself.
 rn_status rn_plan_create_ex(rn_ctx *ctx, const rn_matrix *A, int32_t n_cols, const int32_t *Np, const int32_t *Nj,
                             int64_t nnz_N, const uint8_t *is_root, const double *Bc, int32_t nB, rn_plan **out,
-                            int32_t *guard_in, const RnFetch *extra, unsigned char *extra_out, bool validate);
+                            int32_t *guard_in, const RnFetch *extra, unsigned char *extra_out, bool validate,
+                            const double *gp_in = nullptr);
 // rn_tentative without its synchronisation: kernels queued on guard, the
 // device flags (singular root block, rank-deficient rows) in *flags; then
 // rn_tentative_flags on the flags as read back.
 rn_status rn_tentative_launch(rn_ctx *ctx, int32_t n, int32_t m, const int32_t *Np, const int32_t *Nj,
                               int64_t nnz_N, const uint8_t *is_root, const int32_t *agg, const int32_t *roots,
                               int32_t n_agg, const double *B, int32_t nB, double *T, double *Bc, int32_t *guard,
-                              const int32_t **flags, bool validate);
+                              const int32_t **flags, bool validate, double *gp_out);
 rn_status rn_tentative_flags(rn_ctx *ctx, const int32_t hf[2], int32_t *rank_deficient);
 
 // tape hooks called by rn_energy_min (CG, FP64) -- implemented with the adjoint

@@ -11,6 +11,10 @@
 
 #define RN_NBMAX 4
 
+// Lanes per row of the kernels that write T row by row: 16 where pattern
+// rows hold more than 8 entries on average, else 4.
+static inline int rn_row_group(int64_t nnz, int n) { return (n > 0 && nnz > 8 * (int64_t)n) ? 16 : 4; }
+
 // index of (q, r), q <= r, in the packed upper triangle of an nB x nB matrix
 __host__ __device__ inline int rn_pk(int nB, int q, int r) {
   if (q > r) { const int t = q; q = r; r = t; }
@@ -18,6 +22,28 @@ __host__ __device__ inline int rn_pk(int nB, int q, int r) {
 }
 
 __device__ inline void rn_gram_pinv_eig(int nB, const double *G, double *Gp);
+
+// The entries of one pattern row in rounds of RN_ROW_CHUNK: the column
+// indices of a round are loaded together, then their Bc rows together, so a
+// pass over a short row costs two memory round trips, not two per entry;
+// f(p, b) sees the entries in row order (the sums keep that order).
+#define RN_ROW_CHUNK 8
+template <int NB, class F>
+__device__ inline void rn_row_each(const int32_t *__restrict__ J, int s, int e, const double *__restrict__ Bc, F &&f) {
+  for (int p0 = s; p0 < e; p0 += RN_ROW_CHUNK) {
+    int j[RN_ROW_CHUNK];
+#pragma unroll
+    for (int k = 0; k < RN_ROW_CHUNK; ++k) j[k] = p0 + k < e ? J[p0 + k] : 0;
+    double b[RN_ROW_CHUNK][NB];
+#pragma unroll
+    for (int k = 0; k < RN_ROW_CHUNK; ++k)
+#pragma unroll
+      for (int q = 0; q < NB; ++q) b[k][q] = p0 + k < e ? Bc[(int64_t)j[k] * NB + q] : 0.0;
+#pragma unroll
+    for (int k = 0; k < RN_ROW_CHUNK; ++k)
+      if (p0 + k < e) f(p0 + k, b[k]);
+  }
+}
 
 // Least-squares data of one pattern row: Gp = pinv(B_J^T B_J) where the rows
 // of B_J are Bc[J[p]], p in [s, e).  Formed by CholeskyQR2 over the row's
@@ -33,13 +59,12 @@ __device__ inline int rn_row_pinv(const int32_t *__restrict__ J, int s, int e, c
   double G[NB * NB];
 #pragma unroll
   for (int q = 0; q < NB * NB; ++q) G[q] = 0.0;
-  for (int p = s; p < e; ++p) {
-    const double *b = Bc + (int64_t)J[p] * NB;
+  rn_row_each<NB>(J, s, e, Bc, [&](int, const double *b) {
 #pragma unroll
     for (int q = 0; q < NB; ++q)
 #pragma unroll
       for (int r = 0; r < NB; ++r) G[q * NB + r] += b[q] * b[r];
-  }
+  });
   double dmax = 0.0;
 #pragma unroll
   for (int q = 0; q < NB; ++q) dmax = fmax(dmax, G[q * NB + q]);
@@ -50,7 +75,7 @@ __device__ inline int rn_row_pinv(const int32_t *__restrict__ J, int s, int e, c
   bool ok = dmax > 0.0 && (e - s) >= NB;
   for (int k = 0; k < NB && ok; ++k) {
     double d = G[k * NB + k];
-    for (int l = 0; l < k; ++l) d -= R1[l * NB + k] * R1[l * NB + k];
+    for (int t = 0; t < k; ++t) d -= R1[t * NB + k] * R1[t * NB + k];
     if (!(d > 1e-12 * dmax)) {
       ok = false;
       break;
@@ -59,7 +84,7 @@ __device__ inline int rn_row_pinv(const int32_t *__restrict__ J, int s, int e, c
     R1[k * NB + k] = rk;
     for (int j = k + 1; j < NB; ++j) {
       double v = G[k * NB + j];
-      for (int l = 0; l < k; ++l) v -= R1[l * NB + k] * R1[l * NB + j];
+      for (int t = 0; t < k; ++t) v -= R1[t * NB + k] * R1[t * NB + j];
       R1[k * NB + j] = v / rk;
     }
   }
@@ -71,27 +96,26 @@ __device__ inline int rn_row_pinv(const int32_t *__restrict__ J, int s, int e, c
   double G2[NB * NB];
 #pragma unroll
   for (int q = 0; q < NB * NB; ++q) G2[q] = 0.0;
-  for (int p = s; p < e; ++p) {
-    const double *b = Bc + (int64_t)J[p] * NB;
+  rn_row_each<NB>(J, s, e, Bc, [&](int, const double *b) {
     double qv[NB];
 #pragma unroll
     for (int k = 0; k < NB; ++k) {
       double v = b[k];
 #pragma unroll
-      for (int l = 0; l < k; ++l) v -= R1[l * NB + k] * qv[l];
+      for (int t = 0; t < k; ++t) v -= R1[t * NB + k] * qv[t];
       qv[k] = v / R1[k * NB + k];
     }
 #pragma unroll
     for (int q = 0; q < NB; ++q)
 #pragma unroll
       for (int r = 0; r < NB; ++r) G2[q * NB + r] += qv[q] * qv[r];
-  }
+  });
   double R2[NB * NB];
 #pragma unroll
   for (int q = 0; q < NB * NB; ++q) R2[q] = 0.0;
   for (int k = 0; k < NB; ++k) {
     double d = G2[k * NB + k];
-    for (int l = 0; l < k; ++l) d -= R2[l * NB + k] * R2[l * NB + k];
+    for (int t = 0; t < k; ++t) d -= R2[t * NB + k] * R2[t * NB + k];
     if (!(d > 0.0)) {
       rn_gram_pinv_eig(NB, G, Gp);
       return 1;
@@ -100,7 +124,7 @@ __device__ inline int rn_row_pinv(const int32_t *__restrict__ J, int s, int e, c
     R2[k * NB + k] = rk;
     for (int j = k + 1; j < NB; ++j) {
       double v = G2[k * NB + j];
-      for (int l = 0; l < k; ++l) v -= R2[l * NB + k] * R2[l * NB + j];
+      for (int t = 0; t < k; ++t) v -= R2[t * NB + k] * R2[t * NB + j];
       R2[k * NB + j] = v / rk;
     }
   }
@@ -111,7 +135,7 @@ __device__ inline int rn_row_pinv(const int32_t *__restrict__ J, int s, int e, c
 #pragma unroll
     for (int r = 0; r < NB; ++r) {
       double v = 0.0;
-      for (int l = q; l <= r; ++l) v += R2[q * NB + l] * R1[l * NB + r];
+      for (int t = q; t <= r; ++t) v += R2[q * NB + t] * R1[t * NB + r];
       R[q * NB + r] = r >= q ? v : 0.0;
       Ri[q * NB + r] = 0.0;
     }
@@ -119,7 +143,7 @@ __device__ inline int rn_row_pinv(const int32_t *__restrict__ J, int s, int e, c
     Ri[c * NB + c] = 1.0 / R[c * NB + c];
     for (int r = c - 1; r >= 0; --r) {
       double v = 0.0;
-      for (int l = r + 1; l <= c; ++l) v += R[r * NB + l] * Ri[l * NB + c];
+      for (int t = r + 1; t <= c; ++t) v += R[r * NB + t] * Ri[t * NB + c];
       Ri[r * NB + c] = -v / R[r * NB + r];
     }
   }
@@ -129,7 +153,7 @@ __device__ inline int rn_row_pinv(const int32_t *__restrict__ J, int s, int e, c
     for (int r = 0; r < NB; ++r) {
       double v = 0.0;
 #pragma unroll
-      for (int l = 0; l < NB; ++l) v += Ri[q * NB + l] * Ri[r * NB + l];
+      for (int t = 0; t < NB; ++t) v += Ri[q * NB + t] * Ri[r * NB + t];
       Gp[q * NB + r] = v;
     }
   return 0;
@@ -145,11 +169,16 @@ __device__ inline void rn_gram_pinv_eig(int nB, const double *G, double *Gp) {
       w[q][r] = G[q * nB + r];
       v[q][r] = (q == r) ? 1.0 : 0.0;
     }
-  for (int sweep = 0; sweep < 100; ++sweep) {
-    double off = 0.0;
-    for (int q = 0; q < nB; ++q)
+  // converged once the off-diagonal sum of squares is below 1e-36 of the
+  // diagonal's (rank-deficient G often never reaches an exact zero; rotations
+  // then only move round-off); at most 40 sweeps
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    double off = 0.0, dn = 0.0;
+    for (int q = 0; q < nB; ++q) {
+      dn += w[q][q] * w[q][q];
       for (int r = q + 1; r < nB; ++r) off += w[q][r] * w[q][r];
-    if (off == 0.0) break;
+    }
+    if (off <= 1e-36 * dn) break;
     for (int q = 0; q < nB; ++q)
       for (int r = q + 1; r < nB; ++r) {
         const double wqr = w[q][r];

@@ -148,6 +148,8 @@ __global__ __launch_bounds__(RN_BLOCK) void k_plan_count_m2(int nr, const int32_
   block_to_slot<true>(na, maxna);
 }
 
+// G^+ of every F row (zero for root rows), one thread per row; per-block
+// counts of rows that took the pseudo-inverse fallback
 template <int NB>
 __global__ __launch_bounds__(RN_BLOCK) void k_plan_gram(int n, const int32_t *__restrict__ Np,
                                                        const int32_t *__restrict__ Nj,
@@ -600,7 +602,8 @@ extern "C" rn_status rn_plan_create(rn_ctx *ctx, const rn_matrix *A, int32_t n_c
 
 rn_status rn_plan_create_ex(rn_ctx *ctx, const rn_matrix *A, int32_t n_cols, const int32_t *Np, const int32_t *Nj,
                             int64_t nnz_N, const uint8_t *is_root, const double *Bc, int32_t nB, rn_plan **out,
-                            int32_t *guard_in, const RnFetch *extra, unsigned char *extra_out, bool validate) {
+                            int32_t *guard_in, const RnFetch *extra, unsigned char *extra_out, bool validate,
+                            const double *gp_in) {
   if (!A || !out) return rn_fail(ctx, RN_EINVAL, "rn_plan_create: null argument");
   *out = nullptr;
   const int m = A->block_m;
@@ -651,19 +654,22 @@ rn_status rn_plan_create_ex(rn_ctx *ctx, const rn_matrix *A, int32_t n_cols, con
   if (!misc) return fail(st);
   if (nr == 0 && hipMemsetAsync(misc, 0, 64, ctx->stream) != hipSuccess)
     return fail(rn_fail(ctx, RN_EHIP, "memset"));
-  if (!plan_alloc(pl, &pl->gp, (size_t)(n + 1) * NP * sizeof(double)) || !plan_alloc(pl, &pl->d_terms, 16) ||
+  if (gp_in) {
+    pl->gp = (double *)gp_in;
+    pl->gp_ext = true;
+  }
+  if ((!gp_in && !plan_alloc(pl, &pl->gp, (size_t)(n + 1) * NP * sizeof(double))) || !plan_alloc(pl, &pl->d_terms, 16) ||
       !plan_alloc(pl, &pl->xoff, (size_t)(A->nnz + 1) * m * sizeof(int32_t)))
     return fail(rn_fail(ctx, RN_ENOMEM, "rn_plan_create: device allocation"));
   if (m == 2 && !plan_alloc(pl, &pl->nodeptr, (size_t)(nr + 1) * sizeof(int32_t)))
     return fail(rn_fail(ctx, RN_ENOMEM, "rn_plan_create: device allocation"));
-  pl->fixed_bytes = (size_t)(nr + 1) * 4 * (m == 2 ? 1 : 0) + (size_t)(n + 1) * NP * 8 +
+  pl->fixed_bytes = (size_t)(nr + 1) * 4 * (m == 2 ? 1 : 0) + (gp_in ? 0 : (size_t)(n + 1) * NP * 8) +
                     (size_t)(A->nnz + 1) * m * 4;
   // per-block partial results of the counting kernels
   const int nbn = (int)rn_div_up(n > 0 ? n : 1, RN_BLOCK);
   int32_t *blk_max = (int32_t *)rn_scratch(ctx, SLOT_BLK0, (size_t)(nbn + 1) * sizeof(int32_t), &st);
-  int32_t *blk_bad = (int32_t *)rn_scratch(ctx, SLOT_BLK1, (size_t)(nbn + 1) * sizeof(int32_t), &st);
   int32_t *blk_na = (int32_t *)rn_scratch(ctx, SLOT_PAT_CNT, (size_t)(nbn + 1) * sizeof(int32_t), &st);
-  if (!blk_max || !blk_bad || !blk_na) return fail(st);
+  if (!blk_max || !blk_na) return fail(st);
   if (nr > 0) {
     int nbc;
     if (m == 1) {
@@ -685,14 +691,20 @@ rn_status rn_plan_create_ex(rn_ctx *ctx, const rn_matrix *A, int32_t n_cols, con
     if (hipGetLastError() != hipSuccess) return fail(rn_fail(ctx, RN_EHIP, "launch"));
     hipLaunchKernelGGL((k_finish_slots<true, int32_t>), dim3(2), dim3(RN_BLOCK), 0, ctx->stream, blk_max, nbc, misc,
                        (const int32_t *)blk_na, misc + 2);
-    const dim3 g(nbn), bl(RN_BLOCK);
-    switch (nB) {
-      case 1: hipLaunchKernelGGL(k_plan_gram<1>, g, bl, 0, ctx->stream, n, Np, Nj, is_root, Bc, pl->gp, blk_bad, guard); break;
-      case 2: hipLaunchKernelGGL(k_plan_gram<2>, g, bl, 0, ctx->stream, n, Np, Nj, is_root, Bc, pl->gp, blk_bad, guard); break;
-      case 3: hipLaunchKernelGGL(k_plan_gram<3>, g, bl, 0, ctx->stream, n, Np, Nj, is_root, Bc, pl->gp, blk_bad, guard); break;
-      case 4: hipLaunchKernelGGL(k_plan_gram<4>, g, bl, 0, ctx->stream, n, Np, Nj, is_root, Bc, pl->gp, blk_bad, guard); break;
+    // the Gram data (or none: the caller's, and a zero count)
+    const int nbg = gp_in ? 0 : nbn;
+    int32_t *blk_bad = (int32_t *)rn_scratch(ctx, SLOT_BLK1, (size_t)(nbg + 1) * sizeof(int32_t), &st);
+    if (!blk_bad) return fail(st);
+    if (!gp_in) {
+      const dim3 g(nbg), bl(RN_BLOCK);
+      switch (nB) {
+        case 1: hipLaunchKernelGGL(k_plan_gram<1>, g, bl, 0, ctx->stream, n, Np, Nj, is_root, Bc, pl->gp, blk_bad, guard); break;
+        case 2: hipLaunchKernelGGL(k_plan_gram<2>, g, bl, 0, ctx->stream, n, Np, Nj, is_root, Bc, pl->gp, blk_bad, guard); break;
+        case 3: hipLaunchKernelGGL(k_plan_gram<3>, g, bl, 0, ctx->stream, n, Np, Nj, is_root, Bc, pl->gp, blk_bad, guard); break;
+        case 4: hipLaunchKernelGGL(k_plan_gram<4>, g, bl, 0, ctx->stream, n, Np, Nj, is_root, Bc, pl->gp, blk_bad, guard); break;
+      }
     }
-    hipLaunchKernelGGL((k_finish_slots<false, int32_t>), dim3(1), dim3(RN_BLOCK), 0, ctx->stream, blk_bad, nbn,
+    hipLaunchKernelGGL((k_finish_slots<false, int32_t>), dim3(1), dim3(RN_BLOCK), 0, ctx->stream, blk_bad, nbg,
                        misc + 1);
     if (hipGetLastError() != hipSuccess) return fail(rn_fail(ctx, RN_EHIP, "launch"));
   }
@@ -824,6 +836,7 @@ rn_status rn_plan_create_ex(rn_ctx *ctx, const rn_matrix *A, int32_t n_cols, con
 // wait); the plan keeps only its host object.
 void rn_plan_release(rn_plan *pl) {
   if (!pl->ctx) return;
+  if (pl->gp_ext) pl->gp = nullptr;
   void **bufs[] = {(void **)&pl->codes,   (void **)&pl->ncol,    (void **)&pl->nodeptr, (void **)&pl->gp,
                    (void **)&pl->d_terms, (void **)&pl->blk_row, (void **)&pl->blk_hdr, (void **)&pl->xoff,
                    (void **)&pl->xl,      (void **)&pl->xwin,    (void **)&pl->bce,     (void **)&pl->ccodes};

@@ -106,9 +106,14 @@ extern "C" rn_status rn_setup(rn_ctx *ctx, const rn_matrix *A, const int32_t *ag
   // stage and N was made here, so neither stage validates again
   int32_t *guard = rn_guard_begin(ctx, &st);
   if (!guard) return fail(st);
+  // with candidates beyond the first m, Eq. Tproj forms every F row's G^+;
+  // the plan's projection takes that array instead of forming it again
+  const int NP = nB * (nB + 1) / 2;
+  double *gp = nB > m ? (double *)setup_alloc(s, (size_t)(n + 1) * NP * 8) : nullptr;
+  if (nB > m && !gp) return nomem();
   const int32_t *tflags = nullptr;
   if ((st = rn_tentative_launch(ctx, n, m, Np, Nj, nnzN, is_root, agg, roots, n_agg, B, nB, T, Bc, guard,
-                                &tflags, false)) != RN_OK)
+                                &tflags, false, gp)) != RN_OK)
     return fail(st);
   v.T = T;
   v.Bc = Bc;
@@ -116,9 +121,10 @@ extern "C" rn_status rn_setup(rn_ctx *ctx, const rn_matrix *A, const int32_t *ag
   int32_t hf[2] = {0, 0};
   const RnFetch fl = {tflags, sizeof hf};
   if ((st = rn_plan_create_ex(ctx, A, nc, Np, Nj, nnzN, is_root, Bc, nB, &s->plan, guard, &fl,
-                              (unsigned char *)hf, false)) != RN_OK)
+                              (unsigned char *)hf, false, gp)) != RN_OK)
     return fail(st);
   if ((st = rn_tentative_flags(ctx, hf, &v.rank_deficient)) != RN_OK) return fail(st);
+  if (gp) s->plan->rank_def = v.rank_deficient;  // the same rows, counted by Eq. Tproj
   if ((st = rn_energy_min(ctx, s->plan, A->vals, 1, T, method, iters, precision, P, nullptr, stats, nullptr)) !=
       RN_OK)
     return fail(st);
@@ -140,14 +146,18 @@ extern "C" rn_status rn_setup(rn_ctx *ctx, const rn_matrix *A, const int32_t *ag
     const rn_matrix AT = {n, 1, A->nnz, s->AT_rowptr, s->AT_colind, s->AT_vals};
     int32_t *g2 = rn_guard_begin(ctx, &st);
     if (!g2) return fail(st);
+    double *gph = nB > m ? (double *)setup_alloc(s, (size_t)(n + 1) * NP * 8) : nullptr;
+    if (nB > m && !gph) return nomem();
     if ((st = rn_tentative_launch(ctx, n, m, Np, Nj, nnzN, is_root, agg, roots, n_agg, Bhat, nB, That, Bch, g2,
-                                  &tflags, false)) != RN_OK)
+                                  &tflags, false, gph)) != RN_OK)
       return fail(st);
     const RnFetch fl2 = {tflags, sizeof hf};
     if ((st = rn_plan_create_ex(ctx, &AT, nc, Np, Nj, nnzN, is_root, Bch, nB, &s->plan_T, g2, &fl2,
-                                (unsigned char *)hf, false)) != RN_OK)
+                                (unsigned char *)hf, false, gph)) != RN_OK)
       return fail(st);
-    if ((st = rn_tentative_flags(ctx, hf, nullptr)) != RN_OK) return fail(st);
+    int32_t rd_hat = 0;
+    if ((st = rn_tentative_flags(ctx, hf, &rd_hat)) != RN_OK) return fail(st);
+    if (gph) s->plan_T->rank_def = rd_hat;
     if ((st = rn_energy_min(ctx, s->plan_T, s->AT_vals, 1, That, method, iters, precision, RT, nullptr, stats_RT,
                             nullptr)) != RN_OK)
       return fail(st);

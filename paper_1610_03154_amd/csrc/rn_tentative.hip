@@ -38,17 +38,20 @@ __global__ __launch_bounds__(RN_BLOCK) void k_inject_root(int n_agg, int m, int 
 
 // T on the pattern: root rows = identity row; F row i of aggregate a holds
 // B[i, 0:m] inv(root block) at columns m*a .. m*a+m-1, zero elsewhere.
+// W lanes per row (entries s + l, s + l + W, ...).
+template <int W>
 __global__ __launch_bounds__(RN_BLOCK) void k_tent_T(int n, int m, int nB, const int32_t *__restrict__ Np,
                                                     const int32_t *__restrict__ Nj,
                                                     const uint8_t *__restrict__ is_root,
                                                     const int32_t *__restrict__ agg, const double *__restrict__ B,
                                                     const double *__restrict__ binv, double *__restrict__ T,
                                                     const int32_t *__restrict__ guard) {
-  const int i = blockIdx.x * RN_BLOCK + threadIdx.x;
+  const int64_t gid = (int64_t)blockIdx.x * RN_BLOCK + threadIdx.x;
+  const int i = (int)(gid / W), l = (int)(gid % W);
   if (i >= n || *guard) return;
   const int a = agg[i / m], c = i % m;
   const bool root = is_root[i];
-  for (int p = Np[i]; p < Np[i + 1]; ++p) {
+  for (int p = Np[i] + l; p < Np[i + 1]; p += W) {
     const int j = Nj[p];
     double t = 0.0;
     if (root) {
@@ -61,30 +64,44 @@ __global__ __launch_bounds__(RN_BLOCK) void k_tent_T(int n, int m, int nB, const
   }
 }
 
-// Eq. Tproj on F rows: t <- t + (B_i - t B_J) G^+ B_J^T, G = B_J^T B_J
+// Eq. Tproj on F rows: t <- t + (B_i - t B_J) G^+ B_J^T, G = B_J^T B_J, one
+// thread per row; gp (nullable) receives each row's G^+ packed as the plan
+// keeps it (upper triangle, root rows zero).
 template <int NB>
 __global__ __launch_bounds__(RN_BLOCK) void k_tproj(int n, const int32_t *__restrict__ Np,
                                                    const int32_t *__restrict__ Nj,
                                                    const uint8_t *__restrict__ is_root,
                                                    const double *__restrict__ B, const double *__restrict__ Bc,
-                                                   double *__restrict__ T, int32_t *__restrict__ rank_def,
+                                                   double *__restrict__ T, double *__restrict__ gp,
+                                                   int32_t *__restrict__ rank_def,
                                                    const int32_t *__restrict__ guard) {
+  constexpr int NP = NB * (NB + 1) / 2;
   const int i = blockIdx.x * RN_BLOCK + threadIdx.x;
-  if (i >= n || *guard || is_root[i]) return;
+  if (i >= n || *guard) return;
+  if (is_root[i]) {
+    if (gp)
+#pragma unroll
+      for (int k = 0; k < NP; ++k) gp[(int64_t)i * NP + k] = 0.0;
+    return;
+  }
   double Gp[NB * NB], rr[NB], y[NB], ts[NB];
   const int s = Np[i], e = Np[i + 1];
   // r = B_i - t B_J
 #pragma unroll
   for (int q = 0; q < NB; ++q) ts[q] = 0.0;
-  for (int p = s; p < e; ++p) {
-    const double *b = Bc + (int64_t)Nj[p] * NB;
+  rn_row_each<NB>(Nj, s, e, Bc, [&](int p, const double *b) {
     const double t = T[p];
 #pragma unroll
     for (int q = 0; q < NB; ++q) ts[q] += t * b[q];
-  }
+  });
 #pragma unroll
   for (int q = 0; q < NB; ++q) rr[q] = B[(int64_t)i * NB + q] - ts[q];
   if (rn_row_pinv<NB>(Nj, s, e, Bc, Gp)) atomicAdd(rank_def, 1);
+  if (gp)
+#pragma unroll
+    for (int q = 0; q < NB; ++q)
+#pragma unroll
+      for (int r = q; r < NB; ++r) gp[(int64_t)i * NP + rn_pk(NB, q, r)] = Gp[q * NB + r];
 #pragma unroll
   for (int q = 0; q < NB; ++q) {
     double v = 0.0;
@@ -92,12 +109,24 @@ __global__ __launch_bounds__(RN_BLOCK) void k_tproj(int n, const int32_t *__rest
     for (int r = 0; r < NB; ++r) v += Gp[q * NB + r] * rr[r];
     y[q] = v;
   }
-  for (int p = s; p < e; ++p) {
-    const double *b = Bc + (int64_t)Nj[p] * NB;
+  rn_row_each<NB>(Nj, s, e, Bc, [&](int p, const double *b) {
     double u = 0.0;
 #pragma unroll
     for (int q = 0; q < NB; ++q) u += b[q] * y[q];
     T[p] += u;
+  });
+}
+
+// Eq. Tproj on every F row (nB = 1..4)
+static void launch_tproj(hipStream_t st, int n, int nB, const int32_t *Np, const int32_t *Nj, const uint8_t *is_root,
+                         const double *B, const double *Bc, double *T, double *gp, int32_t *rank_def,
+                         const int32_t *guard) {
+  const dim3 g(rn_div_up(n, RN_BLOCK)), b(RN_BLOCK);
+  switch (nB) {
+    case 1: hipLaunchKernelGGL(k_tproj<1>, g, b, 0, st, n, Np, Nj, is_root, B, Bc, T, gp, rank_def, guard); break;
+    case 2: hipLaunchKernelGGL(k_tproj<2>, g, b, 0, st, n, Np, Nj, is_root, B, Bc, T, gp, rank_def, guard); break;
+    case 3: hipLaunchKernelGGL(k_tproj<3>, g, b, 0, st, n, Np, Nj, is_root, B, Bc, T, gp, rank_def, guard); break;
+    case 4: hipLaunchKernelGGL(k_tproj<4>, g, b, 0, st, n, Np, Nj, is_root, B, Bc, T, gp, rank_def, guard); break;
   }
 }
 
@@ -109,7 +138,7 @@ __global__ __launch_bounds__(RN_BLOCK) void k_tproj(int n, const int32_t *__rest
 rn_status rn_tentative_launch(rn_ctx *ctx, int32_t n, int32_t m, const int32_t *Np, const int32_t *Nj,
                               int64_t nnz_N, const uint8_t *is_root, const int32_t *agg, const int32_t *roots,
                               int32_t n_agg, const double *B, int32_t nB, double *T, double *Bc, int32_t *guard,
-                              const int32_t **flags_out, bool validate) {
+                              const int32_t **flags_out, bool validate, double *gp_out) {
   if ((m != 1 && m != 2) || n < 0 || n % m || n_agg < 0 || nnz_N < 0 || nB < m || nB > RN_NBMAX)
     return rn_fail(ctx, RN_EINVAL, "rn_tentative: bad sizes (n %d, m %d, n_agg %d, nB %d; need m <= nB <= %d)", n,
                    m, n_agg, nB, RN_NBMAX);
@@ -136,16 +165,15 @@ rn_status rn_tentative_launch(rn_ctx *ctx, int32_t n, int32_t m, const int32_t *
     LAUNCH_CHECK(ctx);
   }
   if (n > 0) {
-    hipLaunchKernelGGL(k_tent_T, dim3(rn_div_up(n, RN_BLOCK)), dim3(RN_BLOCK), 0, ctx->stream, n, m, nB, Np, Nj,
-                       is_root, agg, B, binv, T, guard);
+    if (rn_row_group(nnz_N, n) == 16)
+      hipLaunchKernelGGL(k_tent_T<16>, dim3(rn_div_up((int64_t)n * 16, RN_BLOCK)), dim3(RN_BLOCK), 0, ctx->stream, n,
+                         m, nB, Np, Nj, is_root, agg, B, binv, T, guard);
+    else
+      hipLaunchKernelGGL(k_tent_T<4>, dim3(rn_div_up((int64_t)n * 4, RN_BLOCK)), dim3(RN_BLOCK), 0, ctx->stream, n,
+                         m, nB, Np, Nj, is_root, agg, B, binv, T, guard);
     LAUNCH_CHECK(ctx);
     if (nB > m) {
-      const dim3 g(rn_div_up(n, RN_BLOCK)), b(RN_BLOCK);
-      switch (nB) {
-        case 2: hipLaunchKernelGGL(k_tproj<2>, g, b, 0, ctx->stream, n, Np, Nj, is_root, B, Bc, T, flags + 1, guard); break;
-        case 3: hipLaunchKernelGGL(k_tproj<3>, g, b, 0, ctx->stream, n, Np, Nj, is_root, B, Bc, T, flags + 1, guard); break;
-        case 4: hipLaunchKernelGGL(k_tproj<4>, g, b, 0, ctx->stream, n, Np, Nj, is_root, B, Bc, T, flags + 1, guard); break;
-      }
+      launch_tproj(ctx->stream, n, nB, Np, Nj, is_root, B, Bc, T, gp_out, flags + 1, guard);
       LAUNCH_CHECK(ctx);
     }
   }
@@ -171,7 +199,7 @@ extern "C" rn_status rn_tentative(rn_ctx *ctx, int32_t n, int32_t m, const int32
   if (!guard) return st;
   const int32_t *flags = nullptr;
   RN_TRY(rn_tentative_launch(ctx, n, m, Np, Nj, nnz_N, is_root, agg, roots, n_agg, B, nB, T, Bc, guard, &flags,
-                             true));
+                             true, nullptr));
   // one synchronisation: guard and the two flags
   const RnFetch it[2] = {{guard, 4}, {flags, 2 * sizeof(int32_t)}};
   const unsigned char *hb = nullptr;
@@ -205,13 +233,7 @@ extern "C" rn_status rn_enforce(rn_ctx *ctx, int32_t n, int32_t n_cols, const in
   v.ncsr = 1;
   RN_TRY(rn_validate(ctx, v, guard));
   if (n > 0) {
-    const dim3 g(rn_div_up(n, RN_BLOCK)), b(RN_BLOCK);
-    switch (nB) {
-      case 1: hipLaunchKernelGGL(k_tproj<1>, g, b, 0, ctx->stream, n, N_rowptr, N_colind, is_root, B, Bc, vals, flags + 1, guard); break;
-      case 2: hipLaunchKernelGGL(k_tproj<2>, g, b, 0, ctx->stream, n, N_rowptr, N_colind, is_root, B, Bc, vals, flags + 1, guard); break;
-      case 3: hipLaunchKernelGGL(k_tproj<3>, g, b, 0, ctx->stream, n, N_rowptr, N_colind, is_root, B, Bc, vals, flags + 1, guard); break;
-      case 4: hipLaunchKernelGGL(k_tproj<4>, g, b, 0, ctx->stream, n, N_rowptr, N_colind, is_root, B, Bc, vals, flags + 1, guard); break;
-    }
+    launch_tproj(ctx->stream, n, nB, N_rowptr, N_colind, is_root, B, Bc, vals, nullptr, flags + 1, guard);
     LAUNCH_CHECK(ctx);
   }
   const RnFetch it[2] = {{guard, 4}, {flags, 2 * sizeof(int32_t)}};
