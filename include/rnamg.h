@@ -165,7 +165,13 @@ typedef enum {
    * while the next product stages its X window (two launches per step, two D
    * buffers); 0: a separate direction pass (three launches per step).  The
    * two give the same result bit for bit. */
-  RN_OPT_FUSED_CG = 5
+  RN_OPT_FUSED_CG = 5,
+  /* 0 (default): tapes made by rn_tape_create keep the CG iterates R_k, D_k
+   * at every c-th step, c = ceil(sqrt(iters)); c >= 1: that interval.  The
+   * reverse sweep recomputes the steps between checkpoints from the tape's
+   * step lengths (the gradient is the same bit for bit for every c; c = 1
+   * stores every step).  Read when a tape is made. */
+  RN_OPT_TAPE_INTERVAL = 6
 } rn_option;
 rn_status rn_set_option(rn_ctx *ctx, rn_option opt, int32_t value);
 /* Message of the last failure on ctx ("" if none).  Valid until the next
@@ -444,8 +450,12 @@ rn_status rn_constraint_residual(rn_ctx *ctx, int32_t n, int32_t n_cols,
 
 /* ---- a12: adjoint of the CG energy minimisation (map A values -> P) -----
  * Tape for `batch` problems of `iters` CG steps on `plan`; holds the Krylov
- * scalars and the iterates R_k, D_k of every step (checkpoint interval 1;
- * Z_k = Pi(A D_k) is recomputed in the reverse sweep). */
+ * scalars and the iterates R_k, D_k at the checkpoints k = 0, c, 2c, ... < iters
+ * (c from RN_OPT_TAPE_INTERVAL).  The reverse sweep recomputes, from the
+ * checkpoint at or before each step k, the products Z_j = Pi(A D_j) and the
+ * recurrences up to D_k, Z_k and R_{k+1}: c(c-1)/2 extra products per
+ * checkpoint segment, ceil(iters/c) + 4 iterate vectors instead of
+ * iters + 1 pairs. */
 rn_status rn_tape_create(rn_ctx *ctx, rn_plan *plan, int32_t batch,
                          int32_t iters, rn_tape **tape);
 void rn_tape_destroy(rn_tape *tape);

@@ -15,7 +15,7 @@ RN_OK, RN_EINVAL, RN_ENOMEM, RN_ESINGULAR, RN_EBREAKDOWN, RN_ENONFINITE, RN_EHIP
 RN_CG, RN_GMRES, RN_PCG_JACOBI, RN_CGNR = 0, 1, 2, 3
 RN_FP64, RN_FP32_MIXED = 0, 1
 RN_OPT_PERSISTENT_PRODUCT, RN_OPT_PADDED_PATTERN, RN_OPT_FUSED_SETUP, RN_OPT_PRODUCT_LANES, RN_OPT_METRICS, \
-    RN_OPT_FUSED_CG = range(6)
+    RN_OPT_FUSED_CG, RN_OPT_TAPE_INTERVAL = range(7)
 # rn_set_allocator callbacks: void *alloc(size_t bytes, void *user); void release(void *ptr, void *user)
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
 RELEASE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)

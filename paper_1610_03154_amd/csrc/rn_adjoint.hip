@@ -23,8 +23,12 @@
 // Pi is an orthogonal projector row by row, so Q^T(Y) = M(A^T Pi(Y)) (the
 // masked product on a plan of A^T, same pattern, no output projection), and
 // d<Y, Q(X)>/dA_ik = sum over the pattern of row i of Pi(Y)_ij X_kj, which
-// the product's position codes give directly.  Z_k is recomputed from the
-// recorded D_k (the tape keeps R_k and D_k of every step).
+// the product's position codes give directly.  The tape keeps R_k and D_k at
+// the checkpoint steps k = 0, c, 2c, ... only; reverse step k recomputes
+// from the checkpoint k0 <= k, with the recorded alpha_j and beta_j, Z_j =
+// Q(D_j), R_{j+1} = R_j - alpha_j Z_j and D_{j+1} = R_{j+1} + beta_j D_j for
+// j = k0..k (the forward's own expressions, so the same bits), which yields
+// D_k, Z_k and R_{k+1}.
 #include <cstring>
 #include <new>
 #include <type_traits>
@@ -35,8 +39,10 @@ struct rn_tape {
   rn_ctx *ctx = nullptr;  // owner of the device memory (NULL once released)
   const rn_plan *pl = nullptr;
   int32_t batch = 0, K = 0, scal_stride = 0;
+  int32_t c = 1, ncp = 0;             // checkpoint interval and count (steps 0, c, ... < K)
   int64_t nz = 0, nzb = 0;
-  double *R = nullptr, *D = nullptr;  // [K+1][batch][nz]
+  double *R = nullptr, *D = nullptr;  // [ncp][batch][nz]
+  double *W = nullptr;                // [4][batch][nz]: recomputed R and D, two of each
   double *T = nullptr;                // [nz]
   double *scal = nullptr;             // [batch][scal_stride], the forward CG scalars
   int32_t *st = nullptr;              // [batch][ST_STRIDE]
@@ -60,7 +66,7 @@ static unsigned adj_grid(int64_t n) {
 // queued on the context's stream that still reads it runs first).
 void rn_tape_release(rn_tape *t) {
   if (!t->ctx) return;
-  void **bufs[] = {(void **)&t->R,  (void **)&t->D,  (void **)&t->T,  (void **)&t->scal, (void **)&t->st,
+  void **bufs[] = {(void **)&t->R,  (void **)&t->D,  (void **)&t->W,  (void **)&t->T,  (void **)&t->scal, (void **)&t->st,
                    (void **)&t->Rb, (void **)&t->Db, (void **)&t->Zk, (void **)&t->Yb,   (void **)&t->Yh,
                    (void **)&t->gbar, (void **)&t->part, (void **)&t->ATv};
   for (void **b : bufs) {
@@ -109,13 +115,19 @@ extern "C" rn_status rn_tape_create(rn_ctx *ctx, rn_plan *pl, int32_t batch, int
   t->nzb = (int64_t)batch * pl->nnzN;
   t->nnzA = pl->nnzA;
   t->scal_stride = CgLayout(iters).total;
+  int c = ctx->opt[RN_OPT_TAPE_INTERVAL];
+  if (c <= 0)
+    for (c = 1; c * c < iters; ++c) {
+    }
+  t->c = c;
+  t->ncp = iters > 0 ? (iters + c - 1) / c : 1;
   const size_t v = (size_t)(t->nzb + 1) * 8;
-  const size_t slots = (size_t)(iters + 1) * v;
+  const size_t slots = (size_t)t->ncp * v;
   auto get = [&](auto **p, size_t bytes) {
     *p = (std::remove_reference_t<decltype(**p)> *)rn_dev_alloc(ctx, bytes);
     return *p != nullptr;
   };
-  bool ok = get(&t->R, slots) && get(&t->D, slots) && get(&t->T, (size_t)(t->nz + 1) * 8) &&
+  bool ok = get(&t->R, slots) && get(&t->D, slots) && get(&t->W, 4 * v) && get(&t->T, (size_t)(t->nz + 1) * 8) &&
             get(&t->scal, (size_t)batch * t->scal_stride * 8) && get(&t->st, (size_t)batch * ST_STRIDE * 4) &&
             get(&t->Rb, v) && get(&t->Db, v) && get(&t->Zk, v) && get(&t->Yb, v) && get(&t->Yh, v) &&
             get(&t->gbar, (size_t)batch * (iters + 1) * 8) &&
@@ -141,8 +153,12 @@ rn_status rn_tape_record_begin(rn_ctx *ctx, rn_plan *pl, rn_tape *tape, int32_t 
   return RN_OK;
 }
 
-double *rn_tape_R(rn_tape *tape, int k) { return tape->R + (int64_t)k * tape->nzb; }
-double *rn_tape_D(rn_tape *tape, int k) { return tape->D + (int64_t)k * tape->nzb; }
+double *rn_tape_R(rn_tape *tape, int k) {
+  return (k % tape->c == 0 && (k < tape->K || k == 0)) ? tape->R + (int64_t)(k / tape->c) * tape->nzb : nullptr;
+}
+double *rn_tape_D(rn_tape *tape, int k) {
+  return (k % tape->c == 0 && (k < tape->K || k == 0)) ? tape->D + (int64_t)(k / tape->c) * tape->nzb : nullptr;
+}
 
 rn_status rn_tape_record_end(rn_ctx *ctx, rn_tape *tape, const double *scal, const int32_t *st, int32_t batch) {
   HIP_TRY(ctx, hipMemcpyAsync(tape->scal, scal, (size_t)batch * tape->scal_stride * 8, hipMemcpyDeviceToDevice,
@@ -240,6 +256,27 @@ __global__ __launch_bounds__(RN_BLOCK) void k_adj_init(int64_t nz, int K, const 
   const double c = 2.0 * gbar[(int64_t)b * (K + 1)];
   for (int64_t e = (int64_t)blockIdx.x * RN_BLOCK + threadIdx.x; e < nz; e += (int64_t)gridDim.x * RN_BLOCK)
     Yb[off + e] = -(Rb[off + e] + Db[off + e] + c * R0[off + e]);
+}
+
+// One forward step of the recomputation from a checkpoint: R_{j+1} = R_j -
+// alpha_j Z_j and (unless this is the last step needed) D_{j+1} = R_{j+1} +
+// beta_j D_j, with the recorded scalars and the forward kernels' expressions
+__global__ __launch_bounds__(RN_BLOCK) void k_adj_refwd(int64_t nz, int K, int j, int last,
+                                                       const double *__restrict__ Rj, const double *__restrict__ Dj,
+                                                       const double *__restrict__ Zj, double *__restrict__ Rn,
+                                                       double *__restrict__ Dn, const double *__restrict__ tscal,
+                                                       int scal_stride, const int32_t *__restrict__ tst) {
+  const int b = blockIdx.y;
+  if (!adj_active(tst, b, j)) return;
+  const CgLayout L(K);
+  const double *sc = tscal + (int64_t)b * scal_stride;
+  const double al = sc[L.alp + j], be = sc[L.bet + j];
+  const int64_t off = (int64_t)b * nz;
+  for (int64_t e = (int64_t)blockIdx.x * RN_BLOCK + threadIdx.x; e < nz; e += (int64_t)gridDim.x * RN_BLOCK) {
+    const double rr = Rj[off + e] - al * Zj[off + e];
+    Rn[off + e] = rr;
+    if (!last) Dn[off + e] = rr + be * Dj[off + e];
+  }
 }
 
 // Yh = Pi(Yb): one thread per DOF row, the same arithmetic as the product's
@@ -584,17 +621,36 @@ extern "C" rn_status rn_energy_min_bwd(rn_ctx *ctx, rn_plan *pl, rn_plan *plT, c
                        pl->nnzA, t->ATv);
     LAUNCH_CHECK(ctx);
   }
+  double *Wv[4];
+  for (int i = 0; i < 4; ++i) Wv[i] = t->W + (int64_t)i * t->nzb;
   for (int k = kmax - 1; k >= 0; --k) {
-    const double *Dk = rn_tape_D(t, k), *R1 = rn_tape_R(t, k + 1);
-    // Z_k = Q(D_k), recomputed
-    SpgParams q = rn_spg_params(pl);
-    q.Ax = A_vals;
-    q.X = Dk;
-    q.Z = t->Zk;
-    q.project = 1;
-    q.st = t->st;
-    q.kact = k;
-    RN_TRY(rn_launch_spgemm(ctx, pl, MODE_PRODUCT, q, B, false));
+    // D_k, Z_k = Q(D_k) and R_{k+1} from the checkpoint k0 <= k (a batch
+    // entry that stopped before step j skips it, as in every kernel below)
+    const int k0 = (k / t->c) * t->c;
+    const double *Dj = rn_tape_D(t, k0), *Rj = rn_tape_R(t, k0);
+    const double *Dk = nullptr, *R1 = nullptr;
+    for (int j = k0; j <= k; ++j) {
+      SpgParams q = rn_spg_params(pl);
+      q.Ax = A_vals;
+      q.X = Dj;
+      q.Z = t->Zk;
+      q.project = 1;
+      q.st = t->st;
+      q.kact = j;
+      RN_TRY(rn_launch_spgemm(ctx, pl, MODE_PRODUCT, q, B, false));
+      // next iterates into the work vectors not holding R_j, D_j
+      double *Rn = Wv[2 * ((j - k0) & 1)], *Dn = Wv[2 * ((j - k0) & 1) + 1];
+      hipLaunchKernelGGL(k_adj_refwd, g2, bl, 0, ctx->stream, nz, K, j, j == k ? 1 : 0, Rj, Dj, t->Zk, Rn, Dn,
+                         t->scal, t->scal_stride, t->st);
+      LAUNCH_CHECK(ctx);
+      if (j == k) {
+        Dk = Dj;
+        R1 = Rn;
+      } else {
+        Rj = Rn;
+        Dj = Dn;
+      }
+    }
     hipLaunchKernelGGL(k_adj_dots, g2, bl, 0, ctx->stream, nz, k, t->Db, P_bar, t->Rb, t->Zk, R1, Dk, t->part, t->st);
     LAUNCH_CHECK(ctx);
     hipLaunchKernelGGL(k_adj_update, g2, bl, 0, ctx->stream, nz, K, k, (int)ge, t->part, t->scal, t->scal_stride,

@@ -532,6 +532,9 @@ extern "C" rn_status rn_set_option(rn_ctx *ctx, rn_option opt, int32_t value) {
       if (value != 64 && value != 128 && value != 256)
         return rn_fail(ctx, RN_EINVAL, "rn_set_option: product lanes must be 64, 128 or 256");
       break;
+    case RN_OPT_TAPE_INTERVAL:
+      if (value < 0) return rn_fail(ctx, RN_EINVAL, "rn_set_option: the tape interval must be >= 0");
+      break;
     default:
       return rn_fail(ctx, RN_EINVAL, "rn_set_option: unknown option %d", (int)opt);
   }

@@ -191,8 +191,9 @@ rn_status rn_tentative_flags(rn_ctx *ctx, const int32_t hf[2], int32_t *rank_def
 // tape hooks called by rn_energy_min (CG, FP64) -- implemented with the adjoint
 rn_status rn_tape_record_begin(rn_ctx *ctx, rn_plan *pl, rn_tape *tape, int32_t batch, int32_t iters,
                                rn_method method, rn_precision prec, const double *T);
-// the tape's slot k of R (k = 0..K) and of D (k = 0..K), each [batch][nnzN]:
-// the CG kernels write R_k and D_k there as they produce them
+// the tape's checkpoint slot of R_k and of D_k, each [batch][nnzN], when k
+// is a checkpoint step (a multiple of the tape's interval below K), else
+// NULL: the CG kernels write R_k and D_k there as they produce them
 double *rn_tape_R(rn_tape *tape, int k);
 double *rn_tape_D(rn_tape *tape, int k);
 // after the last step: the per-batch scalars and status

@@ -84,13 +84,13 @@ struct XRows {
 };
 
 // Context options (rn_set_option), indexed by rn_option.
-#define RN_OPT_COUNT 6
+#define RN_OPT_COUNT 7
 
 struct rn_ctx {
   hipStream_t stream = nullptr;
   int device = 0;
   std::string err;
-  int32_t opt[RN_OPT_COUNT] = {1, 1, 1, RN_BLOCK, 0, 1};
+  int32_t opt[RN_OPT_COUNT] = {1, 1, 1, RN_BLOCK, 0, 1, 0};
   // device allocator of the caller (rn_set_allocator); NULL: hipMalloc/hipFree
   void *(*alloc_fn)(size_t, void *) = nullptr;
   void (*free_fn)(void *, void *) = nullptr;

@@ -188,3 +188,50 @@ def test_bwd_rejects_unrecorded_tape(R, ctx):
         ctx.energy_min(op.plan, dev(vals[0]), op.T, R.RN_GMRES, K, R.RN_FP64, tape=tape)
     tape.close()
     op.close()
+
+
+@pytest.mark.parametrize("case", ["batch", "early_stop"])
+def test_checkpoint_interval_gives_the_same_gradient(R, case):
+    """RN_OPT_TAPE_INTERVAL: the reverse sweep recomputes the steps between
+    checkpoints with the recorded step lengths and the forward's own
+    expressions, so every interval (1 = every step kept, 0 = ceil(sqrt(K)),
+    up to one checkpoint for the whole run) gives the same gradient bit for
+    bit, and the default matches the oracle's tangent model."""
+    if case == "batch":
+        A0, vals, st, Wt = problem(64, 3)
+        Kc = K
+    else:
+        A0 = W.laplace1d(8)
+        st = O.setup(A0, W.ones(A0.n_rows), 1, 0.25, 1)
+        vals = A0.vals[None, :].copy()
+        Wt = np.random.default_rng(3).standard_normal((1, st["Nj"].size))
+        Kc = 12  # converges before K
+    grads = {}
+    for c in (1, 0, 2, 4, Kc, Kc + 3):
+        cx = R.Context()
+        cx.set_option(R._lib.RN_OPT_TAPE_INTERVAL, c)
+        dA = R.DeviceCSR.from_host(A0.rowptr, A0.colind, A0.vals)
+        op = R.EnergyMinOperator(cx, dA, int(st["nc"]), dev(st["Np"]), dev(st["Nj"]), dev(st["is_root"]),
+                                 dev(st["T"]), dev(st["Bc"]), Kc)
+        P, g = gpu_grad(R, cx, op, vals if vals.shape[0] > 1 else vals[0], Wt if Wt.shape[0] > 1 else Wt[0])
+        grads[c] = (P, g)
+        op.close()
+        cx.close()
+    P1, g1 = grads[1]
+    for c, (P, g) in grads.items():
+        assert np.array_equal(P, P1) and np.array_equal(g, g1), f"interval {c}: max |dg| {np.max(np.abs(g - g1))}"
+    g = g1.reshape(len(Wt), -1)
+    rng = np.random.default_rng(5)
+    for b in range(len(Wt)):
+        v = rng.standard_normal(A0.nnz)
+        _, dP = O.emin_cg_jvp(A0.rowptr, A0.colind, vals[b], v, st["Np"], st["Nj"], st["is_root"], st["nc"],
+                              st["Bc"], 1, st["T"], Kc)
+        rhs = float(Wt[b] @ dP)
+        assert abs(float(g[b] @ v) - rhs) <= JVP_TOL * max(1.0, abs(rhs))
+
+
+def test_tape_interval_option_values(R):
+    cx = R.Context()
+    with pytest.raises(R.RnError):
+        cx.set_option(R._lib.RN_OPT_TAPE_INTERVAL, -1)
+    cx.close()
