@@ -593,7 +593,9 @@ def main():
         out["fp32_mixed_max_rel_dP_vs_oracle"] = _rel(p32, Pref)
         Np, Nj = aux[0].cpu().numpy(), aux[1].cpu().numpy()
         Bc = aux[4].cpu().numpy()
-        out["fp32_mixed_constraint_residual"] = O.constraint_residual(Np, Nj, p32, Bc, np.ones((Np.size - 1, 1)))
+        ones = np.ones((Np.size - 1, 1))
+        out["fp64_constraint_residual"] = O.constraint_residual(Np, Nj, p64, Bc, ones)
+        out["fp32_mixed_constraint_residual"] = O.constraint_residual(Np, Nj, p32, Bc, ones)
         med, cnt, nt, t1 = cpu_baseline()
         out["cpu_baseline"] = {"value": med, "unit": "s", "cores": nt, "kind": "oracle",
                                "value_1_thread": t1, "cpu_model": cpu_model(),
