@@ -12,11 +12,15 @@ The aggregation is an input (computed once on the host before timing).
 Printed: ONE JSON line.  value = seconds per step (lower is better).
 Extra fields: the same step with the FP32-mixed energy minimisation (error
 and constraint residual against the FP64 oracle), the masked-product
-kernel's HBM roofline, cold (a 512 MiB buffer rewritten before every launch,
-so nothing of the operands survives in the 256 MB last-level cache) and warm
-(launches back to back), on this workload and on the 1024^2 upwind, 512^2
-elasticity and 16 x 256^2 batched workloads, the batched forward+backward,
-the other two configurations' setups, and the CPU oracle on the same step.
+kernel's HBM roofline, cold (a 512 MiB buffer read before every launch, so
+nothing of the operands survives in the 256 MB last-level cache, which then
+holds clean lines) and warm (launches back to back), on this workload and on
+the 1024^2 upwind, 512^2 elasticity and 16 x 256^2 batched workloads, the
+headline product also after a 512 MiB buffer is rewritten (the cache then
+holds dirty lines the launch has to write back), a plain device copy moving
+the product's traffic under the same conditions (what streaming reaches on
+this GPU), the batched forward+backward, the other two configurations'
+setups, and the CPU oracle on the same step.
 """
 from __future__ import annotations
 
@@ -125,8 +129,21 @@ def time_steps(inp, precision, steps, warmup):
 
 
 class Flush:
-    """A 512 MiB device buffer rewritten before a cold launch (twice the
-    last-level cache), on the library's stream (torch's current one)."""
+    """A 512 MiB device buffer (twice the last-level cache) read before a
+    cold launch, on the library's stream (torch's current one): the
+    operands are evicted and the caches hold clean lines."""
+
+    def __init__(self):
+        import torch
+        self.buf = torch.ones(FLUSH_BYTES // 4, dtype=torch.float32, device="cuda")
+
+    def __call__(self):
+        self.buf.sum()
+
+
+class WriteFlush:
+    """The same buffer rewritten instead: the caches then hold dirty lines,
+    which the next launch's misses write back to HBM."""
 
     def __init__(self):
         import torch
@@ -136,6 +153,37 @@ class Flush:
     def __call__(self):
         self.k += 1
         self.buf.fill_(float(self.k))
+
+
+def copy_calibration(nbytes, reps, flush):
+    """A device copy moving nbytes (half read, half written): seconds per
+    launch cold (flush before each, as for the product) and warm."""
+    import torch
+    n = max(int(nbytes) // 16, 1)
+    x = torch.ones(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        flush()
+        y.copy_(x)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    ev[0].record()
+    for _ in range(reps):
+        flush()
+        y.copy_(x)
+    ev[1].record()
+    for _ in range(reps):
+        flush()
+    ev[2].record()
+    torch.cuda.synchronize()
+    cold = (ev[0].elapsed_time(ev[1]) - ev[1].elapsed_time(ev[2])) / 1e3 / reps
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(4 * reps):
+        y.copy_(x)
+    e1.record()
+    torch.cuda.synchronize()
+    return cold, e0.elapsed_time(e1) / 1e3 / (4 * reps), 16 * n
 
 
 def time_product(ctx, plan, A_vals, X, precision, reps_warm, reps_cold, flush, batch=None):
@@ -543,6 +591,9 @@ def main():
         return
     wall32, ev32, P32, st32, _ = time_steps(inp, R.RN_FP32_MIXED, args.steps, args.warmup)
     head = headline_roofline(inp, aux, args.reps, args.cold_reps, flush)
+    wcold = headline_roofline(inp, aux, 0, args.cold_reps, WriteFlush(), fp64_only=True)["fp64"]
+    tb = traffic_bytes()
+    cc, cw, cb = copy_calibration(tb if tb else TRAFFIC_BYTES, args.cold_reps, flush)
     others = other_rooflines(args.reps, args.cold_reps, flush)
     t_fb, t_f, nnz_n5 = fwd_bwd(args.fb_reps)
     configs = other_configs(args.other_reps, not args.no_cpu) if args.other_reps > 0 else {}
@@ -571,6 +622,11 @@ def main():
         "spgemm_us_fp64_cold": r64["us_cold"],
         "spgemm_us_fp64_warm": r64["us_warm"],
         "spgemm_frac_fp64_warm": r64["frac_warm"],
+        "spgemm_us_fp64_cold_after_write_flush": wcold["us_cold"],
+        "spgemm_frac_fp64_cold_after_write_flush": wcold["frac_cold"],
+        "copy_calibration": {"kernel": "device copy (torch copy_), the product's traffic moved", "bytes": cb,
+                             "us_cold": cc * 1e6, "GBps_cold": cb / cc / 1e9, "us_warm": cw * 1e6,
+                             "GBps_warm": cb / cw / 1e9},
         "spgemm_fp32_mixed_call": head["fp32_mixed_call"],
         "spgemm_batch4": head["batch4"],
         "rooflines_other": others,
@@ -581,7 +637,7 @@ def main():
         **configs,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_bytes(),
-                     "kernel": r64["kernel"], "timing": "cold: a 512 MiB buffer rewritten before every launch; "
+                     "kernel": r64["kernel"], "timing": "cold: a 512 MiB buffer read before every launch; "
                                                        "(flush + launch) x 50 less flush x 50, HIP events",
                      "bytes_per_launch": r64["bytes_per_launch"], "aux_bytes_per_launch": r64["aux_bytes_per_launch"],
                      "flops_per_launch": head["flops"]},
