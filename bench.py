@@ -42,8 +42,8 @@ METRIC = "energy-min setup s & masked-SpGEMM HBM GB/s; FP32-mix vs FP64; fwd+bwd
 # of cold launches, scaled by the same counters on a copy of known size),
 # valid for the kernel sources they were taken on (sha256 prefix below);
 # otherwise reported as null.
-TRAFFIC_BYTES = 59249975
-TRAFFIC_SRC_SHA = "228a443ee5ff969b"
+TRAFFIC_BYTES = 59239422
+TRAFFIC_SRC_SHA = "2824436861feaf7a"
 TRAFFIC_SRCS = ("paper_1610_03154_amd/csrc/rn_spgemm.hip", "paper_1610_03154_amd/csrc/rn_plan.hip",
                 "paper_1610_03154_amd/csrc/rn_emin.h")
 HBM_PEAK_GBS = 8000.0

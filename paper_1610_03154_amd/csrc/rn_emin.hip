@@ -81,13 +81,32 @@ __global__ __launch_bounds__(RN_BLOCK) void k_cg_update(int64_t nnz, int64_t str
       }
     }
   };
-  // the first round's loads go out with the status, gamma_k and partial
-  // loads (one memory round trip before the first store).  A stopped
-  // entry's loads are made and not used.
+  // the partials' loads go out first, then the first round of elements: the
+  // partials are summed (and delta_k, alpha_k formed) while the element loads
+  // are still in flight.  The additions are rn_reduce_part's, in its order.
+  // A stopped entry's loads are made and not used.
+  const double *pp = part_spg + (int64_t)b * pstride;
+  constexpr int PQ = 8;
+  double pv[PQ];
+  const bool pfew = np <= PQ * RN_BLOCK;
+#pragma unroll
+  for (int q = 0; q < PQ; ++q) {
+    const int i = threadIdx.x + q * RN_BLOCK;
+    pv[q] = pfew && i < np ? pp[i] : 0.0;
+  }
   load(e0);
   const int32_t s0 = st[ST_STATUS], s1 = st[ST_DONE];
   const double gam = sc[CgLayout(K).gam + k];
-  const double dl = rn_reduce_part(part_spg + (int64_t)b * pstride, np, s_w);
+  double dl;
+  if (pfew) {
+    RnAcc a;
+#pragma unroll
+    for (int q = 0; q < PQ; ++q)
+      if (threadIdx.x + q * RN_BLOCK < np) a.add(pv[q]);
+    dl = rn_block_sum2(a.hi, a.lo, s_w);
+  } else {
+    dl = rn_reduce_part(pp, np, s_w);
+  }
   if (s0 || s1) return;
   // (another block may read the status before or after block 0 sets a
   // breakdown here; either way it stops on the same delta_k)
