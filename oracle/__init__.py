@@ -403,3 +403,51 @@ def emin_pcg(Ap, Aj, Ax, Np, Nj, is_root, nc, Bc, nB, T, K):
 
 def emin_cgnr(Ap, Aj, Ax, Np, Nj, is_root, nc, Bc, nB, T, K):
     return emin_cg(Ap, Aj, Ax, Np, Nj, is_root, nc, Bc, nB, T, K, variant="cgnr")
+
+
+def hierarchy(A, B, m=1, theta=0.0, degree=2, iters=4, method="cg", max_levels=10, min_coarse=64):
+    """Alg. root_node_setup applied level by level, each coarse operator the
+    Galerkin product of the level above (Sec. 3.8): strength, aggregation,
+    pattern, tentative T, energy minimisation of P (CG; or GMRES for P and for
+    R^T on A^T with T-hat = T, the left candidates equal to B), A_c = R A P,
+    and the coarse candidates Bc as the next level's B.  Level 0 may be
+    node-blocked (m = 2, A given as its scalar CSR); the coarse levels are
+    scalar (their DOFs are m per aggregate).  Stops after max_levels levels,
+    at a level of at most min_coarse rows, or where a level would not
+    coarsen.  Returns the list of levels: dicts with A, B, m and, above the
+    coarsest, the single-level set-up, P and RT (None for CG)."""
+    levels = []
+    Al, ml = A, m
+    Bl = _f64(B).reshape(A.n_rows, -1)
+    while True:
+        lev = dict(A=Al, B=Bl, m=ml)
+        levels.append(lev)
+        if len(levels) >= max_levels or Al.n_rows <= min_coarse:
+            break
+        st = setup(Al, Bl, ml, theta, degree)
+        nc, nB = st["nc"], Bl.shape[1]
+        if nc == 0 or nc >= Al.n_rows:
+            break
+        args = (st["Np"], st["Nj"], st["is_root"], nc, st["Bc"], nB, st["T"], iters)
+        RT = None
+        if method == "cg":
+            P, info = emin_cg(Al.rowptr, Al.colind, Al.vals, *args)
+            if info["status"] != 0:
+                raise OracleError(info["status"], "hierarchy: CG")
+        else:
+            P, _ = emin_gmres(Al.rowptr, Al.colind, Al.vals, *args)
+            Tp, Tj, Tx = transpose(Al.rowptr, Al.colind, Al.vals)
+            RT, _ = emin_gmres(Tp, Tj, Tx, *args)
+        rt = () if RT is None else (st["Np"], st["Nj"], RT)
+        Acp, Acj, Acx = galerkin(Al.rowptr, Al.colind, Al.vals, st["Np"], st["Nj"], P, nc, *rt)
+        lev.update(setup=st, P=P, RT=RT)
+        Al = type(Al)(nc, nc, Acp, Acj, Acx)
+        Bl = _f64(st["Bc"]).reshape(nc, nB)
+        ml = 1
+    return levels
+
+
+def operator_complexity(levels):
+    """Sec. 2.4: the stored entries of every level's operator over those of
+    the finest (scalar entries)."""
+    return sum(lv["A"].nnz for lv in levels) / levels[0]["A"].nnz
