@@ -16,6 +16,8 @@ kernel's HBM roofline, cold (a 512 MiB buffer read before every launch, so
 nothing of the operands survives in the 256 MB last-level cache, which then
 holds clean lines) and warm (launches back to back), on this workload and on
 the 1024^2 upwind, 512^2 elasticity and 16 x 256^2 batched workloads, the
+multilevel set-up of the headline workload (level sizes, operator
+complexity), the
 headline product also after a 512 MiB buffer is rewritten (the cache then
 holds dirty lines the launch has to write back), a plain device copy moving
 the product's traffic under the same conditions (what streaming reaches on
@@ -453,6 +455,33 @@ def _rel(a, b):
     return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
 
 
+def hierarchy_run(inp):
+    """The multilevel set-up of the headline workload (rn_hierarchy_build:
+    the same theta, pattern degree and CG steps on every level, levels down
+    to 500 rows): level sizes, stored entries, operator complexity (Sec.
+    2.4) and seconds per build (host aggregation of every level included)."""
+    import torch
+    import paper_1610_03154_amd as R
+    ctx = inp["ctx"]
+    B = torch.ones((inp["dA"].n, 1), dtype=torch.float64, device="cuda")
+
+    def build():
+        return ctx.hierarchy(inp["dA"], B, max_levels=10, min_coarse=500, theta=THETA, degree=DEGREE, iters=ITERS,
+                             method=R.RN_CG, precision=R.RN_FP64)
+    build().close()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    h = build()
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    views = [h.view(l) for l in range(h.n_levels)]
+    out = {"levels_n": [v.n for v in views], "levels_nnz": [int(v.nnz_A) for v in views],
+           "operator_complexity": h.operator_complexity(), "s": t,
+           "workload": "q1_aniso512 hierarchy, theta 0.1, S^2 C, 6 CG steps per level, down to 500 rows"}
+    h.close()
+    return out
+
+
 def mixed_vs_oracle_upwind(A, agg, roots, res):
     """P and R^T of both precisions against the FP64 oracle's GMRES, with the
     constraint residual of each (Eq. mode_constraint: P Bc = B, R^T Bc^ = B^)."""
@@ -597,6 +626,7 @@ def main():
     others = other_rooflines(args.reps, args.cold_reps, flush)
     t_fb, t_f, nnz_n5 = fwd_bwd(args.fb_reps)
     configs = other_configs(args.other_reps, not args.no_cpu) if args.other_reps > 0 else {}
+    hier = hierarchy_run(inp)
     r64 = head["fp64"]
     achieved = r64["GBps_cold"]
     p64, p32 = P64.cpu().numpy(), P32.cpu().numpy()
@@ -635,6 +665,7 @@ def main():
                             f"S^2 C (nnz_N {nnz_n5} each), 6 CG steps FP64, loss <W,P>",
         "fwd_only_s": t_f,
         **configs,
+        "hierarchy": hier,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_bytes(),
                      "kernel": r64["kernel"], "timing": "cold: a 512 MiB buffer read before every launch; "

@@ -502,6 +502,49 @@ rn_status rn_setup(rn_ctx *ctx, const rn_matrix *A, const int32_t *agg,
 rn_status rn_setup_view_get(const rn_setup_out *s, rn_setup_view *view);
 void rn_setup_destroy(rn_setup_out *s);
 
+/* ---- F3: multilevel set-up (Alg. root_node_setup level by level; Sec. 3.8:
+ * the next level's operator is the Galerkin product A_c = R A P) ------------
+ * From A_0 = A and B_0 = B (n x nB, device, row-major): for each level l,
+ * strength (theta), the host aggregation on S (rn_aggregate_host, same rules
+ * as the stage call), rn_setup (pattern of the given degree, T, iters steps
+ * of method; RN_GMRES also minimises R^T on A^T with B-hat = B_l), then
+ * A_{l+1} = R A_l P (rn_galerkin; R = P^T for RN_CG, (R^T)^T for RN_GMRES)
+ * and B_{l+1} = Bc.  Level 0 may be node-blocked (block_m = 2, RN_CG only);
+ * the coarse levels are scalar CSR (m DOFs per aggregate of the level
+ * above).  Stops after max_levels (>= 1) levels, at a level of at most
+ * min_coarse rows, or where aggregation would not coarsen (every node its own
+ * aggregate).  Every level's arrays are device memory owned by *out (level
+ * 0's A and B stay the caller's and must stay valid while *out lives) until
+ * rn_hierarchy_destroy, which must come before rn_destroy of ctx.  Host
+ * synchronisations: one per level for the aggregation, plus rn_setup's and
+ * rn_galerkin's.  Errors as for the stage calls; on failure *out is NULL. */
+typedef struct rn_hierarchy rn_hierarchy;
+typedef struct {
+  int32_t n;              /* rows of A_l                                    */
+  int32_t block_m;        /* 1, or 2 for a node-blocked level 0             */
+  int64_t nnz_A;          /* stored entries (blocks for block_m = 2)        */
+  const int32_t *A_rowptr, *A_colind; /* device                             */
+  const double *A_vals;   /* device                                         */
+  const double *B;        /* device, n x nB, the level's candidates         */
+  int32_t nB;
+  int32_t n_agg;          /* aggregates of this level (0 on the coarsest)   */
+  const int32_t *agg, *roots; /* device, n/block_m and n_agg (NULL on the coarsest) */
+  const rn_setup_out *setup; /* the level's set-up: rn_setup_view_get gives
+                                S, N, T, Bc, P (and R^T); NULL on the coarsest */
+  rn_emin_stats stats, stats_RT; /* of its energy minimisations           */
+} rn_level_view;
+rn_status rn_hierarchy_build(rn_ctx *ctx, const rn_matrix *A, const double *B,
+                             int32_t nB, int32_t max_levels, int32_t min_coarse,
+                             double theta, int32_t degree, int32_t iters,
+                             rn_method method, rn_precision precision,
+                             rn_hierarchy **out);
+/* Number of levels (>= 1); 0 for NULL. */
+int32_t rn_hierarchy_levels(const rn_hierarchy *h);
+/* The level's pointers and sizes (host struct); RN_EINVAL out of range. */
+rn_status rn_hierarchy_level(const rn_hierarchy *h, int32_t level,
+                             rn_level_view *view);
+void rn_hierarchy_destroy(rn_hierarchy *h);
+
 #ifdef __cplusplus
 }
 #endif

@@ -188,6 +188,73 @@ class NativeSetup:
             pass
 
 
+class Hierarchy:
+    """Results of rn_hierarchy_build: every level's operator, candidates,
+    aggregation and set-up, device memory owned by the library until close();
+    level(l) copies a level's arrays into new torch tensors."""
+
+    def __init__(self, ctx: "Context", handle, keep):
+        self.ctx = ctx
+        self.handle = handle
+        self._keep = keep  # level 0's A and B: the hierarchy keeps their pointers
+        _LIVE_SETUPS.add(self)
+
+    @property
+    def n_levels(self) -> int:
+        return int(L.lib().rn_hierarchy_levels(self.handle)) if self.handle else 0
+
+    def view(self, level: int):
+        v = L.rn_level_view()
+        self.ctx._check(L.lib().rn_hierarchy_level(self.handle, int(level), C.byref(v)), "rn_hierarchy_level")
+        return v
+
+    def _copy(self, src, n, dtype):
+        t = self.ctx.torch.empty(max(int(n), 1), dtype=dtype, device="cuda")[:int(n)]
+        if n > 0:
+            _d2d(t.data_ptr(), src, t.numel() * t.element_size(), C.c_void_p(self.ctx.stream.cuda_stream))
+        return t
+
+    def level(self, level: int) -> dict:
+        torch = self.ctx.torch
+        v = self.view(level)
+        m, n = v.block_m, v.n
+        out = dict(n=n, block_m=m, nnz_A=int(v.nnz_A), nB=v.nB, n_agg=v.n_agg, stats=v.stats, stats_RT=v.stats_RT,
+                   A_rowptr=self._copy(v.A_rowptr, n // m + 1, torch.int32),
+                   A_colind=self._copy(v.A_colind, v.nnz_A, torch.int32),
+                   A_vals=self._copy(v.A_vals, v.nnz_A * m * m, torch.float64),
+                   B=self._copy(v.B, n * v.nB, torch.float64).reshape(n, v.nB))
+        if v.setup:
+            sv = L.rn_setup_view()
+            self.ctx._check(L.lib().rn_setup_view_get(v.setup, C.byref(sv)), "rn_setup_view_get")
+            out.update(agg=self._copy(v.agg, n // m, torch.int32), roots=self._copy(v.roots, v.n_agg, torch.int32),
+                       n_cols=sv.n_cols, N_rowptr=self._copy(sv.N_rowptr, n + 1, torch.int32),
+                       N_colind=self._copy(sv.N_colind, sv.nnz_N, torch.int32),
+                       is_root=self._copy(sv.is_root, n, torch.uint8), T=self._copy(sv.T, sv.nnz_N, torch.float64),
+                       Bc=self._copy(sv.Bc, sv.n_cols * sv.nB, torch.float64).reshape(sv.n_cols, sv.nB),
+                       P=self._copy(sv.P, sv.nnz_N, torch.float64),
+                       RT=self._copy(sv.RT, sv.nnz_N, torch.float64) if sv.RT else None)
+        return out
+
+    def operator_complexity(self) -> float:
+        """Sec. 2.4: scalar stored entries of all levels over the finest's."""
+        vs = [self.view(l) for l in range(self.n_levels)]
+        tot = [v.nnz_A * v.block_m * v.block_m for v in vs]
+        return sum(tot) / tot[0]
+
+    def close(self):
+        if self.handle:
+            L.lib().rn_hierarchy_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        if sys is None or sys.is_finalizing():
+            return
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Tape:
     """An rn_tape: the recorded CG iterates of one forward run, for the adjoint."""
 
@@ -447,6 +514,17 @@ class Context:
         Acv = torch.empty(max(nnz.value, 1), dtype=torch.float64, device="cuda")
         self._check(L.lib().rn_galerkin(*args, _ptr(Acp), _ptr(Acj), _ptr(Acv), C.byref(nnz)), "rn_galerkin")
         return Acp, Acj[:nnz.value], Acv[:nnz.value]
+
+    def hierarchy(self, A: DeviceCSR, B, max_levels=10, min_coarse=64, theta=0.0, degree=2, iters=4,
+                  method=RN_CG, precision=RN_FP64) -> Hierarchy:
+        """rn_hierarchy_build: the multilevel set-up from A and B (n x nB)."""
+        h = C.c_void_p()
+        d = A.desc()
+        B = B.to(self.torch.float64).reshape(A.n, -1).contiguous()
+        self._check(L.lib().rn_hierarchy_build(self.h, C.byref(d), _ptr(B), int(B.shape[1]), int(max_levels),
+                                               int(min_coarse), C.c_double(theta), int(degree), int(iters), method,
+                                               precision, C.byref(h)), "rn_hierarchy_build")
+        return Hierarchy(self, h, (A, B))
 
     # -- transpose -----------------------------------------------------------
     def setup_native(self, A: DeviceCSR, B, agg, roots, theta=0.0, degree=2, iters=4, method=RN_CG,

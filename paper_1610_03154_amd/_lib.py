@@ -49,6 +49,13 @@ class rn_setup_view(C.Structure):
                 ("plan", C.c_void_p), ("plan_T", C.c_void_p)]
 
 
+class rn_level_view(C.Structure):
+    _fields_ = [("n", C.c_int32), ("block_m", C.c_int32), ("nnz_A", C.c_int64),
+                ("A_rowptr", C.c_void_p), ("A_colind", C.c_void_p), ("A_vals", C.c_void_p), ("B", C.c_void_p),
+                ("nB", C.c_int32), ("n_agg", C.c_int32), ("agg", C.c_void_p), ("roots", C.c_void_p),
+                ("setup", C.c_void_p), ("stats", rn_emin_stats), ("stats_RT", rn_emin_stats)]
+
+
 # name -> (restype, argtypes); every declaration of include/rnamg.h
 _vp, _i32, _i64, _d = C.c_void_p, C.c_int32, C.c_int64, C.c_double
 _pi32, _pi64 = C.POINTER(C.c_int32), C.POINTER(C.c_int64)
@@ -92,6 +99,11 @@ SIGNATURES = {
                         C.POINTER(C.c_void_p), C.POINTER(rn_emin_stats), C.POINTER(rn_emin_stats)]),
     "rn_setup_view_get": (_i32, [_vp, C.POINTER(rn_setup_view)]),
     "rn_setup_destroy": (None, [_vp]),
+    "rn_hierarchy_build": (_i32, [_vp, C.POINTER(rn_matrix), _vp, _i32, _i32, _i32, _d, _i32, _i32, _i32, _i32,
+                                  C.POINTER(C.c_void_p)]),
+    "rn_hierarchy_levels": (_i32, [_vp]),
+    "rn_hierarchy_level": (_i32, [_vp, _i32, C.POINTER(rn_level_view)]),
+    "rn_hierarchy_destroy": (None, [_vp]),
 }
 
 _lib = None
