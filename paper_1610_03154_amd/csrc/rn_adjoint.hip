@@ -479,21 +479,65 @@ __global__ __launch_bounds__(RN_BLOCK) void k_adj_sddmm_w(int nblk, int64_t nz, 
   const double *x = X + (int64_t)b * strideX;
   double *ab = Abar + (int64_t)b * nnzA;
   const int nw = cstride >> 2;
-  for (int rr = t; rr <= nrows; rr += RN_BLOCK) {
-    s_ap[rr] = Ap[r0 + rr] - a0;
-    s_rp[rr] = Np[r0 + rr] - e0;
-    if (rr < nrows) s_root[rr] = is_root[r0 + rr];
+  // one round of loads that depend on the header only (row starts and root
+  // flags, the entries' Yh and records, the window, and for this lane's A
+  // entries their neighbour-row offsets and the Abar values they add to),
+  // then the LDS stores
+  constexpr int NAQ = SPG_ACAP_M1(RN_BLOCK) / RN_BLOCK;  // A entries per lane when they find their row in LDS
+  const int tr = t < nrows ? t : nrows;
+  const int v_ap = Ap[r0 + tr] - a0, v_rp = Np[r0 + tr] - e0;
+  const uint8_t v_root = t < nrows ? is_root[r0 + t] : (uint8_t)0;
+  int v_ap2 = 0, v_rp2 = 0;
+  if (t == 0 && nrows == RN_BLOCK) {  // the end of the last row
+    v_ap2 = Ap[r0 + RN_BLOCK] - a0;
+    v_rp2 = Np[r0 + RN_BLOCK] - e0;
   }
-  for (int q = t; q < ne; q += RN_BLOCK) s_y[q] = y[e0 + q];
-  {
-    const uint32_t *cw = (const uint32_t *)codes + (int64_t)e0 * nw;
-    for (int q = t; q < ne * nw; q += RN_BLOCK) s_rec[(q / nw) * SD_REC + q % nw] = cw[q];
+  const double v_y = t < ne ? y[e0 + t] : 0.0;
+  const uint32_t *cw = (const uint32_t *)codes + (int64_t)e0 * nw;
+  uint32_t v_rec[SD_REC];
+#pragma unroll
+  for (int i = 0; i < SD_REC; ++i) {
+    const int q = t + i * RN_BLOCK;
+    v_rec[i] = q < ne * nw ? cw[q] : 0u;
+  }
+  double v_xw[SPG_XCAP_M1(RN_BLOCK) / RN_BLOCK];
+#pragma unroll
+  for (int i = 0; i < SPG_XCAP_M1(RN_BLOCK) / RN_BLOCK; ++i) {
+    const int q = t + i * RN_BLOCK;
+    v_xw[i] = (nunit > 0 && q < nunit * XW_UNIT) ? x[uwv[i] + q % XW_UNIT] : 0.0;
+  }
+  int v_xo[NAQ];
+  double v_ab[NAQ];
+#pragma unroll
+  for (int i = 0; i < NAQ; ++i) {
+    const int q = t + i * RN_BLOCK;
+    v_xo[i] = 0;
+    v_ab[i] = 0.0;
+    if (q < na) {
+      v_xo[i] = nunit > 0 ? xl[a0 + q] : xoff[a0 + q];
+      v_ab[i] = ab[a0 + q];
+    }
+  }
+  if (t <= nrows) {
+    s_ap[t] = v_ap;
+    s_rp[t] = v_rp;
+  }
+  if (t < nrows) s_root[t] = v_root;
+  if (t == 0 && nrows == RN_BLOCK) {
+    s_ap[RN_BLOCK] = v_ap2;
+    s_rp[RN_BLOCK] = v_rp2;
+  }
+  if (t < ne) s_y[t] = v_y;
+#pragma unroll
+  for (int i = 0; i < SD_REC; ++i) {
+    const int q = t + i * RN_BLOCK;
+    if (q < ne * nw) s_rec[(q / nw) * SD_REC + q % nw] = v_rec[i];
   }
   if (nunit > 0) {
 #pragma unroll
     for (int i = 0; i < SPG_XCAP_M1(RN_BLOCK) / RN_BLOCK; ++i) {
       const int q = t + i * RN_BLOCK;
-      if (q < nunit * XW_UNIT) s_xw[q] = x[uwv[i] + q % XW_UNIT];
+      if (q < nunit * XW_UNIT) s_xw[q] = v_xw[i];
     }
   }
   __syncthreads();
@@ -501,36 +545,50 @@ __global__ __launch_bounds__(RN_BLOCK) void k_adj_sddmm_w(int nblk, int64_t nz, 
     for (int rr = t; rr < nrows; rr += RN_BLOCK)
       for (int q = s_ap[rr]; q < s_ap[rr + 1]; ++q) s_arow[q] = (uint8_t)rr;
   __syncthreads();
-  for (int q = t; q < na; q += RN_BLOCK) {
-    int lo = 0;
-    if (byrow) {
-      lo = s_arow[q];
-    } else {
-      int hi = nrows;  // row: the largest rr with s_ap[rr] <= q
-      while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (s_ap[mid] <= q) lo = mid; else hi = mid;
-      }
+  // the block row of A entry q
+  auto row_of = [&](const int q) -> int {
+    if (byrow) return s_arow[q];
+    int lo = 0, hi = nrows;  // the largest rr with s_ap[rr] <= q
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (s_ap[mid] <= q) lo = mid; else hi = mid;
     }
-    if (s_root[lo]) continue;
+    return lo;
+  };
+  // the sum of A entry q (in row lo) over the row's pattern entries, in pattern order
+  auto entry = [&](const int q, const int lo, const int xo) -> double {
     const int u = q - s_ap[lo];
     const int pb = u + 1;  // byte of the code in each record
     const uint32_t *rec = s_rec + (pb >> 2);
     const int sh = 8 * (pb & 3);
     double acc = 0.0;
     if (nunit > 0) {
-      const int xo = xl[a0 + q];
       for (int r = s_rp[lo]; r < s_rp[lo + 1]; ++r) {
         const uint32_t c = (rec[r * SD_REC] >> sh) & 0xffu;
         if (c != CODE_NONE) acc += s_y[r] * s_xw[xo + (int)c];
       }
     } else {
-      const int xo = xoff[a0 + q];
       for (int r = s_rp[lo]; r < s_rp[lo + 1]; ++r) {
         const uint32_t c = (rec[r * SD_REC] >> sh) & 0xffu;
         if (c != CODE_NONE) acc += s_y[r] * x[xo + (int)c];
       }
     }
+    return acc;
+  };
+  // root rows get no contribution: their Abar entries are not written
+#pragma unroll
+  for (int i = 0; i < NAQ; ++i) {
+    const int q = t + i * RN_BLOCK;
+    if (q < na) {
+      const int lo = row_of(q);
+      if (!s_root[lo]) ab[a0 + q] = v_ab[i] + entry(q, lo, v_xo[i]);
+    }
+  }
+  // blocks with more A entries than that: the rest one at a time
+  for (int q = t + NAQ * RN_BLOCK; q < na; q += RN_BLOCK) {
+    const int lo = row_of(q);
+    if (s_root[lo]) continue;
+    const double acc = entry(q, lo, nunit > 0 ? xl[a0 + q] : xoff[a0 + q]);
     ab[a0 + q] += acc;
   }
 }
