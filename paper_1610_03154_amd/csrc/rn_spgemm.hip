@@ -37,6 +37,14 @@ __device__ inline void spg_st(T *base, uint32_t i, T v) {
   *(T *)((char *)base + i * (uint32_t)sizeof(T)) = v;
 }
 
+// two adjacent elements at element index i (i even, base aligned to the pair)
+template <class T>
+__device__ inline typename std::conditional<sizeof(T) == 8, double2, float2>::type spg_ld2(const T *base,
+                                                                                           uint32_t i) {
+  using T2 = typename std::conditional<sizeof(T) == 8, double2, float2>::type;
+  return *(const T2 *)((const char *)base + i * (uint32_t)sizeof(T));
+}
+
 template <int M, int NB, bool MIXED, int BS>
 struct SpgShape {
   using TV = typename std::conditional<MIXED, float, double>::type;
@@ -310,15 +318,11 @@ __global__ __launch_bounds__(BS) void k_spgemm(const SpgParams p) {
       for (int q = 0; q < NP; ++q) gq[0][q] = s_gp[lrow * NP + q];
 #pragma unroll
       for (int q = 0; q < NB; ++q) bc[0][q] = bcv[q];
-    } else if (proj) {  // root lanes load too (their row and column are in range): no branch
+    } else if (proj && M == 1) {  // root lanes load too (their row and column are in range): no branch
 #pragma unroll
-      for (int c = 0; c < M; ++c) {
-        const uint32_t grow = (M == 1) ? (uint32_t)(r0 + lrow) : (uint32_t)(2 * (r0 + lrow) + c);
+      for (int q = 0; q < NP; ++q) gq[0][q] = spg_ld(p.gp, (uint32_t)(r0 + lrow) * NP + q);
 #pragma unroll
-        for (int q = 0; q < NP; ++q) gq[c][q] = spg_ld(p.gp, grow * NP + q);
-#pragma unroll
-        for (int q = 0; q < NB; ++q) bc[c][q] = spg_ld(p.Bc, (uint32_t)(M * jc0 + c) * NB + q);
-      }
+      for (int q = 0; q < NB; ++q) bc[0][q] = spg_ld(p.Bc, (uint32_t)jc0 * NB + q);
     }
     if constexpr (M == 1) {
       zi[0] = e0 + t;
@@ -408,6 +412,59 @@ __global__ __launch_bounds__(BS) void k_spgemm(const SpgParams p) {
         const int na = s_ap[lrow + 1] - la;
         TV z00 = 0, z01 = 0, z10 = 0, z11 = 0;
         uint32_t w = w0;
+        // Every node's DOF rows start at an even pattern offset: a non-root
+        // node's two rows hold the same even number of entries, a root
+        // node's one each (the plan checks both).  So a non-root neighbour's
+        // pair (2c, 2c + 1) of either row is one aligned two-element load,
+        // and a root neighbour's two entries are the pair at its first row
+        // (x1 = x0 + 1), whenever X itself is aligned to a pair.
+        const bool xpair = ((uintptr_t)X & (2 * sizeof(TV) - 1)) == 0;
+        if (staged && xpair) {
+          // three terms at a time: their loads, then their multiply-adds in
+          // the order of A's row; a term past the row or without a code
+          // loads the pair at 0 and adds nothing (+0 leaves the sums as
+          // they are: they start at +0 and never become -0)
+          using TV2 = typename std::conditional<MIXED, float2, double2>::type;
+          constexpr int U2 = 3;
+          for (int t0 = 0; t0 < na; t0 += U2) {
+            TV2 va[U2], vb[U2];
+            TV av4[U2][NO];
+            bool hit[U2], rootk[U2];
+#pragma unroll
+            for (int u = 0; u < U2; ++u) {
+              const int tt = t0 + u;
+              const bool live = tt < na;
+              const int tq = live ? tt : 0;
+              const int pb = tq + 1, wi = pb >> 2;
+              const uint32_t wd = wi == 0 ? w0 : (wi == 1 ? w1 : (wi == 2 ? w2 : spg_ld(codes, rec + wi)));
+              const uint32_t c = live ? (wd >> (8 * (pb & 3))) & 0xffu : (uint32_t)CODE_NONE;
+              const int x0 = s_x0[la + tq], x1 = s_x1[la + tq];
+              hit[u] = c != CODE_NONE;
+              rootk[u] = c == CODE_ROOT;
+              const uint32_t ia = !hit[u] ? 0u : (uint32_t)(rootk[u] ? x0 : x0 + 2 * (int)c);
+              const uint32_t ib = !hit[u] ? 0u : (uint32_t)(rootk[u] ? x0 : x1 + 2 * (int)c);
+              va[u] = spg_ld2(X, ia);
+              vb[u] = spg_ld2(X, ib);
+#pragma unroll
+              for (int o = 0; o < NO; ++o) av4[u][o] = s_ax[(la + tq) * NO + o];
+            }
+#pragma unroll
+            for (int u = 0; u < U2; ++u) {
+              const TV x00 = va[u].x, x01 = rootk[u] ? TV(0) : va[u].y, x10 = rootk[u] ? TV(0) : vb[u].x,
+                       x11 = rootk[u] ? va[u].y : vb[u].y;
+              const TV *a = av4[u];
+              const bool h = hit[u];
+              z00 += h ? a[0] * x00 : TV(0);
+              z00 += h ? a[1] * x10 : TV(0);
+              z01 += h ? a[0] * x01 : TV(0);
+              z01 += h ? a[1] * x11 : TV(0);
+              z10 += h ? a[2] * x00 : TV(0);
+              z10 += h ? a[3] * x10 : TV(0);
+              z11 += h ? a[2] * x01 : TV(0);
+              z11 += h ? a[3] * x11 : TV(0);
+            }
+          }
+        } else
         for (int tt = 0; tt < na; ++tt) {
           const int pb = tt + 1;  // byte of the code in the record
           if ((pb & 3) == 0) w = pb == 4 ? w1 : (pb == 8 ? w2 : spg_ld(codes, rec + (pb >> 2)));
@@ -431,6 +488,13 @@ __global__ __launch_bounds__(BS) void k_spgemm(const SpgParams p) {
               x11 = spg_ld(X, (uint32_t)x1);
               x01 = 0;
               x10 = 0;
+            } else if (xpair && ((x0 | x1) & 1) == 0) {
+              const auto xa = spg_ld2(X, (uint32_t)(x0 + 2 * (int)c));
+              const auto xb = spg_ld2(X, (uint32_t)(x1 + 2 * (int)c));
+              x00 = xa.x;
+              x01 = xa.y;
+              x10 = xb.x;
+              x11 = xb.y;
             } else {
               x00 = spg_ld(X, (uint32_t)(x0 + 2 * (int)c));
               x01 = spg_ld(X, (uint32_t)(x0 + 2 * (int)c + 1));
@@ -452,6 +516,18 @@ __global__ __launch_bounds__(BS) void k_spgemm(const SpgParams p) {
         z[1] = (double)z01;
         z[M] = (double)z10;
         z[M + 1] = (double)z11;
+      }
+      // the projection data of both DOF rows load after the term loop (held
+      // across it they would cost a workgroup per compute unit)
+      if (proj) {
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+          const uint32_t grow = (uint32_t)(2 * (r0 + lrow) + c);
+#pragma unroll
+          for (int q = 0; q < NP; ++q) gq[c][q] = spg_ld(p.gp, grow * NP + q);
+#pragma unroll
+          for (int q = 0; q < NB; ++q) bc[c][q] = spg_ld(p.Bc, (uint32_t)(M * jc0 + c) * NB + q);
+        }
       }
     }
   }
