@@ -44,8 +44,10 @@ METRIC = "energy-min setup s & masked-SpGEMM HBM GB/s; FP32-mix vs FP64; fwd+bwd
 # of cold launches, scaled by the same counters on a copy of known size),
 # valid for the kernel sources they were taken on (sha256 prefix below);
 # otherwise reported as null.
-TRAFFIC_BYTES = 59239422
-TRAFFIC_SRC_SHA = "2824436861feaf7a"
+TRAFFIC_BYTES = 59239393
+TRAFFIC_SRC_SHA = "ec16a9a5e077f7eb"
+# the other workloads' products (same counters, same calibration, same sources)
+TRAFFIC_OTHER = {"upwind1024": 181788719, "elastic512": 223663016, "aniso_batch256x16": 159695670}
 TRAFFIC_SRCS = ("paper_1610_03154_amd/csrc/rn_spgemm.hip", "paper_1610_03154_amd/csrc/rn_plan.hip",
                 "paper_1610_03154_amd/csrc/rn_emin.h")
 HBM_PEAK_GBS = 8000.0
@@ -278,53 +280,79 @@ def headline_roofline(inp, aux, reps_warm, reps_cold, flush, fp64_only=False):
     return out
 
 
-def other_rooflines(reps_warm, reps_cold, flush):
-    """Cold and warm product launches on the study's other configurations."""
+OTHER_WORKLOADS = ("upwind1024", "elastic512", "aniso_batch256x16")
+
+
+def other_rooflines(reps_warm, reps_cold, flush, only=None):
+    """Cold and warm product launches on the study's other configurations
+    (only: that workload alone)."""
     import torch
     import workloads as W
     import paper_1610_03154_amd as R
     ctx = R.Context()
     res = []
+    if only in (None, "upwind1024"):
+        A = W.upwind_cd(1024)
+        dA = R.DeviceCSR.from_host(A.rowptr, A.colind, A.vals)
+        plan, Nj, na = _struct(ctx, dA, torch.ones((A.n_rows, 1), dtype=torch.float64, device="cuda"), 1, 0.0)
+        X = torch.randn(Nj.numel(), dtype=torch.float64, device="cuda")
+        c, w = time_product(ctx, plan, dA.vals, X, R.RN_FP64, reps_warm, reps_cold, flush)
+        b, a = product_bytes(dA.nnz, dA.n, int(Nj.numel()), dA.n, n_f=dA.n - na)
+        res.append(roof("k_spgemm_p<NB=1,MODE_PRODUCT,fp64,256 lanes> (the product of each GMRES step)",
+                        "upwind1024", b, a, c, w))
+        plan.close()
+    if only in (None, "elastic512"):
+        res += elastic_roofline(ctx, reps_warm, reps_cold, flush)
+    if only in (None, "aniso_batch256x16"):
+        res += batch_roofline(ctx, reps_warm, reps_cold, flush)
+    ctx.close()
+    for r in res:
+        r["traffic"] = traffic_bytes(r["workload"])
+    return res
 
-    def struct(dA, B, m, theta):
-        Sp, Sj = ctx.strength(dA, theta)
-        a, r = R.aggregate_host(Sp.cpu().numpy(), Sj.cpu().numpy())
-        agg, roots = torch.as_tensor(a, device="cuda"), torch.as_tensor(r, device="cuda")
-        Np, Nj, is_root = ctx.pattern(Sp, Sj, agg, roots, 2, m)
-        T, Bc, _ = ctx.tentative(Np, Nj, is_root, agg, roots, m, B)
-        plan = ctx.plan(dA, m * int(roots.numel()), Np, Nj, is_root, Bc)
-        return plan, Nj, int(roots.numel())
 
-    A = W.upwind_cd(1024)
-    dA = R.DeviceCSR.from_host(A.rowptr, A.colind, A.vals)
-    plan, Nj, na = struct(dA, torch.ones((A.n_rows, 1), dtype=torch.float64, device="cuda"), 1, 0.0)
-    X = torch.randn(Nj.numel(), dtype=torch.float64, device="cuda")
-    c, w = time_product(ctx, plan, dA.vals, X, R.RN_FP64, reps_warm, reps_cold, flush)
-    b, a = product_bytes(dA.nnz, dA.n, int(Nj.numel()), dA.n, n_f=dA.n - na)
-    res.append(roof("k_spgemm_p<NB=1,MODE_PRODUCT,fp64,256 lanes> (the product of each GMRES step)",
-                    "upwind1024", b, a, c, w))
-    plan.close()
+def _struct(ctx, dA, B, m, theta):
+    """Strength, aggregation, pattern, tentative T and the product plan."""
+    import torch
+    import paper_1610_03154_amd as R
+    Sp, Sj = ctx.strength(dA, theta)
+    a, r = R.aggregate_host(Sp.cpu().numpy(), Sj.cpu().numpy())
+    agg, roots = torch.as_tensor(a, device="cuda"), torch.as_tensor(r, device="cuda")
+    Np, Nj, is_root = ctx.pattern(Sp, Sj, agg, roots, 2, m)
+    T, Bc, _ = ctx.tentative(Np, Nj, is_root, agg, roots, m, B)
+    plan = ctx.plan(dA, m * int(roots.numel()), Np, Nj, is_root, Bc)
+    return plan, Nj, int(roots.numel())
+
+
+def elastic_roofline(ctx, reps_warm, reps_cold, flush):
+    import torch
+    import workloads as W
+    import paper_1610_03154_amd as R
     Ab, xy = W.q1_elasticity(512)
     dA = R.DeviceCSR.from_host(Ab.rowptr, Ab.colind, Ab.vals.reshape(-1), n=Ab.n_nodes * 2, block_m=2)
-    plan, Nj, na = struct(dA, torch.as_tensor(W.rbm(xy), device="cuda"), 2, 0.0)
+    plan, Nj, na = _struct(ctx, dA, torch.as_tensor(W.rbm(xy), device="cuda"), 2, 0.0)
     X = torch.randn(Nj.numel(), dtype=torch.float64, device="cuda")
     c, w = time_product(ctx, plan, dA.vals, X, R.RN_FP64, reps_warm, reps_cold, flush)
     n = dA.n
     b, a = product_bytes(dA.nnz, Ab.n_nodes, int(Nj.numel()), n, m=2, nB=3, n_f=n - 2 * na)
-    res.append(roof("k_spgemm<M=2,NB=3,MODE_PRODUCT,fp64,256> (node-blocked)", "elastic512", b, a, c, w))
     plan.close()
+    return [roof("k_spgemm<M=2,NB=3,MODE_PRODUCT,fp64,256> (node-blocked)", "elastic512", b, a, c, w)]
+
+
+def batch_roofline(ctx, reps_warm, reps_cold, flush):
+    import torch
+    import workloads as W
+    import paper_1610_03154_amd as R
     A0, vals, _, _ = W.aniso_batch(256, 16, 0)
     dA = R.DeviceCSR.from_host(A0.rowptr, A0.colind, A0.vals)
-    plan, Nj, na = struct(dA, torch.ones((A0.n_rows, 1), dtype=torch.float64, device="cuda"), 1, 0.0)
+    plan, Nj, na = _struct(ctx, dA, torch.ones((A0.n_rows, 1), dtype=torch.float64, device="cuda"), 1, 0.0)
     av = torch.as_tensor(vals, device="cuda")
     X = torch.randn((16, Nj.numel()), dtype=torch.float64, device="cuda")
-    c, w = time_product(ctx, plan, av, X, R.RN_FP64, max(reps_warm // 4, 10), reps_cold, flush)
+    c, w = time_product(ctx, plan, av, X, R.RN_FP64, max(reps_warm // 4, 10) if reps_warm else 0, reps_cold, flush)
     b, a = product_bytes(dA.nnz, dA.n, int(Nj.numel()), dA.n, n_f=dA.n - na, batch=16)
-    res.append(roof("k_spgemm_p, 16 problems per launch (shared structure counted once)", "aniso_batch256x16", b, a,
-                    c, w))
     plan.close()
-    ctx.close()
-    return res
+    return [roof("k_spgemm_p, 16 problems per launch (shared structure counted once)", "aniso_batch256x16", b, a,
+                 c, w)]
 
 
 def fwd_bwd(reps):
@@ -376,15 +404,19 @@ def fwd_bwd(reps):
     return t_fb, t_f, int(Nj.numel())
 
 
-def traffic_bytes():
+def traffic_bytes(workload="q1aniso512"):
+    """HBM bytes per launch from the FETCH_SIZE and WRITE_SIZE counters, or
+    None once the product's sources differ from those the counters were
+    taken on."""
     import hashlib
-    if TRAFFIC_BYTES is None:
+    tb = TRAFFIC_BYTES if workload == "q1aniso512" else TRAFFIC_OTHER.get(workload)
+    if tb is None:
         return None
     h = hashlib.sha256()
     for f in TRAFFIC_SRCS:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
-    return TRAFFIC_BYTES if h.hexdigest()[:16] == TRAFFIC_SRC_SHA else None
+    return tb if h.hexdigest()[:16] == TRAFFIC_SRC_SHA else None
 
 
 def other_configs(reps, check_oracle):
@@ -592,8 +624,12 @@ def main():
     ap.add_argument("--cold-reps", type=int, default=50, help="launches, each after a cache flush, for the cold timing")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle legs")
     ap.add_argument("--fb-reps", type=int, default=5, help="repetitions of the batched forward+backward")
-    ap.add_argument("--roofline-only", action="store_true",
-                    help="only the cold launches of the headline product (the roofline's own loop)")
+    ap.add_argument("--roofline-only", nargs="?", const="q1aniso512", default=None,
+                    choices=("q1aniso512",) + OTHER_WORKLOADS,
+                    help="only the cold launches of one workload's product (default the headline's: the "
+                         "roofline's own loop)")
+    ap.add_argument("--fwd-bwd-only", action="store_true",
+                    help="only the batched forward+backward (for a kernel trace of the adjoint)")
     ap.add_argument("--steps-only", action="store_true",
                     help="only the timed FP64 set-up steps (for a kernel trace of the step)")
     ap.add_argument("--other-reps", type=int, default=3,
@@ -608,6 +644,13 @@ def main():
     torch.cuda.set_device(0)
     inp = build_inputs()
     flush = Flush()
+    if args.fwd_bwd_only:
+        t_fb, t_f, _ = fwd_bwd(args.fb_reps)
+        print(json.dumps({"fwd_bwd_s": t_fb, "fwd_only_s": t_f, "reps": args.fb_reps}))
+        return
+    if args.roofline_only and args.roofline_only != "q1aniso512":
+        print(json.dumps(other_rooflines(0, args.cold_reps, flush, only=args.roofline_only)))
+        return
     if args.roofline_only:
         P, st, plan, aux = gpu_step(inp, R.RN_FP64)
         plan.close()

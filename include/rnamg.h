@@ -160,7 +160,7 @@ typedef enum {
    * the projected residual and the constraint residual of their result into
    * rn_emin_stats (one more product and two reductions per call). */
   RN_OPT_METRICS = 4,
-  /* 1 (default): FP64 CG (RN_CG) without a tape, on plans whose products run
+  /* 1 (default): FP64 CG (RN_CG), with or without a tape, on plans whose products run
    * as persistent workgroups of 256 lanes, forms the direction D = R + beta D
    * while the next product stages its X window (two launches per step, two D
    * buffers); 0: a separate direction pass (three launches per step).  The

@@ -918,12 +918,11 @@ extern "C" rn_status rn_energy_min(rn_ctx *ctx, rn_plan *pl, const double *A_val
 
 // Workspace bytes emin_run requests (each piece rounded to 256 bytes, as the
 // arena carves them), and the bytes of its one read-back.
-// plain FP64 CG without a tape forms each direction inside the next product
+// plain FP64 CG (with or without a tape) forms each direction inside the next
+// product
 // when the context allows it and the persistent product serves the plan
-static bool cg_fused(const rn_ctx *ctx, const rn_plan *pl, int32_t batch, rn_method method, rn_precision prec,
-                     bool tape) {
-  return ctx->opt[RN_OPT_FUSED_CG] && method == RN_CG && prec == RN_FP64 && !tape &&
-         rn_spgemm_fused_grid(pl, batch) > 0;
+static bool cg_fused(const rn_ctx *ctx, const rn_plan *pl, int32_t batch, rn_method method, rn_precision prec) {
+  return ctx->opt[RN_OPT_FUSED_CG] && method == RN_CG && prec == RN_FP64 && rn_spgemm_fused_grid(pl, batch) > 0;
 }
 
 static size_t emin_ws_need(const rn_plan *pl, int32_t batch, bool gm, bool pcg, int K, bool mixed, bool fused,
@@ -962,7 +961,7 @@ extern "C" rn_status rn_energy_min_noalloc(rn_ctx *ctx, rn_plan *pl, const doubl
   if (!ctx->rb_host) return rn_fail(ctx, RN_ENOMEM, "rn_energy_min_noalloc: no read-back area");
   size_t fetch = 0;
   const size_t need = emin_ws_need(pl, batch, method == RN_GMRES, method == RN_PCG_JACOBI, iters,
-                                   prec == RN_FP32_MIXED, cg_fused(ctx, pl, batch, method, prec, false), &fetch);
+                                   prec == RN_FP32_MIXED, cg_fused(ctx, pl, batch, method, prec), &fetch);
   if (need > RN_NOALLOC_SCRATCH_BYTES)
     return rn_fail(ctx, RN_ELIMIT,
                    "rn_energy_min_noalloc: the call needs %zu bytes of scratch, the allocation-free limit is %zu",
@@ -992,7 +991,7 @@ static rn_status emin_run(rn_ctx *ctx, rn_plan *pl, const double *A_vals, int32_
                           rn_emin_stats *stats, rn_tape *tape) {
   const bool mixed = prec == RN_FP32_MIXED;
   const bool gm = method == RN_GMRES;
-  const bool fuse = cg_fused(ctx, pl, batch, method, prec, tape != nullptr);
+  const bool fuse = cg_fused(ctx, pl, batch, method, prec);
   const int K = iters;
   const int64_t nz = pl->nnzN, nzb = (int64_t)batch * nz;
   rn_status st = RN_OK;
@@ -1185,6 +1184,11 @@ static rn_status emin_run(rn_ctx *ctx, rn_plan *pl, const double *A_vals, int32_
         s.hist = hist;
         s.hist_stride = hist_stride;
         RN_TRY(rn_launch_spgemm(ctx, pl, MODE_CG_FSTEP, s, batch, false, &np));
+        // a checkpoint step keeps the D_k the product just formed (a batch
+        // entry that stopped leaves its slot unread: the reverse sweep skips
+        // the steps it did not take)
+        if (double *dt = tape ? rn_tape_D(tape, k) : nullptr)
+          HIP_TRY(ctx, hipMemcpyAsync(dt, Dk, (size_t)nzb * 8, hipMemcpyDeviceToDevice, ctx->stream));
       } else {
         s.X = mixed ? (const void *)D32 : (const void *)D;
         s.Xown = D;

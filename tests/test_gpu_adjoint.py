@@ -196,7 +196,10 @@ def test_checkpoint_interval_gives_the_same_gradient(R, case):
     checkpoints with the recorded step lengths and the forward's own
     expressions, so every interval (1 = every step kept, 0 = ceil(sqrt(K)),
     up to one checkpoint for the whole run) gives the same gradient bit for
-    bit, and the default matches the oracle's tangent model."""
+    bit, and the default matches the oracle's tangent model.  The taped
+    forward with the direction formed inside the next product
+    (RN_OPT_FUSED_CG = 1, the default) records the same iterates as with a
+    separate direction pass, so the gradient is the same bit for bit too."""
     if case == "batch":
         A0, vals, st, Wt = problem(64, 3)
         Kc = K
@@ -207,19 +210,22 @@ def test_checkpoint_interval_gives_the_same_gradient(R, case):
         Wt = np.random.default_rng(3).standard_normal((1, st["Nj"].size))
         Kc = 12  # converges before K
     grads = {}
-    for c in (1, 0, 2, 4, Kc, Kc + 3):
+    runs = [(c, 1) for c in (1, 0, 2, 4, Kc, Kc + 3)] + [(c, 0) for c in (1, 0, Kc + 3)]
+    for c, fused in runs:
         cx = R.Context()
         cx.set_option(R._lib.RN_OPT_TAPE_INTERVAL, c)
+        cx.set_option(R._lib.RN_OPT_FUSED_CG, fused)
         dA = R.DeviceCSR.from_host(A0.rowptr, A0.colind, A0.vals)
         op = R.EnergyMinOperator(cx, dA, int(st["nc"]), dev(st["Np"]), dev(st["Nj"]), dev(st["is_root"]),
                                  dev(st["T"]), dev(st["Bc"]), Kc)
         P, g = gpu_grad(R, cx, op, vals if vals.shape[0] > 1 else vals[0], Wt if Wt.shape[0] > 1 else Wt[0])
-        grads[c] = (P, g)
+        grads[(c, fused)] = (P, g)
         op.close()
         cx.close()
-    P1, g1 = grads[1]
-    for c, (P, g) in grads.items():
-        assert np.array_equal(P, P1) and np.array_equal(g, g1), f"interval {c}: max |dg| {np.max(np.abs(g - g1))}"
+    P1, g1 = grads[(1, 0)]
+    for (c, fused), (P, g) in grads.items():
+        assert np.array_equal(P, P1) and np.array_equal(g, g1), \
+            f"interval {c}, fused {fused}: max |dP| {np.max(np.abs(P - P1))}, max |dg| {np.max(np.abs(g - g1))}"
     g = g1.reshape(len(Wt), -1)
     rng = np.random.default_rng(5)
     for b in range(len(Wt)):
