@@ -167,10 +167,11 @@ typedef enum {
    * two give the same result bit for bit. */
   RN_OPT_FUSED_CG = 5,
   /* 0 (default): tapes made by rn_tape_create keep the CG iterates R_k, D_k
-   * at every c-th step, c = ceil(sqrt(iters)); c >= 1: that interval.  The
-   * reverse sweep recomputes the steps between checkpoints from the tape's
-   * step lengths (the gradient is the same bit for bit for every c; c = 1
-   * stores every step).  Read when a tape is made. */
+   * and Z_k at every c-th step, c = ceil(sqrt(iters)); c >= 1: that
+   * interval.  The reverse sweep recomputes the steps between checkpoints
+   * from the tape's step lengths (the gradient is the same bit for bit for
+   * every c; c = 1 stores every step and recomputes none).  Read when a tape
+   * is made. */
   RN_OPT_TAPE_INTERVAL = 6
 } rn_option;
 rn_status rn_set_option(rn_ctx *ctx, rn_option opt, int32_t value);
@@ -450,12 +451,12 @@ rn_status rn_constraint_residual(rn_ctx *ctx, int32_t n, int32_t n_cols,
 
 /* ---- a12: adjoint of the CG energy minimisation (map A values -> P) -----
  * Tape for `batch` problems of `iters` CG steps on `plan`; holds the Krylov
- * scalars and the iterates R_k, D_k at the checkpoints k = 0, c, 2c, ... < iters
- * (c from RN_OPT_TAPE_INTERVAL).  The reverse sweep recomputes, from the
- * checkpoint at or before each step k, the products Z_j = Pi(A D_j) and the
- * recurrences up to D_k, Z_k and R_{k+1}: c(c-1)/2 extra products per
- * checkpoint segment, ceil(iters/c) + 4 iterate vectors instead of
- * iters + 1 pairs. */
+ * scalars and the iterates R_k, D_k and Z_k = Pi(A D_k) at the checkpoints
+ * k = 0, c, 2c, ... < iters (c from RN_OPT_TAPE_INTERVAL).  The reverse
+ * sweep recomputes, from the checkpoint k0 at or before each step k, the
+ * products Z_j = Pi(A D_j) for k0 < j <= k and the recurrences up to D_k,
+ * Z_k and R_{k+1}: c(c-1)/2 products per checkpoint segment (none with
+ * c = 1), 3 ceil(iters/c) + 4 iterate vectors per problem. */
 rn_status rn_tape_create(rn_ctx *ctx, rn_plan *plan, int32_t batch,
                          int32_t iters, rn_tape **tape);
 void rn_tape_destroy(rn_tape *tape);

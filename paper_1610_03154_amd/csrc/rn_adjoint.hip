@@ -24,11 +24,12 @@
 // masked product on a plan of A^T, same pattern, no output projection), and
 // d<Y, Q(X)>/dA_ik = sum over the pattern of row i of Pi(Y)_ij X_kj, which
 // the product's position codes give directly.  The tape keeps R_k and D_k at
-// the checkpoint steps k = 0, c, 2c, ... only; reverse step k recomputes
+// the checkpoint steps k = 0, c, 2c, ... only, with Z_k = Q(D_k) there (the
+// forward's product writes it into the tape); reverse step k recomputes
 // from the checkpoint k0 <= k, with the recorded alpha_j and beta_j, Z_j =
-// Q(D_j), R_{j+1} = R_j - alpha_j Z_j and D_{j+1} = R_{j+1} + beta_j D_j for
-// j = k0..k (the forward's own expressions, so the same bits), which yields
-// D_k, Z_k and R_{k+1}.
+// Q(D_j) (j > k0), R_{j+1} = R_j - alpha_j Z_j and D_{j+1} = R_{j+1} +
+// beta_j D_j for j = k0..k (the forward's own expressions, so the same
+// bits), which yields D_k, Z_k and R_{k+1}.
 #include <cstring>
 #include <new>
 #include <type_traits>
@@ -42,6 +43,7 @@ struct rn_tape {
   int32_t c = 1, ncp = 0;             // checkpoint interval and count (steps 0, c, ... < K)
   int64_t nz = 0, nzb = 0;
   double *R = nullptr, *D = nullptr;  // [ncp][batch][nz]
+  double *Z = nullptr;                // [ncp][batch][nz]: Z_k = Q(D_k) at the checkpoints k < K
   double *W = nullptr;                // [4][batch][nz]: recomputed R and D, two of each
   double *T = nullptr;                // [nz]
   double *scal = nullptr;             // [batch][scal_stride], the forward CG scalars
@@ -66,7 +68,7 @@ static unsigned adj_grid(int64_t n) {
 // queued on the context's stream that still reads it runs first).
 void rn_tape_release(rn_tape *t) {
   if (!t->ctx) return;
-  void **bufs[] = {(void **)&t->R,  (void **)&t->D,  (void **)&t->W,  (void **)&t->T,  (void **)&t->scal, (void **)&t->st,
+  void **bufs[] = {(void **)&t->R,  (void **)&t->D,  (void **)&t->Z,  (void **)&t->W,  (void **)&t->T,  (void **)&t->scal, (void **)&t->st,
                    (void **)&t->Rb, (void **)&t->Db, (void **)&t->Zk, (void **)&t->Yb,   (void **)&t->Yh,
                    (void **)&t->gbar, (void **)&t->part, (void **)&t->ATv};
   for (void **b : bufs) {
@@ -127,7 +129,7 @@ extern "C" rn_status rn_tape_create(rn_ctx *ctx, rn_plan *pl, int32_t batch, int
     *p = (std::remove_reference_t<decltype(**p)> *)rn_dev_alloc(ctx, bytes);
     return *p != nullptr;
   };
-  bool ok = get(&t->R, slots) && get(&t->D, slots) && get(&t->W, 4 * v) && get(&t->T, (size_t)(t->nz + 1) * 8) &&
+  bool ok = get(&t->R, slots) && get(&t->D, slots) && get(&t->Z, slots) && get(&t->W, 4 * v) && get(&t->T, (size_t)(t->nz + 1) * 8) &&
             get(&t->scal, (size_t)batch * t->scal_stride * 8) && get(&t->st, (size_t)batch * ST_STRIDE * 4) &&
             get(&t->Rb, v) && get(&t->Db, v) && get(&t->Zk, v) && get(&t->Yb, v) && get(&t->Yh, v) &&
             get(&t->gbar, (size_t)batch * (iters + 1) * 8) &&
@@ -135,7 +137,7 @@ extern "C" rn_status rn_tape_create(rn_ctx *ctx, rn_plan *pl, int32_t batch, int
             get(&t->ATv, (size_t)batch * (pl->nnzA + 1) * 8);
   if (!ok) {
     rn_tape_destroy(t);
-    return rn_fail(ctx, RN_ENOMEM, "rn_tape_create: device allocation (%zu bytes of iterates)", 2 * slots);
+    return rn_fail(ctx, RN_ENOMEM, "rn_tape_create: device allocation (%zu bytes of iterates)", 3 * slots);
   }
   *out = t;
   return RN_OK;
@@ -158,6 +160,9 @@ double *rn_tape_R(rn_tape *tape, int k) {
 }
 double *rn_tape_D(rn_tape *tape, int k) {
   return (k % tape->c == 0 && (k < tape->K || k == 0)) ? tape->D + (int64_t)(k / tape->c) * tape->nzb : nullptr;
+}
+double *rn_tape_Z(rn_tape *tape, int k) {
+  return (k % tape->c == 0 && k < tape->K) ? tape->Z + (int64_t)(k / tape->c) * tape->nzb : nullptr;
 }
 
 rn_status rn_tape_record_end(rn_ctx *ctx, rn_tape *tape, const double *scal, const int32_t *st, int32_t batch) {
@@ -686,33 +691,39 @@ extern "C" rn_status rn_energy_min_bwd(rn_ctx *ctx, rn_plan *pl, rn_plan *plT, c
     // entry that stopped before step j skips it, as in every kernel below)
     const int k0 = (k / t->c) * t->c;
     const double *Dj = rn_tape_D(t, k0), *Rj = rn_tape_R(t, k0);
-    const double *Dk = nullptr, *R1 = nullptr;
+    const double *Dk = nullptr, *R1 = nullptr, *Zk = nullptr;
     for (int j = k0; j <= k; ++j) {
-      SpgParams q = rn_spg_params(pl);
-      q.Ax = A_vals;
-      q.X = Dj;
-      q.Z = t->Zk;
-      q.project = 1;
-      q.st = t->st;
-      q.kact = j;
-      RN_TRY(rn_launch_spgemm(ctx, pl, MODE_PRODUCT, q, B, false));
+      const double *Zj = t->Zk;
+      if (j == k0) {
+        Zj = rn_tape_Z(t, k0);  // the forward's own Z_{k0}
+      } else {
+        SpgParams q = rn_spg_params(pl);
+        q.Ax = A_vals;
+        q.X = Dj;
+        q.Z = t->Zk;
+        q.project = 1;
+        q.st = t->st;
+        q.kact = j;
+        RN_TRY(rn_launch_spgemm(ctx, pl, MODE_PRODUCT, q, B, false));
+      }
       // next iterates into the work vectors not holding R_j, D_j
       double *Rn = Wv[2 * ((j - k0) & 1)], *Dn = Wv[2 * ((j - k0) & 1) + 1];
-      hipLaunchKernelGGL(k_adj_refwd, g2, bl, 0, ctx->stream, nz, K, j, j == k ? 1 : 0, Rj, Dj, t->Zk, Rn, Dn,
+      hipLaunchKernelGGL(k_adj_refwd, g2, bl, 0, ctx->stream, nz, K, j, j == k ? 1 : 0, Rj, Dj, Zj, Rn, Dn,
                          t->scal, t->scal_stride, t->st);
       LAUNCH_CHECK(ctx);
       if (j == k) {
         Dk = Dj;
         R1 = Rn;
+        Zk = Zj;
       } else {
         Rj = Rn;
         Dj = Dn;
       }
     }
-    hipLaunchKernelGGL(k_adj_dots, g2, bl, 0, ctx->stream, nz, k, t->Db, P_bar, t->Rb, t->Zk, R1, Dk, t->part, t->st);
+    hipLaunchKernelGGL(k_adj_dots, g2, bl, 0, ctx->stream, nz, k, t->Db, P_bar, t->Rb, Zk, R1, Dk, t->part, t->st);
     LAUNCH_CHECK(ctx);
     hipLaunchKernelGGL(k_adj_update, g2, bl, 0, ctx->stream, nz, K, k, (int)ge, t->part, t->scal, t->scal_stride,
-                       t->st, t->gbar, t->Rb, t->Db, P_bar, R1, Dk, t->Zk, t->Yb);
+                       t->st, t->gbar, t->Rb, t->Db, P_bar, R1, Dk, Zk, t->Yb);
     LAUNCH_CHECK(ctx);
     RN_TRY(adj_project(ctx, pl, k, t));
     // Dbar += M(A^T Pi(Zbar))

@@ -918,6 +918,9 @@ extern "C" rn_status rn_energy_min(rn_ctx *ctx, rn_plan *pl, const double *A_val
 
 // Workspace bytes emin_run requests (each piece rounded to 256 bytes, as the
 // arena carves them), and the bytes of its one read-back.
+// the tape's Z_k slot at a checkpoint step (rn_adjoint.hip), else NULL
+double *rn_tape_Z(rn_tape *tape, int k);
+
 // plain FP64 CG (with or without a tape) forms each direction inside the next
 // product
 // when the context allows it and the persistent product serves the plan
@@ -1169,7 +1172,10 @@ static rn_status emin_run(rn_ctx *ctx, rn_plan *pl, const double *A_vals, int32_
       SpgParams s = p;
       s.k = k;
       s.Ax = Aop;
-      s.Z = Z;
+      // a tape keeps Z_k at its checkpoint steps: the product writes it there
+      double *Zs = tape ? rn_tape_Z(tape, k) : nullptr;
+      double *Zk = Zs ? Zs : Z;
+      s.Z = Zk;
       s.grid = step_grid;
       double *Dk = (fuse && (k & 1)) ? D2 : D;
       int np = 0;
@@ -1194,7 +1200,7 @@ static rn_status emin_run(rn_ctx *ctx, rn_plan *pl, const double *A_vals, int32_
         s.Xown = D;
         RN_TRY(rn_launch_spgemm(ctx, pl, MODE_CG_STEP, s, batch, mixed, &np));
       }
-      hipLaunchKernelGGL(k_cg_update, g2, blk, 0, ctx->stream, nz, nz, K, k, np, pstride_spg, part_spg, P, R, Dk, Z,
+      hipLaunchKernelGGL(k_cg_update, g2, blk, 0, ctx->stream, nz, nz, K, k, np, pstride_spg, part_spg, P, R, Dk, Zk,
                          part_ew, p.scal, scal_stride, p.st, hist, hist_stride,
                          tape ? rn_tape_R(tape, k + 1) : nullptr);
       LAUNCH_CHECK(ctx);
