@@ -160,11 +160,12 @@ typedef enum {
    * the projected residual and the constraint residual of their result into
    * rn_emin_stats (one more product and two reductions per call). */
   RN_OPT_METRICS = 4,
-  /* 1 (default): FP64 CG (RN_CG), with or without a tape, on plans whose products run
-   * as persistent workgroups of 256 lanes, forms the direction D = R + beta D
-   * while the next product stages its X window (two launches per step, two D
-   * buffers); 0: a separate direction pass (three launches per step).  The
-   * two give the same result bit for bit. */
+  /* 1 (default): CG (RN_CG; FP64, with or without a tape, or FP32-mixed) on
+   * plans whose products run as persistent workgroups of 256 lanes forms the
+   * direction D = R + beta D in FP64 while the next product stages its X
+   * window (rounded to FP32 there in the mixed form; two launches per step,
+   * two D buffers); 0: a separate direction pass (three launches per step).
+   * The two give the same result bit for bit. */
   RN_OPT_FUSED_CG = 5,
   /* 0 (default): tapes made by rn_tape_create keep the CG iterates R_k, D_k
    * and Z_k at every c-th step, c = ceil(sqrt(iters)); c >= 1: that

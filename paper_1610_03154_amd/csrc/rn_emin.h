@@ -162,10 +162,10 @@ rn_status rn_launch_spgemm(rn_ctx *ctx, const rn_plan *pl, int mode, const SpgPa
                            int *npart = nullptr);
 SpgParams rn_spg_params(const rn_plan *pl);
 // Workgroups per batch entry of the persistent MODE_CG_FSTEP launch for this
-// plan, or 0 when it cannot run.  FP64 CG passes it as SpgParams::grid to
-// every step product (MODE_CG_STEP too), so the <D, Pi(A D)> partials are
-// grouped alike whichever path forms the direction.
-int rn_spgemm_fused_grid(const rn_plan *pl, int batch);
+// plan (FP64 or FP32-mixed), or 0 when it cannot run.  CG passes it as
+// SpgParams::grid to every step product (MODE_CG_STEP too), so the
+// <D, Pi(A D)> partials are grouped alike whichever path forms the direction.
+int rn_spgemm_fused_grid(const rn_plan *pl, int batch, bool mixed = false);
 
 // rn_plan_create on the caller's guard word (not reset; NULL: a fresh one),
 // with one extra device item (nullable) read back at the plan's

@@ -921,11 +921,12 @@ extern "C" rn_status rn_energy_min(rn_ctx *ctx, rn_plan *pl, const double *A_val
 // the tape's Z_k slot at a checkpoint step (rn_adjoint.hip), else NULL
 double *rn_tape_Z(rn_tape *tape, int k);
 
-// plain FP64 CG (with or without a tape) forms each direction inside the next
-// product
-// when the context allows it and the persistent product serves the plan
+// CG (FP64 with or without a tape, or FP32-mixed) forms each direction inside
+// the next product when the context allows it and the persistent product
+// serves the plan
 static bool cg_fused(const rn_ctx *ctx, const rn_plan *pl, int32_t batch, rn_method method, rn_precision prec) {
-  return ctx->opt[RN_OPT_FUSED_CG] && method == RN_CG && prec == RN_FP64 && rn_spgemm_fused_grid(pl, batch) > 0;
+  return ctx->opt[RN_OPT_FUSED_CG] && method == RN_CG && (prec == RN_FP64 || prec == RN_FP32_MIXED) &&
+         rn_spgemm_fused_grid(pl, batch, prec == RN_FP32_MIXED) > 0;
 }
 
 static size_t emin_ws_need(const rn_plan *pl, int32_t batch, bool gm, bool pcg, int K, bool mixed, bool fused,
@@ -1165,9 +1166,9 @@ static rn_status emin_run(rn_ctx *ctx, rn_plan *pl, const double *A_vals, int32_
       HIP_TRY(ctx, hipMemcpyAsync(rn_tape_R(tape, 0), R, (size_t)nzb * 8, hipMemcpyDeviceToDevice, ctx->stream));
       HIP_TRY(ctx, hipMemcpyAsync(rn_tape_D(tape, 0), D, (size_t)nzb * 8, hipMemcpyDeviceToDevice, ctx->stream));
     }
-    // FP64: every step product on the fused kernel's grid (the same
-    // grouping of the <D, Z> partials with or without fusion and tape)
-    const int step_grid = mixed ? 0 : rn_spgemm_fused_grid(pl, batch);
+    // every step product on the fused kernel's grid (the same grouping of
+    // the <D, Z> partials with or without fusion and tape)
+    const int step_grid = rn_spgemm_fused_grid(pl, batch, mixed);
     for (int k = 0; k < K; ++k) {
       SpgParams s = p;
       s.k = k;
@@ -1189,7 +1190,7 @@ static rn_status emin_run(rn_ctx *ctx, rn_plan *pl, const double *A_vals, int32_
         s.pstride_rr = pstride_ew;
         s.hist = hist;
         s.hist_stride = hist_stride;
-        RN_TRY(rn_launch_spgemm(ctx, pl, MODE_CG_FSTEP, s, batch, false, &np));
+        RN_TRY(rn_launch_spgemm(ctx, pl, MODE_CG_FSTEP, s, batch, mixed, &np));
         // a checkpoint step keeps the D_k the product just formed (a batch
         // entry that stopped leaves its slot unread: the reverse sweep skips
         // the steps it did not take)

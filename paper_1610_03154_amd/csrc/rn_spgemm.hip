@@ -642,15 +642,17 @@ __global__ __launch_bounds__(BS) void k_spgemm_p(const SpgParams p, const int G)
   constexpr int NU = XCAP / XW_UNIT;
   constexpr int NWV = BS / RN_WAVE;
   constexpr int UMAX = 11;
-  // CG step with the direction formed in the staging: X is D_{k-1} and each
-  // window element is R + beta D_{k-1}, loaded as whole doubles, two units
-  // (one per half wave) per load
+  // CG step with the direction formed in the staging: X is D_{k-1} (FP64 in
+  // both precisions) and each window element is R + beta D_{k-1}, loaded as
+  // whole doubles, two units (one per half wave) per load, and in the mixed
+  // form rounded to FP32 once formed (the separate direction pass's FP32
+  // shadow of D_k, bit for bit)
   constexpr bool FUSE = MODE == MODE_CG_FSTEP;
   constexpr bool CGS = MODE == MODE_CG_STEP || FUSE;
-  constexpr int XF = FUSE ? XIT / 2 : 1;
+  constexpr int XF = FUSE ? NUW / 2 : 1;
   // (256 lanes: the partials of beta are summed in the order the separate
   // direction pass uses)
-  static_assert(!FUSE || (!MIXED && XIT % 2 == 0 && BS == RN_BLOCK), "fused step: FP64, units in pairs");
+  static_assert(!FUSE || (NUW % 2 == 0 && BS == RN_BLOCK), "fused step: units in pairs");
   static_assert(NIT * BS == ACAP && NITD * BS == ACAP * DPE, "staging covers the capacity exactly");
   // row starts double-buffered (the projection of one block reads them while
   // the next block is staged); the projection terms have their own buffer:
@@ -687,6 +689,7 @@ __global__ __launch_bounds__(BS) void k_spgemm_p(const SpgParams p, const int G)
   const TV *Ax = (const TV *)p.Ax + (int64_t)b * p.strideA;
   const TV *X = (const TV *)p.X + (int64_t)b * p.strideX;
   const double *Rr = FUSE ? p.Rres + (int64_t)b * p.strideX : nullptr;
+  const double *Dp = FUSE ? (const double *)p.X + (int64_t)b * p.strideX : nullptr;  // fused step: D_{k-1}
   double be = 0.0;  // fused step: beta_{k-1}, set before the first staging
   const int64_t zb = (int64_t)b * p.strideZ;
   double *Z = p.Z + zb;
@@ -750,7 +753,7 @@ __global__ __launch_bounds__(BS) void k_spgemm_p(const SpgParams p, const int G)
     if (MODE == MODE_CG_STEP) r.own = spg_ld(p.Xown + zb, e);
     if (FUSE) {  // this lane's R and D_{k-1} (D_k is formed in the epilogue)
       r.ownr = spg_ld(Rr, e);
-      r.own = spg_ld((const double *)X, e);
+      r.own = spg_ld(Dp, e);
     }
     const int rq = t < h.nrows ? t : h.nrows - 1, rt = t < h.nrows ? t : h.nrows;
     r.rp = spg_ld(p.Np, (uint32_t)(h.r0 + rt));
@@ -791,7 +794,7 @@ __global__ __launch_bounds__(BS) void k_spgemm_p(const SpgParams p, const int G)
         for (int j = 0; j < XF; ++j) {
           const uint32_t xi = (uint32_t)((lane < 32 ? h.uw[2 * j] : h.uw[2 * j + 1]) + (lane & 31));
           r.fr[j] = spg_ld(Rr, xi);
-          r.fd[j] = spg_ld((const double *)X, xi);
+          r.fd[j] = spg_ld(Dp, xi);
         }
       }
 #pragma unroll
@@ -825,11 +828,16 @@ __global__ __launch_bounds__(BS) void k_spgemm_p(const SpgParams p, const int G)
       for (int it = 0; it < NITD; ++it) s_ad[t + it * BS] = r.ad[it];
       if (h.nunit > 0) {
         if (FUSE) {
-          // unit wv + i NWV at element (wv + i NWV) XW_UNIT; the same
-          // rounding as the separate direction pass (no contraction)
+          // the same rounding as the separate direction pass (no
+          // contraction); FP64: unit wv + i NWV at element (wv + i NWV)
+          // XW_UNIT; FP32: units 2 (wv + j NWV) and the next at word
+          // (wv + j NWV) 64, one per half wave
 #pragma unroll
-          for (int j = 0; j < XF; ++j)
-            ((double *)s_xw)[(wv + (2 * j + (lane >> 5)) * NWV) * XW_UNIT + (lane & 31)] = r.fr[j] + be * r.fd[j];
+          for (int j = 0; j < XF; ++j) {
+            const double dk = r.fr[j] + be * r.fd[j];
+            if (MIXED) s_xw[(wv + j * NWV) * 64 + lane] = (TV)dk;
+            else ((double *)s_xw)[(wv + (2 * j + (lane >> 5)) * NWV) * XW_UNIT + (lane & 31)] = dk;
+          }
         } else {
           uint32_t *s_xd = (uint32_t *)s_xw;
 #pragma unroll
@@ -925,7 +933,7 @@ __global__ __launch_bounds__(BS) void k_spgemm_p(const SpgParams p, const int G)
           if (path < 2) av[u - lo] = s_ax[la + u];
           else av[u - lo] = Ax[H.aB + min(la + u, H.naB - 1)];
           if (path == 0) xv[u - lo] = s_xw[xi[u - lo]];
-          else if (FUSE) xv[u - lo] = spg_ld(Rr, xi[u - lo]) + be * spg_ld((const double *)X, xi[u - lo]);
+          else if (FUSE) xv[u - lo] = (TV)(spg_ld(Rr, xi[u - lo]) + be * spg_ld(Dp, xi[u - lo]));
           else xv[u - lo] = spg_ld(X, xi[u - lo]);
         }
 #pragma unroll
@@ -1073,11 +1081,14 @@ template <int M, int NB, int MODE>
 static int launch_m(const SpgParams &p, int batch, bool mixed, hipStream_t s) {
   if constexpr (MODE == MODE_CG_FSTEP) {
     if constexpr (M == 1 && NB <= 2) {
-      if (mixed || !fused_plan(p)) return 0;
-      const int G = p.grid > 0 ? p.grid : persist_grid<NB, MODE, false, RN_BLOCK>(p.nblk, batch);
+      if (!fused_plan(p)) return 0;
+      const int G = p.grid > 0 ? p.grid
+                               : mixed ? persist_grid<NB, MODE, true, RN_BLOCK>(p.nblk, batch)
+                                       : persist_grid<NB, MODE, false, RN_BLOCK>(p.nblk, batch);
       if (G < 8) return 0;
-      hipLaunchKernelGGL((k_spgemm_p<NB, MODE, false, RN_BLOCK>), dim3((unsigned)G, (unsigned)batch),
-                         dim3(RN_BLOCK), 0, s, p, G);
+      const dim3 grid((unsigned)G, (unsigned)batch);
+      if (mixed) hipLaunchKernelGGL((k_spgemm_p<NB, MODE, true, RN_BLOCK>), grid, dim3(RN_BLOCK), 0, s, p, G);
+      else hipLaunchKernelGGL((k_spgemm_p<NB, MODE, false, RN_BLOCK>), grid, dim3(RN_BLOCK), 0, s, p, G);
       return G;
     }
     return 0;
@@ -1132,11 +1143,16 @@ static rn_status launch_mode(rn_ctx *ctx, const rn_plan *pl, const SpgParams &p,
   return RN_OK;
 }
 
-int rn_spgemm_fused_grid(const rn_plan *pl, int batch) {
+int rn_spgemm_fused_grid(const rn_plan *pl, int batch, bool mixed) {
   const SpgParams p = rn_spg_params(pl);
   if (pl->m != 1 || pl->nB > 2 || p.nblk <= 0 || !fused_plan(p)) return 0;
-  const int G = pl->nB == 1 ? persist_grid<1, MODE_CG_FSTEP, false, RN_BLOCK>(p.nblk, batch)
-                            : persist_grid<2, MODE_CG_FSTEP, false, RN_BLOCK>(p.nblk, batch);
+  int G;
+  if (mixed)
+    G = pl->nB == 1 ? persist_grid<1, MODE_CG_FSTEP, true, RN_BLOCK>(p.nblk, batch)
+                    : persist_grid<2, MODE_CG_FSTEP, true, RN_BLOCK>(p.nblk, batch);
+  else
+    G = pl->nB == 1 ? persist_grid<1, MODE_CG_FSTEP, false, RN_BLOCK>(p.nblk, batch)
+                    : persist_grid<2, MODE_CG_FSTEP, false, RN_BLOCK>(p.nblk, batch);
   return G >= 8 ? G : 0;
 }
 

@@ -6,7 +6,10 @@ two D buffers); with it off a separate direction pass forms it.  The two
 paths evaluate the same expressions in the same order, so P, the Krylov
 history and the step count must agree bit for bit; the fused result is
 also held to the FP64 bar against the oracle, including a run that stops
-early inside a fused product, a one-step run and a batch.
+early inside a fused product, a one-step run and a batch.  In the
+FP32-mixed form the fused step rounds each window element of D_k to FP32
+where the separate pass writes D's FP32 shadow: the same bits again, and
+the mixed bar against the FP64 oracle.
 """
 import numpy as np
 import pytest
@@ -14,7 +17,7 @@ import pytest
 import oracle as O
 import workloads as W
 from tests import cases as CS
-from tests.test_gpu_parity import FP64_TOL, dev, host, run_path
+from tests.test_gpu_parity import FP64_TOL, MIXED_TOL, dev, host, run_path
 
 pytestmark = pytest.mark.gpu
 
@@ -25,11 +28,12 @@ def R():
     return R
 
 
-def _run(R, c, fused, K, batch_vals=None):
+def _run(R, c, fused, K, prec=None):
     ctx = R.Context()
     ctx.set_option(R._lib.RN_OPT_FUSED_CG, 1 if fused else 0)
     g = run_path(R, ctx, c)
-    P, st, hist = ctx.energy_min(g["plan"], g["A"].vals, g["T"], R.RN_CG, K, R.RN_FP64, want_hist=True)
+    prec = R.RN_FP64 if prec is None else prec
+    P, st, hist = ctx.energy_min(g["plan"], g["A"].vals, g["T"], R.RN_CG, K, prec, want_hist=True)
     out = host(P), st, host(hist)
     g["plan"].close()
     ctx.close()
@@ -91,6 +95,52 @@ def test_fused_batch(R, nx, batch):
         ref, _ = O.emin_cg(A0.rowptr, A0.colind, vals[b], st["Np"], st["Nj"], st["is_root"], st["nc"], st["Bc"],
                            1, st["T"], 6)
         assert CS.rel_max(Pf[b], ref) <= FP64_TOL
+
+
+# FP32-mixed: (case, steps, whether the persistent product serves the plan)
+MIXED_RUNS = [("poisson32", 4, 1), ("aniso40", 5, 1), ("aniso512", 6, 1), ("poisson37", 4, 1), ("twocand13", 5, 0),
+              ("poisson32", 40, 1), ("aniso40", 1, 1)]
+
+
+@pytest.mark.parametrize("name,K,fuses", MIXED_RUNS)
+def test_fused_mixed_equals_separate_and_oracle(R, name, K, fuses):
+    c = CS.case(name)
+    A = c["A"]
+    Pf, sf, hf = _run(R, c, True, K, R.RN_FP32_MIXED)
+    Ps, ss, hs = _run(R, c, False, K, R.RN_FP32_MIXED)
+    assert sf.fused_cg == fuses and ss.fused_cg == 0
+    assert sf.iters_done == ss.iters_done and sf.status_code == ss.status_code == 0
+    assert np.array_equal(Pf, Ps), f"{name}: fused and separate P differ by {np.max(np.abs(Pf - Ps)):.3e}"
+    assert np.array_equal(hf, hs)
+    if K > 6:  # (past the FP64 run's convergence the mixed iterates are FP32 noise: bit equality only)
+        return
+    ref, info = O.emin_cg(A.rowptr, A.colind, A.vals, c["Np"], c["Nj"], c["is_root"], c["nc"], c["Bc"],
+                          c["B"].shape[1], c["T"], K)
+    err = CS.rel_max(Pf, ref)
+    print(f"{name} K={K} mixed: {sf.iters_done} steps, fused={sf.fused_cg}, max|dP|/max|P| = {err:.2e}")
+    assert err <= MIXED_TOL
+
+
+def test_fused_mixed_batch(R):
+    A0, vals, _, _ = W.aniso_batch(32, 3, 0)
+    st = O.setup(A0, W.ones(A0.n_rows), 1, 0.0, 2)
+    outs = []
+    for fused in (1, 0):
+        ctx = R.Context()
+        ctx.set_option(R._lib.RN_OPT_FUSED_CG, fused)
+        dA = R.DeviceCSR.from_host(A0.rowptr, A0.colind, A0.vals)
+        plan = ctx.plan(dA, st["nc"], dev(st["Np"]), dev(st["Nj"]), dev(st["is_root"]), dev(st["Bc"]))
+        P, s, hist = ctx.energy_min(plan, dev(vals), dev(st["T"]), R.RN_CG, 6, R.RN_FP32_MIXED, want_hist=True)
+        outs.append((host(P), s, host(hist)))
+        plan.close()
+        ctx.close()
+    (Pf, sf, hf), (Ps, ss, hs) = outs
+    assert sf.fused_cg == 1 and ss.fused_cg == 0
+    assert np.array_equal(Pf, Ps) and np.array_equal(hf, hs)
+    for b in range(3):
+        ref, _ = O.emin_cg(A0.rowptr, A0.colind, vals[b], st["Np"], st["Nj"], st["is_root"], st["nc"], st["Bc"],
+                           1, st["T"], 6)
+        assert CS.rel_max(Pf[b], ref) <= MIXED_TOL
 
 
 def test_option_values(R):

@@ -156,3 +156,30 @@ def test_pattern_row_widths(R, ctx, hb, d):
     assert (widest > 64) == ((hb, d) == (35, 2))
     assert np.array_equal(host(Np), Np_o) and np.array_equal(host(Nj), Nj_o)
     assert np.array_equal(host(is_root), ir_o)
+
+
+@pytest.mark.parametrize("name", ["elastic7", "elastic32_t03"])
+def test_node_blocked_unaligned_x(R, ctx, name):
+    """Node-blocked product: with X aligned to a pair of doubles each term's
+    X values come as two-element loads, with X one double off as single
+    loads; the arithmetic and its order are the same, so both give the same
+    bits and match the oracle."""
+    import torch
+    import oracle as O
+    c = CS.case(name)
+    g = run_path(R, ctx, c)
+    X = np.random.default_rng(12).standard_normal(c["Nj"].size)
+    Xa = dev(X)
+    buf = torch.zeros(X.size + 2, dtype=torch.float64, device="cuda")
+    buf[1:1 + X.size] = Xa
+    Xu = buf[1:1 + X.size]
+    assert Xa.data_ptr() % 16 == 0 and Xu.data_ptr() % 16 == 8
+    A = c["A"]
+    ref = O.masked_product(A.rowptr, A.colind, A.vals, c["Np"], c["Nj"], c["nc"], X)
+    refp = O.project(c["Np"], c["Nj"], c["is_root"], c["Bc"], c["B"].shape[1], ref)
+    for project in (False, True):
+        Za = host(ctx.masked_product(g["plan"], g["A"].vals, Xa, project=project))
+        Zu = host(ctx.masked_product(g["plan"], g["A"].vals, Xu, project=project))
+        assert np.array_equal(Za, Zu), f"project={project}: max diff {np.max(np.abs(Za - Zu))}"
+    assert np.max(np.abs(Za - refp)) <= FP64_TOL * np.max(np.abs(refp))
+    g["plan"].close()
