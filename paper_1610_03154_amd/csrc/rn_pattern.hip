@@ -20,18 +20,6 @@ __global__ __launch_bounds__(RN_BLOCK) void k_diag_csr(int n, const int32_t *__r
   diag[i] = d;
 }
 
-__global__ __launch_bounds__(RN_BLOCK) void k_diag_bsr(int nn, const int32_t *__restrict__ Ap,
-                                                      const int32_t *__restrict__ Aj,
-                                                      const double *__restrict__ Ax, double *__restrict__ diag,
-                                                      const int32_t *__restrict__ guard) {
-  const int I = blockIdx.x * RN_BLOCK + threadIdx.x;
-  if (I >= nn || *guard) return;
-  double d0 = 0.0, d1 = 0.0;
-  for (int p = Ap[I]; p < Ap[I + 1]; ++p)
-    if (Aj[p] == I) { d0 = Ax[4 * (int64_t)p + 0]; d1 = Ax[4 * (int64_t)p + 3]; }
-  diag[2 * I] = d0;
-  diag[2 * I + 1] = d1;
-}
 
 // strong when a^2 >= theta^2 |a_ii a_jj| (rounded products, no FMA); the
 // diagonal is always strong.
@@ -54,26 +42,6 @@ __global__ __launch_bounds__(RN_BLOCK) void k_strong_csr(int n, const int32_t *_
   }
 }
 
-__global__ __launch_bounds__(RN_BLOCK) void k_strong_bsr(int nn, const int32_t *__restrict__ Ap,
-                                                        const int32_t *__restrict__ Aj,
-                                                        const double *__restrict__ Ax,
-                                                        const double *__restrict__ diag, double th2,
-                                                        uint8_t *__restrict__ mask,
-                                                        const int32_t *__restrict__ guard) {
-  const int I = blockIdx.x * RN_BLOCK + threadIdx.x;
-  if (I >= nn || *guard) return;
-  for (int p = Ap[I]; p < Ap[I + 1]; ++p) {
-    const int J = Aj[p];
-    bool s = false;
-#pragma unroll
-    for (int c = 0; c < 2; ++c)
-#pragma unroll
-      for (int cc = 0; cc < 2; ++cc)
-        s |= rn_is_strong(Ax[4 * (int64_t)p + 2 * c + cc], diag[2 * I + c], diag[2 * J + cc], th2,
-                          (2 * I + c) == (2 * J + cc));
-    mask[p] = s;
-  }
-}
 
 __global__ __launch_bounds__(RN_BLOCK) void k_gather_u8(const uint8_t *__restrict__ src,
                                                        const int32_t *__restrict__ idx, int64_t n,
@@ -165,6 +133,51 @@ __global__ __launch_bounds__(RN_BLOCK) void k_diag_csr_g(int n, const int32_t *_
   const unsigned long long mine = (who >> base) & ((1ull << SG) - 1);
   if (l == 0 && !mine) diag[i] = 0.0;
   if (hit) diag[i] = d;
+}
+
+// diagonal of a node-blocked (2x2) matrix: both DOFs' entries of the
+// diagonal block (0 where the block is not stored)
+__global__ __launch_bounds__(RN_BLOCK) void k_diag_bsr(int nn, const int32_t *__restrict__ Ap,
+                                                      const int32_t *__restrict__ Aj,
+                                                      const double *__restrict__ Ax, double *__restrict__ diag,
+                                                      const int32_t *__restrict__ guard) {
+  const int I = blockIdx.x * RN_BLOCK + threadIdx.x;
+  if (I >= nn || *guard) return;
+  double d0 = 0.0, d1 = 0.0;
+  for (int p = Ap[I]; p < Ap[I + 1]; ++p)
+    if (Aj[p] == I) {
+      d0 = Ax[4 * (int64_t)p + 0];
+      d1 = Ax[4 * (int64_t)p + 3];
+    }
+  diag[2 * I] = d0;
+  diag[2 * I + 1] = d1;
+}
+
+// node-blocked strength: block (I,J) is strong when any of its four DOF
+// entries is (the boolean OR of the amalgamation); the SG lanes of row I take
+// its blocks side by side
+__global__ __launch_bounds__(RN_BLOCK) void k_strong_bsr(int nn, const int32_t *__restrict__ Ap,
+                                                        const int32_t *__restrict__ Aj,
+                                                        const double *__restrict__ Ax,
+                                                        const double *__restrict__ diag, double th2,
+                                                        uint8_t *__restrict__ mask,
+                                                        const int32_t *__restrict__ guard) {
+  const int g = threadIdx.x / SG, l = threadIdx.x % SG;
+  const int I = blockIdx.x * SRPB + g;
+  if (I >= nn || *guard) return;
+  const double di[2] = {diag[2 * I], diag[2 * I + 1]};
+  for (int p = Ap[I] + l; p < Ap[I + 1]; p += SG) {
+    const int J = Aj[p];
+    const double *a = Ax + 4 * (int64_t)p;
+    const double a4[4] = {a[0], a[1], a[2], a[3]};
+    const double dj[2] = {diag[2 * J], diag[2 * J + 1]};
+    bool s = false;
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int cc = 0; cc < 2; ++cc) s |= rn_is_strong(a4[2 * c + cc], di[c], dj[cc], th2, (2 * I + c) == (2 * J + cc));
+    mask[p] = s;
+  }
 }
 
 // Strong set of node row I made symmetric through A's own structure: entry
@@ -350,7 +363,7 @@ static rn_status strength_sym_launch(rn_ctx *ctx, const rn_matrix *A, double the
                          (const double *)A->vals, diag, th2, (const uint8_t *)nullptr, symmask, cnt, asym, guard);
     } else {
       hipLaunchKernelGGL(k_diag_bsr, g, b, 0, ctx->stream, nn, A->rowptr, A->colind, A->vals, diag, guard);
-      hipLaunchKernelGGL(k_strong_bsr, g, b, 0, ctx->stream, nn, A->rowptr, A->colind, A->vals, diag, th2, mask,
+      hipLaunchKernelGGL(k_strong_bsr, gg, b, 0, ctx->stream, nn, A->rowptr, A->colind, A->vals, diag, th2, mask,
                          guard);
       hipLaunchKernelGGL(k_partner_g<false>, gg, b, 0, ctx->stream, nn, A->rowptr, A->colind,
                          (const double *)nullptr, (const double *)nullptr, th2, mask, symmask, cnt, asym, guard);
@@ -415,7 +428,7 @@ static rn_status strength_transpose_path(rn_ctx *ctx, const rn_matrix *A, double
       hipLaunchKernelGGL(k_diag_bsr, dim3(rn_div_up(nn, RN_BLOCK)), dim3(RN_BLOCK), 0, ctx->stream, nn, A->rowptr,
                          A->colind, A->vals, diag, guard);
       LAUNCH_CHECK(ctx);
-      hipLaunchKernelGGL(k_strong_bsr, dim3(rn_div_up(nn, RN_BLOCK)), dim3(RN_BLOCK), 0, ctx->stream, nn,
+      hipLaunchKernelGGL(k_strong_bsr, dim3(rn_div_up(nn, SRPB)), dim3(RN_BLOCK), 0, ctx->stream, nn,
                          A->rowptr, A->colind, A->vals, diag, th2, mask, guard);
     }
     LAUNCH_CHECK(ctx);
