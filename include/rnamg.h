@@ -405,7 +405,7 @@ rn_status rn_masked_product(rn_ctx *ctx, rn_plan *plan, const double *A_vals,
  * batch entry (its P holds the last good iterate).
  * hist for RN_PCG_JACOBI holds gamma_k = <R_k, Y_k>.
  * tape (nullable, RN_CG + RN_FP64 only): records what rn_energy_min_bwd
- * needs (scalars and the iterates R_k, D_k). */
+ * needs (scalars and the iterates R_k, D_k, Z_k at its checkpoints). */
 rn_status rn_energy_min(rn_ctx *ctx, rn_plan *plan, const double *A_vals,
                         int32_t batch, const double *T, rn_method method,
                         int32_t iters, rn_precision precision, double *P,
