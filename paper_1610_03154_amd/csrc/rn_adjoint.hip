@@ -182,24 +182,34 @@ __device__ inline bool adj_active(const int32_t *tst, int b, int k) {
   return st[ST_STATUS] == 0 && k < st[ST_ITERS];
 }
 
-// partials of <Dbar,D_k>, <Pbar,D_k>, <Rbar,Z_k>, <Dbar,Z_k>, <R_{k+1},Z_k>
-__global__ __launch_bounds__(RN_BLOCK) void k_adj_dots(int64_t nz, int k, const double *__restrict__ Db,
-                                                      const double *__restrict__ Pb, const double *__restrict__ Rb,
-                                                      const double *__restrict__ Zk, const double *__restrict__ R1,
-                                                      const double *__restrict__ Dk, double *__restrict__ part,
-                                                      const int32_t *__restrict__ tst) {
+// The last recomputation step of reverse step k: R_{k+1} = R_k - alpha_k Z_k
+// (the forward's expression), and over the same entries the partials of
+// <Dbar,D_k>, <Pbar,D_k>, <Rbar,Z_k>, <Dbar,Z_k>, <R_{k+1},Z_k>
+__global__ __launch_bounds__(RN_BLOCK) void k_adj_refwd_dots(int64_t nz, int K, int k,
+                                                            const double *__restrict__ Rk,
+                                                            const double *__restrict__ Dk,
+                                                            const double *__restrict__ Zk, double *__restrict__ R1,
+                                                            const double *__restrict__ tscal, int scal_stride,
+                                                            const double *__restrict__ Db,
+                                                            const double *__restrict__ Pb,
+                                                            const double *__restrict__ Rb, double *__restrict__ part,
+                                                            const int32_t *__restrict__ tst) {
   __shared__ double s_w[8];
   const int b = blockIdx.y;
   if (!adj_active(tst, b, k)) return;
+  const CgLayout L(K);
+  const double al = tscal[(int64_t)b * scal_stride + L.alp + k];
   const int64_t off = (int64_t)b * nz;
   RnAcc a[5];
   for (int64_t e = (int64_t)blockIdx.x * RN_BLOCK + threadIdx.x; e < nz; e += (int64_t)gridDim.x * RN_BLOCK) {
     const double db = Db[off + e], dk = Dk[off + e], z = Zk[off + e];
+    const double rr = Rk[off + e] - al * z;
+    R1[off + e] = rr;
     a[0].add(db * dk);
     a[1].add(Pb[off + e] * dk);
     a[2].add(Rb[off + e] * z);
     a[3].add(db * z);
-    a[4].add(R1[off + e] * z);
+    a[4].add(rr * z);
   }
   double *pb = part + (int64_t)b * RN_MAXDOT * gridDim.x;
 #pragma unroll
@@ -264,9 +274,9 @@ __global__ __launch_bounds__(RN_BLOCK) void k_adj_init(int64_t nz, int K, const 
 }
 
 // One forward step of the recomputation from a checkpoint: R_{j+1} = R_j -
-// alpha_j Z_j and (unless this is the last step needed) D_{j+1} = R_{j+1} +
-// beta_j D_j, with the recorded scalars and the forward kernels' expressions
-__global__ __launch_bounds__(RN_BLOCK) void k_adj_refwd(int64_t nz, int K, int j, int last,
+// alpha_j Z_j and D_{j+1} = R_{j+1} + beta_j D_j, with the recorded scalars
+// and the forward kernels' expressions
+__global__ __launch_bounds__(RN_BLOCK) void k_adj_refwd(int64_t nz, int K, int j,
                                                        const double *__restrict__ Rj, const double *__restrict__ Dj,
                                                        const double *__restrict__ Zj, double *__restrict__ Rn,
                                                        double *__restrict__ Dn, const double *__restrict__ tscal,
@@ -280,7 +290,7 @@ __global__ __launch_bounds__(RN_BLOCK) void k_adj_refwd(int64_t nz, int K, int j
   for (int64_t e = (int64_t)blockIdx.x * RN_BLOCK + threadIdx.x; e < nz; e += (int64_t)gridDim.x * RN_BLOCK) {
     const double rr = Rj[off + e] - al * Zj[off + e];
     Rn[off + e] = rr;
-    if (!last) Dn[off + e] = rr + be * Dj[off + e];
+    Dn[off + e] = rr + be * Dj[off + e];
   }
 }
 
@@ -706,10 +716,15 @@ extern "C" rn_status rn_energy_min_bwd(rn_ctx *ctx, rn_plan *pl, rn_plan *plT, c
         q.kact = j;
         RN_TRY(rn_launch_spgemm(ctx, pl, MODE_PRODUCT, q, B, false));
       }
-      // next iterates into the work vectors not holding R_j, D_j
+      // next iterates into the work vectors not holding R_j, D_j; the last
+      // step (R_{k+1} only) also leaves the partials of step k's five dots
       double *Rn = Wv[2 * ((j - k0) & 1)], *Dn = Wv[2 * ((j - k0) & 1) + 1];
-      hipLaunchKernelGGL(k_adj_refwd, g2, bl, 0, ctx->stream, nz, K, j, j == k ? 1 : 0, Rj, Dj, Zj, Rn, Dn,
-                         t->scal, t->scal_stride, t->st);
+      if (j < k)
+        hipLaunchKernelGGL(k_adj_refwd, g2, bl, 0, ctx->stream, nz, K, j, Rj, Dj, Zj, Rn, Dn, t->scal,
+                           t->scal_stride, t->st);
+      else
+        hipLaunchKernelGGL(k_adj_refwd_dots, g2, bl, 0, ctx->stream, nz, K, k, Rj, Dj, Zj, Rn, t->scal,
+                           t->scal_stride, t->Db, P_bar, t->Rb, t->part, t->st);
       LAUNCH_CHECK(ctx);
       if (j == k) {
         Dk = Dj;
@@ -720,8 +735,6 @@ extern "C" rn_status rn_energy_min_bwd(rn_ctx *ctx, rn_plan *pl, rn_plan *plT, c
         Dj = Dn;
       }
     }
-    hipLaunchKernelGGL(k_adj_dots, g2, bl, 0, ctx->stream, nz, k, t->Db, P_bar, t->Rb, Zk, R1, Dk, t->part, t->st);
-    LAUNCH_CHECK(ctx);
     hipLaunchKernelGGL(k_adj_update, g2, bl, 0, ctx->stream, nz, K, k, (int)ge, t->part, t->scal, t->scal_stride,
                        t->st, t->gbar, t->Rb, t->Db, P_bar, R1, Dk, Zk, t->Yb);
     LAUNCH_CHECK(ctx);
