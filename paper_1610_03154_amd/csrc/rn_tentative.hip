@@ -39,8 +39,8 @@ __global__ __launch_bounds__(RN_BLOCK) void k_inject_root(int n_agg, int m, int 
 // T on the pattern: root rows = identity row; F row i of aggregate a holds
 // B[i, 0:m] inv(root block) at columns m*a .. m*a+m-1, zero elsewhere.
 // W lanes per row (entries s + l, s + l + W, ...).
-template <int W>
-__global__ __launch_bounds__(RN_BLOCK) void k_tent_T(int n, int m, int nB, const int32_t *__restrict__ Np,
+template <int W, int M>
+__global__ __launch_bounds__(RN_BLOCK) void k_tent_T(int n, int nB, const int32_t *__restrict__ Np,
                                                     const int32_t *__restrict__ Nj,
                                                     const uint8_t *__restrict__ is_root,
                                                     const int32_t *__restrict__ agg, const double *__restrict__ B,
@@ -49,16 +49,16 @@ __global__ __launch_bounds__(RN_BLOCK) void k_tent_T(int n, int m, int nB, const
   const int64_t gid = (int64_t)blockIdx.x * RN_BLOCK + threadIdx.x;
   const int i = (int)(gid / W), l = (int)(gid % W);
   if (i >= n || *guard) return;
-  const int a = agg[i / m], c = i % m;
+  const int a = agg[i / M], c = i % M;
   const bool root = is_root[i];
   for (int p = Np[i] + l; p < Np[i + 1]; p += W) {
     const int j = Nj[p];
     double t = 0.0;
     if (root) {
-      t = (j == m * a + c) ? 1.0 : 0.0;
-    } else if (j / m == a) {
-      const int cc = j % m;
-      for (int r = 0; r < m; ++r) t += B[(int64_t)i * nB + r] * binv[(int64_t)a * m * m + r * m + cc];
+      t = (j == M * a + c) ? 1.0 : 0.0;
+    } else if (j / M == a) {
+      const int cc = j % M;
+      for (int r = 0; r < M; ++r) t += B[(int64_t)i * nB + r] * binv[(int64_t)a * M * M + r * M + cc];
     }
     T[p] = t;
   }
@@ -165,12 +165,17 @@ rn_status rn_tentative_launch(rn_ctx *ctx, int32_t n, int32_t m, const int32_t *
     LAUNCH_CHECK(ctx);
   }
   if (n > 0) {
-    if (rn_row_group(nnz_N, n) == 16)
-      hipLaunchKernelGGL(k_tent_T<16>, dim3(rn_div_up((int64_t)n * 16, RN_BLOCK)), dim3(RN_BLOCK), 0, ctx->stream, n,
-                         m, nB, Np, Nj, is_root, agg, B, binv, T, guard);
+    // (block_m a template argument: its divisions are shifts)
+    const bool wide = rn_row_group(nnz_N, n) == 16;
+    const dim3 gt(rn_div_up((int64_t)n * (wide ? 16 : 4), RN_BLOCK)), bt(RN_BLOCK);
+    if (wide && m == 2)
+      hipLaunchKernelGGL((k_tent_T<16, 2>), gt, bt, 0, ctx->stream, n, nB, Np, Nj, is_root, agg, B, binv, T, guard);
+    else if (wide)
+      hipLaunchKernelGGL((k_tent_T<16, 1>), gt, bt, 0, ctx->stream, n, nB, Np, Nj, is_root, agg, B, binv, T, guard);
+    else if (m == 2)
+      hipLaunchKernelGGL((k_tent_T<4, 2>), gt, bt, 0, ctx->stream, n, nB, Np, Nj, is_root, agg, B, binv, T, guard);
     else
-      hipLaunchKernelGGL(k_tent_T<4>, dim3(rn_div_up((int64_t)n * 4, RN_BLOCK)), dim3(RN_BLOCK), 0, ctx->stream, n,
-                         m, nB, Np, Nj, is_root, agg, B, binv, T, guard);
+      hipLaunchKernelGGL((k_tent_T<4, 1>), gt, bt, 0, ctx->stream, n, nB, Np, Nj, is_root, agg, B, binv, T, guard);
     LAUNCH_CHECK(ctx);
     if (nB > m) {
       launch_tproj(ctx->stream, n, nB, Np, Nj, is_root, B, Bc, T, gp_out, flags + 1, guard);
