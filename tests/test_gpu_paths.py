@@ -183,3 +183,58 @@ def test_node_blocked_unaligned_x(R, ctx, name):
         assert np.array_equal(Za, Zu), f"project={project}: max diff {np.max(np.abs(Za - Zu))}"
     assert np.max(np.abs(Za - refp)) <= FP64_TOL * np.max(np.abs(refp))
     g["plan"].close()
+
+
+def test_node_blocked_wide_rows(R, ctx):
+    """Node-blocked operator with 25 block terms per row (5 x 5 node stencil,
+    2 x 2 SPD blocks) and aggregates of two nodes (an input): pattern rows of
+    up to 45 node entries, so a product block holds 6 to 20 rows, stages its
+    A slice, and each row's position codes run past the first three words of
+    its record.  Strength and pattern bit for bit; T, the product (X aligned
+    to a pair of doubles and one double off) and 4 CG steps at the FP64 bar
+    against the oracle."""
+    import torch
+    import oracle as O
+    import workloads as W
+    nx = 12
+    nn = nx * nx
+    offs = [(dx, dy) for dy in range(-2, 3) for dx in range(-2, 3)]
+    S = W._csr_from_offsets(nx, nx, offs, [30.0 if o == (0, 0) else -1.0 for o in offs])
+    K2 = np.array([[2.0, 0.5], [0.5, 1.0]])
+    Ab = W.BSR(nn, 2, S.rowptr, S.colind, S.vals[:, None, None] * K2)
+    A = Ab.to_csr()
+    coords = np.stack([(np.arange(nn) % nx + 1) / nx, (np.arange(nn) // nx) / nx], 1)
+    B = W.rbm(coords)
+    agg = (np.arange(nn) // 2).astype(np.int32)
+    roots = np.arange(0, nn, 2).astype(np.int32)
+    st = O.setup(A, B, 2, 0.0, 2, agg=agg, roots=roots)
+    assert np.max(np.diff(Ab.rowptr)) == 25
+    dA = R.DeviceCSR.from_host(Ab.rowptr, Ab.colind, Ab.vals.reshape(-1), n=2 * nn, block_m=2)
+    Sp, Sj = ctx.strength(dA, 0.0)
+    assert np.array_equal(host(Sp), st["Sp"]) and np.array_equal(host(Sj), st["Sj"])
+    Np, Nj, is_root = ctx.pattern(Sp, Sj, dev(agg), dev(roots), 2, 2)
+    assert np.array_equal(host(Np), st["Np"]) and np.array_equal(host(Nj), st["Nj"])
+    assert np.array_equal(host(is_root), st["is_root"])
+    T, Bc, rd = ctx.tentative(Np, Nj, is_root, dev(agg), dev(roots), 2, dev(B))
+    assert rd == 0
+    assert np.max(np.abs(host(T) - st["T"])) <= FP64_TOL * np.max(np.abs(st["T"]))
+    plan = ctx.plan(dA, st["nc"], Np, Nj, is_root, Bc)
+    X = np.random.default_rng(21).standard_normal(st["Nj"].size)
+    ref = O.masked_product(A.rowptr, A.colind, A.vals, st["Np"], st["Nj"], st["nc"], X)
+    refp = O.project(st["Np"], st["Nj"], st["is_root"], st["Bc"], 3, ref)
+    Xa = dev(X)
+    buf = torch.zeros(X.size + 2, dtype=torch.float64, device="cuda")
+    buf[1:1 + X.size] = Xa
+    Xu = buf[1:1 + X.size]
+    Za = host(ctx.masked_product(plan, dA.vals, Xa, project=True))
+    Zu = host(ctx.masked_product(plan, dA.vals, Xu, project=True))
+    assert np.array_equal(Za, Zu)
+    assert np.max(np.abs(Za - refp)) <= FP64_TOL * np.max(np.abs(refp))
+    P, s, _ = ctx.energy_min(plan, dA.vals, T, R.RN_CG, 4, R.RN_FP64)
+    Pref, info = O.emin_cg(A.rowptr, A.colind, A.vals, st["Np"], st["Nj"], st["is_root"], st["nc"], st["Bc"], 3,
+                           st["T"], 4)
+    err = CS.rel_max(host(P), Pref)
+    print(f"wide node-blocked rows: max|dP|/max|P| = {err:.2e}")
+    assert s.status_code == 0 and s.iters_done == info["iters"]
+    assert err <= FP64_TOL
+    plan.close()
