@@ -53,6 +53,11 @@ __device__ inline void rn_row_each(const int32_t *__restrict__ J, int s, int e, 
 // for inverting G directly).  Rank rule: every pivot of the first Cholesky
 // must exceed 1e-12 max(diag G); otherwise the eigen pseudo-inverse of G.
 // Returns 1 when the fallback was taken.
+// rn_row_pinv_g: the same from the row's G = B_J^T B_J, summed by the caller
+// in row order (with other sums of the same pass).
+template <int NB>
+__device__ inline int rn_row_pinv_g(const int32_t *__restrict__ J, int s, int e, const double *__restrict__ Bc,
+                                    const double *G, double *Gp);
 template <int NB>
 __device__ inline int rn_row_pinv(const int32_t *__restrict__ J, int s, int e, const double *__restrict__ Bc,
                                   double *Gp) {
@@ -65,6 +70,11 @@ __device__ inline int rn_row_pinv(const int32_t *__restrict__ J, int s, int e, c
 #pragma unroll
       for (int r = 0; r < NB; ++r) G[q * NB + r] += b[q] * b[r];
   });
+  return rn_row_pinv_g<NB>(J, s, e, Bc, G, Gp);
+}
+template <int NB>
+__device__ inline int rn_row_pinv_g(const int32_t *__restrict__ J, int s, int e, const double *__restrict__ Bc,
+                                    const double *G, double *Gp) {
   double dmax = 0.0;
 #pragma unroll
   for (int q = 0; q < NB; ++q) dmax = fmax(dmax, G[q * NB + q]);

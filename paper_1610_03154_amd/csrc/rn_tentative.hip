@@ -84,19 +84,26 @@ __global__ __launch_bounds__(RN_BLOCK) void k_tproj(int n, const int32_t *__rest
       for (int k = 0; k < NP; ++k) gp[(int64_t)i * NP + k] = 0.0;
     return;
   }
-  double Gp[NB * NB], rr[NB], y[NB], ts[NB];
+  double Gp[NB * NB], rr[NB], y[NB], ts[NB], G[NB * NB];
   const int s = Np[i], e = Np[i + 1];
-  // r = B_i - t B_J
+  // r = B_i - t B_J and G = B_J^T B_J in one pass over the row (each sum in
+  // row order)
 #pragma unroll
   for (int q = 0; q < NB; ++q) ts[q] = 0.0;
+#pragma unroll
+  for (int q = 0; q < NB * NB; ++q) G[q] = 0.0;
   rn_row_each<NB>(Nj, s, e, Bc, [&](int p, const double *b) {
     const double t = T[p];
 #pragma unroll
     for (int q = 0; q < NB; ++q) ts[q] += t * b[q];
+#pragma unroll
+    for (int q = 0; q < NB; ++q)
+#pragma unroll
+      for (int r = 0; r < NB; ++r) G[q * NB + r] += b[q] * b[r];
   });
 #pragma unroll
   for (int q = 0; q < NB; ++q) rr[q] = B[(int64_t)i * NB + q] - ts[q];
-  if (rn_row_pinv<NB>(Nj, s, e, Bc, Gp)) atomicAdd(rank_def, 1);
+  if (rn_row_pinv_g<NB>(Nj, s, e, Bc, G, Gp)) atomicAdd(rank_def, 1);
   if (gp)
 #pragma unroll
     for (int q = 0; q < NB; ++q)
