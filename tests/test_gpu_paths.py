@@ -185,14 +185,17 @@ def test_node_blocked_unaligned_x(R, ctx, name):
     g["plan"].close()
 
 
-def test_node_blocked_wide_rows(R, ctx):
+@pytest.mark.parametrize("degree", [2, 1])
+def test_node_blocked_wide_rows(R, ctx, degree):
     """Node-blocked operator with 25 block terms per row (5 x 5 node stencil,
-    2 x 2 SPD blocks) and aggregates of two nodes (an input): pattern rows of
-    up to 45 node entries, so a product block holds 6 to 20 rows, stages its
-    A slice, and each row's position codes run past the first three words of
-    its record.  Strength and pattern bit for bit; T, the product (X aligned
-    to a pair of doubles and one double off) and 4 CG steps at the FP64 bar
-    against the oracle."""
+    2 x 2 SPD blocks) and aggregates of two nodes (an input).  Degree 2:
+    pattern rows of up to 45 node entries, so a product block holds 6 to 20
+    rows, stages its A slice, and each row's position codes run past the
+    first three words of its record; degree 1: blocks of 32 to 42 rows hold
+    more A entries than the LDS stages, so they read A from global memory.
+    Strength and pattern bit for bit; T, the product (X aligned to a pair of
+    doubles and one double off) and 4 CG steps at the FP64 bar against the
+    oracle."""
     import torch
     import oracle as O
     import workloads as W
@@ -207,12 +210,12 @@ def test_node_blocked_wide_rows(R, ctx):
     B = W.rbm(coords)
     agg = (np.arange(nn) // 2).astype(np.int32)
     roots = np.arange(0, nn, 2).astype(np.int32)
-    st = O.setup(A, B, 2, 0.0, 2, agg=agg, roots=roots)
+    st = O.setup(A, B, 2, 0.0, degree, agg=agg, roots=roots)
     assert np.max(np.diff(Ab.rowptr)) == 25
     dA = R.DeviceCSR.from_host(Ab.rowptr, Ab.colind, Ab.vals.reshape(-1), n=2 * nn, block_m=2)
     Sp, Sj = ctx.strength(dA, 0.0)
     assert np.array_equal(host(Sp), st["Sp"]) and np.array_equal(host(Sj), st["Sj"])
-    Np, Nj, is_root = ctx.pattern(Sp, Sj, dev(agg), dev(roots), 2, 2)
+    Np, Nj, is_root = ctx.pattern(Sp, Sj, dev(agg), dev(roots), degree, 2)
     assert np.array_equal(host(Np), st["Np"]) and np.array_equal(host(Nj), st["Nj"])
     assert np.array_equal(host(is_root), st["is_root"])
     T, Bc, rd = ctx.tentative(Np, Nj, is_root, dev(agg), dev(roots), 2, dev(B))
@@ -234,7 +237,7 @@ def test_node_blocked_wide_rows(R, ctx):
     Pref, info = O.emin_cg(A.rowptr, A.colind, A.vals, st["Np"], st["Nj"], st["is_root"], st["nc"], st["Bc"], 3,
                            st["T"], 4)
     err = CS.rel_max(host(P), Pref)
-    print(f"wide node-blocked rows: max|dP|/max|P| = {err:.2e}")
+    print(f"wide node-blocked rows, degree {degree}: max|dP|/max|P| = {err:.2e}")
     assert s.status_code == 0 and s.iters_done == info["iters"]
     assert err <= FP64_TOL
     plan.close()
