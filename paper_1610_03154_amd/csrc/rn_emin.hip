@@ -709,12 +709,15 @@ __global__ __launch_bounds__(RN_BLOCK) void k_fin_part(int np, const double *__r
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
-// element-wise passes: two elements per lane and up to 2048 workgroups (8
-// per compute unit), enough loads in flight to stream HBM
+// element-wise passes: two elements per lane and up to 1024 workgroups (4
+// per compute unit), enough loads in flight to stream HBM; every dot leaves
+// one partial per workgroup, which the next step sums in every workgroup or
+// in a one-block finisher (2048 workgroups took the upwind1024 set-up 3 %
+// longer, 256 were slower again)
 static unsigned ew_grid(int64_t n) {
   unsigned g = rn_div_up(n, RN_BLOCK * 2);
   if (g < 1) g = 1;
-  if (g > 2048) g = 2048;
+  if (g > 1024) g = 1024;
   return g;
 }
 
